@@ -1,0 +1,378 @@
+"""FP64 reference oracle for the Hodgkin-Huxley hot path (ctypes + numpy).
+
+TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test suite, the smoke entry
+and the CPU-baseline leg of the benchmark import this module.  It shares no
+code with the HIP library: the C part (``hh_oracle.c``) integrates the model of
+Methods, Eq. (1)-(2) step by step in double precision; the numpy part holds the
+dense pieces (input projection, readout, cross entropy, the MLP surrogate and
+Adam), each written from its plain definition.
+
+Models are given as plain dictionaries (see ``model_to_struct``) so that the
+oracle and the HIP library each translate the same description into their own
+representation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libhh_oracle.so")
+
+MAX_GATES = 8
+MAX_CH = 8
+FORMS = {"exp": 0, "sigmoid": 1, "linoid": 2, "bell": 3}
+KINDS = {"ab": 0, "inftau": 1}
+VMETH = {"fe": 0, "ee": 1}
+IN_NONE, IN_CONST, IN_NOISE, IN_DENSE = 0, 1, 2, 3
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, -O2, no fast-math)."""
+    src = os.path.join(_HERE, "hh_oracle.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
+        os.path.getmtime(src), os.path.getmtime(os.path.join(_HERE, "hh_oracle.h"))
+    ):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off",
+             "-o", tmp, src, "-lm"]
+        )
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class OraModel(ctypes.Structure):
+    _fields_ = [
+        ("n_gates", ctypes.c_int32),
+        ("n_channels", ctypes.c_int32),
+        ("v_method", ctypes.c_int32),
+        ("has_syn", ctypes.c_int32),
+        ("gate_kind", ctypes.c_int32 * MAX_GATES),
+        ("rate_form", (ctypes.c_int32 * 2) * MAX_GATES),
+        ("rate_coef", ((ctypes.c_double * 4) * 2) * MAX_GATES),
+        ("ch_n", ctypes.c_int32 * MAX_CH),
+        ("ch_gate", (ctypes.c_int32 * 4) * MAX_CH),
+        ("ch_expo", (ctypes.c_int32 * 4) * MAX_CH),
+        ("ch_gbar", ctypes.c_double * MAX_CH),
+        ("ch_E", ctypes.c_double * MAX_CH),
+        ("C", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("v_th", ctypes.c_double),
+        ("tau_e", ctypes.c_double),
+        ("tau_i", ctypes.c_double),
+        ("E_e", ctypes.c_double),
+        ("E_i", ctypes.c_double),
+    ]
+
+
+def model_to_struct(model: dict) -> OraModel:
+    """Translate a model dictionary into the oracle's C struct.
+
+    model = {"gates": [{"kind": "ab"|"inftau", "rates": [(form, A, B, K, c), (form, A, B, K, c)]}],
+             "channels": [{"gbar": g, "E": E, "gates": [(gate_index, exponent), ...]}],
+             "C": C_m, "dt": dt, "v_th": theta, "v_method": "fe"|"ee",
+             "syn": None | {"tau_e", "tau_i", "E_e", "E_i"}}
+    """
+    s = OraModel()
+    gates, chans = model["gates"], model["channels"]
+    s.n_gates, s.n_channels = len(gates), len(chans)
+    s.v_method = VMETH[model["v_method"]]
+    syn = model.get("syn")
+    s.has_syn = 1 if syn else 0
+    for g, gate in enumerate(gates):
+        s.gate_kind[g] = KINDS[gate["kind"]]
+        for r, rate in enumerate(gate["rates"]):
+            s.rate_form[g][r] = FORMS[rate[0]]
+            for j in range(4):
+                s.rate_coef[g][r][j] = float(rate[1 + j])
+    for c, ch in enumerate(chans):
+        s.ch_n[c] = len(ch["gates"])
+        for k, (gi, ex) in enumerate(ch["gates"]):
+            s.ch_gate[c][k] = gi
+            s.ch_expo[c][k] = ex
+        s.ch_gbar[c] = float(ch["gbar"])
+        s.ch_E[c] = float(ch["E"])
+    s.C, s.dt, s.v_th = float(model["C"]), float(model["dt"]), float(model["v_th"])
+    if syn:
+        s.tau_e, s.tau_i = float(syn["tau_e"]), float(syn["tau_i"])
+        s.E_e, s.E_i = float(syn["E_e"]), float(syn["E_i"])
+    return s
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER
+        d, i32, i64, u32, u64, vp = (ctypes.c_double, ctypes.c_int32, ctypes.c_int64,
+                                     ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p)
+        L.ora_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
+        L.ora_philox4x32_10.restype = None
+        L.ora_noise.argtypes = [u64, u32, i64]
+        L.ora_noise.restype = d
+        L.ora_event_word.argtypes = [u64, u32, i64]
+        L.ora_event_word.restype = u32
+        L.ora_rate.argtypes = [i32, P(d), d, P(d)]
+        L.ora_rate.restype = d
+        L.ora_gate_inf.argtypes = [P(OraModel), vp, i64, i64, i32, d]
+        L.ora_gate_inf.restype = d
+        L.ora_init_state.argtypes = [P(OraModel), vp, i64, vp, vp]
+        L.ora_init_state.restype = None
+        L.ora_n_state.argtypes = [P(OraModel)]
+        L.ora_n_state.restype = i32
+        L.ora_run.argtypes = [P(OraModel), i64, vp, vp, vp, vp, i64, i32, i32, vp, d, d, u64,
+                              vp, vp, vp, vp]
+        L.ora_run.restype = i32
+        L.ora_net_run.argtypes = [P(OraModel), i64, vp, vp, vp, vp, d, vp, u32, d, u64, vp,
+                                  i64, i32, vp]
+        L.ora_net_run.restype = i32
+        L.ora_syn_deliver.argtypes = [i64, vp, vp, vp, d, vp, vp, vp]
+        L.ora_syn_deliver.restype = None
+        L.ora_bptt.argtypes = [P(OraModel), i64, vp, vp, i32, vp, vp, vp, i32, d, vp, vp, vp, vp]
+        L.ora_bptt.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# random numbers (published definitions)
+# --------------------------------------------------------------------------
+def philox4x32_10(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().ora_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def noise(seed: int, nid: int, t: int) -> float:
+    return float(lib().ora_noise(seed, nid, t))
+
+
+def event_word(seed: int, nid: int, t: int) -> int:
+    return int(lib().ora_event_word(seed, nid, t))
+
+
+# --------------------------------------------------------------------------
+# single-neuron pieces
+# --------------------------------------------------------------------------
+def rate(form: str, coefs, V: float):
+    """(value, dvalue/dV) of one rate function."""
+    k = (ctypes.c_double * 4)(*[float(x) for x in coefs])
+    dv = ctypes.c_double()
+    r = lib().ora_rate(FORMS[form], k, float(V), ctypes.byref(dv))
+    return float(r), float(dv.value)
+
+
+def n_state(model: dict) -> int:
+    return 1 + len(model["gates"]) + (2 if model.get("syn") else 0)
+
+
+def init_state(model: dict, v0, coef=None) -> np.ndarray:
+    v0 = _f64(np.atleast_1d(v0))
+    n = v0.shape[0]
+    st = np.zeros((n_state(model), n), dtype=np.float64)
+    coef = _f64(coef)
+    s = model_to_struct(model)
+    lib().ora_init_state(ctypes.byref(s), _p(coef), n, _p(v0), _p(st))
+    return st
+
+
+def run(model: dict, state: np.ndarray, T: int, t0: int = 0, *, i_const=None, noise_mu=None,
+        noise_sigma=None, seed: int = 0, i_dense=None, coef=None, cm=None, ids=None,
+        record_v: bool = False, record_spikes: bool = True, level: bool = False):
+    """Advance independent neurons T steps in place.  Returns dict with
+    'spikes' [T][n] uint8 (upward crossings), 'v' [T][n] (optional) and
+    'level' [n] (count of steps with V >= v_th, optional)."""
+    s = model_to_struct(model)
+    n = state.shape[1]
+    assert state.dtype == np.float64 and state.flags.c_contiguous
+    if i_dense is not None:
+        mode, i_dense = IN_DENSE, _f64(i_dense)
+        assert i_dense.shape == (T, n)
+    elif noise_mu is not None:
+        mode = IN_NOISE
+    elif i_const is not None:
+        mode = IN_CONST
+        i_const = _f64(i_const)
+    else:
+        mode = IN_NONE
+    coef, cm = _f64(coef), _f64(cm)
+    ids = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
+    spk = np.zeros((T, n), np.uint8) if record_spikes else None
+    vr = np.zeros((T, n), np.float64) if record_v else None
+    lv = np.zeros(n, np.float64) if level else None
+    rc = lib().ora_run(ctypes.byref(s), n, _p(coef), _p(cm), _p(ids), _p(state), int(t0), int(T),
+                       mode, _p(i_const), float(noise_mu or 0.0), float(noise_sigma or 0.0),
+                       int(seed), _p(i_dense), _p(spk), _p(vr), _p(lv))
+    if rc != 0:
+        raise ValueError("oracle rejected the model (rc=%d)" % rc)
+    return {"spikes": spk, "v": vr, "level": lv}
+
+
+def net_run(model: dict, state: np.ndarray, csr, w_scale: float, T: int, t0: int = 0, *,
+            ext_mask=None, ext_thresh: int = 0, w_ext: float = 0.0, seed: int = 0, i_const=None):
+    """Recurrent network, T steps in place; returns spikes [T][n] uint8."""
+    s = model_to_struct(model)
+    n = state.shape[1]
+    row_ptr = np.ascontiguousarray(csr[0], dtype=np.int64)
+    col = np.ascontiguousarray(csr[1], dtype=np.int32)
+    w = _f64(csr[2])
+    em = None if ext_mask is None else np.ascontiguousarray(ext_mask, dtype=np.uint8)
+    ic = _f64(i_const)
+    spk = np.zeros((T, n), np.uint8)
+    rc = lib().ora_net_run(ctypes.byref(s), n, _p(state), _p(row_ptr), _p(col), _p(w),
+                           float(w_scale), _p(em), int(ext_thresh), float(w_ext), int(seed),
+                           _p(ic), int(t0), int(T), _p(spk))
+    if rc != 0:
+        raise ValueError("oracle rejected the network (rc=%d)" % rc)
+    return spk
+
+
+def syn_deliver(csr, w_scale: float, spikes, ge, gi):
+    n = len(csr[0]) - 1
+    row_ptr = np.ascontiguousarray(csr[0], dtype=np.int64)
+    col = np.ascontiguousarray(csr[1], dtype=np.int32)
+    w = _f64(csr[2])
+    s = np.ascontiguousarray(spikes, dtype=np.uint8)
+    assert ge.dtype == np.float64 and gi.dtype == np.float64
+    lib().ora_syn_deliver(n, _p(row_ptr), _p(col), _p(w), float(w_scale), _p(s), _p(ge), _p(gi))
+
+
+def bptt(model: dict, state0: np.ndarray, I: np.ndarray, *, cm=None, dL_dr=None, dL_dV=None,
+         smooth: bool = False, beta: float = 0.2):
+    """Forward + reverse sweep.  Returns (r, dI, dCm, dx0)."""
+    s = model_to_struct(model)
+    ns, n = state0.shape
+    T = I.shape[0]
+    st = _f64(state0)
+    I = _f64(I)
+    cm, dL_dr, dL_dV = _f64(cm), _f64(dL_dr), _f64(dL_dV)
+    r = np.zeros(n)
+    dI = np.zeros((T, n))
+    dC = np.zeros(n)
+    dx0 = np.zeros((ns, n))
+    rc = lib().ora_bptt(ctypes.byref(s), n, _p(cm), _p(st), int(T), _p(I), _p(dL_dr), _p(dL_dV),
+                        1 if smooth else 0, float(beta), _p(r), _p(dI), _p(dC), _p(dx0))
+    if rc != 0:
+        raise ValueError("oracle rejected the model (rc=%d)" % rc)
+    return r, dI, dC, dx0
+
+
+# --------------------------------------------------------------------------
+# spike bookkeeping
+# --------------------------------------------------------------------------
+def spike_times(spk: np.ndarray):
+    """List of step-index arrays, one per neuron, from a [T][n] 0/1 raster."""
+    return [np.nonzero(spk[:, i])[0] for i in range(spk.shape[1])]
+
+
+def unpack_bits(bits: np.ndarray, n: int) -> np.ndarray:
+    """[T][words] uint32 little-endian bit rows -> [T][n] uint8 raster."""
+    b = np.ascontiguousarray(bits).view(np.uint8)
+    out = np.unpackbits(b.reshape(bits.shape[0], -1), axis=1, bitorder="little")
+    return out[:, :n]
+
+
+# --------------------------------------------------------------------------
+# dense pieces of the differentiable layer (plain definitions, FP64)
+# --------------------------------------------------------------------------
+def projection(S: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """I = S W: input projection of the linear layer in front of the HH
+    neurons (the Sequential(Linear, HHNode) composition of Fig. 1e)."""
+    return np.asarray(S, np.float64) @ np.asarray(W, np.float64)
+
+
+def projection_weight_grad(S: np.ndarray, dI: np.ndarray) -> np.ndarray:
+    """dW = S^T dI."""
+    return np.asarray(S, np.float64).T @ np.asarray(dI, np.float64)
+
+
+def readout_ce(r: np.ndarray, W: np.ndarray, b: np.ndarray, labels: np.ndarray):
+    """logits = r W + b; mean cross entropy; gradients wrt r, W, b."""
+    r = np.asarray(r, np.float64)
+    z = r @ np.asarray(W, np.float64) + np.asarray(b, np.float64)
+    zmax = z.max(axis=1, keepdims=True)
+    ez = np.exp(z - zmax)
+    prob = ez / ez.sum(axis=1, keepdims=True)
+    B = r.shape[0]
+    loss = float(np.mean(-np.log(prob[np.arange(B), labels])))
+    dz = prob.copy()
+    dz[np.arange(B), labels] -= 1.0
+    dz /= B
+    return loss, dz @ np.asarray(W, np.float64).T, r.T @ dz, dz.sum(axis=0), z
+
+
+# --------------------------------------------------------------------------
+# MLP surrogate: x -> silu(x W1 + b1) -> silu(. W2 + b2) -> . W3 + b3
+# --------------------------------------------------------------------------
+def silu(x):
+    return x / (1.0 + np.exp(-x))
+
+
+def dsilu(x):
+    s = 1.0 / (1.0 + np.exp(-x))
+    return s * (1.0 + x * (1.0 - s))
+
+
+def mlp_forward(params, x):
+    """params = [W1, b1, W2, b2, W3, b3] with Wk [in, out]."""
+    W1, b1, W2, b2, W3, b3 = [np.asarray(p, np.float64) for p in params]
+    x = np.asarray(x, np.float64)
+    a1 = x @ W1 + b1
+    h1 = silu(a1)
+    a2 = h1 @ W2 + b2
+    h2 = silu(a2)
+    y = h2 @ W3 + b3
+    return y, (x, a1, h1, a2, h2)
+
+
+def mlp_backward(params, cache, dy):
+    """Gradients of sum(dy * y) wrt every parameter, and wrt x."""
+    W1, b1, W2, b2, W3, b3 = [np.asarray(p, np.float64) for p in params]
+    x, a1, h1, a2, h2 = cache
+    dy = np.asarray(dy, np.float64)
+    gW3 = h2.T @ dy
+    gb3 = dy.sum(0)
+    dh2 = dy @ W3.T
+    da2 = dh2 * dsilu(a2)
+    gW2 = h1.T @ da2
+    gb2 = da2.sum(0)
+    dh1 = da2 @ W2.T
+    da1 = dh1 * dsilu(a1)
+    gW1 = x.T @ da1
+    gb1 = da1.sum(0)
+    dx = da1 @ W1.T
+    return [gW1, gb1, gW2, gb2, gW3, gb3], dx
+
+
+def mse_loss_grad(y, target):
+    """L = mean over samples of sum over outputs of (y - target)^2; dL/dy."""
+    d = np.asarray(y, np.float64) - np.asarray(target, np.float64)
+    B = d.shape[0]
+    return float(np.sum(d * d) / B), 2.0 * d / B
+
+
+def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam (Kingma & Ba, 2015, Algorithm 1), one update; step counts from 1."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v

@@ -1,0 +1,560 @@
+"""Pins for the FP64 oracle against what the model and mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors, hand-computed closed forms, exact solutions of special
+cases, a library ODE integrator (scipy) on the continuous model of Eq. (1),
+finite differences, and library autograd (torch on the CPU, float64).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2601_21407_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    rows = []
+    for ln in open(os.path.join(GOLD, name)):
+        ln = ln.strip()
+        if ln and not ln.startswith("#"):
+            rows.append(ln.split())
+    return rows
+
+
+# --------------------------------------------------------------------------
+# random numbers
+# --------------------------------------------------------------------------
+def test_philox_known_answers(ora):
+    for row in _gold("philox4x32_10_kat.txt"):
+        v = [int(x, 16) for x in row]
+        assert ora.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_noise_is_standard_normal(ora):
+    from scipy import stats
+    z = np.array([ora.noise(2, i, t) for i in range(50) for t in range(400)])
+    assert abs(z.mean()) < 0.03 and abs(z.std() - 1.0) < 0.03
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    # four consecutive steps share one Philox block but are distinct components
+    assert len({ora.noise(2, 0, t) for t in range(4)}) == 4
+
+
+def test_event_words_are_uniform(ora):
+    thr = int(0.002 * 2**32)
+    n_ev = sum(ora.event_word(3, i, t) < thr for i in range(100) for t in range(2000))
+    # Binomial(200000, 0.002): mean 400, sd 20
+    assert abs(n_ev - 400) < 100
+
+
+# --------------------------------------------------------------------------
+# rate functions
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("form,coef", [
+    ("exp", (4.0, -65.0, -18.0, 0.0)), ("sigmoid", (1.0, -35.0, -10.0, 0.0)),
+    ("linoid", (0.1, -40.0, 10.0, 0.0)), ("linoid", (-0.28, -16.2, -5.0, 0.0)),
+    ("bell", (1000.0, -35.0, 20.0, 3.3)),
+])
+def test_rate_derivative_matches_central_difference(ora, form, coef):
+    for V in np.linspace(-90, 40, 27) + 0.123:
+        r, d = ora.rate(form, coef, V)
+        h = 1e-5
+        fd = (ora.rate(form, coef, V + h)[0] - ora.rate(form, coef, V - h)[0]) / (2 * h)
+        assert abs(d - fd) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_rate_textbook_values(ora):
+    # textbook HH 1952 rate functions written in their usual form
+    V = -52.7
+    am = 0.1 * (V + 40) / (1 - np.exp(-(V + 40) / 10))
+    bm = 4 * np.exp(-(V + 65) / 18)
+    bh = 1 / (1 + np.exp(-(V + 35) / 10))
+    assert ora.rate("linoid", (0.1, -40, 10, 0), V)[0] == pytest.approx(am, rel=1e-13)
+    assert ora.rate("exp", (4, -65, -18, 0), V)[0] == pytest.approx(bm, rel=1e-13)
+    assert ora.rate("sigmoid", (1, -35, -10, 0), V)[0] == pytest.approx(bh, rel=1e-13)
+    # bell: 1/tau of the slow M current, tau = tau_max / (3.3 e^{(V+35)/20} + e^{-(V+35)/20})
+    tau = 1000.0 / (3.3 * np.exp((V + 35) / 20) + np.exp(-(V + 35) / 20))
+    assert ora.rate("bell", (1000, -35, 20, 3.3), V)[0] == pytest.approx(1 / tau, rel=1e-13)
+
+
+def test_linoid_removable_singularity(ora):
+    # A (V - B) / (1 - exp(-(V - B)/K)) -> A K at V = B, slope A/2
+    for A, B, K in [(0.1, -40.0, 10.0), (0.01, -55.0, 10.0), (-0.28, -16.2, -5.0)]:
+        r, d = ora.rate("linoid", (A, B, K, 0), B)
+        assert r == pytest.approx(A * K, rel=1e-15)
+        assert d == pytest.approx(A / 2, rel=1e-15)
+        # continuity across the series switch
+        for du in (0.999e-3, 1.001e-3, -0.999e-3, -1.001e-3):
+            V = B + du * K
+            u = du
+            exact = A * K * u / (-np.expm1(-u))
+            assert ora.rate("linoid", (A, B, K, 0), V)[0] == pytest.approx(exact, rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# steady states and fixed points
+# --------------------------------------------------------------------------
+def test_steady_state_gates_textbook(ora):
+    m = W.classic_hh()
+    st = ora.init_state(m, [-65.0])
+    g = {r[0]: (float(r[2]), float(r[3])) for r in _gold("hh1952_resting.txt")}
+    for k, name in enumerate(["m_inf", "h_inf", "n_inf"]):
+        val, tol = g[name]
+        assert abs(st[1 + k, 0] - val) < tol
+
+
+def _rest_potential(ora, m):
+    from scipy.optimize import brentq
+
+    def dv(V):
+        st = ora.init_state(m, [V])
+        ora.run(m, st, 1, record_spikes=False)
+        return st[0, 0] - V
+    return brentq(dv, -75.0, -60.0, xtol=1e-13)
+
+
+def test_resting_fixed_point(ora):
+    m = W.classic_hh()
+    vr = _rest_potential(ora, m)
+    val, tol = [(float(r[2]), float(r[3])) for r in _gold("hh1952_resting.txt") if r[0] == "v_rest"][0]
+    assert abs(vr - val) < tol
+    # the discrete map keeps (V*, x_inf(V*)) fixed for 1e5 steps
+    st = ora.init_state(m, [vr])
+    st0 = st.copy()
+    ora.run(m, st, 100000, record_spikes=False)
+    assert np.max(np.abs(st - st0)) < 1e-9
+    # exponential Euler in V has the same fixed point
+    me = W.classic_hh(v_method="ee")
+    st = ora.init_state(me, [vr])
+    ora.run(me, st, 100000, record_spikes=False)
+    assert np.max(np.abs(st - st0)) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# exactness of the discretization in special cases
+# --------------------------------------------------------------------------
+def test_exp_euler_exact_at_clamped_voltage(ora):
+    # a huge capacitance holds V fixed; each gate then obeys a linear ODE whose
+    # exact solution exponential Euler reproduces at every step
+    m = W.classic_hh(dt=0.05, C=1e300)
+    V = -48.3
+    st = ora.init_state(m, [-70.0])  # gates at x_inf(-70), far from x_inf(V)
+    p0 = st[1:, 0].copy()
+    st[0, 0] = V
+    out_n = 37
+    ora.run(m, st, out_n, record_spikes=False)
+    pairs = [(("linoid", (0.1, -40, 10, 0)), ("exp", (4, -65, -18, 0))),
+             (("exp", (0.07, -65, -20, 0)), ("sigmoid", (1, -35, -10, 0))),
+             (("linoid", (0.01, -55, 10, 0)), ("exp", (0.125, -65, -80, 0)))]
+    t = out_n * 0.05
+    for g, (ra, rb) in enumerate(pairs):
+        a = ora.rate(ra[0], ra[1], V)[0]
+        b = ora.rate(rb[0], rb[1], V)[0]
+        pinf = a / (a + b)
+        exact = pinf + (p0[g] - pinf) * np.exp(-(a + b) * t)
+        assert abs(st[1 + g, 0] - exact) < 1e-13
+    assert st[0, 0] == V
+
+
+def _leak_only(v_method, dt):
+    m = W.classic_hh(dt=dt, v_method=v_method)
+    m["channels"][0]["gbar"] = 0.0
+    m["channels"][1]["gbar"] = 0.0
+    return m
+
+
+def test_leak_only_forward_euler_closed_form(ora):
+    dt, n, I = 0.05, 500, 3.0
+    m = _leak_only("fe", dt)
+    st = ora.init_state(m, [-80.0])
+    res = ora.run(m, st, n, i_const=[I], record_v=True, record_spikes=False)
+    gL, EL = 0.3, -54.4
+    vinf = EL + I / gL
+    k = np.arange(1, n + 1)
+    exact = vinf + (-80.0 - vinf) * (1 - dt * gL) ** k
+    assert np.max(np.abs(res["v"][:, 0] - exact)) < 1e-11
+
+
+def test_leak_only_exponential_euler_is_exact_rc(ora):
+    dt, n, I = 0.1, 500, 3.0
+    m = _leak_only("ee", dt)
+    st = ora.init_state(m, [-80.0])
+    res = ora.run(m, st, n, i_const=[I], record_v=True, record_spikes=False)
+    gL, EL = 0.3, -54.4
+    vinf = EL + I / gL
+    t = dt * np.arange(1, n + 1)
+    exact = vinf + (-80.0 - vinf) * np.exp(-gL * t)
+    assert np.max(np.abs(res["v"][:, 0] - exact)) < 1e-11
+
+
+# --------------------------------------------------------------------------
+# convergence to the continuous model (library ODE solver)
+# --------------------------------------------------------------------------
+def _hh_rhs(I):
+    def f(t, y):
+        V, m, h, n = y
+        am = 0.1 * (V + 40) / (1 - np.exp(-(V + 40) / 10))
+        bm = 4 * np.exp(-(V + 65) / 18)
+        ah = 0.07 * np.exp(-(V + 65) / 20)
+        bh = 1 / (1 + np.exp(-(V + 35) / 10))
+        an = 0.01 * (V + 55) / (1 - np.exp(-(V + 55) / 10))
+        bn = 0.125 * np.exp(-(V + 65) / 80)
+        iion = 120 * m**3 * h * (V - 50) + 36 * n**4 * (V + 77) + 0.3 * (V + 54.4)
+        return [I - iion, am * (1 - m) - bm * m, ah * (1 - h) - bh * h, an * (1 - n) - bn * n]
+    return f
+
+
+def test_first_order_convergence_subthreshold(ora):
+    from scipy.integrate import solve_ivp
+    I, Tms = 2.0, 10.0
+    y0 = ora.init_state(W.classic_hh(), [-65.0])[:, 0]
+    ref = solve_ivp(_hh_rhs(I), (0, Tms), y0, method="Radau", rtol=1e-12, atol=1e-12).y[:, -1]
+    errs = []
+    for dt in (0.04, 0.02, 0.01, 0.005):
+        m = W.classic_hh(dt=dt)
+        st = ora.init_state(m, [-65.0])
+        ora.run(m, st, int(round(Tms / dt)), i_const=[I], record_spikes=False)
+        errs.append(abs(st[0, 0] - ref[0]))
+    ratios = [errs[k] / errs[k + 1] for k in range(3)]
+    assert all(1.8 < r < 2.2 for r in ratios), (errs, ratios)
+    assert errs[-1] < 1e-2
+
+
+def test_first_spike_time_converges(ora):
+    from scipy.integrate import solve_ivp
+    I = 10.0
+    y0 = ora.init_state(W.classic_hh(), [-65.0])[:, 0]
+
+    def ev(t, y):
+        return y[0]
+    ev.terminal, ev.direction = True, 1
+    sol = solve_ivp(_hh_rhs(I), (0, 20), y0, method="Radau", rtol=1e-11, atol=1e-11, events=ev)
+    t_ref = sol.t_events[0][0]
+    errs = []
+    for dt in (0.02, 0.01, 0.005, 0.0025):
+        m = W.classic_hh(dt=dt)
+        st = ora.init_state(m, [-65.0])
+        res = ora.run(m, st, int(20 / dt), i_const=[I])
+        k = np.nonzero(res["spikes"][:, 0])[0][0]
+        errs.append(abs((k + 1) * dt - t_ref))
+    assert errs[-1] < errs[0] / 4 and errs[-1] < 0.01, (t_ref, errs)
+
+
+# --------------------------------------------------------------------------
+# synapses
+# --------------------------------------------------------------------------
+def _tiny_net(n=60, fan=9, seed=5):
+    return W.net_csr(n=n, fan_out=fan, seed=seed)
+
+
+def test_syn_deliver_equals_dense_product(ora):
+    n = 200
+    csr = W.net_csr(n=n, fan_out=17, seed=9)
+    rng = np.random.default_rng(0)
+    s = (rng.random(n) < 0.3).astype(np.uint8)
+    ge, gi = np.zeros(n), np.zeros(n)
+    ora.syn_deliver(csr, 0.01, s, ge, gi)
+    Wd = np.zeros((n, n))
+    rp, col, w = csr
+    for j in range(n):
+        Wd[j, col[rp[j]:rp[j + 1]]] = w[rp[j]:rp[j + 1]]
+    arr = s.astype(float) @ Wd
+    arr_e = s.astype(float) @ np.where(Wd > 0, Wd, 0.0)
+    arr_i = s.astype(float) @ np.where(Wd < 0, -Wd, 0.0)
+    assert np.allclose(ge, 0.01 * arr_e, rtol=1e-14, atol=0)
+    assert np.allclose(gi, 0.01 * arr_i, rtol=1e-14, atol=0)
+    assert np.allclose(ge - gi, 0.01 * arr, rtol=1e-12, atol=1e-15)
+
+
+def test_csr_structure():
+    n, fan = 500, 37
+    rp, col, w = W.net_csr(n=n, fan_out=fan, seed=2)
+    assert rp[-1] == n * fan and len(col) == n * fan
+    for j in range(n):
+        row = col[rp[j]:rp[j + 1]]
+        assert len(set(row.tolist())) == fan and j not in row and np.all(np.diff(row) > 0)
+    assert np.all(w[: int(0.8 * n) * fan] > 0) and np.all(w[int(0.8 * n) * fan:] < 0)
+
+
+def test_synaptic_decay_closed_form(ora):
+    m = W.with_synapses(W.classic_hh(dt=0.1, v_method="ee"))
+    n = 4
+    csr = (np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    st = ora.init_state(m, np.full(n, -70.0))
+    g0e, g0i = 0.02, 0.05
+    st[4, :] = g0e
+    st[5, :] = g0i
+    steps = 123
+    ora.net_run(m, st, csr, 1.0, steps)
+    assert np.allclose(st[4], g0e * np.exp(-steps * 0.1 / 5.0), rtol=1e-12)
+    assert np.allclose(st[5], g0i * np.exp(-steps * 0.1 / 10.0), rtol=1e-12)
+
+
+def test_network_without_coupling_equals_independent_run(ora):
+    m = W.with_synapses(W.classic_hh(dt=0.05, v_method="ee"))
+    n = 16
+    csr = (np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    I = np.linspace(0, 15, n)
+    a = ora.init_state(m, np.full(n, -65.0))
+    b = a.copy()
+    spk_a = ora.net_run(m, a, csr, 1.0, 800, i_const=I)
+    spk_b = ora.run(m, b, 800, i_const=I)["spikes"]
+    assert np.array_equal(spk_a, spk_b)
+    assert np.allclose(a, b, rtol=0, atol=1e-12)
+
+
+def test_single_synapse_increment(ora):
+    # neuron 0 is driven to spike; it projects to neuron 1 with weight 0.7
+    m = W.with_synapses(W.classic_hh(dt=0.05, v_method="ee"))
+    n = 2
+    csr = (np.array([0, 1, 1], np.int64), np.array([1], np.int32), np.array([0.7]))
+    st = ora.init_state(m, np.full(n, -65.0))
+    I = np.array([15.0, 0.0])
+    T = 400
+    hist = []
+    for k in range(T):
+        ge_before = st[4, 1]
+        spk = ora.net_run(m, st, csr, 0.01, 1, t0=k, i_const=I)
+        hist.append((spk[0, 0], st[4, 1] - ge_before * np.exp(-0.05 / 5.0)))
+    jumps = [d for s, d in hist if s]
+    quiet = [d for s, d in hist if not s]
+    assert len(jumps) >= 2
+    assert np.allclose(jumps, 0.007, rtol=1e-10)
+    assert np.max(np.abs(quiet)) < 1e-15
+
+
+def test_external_drive_events(ora):
+    m = W.with_synapses(W.classic_hh(dt=0.1, v_method="ee"))
+    n = 3
+    csr = (np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    mask = np.array([1, 0, 1], np.uint8)
+    thr = int(0.05 * 2**32)
+    st = ora.init_state(m, np.full(n, -65.0))
+    T = 300
+    ge_hist = []
+    for k in range(T):
+        prev = st[4].copy()
+        ora.net_run(m, st, csr, 1.0, 1, t0=k, ext_mask=mask, ext_thresh=thr, w_ext=0.5, seed=11)
+        ge_hist.append(st[4] - prev * np.exp(-0.1 / 5.0))
+    ge_hist = np.array(ge_hist)
+    for i in range(n):
+        expect = np.array([0.5 if (mask[i] and ora.event_word(11, i, k + 1) < thr) else 0.0
+                           for k in range(T)])
+        assert np.allclose(ge_hist[:, i], expect, atol=1e-13)
+    assert ge_hist[:, 0].sum() > 0
+
+
+# --------------------------------------------------------------------------
+# gradients
+# --------------------------------------------------------------------------
+def _grad_case(v_method="fe", n=16, T=20, seed=0):
+    m = W.classic_hh(dt=0.025, v_method=v_method)
+    rng = np.random.default_rng(seed)
+    I = 8.0 + 6.0 * rng.standard_normal((T, n))
+    cm = 0.8 + 0.4 * rng.random(n)
+    v0 = -65.0 + 30.0 * rng.random(n)  # some neurons start near threshold
+    return m, ora_state(m, v0), I, cm, rng
+
+
+def ora_state(m, v0):
+    from oracle import oracle as O
+    return O.init_state(m, v0)
+
+
+@pytest.mark.parametrize("v_method", ["fe", "ee"])
+def test_bptt_matches_central_differences(ora, v_method):
+    m, st0, I, cm, rng = _grad_case(v_method)
+    n, T = st0.shape[1], I.shape[0]
+    cr = rng.standard_normal(n)
+    cv = rng.standard_normal((T, n)) * 0.01
+
+    def loss(I_, cm_, st_):
+        r, _, _, _ = ora.bptt(m, st_, I_, cm=cm_, dL_dr=cr, dL_dV=cv, smooth=True)
+        # the V part of the loss, recomputed from a plain forward
+        s2 = st_.copy()
+        v = ora.run(m, s2, T, i_dense=I_, cm=cm_, record_v=True, record_spikes=False)["v"]
+        return float(cr @ r + np.sum(cv * v))
+
+    r, dI, dC, dx0 = ora.bptt(m, st0, I, cm=cm, dL_dr=cr, dL_dV=cv, smooth=True)
+    h = 1e-6
+    for (t, i) in [(0, 0), (5, 3), (19, 7), (10, 15), (3, 11)]:
+        Ip, Im = I.copy(), I.copy()
+        Ip[t, i] += h
+        Im[t, i] -= h
+        fd = (loss(Ip, cm, st0) - loss(Im, cm, st0)) / (2 * h)
+        assert abs(dI[t, i] - fd) <= 1e-6 * max(abs(fd), 1e-3), (t, i, dI[t, i], fd)
+    for i in [0, 5, 9]:
+        cp, cmn = cm.copy(), cm.copy()
+        cp[i] += h
+        cmn[i] -= h
+        fd = (loss(I, cp, st0) - loss(I, cmn, st0)) / (2 * h)
+        assert abs(dC[i] - fd) <= 1e-6 * max(abs(fd), 1e-3), (i, dC[i], fd)
+    for s_ in range(st0.shape[0]):
+        for i in [2, 13]:
+            sp, sm = st0.copy(), st0.copy()
+            sp[s_, i] += h
+            sm[s_, i] -= h
+            fd = (loss(I, cm, sp) - loss(I, cm, sm)) / (2 * h)
+            assert abs(dx0[s_, i] - fd) <= 1e-6 * max(abs(fd), 1e-3), (s_, i, dx0[s_, i], fd)
+
+
+def test_bptt_dot_product_identity(ora):
+    # <dL/dI, delta I> equals the directional derivative of L along delta I
+    m, st0, I, cm, rng = _grad_case("fe", seed=3)
+    n, T = st0.shape[1], I.shape[0]
+    cv = rng.standard_normal((T, n))
+    dIdir = rng.standard_normal((T, n))
+    _, dI, _, _ = ora.bptt(m, st0, I, cm=cm, dL_dV=cv)
+
+    def L(eps):
+        s2 = st0.copy()
+        v = ora.run(m, s2, T, i_dense=I + eps * dIdir, cm=cm, record_v=True, record_spikes=False)["v"]
+        return float(np.sum(cv * v))
+    h = 1e-5
+    dd = (L(h) - L(-h)) / (2 * h)
+    # fourth-order stencil with a wider step: truncation O(h^4), round-off ~1e-16 |L| / h
+    H = 2e-3
+    dd4 = (-L(2 * H) + 8 * L(H) - 8 * L(-H) + L(-2 * H)) / (12 * H)
+    assert abs(np.sum(dI * dIdir) - dd4) <= 1e-9 * abs(dd4)
+    assert abs(dd - dd4) <= 1e-6 * abs(dd4)
+
+
+def test_level_spike_count_matches_run(ora):
+    m, st0, I, cm, rng = _grad_case("fe", n=32, T=200, seed=4)
+    r, _, _, _ = ora.bptt(m, st0, I, cm=cm, dL_dr=np.ones(32), smooth=False)
+    s2 = st0.copy()
+    lv = ora.run(m, s2, 200, i_dense=I, cm=cm, level=True, record_spikes=False)["level"]
+    assert np.array_equal(r * 200, lv)
+
+
+# --------------------------------------------------------------------------
+# dense parts, against torch autograd (CPU, float64)
+# --------------------------------------------------------------------------
+def test_readout_ce_against_torch(ora):
+    import torch
+    rng = np.random.default_rng(1)
+    r = rng.random((8, 32))
+    Wo = rng.standard_normal((32, 5))
+    b = rng.standard_normal(5)
+    lab = rng.integers(0, 5, 8)
+    loss, dr, dW, db, _ = ora.readout_ce(r, Wo, b, lab)
+    tr = torch.tensor(r, requires_grad=True)
+    tW = torch.tensor(Wo, requires_grad=True)
+    tb = torch.tensor(b, requires_grad=True)
+    tl = torch.nn.functional.cross_entropy(tr @ tW + tb, torch.tensor(lab))
+    tl.backward()
+    assert loss == pytest.approx(tl.item(), rel=1e-13)
+    assert np.allclose(dr, tr.grad.numpy(), rtol=1e-12, atol=1e-15)
+    assert np.allclose(dW, tW.grad.numpy(), rtol=1e-12, atol=1e-15)
+    assert np.allclose(db, tb.grad.numpy(), rtol=1e-12, atol=1e-15)
+
+
+def _mlp_params(rng, dims=(7, 64, 64, 6)):
+    ps = []
+    for a, b in zip(dims[:-1], dims[1:]):
+        ps += [rng.standard_normal((a, b)) / np.sqrt(a), 0.1 * rng.standard_normal(b)]
+    return ps
+
+
+def test_mlp_forward_backward_against_torch(ora):
+    import torch
+    rng = np.random.default_rng(2)
+    ps = _mlp_params(rng)
+    x = rng.standard_normal((33, 7))
+    tgt = rng.standard_normal((33, 6))
+    y, cache = ora.mlp_forward(ps, x)
+    loss, dy = ora.mse_loss_grad(y, tgt)
+    grads, dx = ora.mlp_backward(ps, cache, dy)
+    tps = [torch.tensor(p, requires_grad=True) for p in ps]
+    tx = torch.tensor(x, requires_grad=True)
+    h = torch.nn.functional.silu(tx @ tps[0] + tps[1])
+    h = torch.nn.functional.silu(h @ tps[2] + tps[3])
+    ty = h @ tps[4] + tps[5]
+    tl = ((ty - torch.tensor(tgt)) ** 2).sum() / 33
+    tl.backward()
+    assert np.allclose(y, ty.detach().numpy(), rtol=1e-13, atol=1e-14)
+    assert loss == pytest.approx(tl.item(), rel=1e-13)
+    for g, tp in zip(grads, tps):
+        assert np.allclose(g, tp.grad.numpy(), rtol=1e-11, atol=1e-14)
+    assert np.allclose(dx, tx.grad.numpy(), rtol=1e-11, atol=1e-14)
+
+
+def test_adam_against_torch(ora):
+    import torch
+    rng = np.random.default_rng(3)
+    p = rng.standard_normal(10)
+    tp = torch.tensor(p.copy(), requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros(10)
+    v = np.zeros(10)
+    for step in range(1, 6):
+        g = rng.standard_normal(10)
+        p, m, v = ora.adam_step(p, g, m, v, step, 1e-2)
+        opt.zero_grad()
+        tp.grad = torch.tensor(g)
+        opt.step()
+    assert np.allclose(p, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_bits_unpack_roundtrip(ora):
+    rng = np.random.default_rng(4)
+    n, T = 100, 7
+    r = (rng.random((T, n)) < 0.3).astype(np.uint8)
+    words = (n + 31) // 32
+    bits = np.zeros((T, words), np.uint32)
+    for t in range(T):
+        for i in range(n):
+            if r[t, i]:
+                bits[t, i // 32] |= np.uint32(1 << (i % 32))
+    assert np.array_equal(ora.unpack_bits(bits, n), r)
+
+
+def _cortical_rhs(I):
+    VT = -56.2
+
+    def f(t, y):
+        V, m, h, n, p, q = y
+        am = -0.32 * (V - VT - 13) / (np.exp(-(V - VT - 13) / 4) - 1)
+        bm = 0.28 * (V - VT - 40) / (np.exp((V - VT - 40) / 5) - 1)
+        ah = 0.128 * np.exp(-(V - VT - 17) / 18)
+        bh = 4 / (1 + np.exp(-(V - VT - 40) / 5))
+        an = -0.032 * (V - VT - 15) / (np.exp(-(V - VT - 15) / 5) - 1)
+        bn = 0.5 * np.exp(-(V - VT - 10) / 40)
+        pinf = 1 / (1 + np.exp(-(V + 35) / 10))
+        taup = 1000.0 / (3.3 * np.exp((V + 35) / 20) + np.exp(-(V + 35) / 20))
+        aq = 0.055 * (-27 - V) / (np.exp((-27 - V) / 3.8) - 1)
+        bq = 0.94 * np.exp((-75 - V) / 17)
+        iion = (50 * m**3 * h * (V - 50) + 6 * n**4 * (V + 90) + 0.3 * p * (V + 90)
+                + 0.1 * q**2 * (V - 120) + 0.15 * (V + 70))
+        return [I - iion, am * (1 - m) - bm * m, ah * (1 - h) - bh * h, an * (1 - n) - bn * n,
+                (pinf - p) / taup, aq * (1 - q) - bq * q]
+    return f
+
+
+@pytest.mark.parametrize("v_method", ["fe", "ee"])
+def test_cortical_channels_converge_to_ode(ora, v_method):
+    """Pospischil-style rate functions written in their published form,
+    integrated by a library stiff solver; the discrete map converges at
+    first order in dt on a subthreshold trace."""
+    from scipy.integrate import solve_ivp
+    I, Tms = 0.5, 10.0
+    y0 = ora.init_state(W.custom_channels(), [-68.0])[:, 0]
+    ref = solve_ivp(_cortical_rhs(I), (0, Tms), y0, method="Radau", rtol=1e-12, atol=1e-12).y[:, -1]
+    errs = []
+    for dt in (0.04, 0.02, 0.01, 0.005):
+        m = W.custom_channels(dt=dt, v_method=v_method)
+        st = ora.init_state(m, [-68.0])
+        ora.run(m, st, int(round(Tms / dt)), i_const=[I], record_spikes=False)
+        errs.append(np.max(np.abs(st[:, 0] - ref) / np.array([10, 1, 1, 1, 1, 1])))
+    ratios = [errs[k] / errs[k + 1] for k in range(3)]
+    assert all(1.7 < r < 2.3 for r in ratios), (errs, ratios)
+
+
+def test_cortical_steady_state_inftau_gate(ora):
+    # the M-type gate is given as (p_inf, 1/tau); its steady state is p_inf itself
+    m = W.custom_channels()
+    for V in (-80.0, -35.0, -10.0):
+        st = ora.init_state(m, [V])
+        assert st[4, 0] == pytest.approx(1 / (1 + np.exp(-(V + 35) / 10)), rel=1e-14)
