@@ -1,0 +1,211 @@
+/*
+ * hh.h -- C ABI of libhh, an MI355X (gfx950) library that time-steps large
+ * populations of Hodgkin-Huxley neurons with user-defined ion channels, and
+ * differentiates through them.
+ *
+ * The model is the point-neuron form of the paper's Eq. (1) (Methods,
+ * "Membrane potential and ion-channel definitions"):
+ *     C dV/dt = I - sum_X gbar_X eta_X(p) (V - E_X) - I_syn,
+ *     dp/dt   = alpha_p(V) (1 - p) - beta_p(V) p,
+ * with eta_X a product of integer powers of gate variables, discretized as in
+ * Methods, "Simplified discretization": exponential Euler for every gate,
+ * explicit Euler for V (Eq. (2)) or exponential Euler in V.  All right-hand
+ * sides of one step are evaluated at the state at the start of that step.
+ * Channels are user-defined as a conductance plus activation/deactivation
+ * rate terms ("Flexibility and extensibility").
+ *
+ * Conventions
+ *  - All array arguments are DEVICE pointers unless marked (host).  The caller
+ *    owns every buffer; the library owns only the opaque hh_model.
+ *  - Layouts are structure-of-arrays.  A population has n = N * B neurons:
+ *    B independent copies (a batch) of N neurons; neuron index b*N + i.
+ *    Per-neuron parameters are [N] arrays shared across the batch.
+ *  - A state buffer is float [n_state][n] with n_state = 2 + n_gates
+ *    (+2 when the model has conductance synapses): V, then the gates in
+ *    descriptor order, then g_e, g_i, and last V_lo.  The membrane potential
+ *    is carried as the unevaluated sum V + V_lo of two floats so that
+ *    per-step changes below half an FP32 ulp of V are not rounded away; V
+ *    alone is the potential to FP32 precision.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream) except hh_init, hh_destroy and hh_check.
+ *  - Return value: HH_OK, or a negative hh_status.  On any status other than
+ *    HH_E_HIP nothing was launched.  No exceptions cross the ABI.
+ *  - Calls that share one hh_model must not run concurrently on different
+ *    streams (the model's small scratch buffers are reused).
+ */
+#ifndef HH_H
+#define HH_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HH_MAX_GATES 8
+#define HH_MAX_CHANNELS 8
+#define HH_MAX_CH_GATES 4
+
+typedef enum {
+  HH_OK = 0,
+  HH_E_INVALID = -1,     /* malformed descriptor or argument */
+  HH_E_SHAPE = -2,       /* sizes inconsistent or out of range */
+  HH_E_HIP = -3,         /* a HIP runtime call failed */
+  HH_E_NONFINITE = -4,   /* hh_check: a state value became NaN/Inf */
+  HH_E_UNSUPPORTED = -5, /* valid request the library does not implement */
+  HH_E_OOM = -6,         /* the library could not allocate its own scratch */
+  HH_E_TIMEOUT = -7      /* hh_check: a persistent kernel gave up waiting */
+} hh_status;
+
+/* Rate-function forms, u = (V - B) / K (V in mV, rates in 1/ms):
+ *   HH_FORM_EXP      A e^u
+ *   HH_FORM_SIGMOID  A / (1 + e^u)
+ *   HH_FORM_LINOID   A (V - B) / (1 - e^{-u})        (value A K at V = B)
+ *   HH_FORM_BELL     (c e^u + e^{-u}) / A                                   */
+enum { HH_FORM_EXP = 0, HH_FORM_SIGMOID = 1, HH_FORM_LINOID = 2, HH_FORM_BELL = 3 };
+/* A gate carries either the (alpha, beta) rates of Eq. (1) or (p_inf, 1/tau). */
+enum { HH_GATE_ALPHA_BETA = 0, HH_GATE_INF_TAU = 1 };
+/* Membrane update: explicit Euler (Eq. (2)) or exponential Euler in V. */
+enum { HH_V_FE = 0, HH_V_EE = 1 };
+/* External current. */
+enum { HH_IN_NONE = 0, HH_IN_CONST = 1, HH_IN_NOISE = 2, HH_IN_DENSE = 3 };
+
+typedef struct {
+  int32_t form;
+  float A, B, K, c;
+} hh_rate;
+
+typedef struct {
+  int32_t kind;    /* HH_GATE_* */
+  hh_rate r[2];    /* (alpha, beta) or (p_inf, 1/tau) */
+} hh_gate;
+
+typedef struct {
+  float gbar, E;                 /* mS/cm^2, mV */
+  int32_t n_gates;               /* 0..HH_MAX_CH_GATES factors; 0 = leak */
+  int32_t gate[HH_MAX_CH_GATES]; /* gate index of each factor */
+  int32_t expo[HH_MAX_CH_GATES]; /* integer exponent 0..8 */
+} hh_channel;
+
+typedef struct {
+  int32_t n_gates, n_channels;
+  hh_gate gates[HH_MAX_GATES];
+  hh_channel channels[HH_MAX_CHANNELS];
+  float C_m;      /* uF/cm^2 (used when no per-neuron C_m is given) */
+  float dt;       /* ms */
+  float v_th;     /* spike threshold, mV: a spike is an upward crossing */
+  int32_t v_method;
+  int32_t has_syn;             /* exponential-decay conductance synapses */
+  float tau_e, tau_i, E_e, E_i;
+} hh_model_desc;
+
+typedef struct hh_model hh_model;
+
+/* Input current for hh_step_n / hh_backward. */
+typedef struct {
+  int32_t mode;          /* HH_IN_* */
+  const float* i_const;  /* HH_IN_CONST: [n] uA/cm^2 */
+  float mu, sigma;       /* HH_IN_NOISE: I = mu + sigma z, z standard normal */
+  uint64_t seed;         /* HH_IN_NOISE: Philox4x32-10 key */
+  const float* i_dense;  /* HH_IN_DENSE: [n_steps][n], row t is step t0 + t */
+} hh_input;
+
+/* Optional outputs of hh_step_n (any pointer may be NULL). */
+typedef struct {
+  uint32_t* spikes;   /* [n_steps][ceil(n/32)] bit i%32 of word i/32 = crossing */
+  float* v_rec;       /* [n_steps][n] V after each step */
+  float* ckpt;        /* [ceil(n_steps/ckpt_every)][n_state][n] state before
+                         steps 0, ckpt_every, 2*ckpt_every, ... of this call */
+  int32_t ckpt_every;
+  float* level;       /* [n] += number of steps ending with V >= v_th */
+} hh_outputs;
+
+/* Create a model for n = N * B neurons from a host descriptor (copied).
+ * coef: nullable [n_gates*8][N] per-neuron rate coefficients, row
+ * g*8 + r*4 + j holding (A, B, K, c)[j] of rate r of gate g; replaces the
+ * descriptor's values.  cm: nullable [N] per-neuron C_m.  Both stay owned by
+ * the caller and must outlive the model.  Errors: HH_E_INVALID for a bad
+ * descriptor (unknown form/kind, gate index out of range, dt <= 0, C_m <= 0,
+ * tau <= 0), HH_E_SHAPE for N < 1, B < 1 or n >= 2^31. */
+int32_t hh_init(hh_model** out, const hh_model_desc* desc, int64_t N, int32_t B,
+                const float* coef, const float* cm);
+int32_t hh_destroy(hh_model* m);
+const char* hh_status_string(int32_t status);
+int32_t hh_n_state(const hh_model* m);
+
+/* Fusion depth: the number of steps one kernel launch keeps in registers
+ * (Methods, "Engineering optimization": operator fusion).  Default 32. */
+int32_t hh_set_fusion(hh_model* m, int32_t k_steps);
+
+/* state <- (V0, p_inf(V0) for every gate, g_e = g_i = 0, V_lo = 0).  v0: nullable [n]
+ * device array; when NULL every neuron starts at v0_scalar. */
+int32_t hh_init_state(hh_model* m, float* state, const float* v0, float v0_scalar, void* stream);
+
+/* Advance `state` by n_steps steps starting at absolute step t0 (the noise
+ * generator is keyed by the absolute step, so runs can be split and resumed).
+ * With a CSR attached (hh_attach_csr) the population is a recurrent network
+ * and each step also delivers that step's spikes through the synapses.
+ * Errors: HH_E_SHAPE for n_steps < 0 or ckpt_every < 1 with ckpt set;
+ * HH_E_INVALID for a missing input array. */
+int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const hh_input* in,
+                  const hh_outputs* out, void* stream);
+
+/* Synaptic connectivity for the recurrent network (Results, cortical network
+ * with sparse synapses and indirect addressing): CSR by source neuron,
+ * row_ptr int64 [n+1], col int32 [nnz] target ids, w float [nnz].  A spike of
+ * source j adds w_scale * w to g_e of each target for w > 0 and
+ * w_scale * |w| to g_i for w < 0, one step after the spike.  Buffers stay
+ * owned by the caller.  Requires has_syn and B == 1. */
+int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, const float* w,
+                      int64_t nnz, float w_scale);
+/* External Poisson drive: neurons with ext_mask[i] != 0 receive w_ext on g_e
+ * at step t when the stream-1 Philox4x32-10 word of (seed, i, t) is below
+ * thresh (event probability thresh / 2^32 per step).  ext_mask: device [n]. */
+int32_t hh_set_external(hh_model* m, const uint8_t* ext_mask, uint32_t thresh, float w_ext,
+                        uint64_t seed);
+
+/* One synaptic delivery outside the time loop: compacts the spiking sources
+ * of `spike_bits` ([ceil(n/32)] words) and adds their synaptic increments to
+ * g_e/g_i of `state`.  n_spikes_out: nullable device int32, receives the
+ * number of spiking sources.  Accumulation is in 64-bit fixed point
+ * (2^-40 mS/cm^2), so the result does not depend on the order of arrivals. */
+int32_t hh_syn_propagate(hh_model* m, const uint32_t* spike_bits, float* state,
+                         int32_t* n_spikes_out, void* stream);
+
+/* Backpropagation through time (Methods, "Gradient learning support",
+ * "Engineering optimization": manual gradients with re-computation).
+ * Forward must have been run from step 0 with dense input and checkpoints
+ * every ckpt_every steps (ckpt as written by hh_step_n).  The loss is
+ *   L = sum_i dL_dlevel[i] * r_i + sum_{t,i} dL_dV[t][i] * V_{t+1,i},
+ * r_i = (1/T) sum_{t=1..T} H(V_t - v_th), differentiated with the surrogate
+ * dH/dV = beta s (1 - s), s = sigmoid(beta (V - v_th)).
+ * Outputs: dI [T][n] = dL/dI_t (written), dCm [N] = dL/dC_m summed over the
+ * batch (written; nullable), dx0 [n_state][n] (written; nullable).
+ * workspace: device scratch of hh_backward_workspace() bytes.
+ * Errors: HH_E_UNSUPPORTED for models with synapses; HH_E_SHAPE for T < 1,
+ * ckpt_every not a multiple of the register segment (10) nor 1..10. */
+int32_t hh_backward(hh_model* m, const float* ckpt, int32_t ckpt_every, const hh_input* in,
+                    int32_t T, const float* dL_dlevel, const float* dL_dV, float beta,
+                    float* dI, float* dCm, float* dx0, void* workspace, size_t workspace_bytes,
+                    void* stream);
+size_t hh_backward_workspace(const hh_model* m, int32_t ckpt_every);
+
+/* Synchronize `stream` and report the first neuron whose state is not finite
+ * (HH_E_NONFINITE, *first_bad = its index) or a persistent-kernel timeout
+ * (HH_E_TIMEOUT).  Clears the flags. */
+int32_t hh_check(hh_model* m, int64_t* first_bad, void* stream);
+
+/* Dense input projection of the layer in front of the neurons (the Linear
+ * of the Sequential(Linear, HHNode) composition, Fig. 1e), on MFMA:
+ *   out[M][N] (float) = A[M][K] (bf16) x W[K][N] (bf16), fp32 accumulate. */
+int32_t hh_proj_forward(const uint16_t* A, const uint16_t* W, float* out, int32_t M, int32_t N,
+                        int32_t K, void* stream);
+/* Weight gradient dW[K][N] (float, written) = A^T dOut, A [M][K] bf16,
+ * dOut [M][N] float (split into two bf16 terms inside the kernel). */
+int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dW, int32_t M, int32_t N,
+                      int32_t K, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,281 @@
+// hh_device.h -- device-side building blocks of the HH hot path for gfx950.
+//
+// Per-neuron arithmetic of one time step (Methods, Eq. (1)-(2), "Simplified
+// discretization"): rate functions, exponential-Euler gates, channel currents,
+// the membrane update and threshold crossing.  Everything here is evaluated
+// in FP32 registers; transcendental functions go straight to the CDNA
+// special-function unit (v_exp_f32 = 2^x, v_log_f32 = log2, v_rcp_f32,
+// v_sqrt_f32, v_sin_f32/v_cos_f32 taking their argument in revolutions).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hhk {
+
+constexpr int kMaxGates = 8;
+constexpr int kMaxCh = 8;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+enum { FORM_EXP = 0, FORM_SIGMOID = 1, FORM_LINOID = 2, FORM_BELL = 3 };
+enum { KIND_AB = 0, KIND_INFTAU = 1 };
+enum { VFE = 0, VEE = 1 };
+enum { IN_NONE = 0, IN_CONST = 1, IN_NOISE = 2, IN_DENSE = 3 };
+
+// One rate function in a form ready for the exp2 unit.  With x = V*s + o =
+// log2(e) (V - B) / K:
+//   exp      r = a 2^x                       a = A
+//   sigmoid  r = a / (1 + 2^x)               a = A
+//   linoid   r = a g(u), u = x ln2,          a = A K,  g(u) = u / (1 - e^{-u})
+//   bell     r = a (c 2^x + 2^-x)            a = 1 / A
+// ik = 1/K scales the V-derivatives.
+struct KRate {
+  float s, o, a, c, ik;
+};
+
+// Kernel-argument image of a model (uniform across the grid).
+struct KModel {
+  int32_t n_gates, n_ch, v_method, has_syn;
+  int32_t kind[kMaxGates];
+  int32_t form[kMaxGates][2];
+  KRate rate[kMaxGates][2];
+  int32_t cexp[kMaxCh][kMaxGates];  // exponent of gate g in channel c (0 = absent)
+  float gbar[kMaxCh], E[kMaxCh];
+  float dt, v_th, C, kdt;           // kdt = -dt log2(e)
+  float decay_e, decay_i, E_e, E_i; // synapse decay factors over one dt
+};
+
+// ---------------------------------------------------------------------------
+// special-function unit
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Rate value (and V-derivative when D) of one rate function.  `form` is
+// uniform across the wavefront, so the switch is a scalar branch.
+template <bool D>
+__device__ __forceinline__ float rate_eval(int form, const KRate& k, float V, float* dr) {
+  const float x = fmaf(V, k.s, k.o);
+  float r;
+  switch (form) {
+    case FORM_EXP: {
+      r = k.a * ex2(x);
+      if (D) *dr = r * k.ik;
+      break;
+    }
+    case FORM_SIGMOID: {
+      const float q = rcp(1.0f + ex2(x));
+      r = k.a * q;
+      if (D) *dr = -r * k.ik * (1.0f - q);
+      break;
+    }
+    case FORM_LINOID: {
+      // g(u) = u / (1 - e^{-u}) has a removable singularity at u = 0.  Below
+      // |u| = 1/4 its Bernoulli series (to u^4) is used: truncation < 1e-8,
+      // while the direct quotient loses ~6e-8/|u| to cancellation.
+      const float u = x * kLn2;
+      const float E = ex2(-x);
+      const float om = 1.0f - E;
+      const float ro = rcp(om);
+      const float u2 = u * u;
+      const bool small = fabsf(u) < 0.25f;
+      const float gs = fmaf(u, 0.5f, fmaf(u2, fmaf(u2, -1.0f / 720.0f, 1.0f / 12.0f), 1.0f));
+      const float g = small ? gs : u * ro;
+      r = k.a * g;
+      if (D) {
+        const float gps = fmaf(u, fmaf(u2, fmaf(u2, 1.0f / 5040.0f, -1.0f / 180.0f), 1.0f / 6.0f), 0.5f);
+        const float gpd = (om - u * E) * ro * ro;
+        *dr = k.a * k.ik * (small ? gps : gpd);
+      }
+      break;
+    }
+    default: {  // FORM_BELL
+      const float ep = ex2(x), em = ex2(-x);
+      r = k.a * fmaf(k.c, ep, em);
+      if (D) *dr = k.a * k.ik * fmaf(k.c, ep, -em);
+      break;
+    }
+  }
+  return r;
+}
+
+// Derived constants of one rate from its (A, B, K, c) -- per-lane version
+// for per-neuron coefficient tables.
+__device__ __forceinline__ KRate derive_rate(int form, float A, float B, float K, float c) {
+  KRate k;
+  k.ik = 1.0f / K;
+  k.s = kLog2e / K;
+  k.o = -B * k.s;
+  k.c = c;
+  k.a = (form == FORM_LINOID) ? A * K : (form == FORM_BELL ? 1.0f / A : A);
+  return k;
+}
+
+// Integer power with a wave-uniform exponent.
+__device__ __forceinline__ float ipow(float p, int e) {
+  switch (e) {
+    case 0: return 1.0f;
+    case 1: return p;
+    case 2: return p * p;
+    case 3: return p * p * p;
+    case 4: { const float q = p * p; return q * q; }
+    default: {
+      float r = 1.0f;
+      for (int j = 0; j < e; ++j) r *= p;
+      return r;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one neuron, one step (Jacobi: every right-hand side at the start state)
+// ---------------------------------------------------------------------------
+// Register arrays sized for NG gates (at least one slot so that leak-only
+// models, NG = 0, still compile).
+template <int NG>
+constexpr int ng1 = NG > 0 ? NG : 1;
+
+template <int NG>
+struct LaneRates {
+  KRate r[ng1<NG>][2];
+};
+
+template <int NG>
+__device__ __forceinline__ void load_rates(const KModel& M, const float* __restrict__ coef,
+                                           int64_t pidx, int64_t N, LaneRates<NG>& L) {
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (coef) {
+        const float* cp = coef + (int64_t)(g * 8 + r * 4) * N + pidx;
+        L.r[g][r] = derive_rate(M.form[g][r], cp[0], cp[N], cp[2 * N], cp[3 * N]);
+      } else {
+        L.r[g][r] = M.rate[g][r];
+      }
+    }
+}
+
+// V is carried as an unevaluated sum vh + vl of two floats: the per-step
+// change of V near rest is far below half an FP32 ulp of V (3.8e-6 mV at
+// -65 mV), and rounding it into vh alone would stall slow subthreshold
+// drift.  The increment is added with an exact two-sum.
+__device__ __forceinline__ void add_to_v(float& vh, float& vl, float dv) {
+  const float y = dv + vl;
+  const float t = vh + y;
+  const float bp = t - vh;
+  const float ap = t - bp;
+  vl = (vh - ap) + (y - bp);
+  vh = t;
+}
+
+// e^{-z} - 1 for z >= 0 without cancellation at small z (series below 0.1,
+// truncation < 2e-9 relative).
+__device__ __forceinline__ float expm1_neg(float z) {
+  // -z + z^2/2 - z^3/6 + z^4/24 - z^5/120
+  const float s = z * fmaf(z, fmaf(z, fmaf(z, fmaf(z, -1.0f / 120.0f, 1.0f / 24.0f), -1.0f / 6.0f), 0.5f), -1.0f);
+  return (z < 0.1f) ? s : ex2(-z * kLog2e) - 1.0f;
+}
+
+// Advance the gates and V by one step (Jacobi: all right-hand sides at the
+// start-of-step state).  p is updated in place; (vh, vl) likewise.
+// I: external current; ge, gi: synaptic conductances held over the step.
+template <int NG>
+__device__ __forceinline__ void neuron_step(const KModel& M, const LaneRates<NG>& L, float dtC,
+                                            float& vh, float& vl, float (&p)[ng1<NG>], float I,
+                                            float ge, float gi) {
+  const float V = vh;
+  // channel terms at the start-of-step gates: total conductance gsum and
+  // sum of g_X E_X, so that I_ion + I_syn = gsum V - esum
+  float gsum = ge + gi;
+  float esum = fmaf(ge, M.E_e, gi * M.E_i);
+#pragma unroll
+  for (int c = 0; c < kMaxCh; ++c) {
+    if (c >= M.n_ch) break;
+    float eta = M.gbar[c];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int e = M.cexp[c][g];
+      if (e) eta *= ipow(p[g], e);
+    }
+    gsum += eta;
+    esum = fmaf(eta, M.E[c], esum);
+  }
+  // gates by exponential Euler at V_t
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const float r0 = rate_eval<false>(M.form[g][0], L.r[g][0], V, nullptr);
+    const float r1 = rate_eval<false>(M.form[g][1], L.r[g][1], V, nullptr);
+    float pinf, e;
+    if (M.kind[g] == KIND_AB) {
+      const float s = r0 + r1;
+      pinf = r0 * rcp(s);
+      e = ex2(s * M.kdt);
+    } else {
+      pinf = r0;
+      e = ex2(r1 * M.kdt);
+    }
+    p[g] = fmaf(p[g] - pinf, e, pinf);
+  }
+  // membrane
+  float dv;
+  if (M.v_method == VFE) {
+    const float iion = fmaf(gsum, vl, fmaf(gsum, V, -esum));
+    dv = dtC * (I - iion);
+  } else {
+    // V' - V = (V - V_inf) (e^{-dt gsum / C} - 1)
+    const float vinf = (I + esum) * rcp(gsum);
+    dv = ((V - vinf) + vl) * expm1_neg(gsum * dtC);
+  }
+  add_to_v(vh, vl, dv);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller
+// ---------------------------------------------------------------------------
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    U4 n;
+    n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    n.y = (uint32_t)p1;
+    n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    n.w = (uint32_t)p0;
+    c = n;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Four standard normals of the noise block (seed, id, blk): Box-Muller on
+// word pairs, u = (w + 1/2) 2^-32.
+__device__ __forceinline__ void normals4(uint64_t seed, uint32_t id, uint64_t blk, float (&z)[4]) {
+  U4 c = {(uint32_t)blk, (uint32_t)(blk >> 32), id, 0u};
+  const U4 w = philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const float s = 2.3283064365386963e-10f;  // 2^-32
+  const float h = 1.1641532182693481e-10f;  // 2^-33
+  const float u0 = fmaf((float)w.x, s, h), u1 = fmaf((float)w.y, s, h);
+  const float u2 = fmaf((float)w.z, s, h), u3 = fmaf((float)w.w, s, h);
+  // -2 ln u = -2 ln2 log2 u
+  const float ra = __builtin_amdgcn_sqrtf(-2.0f * kLn2 * __builtin_amdgcn_logf(u0));
+  const float rb = __builtin_amdgcn_sqrtf(-2.0f * kLn2 * __builtin_amdgcn_logf(u2));
+  // v_cos_f32 / v_sin_f32 take revolutions: cos(2 pi u)
+  z[0] = ra * __builtin_amdgcn_cosf(u1);
+  z[1] = ra * __builtin_amdgcn_sinf(u1);
+  z[2] = rb * __builtin_amdgcn_cosf(u3);
+  z[3] = rb * __builtin_amdgcn_sinf(u3);
+}
+
+__device__ __forceinline__ uint32_t event_word(uint64_t seed, uint32_t id, uint64_t t) {
+  U4 c = {(uint32_t)t, (uint32_t)(t >> 32), id, 1u};
+  return philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32)).x;
+}
+
+}  // namespace hhk

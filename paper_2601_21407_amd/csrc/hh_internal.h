@@ -1,0 +1,62 @@
+// hh_internal.h -- host-side model object and kernel launchers of libhh.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/hh.h"
+#include "hh_device.h"
+
+struct StepArgs {
+  float* state;
+  int64_t n, N;
+  const float* coef;
+  const float* cm;
+  int64_t t0;
+  int32_t nsteps, k_base;
+  int32_t in_mode;
+  const float* i_const;
+  float mu, sigma;
+  uint64_t seed;
+  const float* i_dense;  // row 0 = step k_base of the call
+  uint32_t* spikes;      // row 0 = step k_base of the call
+  int64_t words;
+  float* v_rec;          // row 0 = step k_base of the call
+  float* ckpt;           // slot 0 = step 0 of the call
+  int32_t ckpt_every;
+  float* level;
+  int32_t* bad;
+};
+
+struct hh_model {
+  hh_model_desc desc;
+  hhk::KModel km;
+  int64_t N, n;
+  int32_t B;
+  const float* coef;
+  const float* cm;
+  int32_t k_fuse;
+  int device;
+  // device flags: [0] first non-finite neuron (INT32_MAX = none), [1] timeout
+  int32_t* d_flags;
+  // recurrent network
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const float* w;
+  int64_t nnz;
+  float w_scale;
+  const uint8_t* ext_mask;
+  uint32_t ext_thresh;
+  float w_ext;
+  uint64_t ext_seed;
+  // scratch for synaptic delivery: int64 accumulators [2][2][n], spike list [n],
+  // counters and the grid barrier
+  void* d_scratch;
+  size_t scratch_bytes;
+};
+
+hipError_t launch_init_state(const hh_model* m, float* state, const float* v0, float v0s,
+                             hipStream_t s);
+hipError_t launch_step(const hh_model* m, const StepArgs& a, hipStream_t s);
+
+// recurrent network path of hh_step_n (hh_net.hip)
+int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_steps,
+                               const hh_input* in, const hh_outputs* out, void* stream);

@@ -1,0 +1,391 @@
+// hh_net.hip -- recurrent network of HH neurons with conductance synapses
+// delivered through a CSR connectivity (Results, cortical network; sparse
+// synapses with indirect addressing).
+//
+// Time loop: one persistent cooperative kernel keeps every neuron's state in
+// registers for the whole run.  Per step:
+//   A  each lane advances its neuron with the conductances held over the
+//      step, decays them, adds its external Poisson event, and detects an
+//      upward threshold crossing;
+//      the block compacts its spiking neurons (wave ballot, mbcnt rank, one
+//      LDS atomic per wave) and scatters their CSR rows into the arrival
+//      accumulator of this step (64-bit fixed point, 2^-40 mS/cm^2 per unit,
+//      so the sum does not depend on the order of arrival);
+//   -- grid barrier --
+//   B  each lane takes (and clears) its own arrivals into g_e, g_i.
+// Two accumulator buffers alternate between steps, so one barrier per step
+// suffices.
+//
+// hh_syn_propagate runs the same delivery once, outside the time loop, as
+// three kernels: global compaction, one wavefront per spiking row, apply.
+#include <string.h>
+
+#include <cmath>
+
+#include "hh_internal.h"
+
+using namespace hhk;
+
+namespace {
+
+constexpr float kFix = 1099511627776.0f;        // 2^40
+constexpr float kUnfix = 9.094947017729282e-13f;  // 2^-40
+constexpr int kNetBlock = 512;
+
+struct NetArgs {
+  float* state;
+  int64_t n;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const float* w;
+  float w_scale;
+  const uint8_t* ext_mask;
+  uint32_t ext_thresh;
+  float w_ext;
+  uint64_t ext_seed;
+  const float* i_const;
+  int64_t t0;
+  int32_t nsteps;
+  uint32_t* spikes;
+  int64_t words;
+  unsigned long long* acc;  // [2 buffers][2 (e, i)][n]
+  unsigned* bar;            // [0] arrivals, [1] generation
+  int32_t* flags;           // [0] first non-finite neuron, [1] timeout
+  uint32_t spin_limit;
+};
+
+// Sense-reversing grid barrier over co-resident blocks.  Every wait is
+// bounded: after spin_limit polls the block flags a timeout, and any block
+// that sees the flag leaves the time loop, so the grid always drains.
+__device__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen, uint32_t spin_limit,
+                             int32_t* flags, int* s_ok) {
+  // make this lane's scatter atomics performed at device scope before the
+  // block announces its arrival
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned g = gen;
+    int ok = 1;
+    const unsigned arrived =
+        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[1], g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (++spins > spin_limit) {
+          ok = 0;
+          __hip_atomic_fetch_or(&flags[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    if (__hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+    gen = g + 1;
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+__device__ __forceinline__ void deliver_row(const int64_t* __restrict__ row_ptr,
+                                            const int32_t* __restrict__ col,
+                                            const float* __restrict__ w, float scale40, int j,
+                                            unsigned long long* acc_e, unsigned long long* acc_i,
+                                            int lane0, int stride) {
+  const int64_t r0 = row_ptr[j], r1 = row_ptr[j + 1];
+  for (int64_t q = r0 + lane0; q < r1; q += stride) {
+    const int32_t tgt = col[q];
+    const float wv = w[q];
+    const unsigned long long inc = (unsigned long long)__float2ull_rn(fabsf(wv) * scale40);
+    atomicAdd(wv > 0.0f ? &acc_e[tgt] : &acc_i[tgt], inc);
+  }
+}
+
+template <int NG>
+__global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
+  __shared__ int s_list[kNetBlock];
+  __shared__ int s_cnt;
+  __shared__ int s_ok;
+  const int64_t n = A.n;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool act = i < n;
+  const int64_t ii = act ? i : n - 1;
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (i - lane) >> 5;
+
+  LaneRates<NG> L;
+  load_rates<NG>(M, nullptr, 0, 1, L);
+  const float dtC = M.dt / M.C;
+  const int64_t row_ge = (int64_t)(1 + NG) * n, row_gi = (int64_t)(2 + NG) * n;
+  const int64_t row_lo = (int64_t)(3 + NG) * n;
+  float vh = A.state[ii], vl = A.state[row_lo + ii];
+  float p[ng1<NG>];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) p[g] = A.state[(int64_t)(1 + g) * n + ii];
+  float ge = A.state[row_ge + ii], gi = A.state[row_gi + ii];
+  const float I = A.i_const ? A.i_const[ii] : 0.0f;
+  const bool driven = A.ext_mask && act && A.ext_mask[i];
+  const float scale40 = A.w_scale * kFix;
+  unsigned gen = 0;
+
+  for (int k = 0; k < A.nsteps; ++k) {
+    const int64_t t = A.t0 + k;
+    const float V = vh;
+    neuron_step<NG>(M, L, dtC, vh, vl, p, I, ge, gi);
+    const bool spk = act && (V < M.v_th) && (vh >= M.v_th);
+    ge *= M.decay_e;
+    gi *= M.decay_i;
+    if (driven && event_word(A.ext_seed, (uint32_t)i, (uint64_t)(t + 1)) < A.ext_thresh) ge += A.w_ext;
+
+    // compaction of this block's spiking neurons
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    const uint64_t b = __ballot(spk);
+    if (A.spikes && lane == 0 && w0 < A.words) {
+      uint32_t* row = A.spikes + (int64_t)k * A.words;
+      row[w0] = (uint32_t)b;
+      if (w0 + 1 < A.words) row[w0 + 1] = (uint32_t)(b >> 32);
+    }
+    if (b) {
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&s_cnt, __popcll(b));
+      base = __shfl(base, 0);
+      if (spk) {
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+        s_list[base + rank] = (int)i;
+      }
+    }
+    __syncthreads();
+    const int cnt = s_cnt;
+    unsigned long long* acc_e = A.acc + (int64_t)(k & 1) * 2 * n;
+    unsigned long long* acc_i = acc_e + n;
+    for (int e = 0; e < cnt; ++e)
+      deliver_row(A.row_ptr, A.col, A.w, scale40, s_list[e], acc_e, acc_i, threadIdx.x, blockDim.x);
+
+    if (!grid_barrier(A.bar, gridDim.x, gen, A.spin_limit, A.flags, &s_ok)) break;
+
+    if (act) {
+      const unsigned long long ae = atomicExch(&acc_e[i], 0ull);
+      const unsigned long long ai = atomicExch(&acc_i[i], 0ull);
+      ge += (float)ae * kUnfix;
+      gi += (float)ai * kUnfix;
+    }
+  }
+
+  if (!act) return;
+  A.state[i] = vh;
+  A.state[row_lo + i] = vl;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) A.state[(int64_t)(1 + g) * n + i] = p[g];
+  A.state[row_ge + i] = ge;
+  A.state[row_gi + i] = gi;
+  if (!__builtin_isfinite(vh + vl + ge + gi)) atomicMin(&A.flags[0], (int32_t)i);
+}
+
+__global__ void k_net_reset(unsigned* bar) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    bar[0] = 0u;
+    bar[1] = 0u;
+  }
+}
+
+// ---- one-shot delivery -----------------------------------------------------
+__global__ void k_zero_u32(unsigned* p, int count) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < count) p[j] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ bits, int64_t n,
+                                                 int32_t* __restrict__ list, unsigned* count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool spk = i < n && ((bits[i >> 5] >> (i & 31)) & 1u);
+  const uint64_t b = __ballot(spk);
+  if (!b) return;
+  const int lane = threadIdx.x & 63;
+  unsigned base = 0;
+  if (lane == 0) base = atomicAdd(count, (unsigned)__popcll(b));
+  base = __shfl(base, 0);
+  if (spk) {
+    const unsigned rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+    list[base + rank] = (int32_t)i;
+  }
+}
+
+// One wavefront per spiking source row.
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ list,
+                                                 const unsigned* count,
+                                                 const int64_t* __restrict__ row_ptr,
+                                                 const int32_t* __restrict__ col,
+                                                 const float* __restrict__ w, float scale40,
+                                                 unsigned long long* acc_e,
+                                                 unsigned long long* acc_i) {
+  const unsigned cnt = *count;
+  const int lane = threadIdx.x & 63;
+  const unsigned waves = gridDim.x * (blockDim.x >> 6);
+  for (unsigned e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); e < cnt; e += waves)
+    deliver_row(row_ptr, col, w, scale40, list[e], acc_e, acc_i, lane, 64);
+}
+
+__global__ __launch_bounds__(256) void k_apply(float* __restrict__ ge, float* __restrict__ gi,
+                                               unsigned long long* __restrict__ acc_e,
+                                               unsigned long long* __restrict__ acc_i, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  ge[i] += (float)acc_e[i] * kUnfix;
+  gi[i] += (float)acc_i[i] * kUnfix;
+  acc_e[i] = 0ull;
+  acc_i[i] = 0ull;
+}
+
+// scratch layout
+size_t acc_bytes(int64_t n) { return (size_t)4 * n * sizeof(unsigned long long); }
+size_t list_off(int64_t n) { return acc_bytes(n); }
+size_t ctr_off(int64_t n) { return list_off(n) + (((size_t)n * 4 + 255) & ~(size_t)255); }
+size_t scratch_size(int64_t n) { return ctr_off(n) + 256; }
+
+template <int NG>
+hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_net<NG>, kNetBlock, 0);
+  if (e != hipSuccess) return e;
+  const int64_t nb = (a.n + kNetBlock - 1) / kNetBlock;
+  if (nb > (int64_t)ncu * per_cu) return hipErrorCooperativeLaunchTooLarge;
+  hipLaunchKernelGGL(k_net_reset, dim3(1), dim3(64), 0, s, a.bar);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  void* args[] = {(void*)&m->km, (void*)&a};
+  return hipLaunchCooperativeKernel((const void*)k_net<NG>, dim3((unsigned)nb), dim3(kNetBlock),
+                                    args, 0, s);
+}
+
+}  // namespace
+
+int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_steps,
+                               const hh_input* in, const hh_outputs* out, void* stream) {
+  if (in->mode != HH_IN_NONE && in->mode != HH_IN_CONST) return HH_E_UNSUPPORTED;
+  if (out->v_rec || out->ckpt || out->level) return HH_E_UNSUPPORTED;
+  if (n_steps == 0) return HH_OK;
+  NetArgs a;
+  memset(&a, 0, sizeof(a));
+  a.state = state;
+  a.n = m->n;
+  a.row_ptr = m->row_ptr;
+  a.col = m->col;
+  a.w = m->w;
+  a.w_scale = m->w_scale;
+  a.ext_mask = m->ext_mask;
+  a.ext_thresh = m->ext_thresh;
+  a.w_ext = m->w_ext;
+  a.ext_seed = m->ext_seed;
+  a.i_const = (in->mode == HH_IN_CONST) ? in->i_const : nullptr;
+  a.t0 = t0;
+  a.nsteps = n_steps;
+  a.spikes = out->spikes;
+  a.words = (m->n + 31) / 32;
+  char* sc = (char*)m->d_scratch;
+  a.acc = (unsigned long long*)sc;
+  a.bar = (unsigned*)(sc + ctr_off(m->n)) + 4;
+  a.flags = m->d_flags;
+  a.spin_limit = 1u << 24;
+  hipError_t e;
+  switch (m->km.n_gates) {
+    case 1: e = launch_net<1>(m, a, (hipStream_t)stream); break;
+    case 2: e = launch_net<2>(m, a, (hipStream_t)stream); break;
+    case 3: e = launch_net<3>(m, a, (hipStream_t)stream); break;
+    case 4: e = launch_net<4>(m, a, (hipStream_t)stream); break;
+    case 5: e = launch_net<5>(m, a, (hipStream_t)stream); break;
+    case 6: e = launch_net<6>(m, a, (hipStream_t)stream); break;
+    default: return HH_E_UNSUPPORTED;
+  }
+  if (e == hipErrorCooperativeLaunchTooLarge) return HH_E_UNSUPPORTED;
+  return e == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+extern "C" {
+
+int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, const float* w,
+                      int64_t nnz, float w_scale) {
+  if (!m || !row_ptr || (nnz > 0 && (!col || !w))) return HH_E_INVALID;
+  if (!m->km.has_syn) return HH_E_INVALID;
+  if (m->B != 1 || nnz < 0) return HH_E_SHAPE;
+  if (!(w_scale >= 0.0f) || !std::isfinite(w_scale)) return HH_E_INVALID;
+  if (!m->d_scratch) {
+    const size_t bytes = scratch_size(m->n);
+    if (hipMalloc(&m->d_scratch, bytes) != hipSuccess) {
+      m->d_scratch = nullptr;
+      return HH_E_OOM;
+    }
+    if (hipMemset(m->d_scratch, 0, bytes) != hipSuccess) return HH_E_HIP;
+    m->scratch_bytes = bytes;
+  }
+  m->row_ptr = row_ptr;
+  m->col = col;
+  m->w = w;
+  m->nnz = nnz;
+  m->w_scale = w_scale;
+  return HH_OK;
+}
+
+int32_t hh_set_external(hh_model* m, const uint8_t* ext_mask, uint32_t thresh, float w_ext,
+                        uint64_t seed) {
+  if (!m || !std::isfinite(w_ext)) return HH_E_INVALID;
+  m->ext_mask = ext_mask;
+  m->ext_thresh = thresh;
+  m->w_ext = w_ext;
+  m->ext_seed = seed;
+  return HH_OK;
+}
+
+int32_t hh_syn_propagate(hh_model* m, const uint32_t* spike_bits, float* state,
+                         int32_t* n_spikes_out, void* stream) {
+  if (!m || !spike_bits || !state) return HH_E_INVALID;
+  if (!m->row_ptr || !m->d_scratch) return HH_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = m->n;
+  char* sc = (char*)m->d_scratch;
+  // the one-shot path uses accumulator buffer 1 (the time loop starts on 0
+  // and leaves both buffers cleared)
+  unsigned long long* acc_e = (unsigned long long*)sc + 2 * n;
+  unsigned long long* acc_i = acc_e + n;
+  int32_t* list = (int32_t*)(sc + list_off(n));
+  unsigned* count = (unsigned*)(sc + ctr_off(n));
+  const int G = m->km.n_gates;
+  float* ge = state + (int64_t)(1 + G) * n;
+  float* gi = state + (int64_t)(2 + G) * n;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, count, 1);
+  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, s, spike_bits, n, list, count);
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)ncu * 8), dim3(256), 0, s, list, count, m->row_ptr,
+                     m->col, m->w, m->w_scale * kFix, acc_e, acc_i);
+  hipLaunchKernelGGL(k_apply, dim3(nb), dim3(256), 0, s, ge, gi, acc_e, acc_i, n);
+  if (n_spikes_out)
+    if (hipMemcpyAsync(n_spikes_out, count, sizeof(int32_t), hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+      return HH_E_HIP;
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+int32_t hh_backward(hh_model*, const float*, int32_t, const hh_input*, int32_t, const float*,
+                    const float*, float, float*, float*, float*, void*, size_t, void*) {
+  return HH_E_UNSUPPORTED;
+}
+size_t hh_backward_workspace(const hh_model*, int32_t) { return 0; }
+int32_t hh_proj_forward(const uint16_t*, const uint16_t*, float*, int32_t, int32_t, int32_t, void*) {
+  return HH_E_UNSUPPORTED;
+}
+int32_t hh_proj_wgrad(const uint16_t*, const float*, float*, int32_t, int32_t, int32_t, void*) {
+  return HH_E_UNSUPPORTED;
+}
+}

@@ -1,0 +1,181 @@
+// hh_step.hip -- fused multi-step kernel for independent HH neurons.
+//
+// One lane owns one neuron.  A launch loads the neuron's V, gates and rate
+// coefficients once, runs K steps in registers (operator fusion, Methods
+// "Engineering optimization") and stores the state once.  Per step it only
+// touches memory for what the caller asked to record: one 64-bit spike word
+// per wavefront (ballot), optional V trace, optional checkpoints, and dense
+// input current when the current comes from a preceding layer.
+#include "hh_internal.h"
+
+using namespace hhk;
+
+template <int NG>
+__global__ __launch_bounds__(256) void k_init_state(KModel M, float* __restrict__ state, int64_t n,
+                                                    int64_t N, const float* __restrict__ coef,
+                                                    const float* __restrict__ v0, float v0s) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  LaneRates<NG> L;
+  load_rates<NG>(M, coef, i % N, N, L);
+  const float V = v0 ? v0[i] : v0s;
+  state[i] = V;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const float r0 = rate_eval<false>(M.form[g][0], L.r[g][0], V, nullptr);
+    const float r1 = rate_eval<false>(M.form[g][1], L.r[g][1], V, nullptr);
+    state[(int64_t)(1 + g) * n + i] = (M.kind[g] == KIND_AB) ? r0 / (r0 + r1) : r0;
+  }
+  if (M.has_syn) {
+    state[(int64_t)(1 + NG) * n + i] = 0.0f;
+    state[(int64_t)(2 + NG) * n + i] = 0.0f;
+  }
+  state[(int64_t)(1 + NG + 2 * M.has_syn) * n + i] = 0.0f;  // low part of V
+}
+
+template <int NG, bool JIT>
+__global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool act = i < A.n;
+  const int64_t ii = act ? i : A.n - 1;  // ragged tail: compute on a valid copy, store nothing
+  const int64_t n = A.n;
+  const int64_t pidx = ii % A.N;
+
+  LaneRates<NG> L;
+  load_rates<NG>(M, JIT ? A.coef : nullptr, pidx, A.N, L);
+  const float dtC = A.cm ? M.dt / A.cm[pidx] : M.dt / M.C;
+
+  const int64_t row_lo = (int64_t)(1 + NG + 2 * M.has_syn) * n;  // low part of V
+  float vh = A.state[ii], vl = A.state[row_lo + ii];
+  float p[ng1<NG>];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) p[g] = A.state[(int64_t)(1 + g) * n + ii];
+  float ge = 0.0f, gi = 0.0f;
+  if (M.has_syn) {
+    ge = A.state[(int64_t)(1 + NG) * n + ii];
+    gi = A.state[(int64_t)(2 + NG) * n + ii];
+  }
+
+  // noise: one Philox block gives the normals of four consecutive steps
+  float z[4] = {0.f, 0.f, 0.f, 0.f};
+  const uint32_t nid = (uint32_t)ii;
+  if (A.in_mode == IN_NOISE && (A.t0 & 3)) {
+    normals4(A.seed, nid, (uint64_t)A.t0 >> 2, z);
+    for (int s = 0; s < (int)(A.t0 & 3); ++s) {
+      z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
+    }
+  }
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (i - lane) >> 5;  // first spike word of this wavefront
+  int lvl = 0;
+
+  for (int k = 0; k < A.nsteps; ++k) {
+    const int64_t t = A.t0 + k;
+    const int kk = A.k_base + k;
+    if (A.ckpt && (kk % A.ckpt_every) == 0 && act) {
+      float* c = A.ckpt + (int64_t)(kk / A.ckpt_every) * (2 + NG + 2 * M.has_syn) * n;
+      c[i] = vh;
+      c[row_lo + i] = vl;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) c[(int64_t)(1 + g) * n + i] = p[g];
+      if (M.has_syn) {
+        c[(int64_t)(1 + NG) * n + i] = ge;
+        c[(int64_t)(2 + NG) * n + i] = gi;
+      }
+    }
+    float I = 0.0f;
+    if (A.in_mode == IN_CONST) {
+      I = A.i_const[ii];
+    } else if (A.in_mode == IN_NOISE) {
+      if ((t & 3) == 0) normals4(A.seed, nid, (uint64_t)t >> 2, z);
+      I = fmaf(A.sigma, z[0], A.mu);
+      z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
+    } else if (A.in_mode == IN_DENSE) {
+      I = A.i_dense[(int64_t)k * n + ii];
+    }
+    const float V = vh;
+    neuron_step<NG>(M, L, dtC, vh, vl, p, I, ge, gi);
+    const float Vn = vh;
+    const bool spk = act && (V < M.v_th) && (Vn >= M.v_th);
+    if (A.spikes) {
+      const uint64_t b = __ballot(spk);
+      if (lane == 0 && w0 < A.words) {
+        uint32_t* row = A.spikes + (int64_t)k * A.words;
+        row[w0] = (uint32_t)b;
+        if (w0 + 1 < A.words) row[w0 + 1] = (uint32_t)(b >> 32);
+      }
+    }
+    if (A.v_rec && act) A.v_rec[(int64_t)k * n + i] = Vn;
+    lvl += (Vn >= M.v_th);
+    ge *= M.decay_e;
+    gi *= M.decay_i;
+  }
+
+  if (!act) return;
+  A.state[i] = vh;
+  A.state[row_lo + i] = vl;
+  float chk = vh + vl;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    A.state[(int64_t)(1 + g) * n + i] = p[g];
+    chk += p[g];
+  }
+  if (M.has_syn) {
+    A.state[(int64_t)(1 + NG) * n + i] = ge;
+    A.state[(int64_t)(2 + NG) * n + i] = gi;
+  }
+  if (A.level) A.level[i] += (float)lvl;
+  if (!__builtin_isfinite(chk)) atomicMin(A.bad, (int32_t)i);
+}
+
+template <int NG>
+static hipError_t init_ng(const hh_model* m, float* state, const float* v0, float v0s,
+                          hipStream_t s) {
+  const int bs = 256;
+  const int64_t nb = (m->n + bs - 1) / bs;
+  hipLaunchKernelGGL(k_init_state<NG>, dim3((unsigned)nb), dim3(bs), 0, s, m->km, state, m->n,
+                     m->N, m->coef, v0, v0s);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(const hh_model* m, float* state, const float* v0, float v0s,
+                             hipStream_t s) {
+  switch (m->km.n_gates) {
+    case 0: return init_ng<0>(m, state, v0, v0s, s);
+    case 1: return init_ng<1>(m, state, v0, v0s, s);
+    case 2: return init_ng<2>(m, state, v0, v0s, s);
+    case 3: return init_ng<3>(m, state, v0, v0s, s);
+    case 4: return init_ng<4>(m, state, v0, v0s, s);
+    case 5: return init_ng<5>(m, state, v0, v0s, s);
+    case 6: return init_ng<6>(m, state, v0, v0s, s);
+    case 7: return init_ng<7>(m, state, v0, v0s, s);
+    default: return init_ng<8>(m, state, v0, v0s, s);
+  }
+}
+
+template <int NG>
+static hipError_t step_ng(const hh_model* m, const StepArgs& a, hipStream_t s) {
+  // Small populations use 64-lane blocks so their few wavefronts spread over
+  // as many compute units as possible (the step is latency bound there).
+  const int bs = (a.n < 65536) ? 64 : 256;
+  const int64_t nb = (a.n + bs - 1) / bs;
+  if (a.coef)
+    hipLaunchKernelGGL((k_step<NG, true>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
+  else
+    hipLaunchKernelGGL((k_step<NG, false>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const hh_model* m, const StepArgs& a, hipStream_t s) {
+  switch (m->km.n_gates) {
+    case 0: return step_ng<0>(m, a, s);
+    case 1: return step_ng<1>(m, a, s);
+    case 2: return step_ng<2>(m, a, s);
+    case 3: return step_ng<3>(m, a, s);
+    case 4: return step_ng<4>(m, a, s);
+    case 5: return step_ng<5>(m, a, s);
+    case 6: return step_ng<6>(m, a, s);
+    case 7: return step_ng<7>(m, a, s);
+    default: return step_ng<8>(m, a, s);
+  }
+}

@@ -1,0 +1,255 @@
+"""Python binding of libhh (ctypes).  Argument marshalling only: every step of
+the method runs in the HIP kernels behind the C ABI declared in include/hh.h.
+
+Torch tensors serve as device memory; the current torch stream is passed to
+every call.  If libhh.so is missing or fails to load, importing this module
+raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhh.so")
+
+MAX_GATES, MAX_CH, MAX_CH_GATES = 8, 8, 4
+FORMS = {"exp": 0, "sigmoid": 1, "linoid": 2, "bell": 3}
+KINDS = {"ab": 0, "inftau": 1}
+VMETH = {"fe": 0, "ee": 1}
+IN_NONE, IN_CONST, IN_NOISE, IN_DENSE = 0, 1, 2, 3
+STATUS = {0: "HH_OK", -1: "HH_E_INVALID", -2: "HH_E_SHAPE", -3: "HH_E_HIP",
+          -4: "HH_E_NONFINITE", -5: "HH_E_UNSUPPORTED", -6: "HH_E_OOM", -7: "HH_E_TIMEOUT"}
+
+
+class HHError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__("%s failed: %s (%d)" % (what, STATUS.get(status, "?"), status))
+        self.status = status
+
+
+class Rate(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("A", ctypes.c_float), ("B", ctypes.c_float),
+                ("K", ctypes.c_float), ("c", ctypes.c_float)]
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("r", Rate * 2)]
+
+
+class Channel(ctypes.Structure):
+    _fields_ = [("gbar", ctypes.c_float), ("E", ctypes.c_float), ("n_gates", ctypes.c_int32),
+                ("gate", ctypes.c_int32 * MAX_CH_GATES), ("expo", ctypes.c_int32 * MAX_CH_GATES)]
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("n_gates", ctypes.c_int32), ("n_channels", ctypes.c_int32),
+                ("gates", Gate * MAX_GATES), ("channels", Channel * MAX_CH),
+                ("C_m", ctypes.c_float), ("dt", ctypes.c_float), ("v_th", ctypes.c_float),
+                ("v_method", ctypes.c_int32), ("has_syn", ctypes.c_int32),
+                ("tau_e", ctypes.c_float), ("tau_i", ctypes.c_float),
+                ("E_e", ctypes.c_float), ("E_i", ctypes.c_float)]
+
+
+class Input(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("i_const", ctypes.c_void_p), ("mu", ctypes.c_float),
+                ("sigma", ctypes.c_float), ("seed", ctypes.c_uint64), ("i_dense", ctypes.c_void_p)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("spikes", ctypes.c_void_p), ("v_rec", ctypes.c_void_p), ("ckpt", ctypes.c_void_p),
+                ("ckpt_every", ctypes.c_int32), ("level", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhh.so is not built (%s); run python -m paper_2601_21407_amd.build" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P, vp = ctypes.POINTER, ctypes.c_void_p
+    i32, i64, u32, u64, f32, sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64,
+                                   ctypes.c_float, ctypes.c_size_t)
+    sig = {
+        "hh_init": ([P(vp), P(ModelDesc), i64, i32, vp, vp], i32),
+        "hh_destroy": ([vp], i32),
+        "hh_status_string": ([i32], ctypes.c_char_p),
+        "hh_n_state": ([vp], i32),
+        "hh_set_fusion": ([vp, i32], i32),
+        "hh_init_state": ([vp, vp, vp, f32, vp], i32),
+        "hh_step_n": ([vp, vp, i64, i32, P(Input), P(Outputs), vp], i32),
+        "hh_attach_csr": ([vp, vp, vp, vp, i64, f32], i32),
+        "hh_set_external": ([vp, vp, u32, f32, u64], i32),
+        "hh_syn_propagate": ([vp, vp, vp, vp, vp], i32),
+        "hh_backward": ([vp, vp, i32, P(Input), i32, vp, vp, f32, vp, vp, vp, vp, sz, vp], i32),
+        "hh_backward_workspace": ([vp, i32], sz),
+        "hh_check": ([vp, P(i64), vp], i32),
+        "hh_proj_forward": ([vp, vp, vp, i32, i32, i32, vp], i32),
+        "hh_proj_wgrad": ([vp, vp, vp, i32, i32, i32, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+lib = _load()
+
+
+def exported_symbols():
+    """Names of the C-ABI entry points this binding uses."""
+    return [n for n in ("hh_init", "hh_destroy", "hh_status_string", "hh_n_state", "hh_set_fusion",
+                        "hh_init_state", "hh_step_n", "hh_attach_csr", "hh_set_external",
+                        "hh_syn_propagate", "hh_backward", "hh_backward_workspace", "hh_check",
+                        "hh_proj_forward", "hh_proj_wgrad")]
+
+
+def _ok(status: int, what: str):
+    if status != 0:
+        raise HHError(status, what)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def desc_from_model(model: dict) -> ModelDesc:
+    """Translate a model dictionary (see workloads) into hh_model_desc."""
+    d = ModelDesc()
+    gates, chans = model["gates"], model["channels"]
+    if len(gates) > MAX_GATES or len(chans) > MAX_CH:
+        raise ValueError("too many gates or channels")
+    d.n_gates, d.n_channels = len(gates), len(chans)
+    for g, gate in enumerate(gates):
+        d.gates[g].kind = KINDS[gate["kind"]]
+        for r, rt in enumerate(gate["rates"]):
+            d.gates[g].r[r].form = FORMS[rt[0]]
+            d.gates[g].r[r].A, d.gates[g].r[r].B, d.gates[g].r[r].K, d.gates[g].r[r].c = rt[1:5]
+    for c, ch in enumerate(chans):
+        d.channels[c].gbar, d.channels[c].E = ch["gbar"], ch["E"]
+        d.channels[c].n_gates = len(ch["gates"])
+        for k, (gi, ex) in enumerate(ch["gates"]):
+            d.channels[c].gate[k], d.channels[c].expo[k] = gi, ex
+    d.C_m, d.dt, d.v_th = model["C"], model["dt"], model["v_th"]
+    d.v_method = VMETH[model["v_method"]]
+    syn = model.get("syn")
+    d.has_syn = 1 if syn else 0
+    if syn:
+        d.tau_e, d.tau_i, d.E_e, d.E_i = syn["tau_e"], syn["tau_i"], syn["E_e"], syn["E_i"]
+    return d
+
+
+class Model:
+    """A population of n = N * B HH neurons on the current device."""
+
+    def __init__(self, model: dict, N: int, B: int = 1, coef=None, cm=None, desc=None):
+        self.model = model
+        self.N, self.B, self.n = int(N), int(B), int(N) * int(B)
+        self._keep = [coef, cm]  # the library reads these for the model's lifetime
+        self.desc = desc if desc is not None else desc_from_model(model)
+        h = ctypes.c_void_p()
+        _ok(lib.hh_init(ctypes.byref(h), ctypes.byref(self.desc), self.N, self.B, _ptr(coef),
+                        _ptr(cm)), "hh_init")
+        self.h = h
+        self.n_state = lib.hh_n_state(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.hh_destroy(self.h)
+            self.h = None
+
+    @property
+    def words(self) -> int:
+        return (self.n + 31) // 32
+
+    def set_fusion(self, k: int):
+        _ok(lib.hh_set_fusion(self.h, int(k)), "hh_set_fusion")
+
+    def new_state(self, device="cuda"):
+        return torch.empty((self.n_state, self.n), dtype=torch.float32, device=device)
+
+    def init_state(self, state, v0=None, v0_scalar: float = -65.0):
+        _ok(lib.hh_init_state(self.h, _ptr(state), _ptr(v0), float(v0_scalar), _stream()),
+            "hh_init_state")
+        return state
+
+    def step_n(self, state, n_steps: int, t0: int = 0, *, i_const=None, noise=None, i_dense=None,
+               spikes=None, v_rec=None, ckpt=None, ckpt_every: int = 1, level=None):
+        """noise = (mu, sigma, seed)."""
+        inp = Input()
+        if i_dense is not None:
+            inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
+        elif noise is not None:
+            inp.mode = IN_NOISE
+            inp.mu, inp.sigma, inp.seed = float(noise[0]), float(noise[1]), int(noise[2])
+        elif i_const is not None:
+            inp.mode, inp.i_const = IN_CONST, _ptr(i_const)
+        else:
+            inp.mode = IN_NONE
+        out = Outputs(_ptr(spikes), _ptr(v_rec), _ptr(ckpt), int(ckpt_every), _ptr(level))
+        _ok(lib.hh_step_n(self.h, _ptr(state), int(t0), int(n_steps), ctypes.byref(inp),
+                          ctypes.byref(out), _stream()), "hh_step_n")
+
+    def attach_csr(self, row_ptr, col, w, w_scale: float):
+        self._keep += [row_ptr, col, w]
+        _ok(lib.hh_attach_csr(self.h, _ptr(row_ptr), _ptr(col), _ptr(w), int(col.numel()),
+                              float(w_scale)), "hh_attach_csr")
+
+    def set_external(self, ext_mask, thresh: int, w_ext: float, seed: int):
+        self._keep.append(ext_mask)
+        _ok(lib.hh_set_external(self.h, _ptr(ext_mask), int(thresh), float(w_ext), int(seed)),
+            "hh_set_external")
+
+    def syn_propagate(self, spike_bits, state, n_spikes=None):
+        _ok(lib.hh_syn_propagate(self.h, _ptr(spike_bits), _ptr(state), _ptr(n_spikes), _stream()),
+            "hh_syn_propagate")
+
+    def backward_workspace(self, ckpt_every: int) -> int:
+        return int(lib.hh_backward_workspace(self.h, int(ckpt_every)))
+
+    def backward(self, ckpt, ckpt_every: int, i_dense, T: int, dI, *, dL_dlevel=None, dL_dV=None,
+                 beta: float = 0.2, dCm=None, dx0=None, workspace=None):
+        inp = Input()
+        inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
+        ws_bytes = self.backward_workspace(ckpt_every)
+        if workspace is None and ws_bytes:
+            workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dI.device)
+        _ok(lib.hh_backward(self.h, _ptr(ckpt), int(ckpt_every), ctypes.byref(inp), int(T),
+                            _ptr(dL_dlevel), _ptr(dL_dV), float(beta), _ptr(dI), _ptr(dCm),
+                            _ptr(dx0), _ptr(workspace), ws_bytes, _stream()), "hh_backward")
+
+    def check(self):
+        """Synchronizes; returns (status, first_bad_index)."""
+        fb = ctypes.c_int64(-1)
+        st = lib.hh_check(self.h, ctypes.byref(fb), _stream())
+        return st, fb.value
+
+
+def proj_forward(A_bf16, W_bf16, out):
+    M, K = A_bf16.shape
+    N = W_bf16.shape[1]
+    assert A_bf16.dtype == torch.bfloat16 and W_bf16.dtype == torch.bfloat16
+    assert out.dtype == torch.float32 and tuple(out.shape) == (M, N) and W_bf16.shape[0] == K
+    _ok(lib.hh_proj_forward(_ptr(A_bf16), _ptr(W_bf16), _ptr(out), M, N, K, _stream()),
+        "hh_proj_forward")
+    return out
+
+
+def proj_wgrad(A_bf16, dOut, dW):
+    M, K = A_bf16.shape
+    N = dOut.shape[1]
+    assert A_bf16.dtype == torch.bfloat16 and dOut.dtype == torch.float32
+    assert tuple(dW.shape) == (K, N) and dW.dtype == torch.float32 and dOut.shape[0] == M
+    _ok(lib.hh_proj_wgrad(_ptr(A_bf16), _ptr(dOut), _ptr(dW), M, N, K, _stream()), "hh_proj_wgrad")
+    return dW

@@ -126,11 +126,12 @@ def validation_currents(n: int = 1024, seed: int = 1) -> np.ndarray:
 
 
 def net_csr(n: int = 38000, fan_out: int = 2630, frac_exc: float = 0.8, seed: int = 3,
-            mu: float = -1.0, sigma: float = 0.5):
+            mu: float = -1.0, sigma: float = 0.5, inh_scale: float = 1.0):
     """Random recurrent connectivity: every source has exactly `fan_out`
     distinct non-self targets drawn uniformly, sorted; weights
-    LogNormal(mu, sigma), stored negative for inhibitory sources (ids >=
-    frac_exc * n).  Returns (row_ptr int64 [n+1], col int32 [nnz], w float32 [nnz])."""
+    LogNormal(mu, sigma), stored negative (and multiplied by inh_scale) for
+    inhibitory sources (ids >= frac_exc * n).  Returns (row_ptr int64 [n+1],
+    col int32 [nnz], w float32 [nnz])."""
     rng = np.random.default_rng(seed)
     fan_out = min(fan_out, n - 1)
     nnz = n * fan_out
@@ -147,7 +148,7 @@ def net_csr(n: int = 38000, fan_out: int = 2630, frac_exc: float = 0.8, seed: in
         col[j0 * fan_out: j1 * fan_out] = idx.reshape(-1).astype(np.int32)
     w = rng.lognormal(mu, sigma, nnz).astype(np.float32)
     n_exc = int(round(frac_exc * n))
-    w[n_exc * fan_out:] *= -1.0
+    w[n_exc * fan_out:] *= -inh_scale
     row_ptr = np.arange(0, nnz + 1, fan_out, dtype=np.int64)
     return row_ptr, col, w
 
@@ -162,6 +163,21 @@ def net_external(n: int = 38000, frac: float = 0.01, rate_hz: float = 20.0, dt_m
     mask[rng.choice(n, k, replace=False)] = 1
     p = rate_hz * dt_ms * 1e-3
     return mask, int(np.floor(p * 4294967296.0))
+
+
+# Recurrent-network workload: 38,000 classic HH neurons (exponential Euler in
+# V at dt = 0.1 ms), 80 % excitatory, 2,630 random targets per source,
+# lognormal weights; conductance increment per spike = NET_W_SCALE * |w|
+# (inhibitory weights NET_INH_SCALE times larger); 1 % of neurons receive
+# 20 Hz Poisson events of NET_W_EXT.  The scale was calibrated once with the
+# oracle for a mean rate near 10 Hz.
+NET_W_SCALE = 0.03
+NET_INH_SCALE = 4.0
+NET_W_EXT = 0.5
+
+
+def net_model() -> dict:
+    return with_synapses(classic_hh(dt=0.1, v_method="ee"))
 
 
 def net_v0(n: int, seed: int) -> np.ndarray:

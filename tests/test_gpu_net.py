@@ -1,0 +1,203 @@
+"""GPU parity of the recurrent-network path (persistent kernel with spike
+compaction and CSR scatter) and of hh_syn_propagate, through the C ABI.
+
+Synaptic arrivals are accumulated in 64-bit fixed point on the GPU and in
+FP64 (CSR order) in the oracle.  Networks are chaotic: spike-exact parity is
+required up to the predictability horizon, the first step at which the
+oracle's own raster changes under tiny perturbations (1 FP32 ulp of V0,
+1e-6 of the weight scale); past it the comparison is statistical.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2601_21407_amd import workloads as W
+from tests.gpu_util import need_gpu, print_case, spike_mismatch
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, dtype=None):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), device="cuda", dtype=dtype)
+
+
+def _net_gpu(m, csr, scale, v0, T, *, ext=None, i_const=None, state=None, t0=0):
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    n = len(csr[0]) - 1
+    M = hh.Model(m, n)
+    rp, col, w = _dev(csr[0]), _dev(csr[1]), _dev(csr[2].astype(np.float32))
+    M.attach_csr(rp, col, w, scale)
+    if ext is not None:
+        M.set_external(_dev(ext[0]), ext[1], ext[2], ext[3])
+    st = M.new_state() if state is None else state
+    if state is None:
+        M.init_state(st, v0=_dev(v0.astype(np.float32)))
+    spikes = torch.zeros((max(T, 1), M.words), dtype=torch.int32, device="cuda")
+    ic = None if i_const is None else _dev(np.asarray(i_const, np.float32))
+    M.step_n(st, T, t0, i_const=ic, spikes=spikes)
+    status, bad = M.check()
+    assert status == 0, (status, bad)
+    bits = spikes[:T].cpu().numpy().view(np.uint32)
+    return {"raster": O.unpack_bits(bits, n), "state": st.cpu().numpy(), "state_t": st, "M": M,
+            "bufs": (rp, col, w)}
+
+
+def test_syn_propagate_matches_oracle_and_is_deterministic():
+    print_case("syn_propagate n=5003 fan=300")
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    n = 5003
+    m = W.net_model()
+    csr = W.net_csr(n=n, fan_out=300, seed=11, inh_scale=4.0)
+    rng = np.random.default_rng(1)
+    s = (rng.random(n) < 0.3).astype(np.uint8)
+    words = (n + 31) // 32
+    bits = np.zeros(words * 32, np.uint8)
+    bits[:n] = s
+    packed = np.packbits(bits.reshape(-1, 8), axis=1, bitorder="little").reshape(-1).view(np.uint32)
+    M = hh.Model(m, n)
+    M.attach_csr(_dev(csr[0]), _dev(csr[1]), _dev(csr[2]), 0.03)
+    st = M.new_state()
+    M.init_state(st, v0_scalar=-65.0)
+    G = len(m["gates"])
+    ge0 = rng.random(n).astype(np.float32) * 0.1
+    gi0 = rng.random(n).astype(np.float32) * 0.1
+    st[1 + G] = _dev(ge0)
+    st[2 + G] = _dev(gi0)
+    outs = []
+    for rep in range(2):
+        s2 = st.clone()
+        cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+        M.syn_propagate(_dev(packed), s2, cnt)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == int(s.sum())
+        outs.append(s2.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    ge, gi = ge0.astype(np.float64), gi0.astype(np.float64)
+    O.syn_deliver(csr, 0.03, s, ge, gi)
+    assert np.allclose(outs[0][1 + G], ge, rtol=3e-7, atol=1e-9)
+    assert np.allclose(outs[0][2 + G], gi, rtol=3e-7, atol=1e-9)
+    # everything else untouched
+    assert np.array_equal(outs[0][: 1 + G], st.cpu().numpy()[: 1 + G])
+
+
+def test_syn_propagate_full_network_all_spiking():
+    print_case("syn_propagate full 38000 x 2630 all spiking")
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    n = 38000
+    m = W.net_model()
+    csr = W.net_csr(n=n, inh_scale=W.NET_INH_SCALE)
+    M = hh.Model(m, n)
+    M.attach_csr(_dev(csr[0]), _dev(csr[1]), _dev(csr[2]), W.NET_W_SCALE)
+    st = M.new_state()
+    M.init_state(st, v0_scalar=-65.0)
+    bits = torch.full(((n + 31) // 32,), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    M.syn_propagate(bits, st, cnt)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == n
+    got = st.cpu().numpy()
+    ge, gi = np.zeros(n), np.zeros(n)
+    O.syn_deliver(csr, W.NET_W_SCALE, np.ones(n, np.uint8), ge, gi)
+    G = len(m["gates"])
+    assert np.allclose(got[1 + G], ge, rtol=3e-7, atol=0)
+    assert np.allclose(got[2 + G], gi, rtol=3e-7, atol=0)
+
+
+def _horizon(m, csr, scale, v0, T, ext):
+    """First step at which the oracle raster changes under the probes (T if
+    never), and the reference raster."""
+    kw = dict(ext_mask=ext[0], ext_thresh=ext[1], w_ext=ext[2], seed=ext[3])
+    ref = O.net_run(m, O.init_state(m, v0), csr, scale, T, **kw)
+    h = T
+    v32 = v0.astype(np.float32)
+    ulp = np.spacing(np.abs(v32)).astype(np.float64)
+    for pv0, ps in [(v0 + ulp, scale), (v0 - ulp, scale), (v0, scale * (1 + 1e-6)),
+                    (v0, scale * (1 - 1e-6))]:
+        r = O.net_run(m, O.init_state(m, pv0), csr, ps, T, **kw)
+        d = np.nonzero((r != ref).any(axis=1))[0]
+        if len(d):
+            h = min(h, int(d[0]))
+    return h, ref
+
+
+@pytest.mark.parametrize("n,fan,T", [(2000, 200, 2000), (513, 40, 1500)])
+def test_network_spike_exact_to_horizon(n, fan, T):
+    print_case("network n=%d fan=%d T=%d" % (n, fan, T))
+    m = W.net_model()
+    csr = W.net_csr(n=n, fan_out=fan, seed=5, inh_scale=4.0)
+    mask, thr = W.net_external(n=n, frac=0.05, seed=5)
+    ext = (mask, thr, 0.5, 5)
+    v0 = W.net_v0(n, 5).astype(np.float64)
+    scale = 0.3
+    g = _net_gpu(m, csr, scale, v0, T, ext=ext)
+    h, ref = _horizon(m, csr, scale, v0, T, ext)
+    assert ref.sum() > 5 * n * T * 1e-4  # the network is active (> 5 Hz)
+    upto = max(h - 1, 0)
+    bad = spike_mismatch(g["raster"][:upto], ref[:upto])
+    print("horizon %d of %d steps, spikes %d, mismatched neurons before horizon %d"
+          % (h, T, int(ref.sum()), len(bad)), flush=True)
+    assert len(bad) == 0
+    # determinism: a second run is bit-identical
+    g2 = _net_gpu(m, csr, scale, v0, T, ext=ext)
+    assert np.array_equal(g2["raster"], g["raster"])
+    assert np.array_equal(g2["state"], g["state"])
+
+
+def test_network_resume_and_tiny_cases():
+    print_case("network resume / n=1")
+    m = W.net_model()
+    n, fan = 700, 50
+    csr = W.net_csr(n=n, fan_out=fan, seed=8, inh_scale=4.0)
+    mask, thr = W.net_external(n=n, frac=0.05, seed=8)
+    ext = (mask, thr, 0.5, 8)
+    v0 = W.net_v0(n, 8).astype(np.float64)
+    full = _net_gpu(m, csr, 0.3, v0, 600, ext=ext)
+    a = _net_gpu(m, csr, 0.3, v0, 250, ext=ext)
+    b = _net_gpu(m, csr, 0.3, v0, 350, ext=ext, state=a["state_t"], t0=250)
+    assert np.array_equal(b["state"], full["state"])
+    assert np.array_equal(np.concatenate([a["raster"], b["raster"]]), full["raster"])
+    # a single neuron without synapses, driven by a constant current
+    one = (np.zeros(2, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    g = _net_gpu(m, one, 0.3, np.array([-65.0]), 400, i_const=[12.0])
+    ro = O.net_run(m, O.init_state(m, np.array([-65.0])), one, 0.3, 400, i_const=np.array([12.0]))
+    assert g["raster"].sum() >= 3
+    assert len(spike_mismatch(g["raster"], ro)) == 0
+    # zero steps leaves the state untouched
+    st = full["state_t"].clone()
+    full["M"].step_n(st, 0)
+    assert np.array_equal(st.cpu().numpy(), full["state"])
+
+
+def test_full_network_statistics_and_determinism():
+    """38,000 neurons, 99.94 M synapses: bit-identical reruns; population
+    rates against the oracle, with the tolerance set by the oracle's own
+    spread under a 1 FP32-ulp perturbation of V0 (at least 2 %)."""
+    print_case("full network 38000 x 2630, 3000 steps")
+    n, T = 38000, 3000
+    m = W.net_model()
+    csr = W.net_csr(n=n, inh_scale=W.NET_INH_SCALE)
+    mask, thr = W.net_external(n=n)
+    ext = (mask, thr, W.NET_W_EXT, 3)
+    v0 = W.net_v0(n, 3).astype(np.float64)
+    g1 = _net_gpu(m, csr, W.NET_W_SCALE, v0, T, ext=ext)
+    g2 = _net_gpu(m, csr, W.NET_W_SCALE, v0, T, ext=ext)
+    assert np.array_equal(g1["raster"], g2["raster"]) and np.array_equal(g1["state"], g2["state"])
+    kw = dict(ext_mask=mask, ext_thresh=thr, w_ext=W.NET_W_EXT, seed=3)
+    ro = O.net_run(m, O.init_state(m, v0), csr, W.NET_W_SCALE, T, **kw)
+    v32 = v0.astype(np.float32)
+    rp = O.net_run(m, O.init_state(m, v0 + np.spacing(np.abs(v32)).astype(np.float64)), csr,
+                   W.NET_W_SCALE, T, **kw)
+    ne = int(0.8 * n)
+
+    def rates(r):
+        c = r.sum(0) / (T * 0.1e-3)
+        return np.array([c[:ne].mean(), c[ne:].mean()])
+    rg, rr, rq = rates(g1["raster"]), rates(ro), rates(rp)
+    tol = np.maximum(0.02 * rr, 3 * np.abs(rq - rr))
+    print("rates GPU %s oracle %s perturbed-oracle %s tol %s" % (rg, rr, rq, tol), flush=True)
+    assert np.all(rr > 1.0)
+    assert np.all(np.abs(rg - rr) <= tol)
