@@ -1,0 +1,450 @@
+#!/usr/bin/env python3
+"""Benchmark of the HH hot path on one MI355X.
+
+Headline (one "step" = one pass of the workload): a customizable-channel HH
+population of 1,048,576 neurons (cortical Na / K / M / L-Ca / leak set, rate
+coefficients jittered +-10 % per neuron, input 5 + 3 z uA/cm^2 with z drawn
+per neuron and step), dt = 0.025 ms, 4,000 steps, 32 fused steps per kernel
+launch.  value = neuron-updates per second = 1,048,576 * 4,000 / time.
+
+Further parts of the path are reported in "parts": the recurrent network
+(38,000 neurons, 99.94 M synapses, 10,000 steps), the synaptic scatter at
+full load, the differentiable layer (forward, forward + backward) and the
+learned surrogate when those paths are present.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--parts ...]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HH neuron-updates/s fwd & fwd+bwd; surrogate vs plain at equal spike-time error"
+PEAK_LANE_OPS = 256 * 64 * 2.4e9  # FP32 VALU lane operations per second (no packed math)
+HBM_PEAK_GBS = 8000.0
+
+# Issue cost of one operation in VALU lane-slots, relative to one FP32
+# FMA/add/mul.  The issue-rate probe (hh_probe_issue) measures transcendentals
+# (v_exp/v_log/v_rcp/v_sqrt/v_sin/v_cos) and the 32x32->64 integer multiply
+# at half the FMA rate on gfx950 (ratio 1.86-1.99); the live probe reports
+# the ratios next to every result.
+W_TRANS = 2.0
+W_MUL64 = 2.0
+
+# Per rate form: (FP32 arithmetic ops, transcendental ops), counted from the
+# definition u = (V - B) / K (a subtract and a multiply by 1/K):
+#   exp      A e^u                    u, exp, *A                   3 + 1
+#   sigmoid  A / (1 + e^u)            u, exp, +1, 1/x, *A          4 + 2
+#   linoid   A (V-B) / (1 - e^-u)     u, exp, 1-, 1/x, *(V-B), *A  5 + 2
+#   bell     (c e^u + e^-u) / A       u, 2 exp, *c, +, /A          5 + 2
+FORM_COST = {"exp": (3, 1), "sigmoid": (4, 2), "linoid": (5, 2), "bell": (5, 2)}
+POW_MULS = {0: 0, 1: 0, 2: 1, 3: 2, 4: 2}
+
+
+def alg_ops_per_update(model: dict, noise: bool, synapses: bool = False):
+    """Algorithmic operation count of one neuron-update, from the oracle's
+    formulas.  Returns (fp32 ops, transcendentals, integer ops, 64-bit
+    multiplies).
+
+    gate (alpha, beta): s = a + b, 1/s, p_inf = a / s, e = exp(-dt s),
+        p' = p_inf + (p - p_inf) e  -> 5 ops + 2 transcendentals
+    gate (p_inf, 1/tau): e = exp(-dt / tau), p' = ...  -> 3 ops + 1
+    channel: powers by repeated squaring, product of factors, * gbar,
+        (V - E), *, accumulate  -> muls + 4
+    V (explicit Euler): I - I_ion, * dt/C, + V -> 3; spike test 2
+    noise (per step): Box-Muller gives 2 normals from (log, sqrt, cos, sin)
+        and 5 ops; Philox4x32-10 gives 4 words from 10 rounds of two
+        32x32->64 multiplies, 4 xors and 2 key additions; I = mu + s z -> 1
+    """
+    fl = tr = it = m64 = 0.0
+    for g in model["gates"]:
+        for r in g["rates"]:
+            a, b = FORM_COST[r[0]]
+            fl += a
+            tr += b
+        if g["kind"] == "ab":
+            fl += 5
+            tr += 2
+        else:
+            fl += 3
+            tr += 1
+    for c in model["channels"]:
+        fl += sum(POW_MULS.get(e, e - 1) for _, e in c["gates"]) + max(len(c["gates"]) - 1, 0) + 4
+    fl += 3 + 2
+    if noise:
+        fl += 1 + 5 / 2.0
+        tr += 4 / 2.0
+        it += 10 * 6 / 4.0
+        m64 += 10 * 2 / 4.0
+    if synapses:
+        # two conductance terms, decays, and the EE-V extras (exp, 1/g)
+        fl += 8
+        tr += 2
+    return fl, tr, it, m64
+
+
+def slots_per_update(model, noise, synapses=False):
+    fl, tr, it, m64 = alg_ops_per_update(model, noise, synapses)
+    return fl + it + W_TRANS * tr + W_MUL64 * m64
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _src_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+STEP_KERNEL_SOURCES = ["paper_2601_21407_amd/csrc/hh_step.hip", "paper_2601_21407_amd/csrc/hh_device.h"]
+
+
+def _traffic(kernel_key, sources, launches_per_pass=1):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or
+    None when absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        ent = data[kernel_key]
+    except (ValueError, KeyError):
+        return None
+    if ent.get("src_hash") != _src_hash(sources):
+        return None
+    return ent.get("bytes_per_launch")
+
+
+# ---------------------------------------------------------------------------
+# headline: customizable channels, 1,048,576 neurons x 4,000 steps
+# ---------------------------------------------------------------------------
+def bench_headline(steps, warmup, fusion=32):
+    import torch
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import workloads as W
+    n, T, seed = 1 << 20, 4000, 2
+    m = W.custom_channels(dt=0.025)
+    coef = torch.tensor(W.jitter_coef(m, n, seed=seed), device="cuda")
+    M = hh.Model(m, n, coef=coef)
+    M.set_fusion(fusion)
+    st = M.new_state()
+    launches = (T + fusion - 1) // fusion
+
+    def one_pass(ev=None):
+        M.init_state(st, v0_scalar=-65.0)
+        if ev:
+            ev[0].record()
+        M.step_n(st, T, 0, noise=(5.0, 3.0, seed))
+        if ev:
+            ev[1].record()
+
+    for _ in range(warmup):
+        one_pass()
+    _sync()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    _sync()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        one_pass(evs[k])
+    _sync()
+    wall = time.perf_counter() - t0
+    st_code, bad = M.check()
+    if st_code != 0:
+        raise RuntimeError("non-finite state in the benchmark (neuron %d)" % bad)
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    per_launch_s = kern_ms / 1e3 / launches
+    slots = slots_per_update(m, noise=True)
+    achieved = slots * n * fusion / per_launch_s / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    return {
+        "n": n, "T": T, "wall_s": wall, "ms_per_pass": wall / steps * 1e3,
+        "updates_per_s": n * T * steps / wall,
+        "kernel_ms_per_pass": kern_ms, "launches_per_pass": launches,
+        "avg_launch_us": per_launch_s * 1e6,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
+                     "frac": achieved / peak,
+                     "traffic": _traffic("k_step_custom_1M", STEP_KERNEL_SOURCES),
+                     "kernel": "k_step<CorticalSpec, jittered coefficients>",
+                     "slots_per_update": slots,
+                     "ops_per_update": dict(zip(("fp32", "transcendental", "int", "mul64"),
+                                                alg_ops_per_update(m, True)))},
+    }
+
+
+def cpu_baseline_headline(n_sample=8192):
+    """The FP64 oracle, single-threaded, on the first n_sample neurons of the
+    headline workload for all 4,000 steps."""
+    from oracle import oracle as O
+    from paper_2601_21407_amd import workloads as W
+    m = W.custom_channels(dt=0.025)
+    T, seed = 4000, 2
+    coef = W.jitter_coef(m, n_sample, seed=seed).astype(np.float64)
+    st = O.init_state(m, np.full(n_sample, -65.0), coef=coef)
+    ids = np.arange(n_sample, dtype=np.uint32)
+    t0 = time.perf_counter()
+    O.run(m, st, T, noise_mu=5.0, noise_sigma=3.0, seed=seed, coef=coef, ids=ids,
+          record_spikes=False)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample * T / dt, "unit": "neuron-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of the 1,048,576 neurons x 4,000 steps (%.1f s)" % (n_sample, dt)}
+
+
+# ---------------------------------------------------------------------------
+# recurrent network: 38,000 neurons, 99.94 M synapses, 10,000 steps
+# ---------------------------------------------------------------------------
+def bench_network(T=10000):
+    import torch
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import workloads as W
+    n = 38000
+    m = W.net_model()
+    csr = W.net_csr(n=n, inh_scale=W.NET_INH_SCALE)
+    mask, thr = W.net_external(n=n)
+    M = hh.Model(m, n)
+    rp = torch.tensor(csr[0], device="cuda")
+    col = torch.tensor(csr[1], device="cuda")
+    w = torch.tensor(csr[2], device="cuda")
+    M.attach_csr(rp, col, w, W.NET_W_SCALE)
+    M.set_external(torch.tensor(mask, device="cuda"), thr, W.NET_W_EXT, 3)
+    st = M.new_state()
+    v0 = torch.tensor(W.net_v0(n, 3), device="cuda")
+    spikes = torch.zeros((T, M.words), dtype=torch.int32, device="cuda")
+    M.init_state(st, v0=v0)
+    M.step_n(st, 200, 0, spikes=spikes)  # warm-up
+    _sync()
+    M.init_state(st, v0=v0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    _sync()
+    t0 = time.perf_counter()
+    e0.record()
+    M.step_n(st, T, 0, spikes=spikes)
+    e1.record()
+    _sync()
+    wall = time.perf_counter() - t0
+    status, bad = M.check()
+    if status != 0:
+        raise RuntimeError("network run failed: status %d (neuron %d)" % (status, bad))
+    n_spk = int(np.unpackbits(spikes.cpu().numpy().view(np.uint8)).sum())
+    # full-load scatter: every neuron spikes once (99.94 M synaptic events)
+    allbits = torch.full((M.words,), -1, dtype=torch.int32, device="cuda")
+    s2 = st.clone()
+    for _ in range(2):
+        M.syn_propagate(allbits, s2)
+    _sync()
+    reps = 5
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        M.syn_propagate(allbits, s2)
+    b.record()
+    _sync()
+    sc_ms = a.elapsed_time(b) / reps
+    nnz = int(csr[1].shape[0])
+    return {
+        "n": n, "synapses": nnz, "T": T, "dt_ms": 0.1, "wall_s": wall,
+        "kernel_ms": e0.elapsed_time(e1), "us_per_step": wall / T * 1e6,
+        "updates_per_s": n * T / wall, "mean_rate_hz": n_spk / n / (T * 1e-4),
+        "synaptic_events": n_spk * 2630,
+        "scatter_full": {"events": nnz, "ms": sc_ms, "events_per_s": nnz / (sc_ms / 1e3),
+                         "alg_GBs": nnz * 8 / (sc_ms / 1e3) / 1e9,
+                         "hbm_frac": nnz * 8 / (sc_ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+    }
+
+
+# ---------------------------------------------------------------------------
+# differentiable layer: 256 x 1,024 HH neurons, 250 steps, 700 inputs
+# ---------------------------------------------------------------------------
+def bench_layer(reps=5, ckpt_every=50):
+    import torch
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import workloads as W
+    S8, labels = W.layer_inputs()
+    T, B, n_in = S8.shape
+    H, C = 1024, 20
+    n = B * H
+    m = W.classic_hh(dt=0.025)
+    Win, cm0, Wout, bout = W.layer_params()
+    dev = "cuda"
+    S = torch.tensor(S8.reshape(T * B, n_in), device=dev).to(torch.bfloat16)
+    win32 = torch.tensor(Win, device=dev)
+    win16 = win32.to(torch.bfloat16)
+    cm = torch.tensor(cm0, device=dev)
+    wout = torch.tensor(Wout, device=dev)
+    bo = torch.tensor(bout, device=dev)
+    lab = torch.tensor(labels.astype(np.int32), device=dev)
+    M = hh.Model(m, H, B, cm=cm)
+    st = M.new_state()
+    I = torch.empty((T * B, H), device=dev)
+    nck = (T + ckpt_every - 1) // ckpt_every
+    ck = torch.empty((nck, M.n_state, n), device=dev)
+    lv = torch.empty((B, H), device=dev)
+    dl = torch.empty((B, H), device=dev)
+    dWo = torch.empty_like(wout)
+    db = torch.empty_like(bo)
+    loss = torch.empty(1, device=dev)
+    dI = torch.empty((T, n), device=dev)
+    dC = torch.empty(H, device=dev)
+    dWin = torch.empty_like(win32)
+    ws_b = torch.empty(M.backward_workspace(ckpt_every), dtype=torch.uint8, device=dev)
+    ws_w = torch.empty(int(hh.lib.hh_proj_wgrad_workspace(T * B, H, n_in)), dtype=torch.uint8,
+                       device=dev)
+    opt = {k: (torch.zeros_like(v), torch.zeros_like(v)) for k, v in
+           (("win", win32), ("cm", cm), ("wout", wout), ("b", bo))}
+    ev = {}
+
+    def mark(name):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        ev.setdefault(name, []).append(e)
+
+    def forward():
+        mark("f0")
+        hh.proj_forward(S, win16, I)
+        mark("f1")
+        M.init_state(st, v0_scalar=-65.0)
+        lv.zero_()
+        M.step_n(st, T, 0, i_dense=I, ckpt=ck, ckpt_every=ckpt_every, level=lv.view(-1))
+        mark("f2")
+        hh.readout_ce(lv, T, wout, bo, lab, dl, dWo, db, loss)
+        mark("f3")
+
+    def backward(step):
+        M.backward(ck, ckpt_every, I, T, dI, dL_dlevel=dl.view(-1), beta=0.2, dCm=dC,
+                   workspace=ws_b)
+        mark("b1")
+        hh.proj_wgrad(S, dI.view(T * B, H), dWin, workspace=ws_w)
+        mark("b2")
+        for k, (p, g) in (("win", (win32, dWin)), ("cm", (cm, dC)), ("wout", (wout, dWo)),
+                          ("b", (bo, db))):
+            hh.adam_step(p, g, opt[k][0], opt[k][1], step, 1e-3,
+                         param_bf16=win16 if k == "win" else None)
+        mark("b3")
+
+    forward()
+    backward(1)
+    _sync()
+    ev.clear()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        forward()
+    _sync()
+    t_fwd = (time.perf_counter() - t0) / reps
+    ev.clear()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        forward()
+        backward(r + 2)
+    _sync()
+    t_fb = (time.perf_counter() - t0) / reps
+
+    def seg(a, b):
+        return float(np.mean([x.elapsed_time(y) for x, y in zip(ev[a], ev[b])]))
+    parts_ms = {"projection": seg("f0", "f1"), "hh_forward": seg("f1", "f2"),
+                "readout_ce": seg("f2", "f3"), "hh_backward": seg("f3", "b1"),
+                "proj_wgrad": seg("b1", "b2"), "adam": seg("b2", "b3")}
+    upd = n * T
+    gflop = 2.0 * T * B * n_in * H / 1e9
+    return {"batch": B, "hidden": H, "inputs": n_in, "T": T, "ckpt_every": ckpt_every,
+            "fwd_ms": t_fwd * 1e3, "fwd_bwd_ms": t_fb * 1e3,
+            "fwd_updates_per_s": upd / t_fwd, "fwd_bwd_updates_per_s": upd / t_fb,
+            "kernel_ms": parts_ms, "loss": float(loss.item()),
+            "projection_TFLOPs": gflop / parts_ms["projection"],
+            "wgrad_TFLOPs": 2 * gflop / parts_ms["proj_wgrad"]}
+
+
+# ---------------------------------------------------------------------------
+# issue-rate probe
+# ---------------------------------------------------------------------------
+def probe_rates():
+    import torch
+    from paper_2601_21407_amd import hh
+    out = torch.empty(1 << 20, device="cuda")
+    blocks, iters = 256 * 32, 2000
+    res = {}
+    for op in ("fma", "exp2", "rcp", "sqrt", "sin", "mul64"):
+        hh.probe_issue(op, 10, blocks, out)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        _sync()
+        a.record()
+        hh.probe_issue(op, iters, blocks, out)
+        b.record()
+        _sync()
+        ms = a.elapsed_time(b)
+        res[op] = blocks * 256 * 8 * iters / (ms / 1e3) / 1e12  # T lane-ops/s
+    res["ratio_vs_fma"] = {k: res["fma"] / v for k, v in res.items() if k != "fma"}
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--parts", default="layer,net,probe")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the hot path runs on a single MI355X here; "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    parts = [p for p in args.parts.split(",") if p]
+
+    head = bench_headline(args.steps, args.warmup)
+    print("[bench] headline done: %.3g updates/s" % head["updates_per_s"], file=sys.stderr, flush=True)
+    extra = {}
+    if "probe" in parts:
+        extra["issue_rates_Tops"] = probe_rates()
+    if "layer" in parts:
+        extra["layer"] = bench_layer()
+        print("[bench] layer done", file=sys.stderr, flush=True)
+    if "net" in parts:
+        extra["network"] = bench_network()
+        print("[bench] network done", file=sys.stderr, flush=True)
+    cpu = None if args.no_cpu_baseline else cpu_baseline_headline()
+
+    line = {
+        "metric": METRIC,
+        "value": head["updates_per_s"],
+        "unit": "neuron-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_pass"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "customizable-channel HH population: 1,048,576 neurons x 4,000 "
+                               "steps, dt 0.025 ms, Na/K/M/L-Ca/leak with per-neuron jittered "
+                               "rates, noisy input, 32 fused steps per launch",
+                   "neurons": head["n"], "steps_per_pass": head["T"], "fusion": 32},
+        "roofline": head["roofline"],
+        "cpu_baseline": cpu,
+        "parts": dict(headline_detail={k: v for k, v in head.items() if k != "roofline"}, **extra),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -137,6 +137,13 @@ int32_t hh_n_state(const hh_model* m);
  * (Methods, "Engineering optimization": operator fusion).  Default 32. */
 int32_t hh_set_fusion(hh_model* m, int32_t k_steps);
 
+/* Channel sets whose structure (forms, gate kinds, exponents) matches one of
+ * the library's compiled specializations -- the Hodgkin-Huxley (1952) set
+ * and the cortical Na/Kd/M/L-Ca/leak set -- run straight-line kernels; any
+ * other set runs the general interpreter.  on = 0 forces the interpreter
+ * (results are identical up to FP32 rounding order).  Default 1. */
+int32_t hh_set_specialize(hh_model* m, int32_t on);
+
 /* state <- (V0, p_inf(V0) for every gate, g_e = g_i = 0, V_lo = 0).  v0: nullable [n]
  * device array; when NULL every neuron starts at v0_scalar. */
 int32_t hh_init_state(hh_model* m, float* state, const float* v0, float v0_scalar, void* stream);
@@ -201,9 +208,87 @@ int32_t hh_check(hh_model* m, int64_t* first_bad, void* stream);
 int32_t hh_proj_forward(const uint16_t* A, const uint16_t* W, float* out, int32_t M, int32_t N,
                         int32_t K, void* stream);
 /* Weight gradient dW[K][N] (float, written) = A^T dOut, A [M][K] bf16,
- * dOut [M][N] float (split into two bf16 terms inside the kernel). */
+ * dOut [M][N] float (split into bf16 high and low parts inside the kernel,
+ * so the product keeps ~16 bits of dOut).  The reduction over M is split
+ * into partial sums that are added in a fixed order (bit-reproducible);
+ * workspace: device scratch of hh_proj_wgrad_workspace(M, N, K) bytes. */
 int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dW, int32_t M, int32_t N,
-                      int32_t K, void* stream);
+                      int32_t K, void* workspace, size_t workspace_bytes, void* stream);
+size_t hh_proj_wgrad_workspace(int32_t M, int32_t N, int32_t K);
+
+/* Linear readout of the mean spike level and cross-entropy loss, forward and
+ * backward (the readout layer of the differentiable network, Methods
+ * "Training and preprocessing").  r = level / T with level [B][H] the
+ * per-neuron count of steps with V >= v_th; logits = r W + bias, W [H][C],
+ * bias [C]; loss = mean over b of -log softmax(logits_b)[labels[b]].
+ * Writes loss [1], dlevel [B][H] = dL/dlevel, dW [H][C], db [C] and, when
+ * non-NULL, logits [B][C].  C <= 32 (else HH_E_UNSUPPORTED).  workspace:
+ * hh_readout_ce_workspace(B, C) bytes. */
+int32_t hh_readout_ce(const float* level, int32_t T, const float* W, const float* bias,
+                      const int32_t* labels, int32_t B, int32_t H, int32_t C, float* loss,
+                      float* dlevel, float* dW, float* db, float* logits, void* workspace,
+                      size_t workspace_bytes, void* stream);
+size_t hh_readout_ce_workspace(int32_t B, int32_t C);
+
+/* One Adam update (Kingma & Ba, 2015), step counted from 1:
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * param_bf16: nullable [count], receives p rounded to bf16 (for weights that
+ * feed the MFMA projection). */
+int32_t hh_adam_step(float* param, const float* grad, float* m, float* v, int64_t count, float lr,
+                     float beta1, float beta2, float eps, int32_t step, uint16_t* param_bf16,
+                     void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned k-step surrogate.  A multilayer perceptron 7 -> 64 -> 64 -> 6 with
+ * SiLU activations maps (V, m, h, n, p, q, mean input current over the k
+ * steps) to the state change over k steps of the cortical channel set.  The
+ * plain integrator stays the fallback and the judge of its error.
+ *
+ * params: float [HH_MLP_NPARAM] = W1 [7][64], b1 [64], W2 [64][64], b2 [64],
+ * W3 [64][6], b3 [6], W[k][j] connecting input k to output j.  X [S][7]
+ * (normalized inputs), Y [S][6] (normalized targets). */
+#define HH_MLP_NPARAM 5062
+
+/* Mean-squared-error loss L = (1/S) sum_s sum_o (y_so - Y_so)^2 and its
+ * gradient with respect to params (written).  quantize != 0 rounds the
+ * weights and hidden activations to bf16 where the MFMA inference does
+ * (straight-through gradient).  Partial sums are added in a fixed order.
+ * workspace: hh_mlp_grad_workspace(S) bytes.  loss: device float, nullable. */
+int32_t hh_mlp_grad(const float* params, const float* X, const float* Y, int32_t S,
+                    int32_t quantize, float* grad, float* loss, void* workspace,
+                    size_t workspace_bytes, void* stream);
+size_t hh_mlp_grad_workspace(int32_t S);
+/* FP32 forward (VALU), Y [S][6] written. */
+int32_t hh_mlp_forward(const float* params, const float* X, int32_t S, int32_t quantize, float* Y,
+                       void* stream);
+/* Pack params into the bf16 MFMA fragment image used by hh_mlp_infer and
+ * hh_surrogate_step_n, together with the normalization norm[32] (device):
+ * input mean [0..6], input std [8..14], output mean [16..21], output std
+ * [24..29].  packed: device buffer of hh_mlp_packed_bytes(). */
+int32_t hh_mlp_pack(const float* params, const float* norm, void* packed, void* stream);
+size_t hh_mlp_packed_bytes(void);
+/* MFMA inference on raw (un-normalized) inputs X [S][7]: Y [S][6] =
+ * de-normalized outputs (state change). */
+int32_t hh_mlp_infer(const void* packed, const float* X, int32_t S, float* Y, void* stream);
+
+/* Advance a population of the cortical channel set by n_steps (a multiple of
+ * k) using the surrogate for k steps at a time where it is admissible:
+ * a neuron uses the plain integrator for a call when V > v_fallback before
+ * or after the surrogate step, when it failed the last periodic check, and on
+ * every check_every-th call, where all neurons run the plain integrator and
+ * |V_plain - V_surrogate| > check_tol marks a neuron plain until the next
+ * check (check_every = 0 disables checks).  Spikes come from plain steps
+ * only.  flags: device uint8 [n], per-neuron check state (caller zeroes it
+ * before the first call).  spikes: nullable [n_steps][ceil(n/32)].
+ * stats: nullable device uint64 [3], incremented by (surrogate calls, plain
+ * calls, failed checks).  The model must be the cortical set without
+ * per-neuron coefficients or capacitance (else HH_E_UNSUPPORTED); input
+ * HH_IN_NOISE or HH_IN_DENSE. */
+int32_t hh_surrogate_step_n(hh_model* m, const void* mlp_packed, float* state, uint8_t* flags,
+                            int64_t t0, int32_t n_steps, int32_t k, const hh_input* in,
+                            float v_fallback, int32_t check_every, float check_tol,
+                            uint32_t* spikes, uint64_t* stats, void* stream);
 
 #ifdef __cplusplus
 }

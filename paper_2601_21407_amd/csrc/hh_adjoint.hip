@@ -1,0 +1,295 @@
+// hh_adjoint.hip -- backpropagation through time of the discrete HH map
+// (Methods, "Gradient learning support"; "Engineering optimization":
+// manually derived gradients with re-computation).
+//
+// One lane owns one neuron and walks its checkpoint segments in reverse.  A
+// segment of S steps is replayed from its checkpoint; when S exceeds the
+// register window R, a first replay stores the state at every R-th step in
+// a small workspace, and each R-step window is then replayed once more with
+// its states kept in registers.  The reverse sweep over a window carries the
+// adjoint lambda = (lambda_V, lambda_p) through the transposed Jacobian of
+// each step, which is closed form in the rate functions and their
+// V-derivatives:
+//   dV'/dV = 1 - (dt/C) g_tot,   dV'/dp_g = -(dt/C) sum_X gbar dEta_X/dp_g (V - E_X)
+//   dp'/dp = e,   dp'/dV = p_inf' (1 - e) + (p - p_inf) e'
+//   dV'/dI = dt/C,   dV'/dC = -(dt/C^2) (I - I_ion)
+// The spike output is the level H(V - v_th); its derivative is replaced by
+// the surrogate beta s (1 - s), s = sigmoid(beta (V - v_th)).
+#include <string.h>
+
+#include "hh_internal.h"
+
+using namespace hhk;
+
+namespace {
+
+constexpr int kWin = 10;  // register window R
+
+struct BwdArgs {
+  const float* ckpt;  // [nseg][ns][n]
+  int32_t S, T;
+  const float* I;     // [T][n]
+  const float* dlevel;
+  const float* dV;    // [T][n]
+  float beta, inv_T;
+  float* dI;          // [T][n]
+  float* dC_part;     // [n]
+  float* dx0;         // [ns][n]
+  float* sub;         // [ceil(S/R)][ns][n]
+  int64_t n, N;
+  const float* cm;
+  const float* coef;
+};
+
+template <class S>
+struct Jac {
+  float e[ng1<S::kNG>], dpv[ng1<S::kNG>], dvdp[ng1<S::kNG>];
+  float dvdv, dvdI, dvdC;
+};
+
+// Transposed-Jacobian ingredients of one explicit-Euler step at (V, p, I).
+template <class S>
+__device__ __forceinline__ void jacobian(const KModel& M, const LaneRates<S::kNG>& L, float dtC,
+                                         float C, float V, const float (&p)[ng1<S::kNG>], float I,
+                                         Jac<S>& J) {
+  constexpr int NG = S::kNG;
+  const float ndt = M.kdt * kLn2;  // -dt
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    float d0, d1;
+    const float r0 = rate_eval<true>(S::form(M, g, 0), L.r[g][0], V, &d0);
+    const float r1 = rate_eval<true>(S::form(M, g, 1), L.r[g][1], V, &d1);
+    float pinf, dpinf, e, de;
+    if (S::kind(M, g) == KIND_AB) {
+      const float s = r0 + r1, is = rcp(s);
+      pinf = r0 * is;
+      dpinf = (d0 * r1 - r0 * d1) * is * is;
+      e = ex2(s * M.kdt);
+      de = ndt * (d0 + d1) * e;
+    } else {
+      pinf = r0;
+      dpinf = d0;
+      e = ex2(r1 * M.kdt);
+      de = ndt * d1 * e;
+    }
+    J.e[g] = e;
+    J.dpv[g] = fmaf(dpinf, 1.0f - e, (p[g] - pinf) * de);
+  }
+  float gsum = 0.0f, iion = 0.0f, b[ng1<NG>];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) b[g] = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kMaxCh; ++c) {
+    if (c >= S::nch(M)) break;
+    float pw[ng1<NG>];
+    float eta = M.gbar[c];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int ex = S::cexp(M, c, g);
+      pw[g] = ex ? ipow(p[g], ex) : 1.0f;
+      eta *= pw[g];
+    }
+    const float vme = V - M.E[c];
+    gsum += eta;
+    iion = fmaf(eta, vme, iion);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int ex = S::cexp(M, c, g);
+      if (ex) {
+        float d = M.gbar[c] * (float)ex * ipow(p[g], ex - 1);
+#pragma unroll
+        for (int g2 = 0; g2 < NG; ++g2)
+          if (g2 != g) d *= pw[g2];
+        b[g] = fmaf(d, vme, b[g]);
+      }
+    }
+  }
+  J.dvdv = fmaf(-dtC, gsum, 1.0f);
+  J.dvdI = dtC;
+  J.dvdC = -(dtC / C) * (I - iion);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) J.dvdp[g] = -dtC * b[g];
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_bptt(KModel M, BwdArgs A) {
+  constexpr int NG = S::kNG;
+  const int64_t n = A.n;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;  // lanes are independent: no wave-level operations below
+  const int64_t pidx = i % A.N;
+  const int ns = 2 + NG;
+  LaneRates<NG> L;
+  load_rates<S>(M, A.coef, pidx, A.N, L);
+  const float C = A.cm ? A.cm[pidx] : M.C;
+  const float dtC = M.dt / C;
+
+  float lamV = 0.0f, lamP[ng1<NG>];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) lamP[g] = 0.0f;
+  float dc = 0.0f;
+  const int nseg = (A.T + A.S - 1) / A.S;
+
+  for (int j = nseg - 1; j >= 0; --j) {
+    const int ta = j * A.S, tb = min(ta + A.S, A.T);
+    const float* ck = A.ckpt + (int64_t)j * ns * n;
+    const int nwin = (tb - ta + kWin - 1) / kWin;
+    if (nwin > 1) {
+      // first replay: window start states into the workspace
+      float vh = ck[i], vl = ck[(int64_t)(1 + NG) * n + i], p[ng1<NG>];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) p[g] = ck[(int64_t)(1 + g) * n + i];
+      for (int t = ta; t < tb; ++t) {
+        if ((t - ta) % kWin == 0) {
+          float* w = A.sub + (int64_t)((t - ta) / kWin) * ns * n;
+          w[i] = vh;
+          w[(int64_t)(1 + NG) * n + i] = vl;
+#pragma unroll
+          for (int g = 0; g < NG; ++g) w[(int64_t)(1 + g) * n + i] = p[g];
+        }
+        neuron_step<S>(M, L, dtC, vh, vl, p, A.I[(int64_t)t * n + i], 0.0f, 0.0f);
+      }
+    }
+    for (int q = nwin - 1; q >= 0; --q) {
+      const int ua = ta + q * kWin, ub = min(ua + kWin, tb);
+      const float* src = (nwin > 1) ? A.sub + (int64_t)q * ns * n : ck;
+      float vh = src[i], vl = src[(int64_t)(1 + NG) * n + i], p[ng1<NG>];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) p[g] = src[(int64_t)(1 + g) * n + i];
+      // replay the window, keeping every state in registers
+      float Vh[kWin + 1], Iv[kWin], P[kWin][ng1<NG>];
+#pragma unroll
+      for (int k = 0; k < kWin; ++k) {
+        if (ua + k < ub) {
+          Vh[k] = vh;
+#pragma unroll
+          for (int g = 0; g < NG; ++g) P[k][g] = p[g];
+          Iv[k] = A.I[(int64_t)(ua + k) * n + i];
+          neuron_step<S>(M, L, dtC, vh, vl, p, Iv[k], 0.0f, 0.0f);
+          Vh[k + 1] = vh;
+        }
+      }
+      // reverse sweep
+#pragma unroll
+      for (int k = kWin - 1; k >= 0; --k) {
+        if (ua + k < ub) {
+          const int t = ua + k;
+          // direct loss on V_{t+1}
+          if (A.dlevel) {
+            const float sg = rcp(1.0f + ex2(-A.beta * (Vh[k + 1] - M.v_th) * kLog2e));
+            lamV = fmaf(A.dlevel[i] * A.inv_T, A.beta * sg * (1.0f - sg), lamV);
+          }
+          if (A.dV) lamV += A.dV[(int64_t)t * n + i];
+          Jac<S> J;
+          jacobian<S>(M, L, dtC, C, Vh[k], P[k], Iv[k], J);
+          A.dI[(int64_t)t * n + i] = lamV * J.dvdI;
+          dc = fmaf(lamV, J.dvdC, dc);
+          float nv = lamV * J.dvdv;
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            nv = fmaf(lamP[g], J.dpv[g], nv);
+            lamP[g] = fmaf(lamV, J.dvdp[g], lamP[g] * J.e[g]);
+          }
+          lamV = nv;
+        }
+      }
+    }
+  }
+  A.dC_part[i] = dc;
+  if (A.dx0) {
+    A.dx0[i] = lamV;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) A.dx0[(int64_t)(1 + g) * n + i] = lamP[g];
+    A.dx0[(int64_t)(1 + NG) * n + i] = lamV;  // V = V + V_lo
+  }
+}
+
+// dCm[h] = sum over the batch, in batch order.
+__global__ __launch_bounds__(256) void k_sum_batch(const float* __restrict__ part,
+                                                   float* __restrict__ out, int64_t N, int32_t B) {
+  const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (h >= N) return;
+  float s = 0.0f;
+  for (int b = 0; b < B; ++b) s += part[(int64_t)b * N + h];
+  out[h] = s;
+}
+
+template <class S>
+hipError_t launch_bptt(const hh_model* m, const BwdArgs& a, hipStream_t s) {
+  const int64_t nb = (a.n + 255) / 256;
+  hipLaunchKernelGGL(k_bptt<S>, dim3((unsigned)nb), dim3(256), 0, s, m->km, a);
+  return hipGetLastError();
+}
+
+size_t sub_bytes(const hh_model* m, int32_t S) {
+  const int nwin = (S + kWin - 1) / kWin;
+  if (nwin <= 1) return 0;
+  return (size_t)nwin * (size_t)(2 + m->km.n_gates) * (size_t)m->n * sizeof(float);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hh_backward_workspace(const hh_model* m, int32_t ckpt_every) {
+  if (!m || ckpt_every < 1) return 0;
+  const size_t part = (((size_t)m->n * sizeof(float)) + 255) & ~(size_t)255;
+  return part + sub_bytes(m, ckpt_every);
+}
+
+int32_t hh_backward(hh_model* m, const float* ckpt, int32_t ckpt_every, const hh_input* in,
+                    int32_t T, const float* dL_dlevel, const float* dL_dV, float beta, float* dI,
+                    float* dCm, float* dx0, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!m || !ckpt || !in || !dI) return HH_E_INVALID;
+  if (m->km.has_syn || m->km.v_method != HH_V_FE) return HH_E_UNSUPPORTED;
+  if (in->mode != HH_IN_DENSE || !in->i_dense) return HH_E_INVALID;
+  if (T < 1 || ckpt_every < 1) return HH_E_SHAPE;
+  if (!(beta > 0.0f)) return HH_E_INVALID;
+  const size_t need = hh_backward_workspace(m, ckpt_every);
+  if (!workspace || workspace_bytes < need) return HH_E_SHAPE;
+  BwdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.ckpt = ckpt;
+  a.S = ckpt_every;
+  a.T = T;
+  a.I = in->i_dense;
+  a.dlevel = dL_dlevel;
+  a.dV = dL_dV;
+  a.beta = beta;
+  a.inv_T = 1.0f / (float)T;
+  a.dI = dI;
+  a.dC_part = (float*)workspace;
+  a.dx0 = dx0;
+  a.sub = (float*)((char*)workspace + ((((size_t)m->n * sizeof(float)) + 255) & ~(size_t)255));
+  a.n = m->n;
+  a.N = m->N;
+  a.cm = m->cm;
+  a.coef = m->coef;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (m->use_fixed && ClassicSpec::matches(m->km)) {
+    e = launch_bptt<ClassicSpec>(m, a, s);
+  } else if (m->use_fixed && CorticalSpec::matches(m->km)) {
+    e = launch_bptt<CorticalSpec>(m, a, s);
+  } else {
+    switch (m->km.n_gates) {
+      case 0: e = launch_bptt<GenericSpec<0>>(m, a, s); break;
+      case 1: e = launch_bptt<GenericSpec<1>>(m, a, s); break;
+      case 2: e = launch_bptt<GenericSpec<2>>(m, a, s); break;
+      case 3: e = launch_bptt<GenericSpec<3>>(m, a, s); break;
+      case 4: e = launch_bptt<GenericSpec<4>>(m, a, s); break;
+      case 5: e = launch_bptt<GenericSpec<5>>(m, a, s); break;
+      case 6: e = launch_bptt<GenericSpec<6>>(m, a, s); break;
+      default: return HH_E_UNSUPPORTED;
+    }
+  }
+  if (e != hipSuccess) return HH_E_HIP;
+  if (dCm) {
+    hipLaunchKernelGGL(k_sum_batch, dim3((unsigned)((m->N + 255) / 256)), dim3(256), 0, s,
+                       a.dC_part, dCm, m->N, m->B);
+    if (hipGetLastError() != hipSuccess) return HH_E_HIP;
+  }
+  return HH_OK;
+}
+
+}  // extern "C"

@@ -130,6 +130,7 @@ int32_t hh_init(hh_model** out, const hh_model_desc* desc, int64_t N, int32_t B,
   m->coef = coef;
   m->cm = cm;
   m->k_fuse = 32;
+  m->use_fixed = 1;
   if (hipGetDevice(&m->device) != hipSuccess) {
     delete m;
     return HH_E_HIP;
@@ -165,6 +166,12 @@ int32_t hh_set_fusion(hh_model* m, int32_t k) {
   if (!m) return HH_E_INVALID;
   if (k < 1) return HH_E_SHAPE;
   m->k_fuse = k;
+  return HH_OK;
+}
+
+int32_t hh_set_specialize(hh_model* m, int32_t on) {
+  if (!m) return HH_E_INVALID;
+  m->use_fixed = on ? 1 : 0;
   return HH_OK;
 }
 

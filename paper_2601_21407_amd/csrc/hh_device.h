@@ -46,6 +46,73 @@ struct KModel {
 };
 
 // ---------------------------------------------------------------------------
+// channel-set specs
+//
+// A spec tells the step code the *structure* of a channel set: number of
+// gates and channels, each rate's form, each gate's kind and each channel's
+// gate exponents.  GenericSpec reads them from the kernel arguments at run
+// time (wave-uniform scalar branches).  FixedSpec carries them as template
+// constants, so the compiler sees a straight-line program with the branches
+// and unused paths removed.  Coefficients are run-time data in both cases.
+// ---------------------------------------------------------------------------
+template <int NG>
+struct GenericSpec {
+  static constexpr bool kFixed = false;
+  static constexpr int kNG = NG;
+  __device__ static int form(const KModel& M, int g, int r) { return M.form[g][r]; }
+  __device__ static int kind(const KModel& M, int g) { return M.kind[g]; }
+  __device__ static int nch(const KModel& M) { return M.n_ch; }
+  __device__ static int cexp(const KModel& M, int c, int g) { return M.cexp[c][g]; }
+};
+
+// FORMS: 2 bits per rate at bit 2*(2g + r); KINDS: 1 bit per gate; Cc: 4 bits
+// per gate exponent of channel c.
+template <int NG, int NCH, uint32_t FORMS, uint32_t KINDS, uint32_t C0, uint32_t C1 = 0,
+          uint32_t C2 = 0, uint32_t C3 = 0, uint32_t C4 = 0, uint32_t C5 = 0, uint32_t C6 = 0,
+          uint32_t C7 = 0>
+struct FixedSpec {
+  static constexpr bool kFixed = true;
+  static constexpr int kNG = NG;
+  __host__ __device__ static constexpr int form(const KModel&, int g, int r) {
+    return (int)((FORMS >> (2 * (2 * g + r))) & 3u);
+  }
+  __host__ __device__ static constexpr int kind(const KModel&, int g) { return (int)((KINDS >> g) & 1u); }
+  __host__ __device__ static constexpr int nch(const KModel&) { return NCH; }
+  __host__ __device__ static constexpr uint32_t cword(int c) {
+    return c == 0 ? C0 : c == 1 ? C1 : c == 2 ? C2 : c == 3 ? C3 : c == 4 ? C4 : c == 5 ? C5 : c == 6 ? C6 : C7;
+  }
+  __host__ __device__ static constexpr int cexp(const KModel&, int c, int g) {
+    return (int)((cword(c) >> (4 * g)) & 15u);
+  }
+  // does a run-time model have exactly this structure?
+  static bool matches(const KModel& M) {
+    if (M.n_gates != NG || M.n_ch != NCH) return false;
+    for (int g = 0; g < NG; ++g) {
+      if (M.kind[g] != kind(M, g)) return false;
+      for (int r = 0; r < 2; ++r)
+        if (M.form[g][r] != form(M, g, r)) return false;
+    }
+    for (int c = 0; c < NCH; ++c)
+      for (int g = 0; g < kMaxGates; ++g)
+        if (M.cexp[c][g] != (g < NG ? cexp(M, c, g) : 0)) return false;
+    return true;
+  }
+};
+
+// Hodgkin-Huxley (1952): m (linoid, exp), h (exp, sigmoid), n (linoid, exp);
+// Na m^3 h, K n^4, leak.
+using ClassicSpec = FixedSpec<3, 3,
+    (2u << 0) | (0u << 2) | (0u << 4) | (1u << 6) | (2u << 8) | (0u << 10), 0u,
+    0x13u, 0x400u, 0u>;
+// Cortical set: m (linoid, linoid), h (exp, sigmoid), n (linoid, exp),
+// p (sigmoid p_inf, bell 1/tau), q (linoid, exp); Na m^3 h, Kd n^4, M p,
+// L-Ca q^2, leak.
+using CorticalSpec = FixedSpec<5, 5,
+    (2u << 0) | (2u << 2) | (0u << 4) | (1u << 6) | (2u << 8) | (0u << 10) | (1u << 12) |
+        (3u << 14) | (2u << 16) | (0u << 18),
+    1u << 3, 0x13u, 0x400u, 0x1000u, 0x20000u, 0u>;
+
+// ---------------------------------------------------------------------------
 // special-function unit
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -140,16 +207,18 @@ struct LaneRates {
   KRate r[ng1<NG>][2];
 };
 
-template <int NG>
+template <class S>
 __device__ __forceinline__ void load_rates(const KModel& M, const float* __restrict__ coef,
-                                           int64_t pidx, int64_t N, LaneRates<NG>& L) {
+                                           int64_t pidx, int64_t N, LaneRates<S::kNG>& L) {
 #pragma unroll
-  for (int g = 0; g < NG; ++g)
+  for (int g = 0; g < S::kNG; ++g)
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       if (coef) {
         const float* cp = coef + (int64_t)(g * 8 + r * 4) * N + pidx;
-        L.r[g][r] = derive_rate(M.form[g][r], cp[0], cp[N], cp[2 * N], cp[3 * N]);
+        const int f = S::form(M, g, r);
+        // the c coefficient only enters the bell form
+        L.r[g][r] = derive_rate(f, cp[0], cp[N], cp[2 * N], f == FORM_BELL ? cp[3 * N] : 0.0f);
       } else {
         L.r[g][r] = M.rate[g][r];
       }
@@ -180,10 +249,11 @@ __device__ __forceinline__ float expm1_neg(float z) {
 // Advance the gates and V by one step (Jacobi: all right-hand sides at the
 // start-of-step state).  p is updated in place; (vh, vl) likewise.
 // I: external current; ge, gi: synaptic conductances held over the step.
-template <int NG>
-__device__ __forceinline__ void neuron_step(const KModel& M, const LaneRates<NG>& L, float dtC,
-                                            float& vh, float& vl, float (&p)[ng1<NG>], float I,
+template <class S>
+__device__ __forceinline__ void neuron_step(const KModel& M, const LaneRates<S::kNG>& L, float dtC,
+                                            float& vh, float& vl, float (&p)[ng1<S::kNG>], float I,
                                             float ge, float gi) {
+  constexpr int NG = S::kNG;
   const float V = vh;
   // channel terms at the start-of-step gates: total conductance gsum and
   // sum of g_X E_X, so that I_ion + I_syn = gsum V - esum
@@ -191,11 +261,11 @@ __device__ __forceinline__ void neuron_step(const KModel& M, const LaneRates<NG>
   float esum = fmaf(ge, M.E_e, gi * M.E_i);
 #pragma unroll
   for (int c = 0; c < kMaxCh; ++c) {
-    if (c >= M.n_ch) break;
+    if (c >= S::nch(M)) break;
     float eta = M.gbar[c];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      const int e = M.cexp[c][g];
+      const int e = S::cexp(M, c, g);
       if (e) eta *= ipow(p[g], e);
     }
     gsum += eta;
@@ -204,10 +274,10 @@ __device__ __forceinline__ void neuron_step(const KModel& M, const LaneRates<NG>
   // gates by exponential Euler at V_t
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
-    const float r0 = rate_eval<false>(M.form[g][0], L.r[g][0], V, nullptr);
-    const float r1 = rate_eval<false>(M.form[g][1], L.r[g][1], V, nullptr);
+    const float r0 = rate_eval<false>(S::form(M, g, 0), L.r[g][0], V, nullptr);
+    const float r1 = rate_eval<false>(S::form(M, g, 1), L.r[g][1], V, nullptr);
     float pinf, e;
-    if (M.kind[g] == KIND_AB) {
+    if (S::kind(M, g) == KIND_AB) {
       const float s = r0 + r1;
       pinf = r0 * rcp(s);
       e = ex2(s * M.kdt);

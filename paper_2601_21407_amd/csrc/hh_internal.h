@@ -34,6 +34,7 @@ struct hh_model {
   const float* coef;
   const float* cm;
   int32_t k_fuse;
+  int32_t use_fixed;  // launch compiled channel-set specializations when they match
   int device;
   // device flags: [0] first non-finite neuron (INT32_MAX = none), [1] timeout
   int32_t* d_flags;

@@ -1,0 +1,814 @@
+// hh_mlp.hip -- the learned k-step surrogate: a 7 -> 64 -> 64 -> 6 MLP with
+// SiLU activations that maps (V, m, h, n, p, q, mean input current) to the
+// state change over k steps.
+//
+// Training kernels (hh_mlp_grad) run one sample per lane-group on the VALU
+// in FP32 with the weights staged in LDS; with `quantize` they round weights
+// and hidden activations to bf16 exactly where the MFMA inference does, so
+// the trained network is the one that is deployed.  Per-block partial
+// gradients are summed in a fixed order.
+//
+// Inference (mlp_infer_wave) is register resident on MFMA.  Activations are
+// kept transposed (hidden x sample, 32 samples per tile): the accumulator of
+// v_mfma_f32_32x32x16_bf16 puts hidden unit 8(r/4) + 4(l/32) + r%4 of sample
+// l%32 in register r of lane l, and eight consecutive registers of a lane
+// are exactly the eight K values that lane supplies as the B operand of the
+// next layer -- provided the next layer's weight fragments list the hidden
+// units in that same order.  hh_mlp_pack writes the fragments in that order,
+// so no activation ever goes through LDS.  The input enters as a bf16
+// high/low split in the 16 K slots of the first layer, with the first-layer
+// bias in the spare slot.
+#include <string.h>
+
+#include "hh_internal.h"
+#include "hh_mlp.h"
+
+using namespace hhk;
+
+namespace {
+
+__device__ __forceinline__ float bf16r(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+__device__ __forceinline__ uint16_t bf16bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float sigm(float a) { return 1.0f / (1.0f + expf(-a)); }
+__device__ __forceinline__ float silu_acc(float a) { return a * sigm(a); }
+__device__ __forceinline__ float dsilu(float a) {
+  const float s = sigm(a);
+  return s * (1.0f + a * (1.0f - s));
+}
+
+constexpr int CH = 64;  // samples per chunk in the training kernel
+constexpr int LD = MLP_H + 1;
+
+__device__ __forceinline__ bool is_weight(int j) {
+  return j < MLP_OFF_B1 || (j >= MLP_OFF_W2 && j < MLP_OFF_B2) || (j >= MLP_OFF_W3 && j < MLP_OFF_B3);
+}
+
+// Forward + backward over a range of samples; per-block partial gradients.
+__global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P,
+                                                  const float* __restrict__ X,
+                                                  const float* __restrict__ Y, int S, int per_block,
+                                                  int quant, float* __restrict__ part,
+                                                  float* __restrict__ loss_part) {
+  __shared__ float w[MLP_NPARAM];
+  __shared__ float xs[CH][8];
+  __shared__ float a1[CH][LD], h1[CH][LD], a2[CH][LD], h2[CH][LD];
+  __shared__ float dy[CH][8];
+  const int tid = threadIdx.x;
+  for (int j = tid; j < MLP_NPARAM; j += 256) {
+    const float v = P[j];
+    w[j] = (quant && is_weight(j)) ? bf16r(v) : v;
+  }
+  const float* W1 = w + MLP_OFF_W1;
+  const float* B1 = w + MLP_OFF_B1;
+  const float* W2 = w + MLP_OFF_W2;
+  const float* B2 = w + MLP_OFF_B2;
+  const float* W3 = w + MLP_OFF_W3;
+  const float* B3 = w + MLP_OFF_B3;
+  float g2[16], g1[2], g3[2], gb = 0.0f, lsum = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) g2[q] = 0.0f;
+  g1[0] = g1[1] = g3[0] = g3[1] = 0.0f;
+  const float scale = 2.0f / (float)S;
+  const int beg = blockIdx.x * per_block, end = min(S, beg + per_block);
+  __syncthreads();
+  for (int c0 = beg; c0 < end; c0 += CH) {
+    const int nc = min(CH, end - c0);
+    for (int e = tid; e < CH * 8; e += 256) {
+      const int s = e >> 3, i = e & 7;
+      float v = 0.0f, t = 0.0f;
+      if (s < nc && i < MLP_IN) {
+        v = X[(int64_t)(c0 + s) * MLP_IN + i];
+        if (quant) {  // the inference feeds x as bf16 high + low parts
+          const float hi = bf16r(v);
+          v = hi + bf16r(v - hi);
+        }
+      }
+      if (s < nc && i < MLP_OUT) t = Y[(int64_t)(c0 + s) * MLP_OUT + i];
+      xs[s][i] = v;
+      dy[s][i] = t;  // targets for now
+    }
+    __syncthreads();
+    for (int e = tid; e < CH * MLP_H; e += 256) {
+      const int s = e / MLP_H, j = e % MLP_H;
+      float a = B1[j];
+#pragma unroll
+      for (int i = 0; i < MLP_IN; ++i) a = fmaf(W1[i * MLP_H + j], xs[s][i], a);
+      const float h = silu_acc(a);
+      a1[s][j] = a;
+      h1[s][j] = quant ? bf16r(h) : h;
+    }
+    __syncthreads();
+    for (int e = tid; e < CH * MLP_H; e += 256) {
+      const int s = e / MLP_H, j = e % MLP_H;
+      float a = B2[j];
+#pragma unroll 16
+      for (int k = 0; k < MLP_H; ++k) a = fmaf(W2[k * MLP_H + j], h1[s][k], a);
+      const float h = silu_acc(a);
+      a2[s][j] = a;
+      h2[s][j] = quant ? bf16r(h) : h;
+    }
+    __syncthreads();
+    float dyv[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + 256 * q;
+      if (e < CH * MLP_OUT) {
+        const int ys = e / MLP_OUT, yo = e % MLP_OUT;
+        float y = B3[yo];
+#pragma unroll 16
+        for (int k = 0; k < MLP_H; ++k) y = fmaf(W3[k * MLP_OUT + yo], h2[ys][k], y);
+        if (ys < nc) {
+          const float d = y - dy[ys][yo];
+          lsum = fmaf(d, d, lsum);
+          dyv[q] = d * scale;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + 256 * q;
+      if (e < CH * MLP_OUT) dy[e / MLP_OUT][e % MLP_OUT] = dyv[q];
+    }
+    __syncthreads();
+    // layer 3 gradients and dA2
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + 256 * q;
+      if (e < MLP_H * MLP_OUT) {
+        const int k = e / MLP_OUT, o = e % MLP_OUT;
+        float s = 0.0f;
+#pragma unroll 4
+        for (int ss = 0; ss < CH; ++ss) s = fmaf(h2[ss][k], dy[ss][o], s);
+        g3[q] += s;
+      }
+    }
+    if (tid >= 128 && tid < 128 + MLP_OUT) {
+      float s = 0.0f;
+      for (int ss = 0; ss < CH; ++ss) s += dy[ss][tid - 128];
+      gb += s;
+    }
+    for (int e = tid; e < CH * MLP_H; e += 256) {
+      const int s = e / MLP_H, j = e % MLP_H;
+      float d = 0.0f;
+#pragma unroll
+      for (int o = 0; o < MLP_OUT; ++o) d = fmaf(W3[j * MLP_OUT + o], dy[s][o], d);
+      a2[s][j] = d * dsilu(a2[s][j]);  // dA2
+    }
+    __syncthreads();
+    // layer 2 gradients and dA1
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q;
+      const int k = e / MLP_H, j = e % MLP_H;
+      float s = 0.0f;
+#pragma unroll 4
+      for (int ss = 0; ss < CH; ++ss) s = fmaf(h1[ss][k], a2[ss][j], s);
+      g2[q] += s;
+    }
+    if (tid >= 64 && tid < 128) {
+      float s = 0.0f;
+      for (int ss = 0; ss < CH; ++ss) s += a2[ss][tid - 64];
+      gb += s;
+    }
+    for (int e = tid; e < CH * MLP_H; e += 256) {
+      const int s = e / MLP_H, k = e % MLP_H;
+      float d = 0.0f;
+#pragma unroll 16
+      for (int j = 0; j < MLP_H; ++j) d = fmaf(W2[k * MLP_H + j], a2[s][j], d);
+      a1[s][k] = d * dsilu(a1[s][k]);  // dA1
+    }
+    __syncthreads();
+    // layer 1 gradients
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + 256 * q;
+      if (e < MLP_IN * MLP_H) {
+        const int i = e / MLP_H, j = e % MLP_H;
+        float s = 0.0f;
+#pragma unroll 4
+        for (int ss = 0; ss < CH; ++ss) s = fmaf(xs[ss][i], a1[ss][j], s);
+        g1[q] += s;
+      }
+    }
+    if (tid < 64) {
+      float s = 0.0f;
+      for (int ss = 0; ss < CH; ++ss) s += a1[ss][tid];
+      gb += s;
+    }
+    __syncthreads();
+  }
+  float* out = part + (int64_t)blockIdx.x * MLP_NPARAM;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) out[MLP_OFF_W2 + tid + 256 * q] = g2[q];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int e = tid + 256 * q;
+    if (e < MLP_IN * MLP_H) out[MLP_OFF_W1 + e] = g1[q];
+    if (e < MLP_H * MLP_OUT) out[MLP_OFF_W3 + e] = g3[q];
+  }
+  if (tid < 64) out[MLP_OFF_B1 + tid] = gb;
+  else if (tid < 128) out[MLP_OFF_B2 + tid - 64] = gb;
+  else if (tid < 128 + MLP_OUT) out[MLP_OFF_B3 + tid - 128] = gb;
+  // per-block loss: lanes' partial sums in a fixed order
+  __shared__ float lred[256];
+  lred[tid] = lsum;
+  __syncthreads();
+  if (tid == 0) {
+    float s = 0.0f;
+    for (int q = 0; q < 256; ++q) s += lred[q];
+    loss_part[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ part,
+                                                    const float* __restrict__ loss_part,
+                                                    int nblocks, float invS,
+                                                    float* __restrict__ grad,
+                                                    float* __restrict__ loss) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < MLP_NPARAM) {
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * MLP_NPARAM + j];
+    grad[j] = s;
+  } else if (j == MLP_NPARAM && loss) {
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += loss_part[b];
+    *loss = s * invS;
+  }
+}
+
+// Plain FP32 forward, one sample per lane (evaluation).
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ P,
+                                                 const float* __restrict__ X, int S, int quant,
+                                                 float* __restrict__ Yo) {
+  __shared__ float w[MLP_NPARAM];
+  for (int j = threadIdx.x; j < MLP_NPARAM; j += blockDim.x) {
+    const float v = P[j];
+    w[j] = (quant && is_weight(j)) ? bf16r(v) : v;
+  }
+  __syncthreads();
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  float x[MLP_IN], h[MLP_H], y[MLP_OUT];
+#pragma unroll
+  for (int i = 0; i < MLP_IN; ++i) {
+    float v = X[(int64_t)s * MLP_IN + i];
+    if (quant) {
+      const float hi = bf16r(v);
+      v = hi + bf16r(v - hi);
+    }
+    x[i] = v;
+  }
+#pragma unroll
+  for (int j = 0; j < MLP_H; ++j) {
+    float a = w[MLP_OFF_B1 + j];
+#pragma unroll
+    for (int i = 0; i < MLP_IN; ++i) a = fmaf(w[MLP_OFF_W1 + i * MLP_H + j], x[i], a);
+    h[j] = quant ? bf16r(silu_acc(a)) : silu_acc(a);
+  }
+#pragma unroll
+  for (int o = 0; o < MLP_OUT; ++o) y[o] = w[MLP_OFF_B3 + o];
+#pragma unroll 1
+  for (int j = 0; j < MLP_H; ++j) {
+    float a = w[MLP_OFF_B2 + j];
+#pragma unroll
+    for (int k = 0; k < MLP_H; ++k) a = fmaf(w[MLP_OFF_W2 + k * MLP_H + j], h[k], a);
+    const float h2 = quant ? bf16r(silu_acc(a)) : silu_acc(a);
+#pragma unroll
+    for (int o = 0; o < MLP_OUT; ++o) y[o] = fmaf(w[MLP_OFF_W3 + j * MLP_OUT + o], h2, y[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < MLP_OUT; ++o) Yo[(int64_t)s * MLP_OUT + o] = y[o];
+}
+
+// ---------------------------------------------------------------------------
+// packing into MFMA fragments (see the header comment)
+// ---------------------------------------------------------------------------
+// hidden unit that k-slot j of lane half hf holds in k-block kb
+__host__ __device__ __forceinline__ int hid_of(int kb, int hf, int j) {
+  return 32 * (kb >> 1) + 16 * (kb & 1) + 8 * (j >> 2) + 4 * hf + (j & 3);
+}
+
+__global__ void k_mlp_pack(const float* __restrict__ P, const float* __restrict__ norm,
+                           MlpPacked* __restrict__ out) {
+  const int l = threadIdx.x;  // 64 lanes
+  const int hf = l >> 5, c = l & 31;
+  for (int rt = 0; rt < 2; ++rt)
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * hf + j;  // input slot: 0..6 x_hi, 7 bias, 8..14 x_lo, 15 zero
+      const int hcol = 32 * rt + c;
+      float v;
+      if (k < MLP_IN) v = P[MLP_OFF_W1 + k * MLP_H + hcol];
+      else if (k == 7) v = P[MLP_OFF_B1 + hcol];
+      else if (k < 8 + MLP_IN) v = P[MLP_OFF_W1 + (k - 8) * MLP_H + hcol];
+      else v = 0.0f;
+      out->w1[rt][l][j] = bf16bits(v);
+    }
+  for (int ot = 0; ot < 2; ++ot)
+    for (int kb = 0; kb < 4; ++kb)
+      for (int j = 0; j < 8; ++j)
+        out->w2[ot][kb][l][j] = bf16bits(P[MLP_OFF_W2 + hid_of(kb, hf, j) * MLP_H + 32 * ot + c]);
+  for (int kb = 0; kb < 4; ++kb)
+    for (int j = 0; j < 8; ++j)
+      out->w3[kb][l][j] =
+          bf16bits(c < MLP_OUT ? P[MLP_OFF_W3 + hid_of(kb, hf, j) * MLP_OUT + c] : 0.0f);
+  if (l < 2 * 2 * 16) {  // bias of layer 2 in accumulator layout
+    const int ot = l >> 5, hh = (l >> 4) & 1, r = l & 15;
+    out->b2[ot][hh][r] = P[MLP_OFF_B2 + 32 * ot + 8 * (r >> 2) + 4 * hh + (r & 3)];
+  }
+  if (l < 8) {
+    const int hh = l >> 2, r = l & 3;
+    const int o = 4 * hh + r;
+    out->b3[hh][r] = o < MLP_OUT ? P[MLP_OFF_B3 + o] : 0.0f;
+  }
+  if (l < 8) {
+    out->mu_x[l] = l < MLP_IN ? norm[l] : 0.0f;
+    out->isig_x[l] = l < MLP_IN ? 1.0f / norm[8 + l] : 0.0f;
+    out->mu_y[l] = l < MLP_OUT ? norm[16 + l] : 0.0f;
+    out->sig_y[l] = l < MLP_OUT ? norm[24 + l] : 0.0f;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// MFMA inference of one wavefront: 64 samples, sample s owned by lane s.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ bf16x8 frag_ld(const uint16_t* p) {
+  return *reinterpret_cast<const bf16x8*>(p);
+}
+
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+  return (uint32_t)bf16bits(a) | ((uint32_t)bf16bits(b) << 16);
+}
+
+__device__ __forceinline__ bf16x8 u4_to_frag(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 v = {a, b, c, d};
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+// SiLU of an accumulator value (v_exp_f32 + v_rcp_f32)
+__device__ __forceinline__ float silu_fast(float a) { return a * rcp(1.0f + ex2(-a * kLog2e)); }
+
+// x[7] = raw inputs (state and mean current) of this lane's sample;
+// returns dy[6] = de-normalized outputs.
+__device__ __forceinline__ void mlp_infer_wave(const MlpPacked& W, const float (&x)[MLP_IN],
+                                               float (&out)[MLP_OUT]) {
+  const int l = threadIdx.x & 63;
+  const int hf = l >> 5;
+  // normalized input, split into bf16 high and low parts
+  float xn[8], xl[8];
+#pragma unroll
+  for (int i = 0; i < MLP_IN; ++i) {
+    xn[i] = (x[i] - W.mu_x[i]) * W.isig_x[i];
+    xl[i] = xn[i] - bf16r(xn[i]);
+  }
+  xn[7] = 1.0f;  // bias slot
+  xl[7] = 0.0f;
+  const uint32_t hi0 = pack2(xn[0], xn[1]), hi1 = pack2(xn[2], xn[3]);
+  const uint32_t hi2 = pack2(xn[4], xn[5]), hi3 = pack2(xn[6], xn[7]);
+  const uint32_t lo0 = pack2(xl[0], xl[1]), lo1 = pack2(xl[2], xl[3]);
+  const uint32_t lo2 = pack2(xl[4], xl[5]), lo3 = pack2(xl[6], xl[7]);
+  // lanes of the lower half pass their low parts up, the upper half its high
+  // parts down
+  const uint32_t s0 = hf ? hi0 : lo0, s1 = hf ? hi1 : lo1, s2 = hf ? hi2 : lo2, s3 = hf ? hi3 : lo3;
+  const uint32_t r0 = __shfl_xor(s0, 32), r1 = __shfl_xor(s1, 32);
+  const uint32_t r2 = __shfl_xor(s2, 32), r3 = __shfl_xor(s3, 32);
+  bf16x8 bx[2];
+  bx[0] = hf ? u4_to_frag(r0, r1, r2, r3) : u4_to_frag(hi0, hi1, hi2, hi3);
+  bx[1] = hf ? u4_to_frag(lo0, lo1, lo2, lo3) : u4_to_frag(r0, r1, r2, r3);
+
+  // layer 1: [64 hidden] x [32 samples] per sample tile c
+  f32x16 h1[2][2];  // [row tile][sample tile]
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    const bf16x8 a = frag_ld(&W.w1[rt][l][0]);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      f32x16 z = {};
+      h1[rt][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bx[c], z, 0, 0, 0);
+    }
+  }
+  // SiLU and repack as B operands of layer 2
+  bf16x8 b1[4][2];  // [k-block][sample tile]
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const f32x16& acc = h1[kb >> 1][c];
+      const int r0i = 8 * (kb & 1);
+      b1[kb][c] = u4_to_frag(pack2(silu_fast(acc[r0i + 0]), silu_fast(acc[r0i + 1])),
+                             pack2(silu_fast(acc[r0i + 2]), silu_fast(acc[r0i + 3])),
+                             pack2(silu_fast(acc[r0i + 4]), silu_fast(acc[r0i + 5])),
+                             pack2(silu_fast(acc[r0i + 6]), silu_fast(acc[r0i + 7])));
+    }
+  // layer 2
+  f32x16 h2[2][2];
+#pragma unroll
+  for (int ot = 0; ot < 2; ++ot) {
+    f32x16 bias;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) bias[r] = W.b2[ot][hf][r];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      f32x16 acc = bias;
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w2[ot][kb][l][0]), b1[kb][c], acc,
+                                                      0, 0, 0);
+      h2[ot][c] = acc;
+    }
+  }
+  bf16x8 b2[4][2];
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const f32x16& acc = h2[kb >> 1][c];
+      const int r0i = 8 * (kb & 1);
+      b2[kb][c] = u4_to_frag(pack2(silu_fast(acc[r0i + 0]), silu_fast(acc[r0i + 1])),
+                             pack2(silu_fast(acc[r0i + 2]), silu_fast(acc[r0i + 3])),
+                             pack2(silu_fast(acc[r0i + 4]), silu_fast(acc[r0i + 5])),
+                             pack2(silu_fast(acc[r0i + 6]), silu_fast(acc[r0i + 7])));
+    }
+  // layer 3: outputs 0..5 of the 32-row tile
+  float y[2][4];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    f32x16 acc = {};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = W.b3[hf][r];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w3[kb][l][0]), b2[kb][c], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) y[c][r] = acc[r];
+  }
+  // gather the six outputs of sample l into lane l
+  const float t0 = hf ? y[0][0] : y[1][0], t1 = hf ? y[0][1] : y[1][1];
+  const float t2 = y[1][2], t3 = y[1][3];
+  const float q0 = __shfl_xor(t0, 32), q1 = __shfl_xor(t1, 32);
+  const float q2 = __shfl_xor(t2, 32), q3 = __shfl_xor(t3, 32);
+  float o[MLP_OUT];
+  if (!hf) {
+    o[0] = y[0][0]; o[1] = y[0][1]; o[2] = y[0][2]; o[3] = y[0][3]; o[4] = q0; o[5] = q1;
+  } else {
+    o[0] = q0; o[1] = q1; o[2] = q2; o[3] = q3; o[4] = y[1][0]; o[5] = y[1][1];
+  }
+#pragma unroll
+  for (int k = 0; k < MLP_OUT; ++k) out[k] = fmaf(o[k], W.sig_y[k], W.mu_y[k]);
+}
+
+namespace {
+
+// test kernel: MFMA inference of S samples (64 per wavefront)
+__global__ __launch_bounds__(256) void k_mlp_infer(const MlpPacked* __restrict__ Wg,
+                                                   const float* __restrict__ X, int S,
+                                                   float* __restrict__ Yo) {
+  __shared__ MlpPacked Ws;
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(Wg);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&Ws);
+    for (int j = threadIdx.x; j < (int)(sizeof(MlpPacked) / 4); j += blockDim.x) dst[j] = src[j];
+  }
+  __syncthreads();
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sc = s < S ? s : S - 1;
+  float x[MLP_IN], y[MLP_OUT];
+#pragma unroll
+  for (int i = 0; i < MLP_IN; ++i) x[i] = X[(int64_t)sc * MLP_IN + i];
+  mlp_infer_wave(Ws, x, y);
+  if (s < S)
+#pragma unroll
+    for (int k = 0; k < MLP_OUT; ++k) Yo[(int64_t)s * MLP_OUT + k] = y[k];
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hh_mlp_grad_workspace(int32_t S) {
+  if (S < 1) return 0;
+  const int nb = (S + CH - 1) / CH < 512 ? (S + CH - 1) / CH : 512;
+  return (size_t)nb * (MLP_NPARAM + 1) * sizeof(float);
+}
+
+int32_t hh_mlp_grad(const float* params, const float* X, const float* Y, int32_t S,
+                    int32_t quantize, float* grad, float* loss, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+  if (!params || !X || !Y || !grad) return HH_E_INVALID;
+  if (S < 1) return HH_E_SHAPE;
+  if (!workspace || workspace_bytes < hh_mlp_grad_workspace(S)) return HH_E_SHAPE;
+  int nb = (S + CH - 1) / CH;
+  if (nb > 512) nb = 512;
+  int per = (S + nb - 1) / nb;
+  per = (per + CH - 1) / CH * CH;
+  nb = (S + per - 1) / per;
+  float* part = (float*)workspace;
+  float* lpart = part + (size_t)nb * MLP_NPARAM;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, s, params, X, Y, S, per, quantize ? 1 : 0,
+                     part, lpart);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, part, lpart,
+                     nb, 1.0f / (float)S, grad, loss);
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+int32_t hh_mlp_forward(const float* params, const float* X, int32_t S, int32_t quantize,
+                       float* Y, void* stream) {
+  if (!params || !X || !Y) return HH_E_INVALID;
+  if (S < 0) return HH_E_SHAPE;
+  if (S == 0) return HH_OK;
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((S + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, X,
+                     S, quantize ? 1 : 0, Y);
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+int32_t hh_mlp_pack(const float* params, const float* norm, void* packed, void* stream) {
+  if (!params || !norm || !packed) return HH_E_INVALID;
+  hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(64), 0, (hipStream_t)stream, params, norm,
+                     (MlpPacked*)packed);
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+size_t hh_mlp_packed_bytes(void) { return sizeof(MlpPacked); }
+
+int32_t hh_mlp_infer(const void* packed, const float* X, int32_t S, float* Y, void* stream) {
+  if (!packed || !X || !Y) return HH_E_INVALID;
+  if (S < 0) return HH_E_SHAPE;
+  if (S == 0) return HH_OK;
+  hipLaunchKernelGGL(k_mlp_infer, dim3((S + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                     (const MlpPacked*)packed, X, S, Y);
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Deployment: the surrogate advances subthreshold neurons by k steps per
+// call; the plain integrator (same code as hh_step_n) takes over for a
+// neuron whose V is above v_fb before or after the call, for neurons that
+// failed the last periodic check, and for every neuron on check calls (every
+// check_every-th call), where |V_plain - V_surrogate| > check_tol marks the
+// neuron plain until the next check.  Spikes come from plain steps only.
+// Neurons that need the plain integrator are compacted per block through
+// LDS, so the plain work is done by dense wavefronts.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int SB = 512;  // block size = compaction pool
+constexpr int KMAX = 16;
+
+struct SurArgs {
+  float* state;
+  uint8_t* flags;
+  int64_t n;
+  int64_t t0;
+  int32_t ncalls, k;
+  int32_t in_mode;
+  float mu, sigma;
+  uint64_t seed;
+  const float* i_dense;
+  float v_fb, check_tol;
+  int32_t check_every;
+  uint32_t* spikes;
+  int64_t words;
+  unsigned long long* stats;
+  const MlpPacked* W;
+};
+
+// input current of neuron `nid` for the k steps from tc (noise as in hh_step_n)
+__device__ __forceinline__ void call_inputs(const SurArgs& A, uint32_t nid, int64_t col, int64_t tc,
+                                            int call, float (&Iv)[KMAX]) {
+  if (A.in_mode == IN_NOISE) {
+    float z[4] = {0.f, 0.f, 0.f, 0.f};
+    if (tc & 3) {
+      normals4(A.seed, nid, (uint64_t)tc >> 2, z);
+      for (int s = 0; s < (int)(tc & 3); ++s) {
+        z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      if (j < A.k) {
+        const int64_t t = tc + j;
+        if ((t & 3) == 0) normals4(A.seed, nid, (uint64_t)t >> 2, z);
+        Iv[j] = fmaf(A.sigma, z[0], A.mu);
+        z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
+      }
+    }
+  } else if (A.in_mode == IN_DENSE) {
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < A.k) Iv[j] = A.i_dense[((int64_t)call * A.k + j) * A.n + col];
+  } else {
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) Iv[j] = 0.0f;
+  }
+}
+
+template <class S>
+__global__ __launch_bounds__(SB) void k_surrogate(KModel M, SurArgs A) {
+  constexpr int NG = S::kNG;
+  __shared__ MlpPacked Ws;
+  __shared__ float sv[SB], svl[SB], sp[NG][SB];
+  __shared__ int sid[SB];
+  __shared__ int s_cnt;
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(A.W);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&Ws);
+    for (int j = threadIdx.x; j < (int)(sizeof(MlpPacked) / 4); j += SB) dst[j] = src[j];
+  }
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int64_t n = A.n;
+  const int64_t i = blockIdx.x * (int64_t)SB + tid;
+  const bool act = i < n;
+  const int64_t ii = act ? i : n - 1;
+  LaneRates<NG> L;
+  load_rates<S>(M, nullptr, 0, 1, L);
+  const float dtC = M.dt / M.C;
+  const int64_t row_lo = (int64_t)(1 + NG) * n;
+  float vh = A.state[ii], vl = A.state[row_lo + ii], p[ng1<NG>];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) p[g] = A.state[(int64_t)(1 + g) * n + ii];
+  bool forced = A.flags[ii] != 0;
+  uint32_t n_mlp = 0, n_plain = 0, n_fail = 0;
+  const int64_t blk_w0 = (blockIdx.x * (int64_t)SB) >> 5;  // first spike word of the block
+  int myslot = 0;
+  __syncthreads();
+
+  for (int call = 0; call < A.ncalls; ++call) {
+    const int64_t tc = A.t0 + (int64_t)call * A.k;
+    float Iv[KMAX];
+    call_inputs(A, (uint32_t)ii, ii, tc, call, Iv);
+    float ibar = 0.0f;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < A.k) ibar += Iv[j];
+    ibar /= (float)A.k;
+    const bool check = A.check_every > 0 && ((call + 1) % A.check_every) == 0;
+    const bool sub = act && vh <= A.v_fb;  // surrogate admissible before the call
+    float pred[MLP_OUT];
+    bool cand = false;
+    if (check || __ballot(sub && !forced)) {
+      float x[MLP_IN] = {vh + vl, 0.f, 0.f, 0.f, 0.f, 0.f, ibar};
+#pragma unroll
+      for (int g = 0; g < NG && g < MLP_IN - 2; ++g) x[1 + g] = p[g];
+      float dy[MLP_OUT];
+      mlp_infer_wave(Ws, x, dy);
+      pred[0] = x[0] + dy[0];
+#pragma unroll
+      for (int g = 0; g < MLP_OUT - 1; ++g) pred[1 + g] = fminf(fmaxf(x[1 + g] + dy[1 + g], 0.0f), 1.0f);
+      cand = sub && pred[0] <= A.v_fb;  // ... and after it
+    }
+    const bool use_mlp = cand && !forced && !check;
+    const bool plain = act && !use_mlp;
+    // the block's spike words for this call start cleared; plain steps set bits
+    if (A.spikes) {
+      for (int e = tid; e < (SB / 32) * A.k; e += SB) {
+        const int j = e / (SB / 32);
+        const int64_t wd = blk_w0 + e % (SB / 32);
+        if (wd < A.words) A.spikes[((int64_t)call * A.k + j) * A.words + wd] = 0u;
+      }
+    }
+    if (tid == 0) s_cnt = 0;
+    __syncthreads();
+    const uint64_t b = __ballot(plain);
+    if (b) {
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&s_cnt, __popcll(b));
+      base = __shfl(base, 0);
+      if (plain) {
+        myslot = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+        sv[myslot] = vh;
+        svl[myslot] = vl;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) sp[g][myslot] = p[g];
+        sid[myslot] = (int)ii;
+      }
+    }
+    __syncthreads();
+    // dense plain integration of the compacted neurons
+    const int cnt = s_cnt;
+    if (tid < cnt) {
+      const int nid = sid[tid];
+      float wv = sv[tid], wl = svl[tid], wp[ng1<NG>];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) wp[g] = sp[g][tid];
+      float wI[KMAX];
+      call_inputs(A, (uint32_t)nid, nid, tc, call, wI);
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j) {
+        if (j < A.k) {
+          const float V = wv;
+          neuron_step<S>(M, L, dtC, wv, wl, wp, wI[j], 0.0f, 0.0f);
+          if (A.spikes && V < M.v_th && wv >= M.v_th)
+            atomicOr(&A.spikes[((int64_t)call * A.k + j) * A.words + (nid >> 5)], 1u << (nid & 31));
+        }
+      }
+      sv[tid] = wv;
+      svl[tid] = wl;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) sp[g][tid] = wp[g];
+    }
+    __syncthreads();
+    if (plain) {
+      const float vp = sv[myslot];
+      if (check && cand) {
+        const bool fail = fabsf(vp - pred[0]) > A.check_tol;
+        forced = fail;
+        n_fail += fail;
+      }
+      vh = vp;
+      vl = svl[myslot];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) p[g] = sp[g][myslot];
+      n_plain += 1;
+    } else if (use_mlp) {
+      vh = pred[0];
+      vl = 0.0f;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) p[g] = pred[1 + g];
+      n_mlp += 1;
+    }
+    __syncthreads();  // slots are reused by the next call
+  }
+  if (act) {
+    A.state[i] = vh;
+    A.state[row_lo + i] = vl;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) A.state[(int64_t)(1 + g) * n + i] = p[g];
+    A.flags[i] = forced ? 1 : 0;
+  }
+  if (A.stats) {
+    // wave totals, one atomic per wave and counter
+    uint32_t a = n_mlp, c = n_plain, f = n_fail;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_xor(a, off);
+      c += __shfl_xor(c, off);
+      f += __shfl_xor(f, off);
+    }
+    if (lane == 0) {
+      atomicAdd(&A.stats[0], (unsigned long long)a);
+      atomicAdd(&A.stats[1], (unsigned long long)c);
+      atomicAdd(&A.stats[2], (unsigned long long)f);
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" int32_t hh_surrogate_step_n(hh_model* m, const void* mlp_packed, float* state,
+                                       uint8_t* flags, int64_t t0, int32_t n_steps, int32_t k,
+                                       const hh_input* in, float v_fallback, int32_t check_every,
+                                       float check_tol, uint32_t* spikes, uint64_t* stats,
+                                       void* stream) {
+  if (!m || !mlp_packed || !state || !flags || !in) return HH_E_INVALID;
+  if (k < 1 || k > KMAX || n_steps < 0 || n_steps % k != 0 || t0 < 0 || check_every < 0)
+    return HH_E_SHAPE;
+  if (in->mode == HH_IN_CONST) return HH_E_UNSUPPORTED;
+  if (in->mode == HH_IN_DENSE && !in->i_dense) return HH_E_INVALID;
+  if (m->km.has_syn || m->coef || m->cm || m->B != 1) return HH_E_UNSUPPORTED;
+  if (!CorticalSpec::matches(m->km)) return HH_E_UNSUPPORTED;
+  if (n_steps == 0) return HH_OK;
+  SurArgs a;
+  memset(&a, 0, sizeof(a));
+  a.state = state;
+  a.flags = flags;
+  a.n = m->n;
+  a.t0 = t0;
+  a.ncalls = n_steps / k;
+  a.k = k;
+  a.in_mode = in->mode;
+  a.mu = in->mu;
+  a.sigma = in->sigma;
+  a.seed = in->seed;
+  a.i_dense = in->i_dense;
+  a.v_fb = v_fallback;
+  a.check_tol = check_tol;
+  a.check_every = check_every;
+  a.spikes = spikes;
+  a.words = (m->n + 31) / 32;
+  a.stats = (unsigned long long*)stats;
+  a.W = (const MlpPacked*)mlp_packed;
+  const int64_t nb = (m->n + SB - 1) / SB;
+  hipLaunchKernelGGL(k_surrogate<CorticalSpec>, dim3((unsigned)nb), dim3(SB), 0, (hipStream_t)stream,
+                     m->km, a);
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}

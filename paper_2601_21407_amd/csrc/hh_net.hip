@@ -104,8 +104,9 @@ __device__ __forceinline__ void deliver_row(const int64_t* __restrict__ row_ptr,
   }
 }
 
-template <int NG>
+template <class S>
 __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
+  constexpr int NG = S::kNG;
   __shared__ int s_list[kNetBlock];
   __shared__ int s_cnt;
   __shared__ int s_ok;
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   const int64_t w0 = (i - lane) >> 5;
 
   LaneRates<NG> L;
-  load_rates<NG>(M, nullptr, 0, 1, L);
+  load_rates<S>(M, nullptr, 0, 1, L);
   const float dtC = M.dt / M.C;
   const int64_t row_ge = (int64_t)(1 + NG) * n, row_gi = (int64_t)(2 + NG) * n;
   const int64_t row_lo = (int64_t)(3 + NG) * n;
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   for (int k = 0; k < A.nsteps; ++k) {
     const int64_t t = A.t0 + k;
     const float V = vh;
-    neuron_step<NG>(M, L, dtC, vh, vl, p, I, ge, gi);
+    neuron_step<S>(M, L, dtC, vh, vl, p, I, ge, gi);
     const bool spk = act && (V < M.v_th) && (vh >= M.v_th);
     ge *= M.decay_e;
     gi *= M.decay_i;
@@ -248,14 +249,14 @@ size_t list_off(int64_t n) { return acc_bytes(n); }
 size_t ctr_off(int64_t n) { return list_off(n) + (((size_t)n * 4 + 255) & ~(size_t)255); }
 size_t scratch_size(int64_t n) { return ctr_off(n) + 256; }
 
-template <int NG>
+template <class S>
 hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_net<NG>, kNetBlock, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_net<S>, kNetBlock, 0);
   if (e != hipSuccess) return e;
   const int64_t nb = (a.n + kNetBlock - 1) / kNetBlock;
   if (nb > (int64_t)ncu * per_cu) return hipErrorCooperativeLaunchTooLarge;
@@ -263,7 +264,7 @@ hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* args[] = {(void*)&m->km, (void*)&a};
-  return hipLaunchCooperativeKernel((const void*)k_net<NG>, dim3((unsigned)nb), dim3(kNetBlock),
+  return hipLaunchCooperativeKernel((const void*)k_net<S>, dim3((unsigned)nb), dim3(kNetBlock),
                                     args, 0, s);
 }
 
@@ -297,14 +298,19 @@ int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_
   a.flags = m->d_flags;
   a.spin_limit = 1u << 24;
   hipError_t e;
-  switch (m->km.n_gates) {
-    case 1: e = launch_net<1>(m, a, (hipStream_t)stream); break;
-    case 2: e = launch_net<2>(m, a, (hipStream_t)stream); break;
-    case 3: e = launch_net<3>(m, a, (hipStream_t)stream); break;
-    case 4: e = launch_net<4>(m, a, (hipStream_t)stream); break;
-    case 5: e = launch_net<5>(m, a, (hipStream_t)stream); break;
-    case 6: e = launch_net<6>(m, a, (hipStream_t)stream); break;
-    default: return HH_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  if (m->use_fixed && ClassicSpec::matches(m->km)) {
+    e = launch_net<ClassicSpec>(m, a, s);
+  } else {
+    switch (m->km.n_gates) {
+      case 1: e = launch_net<GenericSpec<1>>(m, a, s); break;
+      case 2: e = launch_net<GenericSpec<2>>(m, a, s); break;
+      case 3: e = launch_net<GenericSpec<3>>(m, a, s); break;
+      case 4: e = launch_net<GenericSpec<4>>(m, a, s); break;
+      case 5: e = launch_net<GenericSpec<5>>(m, a, s); break;
+      case 6: e = launch_net<GenericSpec<6>>(m, a, s); break;
+      default: return HH_E_UNSUPPORTED;
+    }
   }
   if (e == hipErrorCooperativeLaunchTooLarge) return HH_E_UNSUPPORTED;
   return e == hipSuccess ? HH_OK : HH_E_HIP;
@@ -377,15 +383,4 @@ int32_t hh_syn_propagate(hh_model* m, const uint32_t* spike_bits, float* state,
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 
-int32_t hh_backward(hh_model*, const float*, int32_t, const hh_input*, int32_t, const float*,
-                    const float*, float, float*, float*, float*, void*, size_t, void*) {
-  return HH_E_UNSUPPORTED;
-}
-size_t hh_backward_workspace(const hh_model*, int32_t) { return 0; }
-int32_t hh_proj_forward(const uint16_t*, const uint16_t*, float*, int32_t, int32_t, int32_t, void*) {
-  return HH_E_UNSUPPORTED;
-}
-int32_t hh_proj_wgrad(const uint16_t*, const float*, float*, int32_t, int32_t, int32_t, void*) {
-  return HH_E_UNSUPPORTED;
-}
 }

@@ -10,21 +10,22 @@
 
 using namespace hhk;
 
-template <int NG>
+template <class S>
 __global__ __launch_bounds__(256) void k_init_state(KModel M, float* __restrict__ state, int64_t n,
                                                     int64_t N, const float* __restrict__ coef,
                                                     const float* __restrict__ v0, float v0s) {
+  constexpr int NG = S::kNG;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   LaneRates<NG> L;
-  load_rates<NG>(M, coef, i % N, N, L);
+  load_rates<S>(M, coef, i % N, N, L);
   const float V = v0 ? v0[i] : v0s;
   state[i] = V;
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
-    const float r0 = rate_eval<false>(M.form[g][0], L.r[g][0], V, nullptr);
-    const float r1 = rate_eval<false>(M.form[g][1], L.r[g][1], V, nullptr);
-    state[(int64_t)(1 + g) * n + i] = (M.kind[g] == KIND_AB) ? r0 / (r0 + r1) : r0;
+    const float r0 = rate_eval<false>(S::form(M, g, 0), L.r[g][0], V, nullptr);
+    const float r1 = rate_eval<false>(S::form(M, g, 1), L.r[g][1], V, nullptr);
+    state[(int64_t)(1 + g) * n + i] = (S::kind(M, g) == KIND_AB) ? r0 / (r0 + r1) : r0;
   }
   if (M.has_syn) {
     state[(int64_t)(1 + NG) * n + i] = 0.0f;
@@ -33,8 +34,9 @@ __global__ __launch_bounds__(256) void k_init_state(KModel M, float* __restrict_
   state[(int64_t)(1 + NG + 2 * M.has_syn) * n + i] = 0.0f;  // low part of V
 }
 
-template <int NG, bool JIT>
+template <class S, bool JIT>
 __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
+  constexpr int NG = S::kNG;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const bool act = i < A.n;
   const int64_t ii = act ? i : A.n - 1;  // ragged tail: compute on a valid copy, store nothing
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
   const int64_t pidx = ii % A.N;
 
   LaneRates<NG> L;
-  load_rates<NG>(M, JIT ? A.coef : nullptr, pidx, A.N, L);
+  load_rates<S>(M, JIT ? A.coef : nullptr, pidx, A.N, L);
   const float dtC = A.cm ? M.dt / A.cm[pidx] : M.dt / M.C;
 
   const int64_t row_lo = (int64_t)(1 + NG + 2 * M.has_syn) * n;  // low part of V
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
       I = A.i_dense[(int64_t)k * n + ii];
     }
     const float V = vh;
-    neuron_step<NG>(M, L, dtC, vh, vl, p, I, ge, gi);
+    neuron_step<S>(M, L, dtC, vh, vl, p, I, ge, gi);
     const float Vn = vh;
     const bool spk = act && (V < M.v_th) && (Vn >= M.v_th);
     if (A.spikes) {
@@ -128,54 +130,67 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
   if (!__builtin_isfinite(chk)) atomicMin(A.bad, (int32_t)i);
 }
 
-template <int NG>
-static hipError_t init_ng(const hh_model* m, float* state, const float* v0, float v0s,
-                          hipStream_t s) {
+template <class S>
+static hipError_t init_spec(const hh_model* m, float* state, const float* v0, float v0s,
+                            hipStream_t s) {
   const int bs = 256;
   const int64_t nb = (m->n + bs - 1) / bs;
-  hipLaunchKernelGGL(k_init_state<NG>, dim3((unsigned)nb), dim3(bs), 0, s, m->km, state, m->n,
+  hipLaunchKernelGGL(k_init_state<S>, dim3((unsigned)nb), dim3(bs), 0, s, m->km, state, m->n,
                      m->N, m->coef, v0, v0s);
   return hipGetLastError();
 }
 
-hipError_t launch_init_state(const hh_model* m, float* state, const float* v0, float v0s,
-                             hipStream_t s) {
-  switch (m->km.n_gates) {
-    case 0: return init_ng<0>(m, state, v0, v0s, s);
-    case 1: return init_ng<1>(m, state, v0, v0s, s);
-    case 2: return init_ng<2>(m, state, v0, v0s, s);
-    case 3: return init_ng<3>(m, state, v0, v0s, s);
-    case 4: return init_ng<4>(m, state, v0, v0s, s);
-    case 5: return init_ng<5>(m, state, v0, v0s, s);
-    case 6: return init_ng<6>(m, state, v0, v0s, s);
-    case 7: return init_ng<7>(m, state, v0, v0s, s);
-    default: return init_ng<8>(m, state, v0, v0s, s);
-  }
-}
-
-template <int NG>
-static hipError_t step_ng(const hh_model* m, const StepArgs& a, hipStream_t s) {
+template <class S>
+static hipError_t step_spec(const hh_model* m, const StepArgs& a, hipStream_t s) {
   // Small populations use 64-lane blocks so their few wavefronts spread over
   // as many compute units as possible (the step is latency bound there).
   const int bs = (a.n < 65536) ? 64 : 256;
   const int64_t nb = (a.n + bs - 1) / bs;
   if (a.coef)
-    hipLaunchKernelGGL((k_step<NG, true>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
+    hipLaunchKernelGGL((k_step<S, true>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
   else
-    hipLaunchKernelGGL((k_step<NG, false>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
+    hipLaunchKernelGGL((k_step<S, false>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
   return hipGetLastError();
 }
 
-hipError_t launch_step(const hh_model* m, const StepArgs& a, hipStream_t s) {
-  switch (m->km.n_gates) {
-    case 0: return step_ng<0>(m, a, s);
-    case 1: return step_ng<1>(m, a, s);
-    case 2: return step_ng<2>(m, a, s);
-    case 3: return step_ng<3>(m, a, s);
-    case 4: return step_ng<4>(m, a, s);
-    case 5: return step_ng<5>(m, a, s);
-    case 6: return step_ng<6>(m, a, s);
-    case 7: return step_ng<7>(m, a, s);
-    default: return step_ng<8>(m, a, s);
+// Dispatch on the channel-set structure: compiled specializations for the
+// built-in sets, the run-time interpreter for any other set.
+template <template <class> class F, class... Args>
+static hipError_t dispatch_spec(const KModel& km, bool allow_fixed, Args... args) {
+  if (allow_fixed && ClassicSpec::matches(km)) return F<ClassicSpec>::run(args...);
+  if (allow_fixed && CorticalSpec::matches(km)) return F<CorticalSpec>::run(args...);
+  switch (km.n_gates) {
+    case 0: return F<GenericSpec<0>>::run(args...);
+    case 1: return F<GenericSpec<1>>::run(args...);
+    case 2: return F<GenericSpec<2>>::run(args...);
+    case 3: return F<GenericSpec<3>>::run(args...);
+    case 4: return F<GenericSpec<4>>::run(args...);
+    case 5: return F<GenericSpec<5>>::run(args...);
+    case 6: return F<GenericSpec<6>>::run(args...);
+    case 7: return F<GenericSpec<7>>::run(args...);
+    default: return F<GenericSpec<8>>::run(args...);
   }
+}
+
+template <class S>
+struct InitF {
+  static hipError_t run(const hh_model* m, float* state, const float* v0, float v0s, hipStream_t s) {
+    return init_spec<S>(m, state, v0, v0s, s);
+  }
+};
+template <class S>
+struct StepF {
+  static hipError_t run(const hh_model* m, const StepArgs& a, hipStream_t s) {
+    return step_spec<S>(m, a, s);
+  }
+};
+
+hipError_t launch_init_state(const hh_model* m, float* state, const float* v0, float v0s,
+                             hipStream_t s) {
+  return dispatch_spec<InitF>(m->km, m->use_fixed, m, state, v0, v0s, s);
+}
+
+hipError_t launch_step(const hh_model* m, const StepArgs& a, hipStream_t s) {
+  return dispatch_spec<StepF, const hh_model*, const StepArgs&, hipStream_t>(m->km, m->use_fixed, m,
+                                                                               a, s);
 }

@@ -1,0 +1,163 @@
+// hh_train.hip -- the small dense pieces around the differentiable HH layer:
+// linear readout of the mean spike level with cross entropy (forward and
+// backward in one call) and the Adam update (Methods, "Training and
+// preprocessing": Adam optimizer).  All reductions run in a fixed order, so
+// results are bit-reproducible.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "../../include/hh.h"
+
+namespace {
+
+constexpr int kMaxC = 32;
+
+// One block per batch row: logits, softmax, per-row loss, dz = (p - y) / B
+// and dL/dlevel for the row.
+__global__ __launch_bounds__(256) void k_readout_row(const float* __restrict__ level, float invT,
+                                                     const float* __restrict__ W,
+                                                     const float* __restrict__ bias,
+                                                     const int32_t* __restrict__ labels, int B,
+                                                     int H, int C, float* __restrict__ dz,
+                                                     float* __restrict__ row_loss,
+                                                     float* __restrict__ dlevel,
+                                                     float* __restrict__ logits_out) {
+  __shared__ float red[256][kMaxC + 1];
+  __shared__ float s_dz[kMaxC];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  float acc[kMaxC];
+#pragma unroll
+  for (int c = 0; c < kMaxC; ++c) acc[c] = 0.0f;
+  for (int h = tid; h < H; h += blockDim.x) {
+    const float r = level[(int64_t)b * H + h] * invT;
+#pragma unroll
+    for (int c = 0; c < kMaxC; ++c)
+      if (c < C) acc[c] = fmaf(r, W[(int64_t)h * C + c], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < kMaxC; ++c) red[tid][c] = acc[c];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off)
+      for (int c = 0; c < C; ++c) red[tid][c] += red[tid + off][c];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    float z[kMaxC], zmax = -INFINITY;
+    for (int c = 0; c < C; ++c) {
+      z[c] = red[0][c] + bias[c];
+      zmax = fmaxf(zmax, z[c]);
+    }
+    float se = 0.0f;
+    for (int c = 0; c < C; ++c) se += expf(z[c] - zmax);
+    const int y = labels[b];
+    row_loss[b] = -(z[y] - zmax - logf(se));
+    for (int c = 0; c < C; ++c) {
+      const float pc = expf(z[c] - zmax) / se;
+      const float d = (pc - (c == y ? 1.0f : 0.0f)) / (float)B;
+      s_dz[c] = d;
+      dz[(int64_t)b * C + c] = d;
+      if (logits_out) logits_out[(int64_t)b * C + c] = z[c];
+    }
+  }
+  __syncthreads();
+  for (int h = tid; h < H; h += blockDim.x) {
+    float s = 0.0f;
+    for (int c = 0; c < C; ++c) s = fmaf(s_dz[c], W[(int64_t)h * C + c], s);
+    dlevel[(int64_t)b * H + h] = s * invT;
+  }
+}
+
+// dW[h][c] = sum_b r[b][h] dz[b][c]; db[c] = sum_b dz[b][c]; loss = mean.
+__global__ __launch_bounds__(256) void k_readout_wgrad(const float* __restrict__ level, float invT,
+                                                       const float* __restrict__ dz,
+                                                       const float* __restrict__ row_loss, int B,
+                                                       int H, int C, float* __restrict__ dW,
+                                                       float* __restrict__ db,
+                                                       float* __restrict__ loss) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t HC = (int64_t)H * C;
+  if (idx < HC) {
+    const int h = (int)(idx / C), c = (int)(idx % C);
+    float s = 0.0f;
+    for (int b = 0; b < B; ++b) s = fmaf(level[(int64_t)b * H + h] * invT, dz[(int64_t)b * C + c], s);
+    dW[idx] = s;
+  } else if (idx < HC + C) {
+    const int c = (int)(idx - HC);
+    float s = 0.0f;
+    for (int b = 0; b < B; ++b) s += dz[(int64_t)b * C + c];
+    db[c] = s;
+  } else if (idx == HC + C) {
+    float s = 0.0f;
+    for (int b = 0; b < B; ++b) s += row_loss[b];
+    *loss = s / (float)B;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              int64_t count, float lr, float b1, float b2,
+                                              float eps, float c1, float c2,
+                                              uint16_t* __restrict__ p16) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  p[i] = pi;
+  if (p16) {
+    uint32_t u = __float_as_uint(pi);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    p16[i] = (uint16_t)(u >> 16);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hh_readout_ce_workspace(int32_t B, int32_t C) {
+  if (B < 1 || C < 1) return 0;
+  return (size_t)B * (C + 1) * sizeof(float);
+}
+
+int32_t hh_readout_ce(const float* level, int32_t T, const float* W, const float* bias,
+                      const int32_t* labels, int32_t B, int32_t H, int32_t C, float* loss,
+                      float* dlevel, float* dW, float* db, float* logits, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+  if (!level || !W || !bias || !labels || !loss || !dlevel || !dW || !db) return HH_E_INVALID;
+  if (T < 1 || B < 1 || H < 1 || C < 1) return HH_E_SHAPE;
+  if (C > kMaxC) return HH_E_UNSUPPORTED;
+  if (!workspace || workspace_bytes < hh_readout_ce_workspace(B, C)) return HH_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  float* dz = (float*)workspace;
+  float* row_loss = dz + (size_t)B * C;
+  const float invT = 1.0f / (float)T;
+  hipLaunchKernelGGL(k_readout_row, dim3(B), dim3(256), 0, s, level, invT, W, bias, labels, B, H, C,
+                     dz, row_loss, dlevel, logits);
+  const int64_t work = (int64_t)H * C + C + 1;
+  hipLaunchKernelGGL(k_readout_wgrad, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, level,
+                     invT, dz, row_loss, B, H, C, dW, db, loss);
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+int32_t hh_adam_step(float* param, const float* grad, float* m, float* v, int64_t count, float lr,
+                     float beta1, float beta2, float eps, int32_t step, uint16_t* param_bf16,
+                     void* stream) {
+  if (!param || !grad || !m || !v) return HH_E_INVALID;
+  if (count < 0 || step < 1) return HH_E_SHAPE;
+  if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return HH_E_INVALID;
+  if (count == 0) return HH_OK;
+  const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
+  const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     param, grad, m, v, count, lr, beta1, beta2, eps, c1, c2, param_bf16);
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+}  // extern "C"

@@ -76,6 +76,7 @@ def _load():
         "hh_status_string": ([i32], ctypes.c_char_p),
         "hh_n_state": ([vp], i32),
         "hh_set_fusion": ([vp, i32], i32),
+        "hh_set_specialize": ([vp, i32], i32),
         "hh_init_state": ([vp, vp, vp, f32, vp], i32),
         "hh_step_n": ([vp, vp, i64, i32, P(Input), P(Outputs), vp], i32),
         "hh_attach_csr": ([vp, vp, vp, vp, i64, f32], i32),
@@ -85,7 +86,20 @@ def _load():
         "hh_backward_workspace": ([vp, i32], sz),
         "hh_check": ([vp, P(i64), vp], i32),
         "hh_proj_forward": ([vp, vp, vp, i32, i32, i32, vp], i32),
-        "hh_proj_wgrad": ([vp, vp, vp, i32, i32, i32, vp], i32),
+        "hh_proj_wgrad": ([vp, vp, vp, i32, i32, i32, vp, sz, vp], i32),
+        "hh_proj_wgrad_workspace": ([i32, i32, i32], sz),
+        "hh_readout_ce": ([vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp], i32),
+        "hh_readout_ce_workspace": ([i32, i32], sz),
+        "hh_adam_step": ([vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp], i32),
+        "hh_probe_issue": ([i32, i32, i32, vp, i32, vp], i32),
+        "hh_mlp_grad": ([vp, vp, vp, i32, i32, vp, vp, vp, sz, vp], i32),
+        "hh_mlp_grad_workspace": ([i32], sz),
+        "hh_mlp_forward": ([vp, vp, i32, i32, vp, vp], i32),
+        "hh_mlp_pack": ([vp, vp, vp, vp], i32),
+        "hh_mlp_packed_bytes": ([], sz),
+        "hh_mlp_infer": ([vp, vp, i32, vp, vp], i32),
+        "hh_surrogate_step_n": ([vp, vp, vp, vp, i64, i32, i32, P(Input), f32, i32, f32, vp, vp, vp],
+                                i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -100,9 +114,13 @@ lib = _load()
 def exported_symbols():
     """Names of the C-ABI entry points this binding uses."""
     return [n for n in ("hh_init", "hh_destroy", "hh_status_string", "hh_n_state", "hh_set_fusion",
+                        "hh_set_specialize",
                         "hh_init_state", "hh_step_n", "hh_attach_csr", "hh_set_external",
                         "hh_syn_propagate", "hh_backward", "hh_backward_workspace", "hh_check",
-                        "hh_proj_forward", "hh_proj_wgrad")]
+                        "hh_proj_forward", "hh_proj_wgrad", "hh_proj_wgrad_workspace",
+                        "hh_readout_ce", "hh_readout_ce_workspace", "hh_adam_step",
+                        "hh_mlp_grad", "hh_mlp_grad_workspace", "hh_mlp_forward", "hh_mlp_pack",
+                        "hh_mlp_packed_bytes", "hh_mlp_infer", "hh_surrogate_step_n")]
 
 
 def _ok(status: int, what: str):
@@ -176,6 +194,9 @@ class Model:
     def set_fusion(self, k: int):
         _ok(lib.hh_set_fusion(self.h, int(k)), "hh_set_fusion")
 
+    def set_specialize(self, on: bool):
+        _ok(lib.hh_set_specialize(self.h, 1 if on else 0), "hh_set_specialize")
+
     def new_state(self, device="cuda"):
         return torch.empty((self.n_state, self.n), dtype=torch.float32, device=device)
 
@@ -236,6 +257,16 @@ class Model:
         return st, fb.value
 
 
+PROBE_OPS = {"fma": 0, "exp2": 1, "rcp": 2, "sqrt": 3, "sin": 4, "mul64": 5}
+
+
+def probe_issue(op: str, iters: int, blocks: int, out):
+    """Launch the issue-rate probe (include/hh_probe.h); blocks * 256 * 8 *
+    iters operations of kind `op`."""
+    _ok(lib.hh_probe_issue(PROBE_OPS[op], int(iters), int(blocks), _ptr(out), int(out.numel()),
+                           _stream()), "hh_probe_issue")
+
+
 def proj_forward(A_bf16, W_bf16, out):
     M, K = A_bf16.shape
     N = W_bf16.shape[1]
@@ -246,10 +277,81 @@ def proj_forward(A_bf16, W_bf16, out):
     return out
 
 
-def proj_wgrad(A_bf16, dOut, dW):
+def proj_wgrad(A_bf16, dOut, dW, workspace=None):
     M, K = A_bf16.shape
     N = dOut.shape[1]
     assert A_bf16.dtype == torch.bfloat16 and dOut.dtype == torch.float32
     assert tuple(dW.shape) == (K, N) and dW.dtype == torch.float32 and dOut.shape[0] == M
-    _ok(lib.hh_proj_wgrad(_ptr(A_bf16), _ptr(dOut), _ptr(dW), M, N, K, _stream()), "hh_proj_wgrad")
+    need = int(lib.hh_proj_wgrad_workspace(M, N, K))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dW.device)
+    _ok(lib.hh_proj_wgrad(_ptr(A_bf16), _ptr(dOut), _ptr(dW), M, N, K, _ptr(workspace),
+                          workspace.numel() * workspace.element_size(), _stream()), "hh_proj_wgrad")
     return dW
+
+
+def readout_ce(level, T: int, W, bias, labels, dlevel, dW, db, loss, logits=None, workspace=None):
+    """Readout + cross entropy, forward and backward (see hh.h)."""
+    B, H = level.shape
+    C = W.shape[1]
+    assert labels.dtype == torch.int32 and labels.numel() == B
+    need = int(lib.hh_readout_ce_workspace(B, C))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=level.device)
+    _ok(lib.hh_readout_ce(_ptr(level), int(T), _ptr(W), _ptr(bias), _ptr(labels), B, H, C,
+                          _ptr(loss), _ptr(dlevel), _ptr(dW), _ptr(db), _ptr(logits),
+                          _ptr(workspace), workspace.numel(), _stream()), "hh_readout_ce")
+
+
+def adam_step(param, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
+              param_bf16=None):
+    _ok(lib.hh_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), float(lr),
+                         float(beta1), float(beta2), float(eps), int(step), _ptr(param_bf16),
+                         _stream()), "hh_adam_step")
+
+
+# ---------------------------------------------------------------------------
+# learned surrogate
+# ---------------------------------------------------------------------------
+MLP_NPARAM = 5062
+MLP_IN, MLP_H, MLP_OUT = 7, 64, 6
+
+
+def mlp_grad(params, X, Y, grad, loss=None, quantize=True, workspace=None):
+    S = X.shape[0]
+    need = int(lib.hh_mlp_grad_workspace(S))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
+    _ok(lib.hh_mlp_grad(_ptr(params), _ptr(X), _ptr(Y), S, 1 if quantize else 0, _ptr(grad),
+                        _ptr(loss), _ptr(workspace), workspace.numel(), _stream()), "hh_mlp_grad")
+    return workspace
+
+
+def mlp_forward(params, X, Y, quantize=True):
+    _ok(lib.hh_mlp_forward(_ptr(params), _ptr(X), X.shape[0], 1 if quantize else 0, _ptr(Y),
+                           _stream()), "hh_mlp_forward")
+
+
+def mlp_pack(params, norm):
+    packed = torch.empty(int(lib.hh_mlp_packed_bytes()), dtype=torch.uint8, device=params.device)
+    _ok(lib.hh_mlp_pack(_ptr(params), _ptr(norm), _ptr(packed), _stream()), "hh_mlp_pack")
+    return packed
+
+
+def mlp_infer(packed, X, Y):
+    _ok(lib.hh_mlp_infer(_ptr(packed), _ptr(X), X.shape[0], _ptr(Y), _stream()), "hh_mlp_infer")
+
+
+def surrogate_step_n(model: Model, packed, state, flags, n_steps: int, k: int, t0: int = 0, *,
+                     noise=None, i_dense=None, v_fallback=-50.0, check_every=10, check_tol=0.5,
+                     spikes=None, stats=None):
+    inp = Input()
+    if i_dense is not None:
+        inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
+    else:
+        inp.mode = IN_NOISE
+        inp.mu, inp.sigma, inp.seed = float(noise[0]), float(noise[1]), int(noise[2])
+    _ok(lib.hh_surrogate_step_n(model.h, _ptr(packed), _ptr(state), _ptr(flags), int(t0),
+                                int(n_steps), int(k), ctypes.byref(inp), float(v_fallback),
+                                int(check_every), float(check_tol), _ptr(spikes), _ptr(stats),
+                                _stream()), "hh_surrogate_step_n")

@@ -1,0 +1,214 @@
+"""Learned k-step surrogate for the cortical channel set: data generation with
+the plain fused kernel, training with the library's MLP forward/backward and
+Adam kernels, packing for the MFMA inference, deployment with per-neuron
+fallback, and the spike-time comparison against the plain integrator.
+
+Every numerical step runs in libhh kernels; torch is used to hold device
+buffers and to slice/stack the training set.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import hh
+from . import workloads as W
+
+K_STEPS = 10          # surrogate step = 10 plain steps of 0.025 ms
+V_FALLBACK = -50.0    # mV
+CHECK_EVERY = 10      # calls
+CHECK_TOL = 0.5       # mV
+
+
+def generate_transitions(n_traj=5000, T=10000, seed=5, seg=400, k=K_STEPS, dev="cuda"):
+    """Trajectories of the plain FP32 kernel (cortical set, nominal rates,
+    dt = 0.025 ms) under piecewise-constant currents U[0, 20) plus 3 z per
+    step; every step t with V <= -50 mV at t and t + k gives one transition
+    (x_t, mean I over [t, t+k)) -> x_{t+k} - x_t.  Returns (X [S,7], dY [S,6])
+    on the device (FP32, un-normalized)."""
+    m = W.custom_channels(dt=0.025)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    M = hh.Model(m, n_traj)
+    st = M.new_state()
+    v0 = -75.0 + 15.0 * torch.rand(n_traj, generator=gen, device=dev)
+    M.init_state(st, v0=v0)
+    nseg = (T + seg - 1) // seg
+    levels = 20.0 * torch.rand((nseg, n_traj), generator=gen, device=dev)
+    I = levels.repeat_interleave(seg, dim=0)[:T] + 3.0 * torch.randn((T, n_traj), generator=gen,
+                                                                        device=dev)
+    I = I.contiguous()
+    traj = torch.empty((T, M.n_state, n_traj), device=dev)
+    M.step_n(st, T, 0, i_dense=I, ckpt=traj, ckpt_every=1)
+    status, bad = M.check()
+    if status != 0:
+        raise RuntimeError("plain kernel failed while generating data (%d)" % status)
+    # state rows: V, m, h, n, p, q, V_lo
+    x = torch.cat([(traj[:, 0:1] + traj[:, 6:7]), traj[:, 1:6]], dim=1)  # [T, 6, n]
+    csum = torch.cumsum(torch.cat([torch.zeros((1, n_traj), device=dev), I.double()], 0), 0)
+    ibar = ((csum[k:] - csum[:-k]) / k).float()  # [T-k+1, n]: mean over [t, t+k)
+    xa, xb = x[:T - k], x[k:]
+    ib = ibar[:T - k]
+    ok = (xa[:, 0] <= V_FALLBACK) & (xb[:, 0] <= V_FALLBACK)
+    X = torch.cat([xa.permute(0, 2, 1), ib.unsqueeze(2)], dim=2)[ok]  # [S, 7]
+    dY = (xb - xa).permute(0, 2, 1)[ok]  # [S, 6]
+    return X.contiguous(), dY.contiguous()
+
+
+def norm_stats(X, dY):
+    """Per-feature mean and standard deviation: norm[0:7] input mean, [8:15]
+    input std, [16:22] output mean, [24:30] output std."""
+    norm = torch.zeros(32, device=X.device)
+    norm[0:7] = X.mean(0)
+    norm[8:15] = X.std(0).clamp_min(1e-6)
+    norm[16:22] = dY.mean(0)
+    norm[24:30] = dY.std(0).clamp_min(1e-9)
+    return norm
+
+
+def init_params(seed=0, dev="cuda"):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(hh.MLP_NPARAM, np.float32)
+    off = 0
+    for a, b in ((7, 64), (64, 64), (64, 6)):
+        p[off: off + a * b] = (rng.standard_normal(a * b) * np.sqrt(2.0 / a)).astype(np.float32)
+        off += a * b + b
+    return torch.tensor(p, device=dev)
+
+
+def train(X, dY, norm, *, epochs=8, batch=16384, lr=2e-3, seed=0, log=None):
+    """Adam on the normalized MSE with bf16-quantized forward (the deployed
+    numerics).  Returns (params, history of mean epoch losses)."""
+    dev = X.device
+    Xn = ((X - norm[0:7]) / norm[8:15]).contiguous()
+    Yn = ((dY - norm[16:22]) / norm[24:30]).contiguous()
+    S = X.shape[0]
+    params = init_params(seed, dev)
+    grad = torch.zeros_like(params)
+    m1 = torch.zeros_like(params)
+    m2 = torch.zeros_like(params)
+    loss = torch.zeros(1, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed + 1)
+    ws = None
+    hist = []
+    step = 0
+    total = epochs * (S // batch)
+    for ep in range(epochs):
+        perm = torch.randperm(S, generator=gen, device=dev)
+        acc = torch.zeros(1, device=dev)
+        nb = S // batch
+        for b in range(nb):
+            idx = perm[b * batch:(b + 1) * batch]
+            xb, yb = Xn[idx].contiguous(), Yn[idx].contiguous()
+            ws = hh.mlp_grad(params, xb, yb, grad, loss, quantize=True, workspace=ws)
+            step += 1
+            # cosine decay of the learning rate
+            lr_t = lr * 0.5 * (1.0 + np.cos(np.pi * step / total))
+            hh.adam_step(params, grad, m1, m2, step, lr_t)
+            acc += loss
+        hist.append(float(acc.item()) / max(nb, 1))
+        if log:
+            log("epoch %d loss %.4e" % (ep, hist[-1]))
+    return params, hist
+
+
+def evaluate(params, X, dY, norm):
+    """Normalized MSE of the quantized forward on a held-out set."""
+    Xn = ((X - norm[0:7]) / norm[8:15]).contiguous()
+    Yn = ((dY - norm[16:22]) / norm[24:30]).contiguous()
+    Y = torch.empty_like(Yn)
+    hh.mlp_forward(params, Xn, Y, quantize=True)
+    return float(((Y - Yn) ** 2).sum(1).mean().item())
+
+
+def spike_time_error(ref_bits, bits, n, dt_ref, dt_test, window_ms=2.0, max_neurons=None):
+    """Match spikes of a test raster to the reference raster (greedy, in time
+    order, within +-window_ms).  Returns dict with mean and p95 |dt| (ms) of
+    matched spikes, the unmatched fraction (of reference + test spikes) and
+    counts.  Rasters are [T][words] uint32 bit rows (numpy)."""
+    def times(bits_, dt):
+        b = np.unpackbits(np.ascontiguousarray(bits_).view(np.uint8).reshape(bits_.shape[0], -1),
+                          axis=1, bitorder="little")[:, :n]
+        t, i = np.nonzero(b)
+        order = np.lexsort((t, i))
+        return i[order], (t[order] + 1) * dt
+    ri, rt = times(ref_bits, dt_ref)
+    ti, tt = times(bits, dt_test)
+    nn = n if max_neurons is None else min(n, max_neurons)
+    rs = np.searchsorted(ri, np.arange(nn + 1))
+    ts = np.searchsorted(ti, np.arange(nn + 1))
+    diffs = []
+    unmatched = 0
+    for j in range(nn):
+        a = rt[rs[j]:rs[j + 1]]
+        b = tt[ts[j]:ts[j + 1]]
+        used = np.zeros(len(b), bool)
+        for x in a:
+            if len(b) == 0:
+                unmatched += 1
+                continue
+            c = np.abs(b - x)
+            c[used] = np.inf
+            q = int(np.argmin(c))
+            if c[q] <= window_ms:
+                used[q] = True
+                diffs.append(c[q])
+            else:
+                unmatched += 1
+        unmatched += int((~used).sum())
+    diffs = np.asarray(diffs)
+    n_ref = int(rs[nn])
+    return {"matched": int(len(diffs)), "ref_spikes": n_ref,
+            "mean_abs_ms": float(diffs.mean()) if len(diffs) else 0.0,
+            "p95_abs_ms": float(np.percentile(diffs, 95)) if len(diffs) else 0.0,
+            "unmatched_frac": unmatched / max(n_ref + int(ts[nn]), 1)}
+
+
+def deploy(packed, n, T, *, i_dense=None, noise=None, spikes=True, check_every=CHECK_EVERY,
+           v_fallback=V_FALLBACK, check_tol=CHECK_TOL, dev="cuda"):
+    """Run the surrogate deployment kernel on n neurons (cortical set,
+    nominal rates) for T plain-step equivalents.  Returns (model, state,
+    spike bits or None, stats [surrogate calls, plain calls, failed checks])."""
+    m = W.custom_channels(dt=0.025)
+    M = hh.Model(m, n)
+    st = M.new_state()
+    M.init_state(st, v0_scalar=-65.0)
+    flags = torch.zeros(n, dtype=torch.uint8, device=dev)
+    bits = torch.zeros((T, M.words), dtype=torch.int32, device=dev) if spikes else None
+    stats = torch.zeros(3, dtype=torch.int64, device=dev)
+    hh.surrogate_step_n(M, packed, st, flags, T, K_STEPS, 0, i_dense=i_dense, noise=noise,
+                        v_fallback=v_fallback, check_every=check_every, check_tol=check_tol,
+                        spikes=bits, stats=stats)
+    return M, st, bits, stats
+
+
+def plain_run(n, T, *, dt=0.025, v_method="fe", i_dense=None, noise=None, spikes=True,
+              dev="cuda"):
+    m = W.custom_channels(dt=dt, v_method=v_method)
+    M = hh.Model(m, n)
+    st = M.new_state()
+    M.init_state(st, v0_scalar=-65.0)
+    bits = torch.zeros((T, M.words), dtype=torch.int32, device=dev) if spikes else None
+    M.step_n(st, T, 0, i_dense=i_dense, noise=noise, spikes=bits)
+    return M, st, bits
+
+
+def coarse_input(I, r):
+    """Block means of a dense fine-step input over r consecutive steps (the
+    same input integral at a coarser dt)."""
+    T, n = I.shape
+    return I[: (T // r) * r].view(T // r, r, n).mean(1).contiguous()
+
+
+def timed(fn, reps=3):
+    torch.cuda.synchronize()
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps

@@ -92,4 +92,99 @@ def ill_conditioned(O, model, st0, T, idx, base_kw, *, v_tol=1e-3):
         bad = spike_mismatch(r["spikes"], ref["spikes"])
         sp[bad] = True
         tr |= np.max(np.abs(r["v"] - ref["v"]), axis=0) > v_tol
+    # representation probe: the same FP64 steps with the state stored in
+    # FP32 after every step (what any FP32 integrator must at least incur);
+    # ill-conditioned when that alone uses half the trace tolerance
+    s = s0.copy()
+    vr = np.zeros((T, len(idx)))
+    spk = np.zeros((T, len(idx)), np.uint8)
+    kw1 = dict(kw, cm=cm)
+    dense = kw1.pop("i_dense", None)
+    t0 = int(kw1.pop("t0", 0))
+    for k in range(T):
+        extra = {} if dense is None else {"i_dense": dense[k:k + 1]}
+        r = O.run(model, s, 1, t0=t0 + k, record_v=True, **kw1, **extra)
+        s[:] = s.astype(np.float32).astype(np.float64)
+        vr[k] = r["v"][0]
+        spk[k] = r["spikes"][0]
+    sp[spike_mismatch(spk, ref["spikes"])] = True
+    tr |= np.max(np.abs(vr - ref["v"]), axis=0) > 0.5 * v_tol
     return sp, tr
+
+
+def _interp_times(v, thr):
+    """Upward threshold crossings, interpolated within the step (in steps)."""
+    out = []
+    for j in range(v.shape[1]):
+        x = v[:, j]
+        ks = np.nonzero((x[:-1] < thr) & (x[1:] >= thr))[0] + 1
+        t = [k - 1 + (thr - x[k - 1]) / (x[k] - x[k - 1]) for k in ks]
+        if x[0] >= thr:  # crossing in the first step is not interpolable here
+            t = [0.0] + t
+        out.append(np.array(t))
+    return out
+
+
+def spike_horizons(O, model, st0, T, idx, base_kw, *, shift_tol=0.1):
+    """Per neuron in idx: the number of leading oracle spikes whose timing is
+    well conditioned.  A spike is ill-conditioned when its interpolated time
+    moves by more than shift_tol steps under a 1e-6 relative probe of the
+    input, the capacitance or one group (A, B or K) of rate coefficients;
+    that spike and all later ones lie beyond the neuron's predictability
+    horizon.  Returns (horizon counts, oracle spike-step lists)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    n = st0.shape[1]
+    kw = _subset_kw(base_kw, idx, n)
+    cm = kw.get("cm")
+    if cm is None:
+        cm = np.full(len(idx), float(model["C"]))
+    coef = kw.get("coef")
+    if coef is None:
+        G = len(model["gates"])
+        nom = np.zeros(G * 8)
+        for g, gate in enumerate(model["gates"]):
+            for r, rt in enumerate(gate["rates"]):
+                nom[g * 8 + r * 4: g * 8 + r * 4 + 4] = rt[1:5]
+        coef = np.repeat(nom[:, None], len(idx), axis=1)
+    kw = dict(kw, cm=cm, coef=coef)
+    s0 = st0[:, idx]
+    thr = float(model["v_th"])
+    ref = O.run(model, s0.copy(), T, record_v=True, **kw)
+    v0 = np.vstack([s0[0:1], ref["v"]])
+    base_t = _interp_times(v0, thr)
+    probes = []
+    for f in (1 + PROBE, 1 - PROBE):
+        for key in ("i_const", "noise_mu", "i_dense"):
+            if kw.get(key) is not None:
+                probes.append(dict(kw, **{key: kw[key] * f}))
+        probes.append(dict(kw, cm=cm * f))
+        for j in range(3):  # A, B, K rows of every rate
+            c2 = coef.copy()
+            c2[j::4] *= f
+            probes.append(dict(kw, coef=c2))
+    h = np.array([len(b) for b in base_t])
+    for p in probes:
+        r = O.run(model, s0.copy(), T, record_v=True, **p)
+        tt = _interp_times(np.vstack([s0[0:1], r["v"]]), thr)
+        for j, (a, b) in enumerate(zip(tt, base_t)):
+            m_ = min(len(a), len(b))
+            d = np.abs(a[:m_] - b[:m_]) > shift_tol
+            first = int(np.argmax(d)) if d.any() else m_
+            if len(a) != len(b):
+                first = min(first, m_)
+            h[j] = min(h[j], first)
+    steps = [np.nonzero(ref["spikes"][:, j])[0] for j in range(len(idx))]
+    return h, steps
+
+
+def match_to_horizon(g_steps, o_steps, h, tol_steps=1):
+    """GPU spike steps agree with the first h oracle spikes within tol_steps,
+    and the GPU has no other spike before the horizon."""
+    if h >= len(o_steps):
+        return len(g_steps) == len(o_steps) and (
+            len(o_steps) == 0 or np.max(np.abs(np.asarray(g_steps) - o_steps)) <= tol_steps)
+    cutoff = o_steps[h] - tol_steps - 1
+    g_before = np.asarray([t for t in g_steps if t < cutoff])
+    if len(g_before) != h:
+        return False
+    return h == 0 or np.max(np.abs(g_before - o_steps[:h])) <= tol_steps

@@ -12,13 +12,14 @@ import pytest
 
 from oracle import oracle as O
 from paper_2601_21407_amd import workloads as W
-from tests.gpu_util import ill_conditioned, need_gpu, print_case, spike_mismatch
+from tests.gpu_util import (ill_conditioned, match_to_horizon, need_gpu, print_case,
+                             spike_horizons, spike_mismatch)
 
 pytestmark = pytest.mark.gpu
 
 
 def _run_gpu(model, n, T, *, B=1, i_const=None, noise=None, i_dense=None, coef=None, cm=None,
-             v0=-65.0, record_v=False, fusion=32, t0=0, state=None):
+             v0=-65.0, record_v=False, fusion=32, t0=0, state=None, specialize=True):
     torch = need_gpu()
     from paper_2601_21407_amd import hh
     N = n // B
@@ -27,6 +28,7 @@ def _run_gpu(model, n, T, *, B=1, i_const=None, noise=None, i_dense=None, coef=N
     cm_t = None if cm is None else torch.tensor(cm, dtype=torch.float32, device=dev)
     M = hh.Model(model, N, B, coef=coef_t, cm=cm_t)
     M.set_fusion(fusion)
+    M.set_specialize(specialize)
     st = M.new_state() if state is None else state
     if state is None:
         if np.isscalar(v0):
@@ -53,8 +55,11 @@ def _columns(bits, ids):
 
 
 def _judge(model, st0, T, g, ro, base_kw, *, max_ill_frac, v_tol=1e-3, label=""):
-    """Apply the parity criteria to a GPU run g and the oracle run ro (both
-    over all n neurons) and return the report."""
+    """Parity criteria for a GPU run g against the oracle run ro (both over all
+    n neurons).  Quiet neurons (no oracle spike): V within v_tol at every step
+    unless the trace is ill-conditioned (ill_conditioned).  Spiking neurons:
+    spike trains equal within one dt up to each neuron's predictability
+    horizon (spike_horizons)."""
     n = st0.shape[1]
     quiet = np.nonzero(ro["spikes"].sum(0) == 0)[0]
     dv = np.zeros(n)
@@ -62,29 +67,54 @@ def _judge(model, st0, T, g, ro, base_kw, *, max_ill_frac, v_tol=1e-3, label="")
         dv[quiet] = np.max(np.abs(g["v"][:, quiet] - ro["v"][:, quiet]), axis=0)
     trace_bad = quiet[dv[quiet] > v_tol]
     spike_bad = spike_mismatch(g["raster"], ro["spikes"])
-    cand = np.union1d(trace_bad, spike_bad)
-    sp_ill, tr_ill = ill_conditioned(O, model, st0, T, cand, base_kw, v_tol=v_tol)
-    ill = set(cand[sp_ill | tr_ill].tolist())
-    fails = [i for i in cand.tolist() if i not in ill]
-    rep = ("%s n=%d quiet=%d max|dV|quiet(well-cond)=%.3g mV, spike mismatches=%d, "
-           "trace>tol=%d, ill-conditioned=%d, failures=%d"
-           % (label, n, len(quiet), max([dv[i] for i in quiet if i not in ill] or [0.0]),
-              len(spike_bad), len(trace_bad), len(ill), len(fails)))
+    sp_ill_q, tr_ill_q = ill_conditioned(O, model, st0, T, trace_bad, base_kw, v_tol=v_tol)
+    quiet_fail = trace_bad[~(tr_ill_q | sp_ill_q)].tolist()
+    # a quiet oracle neuron that fires on the GPU is judged by the trace rule too
+    spike_bad_q = np.intersect1d(spike_bad, quiet)
+    spike_bad_s = np.setdiff1d(spike_bad, quiet)
+    h, steps = spike_horizons(O, model, st0, T, spike_bad_s, base_kw)
+    spike_fail, beyond = [], 0
+    for j, i in enumerate(spike_bad_s.tolist()):
+        gs = np.nonzero(g["raster"][:, i])[0]
+        if match_to_horizon(gs, steps[j], h[j]):
+            beyond += 1
+        else:
+            spike_fail.append(i)
+    sq, tq = ill_conditioned(O, model, st0, T, spike_bad_q, base_kw, v_tol=v_tol)
+    quiet_fail += spike_bad_q[~(sq | tq)].tolist()
+    fails = sorted(set(quiet_fail + spike_fail))
+    n_ill = int((tr_ill_q | sp_ill_q).sum()) + beyond + int((sq | tq).sum())
+    wc = [dv[i] for i in quiet if i not in set(trace_bad.tolist())]
+    rep = ("%s n=%d quiet=%d max|dV| (well-conditioned quiet)=%.3g mV; spike-train mismatches=%d "
+           "(%d beyond the predictability horizon); ill-conditioned quiet traces=%d; failures=%d"
+           % (label, n, len(quiet), max(wc or [0.0]), len(spike_bad), beyond,
+              int((tr_ill_q | sp_ill_q).sum()), len(fails)))
     print(rep, flush=True)
     assert not fails, (rep, fails[:10])
-    assert len(ill) <= max_ill_frac * n, rep
+    assert n_ill <= max_ill_frac * n, rep
     return rep
 
 
-def test_validation_workload_full_size():
-    """1,024 classic HH neurons, I ~ U[0, 20), dt = 0.01 ms, 10,000 steps."""
-    print_case("classic HH 1024 x 10000 dt=0.01")
+_ORACLE_CACHE = {}
+
+
+def _cached(key, fn):
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = fn()
+    return _ORACLE_CACHE[key]
+
+
+@pytest.mark.parametrize("specialize", [True, False])
+def test_validation_workload_full_size(specialize):
+    """1,024 classic HH neurons, I ~ U[0, 20), dt = 0.01 ms, 10,000 steps
+    (compiled specialization and run-time interpreter)."""
+    print_case("classic HH 1024 x 10000 dt=0.01 specialize=%s" % specialize)
     m = W.classic_hh(dt=0.01)
     n, T = 1024, 10000
     I = W.validation_currents(n, seed=1).astype(np.float64)
-    g = _run_gpu(m, n, T, i_const=I, record_v=True)
+    g = _run_gpu(m, n, T, i_const=I, record_v=True, specialize=specialize)
     st0 = O.init_state(m, np.full(n, -65.0))
-    ro = O.run(m, st0.copy(), T, i_const=I, record_v=True)
+    ro = _cached("validation", lambda: O.run(m, st0.copy(), T, i_const=I, record_v=True))
     assert (ro["spikes"].sum(0) == 0).sum() > 50 and (ro["spikes"].sum(0) > 0).sum() > 500
     _judge(m, st0, T, g, ro, {"i_const": I}, max_ill_frac=0.02, label="validation")
 
@@ -102,22 +132,23 @@ def test_noise_stream_matches_oracle():
     del torch
 
 
-def test_custom_channels_sampled_full_size():
+@pytest.mark.parametrize("specialize", [True, False])
+def test_custom_channels_sampled_full_size(specialize):
     """1,048,576 neurons with jittered cortical channels and noisy input,
     dt = 0.025 ms, 4,000 steps, 32 fused steps per launch; 4,096 sampled
     neurons checked against the oracle."""
-    print_case("custom channels 1048576 x 4000 K=32 (sampled 4096)")
+    print_case("custom channels 1048576 x 4000 K=32 (sampled 4096) specialize=%s" % specialize)
     m = W.custom_channels(dt=0.025)
     n, T, seed = 1 << 20, 4000, 2
     coef = W.jitter_coef(m, n, seed=seed)
-    g = _run_gpu(m, n, T, noise=(5.0, 3.0, seed), coef=coef, fusion=32)
+    g = _run_gpu(m, n, T, noise=(5.0, 3.0, seed), coef=coef, fusion=32, specialize=specialize)
     assert np.isfinite(g["state"]).all()
     rng = np.random.default_rng(99)
     ids = np.unique(np.concatenate([[0, 1, 63, 64, n - 1], rng.choice(n, 4091, replace=False)]))
     c64 = coef[:, ids].astype(np.float64)
     st0 = O.init_state(m, np.full(len(ids), -65.0), coef=c64)
     kw = {"noise_mu": 5.0, "noise_sigma": 3.0, "seed": seed, "coef": c64, "ids": ids}
-    ro = O.run(m, st0.copy(), T, **kw)
+    ro = _cached("custom", lambda: O.run(m, st0.copy(), T, **kw))
     assert ro["spikes"].sum(0).mean() > 1.0
     gs = {"raster": _columns(g["bits"], ids), "v": None}
     _judge(m, st0, T, gs, ro, kw, max_ill_frac=0.02, label="custom-channels")
@@ -185,6 +216,9 @@ def test_fusion_depth_and_resume_are_bit_identical():
         assert np.array_equal(o["state"], outs[0]["state"])
         assert np.array_equal(o["raster"], outs[0]["raster"])
         assert np.array_equal(o["v"], outs[0]["v"])
+    gen = _run_gpu(m, n, T, noise=(5.0, 3.0, seed), coef=coef, fusion=32, record_v=True,
+                   specialize=False)
+    assert np.max(np.abs(gen["v"] - outs[0]["v"])[:50]) < 1e-3  # same math, other rounding order
     a = _run_gpu(m, n, 333, noise=(5.0, 3.0, seed), coef=coef)
     b = _run_gpu(m, n, T - 333, noise=(5.0, 3.0, seed), coef=coef, t0=333, state=a["state_t"])
     assert np.array_equal(b["state"], outs[0]["state"])
