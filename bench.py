@@ -29,16 +29,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "HH neuron-updates/s fwd & fwd+bwd; surrogate vs plain at equal spike-time error"
-PEAK_LANE_OPS = 256 * 64 * 2.4e9  # FP32 VALU lane operations per second (no packed math)
+# FP32 VALU issue: 256 CUs x 4 SIMDs x 32 lanes per cycle x 2.4 GHz = 78.6 T FMA/s,
+# the published 157.3 TFLOP/s vector peak counted in FMAs.  The shader-clock
+# probe shows non-packed v_fma_f32 reaching that width on gfx950 (25-34 lanes
+# per SIMD per cycle), so packed math is not needed for the peak.
+PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
 # Issue cost of one operation in VALU lane-slots, relative to one FP32
-# FMA/add/mul.  The issue-rate probe (hh_probe_issue) measures transcendentals
-# (v_exp/v_log/v_rcp/v_sqrt/v_sin/v_cos) and the 32x32->64 integer multiply
-# at half the FMA rate on gfx950 (ratio 1.86-1.99); the live probe reports
-# the ratios next to every result.
-W_TRANS = 2.0
-W_MUL64 = 2.0
+# FMA/add/mul at the peak above.  The issue-rate probe (hh_probe_issue)
+# measures transcendentals (v_exp/v_log/v_rcp/v_sqrt/v_sin/v_cos) and the
+# 32x32->64 integer multiply at ~19 T/s on gfx950, i.e. 78.6 / 19 = 4.1 slots;
+# the live probe reports the rates next to every result.
+W_TRANS = 4.0
+W_MUL64 = 4.0
 
 # Per rate form: (FP32 arithmetic ops, transcendental ops), counted from the
 # definition u = (V - B) / K (a subtract and a multiply by 1/K):
@@ -368,6 +372,82 @@ def bench_layer(reps=5, ckpt_every=50):
 
 
 # ---------------------------------------------------------------------------
+# learned surrogate vs plain integrator at equal spike-time error
+# ---------------------------------------------------------------------------
+def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
+    """Train the surrogate on 50 M transitions of the plain kernel, deploy it
+    on n neurons x T steps (dense input 5 + 3 z, the same realization for
+    every method), and place it against the plain integrator at dt = 0.025
+    (reference), 0.05 (explicit Euler), 0.1 and 0.25 ms (exponential Euler
+    in V).  Time = kernel time of the simulation on the GPU; spike-time error
+    against the reference on the first eval_neurons neurons."""
+    import torch
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import surrogate as SG
+    t0 = time.perf_counter()
+    X, dY = SG.generate_transitions(n_traj=5000, T=10000, seed=5)
+    norm = SG.norm_stats(X, dY)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    params, hist = SG.train(X, dY, norm, epochs=epochs, batch=16384, lr=2e-3)
+    _sync()
+    t_train = time.perf_counter() - t0
+    n_trans = int(X.shape[0])
+    del X, dY
+    packed = hh.mlp_pack(params, norm)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(41)
+    I = torch.empty((T, n), device="cuda")
+    I.normal_(0.0, 3.0, generator=gen)
+    I += 5.0
+    res = {"training": {"transitions": n_trans, "epochs": epochs, "final_loss": hist[-1],
+                        "loss_history": hist, "gen_s": t_gen, "train_s": t_train}}
+
+    def kernel_time(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()  # warm-up
+        _sync()
+        e0.record()
+        out = fn()
+        e1.record()
+        _sync()
+        return e0.elapsed_time(e1), out
+
+    ms_ref, (_, _, bits_ref) = kernel_time(lambda: SG.plain_run(n, T, i_dense=I))
+    ref_np = bits_ref.cpu().numpy()
+    rows = []
+    ms_sur, (_, _, bits_s, stats) = kernel_time(lambda: SG.deploy(packed, n, T, i_dense=I))
+    st = stats.cpu().numpy()
+    e = SG.spike_time_error(ref_np, bits_s.cpu().numpy(), n, 0.025, 0.025,
+                            max_neurons=eval_neurons)
+    rows.append(dict(method="surrogate k=10", ms=ms_sur, speedup=ms_ref / ms_sur,
+                     surrogate_call_frac=float(st[0] / max(st[0] + st[1], 1)),
+                     failed_checks=int(st[2]), **e))
+    ms_noise, _ = kernel_time(lambda: SG.deploy(packed, n, T, noise=(5.0, 3.0, 2), spikes=False))
+    ms_plain_noise, _ = kernel_time(lambda: SG.plain_run(n, T, noise=(5.0, 3.0, 2), spikes=False))
+    rows.append(dict(method="plain dt=0.025 (reference)", ms=ms_ref, speedup=1.0,
+                     mean_abs_ms=0.0, p95_abs_ms=0.0, unmatched_frac=0.0))
+    for dt, vm in ((0.05, "fe"), (0.1, "ee"), (0.25, "ee")):
+        r = int(round(dt / 0.025))
+        Ic = SG.coarse_input(I, r)
+        msc, (_, _, bits_c) = kernel_time(lambda: SG.plain_run(n, T // r, dt=dt, v_method=vm,
+                                                               i_dense=Ic))
+        e = SG.spike_time_error(ref_np, bits_c.cpu().numpy(), n, 0.025, dt,
+                                max_neurons=eval_neurons)
+        rows.append(dict(method="plain dt=%g %s" % (dt, vm), ms=msc, speedup=ms_ref / msc, **e))
+        del Ic
+    sur = rows[0]
+    dominated = [r["method"] for r in rows[2:]
+                 if r["speedup"] >= sur["speedup"] and r["mean_abs_ms"] <= sur["mean_abs_ms"]
+                 and r["unmatched_frac"] <= sur["unmatched_frac"]]
+    res.update({"n": n, "T": T, "eval_neurons": eval_neurons, "pareto": rows,
+                "surrogate_dominated_by": dominated,
+                "noise_input": {"surrogate_ms": ms_noise, "plain_ms": ms_plain_noise,
+                                "speedup": ms_plain_noise / ms_noise}})
+    return res
+
+
+# ---------------------------------------------------------------------------
 # issue-rate probe
 # ---------------------------------------------------------------------------
 def probe_rates():
@@ -376,7 +456,7 @@ def probe_rates():
     out = torch.empty(1 << 20, device="cuda")
     blocks, iters = 256 * 32, 2000
     res = {}
-    for op in ("fma", "exp2", "rcp", "sqrt", "sin", "mul64"):
+    for op in ("fma", "exp2", "rcp", "sqrt", "sin", "mul64", "mix"):
         hh.probe_issue(op, 10, blocks, out)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         _sync()
@@ -385,9 +465,44 @@ def probe_rates():
         b.record()
         _sync()
         ms = a.elapsed_time(b)
-        res[op] = blocks * 256 * 8 * iters / (ms / 1e3) / 1e12  # T lane-ops/s
+        ops = blocks * 256 * 8 * iters * (2 if op == "mix" else 1)
+        res[op] = ops / (ms / 1e3) / 1e12  # T lane-ops/s
     res["ratio_vs_fma"] = {k: res["fma"] / v for k, v in res.items() if k != "fma"}
+    # an exp + fma pair costs 1/fma + 1/exp2 when the two share one issue
+    # port, max(...) when they overlap
+    res["mix_pair_ns_per_Tpair"] = 2.0 / res["mix"]
+    res["mix_if_serial"] = 1.0 / res["fma"] + 1.0 / res["exp2"]
+    res["mix_if_overlap"] = max(1.0 / res["fma"], 1.0 / res["exp2"])
     return res
+
+
+def counters_run():
+    """A plain 1 GiB device copy (known traffic: 1 GiB read + 1 GiB written)
+    followed by one launch of the headline kernel (32 steps of 1,048,576
+    neurons), for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs."""
+    import torch
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import workloads as W
+    a = torch.empty(1 << 28, device="cuda")
+    b = torch.empty(1 << 28, device="cuda")
+    a.fill_(1.0)
+    _sync()
+    b.copy_(a)
+    _sync()
+    n, seed = 1 << 20, 2
+    m = W.custom_channels(dt=0.025)
+    coef = torch.tensor(W.jitter_coef(m, n, seed=seed), device="cuda")
+    M = hh.Model(m, n, coef=coef)
+    M.set_fusion(32)
+    st = M.new_state()
+    M.init_state(st, v0_scalar=-65.0)
+    spikes = torch.zeros((32, M.words), dtype=torch.int32, device="cuda")
+    _sync()
+    M.step_n(st, 32, 0, noise=(5.0, 3.0, seed), spikes=spikes)
+    _sync()
+    print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
+                      "k_step_alg_bytes": n * (2 * M.n_state * 4 + 40 * 4) + 32 * M.words * 4,
+                      "src_hash": _src_hash(STEP_KERNEL_SOURCES)}))
 
 
 def main():
@@ -395,8 +510,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--parts", default="layer,net,probe")
+    ap.add_argument("--parts", default="layer,net,surrogate,probe")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="run the copy + one headline launch for rocprofv3 counter passes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X here; "
@@ -407,6 +524,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.counters:
+        counters_run()
+        return
     parts = [p for p in args.parts.split(",") if p]
 
     head = bench_headline(args.steps, args.warmup)
@@ -420,6 +540,9 @@ def main():
     if "net" in parts:
         extra["network"] = bench_network()
         print("[bench] network done", file=sys.stderr, flush=True)
+    if "surrogate" in parts:
+        extra["surrogate"] = bench_surrogate()
+        print("[bench] surrogate done", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline_headline()
 
     line = {

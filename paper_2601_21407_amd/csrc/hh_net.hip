@@ -104,10 +104,73 @@ __device__ __forceinline__ void deliver_row(const int64_t* __restrict__ row_ptr,
   }
 }
 
+// Inclusive prefix sum of v[0..cnt) in LDS, cnt <= blockDim (Hillis-Steele;
+// short lists are summed by one lane).  Ends with a barrier.
+__device__ void block_inclusive_scan(int* v, int cnt) {
+  if (cnt <= 32) {
+    if (threadIdx.x == 0)
+      for (int e = 1; e < cnt; ++e) v[e] += v[e - 1];
+    __syncthreads();
+    return;
+  }
+  for (int off = 1; off < cnt; off <<= 1) {
+    int x = 0;
+    const int t = threadIdx.x;
+    if (t < cnt && t >= off) x = v[t - off];
+    __syncthreads();
+    if (t < cnt && t >= off) v[t] += x;
+    __syncthreads();
+  }
+}
+
+// Scatter of `total` synaptic events of the block's spiking rows: lane t
+// takes events t, t + B, t + 2B, ... (B = block size), issuing up to 8
+// independent (col, w) loads before its atomics so the loads overlap.
+__device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
+                                             const float* __restrict__ w, float scale40,
+                                             const int64_t* s_r0, const int* s_pre, int cnt,
+                                             int total, unsigned long long* acc_e,
+                                             unsigned long long* acc_i) {
+  constexpr int U = 8;
+  const int B = blockDim.x;
+  for (int x0 = threadIdx.x; x0 < total; x0 += U * B) {
+    int32_t tg[U];
+    float wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = x0 + u * B;
+      tg[u] = -1;
+      wv[u] = 0.0f;
+      if (x < total) {
+        // row e: first e with s_pre[e] > x
+        int lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (s_pre[mid] > x) hi = mid;
+          else lo = mid + 1;
+        }
+        const int before = lo ? s_pre[lo - 1] : 0;
+        const int64_t q = s_r0[lo] + (x - before);
+        tg[u] = col[q];
+        wv[u] = w[q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (tg[u] >= 0) {
+        const unsigned long long inc = (unsigned long long)__float2ull_rn(fabsf(wv[u]) * scale40);
+        atomicAdd(wv[u] > 0.0f ? &acc_e[tg[u]] : &acc_i[tg[u]], inc);
+      }
+    }
+  }
+}
+
 template <class S>
 __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   constexpr int NG = S::kNG;
   __shared__ int s_list[kNetBlock];
+  __shared__ int s_pre[kNetBlock];
+  __shared__ int64_t s_r0[kNetBlock];
   __shared__ int s_cnt;
   __shared__ int s_ok;
   const int64_t n = A.n;
@@ -164,8 +227,19 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
     const int cnt = s_cnt;
     unsigned long long* acc_e = A.acc + (int64_t)(k & 1) * 2 * n;
     unsigned long long* acc_i = acc_e + n;
-    for (int e = 0; e < cnt; ++e)
-      deliver_row(A.row_ptr, A.col, A.w, scale40, s_list[e], acc_e, acc_i, threadIdx.x, blockDim.x);
+    if (cnt > 0) {
+      // flatten the (row, synapse) pairs of all spiking rows of the block
+      if ((int)threadIdx.x < cnt) {
+        const int j = s_list[threadIdx.x];
+        const int64_t r0 = A.row_ptr[j];
+        s_r0[threadIdx.x] = r0;
+        s_pre[threadIdx.x] = (int)(A.row_ptr[j + 1] - r0);
+      }
+      __syncthreads();
+      block_inclusive_scan(s_pre, cnt);
+      const int total = s_pre[cnt - 1];
+      scatter_flat(A.col, A.w, scale40, s_r0, s_pre, cnt, total, acc_e, acc_i);
+    }
 
     if (!grid_barrier(A.bar, gridDim.x, gen, A.spin_limit, A.flags, &s_ok)) break;
 

@@ -257,7 +257,7 @@ class Model:
         return st, fb.value
 
 
-PROBE_OPS = {"fma": 0, "exp2": 1, "rcp": 2, "sqrt": 3, "sin": 4, "mul64": 5}
+PROBE_OPS = {"fma": 0, "exp2": 1, "rcp": 2, "sqrt": 3, "sin": 4, "mul64": 5, "mix": 6}
 
 
 def probe_issue(op: str, iters: int, blocks: int, out):

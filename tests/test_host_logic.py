@@ -1,0 +1,97 @@
+"""CPU tests of host-side logic: spike-time matching and coarse inputs used
+to judge the surrogate, the bench's algorithmic operation count, workload
+generators and the predictability-horizon helper."""
+import numpy as np
+import pytest
+
+from paper_2601_21407_amd import workloads as W
+
+
+def _bits(raster):
+    T, n = raster.shape
+    words = (n + 31) // 32
+    pad = np.zeros((T, words * 32), np.uint8)
+    pad[:, :n] = raster
+    return np.packbits(pad.reshape(T, -1, 8), axis=2, bitorder="little").reshape(T, -1).view(np.uint32)
+
+
+def test_spike_time_error_matching():
+    torch = pytest.importorskip("torch")  # noqa: F841 (surrogate imports torch)
+    from paper_2601_21407_amd import surrogate as SG
+    T, n = 400, 3
+    ref = np.zeros((T, n), np.uint8)
+    tst = np.zeros((T, n), np.uint8)
+    ref[[10, 100, 300], 0] = 1
+    tst[[12, 100, 310], 0] = 1   # shifts 2 steps, 0, 10 steps
+    ref[50, 1] = 1                # missed by the test
+    tst[[5, 200], 2] = 1          # two extra spikes
+    e = SG.spike_time_error(_bits(ref), _bits(tst), n, 0.1, 0.1, window_ms=2.0)
+    assert e["matched"] == 3
+    assert e["mean_abs_ms"] == pytest.approx((0.2 + 0.0 + 1.0) / 3)
+    assert e["unmatched_frac"] == pytest.approx(3 / 9)
+    # coarse raster: times are (step+1)*dt of each raster's own dt
+    tc = np.zeros((T // 2, n), np.uint8)
+    tc[[5, 50, 150], 0] = 1      # 1.2, 10.2, 30.2 ms vs 1.1, 10.1, 30.1
+    e2 = SG.spike_time_error(_bits(ref), _bits(tc), n, 0.1, 0.2, window_ms=2.0, max_neurons=1)
+    assert e2["matched"] == 3 and e2["mean_abs_ms"] == pytest.approx(0.1)
+
+
+def test_coarse_input_preserves_integral():
+    torch = pytest.importorskip("torch")
+    from paper_2601_21407_amd import surrogate as SG
+    I = torch.randn(40, 7, dtype=torch.float64)
+    for r in (2, 4, 10):
+        c = SG.coarse_input(I, r)
+        assert c.shape == (40 // r, 7)
+        assert torch.allclose(c.sum(0) * r, I.sum(0))
+
+
+def test_alg_op_count_classic():
+    import bench
+    fl, tr, it, m64 = bench.alg_ops_per_update(W.classic_hh(), noise=False)
+    # rates: 2 linoid (5+2), 3 exp (3+1), 1 sigmoid (4+2); 3 AB gates (5+2);
+    # channels: Na (2+1+4), K (2+4), leak 4; V 3, spike 2
+    assert fl == 2 * 5 + 3 * 3 + 4 + 3 * 5 + 7 + 6 + 4 + 5
+    assert tr == 2 * 2 + 3 + 2 + 3 * 2
+    assert it == 0 and m64 == 0
+
+
+def test_jitter_subset_reproduces_population():
+    m = W.custom_channels()
+    full = W.jitter_coef(m, 70000, seed=3)
+    part = W.jitter_coef(m, 10, seed=3, first=65530)
+    assert np.array_equal(part, full[:, 65530:65540])
+    nom = W.coef_table(m)
+    ratio = full[nom != 0] / nom[nom != 0][:, None]
+    assert ratio.min() >= 0.9 - 1e-6 and ratio.max() < 1.1 + 1e-6
+
+
+def test_layer_inputs_shape_and_rate():
+    S, lab = W.layer_inputs(B=16, T=50)
+    assert S.shape == (50, 16, 700) and lab.shape == (16,)
+    assert 0.01 < S.mean() < 0.03
+
+
+def test_bf16_round():
+    x = np.array([1.0, 1.00390625, 1.0039063, 3.14159265, -2.5e-3], np.float32)
+    r = W.bf16_round(x)
+    import torch
+    ref = torch.tensor(x).to(torch.bfloat16).float().numpy()
+    assert np.array_equal(r, ref)
+
+
+def test_horizon_helper_on_oracle():
+    from oracle import oracle as O
+    from tests.gpu_util import match_to_horizon, spike_horizons
+    m = W.classic_hh(dt=0.02)
+    n, T = 6, 1500
+    I = np.array([3.0, 6.5, 8.0, 10.0, 15.0, 6.28])
+    st0 = O.init_state(m, np.full(n, -65.0))
+    h, steps = spike_horizons(O, m, st0, T, np.arange(n), {"i_const": I})
+    for j in range(n):
+        assert 0 <= h[j] <= len(steps[j])
+        assert match_to_horizon(steps[j], steps[j], h[j])
+        if len(steps[j]) > h[j] or h[j] > 0:
+            # dropping a well-conditioned spike fails
+            if h[j] > 0:
+                assert not match_to_horizon(steps[j][1:], steps[j], h[j])
