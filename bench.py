@@ -259,9 +259,25 @@ def bench_network(T=10000):
     _sync()
     sc_ms = a.elapsed_time(b) / reps
     nnz = int(csr[1].shape[0])
+    # barrier floor: the same grid (blocks of 512) running only the per-step
+    # grid barrier, then barrier + accumulator reads
+    blocks = (n + 511) // 512
+    floor = {}
+    work = None
+    for mode, name in ((0, "barrier_us"), (1, "barrier_plus_acc_us")):
+        work = hh.probe_barrier(100, blocks, mode, work)
+        _sync()
+        a.record()
+        work = hh.probe_barrier(T, blocks, mode, work)
+        b.record()
+        _sync()
+        floor[name] = a.elapsed_time(b) / T * 1e3
+    kern_us = e0.elapsed_time(e1) / T * 1e3
+    floor["step_over_floor"] = kern_us / floor["barrier_plus_acc_us"]
     return {
         "n": n, "synapses": nnz, "T": T, "dt_ms": 0.1, "wall_s": wall,
         "kernel_ms": e0.elapsed_time(e1), "us_per_step": wall / T * 1e6,
+        "kernel_us_per_step": kern_us, "barrier_floor": floor,
         "updates_per_s": n * T / wall, "mean_rate_hz": n_spk / n / (T * 1e-4),
         "synaptic_events": n_spk * 2630,
         "scatter_full": {"events": nnz, "ms": sc_ms, "events_per_s": nnz / (sc_ms / 1e3),
@@ -285,7 +301,8 @@ def bench_layer(reps=5, ckpt_every=50):
     Win, cm0, Wout, bout = W.layer_params()
     dev = "cuda"
     S = torch.tensor(S8.reshape(T * B, n_in), device=dev).to(torch.bfloat16)
-    win32 = torch.tensor(Win, device=dev)
+    # the projection keeps the weights transposed: [H][n_in], K contiguous
+    win32 = torch.tensor(np.ascontiguousarray(Win.T), device=dev)
     win16 = win32.to(torch.bfloat16)
     cm = torch.tensor(cm0, device=dev)
     wout = torch.tensor(Wout, device=dev)
@@ -423,6 +440,16 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
     rows.append(dict(method="surrogate k=10", ms=ms_sur, speedup=ms_ref / ms_sur,
                      surrogate_call_frac=float(st[0] / max(st[0] + st[1], 1)),
                      failed_checks=int(st[2]), **e))
+    # the same deployment with the periodic check every 20 calls
+    ms_s20, (_, _, bits_s20, st20) = kernel_time(lambda: SG.deploy(packed, n, T, i_dense=I,
+                                                                   check_every=20))
+    st20 = st20.cpu().numpy()
+    e20 = SG.spike_time_error(ref_np, bits_s20.cpu().numpy(), n, 0.025, 0.025,
+                              max_neurons=eval_neurons)
+    rows.append(dict(method="surrogate k=10, check every 20 calls", ms=ms_s20, speedup=ms_ref / ms_s20,
+                     surrogate_call_frac=float(st20[0] / max(st20[0] + st20[1], 1)),
+                     failed_checks=int(st20[2]), **e20))
+    del bits_s20
     ms_noise, _ = kernel_time(lambda: SG.deploy(packed, n, T, noise=(5.0, 3.0, 2), spikes=False))
     ms_plain_noise, _ = kernel_time(lambda: SG.plain_run(n, T, noise=(5.0, 3.0, 2), spikes=False))
     rows.append(dict(method="plain dt=0.025 (reference)", ms=ms_ref, speedup=1.0,
@@ -437,7 +464,7 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
         rows.append(dict(method="plain dt=%g %s" % (dt, vm), ms=msc, speedup=ms_ref / msc, **e))
         del Ic
     sur = rows[0]
-    dominated = [r["method"] for r in rows[2:]
+    dominated = [r["method"] for r in rows[3:]
                  if r["speedup"] >= sur["speedup"] and r["mean_abs_ms"] <= sur["mean_abs_ms"]
                  and r["unmatched_frac"] <= sur["unmatched_frac"]]
     res.update({"n": n, "T": T, "eval_neurons": eval_neurons, "pareto": rows,
@@ -455,24 +482,37 @@ def probe_rates():
     from paper_2601_21407_amd import hh
     out = torch.empty(1 << 20, device="cuda")
     blocks, iters = 256 * 32, 2000
-    res = {}
-    for op in ("fma", "exp2", "rcp", "sqrt", "sin", "mul64", "mix"):
+    res, ms_of = {}, {}
+    for op in ("fma", "exp2", "rcp", "sqrt", "sin", "mul64", "mix", "pkfma16", "exp16", "mfma16",
+               "mfma16_valu"):
+        it = iters // 8 if op.startswith("mfma") else iters
         hh.probe_issue(op, 10, blocks, out)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         _sync()
         a.record()
-        hh.probe_issue(op, iters, blocks, out)
+        hh.probe_issue(op, it, blocks, out)
         b.record()
         _sync()
         ms = a.elapsed_time(b)
-        ops = blocks * 256 * 8 * iters * (2 if op == "mix" else 1)
+        ms_of[op] = ms
+        if op.startswith("mfma"):
+            res[op + "_tflops"] = blocks * 4 * it * 2 * 32768 / (ms / 1e3) / 1e12
+            continue
+        ops = blocks * 256 * 8 * it * (2 if op in ("mix", "pkfma16") else 1)
         res[op] = ops / (ms / 1e3) / 1e12  # T lane-ops/s
-    res["ratio_vs_fma"] = {k: res["fma"] / v for k, v in res.items() if k != "fma"}
+    res["ratio_vs_fma"] = {k: res["fma"] / res[k] for k in
+                           ("exp2", "rcp", "sqrt", "sin", "mul64", "mix", "pkfma16", "exp16")}
     # an exp + fma pair costs 1/fma + 1/exp2 when the two share one issue
     # port, max(...) when they overlap
     res["mix_pair_ns_per_Tpair"] = 2.0 / res["mix"]
     res["mix_if_serial"] = 1.0 / res["fma"] + 1.0 / res["exp2"]
     res["mix_if_overlap"] = max(1.0 / res["fma"], 1.0 / res["exp2"])
+    # matrix products with 32 FMAs per lane interleaved: serial issue would
+    # take the sum of the two parts' times, full overlap their maximum
+    it = iters // 8
+    t_valu = blocks * 256 * 32 * it / (res["fma"] * 1e12) * 1e3
+    res["mfma_valu_ms"] = {"mfma": ms_of["mfma16"], "valu_alone": t_valu,
+                           "together": ms_of["mfma16_valu"]}
     return res
 
 

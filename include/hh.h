@@ -204,15 +204,18 @@ int32_t hh_check(hh_model* m, int64_t* first_bad, void* stream);
 
 /* Dense input projection of the layer in front of the neurons (the Linear
  * of the Sequential(Linear, HHNode) composition, Fig. 1e), on MFMA:
- *   out[M][N] (float) = A[M][K] (bf16) x W[K][N] (bf16), fp32 accumulate. */
-int32_t hh_proj_forward(const uint16_t* A, const uint16_t* W, float* out, int32_t M, int32_t N,
+ *   out[M][N] (float) = A[M][K] (bf16) x Wt[N][K]^T (bf16), fp32 accumulate.
+ * The weights are stored transposed (Wt [N][K], K contiguous), so that both
+ * operands are K-contiguous.  All arrays row-major, device memory. */
+int32_t hh_proj_forward(const uint16_t* A, const uint16_t* Wt, float* out, int32_t M, int32_t N,
                         int32_t K, void* stream);
-/* Weight gradient dW[K][N] (float, written) = A^T dOut, A [M][K] bf16,
+/* Weight gradient dWt[N][K] (float, written) = dOut^T A, A [M][K] bf16,
  * dOut [M][N] float (split into bf16 high and low parts inside the kernel,
  * so the product keeps ~16 bits of dOut).  The reduction over M is split
  * into partial sums that are added in a fixed order (bit-reproducible);
- * workspace: device scratch of hh_proj_wgrad_workspace(M, N, K) bytes. */
-int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dW, int32_t M, int32_t N,
+ * workspace: device scratch of hh_proj_wgrad_workspace(M, N, K) bytes
+ * (none for M == 0, where dWt is zeroed). */
+int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t M, int32_t N,
                       int32_t K, void* workspace, size_t workspace_bytes, void* stream);
 size_t hh_proj_wgrad_workspace(int32_t M, int32_t N, int32_t K);
 

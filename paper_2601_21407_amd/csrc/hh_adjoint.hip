@@ -129,25 +129,34 @@ __global__ __launch_bounds__(256) void k_bptt(KModel M, BwdArgs A) {
   for (int g = 0; g < NG; ++g) lamP[g] = 0.0f;
   float dc = 0.0f;
   const int nseg = (A.T + A.S - 1) / A.S;
+  // the loss term on the level, per step: dL/dlevel / T
+  const float dlv = A.dlevel ? A.dlevel[i] * A.inv_T : 0.0f;
 
   for (int j = nseg - 1; j >= 0; --j) {
     const int ta = j * A.S, tb = min(ta + A.S, A.T);
     const float* ck = A.ckpt + (int64_t)j * ns * n;
     const int nwin = (tb - ta + kWin - 1) / kWin;
     if (nwin > 1) {
-      // first replay: window start states into the workspace
+      // first replay: window start states into the workspace.  The inputs
+      // of a window are loaded together before its steps (one memory
+      // latency per window, not per step).
       float vh = ck[i], vl = ck[(int64_t)(1 + NG) * n + i], p[ng1<NG>];
 #pragma unroll
       for (int g = 0; g < NG; ++g) p[g] = ck[(int64_t)(1 + g) * n + i];
-      for (int t = ta; t < tb; ++t) {
-        if ((t - ta) % kWin == 0) {
-          float* w = A.sub + (int64_t)((t - ta) / kWin) * ns * n;
-          w[i] = vh;
-          w[(int64_t)(1 + NG) * n + i] = vl;
+      for (int w = 0; w < nwin; ++w) {
+        const int ua = ta + w * kWin;
+        float Icur[kWin];
 #pragma unroll
-          for (int g = 0; g < NG; ++g) w[(int64_t)(1 + g) * n + i] = p[g];
-        }
-        neuron_step<S>(M, L, dtC, vh, vl, p, A.I[(int64_t)t * n + i], 0.0f, 0.0f);
+        for (int k = 0; k < kWin; ++k)
+          Icur[k] = ua + k < tb ? A.I[(int64_t)(ua + k) * n + i] : 0.0f;
+        float* ws = A.sub + (int64_t)w * ns * n;
+        ws[i] = vh;
+        ws[(int64_t)(1 + NG) * n + i] = vl;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) ws[(int64_t)(1 + g) * n + i] = p[g];
+#pragma unroll
+        for (int k = 0; k < kWin; ++k)
+          if (ua + k < tb) neuron_step<S>(M, L, dtC, vh, vl, p, Icur[k], 0.0f, 0.0f);
       }
     }
     for (int q = nwin - 1; q >= 0; --q) {
@@ -177,7 +186,7 @@ __global__ __launch_bounds__(256) void k_bptt(KModel M, BwdArgs A) {
           // direct loss on V_{t+1}
           if (A.dlevel) {
             const float sg = rcp(1.0f + ex2(-A.beta * (Vh[k + 1] - M.v_th) * kLog2e));
-            lamV = fmaf(A.dlevel[i] * A.inv_T, A.beta * sg * (1.0f - sg), lamV);
+            lamV = fmaf(dlv, A.beta * sg * (1.0f - sg), lamV);
           }
           if (A.dV) lamV += A.dV[(int64_t)t * n + i];
           Jac<S> J;

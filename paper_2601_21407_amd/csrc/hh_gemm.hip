@@ -1,19 +1,30 @@
 // hh_gemm.hip -- dense input projection of the differentiable layer on MFMA.
 //
-//   forward   out[M][N] = A[M][K] . W[K][N]          (bf16 x bf16 -> fp32)
-//   wgrad     dW[K][N]  = A^T . dOut                  (dOut fp32 split into
+//   forward   out[M][N] = A[M][K] . Wt[N][K]^T        (bf16 x bf16 -> fp32)
+//   wgrad     dWt[N][K] = dOut^T . A                  (dOut fp32 split into
 //                                                      bf16 hi + lo terms)
 //
-// Tiling: a 256-lane block computes a 128 x 128 output tile; its four
-// wavefronts each own 64 x 64 = 2 x 2 tiles of v_mfma_f32_32x32x16_bf16.
-// The block stages a 128 x 32 slab of each operand through LDS per
-// iteration, laid out so that every lane reads its 8 consecutive K values
-// of an MFMA operand as one 16-byte LDS read.  Rows are padded by 8 bf16
-// to spread LDS banks.
+// The weights are kept as Wt [N][K] (K contiguous), so both operands of the
+// forward product are K-contiguous rows and every lane's MFMA operand -- 8
+// consecutive K values -- is one 16-byte LDS read of a row-major slab, with
+// no transposition anywhere.
 //
 // MFMA 32x32x16 operand layout (lane l): A row l%32, k = 8*(l/32)..+7;
 // B column l%32, same k; accumulator register r holds row
 // 8*(r/4) + 4*(l/32) + r%4, column l%32.
+//
+// Forward: a 512-lane block computes a 256 x 128 output tile; its eight
+// wavefronts each own 64 x 64 = 2 x 2 MFMA tiles.  Slabs of 32 K values of
+// both operands are staged through two LDS buffers: the global loads of slab
+// s+1 are in flight (in registers) while slab s is multiplied, so one barrier
+// per slab suffices.  Rows are padded to 40 bf16 (80 bytes), which makes the
+// 16-byte fragment reads of eight consecutive rows hit all banks once.
+//
+// Weight gradient: the reduction runs over M, the slow dimension of both
+// A and dOut, so each lane gathers 16 consecutive rows of one column
+// (coalesced across lanes) and writes them as M-contiguous LDS rows; the
+// reduction over M is split across blocks and the partials are added in a
+// fixed order.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,7 +35,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 128, BN = 128, BK = 32, LDSK = BK + 8;
+constexpr int FBM = 256, FBN = 128, SK = 32, LDK = SK + 8;
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   // round to nearest even
@@ -38,31 +49,60 @@ __device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
   return *reinterpret_cast<const bf16x8*>(p);
 }
 
-// XCD-aware tile order: consecutive block ids go to different XCDs
-// (round-robin over 8), so the 8 column tiles of one row panel are given to
-// ids that share id % 8 -- they run on the same XCD and share its L2 copy of
-// the row panel.
-__device__ __forceinline__ void tile_of(int b, int tiles_m, int tiles_n, int& tm, int& tn) {
-  if (tiles_n == 8 && tiles_m % 8 == 0) {
-    tn = (b >> 3) & 7;
-    tm = (b & 7) + 8 * (b >> 6);
-  } else {
-    tm = b / tiles_n;
-    tn = b % tiles_n;
-  }
+// XCD-aware tile order: consecutive block ids run on different XCDs (round
+// robin over 8), so block b takes logical tile (b % 8) * per + b / 8: each
+// XCD walks a contiguous range of row panels, and the column tiles of a
+// panel share that XCD's L2 copy of it.  Returns false for the padding ids.
+__device__ __forceinline__ bool tile_of(int b, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int T = tiles_m * tiles_n;
+  const int per = (T + 7) / 8;
+  const int L = (b % 8) * per + b / 8;
+  if (L >= T) return false;
+  tm = L / tiles_n;
+  tn = L % tiles_n;
+  return true;
 }
 
-__global__ __launch_bounds__(256) void k_proj_fwd(const uint16_t* __restrict__ A,
-                                                  const uint16_t* __restrict__ W,
-                                                  float* __restrict__ C, int M, int N, int K) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDSK];  // [m][k]
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDSK];  // [n][k]
-  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+// 8 consecutive bf16 of a row starting at element k of a row of length K
+// (zero past K); `al` = K % 4 == 0 and 8-byte aligned base (uniform).
+__device__ __forceinline__ uint4 load8(const uint16_t* row, int k, int K, bool al) {
+  uint4 v = {0u, 0u, 0u, 0u};
+  if (al && k + 8 <= K) {
+    const uint2 a = *reinterpret_cast<const uint2*>(row + k);
+    const uint2 b = *reinterpret_cast<const uint2*>(row + k + 4);
+    v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+  } else {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (k + e < K) w[e >> 1] |= (uint32_t)row[k + e] << (16 * (e & 1));
+    v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(512, 4) void k_proj_fwd(const uint16_t* __restrict__ A,
+                                                     const uint16_t* __restrict__ Wt,
+                                                     float* __restrict__ C, int M, int N, int K,
+                                                     int al) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][FBM * LDK];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][FBN * LDK];  // [n][k]
+  const int tiles_m = (M + FBM - 1) / FBM, tiles_n = (N + FBN - 1) / FBN;
   int tm, tn;
-  tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
-  const int m0 = tm * BM, n0 = tn * BN;
+  if (!tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn)) return;
+  const int m0 = tm * FBM, n0 = tn * FBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+  const bool aligned = al != 0;
+  // load assignment: A chunks tid and tid + 512 (row = c / 4, k = 8 (c % 4)),
+  // Wt chunk tid
+  const int ar0 = tid >> 2, ar1 = (tid + 512) >> 2, akc = (tid & 3) * 8;
+  const int br = tid >> 2;
+  const uint16_t* arow0 = A + (int64_t)min(m0 + ar0, M - 1) * K;
+  const uint16_t* arow1 = A + (int64_t)min(m0 + ar1, M - 1) * K;
+  const uint16_t* brow = Wt + (int64_t)min(n0 + br, N - 1) * K;
+  const bool av0 = m0 + ar0 < M, av1 = m0 + ar1 < M, bv = n0 + br < N;
+
   f32x16 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -71,105 +111,89 @@ __global__ __launch_bounds__(256) void k_proj_fwd(const uint16_t* __restrict__ A
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    // A slab: 128 rows x 32 k, as 4-element pieces (rows are only 8-byte aligned)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int piece = tid + 256 * q;  // 0..1023
-      const int r = piece >> 3, kc = (piece & 7) * 4;
-      const int gm = m0 + r, gk = k0 + kc;
-      uint16_t v[4] = {0, 0, 0, 0};
-      if (gm < M) {
-        const uint16_t* src = A + (int64_t)gm * K + gk;
-        if (gk + 3 < K && ((((uintptr_t)src) & 7u) == 0)) {
-          const uint2 w2 = *reinterpret_cast<const uint2*>(src);
-          v[0] = (uint16_t)w2.x; v[1] = (uint16_t)(w2.x >> 16);
-          v[2] = (uint16_t)w2.y; v[3] = (uint16_t)(w2.y >> 16);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (gk + e < K) v[e] = src[e];
-        }
-      }
-      uint16_t* dst = As + r * LDSK + kc;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) dst[e] = v[e];
+  const uint4 zero = {0u, 0u, 0u, 0u};
+  uint4 ra0 = av0 ? load8(arow0, akc, K, aligned) : zero;
+  uint4 ra1 = av1 ? load8(arow1, akc, K, aligned) : zero;
+  uint4 rb = bv ? load8(brow, akc, K, aligned) : zero;
+  *reinterpret_cast<uint4*>(&As[0][ar0 * LDK + akc]) = ra0;
+  *reinterpret_cast<uint4*>(&As[0][ar1 * LDK + akc]) = ra1;
+  *reinterpret_cast<uint4*>(&Bs[0][br * LDK + akc]) = rb;
+  __syncthreads();
+  const int ns = (K + SK - 1) / SK;
+  for (int s = 0; s < ns; ++s) {
+    const int buf = s & 1;
+    const bool more = s + 1 < ns;
+    if (more) {  // next slab's loads in flight during this slab's products
+      const int k1 = (s + 1) * SK + akc;
+      ra0 = av0 ? load8(arow0, k1, K, aligned) : zero;
+      ra1 = av1 ? load8(arow1, k1, K, aligned) : zero;
+      rb = bv ? load8(brow, k1, K, aligned) : zero;
     }
-    // W slab: 32 k rows x 128 n, stored transposed
+    const uint16_t* as = As[buf];
+    const uint16_t* bs = Bs[buf];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int piece = tid + 256 * q;  // 0..511
-      const int kr = piece >> 4, nc = (piece & 15) * 8;
-      const int gk = k0 + kr, gn = n0 + nc;
-      uint16_t v[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = 0;
-      if (gk < K) {
-        const uint16_t* src = W + (int64_t)gk * N + gn;
-        if (gn + 7 < N && ((((uintptr_t)src) & 15u) == 0)) {
-          const uint4 w4 = *reinterpret_cast<const uint4*>(src);
-          const uint32_t ww[4] = {w4.x, w4.y, w4.z, w4.w};
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            v[2 * e] = (uint16_t)ww[e];
-            v[2 * e + 1] = (uint16_t)(ww[e] >> 16);
-          }
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (gn + e < N) v[e] = src[e];
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) Bs[(nc + e) * LDSK + kr] = v[e];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
+    for (int kk = 0; kk < SK; kk += 16) {
       const int kl = kk + 8 * (lane >> 5);
       bf16x8 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = lds8(As + (wm * 64 + i * 32 + (lane & 31)) * LDSK + kl);
+      for (int i = 0; i < 2; ++i) a[i] = lds8(as + (wm * 64 + i * 32 + (lane & 31)) * LDK + kl);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = lds8(Bs + (wn * 64 + j * 32 + (lane & 31)) * LDSK + kl);
+      for (int j = 0; j < 2; ++j) b[j] = lds8(bs + (wn * 64 + j * 32 + (lane & 31)) * LDK + kl);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (more) {
+      // the other buffer was last read in slab s-1, before the barrier below
+      *reinterpret_cast<uint4*>(&As[buf ^ 1][ar0 * LDK + akc]) = ra0;
+      *reinterpret_cast<uint4*>(&As[buf ^ 1][ar1 * LDK + akc]) = ra1;
+      *reinterpret_cast<uint4*>(&Bs[buf ^ 1][br * LDK + akc]) = rb;
+    }
     __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 64 + j * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int col = n0 + wn * 64 + j * 32 + (lane & 31);
         if (row < M && col < N) C[(int64_t)row * N + col] = acc[i][j][r];
       }
+    }
 }
 
 // Weight gradient, one split of the reduction over M per blockIdx.y.
-// Output tile: 128 (k) x 128 (n).  Per iteration 32 rows of M are staged:
-// A^T slab [k][m] and dOut^T slabs [n][m] as bf16 hi and lo parts.
-__global__ __launch_bounds__(256) void k_proj_wgrad(const uint16_t* __restrict__ A,
-                                                    const float* __restrict__ D,
-                                                    float* __restrict__ part, int M, int N, int K,
-                                                    int rows_per_split) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDSK];   // [k][m]
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[BN * LDSK];   // [n][m]
-  __shared__ __attribute__((aligned(16))) uint16_t Bl[BN * LDSK];   // [n][m]
-  const int tiles_k = (K + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
-  const int tk = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
-  (void)tiles_k;
-  const int k0 = tk * BM, n0 = tn * BN;
+// Output tile: 128 (n) x 128 (k) of dWt; four wavefronts of 64 x 64.  Per
+// slab 32 rows of M are staged as dOut^T [n][m] (bf16 hi and lo parts) and
+// A^T [k][m]: lane t gathers rows m..m+15 of column t % 128 (each load
+// instruction reads consecutive columns of one row) and writes them as two
+// 16-byte LDS stores.
+constexpr int GBN = 128, GBK = 128;
+
+__global__ __launch_bounds__(256, 2) void k_proj_wgrad(const uint16_t* __restrict__ A,
+                                                       const float* __restrict__ D,
+                                                       float* __restrict__ part, int M, int N,
+                                                       int K, int rows_per_split) {
+  __shared__ __attribute__((aligned(16))) uint16_t Dh[2][GBN * LDK];  // [n][m]
+  __shared__ __attribute__((aligned(16))) uint16_t Dl[2][GBN * LDK];  // [n][m]
+  __shared__ __attribute__((aligned(16))) uint16_t At[2][GBK * LDK];  // [k][m]
+  const int tiles_n = (N + GBN - 1) / GBN;
+  const int tn = blockIdx.x % tiles_n, tk = blockIdx.x / tiles_n;
+  const int n0 = tn * GBN, k0 = tk * GBK;
   const int mbeg = blockIdx.y * rows_per_split;
   const int mend = min(M, mbeg + rows_per_split);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wn = wave >> 1, wk = wave & 1;
+  // gather assignment: column c = tid % 128, rows g*16 .. g*16+15 of the slab
+  const int c = tid & 127, g = tid >> 7;
+  const bool dv = n0 + c < N, av = k0 + c < K;
+  const float* dcol = D + min(n0 + c, N - 1);
+  const uint16_t* acol = A + min(k0 + c, K - 1);
+
   f32x16 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -178,87 +202,90 @@ __global__ __launch_bounds__(256) void k_proj_wgrad(const uint16_t* __restrict__
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  for (int ms = mbeg; ms < mend; ms += BK) {
-    // A slab: 32 m rows x 128 k columns -> As[k][m]
+  float dreg[16];
+  uint16_t areg[16];
+  auto gather = [&](int ms) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int piece = tid + 256 * q;  // 0..1023: 32 rows x 32 pieces of 4
-      const int mr = piece >> 5, kc = (piece & 31) * 4;
-      const int gm = ms + mr, gk = k0 + kc;
-      uint16_t v[4] = {0, 0, 0, 0};
-      if (gm < mend) {
-        const uint16_t* src = A + (int64_t)gm * K + gk;
-        if (gk + 3 < K && ((((uintptr_t)src) & 7u) == 0)) {
-          const uint2 w2 = *reinterpret_cast<const uint2*>(src);
-          v[0] = (uint16_t)w2.x; v[1] = (uint16_t)(w2.x >> 16);
-          v[2] = (uint16_t)w2.y; v[3] = (uint16_t)(w2.y >> 16);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (gk + e < K) v[e] = src[e];
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) As[(kc + e) * LDSK + mr] = v[e];
+    for (int e = 0; e < 16; ++e) {
+      const int m = ms + g * 16 + e;
+      const bool ok = m < mend;
+      dreg[e] = (ok && dv) ? dcol[(int64_t)m * N] : 0.0f;
+      areg[e] = (ok && av) ? acol[(int64_t)m * K] : (uint16_t)0;
     }
-    // dOut slab: 32 m rows x 128 n columns (fp32) -> Bh/Bl[n][m]
+  };
+  auto stash = [&](int buf) {
+    uint32_t h[8], l[8], a[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int piece = tid + 256 * q;  // 32 rows x 32 pieces of 4 floats
-      const int mr = piece >> 5, nc = (piece & 31) * 4;
-      const int gm = ms + mr, gn = n0 + nc;
-      float v[4] = {0.f, 0.f, 0.f, 0.f};
-      if (gm < mend) {
-        const float* src = D + (int64_t)gm * N + gn;
-        if (gn + 3 < N && ((((uintptr_t)src) & 15u) == 0)) {
-          const float4 f4 = *reinterpret_cast<const float4*>(src);
-          v[0] = f4.x; v[1] = f4.y; v[2] = f4.z; v[3] = f4.w;
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (gn + e < N) v[e] = src[e];
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint16_t hi = f2bf(v[e]);
-        Bh[(nc + e) * LDSK + mr] = hi;
-        Bl[(nc + e) * LDSK + mr] = f2bf(v[e] - bf2f(hi));
-      }
+    for (int e = 0; e < 8; ++e) {
+      const uint16_t h0 = f2bf(dreg[2 * e]), h1 = f2bf(dreg[2 * e + 1]);
+      const uint16_t l0 = f2bf(dreg[2 * e] - bf2f(h0)), l1 = f2bf(dreg[2 * e + 1] - bf2f(h1));
+      h[e] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      l[e] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+      a[e] = (uint32_t)areg[2 * e] | ((uint32_t)areg[2 * e + 1] << 16);
     }
-    __syncthreads();
+    uint4* ph = reinterpret_cast<uint4*>(&Dh[buf][c * LDK + g * 16]);
+    uint4* pl = reinterpret_cast<uint4*>(&Dl[buf][c * LDK + g * 16]);
+    uint4* pa = reinterpret_cast<uint4*>(&At[buf][c * LDK + g * 16]);
+    ph[0] = make_uint4(h[0], h[1], h[2], h[3]);
+    ph[1] = make_uint4(h[4], h[5], h[6], h[7]);
+    pl[0] = make_uint4(l[0], l[1], l[2], l[3]);
+    pl[1] = make_uint4(l[4], l[5], l[6], l[7]);
+    pa[0] = make_uint4(a[0], a[1], a[2], a[3]);
+    pa[1] = make_uint4(a[4], a[5], a[6], a[7]);
+  };
+
+  gather(mbeg);
+  stash(0);
+  __syncthreads();
+  const int ns = (mend - mbeg + SK - 1) / SK;
+  for (int s = 0; s < ns; ++s) {
+    const int buf = s & 1;
+    const bool more = s + 1 < ns;
+    if (more) gather(mbeg + (s + 1) * SK);
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
-      const int kl = kk + 8 * (lane >> 5);
-      bf16x8 a[2], bh[2], bl[2];
+    for (int kk = 0; kk < SK; kk += 16) {
+      const int ml = kk + 8 * (lane >> 5);
+      bf16x8 ah[2], al[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = lds8(As + (wm * 64 + i * 32 + (lane & 31)) * LDSK + kl);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        bh[j] = lds8(Bh + (wn * 64 + j * 32 + (lane & 31)) * LDSK + kl);
-        bl[j] = lds8(Bl + (wn * 64 + j * 32 + (lane & 31)) * LDSK + kl);
+      for (int i = 0; i < 2; ++i) {
+        ah[i] = lds8(&Dh[buf][(wn * 64 + i * 32 + (lane & 31)) * LDK + ml]);
+        al[i] = lds8(&Dl[buf][(wn * 64 + i * 32 + (lane & 31)) * LDK + ml]);
       }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = lds8(&At[buf][(wk * 64 + j * 32 + (lane & 31)) * LDK + ml]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], b[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], b[j], acc[i][j], 0, 0, 0);
         }
     }
+    if (more) stash(buf ^ 1);
     __syncthreads();
   }
-  float* P = part + (int64_t)blockIdx.y * K * N;
+  float* P = part + (int64_t)blockIdx.y * N * K;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+      const int col = k0 + wk * 64 + j * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = k0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int col = n0 + wn * 64 + j * 32 + (lane & 31);
-        if (row < K && col < N) P[(int64_t)row * N + col] = acc[i][j][r];
+        const int row = n0 + wn * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row < N && col < K) P[(int64_t)row * K + col] = acc[i][j][r];
       }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, int64_t count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0.0f;
+}
+
+hipError_t fill_zero(float* p, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count);
+  return hipGetLastError();
 }
 
 // Sum of the split partials in a fixed order (deterministic).
@@ -273,7 +300,7 @@ __global__ __launch_bounds__(256) void k_sum_splits(const float* __restrict__ pa
 }
 
 int wgrad_splits(int M) {
-  // enough blocks to fill the chip; each split reduces at least 256 rows
+  // enough blocks to fill the chip; each split reduces at least 2048 rows
   int s = (M + 2047) / 2048;
   if (s > 64) s = 64;
   return s < 1 ? 1 : s;
@@ -283,13 +310,17 @@ int wgrad_splits(int M) {
 
 extern "C" {
 
-int32_t hh_proj_forward(const uint16_t* A, const uint16_t* W, float* out, int32_t M, int32_t N,
+int32_t hh_proj_forward(const uint16_t* A, const uint16_t* Wt, float* out, int32_t M, int32_t N,
                         int32_t K, void* stream) {
-  if (!A || !W || !out) return HH_E_INVALID;
   if (M < 0 || N < 0 || K < 0) return HH_E_SHAPE;
   if (M == 0 || N == 0) return HH_OK;
-  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  hipLaunchKernelGGL(k_proj_fwd, dim3(tiles), dim3(256), 0, (hipStream_t)stream, A, W, out, M, N, K);
+  if (!out || (K > 0 && (!A || !Wt))) return HH_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  if (K == 0) return fill_zero(out, (int64_t)M * N, s) == hipSuccess ? HH_OK : HH_E_HIP;
+  const int tiles = ((M + FBM - 1) / FBM) * ((N + FBN - 1) / FBN);
+  const int blocks = (tiles + 7) / 8 * 8;
+  const int al = (K % 4 == 0) && ((uintptr_t)A % 8 == 0) && ((uintptr_t)Wt % 8 == 0);
+  hipLaunchKernelGGL(k_proj_fwd, dim3(blocks), dim3(512), 0, s, A, Wt, out, M, N, K, al);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 
@@ -298,24 +329,25 @@ size_t hh_proj_wgrad_workspace(int32_t M, int32_t N, int32_t K) {
   return (size_t)wgrad_splits(M) * (size_t)K * (size_t)N * sizeof(float);
 }
 
-int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dW, int32_t M, int32_t N,
+int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t M, int32_t N,
                       int32_t K, void* workspace, size_t workspace_bytes, void* stream) {
-  if (!A || !dOut || !dW) return HH_E_INVALID;
   if (M < 0 || N < 0 || K < 0) return HH_E_SHAPE;
   if (N == 0 || K == 0) return HH_OK;
-  const size_t need = hh_proj_wgrad_workspace(M > 0 ? M : 1, N, K);
-  if (!workspace || workspace_bytes < need) return HH_E_SHAPE;
-  const int splits = wgrad_splits(M > 0 ? M : 1);
-  int rows = (M + splits - 1) / splits;
-  rows = (rows + BK - 1) / BK * BK;
-  const int tiles = ((K + BM - 1) / BM) * ((N + BN - 1) / BN);
+  if (!dWt || (M > 0 && (!A || !dOut))) return HH_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
+  if (M == 0) return fill_zero(dWt, (int64_t)N * K, s) == hipSuccess ? HH_OK : HH_E_HIP;
+  const size_t need = hh_proj_wgrad_workspace(M, N, K);
+  if (!workspace || workspace_bytes < need) return HH_E_SHAPE;
+  const int splits = wgrad_splits(M);
+  int rows = (M + splits - 1) / splits;
+  rows = (rows + SK - 1) / SK * SK;
+  const int tiles = ((K + GBK - 1) / GBK) * ((N + GBN - 1) / GBN);
   float* part = (float*)workspace;
   hipLaunchKernelGGL(k_proj_wgrad, dim3(tiles, splits), dim3(256), 0, s, A, dOut, part, M, N, K,
                      rows);
   const int64_t count = (int64_t)K * N;
-  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, part, dW,
-                     count, splits);
+  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, part,
+                     dWt, count, splits);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 

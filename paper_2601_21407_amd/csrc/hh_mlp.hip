@@ -351,8 +351,12 @@ __device__ __forceinline__ bf16x8 frag_ld(const uint16_t* p) {
   return *reinterpret_cast<const bf16x8*>(p);
 }
 
+// two FP32 values as a bf16 pair, rounded to nearest even (one
+// v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint32_t pack2(float a, float b) {
-  return (uint32_t)bf16bits(a) | ((uint32_t)bf16bits(b) << 16);
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  const bf2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
 }
 
 __device__ __forceinline__ bf16x8 u4_to_frag(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
@@ -363,6 +367,50 @@ __device__ __forceinline__ bf16x8 u4_to_frag(uint32_t a, uint32_t b, uint32_t c,
 
 // SiLU of an accumulator value (v_exp_f32 + v_rcp_f32)
 __device__ __forceinline__ float silu_fast(float a) { return a * rcp(1.0f + ex2(-a * kLog2e)); }
+
+// SiLU of accumulator registers r0..r0+7 as a bf16 B-operand fragment
+__device__ __forceinline__ bf16x8 act_frag(const f32x16& acc, int r0) {
+  return u4_to_frag(pack2(silu_fast(acc[r0 + 0]), silu_fast(acc[r0 + 1])),
+                    pack2(silu_fast(acc[r0 + 2]), silu_fast(acc[r0 + 3])),
+                    pack2(silu_fast(acc[r0 + 4]), silu_fast(acc[r0 + 5])),
+                    pack2(silu_fast(acc[r0 + 6]), silu_fast(acc[r0 + 7])));
+}
+
+// Layers 1-3 for the 32-sample tile whose layer-1 B operand is bx; returns
+// the first four accumulator registers of the output tile (outputs 0-3 of
+// sample l%32 in the lower half-wave, outputs 4-5 in r = 0, 1 of the upper).
+__device__ __forceinline__ void mlp_tile(const MlpPacked& W, bf16x8 bx, float (&y)[4]) {
+  const int l = threadIdx.x & 63;
+  const int hf = l >> 5;
+  const f32x16 z = {};
+  const f32x16 h1a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w1[0][l][0]), bx, z, 0, 0, 0);
+  const f32x16 h1b = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w1[1][l][0]), bx, z, 0, 0, 0);
+  const bf16x8 b10 = act_frag(h1a, 0), b11 = act_frag(h1a, 8);
+  const bf16x8 b12 = act_frag(h1b, 0), b13 = act_frag(h1b, 8);
+  // layer 2, one 32-row output tile at a time, each activated at once
+  bf16x8 b2[4];
+#pragma unroll
+  for (int ot = 0; ot < 2; ++ot) {
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = W.b2[ot][hf][r];
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w2[ot][0][l][0]), b10, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w2[ot][1][l][0]), b11, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w2[ot][2][l][0]), b12, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w2[ot][3][l][0]), b13, acc, 0, 0, 0);
+    b2[2 * ot] = act_frag(acc, 0);
+    b2[2 * ot + 1] = act_frag(acc, 8);
+  }
+  // layer 3: outputs 0..5 in the first rows of a 32-row tile
+  f32x16 acc = {};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = W.b3[hf][r];
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb)
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w3[kb][l][0]), b2[kb], acc, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) y[r] = acc[r];
+}
 
 // x[7] = raw inputs (state and mean current) of this lane's sample;
 // returns dy[6] = de-normalized outputs.
@@ -392,82 +440,21 @@ __device__ __forceinline__ void mlp_infer_wave(const MlpPacked& W, const float (
   bx[0] = hf ? u4_to_frag(r0, r1, r2, r3) : u4_to_frag(hi0, hi1, hi2, hi3);
   bx[1] = hf ? u4_to_frag(lo0, lo1, lo2, lo3) : u4_to_frag(r0, r1, r2, r3);
 
-  // layer 1: [64 hidden] x [32 samples] per sample tile c
-  f32x16 h1[2][2];  // [row tile][sample tile]
-#pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
-    const bf16x8 a = frag_ld(&W.w1[rt][l][0]);
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      f32x16 z = {};
-      h1[rt][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bx[c], z, 0, 0, 0);
-    }
-  }
-  // SiLU and repack as B operands of layer 2
-  bf16x8 b1[4][2];  // [k-block][sample tile]
-#pragma unroll
-  for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const f32x16& acc = h1[kb >> 1][c];
-      const int r0i = 8 * (kb & 1);
-      b1[kb][c] = u4_to_frag(pack2(silu_fast(acc[r0i + 0]), silu_fast(acc[r0i + 1])),
-                             pack2(silu_fast(acc[r0i + 2]), silu_fast(acc[r0i + 3])),
-                             pack2(silu_fast(acc[r0i + 4]), silu_fast(acc[r0i + 5])),
-                             pack2(silu_fast(acc[r0i + 6]), silu_fast(acc[r0i + 7])));
-    }
-  // layer 2
-  f32x16 h2[2][2];
-#pragma unroll
-  for (int ot = 0; ot < 2; ++ot) {
-    f32x16 bias;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) bias[r] = W.b2[ot][hf][r];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      f32x16 acc = bias;
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb)
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w2[ot][kb][l][0]), b1[kb][c], acc,
-                                                      0, 0, 0);
-      h2[ot][c] = acc;
-    }
-  }
-  bf16x8 b2[4][2];
-#pragma unroll
-  for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const f32x16& acc = h2[kb >> 1][c];
-      const int r0i = 8 * (kb & 1);
-      b2[kb][c] = u4_to_frag(pack2(silu_fast(acc[r0i + 0]), silu_fast(acc[r0i + 1])),
-                             pack2(silu_fast(acc[r0i + 2]), silu_fast(acc[r0i + 3])),
-                             pack2(silu_fast(acc[r0i + 4]), silu_fast(acc[r0i + 5])),
-                             pack2(silu_fast(acc[r0i + 6]), silu_fast(acc[r0i + 7])));
-    }
-  // layer 3: outputs 0..5 of the 32-row tile
-  float y[2][4];
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    f32x16 acc = {};
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = W.b3[hf][r];
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w3[kb][l][0]), b2[kb][c], acc, 0, 0, 0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) y[c][r] = acc[r];
-  }
+  // the two 32-sample tiles one after the other (fewer live registers)
+  float y0[4], y1[4];
+  mlp_tile(W, bx[0], y0);
+  __builtin_amdgcn_sched_barrier(0);  // keep the tiles apart: registers, not ILP, are scarce
+  mlp_tile(W, bx[1], y1);
   // gather the six outputs of sample l into lane l
-  const float t0 = hf ? y[0][0] : y[1][0], t1 = hf ? y[0][1] : y[1][1];
-  const float t2 = y[1][2], t3 = y[1][3];
+  const float t0 = hf ? y0[0] : y1[0], t1 = hf ? y0[1] : y1[1];
+  const float t2 = y1[2], t3 = y1[3];
   const float q0 = __shfl_xor(t0, 32), q1 = __shfl_xor(t1, 32);
   const float q2 = __shfl_xor(t2, 32), q3 = __shfl_xor(t3, 32);
   float o[MLP_OUT];
   if (!hf) {
-    o[0] = y[0][0]; o[1] = y[0][1]; o[2] = y[0][2]; o[3] = y[0][3]; o[4] = q0; o[5] = q1;
+    o[0] = y0[0]; o[1] = y0[1]; o[2] = y0[2]; o[3] = y0[3]; o[4] = q0; o[5] = q1;
   } else {
-    o[0] = q0; o[1] = q1; o[2] = q2; o[3] = q3; o[4] = y[1][0]; o[5] = y[1][1];
+    o[0] = q0; o[1] = q1; o[2] = q2; o[3] = q3; o[4] = y1[0]; o[5] = y1[1];
   }
 #pragma unroll
   for (int k = 0; k < MLP_OUT; ++k) out[k] = fmaf(o[k], W.sig_y[k], W.mu_y[k]);
@@ -565,13 +552,19 @@ int32_t hh_mlp_infer(const void* packed, const float* X, int32_t S, float* Y, vo
 // failed the last periodic check, and for every neuron on check calls (every
 // check_every-th call), where |V_plain - V_surrogate| > check_tol marks the
 // neuron plain until the next check.  Spikes come from plain steps only.
-// Neurons that need the plain integrator are compacted per block through
-// LDS, so the plain work is done by dense wavefronts.
+//
+// A block of SB neurons is the compaction pool: neurons that need the plain
+// integrator on a call are packed into the first slots of an LDS pool, so
+// the plain work runs on dense wavefronts.  Blocks are small (4 wavefronts)
+// and several share a CU, so one block's plain phase overlaps the others'
+// MLP phases.  Pool slots, the pool counter and the spike words are double
+// buffered by call parity: two barriers per call.
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int SB = 512;  // block size = compaction pool
+constexpr int SB = 256;  // block size = compaction pool
 constexpr int KMAX = 16;
+constexpr int SBW = SB / 32;  // spike words per block and step
 
 struct SurArgs {
   float* state;
@@ -591,9 +584,11 @@ struct SurArgs {
   const MlpPacked* W;
 };
 
-// input current of neuron `nid` for the k steps from tc (noise as in hh_step_n)
-__device__ __forceinline__ void call_inputs(const SurArgs& A, uint32_t nid, int64_t col, int64_t tc,
-                                            int call, float (&Iv)[KMAX]) {
+// mean input current of neuron nid over the k steps from tc (dense input:
+// column col of the rows of call `call`); noise as in hh_step_n
+__device__ __forceinline__ float call_mean_input(const SurArgs& A, uint32_t nid, int64_t col,
+                                                 int64_t tc, int call) {
+  float sum = 0.0f;
   if (A.in_mode == IN_NOISE) {
     float z[4] = {0.f, 0.f, 0.f, 0.f};
     if (tc & 3) {
@@ -602,40 +597,38 @@ __device__ __forceinline__ void call_inputs(const SurArgs& A, uint32_t nid, int6
         z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
       }
     }
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j) {
-      if (j < A.k) {
-        const int64_t t = tc + j;
-        if ((t & 3) == 0) normals4(A.seed, nid, (uint64_t)t >> 2, z);
-        Iv[j] = fmaf(A.sigma, z[0], A.mu);
-        z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
-      }
+    for (int j = 0; j < A.k; ++j) {
+      const int64_t t = tc + j;
+      if ((t & 3) == 0) normals4(A.seed, nid, (uint64_t)t >> 2, z);
+      sum += fmaf(A.sigma, z[0], A.mu);
+      z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
     }
   } else if (A.in_mode == IN_DENSE) {
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < A.k) Iv[j] = A.i_dense[((int64_t)call * A.k + j) * A.n + col];
-  } else {
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j) Iv[j] = 0.0f;
+    const float* src = A.i_dense + (int64_t)call * A.k * A.n + col;
+    for (int j = 0; j < A.k; ++j) sum += src[(int64_t)j * A.n];
   }
+  return sum / (float)A.k;
 }
 
 template <class S>
-__global__ __launch_bounds__(SB) void k_surrogate(KModel M, SurArgs A) {
+__global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
   constexpr int NG = S::kNG;
   __shared__ MlpPacked Ws;
-  __shared__ float sv[SB], svl[SB], sp[NG][SB];
-  __shared__ int sid[SB];
-  __shared__ int s_cnt;
+  __shared__ float sv[2][SB], svl[2][SB], sp[2][NG][SB];
+  __shared__ int sid[2][SB];
+  __shared__ uint32_t sbits[KMAX][SBW];
+  __shared__ int s_cnt[2];
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(A.W);
     uint32_t* dst = reinterpret_cast<uint32_t*>(&Ws);
     for (int j = threadIdx.x; j < (int)(sizeof(MlpPacked) / 4); j += SB) dst[j] = src[j];
   }
   const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < KMAX * SBW) sbits[tid / SBW][tid % SBW] = 0u;
+  if (tid < 2) s_cnt[tid] = 0;
   const int64_t n = A.n;
-  const int64_t i = blockIdx.x * (int64_t)SB + tid;
+  const int64_t blk0 = blockIdx.x * (int64_t)SB;
+  const int64_t i = blk0 + tid;
   const bool act = i < n;
   const int64_t ii = act ? i : n - 1;
   LaneRates<NG> L;
@@ -647,27 +640,21 @@ __global__ __launch_bounds__(SB) void k_surrogate(KModel M, SurArgs A) {
   for (int g = 0; g < NG; ++g) p[g] = A.state[(int64_t)(1 + g) * n + ii];
   bool forced = A.flags[ii] != 0;
   uint32_t n_mlp = 0, n_plain = 0, n_fail = 0;
-  const int64_t blk_w0 = (blockIdx.x * (int64_t)SB) >> 5;  // first spike word of the block
-  int myslot = 0;
+  const int64_t blk_w0 = blk0 >> 5;  // first spike word of the block
   __syncthreads();
 
   for (int call = 0; call < A.ncalls; ++call) {
+    const int cb = call & 1;
     const int64_t tc = A.t0 + (int64_t)call * A.k;
-    float Iv[KMAX];
-    call_inputs(A, (uint32_t)ii, ii, tc, call, Iv);
-    float ibar = 0.0f;
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < A.k) ibar += Iv[j];
-    ibar /= (float)A.k;
     const bool check = A.check_every > 0 && ((call + 1) % A.check_every) == 0;
     const bool sub = act && vh <= A.v_fb;  // surrogate admissible before the call
     float pred[MLP_OUT];
     bool cand = false;
-    if (check || __ballot(sub && !forced)) {
-      float x[MLP_IN] = {vh + vl, 0.f, 0.f, 0.f, 0.f, 0.f, ibar};
+    if (__ballot(check ? act : (sub && !forced))) {
+      float x[MLP_IN] = {vh + vl, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int g = 0; g < NG && g < MLP_IN - 2; ++g) x[1 + g] = p[g];
+      x[MLP_IN - 1] = call_mean_input(A, (uint32_t)ii, ii, tc, call);
       float dy[MLP_OUT];
       mlp_infer_wave(Ws, x, dy);
       pred[0] = x[0] + dy[0];
@@ -677,67 +664,79 @@ __global__ __launch_bounds__(SB) void k_surrogate(KModel M, SurArgs A) {
     }
     const bool use_mlp = cand && !forced && !check;
     const bool plain = act && !use_mlp;
-    // the block's spike words for this call start cleared; plain steps set bits
-    if (A.spikes) {
-      for (int e = tid; e < (SB / 32) * A.k; e += SB) {
-        const int j = e / (SB / 32);
-        const int64_t wd = blk_w0 + e % (SB / 32);
-        if (wd < A.words) A.spikes[((int64_t)call * A.k + j) * A.words + wd] = 0u;
-      }
-    }
-    if (tid == 0) s_cnt = 0;
-    __syncthreads();
+    int myslot = 0;
     const uint64_t b = __ballot(plain);
     if (b) {
       int base = 0;
-      if (lane == 0) base = atomicAdd(&s_cnt, __popcll(b));
+      if (lane == 0) base = atomicAdd(&s_cnt[cb], __popcll(b));
       base = __shfl(base, 0);
       if (plain) {
         myslot = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-        sv[myslot] = vh;
-        svl[myslot] = vl;
+        sv[cb][myslot] = vh;
+        svl[cb][myslot] = vl;
 #pragma unroll
-        for (int g = 0; g < NG; ++g) sp[g][myslot] = p[g];
-        sid[myslot] = (int)ii;
+        for (int g = 0; g < NG; ++g) sp[cb][g][myslot] = p[g];
+        sid[cb][myslot] = tid;
       }
     }
-    __syncthreads();
-    // dense plain integration of the compacted neurons
-    const int cnt = s_cnt;
+    __syncthreads();  // pool of this call complete
+    const int cnt = s_cnt[cb];
     if (tid < cnt) {
-      const int nid = sid[tid];
-      float wv = sv[tid], wl = svl[tid], wp[ng1<NG>];
+      // dense plain integration of the compacted neurons
+      const int loc = sid[cb][tid];
+      const int64_t nid = blk0 + loc;
+      float wv = sv[cb][tid], wl = svl[cb][tid], wp[ng1<NG>];
 #pragma unroll
-      for (int g = 0; g < NG; ++g) wp[g] = sp[g][tid];
-      float wI[KMAX];
-      call_inputs(A, (uint32_t)nid, nid, tc, call, wI);
-#pragma unroll
-      for (int j = 0; j < KMAX; ++j) {
-        if (j < A.k) {
-          const float V = wv;
-          neuron_step<S>(M, L, dtC, wv, wl, wp, wI[j], 0.0f, 0.0f);
-          if (A.spikes && V < M.v_th && wv >= M.v_th)
-            atomicOr(&A.spikes[((int64_t)call * A.k + j) * A.words + (nid >> 5)], 1u << (nid & 31));
+      for (int g = 0; g < NG; ++g) wp[g] = sp[cb][g][tid];
+      float z[4] = {0.f, 0.f, 0.f, 0.f};
+      if (A.in_mode == IN_NOISE && (tc & 3)) {
+        normals4(A.seed, (uint32_t)nid, (uint64_t)tc >> 2, z);
+        for (int s = 0; s < (int)(tc & 3); ++s) {
+          z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
         }
       }
-      sv[tid] = wv;
-      svl[tid] = wl;
+      const float* dsrc = A.i_dense ? A.i_dense + (int64_t)call * A.k * A.n + nid : nullptr;
+      for (int j = 0; j < A.k; ++j) {
+        float I = 0.0f;
+        if (A.in_mode == IN_NOISE) {
+          const int64_t t = tc + j;
+          if ((t & 3) == 0) normals4(A.seed, (uint32_t)nid, (uint64_t)t >> 2, z);
+          I = fmaf(A.sigma, z[0], A.mu);
+          z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
+        } else if (A.in_mode == IN_DENSE) {
+          I = dsrc[(int64_t)j * A.n];
+        }
+        const float V = wv;
+        neuron_step<S>(M, L, dtC, wv, wl, wp, I, 0.0f, 0.0f);
+        if (V < M.v_th && wv >= M.v_th) atomicOr(&sbits[j][loc >> 5], 1u << (loc & 31));
+      }
+      sv[cb][tid] = wv;
+      svl[cb][tid] = wl;
 #pragma unroll
-      for (int g = 0; g < NG; ++g) sp[g][tid] = wp[g];
+      for (int g = 0; g < NG; ++g) sp[cb][g][tid] = wp[g];
     }
-    __syncthreads();
+    if (tid == 0) s_cnt[cb ^ 1] = 0;  // counter of the next call (last read before this call)
+    __syncthreads();  // plain results and spike bits complete
+    if (tid < A.k * SBW) {
+      // the block's spike words of this call; cleared for the next call by
+      // the same thread
+      const int j = tid / SBW, w = tid % SBW;
+      const int64_t wd = blk_w0 + w;
+      if (A.spikes && wd < A.words) A.spikes[((int64_t)call * A.k + j) * A.words + wd] = sbits[j][w];
+      sbits[j][w] = 0u;
+    }
     if (plain) {
-      const float vp = sv[myslot];
+      const float vp = sv[cb][myslot];
       if (check && cand) {
         const bool fail = fabsf(vp - pred[0]) > A.check_tol;
         forced = fail;
         n_fail += fail;
       }
       vh = vp;
-      vl = svl[myslot];
+      vl = svl[cb][myslot];
 #pragma unroll
-      for (int g = 0; g < NG; ++g) p[g] = sp[g][myslot];
+      for (int g = 0; g < NG; ++g) p[g] = sp[cb][g][myslot];
       n_plain += 1;
     } else if (use_mlp) {
       vh = pred[0];
@@ -746,7 +745,6 @@ __global__ __launch_bounds__(SB) void k_surrogate(KModel M, SurArgs A) {
       for (int g = 0; g < NG; ++g) p[g] = pred[1 + g];
       n_mlp += 1;
     }
-    __syncthreads();  // slots are reused by the next call
   }
   if (act) {
     A.state[i] = vh;

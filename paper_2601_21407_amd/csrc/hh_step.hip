@@ -34,7 +34,11 @@ __global__ __launch_bounds__(256) void k_init_state(KModel M, float* __restrict_
   state[(int64_t)(1 + NG + 2 * M.has_syn) * n + i] = 0.0f;  // low part of V
 }
 
-template <class S, bool JIT>
+// PF: dense input whose rows are prefetched four steps ahead (the time loop
+// is unrolled by four so the prefetched values stay in registers); used for
+// the built-in channel sets, where a step is short enough that the load
+// latency would otherwise show.
+template <class S, bool JIT, bool PF>
 __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
   constexpr int NG = S::kNG;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -70,47 +74,97 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
   const int lane = threadIdx.x & 63;
   const int64_t w0 = (i - lane) >> 5;  // first spike word of this wavefront
   int lvl = 0;
-
-  for (int k = 0; k < A.nsteps; ++k) {
-    const int64_t t = A.t0 + k;
-    const int kk = A.k_base + k;
-    if (A.ckpt && (kk % A.ckpt_every) == 0 && act) {
-      float* c = A.ckpt + (int64_t)(kk / A.ckpt_every) * (2 + NG + 2 * M.has_syn) * n;
-      c[i] = vh;
-      c[row_lo + i] = vl;
+  if constexpr (PF) {
+    // dense input: the rows of the next four steps are loaded while the
+    // current four are integrated, so no step waits for HBM
+    const float* drow = A.i_dense + ii;
+    float Icur[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int g = 0; g < NG; ++g) c[(int64_t)(1 + g) * n + i] = p[g];
-      if (M.has_syn) {
-        c[(int64_t)(1 + NG) * n + i] = ge;
-        c[(int64_t)(2 + NG) * n + i] = gi;
+    for (int j = 0; j < 4; ++j)
+      if (j < A.nsteps) Icur[j] = drow[(int64_t)j * n];
+    for (int k0 = 0; k0 < A.nsteps; k0 += 4) {
+      float Inext[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (k0 + 4 + j < A.nsteps) Inext[j] = drow[(int64_t)(k0 + 4 + j) * n];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + j;
+        if (k >= A.nsteps) break;
+        const int kk = A.k_base + k;
+        if (A.ckpt && (kk % A.ckpt_every) == 0 && act) {
+          float* c = A.ckpt + (int64_t)(kk / A.ckpt_every) * (2 + NG + 2 * M.has_syn) * n;
+          c[i] = vh;
+          c[row_lo + i] = vl;
+#pragma unroll
+          for (int g = 0; g < NG; ++g) c[(int64_t)(1 + g) * n + i] = p[g];
+          if (M.has_syn) {
+            c[(int64_t)(1 + NG) * n + i] = ge;
+            c[(int64_t)(2 + NG) * n + i] = gi;
+          }
+        }
+        const float V = vh;
+        neuron_step<S>(M, L, dtC, vh, vl, p, Icur[j], ge, gi);
+        const float Vn = vh;
+        const bool spk = act && (V < M.v_th) && (Vn >= M.v_th);
+        if (A.spikes) {
+          const uint64_t b = __ballot(spk);
+          if (lane == 0 && w0 < A.words) {
+            uint32_t* row = A.spikes + (int64_t)k * A.words;
+            row[w0] = (uint32_t)b;
+            if (w0 + 1 < A.words) row[w0 + 1] = (uint32_t)(b >> 32);
+          }
+        }
+        if (A.v_rec && act) A.v_rec[(int64_t)k * n + i] = Vn;
+        lvl += (Vn >= M.v_th);
+        ge *= M.decay_e;
+        gi *= M.decay_i;
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Icur[j] = Inext[j];
     }
-    float I = 0.0f;
-    if (A.in_mode == IN_CONST) {
-      I = A.i_const[ii];
-    } else if (A.in_mode == IN_NOISE) {
-      if ((t & 3) == 0) normals4(A.seed, nid, (uint64_t)t >> 2, z);
-      I = fmaf(A.sigma, z[0], A.mu);
-      z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
-    } else if (A.in_mode == IN_DENSE) {
-      I = A.i_dense[(int64_t)k * n + ii];
-    }
-    const float V = vh;
-    neuron_step<S>(M, L, dtC, vh, vl, p, I, ge, gi);
-    const float Vn = vh;
-    const bool spk = act && (V < M.v_th) && (Vn >= M.v_th);
-    if (A.spikes) {
-      const uint64_t b = __ballot(spk);
-      if (lane == 0 && w0 < A.words) {
-        uint32_t* row = A.spikes + (int64_t)k * A.words;
-        row[w0] = (uint32_t)b;
-        if (w0 + 1 < A.words) row[w0 + 1] = (uint32_t)(b >> 32);
+  } else {
+    for (int k = 0; k < A.nsteps; ++k) {
+      const int64_t t = A.t0 + k;
+      const int kk = A.k_base + k;
+      if (A.ckpt && (kk % A.ckpt_every) == 0 && act) {
+        float* c = A.ckpt + (int64_t)(kk / A.ckpt_every) * (2 + NG + 2 * M.has_syn) * n;
+        c[i] = vh;
+        c[row_lo + i] = vl;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) c[(int64_t)(1 + g) * n + i] = p[g];
+        if (M.has_syn) {
+          c[(int64_t)(1 + NG) * n + i] = ge;
+          c[(int64_t)(2 + NG) * n + i] = gi;
+        }
       }
+      float I = 0.0f;
+      if (A.in_mode == IN_CONST) {
+        I = A.i_const[ii];
+      } else if (A.in_mode == IN_NOISE) {
+        if ((t & 3) == 0) normals4(A.seed, nid, (uint64_t)t >> 2, z);
+        I = fmaf(A.sigma, z[0], A.mu);
+        z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
+      } else if (A.in_mode == IN_DENSE) {
+        I = A.i_dense[(int64_t)k * n + ii];
+      }
+      const float V = vh;
+      neuron_step<S>(M, L, dtC, vh, vl, p, I, ge, gi);
+      const float Vn = vh;
+      const bool spk = act && (V < M.v_th) && (Vn >= M.v_th);
+      if (A.spikes) {
+        const uint64_t b = __ballot(spk);
+        if (lane == 0 && w0 < A.words) {
+          uint32_t* row = A.spikes + (int64_t)k * A.words;
+          row[w0] = (uint32_t)b;
+          if (w0 + 1 < A.words) row[w0 + 1] = (uint32_t)(b >> 32);
+        }
+      }
+      if (A.v_rec && act) A.v_rec[(int64_t)k * n + i] = Vn;
+      lvl += (Vn >= M.v_th);
+      ge *= M.decay_e;
+      gi *= M.decay_i;
     }
-    if (A.v_rec && act) A.v_rec[(int64_t)k * n + i] = Vn;
-    lvl += (Vn >= M.v_th);
-    ge *= M.decay_e;
-    gi *= M.decay_i;
   }
 
   if (!act) return;
@@ -146,10 +200,20 @@ static hipError_t step_spec(const hh_model* m, const StepArgs& a, hipStream_t s)
   // as many compute units as possible (the step is latency bound there).
   const int bs = (a.n < 65536) ? 64 : 256;
   const int64_t nb = (a.n + bs - 1) / bs;
-  if (a.coef)
-    hipLaunchKernelGGL((k_step<S, true>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
-  else
-    hipLaunchKernelGGL((k_step<S, false>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
+  bool pf = false;
+  if constexpr (S::kFixed) pf = a.in_mode == IN_DENSE;
+  if (pf) {
+    if constexpr (S::kFixed) {
+      if (a.coef)
+        hipLaunchKernelGGL((k_step<S, true, true>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
+      else
+        hipLaunchKernelGGL((k_step<S, false, true>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
+    }
+  } else if (a.coef) {
+    hipLaunchKernelGGL((k_step<S, true, false>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
+  } else {
+    hipLaunchKernelGGL((k_step<S, false, false>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
+  }
   return hipGetLastError();
 }
 

@@ -92,6 +92,8 @@ def _load():
         "hh_readout_ce_workspace": ([i32, i32], sz),
         "hh_adam_step": ([vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp], i32),
         "hh_probe_issue": ([i32, i32, i32, vp, i32, vp], i32),
+        "hh_probe_barrier_bytes": ([i32], sz),
+        "hh_probe_barrier": ([i32, i32, i32, vp, sz, vp], i32),
         "hh_mlp_grad": ([vp, vp, vp, i32, i32, vp, vp, vp, sz, vp], i32),
         "hh_mlp_grad_workspace": ([i32], sz),
         "hh_mlp_forward": ([vp, vp, i32, i32, vp, vp], i32),
@@ -257,7 +259,8 @@ class Model:
         return st, fb.value
 
 
-PROBE_OPS = {"fma": 0, "exp2": 1, "rcp": 2, "sqrt": 3, "sin": 4, "mul64": 5, "mix": 6}
+PROBE_OPS = {"fma": 0, "exp2": 1, "rcp": 2, "sqrt": 3, "sin": 4, "mul64": 5, "mix": 6,
+             "pkfma16": 7, "exp16": 8, "mfma16": 9, "mfma16_valu": 10}
 
 
 def probe_issue(op: str, iters: int, blocks: int, out):
@@ -267,27 +270,42 @@ def probe_issue(op: str, iters: int, blocks: int, out):
                            _stream()), "hh_probe_issue")
 
 
-def proj_forward(A_bf16, W_bf16, out):
+def probe_barrier(steps: int, blocks: int, mode: int, work=None):
+    """Launch the barrier-floor probe (include/hh_probe.h); returns the work
+    buffer for reuse."""
+    need = int(lib.hh_probe_barrier_bytes(int(blocks)))
+    if work is None or work.numel() < need:
+        work = torch.empty(need, dtype=torch.uint8, device="cuda")
+    _ok(lib.hh_probe_barrier(int(steps), int(blocks), int(mode), _ptr(work), work.numel(), _stream()),
+        "hh_probe_barrier")
+    return work
+
+
+def proj_forward(A_bf16, Wt_bf16, out):
+    """out [M][N] = A [M][K] . Wt [N][K]^T (bf16 operands, FP32 result)."""
     M, K = A_bf16.shape
-    N = W_bf16.shape[1]
-    assert A_bf16.dtype == torch.bfloat16 and W_bf16.dtype == torch.bfloat16
-    assert out.dtype == torch.float32 and tuple(out.shape) == (M, N) and W_bf16.shape[0] == K
-    _ok(lib.hh_proj_forward(_ptr(A_bf16), _ptr(W_bf16), _ptr(out), M, N, K, _stream()),
+    N = Wt_bf16.shape[0]
+    assert A_bf16.dtype == torch.bfloat16 and Wt_bf16.dtype == torch.bfloat16
+    assert out.dtype == torch.float32 and tuple(out.shape) == (M, N) and Wt_bf16.shape[1] == K
+    assert A_bf16.is_contiguous() and Wt_bf16.is_contiguous() and out.is_contiguous()
+    _ok(lib.hh_proj_forward(_ptr(A_bf16), _ptr(Wt_bf16), _ptr(out), M, N, K, _stream()),
         "hh_proj_forward")
     return out
 
 
-def proj_wgrad(A_bf16, dOut, dW, workspace=None):
+def proj_wgrad(A_bf16, dOut, dWt, workspace=None):
+    """dWt [N][K] = dOut [M][N]^T . A [M][K]."""
     M, K = A_bf16.shape
     N = dOut.shape[1]
     assert A_bf16.dtype == torch.bfloat16 and dOut.dtype == torch.float32
-    assert tuple(dW.shape) == (K, N) and dW.dtype == torch.float32 and dOut.shape[0] == M
+    assert tuple(dWt.shape) == (N, K) and dWt.dtype == torch.float32 and dOut.shape[0] == M
+    assert A_bf16.is_contiguous() and dOut.is_contiguous() and dWt.is_contiguous()
     need = int(lib.hh_proj_wgrad_workspace(M, N, K))
     if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dW.device)
-    _ok(lib.hh_proj_wgrad(_ptr(A_bf16), _ptr(dOut), _ptr(dW), M, N, K, _ptr(workspace),
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dWt.device)
+    _ok(lib.hh_proj_wgrad(_ptr(A_bf16), _ptr(dOut), _ptr(dWt), M, N, K, _ptr(workspace),
                           workspace.numel() * workspace.element_size(), _stream()), "hh_proj_wgrad")
-    return dW
+    return dWt
 
 
 def readout_ce(level, T: int, W, bias, labels, dlevel, dW, db, loss, logits=None, workspace=None):

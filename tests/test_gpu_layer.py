@@ -21,11 +21,13 @@ pytestmark = pytest.mark.gpu
 
 def _bf16_tensor(x):
     import torch
-    return torch.tensor(np.asarray(x, np.float32), device="cuda").to(torch.bfloat16)
+    return torch.tensor(np.ascontiguousarray(x, np.float32), device="cuda").to(torch.bfloat16)
 
 
 @pytest.mark.parametrize("M,N,K,binary", [(300, 200, 70, False), (129, 1025, 33, True),
-                                          (1, 1, 1, False), (640, 256, 700, True)])
+                                          (1, 1, 1, False), (640, 256, 700, True),
+                                          (257, 129, 36, False), (0, 5, 7, False),
+                                          (3, 4, 0, False), (4100, 300, 701, True)])
 def test_projection_forward_and_wgrad_small(M, N, K, binary):
     print_case("proj M=%d N=%d K=%d" % (M, N, K))
     torch = need_gpu()
@@ -35,17 +37,18 @@ def test_projection_forward_and_wgrad_small(M, N, K, binary):
     Wt = rng.standard_normal((K, N))
     A16, W16 = W.bf16_round(A), W.bf16_round(Wt)
     out = torch.empty((M, N), device="cuda")
-    hh.proj_forward(_bf16_tensor(A16), _bf16_tensor(W16), out)
+    # the library takes the weights transposed, Wt [N][K]
+    hh.proj_forward(_bf16_tensor(A16), _bf16_tensor(W16.T), out)
     ref = O.projection(A16, W16)
     scale = np.abs(A16.astype(np.float64)) @ np.abs(W16.astype(np.float64))
     assert np.all(np.abs(out.cpu().numpy() - ref) <= 1e-6 * scale + 1e-30)
     dO = rng.standard_normal((M, N)).astype(np.float32)
-    dW = torch.empty((K, N), device="cuda")
-    hh.proj_wgrad(_bf16_tensor(A16), torch.tensor(dO, device="cuda"), dW)
+    dWt = torch.empty((N, K), device="cuda")
+    hh.proj_wgrad(_bf16_tensor(A16), torch.tensor(dO, device="cuda"), dWt)
     refw = O.projection_weight_grad(A16, dO)
     scw = np.abs(A16.astype(np.float64)).T @ np.abs(dO.astype(np.float64))
     # dOut enters as bf16 hi + lo parts: ~2^-16 relative per term
-    assert np.all(np.abs(dW.cpu().numpy() - refw) <= 2e-5 * scw + 1e-30)
+    assert np.all(np.abs(dWt.cpu().numpy().T - refw) <= 2e-5 * scw + 1e-30)
 
 
 def test_projection_full_size_sampled():
@@ -60,7 +63,7 @@ def test_projection_full_size_sampled():
     W16 = W.bf16_round(Win)
     At = _bf16_tensor(A)
     out = torch.empty((T * B, 1024), device="cuda")
-    hh.proj_forward(At, _bf16_tensor(W16), out)
+    hh.proj_forward(At, _bf16_tensor(W16.T), out)
     rows = np.random.default_rng(0).choice(T * B, 400, replace=False)
     ref = O.projection(A[rows], W16)
     scale = np.abs(A[rows]) @ np.abs(W16.astype(np.float64))
@@ -68,12 +71,12 @@ def test_projection_full_size_sampled():
     assert np.all(np.abs(got - ref) <= 1e-6 * scale + 1e-30)
     # weight gradient of the same shapes, checked on a column block
     dO = np.random.default_rng(1).standard_normal((T * B, 1024)).astype(np.float32) * 1e-3
-    dW = torch.empty((n_in, 1024), device="cuda")
-    hh.proj_wgrad(At, torch.tensor(dO, device="cuda"), dW)
+    dWt = torch.empty((1024, n_in), device="cuda")
+    hh.proj_wgrad(At, torch.tensor(dO, device="cuda"), dWt)
     cols = slice(0, 1024, 37)
     refw = O.projection_weight_grad(A, dO[:, cols])
     scw = np.abs(A).T @ np.abs(dO[:, cols].astype(np.float64))
-    assert np.all(np.abs(dW.cpu().numpy()[:, cols] - refw) <= 2e-5 * scw + 1e-30)
+    assert np.all(np.abs(dWt.cpu().numpy()[cols, :].T - refw) <= 2e-5 * scw + 1e-30)
 
 
 def _bwd_case(n=16, T=20, seed=0, B=1):
