@@ -168,7 +168,6 @@ __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
 template <class S>
 __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   constexpr int NG = S::kNG;
-  __shared__ int s_list[kNetBlock];
   __shared__ int s_pre[kNetBlock];
   __shared__ int64_t s_r0[kNetBlock];
   __shared__ int s_cnt;
@@ -194,6 +193,10 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   const bool driven = A.ext_mask && act && A.ext_mask[i];
   const float scale40 = A.w_scale * kFix;
   unsigned gen = 0;
+  // this neuron's CSR row, read once: a spiking lane hands it to the
+  // block's scatter without another dependent load
+  const int64_t my_r0 = A.row_ptr[ii];
+  const int my_len = (int)(A.row_ptr[ii + 1] - my_r0);
 
   for (int k = 0; k < A.nsteps; ++k) {
     const int64_t t = A.t0 + k;
@@ -220,7 +223,9 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
       if (spk) {
         const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-        s_list[base + rank] = (int)i;
+        // flatten the (row, synapse) pairs of all spiking rows of the block
+        s_r0[base + rank] = my_r0;
+        s_pre[base + rank] = my_len;
       }
     }
     __syncthreads();
@@ -228,14 +233,6 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
     unsigned long long* acc_e = A.acc + (int64_t)(k & 1) * 2 * n;
     unsigned long long* acc_i = acc_e + n;
     if (cnt > 0) {
-      // flatten the (row, synapse) pairs of all spiking rows of the block
-      if ((int)threadIdx.x < cnt) {
-        const int j = s_list[threadIdx.x];
-        const int64_t r0 = A.row_ptr[j];
-        s_r0[threadIdx.x] = r0;
-        s_pre[threadIdx.x] = (int)(A.row_ptr[j + 1] - r0);
-      }
-      __syncthreads();
       block_inclusive_scan(s_pre, cnt);
       const int total = s_pre[cnt - 1];
       scatter_flat(A.col, A.w, scale40, s_r0, s_pre, cnt, total, acc_e, acc_i);
