@@ -309,6 +309,7 @@ def bench_layer(reps=5, ckpt_every=50):
     bo = torch.tensor(bout, device=dev)
     lab = torch.tensor(labels.astype(np.int32), device=dev)
     M = hh.Model(m, H, B, cm=cm)
+    M.set_fusion(T)  # the whole 250-step forward in one launch: state stays in registers
     st = M.new_state()
     I = torch.empty((T * B, H), device=dev)
     nck = (T + ckpt_every - 1) // ckpt_every
@@ -463,10 +464,32 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
                                 max_neurons=eval_neurons)
         rows.append(dict(method="plain dt=%g %s" % (dt, vm), ms=msc, speedup=ms_ref / msc, **e))
         del Ic
-    sur = rows[0]
-    dominated = [r["method"] for r in rows[3:]
-                 if r["speedup"] >= sur["speedup"] and r["mean_abs_ms"] <= sur["mean_abs_ms"]
-                 and r["unmatched_frac"] <= sur["unmatched_frac"]]
+    # the same method with a longer surrogate step (k = 20 steps per call):
+    # the network's cost per call is fixed, the plain steps it replaces double
+    X20, dY20 = SG.generate_transitions(n_traj=5000, T=10000, seed=5, k=20)
+    norm20 = SG.norm_stats(X20, dY20)
+    params20, hist20 = SG.train(X20, dY20, norm20, epochs=epochs, batch=16384, lr=2e-3)
+    del X20, dY20
+    packed20 = hh.mlp_pack(params20, norm20)
+    ms20, (_, _, bits20, st20k) = kernel_time(lambda: SG.deploy(packed20, n, T, i_dense=I, k=20))
+    st20k = st20k.cpu().numpy()
+    e20k = SG.spike_time_error(ref_np, bits20.cpu().numpy(), n, 0.025, 0.025,
+                               max_neurons=eval_neurons)
+    rows.insert(2, dict(method="surrogate k=20 (longer step than configured)", ms=ms20,
+                        speedup=ms_ref / ms20, final_loss=hist20[-1],
+                        surrogate_call_frac=float(st20k[0] / max(st20k[0] + st20k[1], 1)),
+                        failed_checks=int(st20k[2]), **e20k))
+    del bits20
+    # a surrogate row is dominated by a plain row that is at least as fast
+    # and at least as accurate (mean |dt| and unmatched fraction)
+    plain_rows = [r for r in rows if r["method"].startswith("plain")]
+    for r0 in rows:
+        if r0["method"].startswith("surrogate"):
+            r0["dominated_by"] = [r["method"] for r in plain_rows
+                                  if r["speedup"] >= r0["speedup"]
+                                  and r["mean_abs_ms"] <= r0["mean_abs_ms"]
+                                  and r["unmatched_frac"] <= r0["unmatched_frac"]]
+    dominated = rows[0]["dominated_by"]
     res.update({"n": n, "T": T, "eval_neurons": eval_neurons, "pareto": rows,
                 "surrogate_dominated_by": dominated,
                 "noise_input": {"surrogate_ms": ms_noise, "plain_ms": ms_plain_noise,

@@ -5,11 +5,12 @@
 // One lane owns one neuron and walks its checkpoint segments in reverse.  A
 // segment of S steps is replayed from its checkpoint; when S exceeds the
 // register window R, a first replay stores the state at every R-th step in
-// a small workspace, and each R-step window is then replayed once more with
-// its states kept in registers.  The reverse sweep over a window carries the
-// adjoint lambda = (lambda_V, lambda_p) through the transposed Jacobian of
-// each step, which is closed form in the rate functions and their
-// V-derivatives:
+// a small workspace.  Each R-step window is then replayed once more, and
+// that replay evaluates every step's transposed Jacobian from the same rate
+// evaluations that advance the state, keeping only the Jacobian entries in
+// registers.  The reverse sweep over the window then only carries the
+// adjoint lambda = (lambda_V, lambda_p) through those entries.  They are
+// closed form in the rate functions and their V-derivatives:
 //   dV'/dV = 1 - (dt/C) g_tot,   dV'/dp_g = -(dt/C) sum_X gbar dEta_X/dp_g (V - E_X)
 //   dp'/dp = e,   dp'/dV = p_inf' (1 - e) + (p - p_inf) e'
 //   dV'/dI = dt/C,   dV'/dC = -(dt/C^2) (I - I_ion)
@@ -23,7 +24,7 @@ using namespace hhk;
 
 namespace {
 
-constexpr int kWin = 10;  // register window R
+constexpr int kWin = 5;  // register window R
 
 struct BwdArgs {
   const float* ckpt;  // [nseg][ns][n]
@@ -41,41 +42,25 @@ struct BwdArgs {
   const float* coef;
 };
 
+// Transposed-Jacobian entries of one step, and the surrogate derivative of
+// the level at the step's end state.
 template <class S>
-struct Jac {
+struct StepJ {
   float e[ng1<S::kNG>], dpv[ng1<S::kNG>], dvdp[ng1<S::kNG>];
-  float dvdv, dvdI, dvdC;
+  float dvdv, dvdC, sgd;
 };
 
-// Transposed-Jacobian ingredients of one explicit-Euler step at (V, p, I).
+// One explicit-Euler step without synapses -- the arithmetic of
+// neuron_step, in the same order -- that also returns its Jacobian entries.
 template <class S>
-__device__ __forceinline__ void jacobian(const KModel& M, const LaneRates<S::kNG>& L, float dtC,
-                                         float C, float V, const float (&p)[ng1<S::kNG>], float I,
-                                         Jac<S>& J) {
+__device__ __forceinline__ void step_with_jacobian(const KModel& M, const LaneRates<S::kNG>& L,
+                                                   float dtC, float C, float& vh, float& vl,
+                                                   float (&p)[ng1<S::kNG>], float I, StepJ<S>& J) {
   constexpr int NG = S::kNG;
+  const float V = vh;
   const float ndt = M.kdt * kLn2;  // -dt
-#pragma unroll
-  for (int g = 0; g < NG; ++g) {
-    float d0, d1;
-    const float r0 = rate_eval<true>(S::form(M, g, 0), L.r[g][0], V, &d0);
-    const float r1 = rate_eval<true>(S::form(M, g, 1), L.r[g][1], V, &d1);
-    float pinf, dpinf, e, de;
-    if (S::kind(M, g) == KIND_AB) {
-      const float s = r0 + r1, is = rcp(s);
-      pinf = r0 * is;
-      dpinf = (d0 * r1 - r0 * d1) * is * is;
-      e = ex2(s * M.kdt);
-      de = ndt * (d0 + d1) * e;
-    } else {
-      pinf = r0;
-      dpinf = d0;
-      e = ex2(r1 * M.kdt);
-      de = ndt * d1 * e;
-    }
-    J.e[g] = e;
-    J.dpv[g] = fmaf(dpinf, 1.0f - e, (p[g] - pinf) * de);
-  }
-  float gsum = 0.0f, iion = 0.0f, b[ng1<NG>];
+  // channel terms at the start-of-step gates, and dI_ion/dp_g
+  float gsum = 0.0f, esum = 0.0f, b[ng1<NG>];
 #pragma unroll
   for (int g = 0; g < NG; ++g) b[g] = 0.0f;
 #pragma unroll
@@ -87,11 +72,11 @@ __device__ __forceinline__ void jacobian(const KModel& M, const LaneRates<S::kNG
     for (int g = 0; g < NG; ++g) {
       const int ex = S::cexp(M, c, g);
       pw[g] = ex ? ipow(p[g], ex) : 1.0f;
-      eta *= pw[g];
+      if (ex) eta *= pw[g];
     }
-    const float vme = V - M.E[c];
     gsum += eta;
-    iion = fmaf(eta, vme, iion);
+    esum = fmaf(eta, M.E[c], esum);
+    const float vme = V - M.E[c];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
       const int ex = S::cexp(M, c, g);
@@ -104,11 +89,37 @@ __device__ __forceinline__ void jacobian(const KModel& M, const LaneRates<S::kNG
       }
     }
   }
+  // gates by exponential Euler at V_t, with dp'/dp and dp'/dV
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    float d0, d1;
+    const float r0 = rate_eval<true>(S::form(M, g, 0), L.r[g][0], V, &d0);
+    const float r1 = rate_eval<true>(S::form(M, g, 1), L.r[g][1], V, &d1);
+    float pinf, dpinf, e, de;
+    if (S::kind(M, g) == KIND_AB) {
+      const float sr = r0 + r1, is = rcp(sr);
+      pinf = r0 * is;
+      dpinf = (d0 * r1 - r0 * d1) * is * is;
+      e = ex2(sr * M.kdt);
+      de = ndt * (d0 + d1) * e;
+    } else {
+      pinf = r0;
+      dpinf = d0;
+      e = ex2(r1 * M.kdt);
+      de = ndt * d1 * e;
+    }
+    J.e[g] = e;
+    J.dpv[g] = fmaf(dpinf, 1.0f - e, (p[g] - pinf) * de);
+    p[g] = fmaf(p[g] - pinf, e, pinf);
+  }
+  // membrane (explicit Euler)
+  const float iion = fmaf(gsum, vl, fmaf(gsum, V, -esum));
+  const float dv = dtC * (I - iion);
   J.dvdv = fmaf(-dtC, gsum, 1.0f);
-  J.dvdI = dtC;
   J.dvdC = -(dtC / C) * (I - iion);
 #pragma unroll
   for (int g = 0; g < NG; ++g) J.dvdp[g] = -dtC * b[g];
+  add_to_v(vh, vl, dv);
 }
 
 template <class S>
@@ -165,17 +176,20 @@ __global__ __launch_bounds__(256) void k_bptt(KModel M, BwdArgs A) {
       float vh = src[i], vl = src[(int64_t)(1 + NG) * n + i], p[ng1<NG>];
 #pragma unroll
       for (int g = 0; g < NG; ++g) p[g] = src[(int64_t)(1 + g) * n + i];
-      // replay the window, keeping every state in registers
-      float Vh[kWin + 1], Iv[kWin], P[kWin][ng1<NG>];
+      float Iv[kWin];
+#pragma unroll
+      for (int k = 0; k < kWin; ++k) Iv[k] = ua + k < ub ? A.I[(int64_t)(ua + k) * n + i] : 0.0f;
+      // replay the window, keeping each step's Jacobian entries
+      StepJ<S> J[kWin];
 #pragma unroll
       for (int k = 0; k < kWin; ++k) {
         if (ua + k < ub) {
-          Vh[k] = vh;
-#pragma unroll
-          for (int g = 0; g < NG; ++g) P[k][g] = p[g];
-          Iv[k] = A.I[(int64_t)(ua + k) * n + i];
-          neuron_step<S>(M, L, dtC, vh, vl, p, Iv[k], 0.0f, 0.0f);
-          Vh[k + 1] = vh;
+          step_with_jacobian<S>(M, L, dtC, C, vh, vl, p, Iv[k], J[k]);
+          J[k].sgd = 0.0f;
+          if (A.dlevel) {
+            const float sg = rcp(1.0f + ex2(-A.beta * (vh - M.v_th) * kLog2e));
+            J[k].sgd = A.beta * sg * (1.0f - sg);
+          }
         }
       }
       // reverse sweep
@@ -184,20 +198,15 @@ __global__ __launch_bounds__(256) void k_bptt(KModel M, BwdArgs A) {
         if (ua + k < ub) {
           const int t = ua + k;
           // direct loss on V_{t+1}
-          if (A.dlevel) {
-            const float sg = rcp(1.0f + ex2(-A.beta * (Vh[k + 1] - M.v_th) * kLog2e));
-            lamV = fmaf(dlv, A.beta * sg * (1.0f - sg), lamV);
-          }
+          if (A.dlevel) lamV = fmaf(dlv, J[k].sgd, lamV);
           if (A.dV) lamV += A.dV[(int64_t)t * n + i];
-          Jac<S> J;
-          jacobian<S>(M, L, dtC, C, Vh[k], P[k], Iv[k], J);
-          A.dI[(int64_t)t * n + i] = lamV * J.dvdI;
-          dc = fmaf(lamV, J.dvdC, dc);
-          float nv = lamV * J.dvdv;
+          A.dI[(int64_t)t * n + i] = lamV * dtC;
+          dc = fmaf(lamV, J[k].dvdC, dc);
+          float nv = lamV * J[k].dvdv;
 #pragma unroll
           for (int g = 0; g < NG; ++g) {
-            nv = fmaf(lamP[g], J.dpv[g], nv);
-            lamP[g] = fmaf(lamV, J.dvdp[g], lamP[g] * J.e[g]);
+            nv = fmaf(lamP[g], J[k].dpv[g], nv);
+            lamP[g] = fmaf(lamV, J[k].dvdp[g], lamP[g] * J[k].e[g]);
           }
           lamV = nv;
         }
@@ -213,14 +222,29 @@ __global__ __launch_bounds__(256) void k_bptt(KModel M, BwdArgs A) {
   }
 }
 
-// dCm[h] = sum over the batch, in batch order.
-__global__ __launch_bounds__(256) void k_sum_batch(const float* __restrict__ part,
-                                                   float* __restrict__ out, int64_t N, int32_t B) {
-  const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (h >= N) return;
+// dCm[h] = sum over the batch: a block owns 64 units h; its 16 lane groups
+// each sum a sixteenth of the batch, and the partial sums are added in group
+// order (deterministic).
+constexpr int SBH = 64, SBG = 16;
+
+__global__ __launch_bounds__(SBH * SBG) void k_sum_batch(const float* __restrict__ part,
+                                                         float* __restrict__ out, int64_t N,
+                                                         int32_t B) {
+  __shared__ float red[SBG][SBH];
+  const int hx = threadIdx.x % SBH, g = threadIdx.x / SBH;
+  const int64_t h = blockIdx.x * (int64_t)SBH + hx;
+  const int per = (B + SBG - 1) / SBG;
+  const int b0 = g * per, b1 = min(B, b0 + per);
   float s = 0.0f;
-  for (int b = 0; b < B; ++b) s += part[(int64_t)b * N + h];
-  out[h] = s;
+  if (h < N)
+    for (int b = b0; b < b1; ++b) s += part[(int64_t)b * N + h];
+  red[g][hx] = s;
+  __syncthreads();
+  if (g == 0 && h < N) {
+    float t = 0.0f;
+    for (int q = 0; q < SBG; ++q) t += red[q][hx];
+    out[h] = t;
+  }
 }
 
 template <class S>
@@ -294,8 +318,8 @@ int32_t hh_backward(hh_model* m, const float* ckpt, int32_t ckpt_every, const hh
   }
   if (e != hipSuccess) return HH_E_HIP;
   if (dCm) {
-    hipLaunchKernelGGL(k_sum_batch, dim3((unsigned)((m->N + 255) / 256)), dim3(256), 0, s,
-                       a.dC_part, dCm, m->N, m->B);
+    hipLaunchKernelGGL(k_sum_batch, dim3((unsigned)((m->N + SBH - 1) / SBH)), dim3(SBH * SBG), 0,
+                       s, a.dC_part, dCm, m->N, m->B);
     if (hipGetLastError() != hipSuccess) return HH_E_HIP;
   }
   return HH_OK;

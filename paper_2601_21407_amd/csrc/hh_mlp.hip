@@ -563,7 +563,7 @@ int32_t hh_mlp_infer(const void* packed, const float* X, int32_t S, float* Y, vo
 namespace {
 
 constexpr int SB = 256;  // block size = compaction pool
-constexpr int KMAX = 16;
+constexpr int KMAX = 32;  // steps per surrogate call (k * SB/32 <= SB threads clear the spike words)
 constexpr int SBW = SB / 32;  // spike words per block and step
 
 struct SurArgs {

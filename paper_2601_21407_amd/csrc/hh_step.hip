@@ -78,6 +78,8 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
     // dense input: the rows of the next four steps are loaded while the
     // current four are integrated, so no step waits for HBM
     const float* drow = A.i_dense + ii;
+    // steps until the next checkpoint (a counter, not a division per step)
+    int to_ck = A.ckpt ? (A.ckpt_every - A.k_base % A.ckpt_every) % A.ckpt_every : -1;
     float Icur[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -92,17 +94,21 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
         const int k = k0 + j;
         if (k >= A.nsteps) break;
         const int kk = A.k_base + k;
-        if (A.ckpt && (kk % A.ckpt_every) == 0 && act) {
-          float* c = A.ckpt + (int64_t)(kk / A.ckpt_every) * (2 + NG + 2 * M.has_syn) * n;
-          c[i] = vh;
-          c[row_lo + i] = vl;
+        if (to_ck == 0) {
+          to_ck = A.ckpt_every;
+          if (act) {
+            float* c = A.ckpt + (int64_t)(kk / A.ckpt_every) * (2 + NG + 2 * M.has_syn) * n;
+            c[i] = vh;
+            c[row_lo + i] = vl;
 #pragma unroll
-          for (int g = 0; g < NG; ++g) c[(int64_t)(1 + g) * n + i] = p[g];
-          if (M.has_syn) {
-            c[(int64_t)(1 + NG) * n + i] = ge;
-            c[(int64_t)(2 + NG) * n + i] = gi;
+            for (int g = 0; g < NG; ++g) c[(int64_t)(1 + g) * n + i] = p[g];
+            if (M.has_syn) {
+              c[(int64_t)(1 + NG) * n + i] = ge;
+              c[(int64_t)(2 + NG) * n + i] = gi;
+            }
           }
         }
+        if (to_ck > 0) --to_ck;
         const float V = vh;
         neuron_step<S>(M, L, dtC, vh, vl, p, Icur[j], ge, gi);
         const float Vn = vh;

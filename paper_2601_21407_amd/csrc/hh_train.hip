@@ -70,28 +70,51 @@ __global__ __launch_bounds__(256) void k_readout_row(const float* __restrict__ l
 }
 
 // dW[h][c] = sum_b r[b][h] dz[b][c]; db[c] = sum_b dz[b][c]; loss = mean.
-__global__ __launch_bounds__(256) void k_readout_wgrad(const float* __restrict__ level, float invT,
-                                                       const float* __restrict__ dz,
-                                                       const float* __restrict__ row_loss, int B,
-                                                       int H, int C, float* __restrict__ dW,
-                                                       float* __restrict__ db,
-                                                       float* __restrict__ loss) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t HC = (int64_t)H * C;
-  if (idx < HC) {
-    const int h = (int)(idx / C), c = (int)(idx % C);
+// A block owns 32 readout rows h; its 8 lane groups each sum one eighth of
+// the batch, and the eight partial sums are added in group order.  Block 0
+// also forms db and the loss.
+constexpr int RW_H = 32, RW_G = 8;
+
+__global__ __launch_bounds__(RW_H * RW_G) void k_readout_wgrad(
+    const float* __restrict__ level, float invT, const float* __restrict__ dz,
+    const float* __restrict__ row_loss, int B, int H, int C, float* __restrict__ dW,
+    float* __restrict__ db, float* __restrict__ loss) {
+  __shared__ float part[RW_G][RW_H][kMaxC + 1];
+  const int tid = threadIdx.x, hx = tid % RW_H, g = tid / RW_H;
+  const int h = blockIdx.x * RW_H + hx;
+  float acc[kMaxC];
+#pragma unroll
+  for (int c = 0; c < kMaxC; ++c) acc[c] = 0.0f;
+  const int per = (B + RW_G - 1) / RW_G;
+  const int b0 = g * per, b1 = min(B, b0 + per);
+  if (h < H) {
+    for (int b = b0; b < b1; ++b) {
+      const float r = level[(int64_t)b * H + h] * invT;
+#pragma unroll
+      for (int c = 0; c < kMaxC; ++c)
+        if (c < C) acc[c] = fmaf(r, dz[(int64_t)b * C + c], acc[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kMaxC; ++c) part[g][hx][c] = acc[c];
+  __syncthreads();
+  for (int e = tid; e < RW_H * C; e += blockDim.x) {
+    const int hh = e / C, c = e % C;
     float s = 0.0f;
-    for (int b = 0; b < B; ++b) s = fmaf(level[(int64_t)b * H + h] * invT, dz[(int64_t)b * C + c], s);
-    dW[idx] = s;
-  } else if (idx < HC + C) {
-    const int c = (int)(idx - HC);
-    float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += dz[(int64_t)b * C + c];
-    db[c] = s;
-  } else if (idx == HC + C) {
-    float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += row_loss[b];
-    *loss = s / (float)B;
+    for (int q = 0; q < RW_G; ++q) s += part[q][hh][c];
+    const int hg = blockIdx.x * RW_H + hh;
+    if (hg < H) dW[(int64_t)hg * C + c] = s;
+  }
+  if (blockIdx.x == 0) {
+    if (tid < C) {
+      float s = 0.0f;
+      for (int b = 0; b < B; ++b) s += dz[(int64_t)b * C + tid];
+      db[tid] = s;
+    } else if (tid == C) {
+      float s = 0.0f;
+      for (int b = 0; b < B; ++b) s += row_loss[b];
+      *loss = s / (float)B;
+    }
   }
 }
 
@@ -139,9 +162,8 @@ int32_t hh_readout_ce(const float* level, int32_t T, const float* W, const float
   const float invT = 1.0f / (float)T;
   hipLaunchKernelGGL(k_readout_row, dim3(B), dim3(256), 0, s, level, invT, W, bias, labels, B, H, C,
                      dz, row_loss, dlevel, logits);
-  const int64_t work = (int64_t)H * C + C + 1;
-  hipLaunchKernelGGL(k_readout_wgrad, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, level,
-                     invT, dz, row_loss, B, H, C, dW, db, loss);
+  hipLaunchKernelGGL(k_readout_wgrad, dim3((unsigned)((H + RW_H - 1) / RW_H)), dim3(RW_H * RW_G), 0,
+                     s, level, invT, dz, row_loss, B, H, C, dW, db, loss);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 

@@ -168,9 +168,9 @@ def spike_time_error(ref_bits, bits, n, dt_ref, dt_test, window_ms=2.0, max_neur
 
 
 def deploy(packed, n, T, *, i_dense=None, noise=None, spikes=True, check_every=CHECK_EVERY,
-           v_fallback=V_FALLBACK, check_tol=CHECK_TOL, dev="cuda"):
+           v_fallback=V_FALLBACK, check_tol=CHECK_TOL, k=K_STEPS, dev="cuda"):
     """Run the surrogate deployment kernel on n neurons (cortical set,
-    nominal rates) for T plain-step equivalents.  Returns (model, state,
+    nominal rates) for T plain-step equivalents, k steps per call.  Returns (model, state,
     spike bits or None, stats [surrogate calls, plain calls, failed checks])."""
     m = W.custom_channels(dt=0.025)
     M = hh.Model(m, n)
@@ -179,7 +179,7 @@ def deploy(packed, n, T, *, i_dense=None, noise=None, spikes=True, check_every=C
     flags = torch.zeros(n, dtype=torch.uint8, device=dev)
     bits = torch.zeros((T, M.words), dtype=torch.int32, device=dev) if spikes else None
     stats = torch.zeros(3, dtype=torch.int64, device=dev)
-    hh.surrogate_step_n(M, packed, st, flags, T, K_STEPS, 0, i_dense=i_dense, noise=noise,
+    hh.surrogate_step_n(M, packed, st, flags, T, k, 0, i_dense=i_dense, noise=noise,
                         v_fallback=v_fallback, check_every=check_every, check_tol=check_tol,
                         spikes=bits, stats=stats)
     return M, st, bits, stats
