@@ -301,6 +301,9 @@ def bench_layer(reps=5, ckpt_every=50):
     Win, cm0, Wout, bout = W.layer_params()
     dev = "cuda"
     S = torch.tensor(S8.reshape(T * B, n_in), device=dev).to(torch.bfloat16)
+    # the same spikes bit-packed for the forward product (1/16 of the bytes)
+    Sbits = torch.tensor(W.pack_bits(S8.reshape(T * B, n_in)), device=dev)
+    SbitsT = torch.tensor(W.pack_bits(S8.reshape(T * B, n_in).T), device=dev)  # for dW
     # the projection keeps the weights transposed: [H][n_in], K contiguous
     win32 = torch.tensor(np.ascontiguousarray(Win.T), device=dev)
     win16 = win32.to(torch.bfloat16)
@@ -336,7 +339,7 @@ def bench_layer(reps=5, ckpt_every=50):
 
     def forward():
         mark("f0")
-        hh.proj_forward(S, win16, I)
+        hh.proj_forward_bits(Sbits, n_in, win16, I)
         mark("f1")
         M.init_state(st, v0_scalar=-65.0)
         lv.zero_()
@@ -349,7 +352,7 @@ def bench_layer(reps=5, ckpt_every=50):
         M.backward(ck, ckpt_every, I, T, dI, dL_dlevel=dl.view(-1), beta=0.2, dCm=dC,
                    workspace=ws_b)
         mark("b1")
-        hh.proj_wgrad(S, dI.view(T * B, H), dWin, workspace=ws_w)
+        hh.proj_wgrad_bits(SbitsT, T * B, dI.view(T * B, H), dWin, workspace=ws_w)
         mark("b2")
         for k, (p, g) in (("win", (win32, dWin)), ("cm", (cm, dC)), ("wout", (wout, dWo)),
                           ("b", (bo, db))):

@@ -209,6 +209,12 @@ int32_t hh_check(hh_model* m, int64_t* first_bad, void* stream);
  * operands are K-contiguous.  All arrays row-major, device memory. */
 int32_t hh_proj_forward(const uint16_t* A, const uint16_t* Wt, float* out, int32_t M, int32_t N,
                         int32_t K, void* stream);
+/* The same product for a binary (spike) input given as bits:
+ * A_bits [M][words_per_row] uint32 (device), bit k%32 of word k/32 of row m
+ * is A[m][k] in {0, 1}; words_per_row >= ceil(K/32), bits at k >= K are
+ * ignored.  A costs 1/16 of the bf16 input's memory traffic. */
+int32_t hh_proj_forward_bits(const uint32_t* A_bits, int32_t words_per_row, const uint16_t* Wt,
+                             float* out, int32_t M, int32_t N, int32_t K, void* stream);
 /* Weight gradient dWt[N][K] (float, written) = dOut^T A, A [M][K] bf16,
  * dOut [M][N] float (split into bf16 high and low parts inside the kernel,
  * so the product keeps ~16 bits of dOut).  The reduction over M is split
@@ -218,6 +224,12 @@ int32_t hh_proj_forward(const uint16_t* A, const uint16_t* Wt, float* out, int32
 int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t M, int32_t N,
                       int32_t K, void* workspace, size_t workspace_bytes, void* stream);
 size_t hh_proj_wgrad_workspace(int32_t M, int32_t N, int32_t K);
+/* The same weight gradient for a binary A given transposed as bits:
+ * At_bits [K][words_per_col] uint32 (device), bit m%32 of word m/32 of row k
+ * is A[m][k] in {0, 1}; words_per_col >= ceil(M/32).  Same workspace. */
+int32_t hh_proj_wgrad_bits(const uint32_t* At_bits, int32_t words_per_col, const float* dOut,
+                           float* dWt, int32_t M, int32_t N, int32_t K, void* workspace,
+                           size_t workspace_bytes, void* stream);
 
 /* Linear readout of the mean spike level and cross-entropy loss, forward and
  * backward (the readout layer of the differentiable network, Methods

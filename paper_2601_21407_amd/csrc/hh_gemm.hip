@@ -166,6 +166,122 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd(const uint16_t* __restrict_
     }
 }
 
+// Forward with binary (spike) input: A given as bits, A_bits [M][wpr] uint32,
+// bit k%32 of word k/32 = A[m][k] in {0, 1}.  The A slab of each 32-wide K
+// step is one word per row; it is expanded to bf16 (0 or 1.0) while being
+// written to LDS, so A costs 1/16 of the bf16 path's traffic and only the
+// weight slab is staged from memory -- prefetched two slabs ahead.
+__device__ __forceinline__ uint4 bits_to_bf16x8(uint32_t b8) {
+  // bit j -> bf16 1.0 (0x3F80) or 0 in element j
+  uint32_t w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t lo = (b8 >> (2 * q)) & 1u, hi = (b8 >> (2 * q + 1)) & 1u;
+    w[q] = lo * 0x3F80u + hi * 0x3F800000u;
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __restrict__ Ab, int wpr,
+                                                          const uint16_t* __restrict__ Wt,
+                                                          float* __restrict__ C, int M, int N,
+                                                          int K, int al) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][FBM * LDK];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][FBN * LDK];  // [n][k]
+  const int tiles_m = (M + FBM - 1) / FBM, tiles_n = (N + FBN - 1) / FBN;
+  int tm, tn;
+  if (!tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn)) return;
+  const int m0 = tm * FBM, n0 = tn * FBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const bool aligned = al != 0;
+  // A: thread expands 16 bits (half h of the slab word) of row ar;
+  // Wt: chunk tid (row br, k = 8 (tid % 4))
+  const int ar = tid >> 1, ah = tid & 1;
+  const bool av = m0 + ar < M;
+  const uint32_t* arow = Ab + (int64_t)min(m0 + ar, M - 1) * wpr;
+  const int br = tid >> 2, bkc = (tid & 3) * 8;
+  const bool bv = n0 + br < N;
+  const uint16_t* brow = Wt + (int64_t)min(n0 + br, N - 1) * K;
+  const int ns = (K + SK - 1) / SK;
+
+  auto a_bits = [&](int s) -> uint32_t {
+    if (!av || s >= ns) return 0u;
+    uint32_t w = arow[s];
+    const int valid = K - s * SK;  // bits past K are ignored
+    if (valid < 32) w &= (1u << valid) - 1u;
+    return (w >> (16 * ah)) & 0xFFFFu;
+  };
+  auto b_load = [&](int s) -> uint4 {
+    const uint4 zero = {0u, 0u, 0u, 0u};
+    if (!bv || s >= ns) return zero;
+    return load8(brow, s * SK + bkc, K, aligned);
+  };
+  auto stash = [&](int buf, uint32_t a16, uint4 b) {
+    uint4* pa = reinterpret_cast<uint4*>(&As[buf][ar * LDK + 16 * ah]);
+    pa[0] = bits_to_bf16x8(a16 & 0xFFu);
+    pa[1] = bits_to_bf16x8(a16 >> 8);
+    *reinterpret_cast<uint4*>(&Bs[buf][br * LDK + bkc]) = b;
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  auto compute = [&](int buf) {
+    const uint16_t* as = As[buf];
+    const uint16_t* bs = Bs[buf];
+#pragma unroll
+    for (int kk = 0; kk < SK; kk += 16) {
+      const int kl = kk + 8 * (lane >> 5);
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = lds8(as + (wm * 64 + i * 32 + (lane & 31)) * LDK + kl);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = lds8(bs + (wn * 64 + j * 32 + (lane & 31)) * LDK + kl);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  };
+
+  // slab s sits in LDS buffer s % 2; the weight slabs s+1 and s+2 are in
+  // registers (rb1, rb2) while slab s is multiplied
+  stash(0, a_bits(0), b_load(0));
+  uint4 rb1 = b_load(1), rb2 = b_load(2);
+  uint32_t ra1 = a_bits(1), ra2 = a_bits(2);
+  __syncthreads();
+  for (int s = 0; s < ns; ++s) {
+    compute(s & 1);
+    if (s + 1 < ns) {
+      // buffer (s+1)%2 was last read in slab s-1, before the previous barrier
+      stash((s + 1) & 1, ra1, rb1);
+      rb1 = rb2;
+      ra1 = ra2;
+      rb2 = b_load(s + 3);
+      ra2 = a_bits(s + 3);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 64 + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row < M && col < N) C[(int64_t)row * N + col] = acc[i][j][r];
+      }
+    }
+}
+
 // Weight gradient, one split of the reduction over M per blockIdx.y.
 // Output tile: 128 (n) x 128 (k) of dWt; four wavefronts of 64 x 64.  Per
 // slab 32 rows of M are staged as dOut^T [n][m] (bf16 hi and lo parts) and
@@ -174,7 +290,11 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd(const uint16_t* __restrict_
 // 16-byte LDS stores.
 constexpr int GBN = 128, GBK = 128;
 
+// BITS: A given transposed as bits, At_bits [K][wpc] (bit m%32 of word m/32
+// of row k = A[m][k]); a lane's 16 rows of one column are then one word.
+template <bool BITS>
 __global__ __launch_bounds__(256, 2) void k_proj_wgrad(const uint16_t* __restrict__ A,
+                                                       const uint32_t* __restrict__ Atb, int wpc,
                                                        const float* __restrict__ D,
                                                        float* __restrict__ part, int M, int N,
                                                        int K, int rows_per_split) {
@@ -192,7 +312,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_wgrad(const uint16_t* __restric
   const int c = tid & 127, g = tid >> 7;
   const bool dv = n0 + c < N, av = k0 + c < K;
   const float* dcol = D + min(n0 + c, N - 1);
-  const uint16_t* acol = A + min(k0 + c, K - 1);
+  const uint16_t* acol = BITS ? nullptr : A + min(k0 + c, K - 1);
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -204,13 +324,24 @@ __global__ __launch_bounds__(256, 2) void k_proj_wgrad(const uint16_t* __restric
 
   float dreg[16];
   uint16_t areg[16];
+  uint32_t abits = 0u;
+  const uint32_t* bcol = BITS ? Atb + (int64_t)min(k0 + c, K - 1) * wpc : nullptr;
   auto gather = [&](int ms) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int m = ms + g * 16 + e;
       const bool ok = m < mend;
       dreg[e] = (ok && dv) ? dcol[(int64_t)m * N] : 0.0f;
-      areg[e] = (ok && av) ? acol[(int64_t)m * K] : (uint16_t)0;
+      if (!BITS) areg[e] = (ok && av) ? acol[(int64_t)m * K] : (uint16_t)0;
+    }
+    if (BITS) {
+      // rows ms + 16 g .. + 15: half (g) of word ms / 32 (ms is a multiple
+      // of 32); rows at or past mend belong to the next split
+      const int m = ms + g * 16;
+      const int valid = mend - m;
+      uint32_t w = (av && valid > 0) ? (bcol[m >> 5] >> (16 * g)) & 0xFFFFu : 0u;
+      if (valid < 16) w &= valid > 0 ? (1u << valid) - 1u : 0u;
+      abits = w;
     }
   };
   auto stash = [&](int buf) {
@@ -221,7 +352,10 @@ __global__ __launch_bounds__(256, 2) void k_proj_wgrad(const uint16_t* __restric
       const uint16_t l0 = f2bf(dreg[2 * e] - bf2f(h0)), l1 = f2bf(dreg[2 * e + 1] - bf2f(h1));
       h[e] = (uint32_t)h0 | ((uint32_t)h1 << 16);
       l[e] = (uint32_t)l0 | ((uint32_t)l1 << 16);
-      a[e] = (uint32_t)areg[2 * e] | ((uint32_t)areg[2 * e + 1] << 16);
+      if (BITS)
+        a[e] = ((abits >> (2 * e)) & 1u) * 0x3F80u + ((abits >> (2 * e + 1)) & 1u) * 0x3F800000u;
+      else
+        a[e] = (uint32_t)areg[2 * e] | ((uint32_t)areg[2 * e + 1] << 16);
     }
     uint4* ph = reinterpret_cast<uint4*>(&Dh[buf][c * LDK + g * 16]);
     uint4* pl = reinterpret_cast<uint4*>(&Dl[buf][c * LDK + g * 16]);
@@ -324,6 +458,22 @@ int32_t hh_proj_forward(const uint16_t* A, const uint16_t* Wt, float* out, int32
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 
+int32_t hh_proj_forward_bits(const uint32_t* A_bits, int32_t words_per_row, const uint16_t* Wt,
+                             float* out, int32_t M, int32_t N, int32_t K, void* stream) {
+  if (M < 0 || N < 0 || K < 0) return HH_E_SHAPE;
+  if (M == 0 || N == 0) return HH_OK;
+  if (!out || (K > 0 && (!A_bits || !Wt))) return HH_E_INVALID;
+  if (words_per_row < (K + 31) / 32) return HH_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  if (K == 0) return fill_zero(out, (int64_t)M * N, s) == hipSuccess ? HH_OK : HH_E_HIP;
+  const int tiles = ((M + FBM - 1) / FBM) * ((N + FBN - 1) / FBN);
+  const int blocks = (tiles + 7) / 8 * 8;
+  const int al = (K % 4 == 0) && ((uintptr_t)Wt % 8 == 0);
+  hipLaunchKernelGGL(k_proj_fwd_bits, dim3(blocks), dim3(512), 0, s, A_bits, words_per_row, Wt, out,
+                     M, N, K, al);
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
 size_t hh_proj_wgrad_workspace(int32_t M, int32_t N, int32_t K) {
   if (M <= 0 || N <= 0 || K <= 0) return 0;
   return (size_t)wgrad_splits(M) * (size_t)K * (size_t)N * sizeof(float);
@@ -343,8 +493,32 @@ int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t 
   rows = (rows + SK - 1) / SK * SK;
   const int tiles = ((K + GBK - 1) / GBK) * ((N + GBN - 1) / GBN);
   float* part = (float*)workspace;
-  hipLaunchKernelGGL(k_proj_wgrad, dim3(tiles, splits), dim3(256), 0, s, A, dOut, part, M, N, K,
-                     rows);
+  hipLaunchKernelGGL(k_proj_wgrad<false>, dim3(tiles, splits), dim3(256), 0, s, A, nullptr, 0, dOut,
+                     part, M, N, K, rows);
+  const int64_t count = (int64_t)K * N;
+  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, part,
+                     dWt, count, splits);
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+int32_t hh_proj_wgrad_bits(const uint32_t* At_bits, int32_t words_per_col, const float* dOut,
+                           float* dWt, int32_t M, int32_t N, int32_t K, void* workspace,
+                           size_t workspace_bytes, void* stream) {
+  if (M < 0 || N < 0 || K < 0) return HH_E_SHAPE;
+  if (N == 0 || K == 0) return HH_OK;
+  if (!dWt || (M > 0 && (!At_bits || !dOut))) return HH_E_INVALID;
+  if (words_per_col < (M + 31) / 32) return HH_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  if (M == 0) return fill_zero(dWt, (int64_t)N * K, s) == hipSuccess ? HH_OK : HH_E_HIP;
+  const size_t need = hh_proj_wgrad_workspace(M, N, K);
+  if (!workspace || workspace_bytes < need) return HH_E_SHAPE;
+  const int splits = wgrad_splits(M);
+  int rows = (M + splits - 1) / splits;
+  rows = (rows + SK - 1) / SK * SK;
+  const int tiles = ((K + GBK - 1) / GBK) * ((N + GBN - 1) / GBN);
+  float* part = (float*)workspace;
+  hipLaunchKernelGGL(k_proj_wgrad<true>, dim3(tiles, splits), dim3(256), 0, s, nullptr, At_bits,
+                     words_per_col, dOut, part, M, N, K, rows);
   const int64_t count = (int64_t)K * N;
   hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, part,
                      dWt, count, splits);

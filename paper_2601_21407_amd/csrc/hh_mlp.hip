@@ -230,20 +230,34 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P,
   }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ part,
-                                                    const float* __restrict__ loss_part,
-                                                    int nblocks, float invS,
-                                                    float* __restrict__ grad,
-                                                    float* __restrict__ loss) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum of the per-block partial gradients (and losses): a block owns 64
+// entries; its 16 lane groups each add a sixteenth of the partials, and the
+// group sums are added in group order (deterministic).
+constexpr int RD_J = 64, RD_G = 16;
+
+__global__ __launch_bounds__(RD_J * RD_G) void k_mlp_reduce(const float* __restrict__ part,
+                                                          const float* __restrict__ loss_part,
+                                                          int nblocks, float invS,
+                                                          float* __restrict__ grad,
+                                                          float* __restrict__ loss) {
+  __shared__ float red[RD_G][RD_J];
+  const int jx = threadIdx.x % RD_J, g = threadIdx.x / RD_J;
+  const int j = blockIdx.x * RD_J + jx;  // MLP_NPARAM = the loss
+  const int per = (nblocks + RD_G - 1) / RD_G;
+  const int b0 = g * per, b1 = min(nblocks, b0 + per);
+  float s = 0.0f;
   if (j < MLP_NPARAM) {
-    float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * MLP_NPARAM + j];
-    grad[j] = s;
-  } else if (j == MLP_NPARAM && loss) {
-    float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += loss_part[b];
-    *loss = s * invS;
+    for (int b = b0; b < b1; ++b) s += part[(int64_t)b * MLP_NPARAM + j];
+  } else if (j == MLP_NPARAM) {
+    for (int b = b0; b < b1; ++b) s += loss_part[b];
+  }
+  red[g][jx] = s;
+  __syncthreads();
+  if (g == 0 && j <= MLP_NPARAM) {
+    float t = 0.0f;
+    for (int q = 0; q < RD_G; ++q) t += red[q][jx];
+    if (j < MLP_NPARAM) grad[j] = t;
+    else if (loss) *loss = t * invS;
   }
 }
 
@@ -510,8 +524,8 @@ int32_t hh_mlp_grad(const float* params, const float* X, const float* Y, int32_t
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, s, params, X, Y, S, per, quantize ? 1 : 0,
                      part, lpart);
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, part, lpart,
-                     nb, 1.0f / (float)S, grad, loss);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + RD_J - 1) / RD_J), dim3(RD_J * RD_G), 0, s,
+                     part, lpart, nb, 1.0f / (float)S, grad, loss);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 

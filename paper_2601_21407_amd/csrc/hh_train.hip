@@ -70,29 +70,37 @@ __global__ __launch_bounds__(256) void k_readout_row(const float* __restrict__ l
 }
 
 // dW[h][c] = sum_b r[b][h] dz[b][c]; db[c] = sum_b dz[b][c]; loss = mean.
-// A block owns 32 readout rows h; its 8 lane groups each sum one eighth of
-// the batch, and the eight partial sums are added in group order.  Block 0
-// also forms db and the loss.
-constexpr int RW_H = 32, RW_G = 8;
+// A block owns 32 readout rows h; the batch goes through LDS in chunks of
+// 256 rows of dz, whose eight 32-row parts are summed by the block's eight
+// lane groups; the group partials are added in group order.  Block 0 also
+// forms db and the loss.
+constexpr int RW_H = 32, RW_G = 8, RW_CH = 256;
 
 __global__ __launch_bounds__(RW_H * RW_G) void k_readout_wgrad(
     const float* __restrict__ level, float invT, const float* __restrict__ dz,
     const float* __restrict__ row_loss, int B, int H, int C, float* __restrict__ dW,
     float* __restrict__ db, float* __restrict__ loss) {
+  __shared__ float s_dz[RW_CH][kMaxC + 1];
   __shared__ float part[RW_G][RW_H][kMaxC + 1];
   const int tid = threadIdx.x, hx = tid % RW_H, g = tid / RW_H;
   const int h = blockIdx.x * RW_H + hx;
   float acc[kMaxC];
 #pragma unroll
   for (int c = 0; c < kMaxC; ++c) acc[c] = 0.0f;
-  const int per = (B + RW_G - 1) / RW_G;
-  const int b0 = g * per, b1 = min(B, b0 + per);
-  if (h < H) {
-    for (int b = b0; b < b1; ++b) {
-      const float r = level[(int64_t)b * H + h] * invT;
+  for (int c0 = 0; c0 < B; c0 += RW_CH) {
+    const int nb = min(RW_CH, B - c0);
+    __syncthreads();  // previous chunk consumed
+    for (int e = tid; e < nb * C; e += blockDim.x) s_dz[e / C][e % C] = dz[(int64_t)c0 * C + e];
+    __syncthreads();
+    const int per = RW_CH / RW_G;
+    const int b0 = g * per, b1 = min(nb, b0 + per);
+    if (h < H) {
+      for (int b = b0; b < b1; ++b) {
+        const float r = level[(int64_t)(c0 + b) * H + h] * invT;
 #pragma unroll
-      for (int c = 0; c < kMaxC; ++c)
-        if (c < C) acc[c] = fmaf(r, dz[(int64_t)b * C + c], acc[c]);
+        for (int c = 0; c < kMaxC; ++c)
+          if (c < C) acc[c] = fmaf(r, s_dz[b][c], acc[c]);
+      }
     }
   }
 #pragma unroll

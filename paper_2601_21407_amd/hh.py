@@ -86,8 +86,10 @@ def _load():
         "hh_backward_workspace": ([vp, i32], sz),
         "hh_check": ([vp, P(i64), vp], i32),
         "hh_proj_forward": ([vp, vp, vp, i32, i32, i32, vp], i32),
+        "hh_proj_forward_bits": ([vp, i32, vp, vp, i32, i32, i32, vp], i32),
         "hh_proj_wgrad": ([vp, vp, vp, i32, i32, i32, vp, sz, vp], i32),
         "hh_proj_wgrad_workspace": ([i32, i32, i32], sz),
+        "hh_proj_wgrad_bits": ([vp, i32, vp, vp, i32, i32, i32, vp, sz, vp], i32),
         "hh_readout_ce": ([vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "hh_readout_ce_workspace": ([i32, i32], sz),
         "hh_adam_step": ([vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp], i32),
@@ -119,7 +121,8 @@ def exported_symbols():
                         "hh_set_specialize",
                         "hh_init_state", "hh_step_n", "hh_attach_csr", "hh_set_external",
                         "hh_syn_propagate", "hh_backward", "hh_backward_workspace", "hh_check",
-                        "hh_proj_forward", "hh_proj_wgrad", "hh_proj_wgrad_workspace",
+                        "hh_proj_forward", "hh_proj_forward_bits", "hh_proj_wgrad",
+                        "hh_proj_wgrad_workspace", "hh_proj_wgrad_bits",
                         "hh_readout_ce", "hh_readout_ce_workspace", "hh_adam_step",
                         "hh_mlp_grad", "hh_mlp_grad_workspace", "hh_mlp_forward", "hh_mlp_pack",
                         "hh_mlp_packed_bytes", "hh_mlp_infer", "hh_surrogate_step_n")]
@@ -293,6 +296,19 @@ def proj_forward(A_bf16, Wt_bf16, out):
     return out
 
 
+def proj_forward_bits(A_bits, K: int, Wt_bf16, out):
+    """out [M][N] = A . Wt^T for a binary A given as bits: A_bits int32
+    [M][words], bit k%32 of word k/32 = A[m][k]."""
+    M, wpr = A_bits.shape
+    N = Wt_bf16.shape[0]
+    assert A_bits.dtype == torch.int32 and Wt_bf16.dtype == torch.bfloat16
+    assert tuple(out.shape) == (M, N) and out.dtype == torch.float32 and Wt_bf16.shape[1] == K
+    assert A_bits.is_contiguous() and Wt_bf16.is_contiguous() and out.is_contiguous()
+    _ok(lib.hh_proj_forward_bits(_ptr(A_bits), int(wpr), _ptr(Wt_bf16), _ptr(out), M, N, int(K),
+                                 _stream()), "hh_proj_forward_bits")
+    return out
+
+
 def proj_wgrad(A_bf16, dOut, dWt, workspace=None):
     """dWt [N][K] = dOut [M][N]^T . A [M][K]."""
     M, K = A_bf16.shape
@@ -305,6 +321,23 @@ def proj_wgrad(A_bf16, dOut, dWt, workspace=None):
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dWt.device)
     _ok(lib.hh_proj_wgrad(_ptr(A_bf16), _ptr(dOut), _ptr(dWt), M, N, K, _ptr(workspace),
                           workspace.numel() * workspace.element_size(), _stream()), "hh_proj_wgrad")
+    return dWt
+
+
+def proj_wgrad_bits(At_bits, M: int, dOut, dWt, workspace=None):
+    """dWt [N][K] = dOut [M][N]^T . A for a binary A given transposed as
+    bits: At_bits int32 [K][words], bit m%32 of word m/32 = A[m][k]."""
+    K, wpc = At_bits.shape
+    N = dOut.shape[1]
+    assert At_bits.dtype == torch.int32 and dOut.dtype == torch.float32
+    assert tuple(dWt.shape) == (N, K) and dWt.dtype == torch.float32 and dOut.shape[0] == M
+    assert At_bits.is_contiguous() and dOut.is_contiguous() and dWt.is_contiguous()
+    need = int(lib.hh_proj_wgrad_workspace(M, N, K))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dWt.device)
+    _ok(lib.hh_proj_wgrad_bits(_ptr(At_bits), int(wpc), _ptr(dOut), _ptr(dWt), int(M), N, K,
+                               _ptr(workspace), workspace.numel() * workspace.element_size(),
+                               _stream()), "hh_proj_wgrad_bits")
     return dWt
 
 

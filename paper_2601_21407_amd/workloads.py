@@ -205,6 +205,18 @@ def layer_inputs(B: int = 256, T: int = 250, n_in: int = 700, n_cls: int = 20, s
     return S, labels.astype(np.int64)
 
 
+def pack_bits(A) -> np.ndarray:
+    """Binary matrix [M, K] (any dtype, values 0/1) to int32 words [M, ceil(K/32)]:
+    bit k%32 of word k/32 is A[m, k]."""
+    A = np.asarray(A) != 0
+    M, K = A.shape
+    wpr = (K + 31) // 32
+    pad = np.zeros((M, wpr * 32), np.uint8)
+    pad[:, :K] = A
+    by = np.packbits(pad.reshape(M, wpr * 4, 8), axis=2, bitorder="little").reshape(M, wpr * 4)
+    return np.ascontiguousarray(by).view(np.uint32).view(np.int32).reshape(M, wpr)
+
+
 def layer_params(n_in: int = 700, H: int = 1024, n_cls: int = 20, seed: int = 4,
                  w_mean: float = 0.5, w_std: float = 0.8):
     """Initial parameters of the differentiable layer: W_in [n_in, H] (to be

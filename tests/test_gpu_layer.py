@@ -51,6 +51,54 @@ def test_projection_forward_and_wgrad_small(M, N, K, binary):
     assert np.all(np.abs(dWt.cpu().numpy().T - refw) <= 2e-5 * scw + 1e-30)
 
 
+@pytest.mark.parametrize("M,N,K", [(300, 200, 70), (129, 1025, 33), (1, 1, 1), (640, 256, 700),
+                                   (257, 129, 32), (513, 130, 64), (3, 4, 0), (0, 5, 7)])
+def test_projection_forward_bits(M, N, K):
+    """Spike input given as bits: the product equals the oracle's on the
+    unpacked 0/1 matrix, and the bf16-input kernel's result."""
+    print_case("proj bits M=%d N=%d K=%d" % (M, N, K))
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    rng = np.random.default_rng(7 * M + N + K)
+    A = (rng.random((M, K)) < 0.1).astype(np.float32)
+    W16 = W.bf16_round(rng.standard_normal((K, N)))
+    bits = W.pack_bits(A) if M > 0 else np.zeros((0, max(1, (K + 31) // 32)), np.int32)
+    if bits.shape[1] == 0:
+        bits = np.zeros((M, 1), np.int32)
+    # junk in the bits past K must be ignored
+    if K % 32:
+        bits = bits.copy()
+        bits[:, -1] |= np.int32(-1 << (K % 32)) if K % 32 else 0
+    out = torch.empty((M, N), device="cuda")
+    Wt = _bf16_tensor(W16.T)
+    hh.proj_forward_bits(torch.tensor(bits, device="cuda"), K, Wt, out)
+    ref = O.projection(A, W16)
+    scale = np.abs(A.astype(np.float64)) @ np.abs(W16.astype(np.float64))
+    assert np.all(np.abs(out.cpu().numpy() - ref) <= 1e-6 * scale + 1e-30)
+    if M > 0 and K > 0:
+        out2 = torch.empty((M, N), device="cuda")
+        hh.proj_forward(_bf16_tensor(A), Wt, out2)
+        # same products, same tile order: identical
+        assert torch.equal(out, out2)
+    # weight gradient from the transposed bits (junk past M ignored)
+    dO = rng.standard_normal((M, N)).astype(np.float32)
+    bT = W.pack_bits(A.T) if K > 0 else np.zeros((0, 1), np.int32)
+    if bT.shape[1] == 0:
+        bT = np.zeros((K, 1), np.int32)
+    if M % 32:
+        bT = bT.copy()
+        bT[:, -1] |= np.int32(-1 << (M % 32))
+    dWt = torch.empty((N, K), device="cuda")
+    hh.proj_wgrad_bits(torch.tensor(bT, device="cuda"), M, torch.tensor(dO, device="cuda"), dWt)
+    refw = O.projection_weight_grad(A, dO)
+    scw = np.abs(A.astype(np.float64)).T @ np.abs(dO.astype(np.float64))
+    assert np.all(np.abs(dWt.cpu().numpy().T - refw) <= 2e-5 * scw + 1e-30)
+    if M > 0 and K > 0:
+        dWt2 = torch.empty((N, K), device="cuda")
+        hh.proj_wgrad(_bf16_tensor(A), torch.tensor(dO, device="cuda"), dWt2)
+        assert torch.equal(dWt, dWt2)
+
+
 def test_projection_full_size_sampled():
     """S [250*256 x 700] Bernoulli spikes x W_in [700 x 1024] bf16."""
     print_case("proj full 64000 x 1024 x 700")
@@ -69,6 +117,10 @@ def test_projection_full_size_sampled():
     scale = np.abs(A[rows]) @ np.abs(W16.astype(np.float64))
     got = out.cpu().numpy()[rows]
     assert np.all(np.abs(got - ref) <= 1e-6 * scale + 1e-30)
+    # the bit-packed spike input gives the identical product
+    outb = torch.empty_like(out)
+    hh.proj_forward_bits(torch.tensor(W.pack_bits(A), device="cuda"), n_in, _bf16_tensor(W16.T), outb)
+    assert torch.equal(out, outb)
     # weight gradient of the same shapes, checked on a column block
     dO = np.random.default_rng(1).standard_normal((T * B, 1024)).astype(np.float32) * 1e-3
     dWt = torch.empty((1024, n_in), device="cuda")

@@ -95,3 +95,16 @@ def test_horizon_helper_on_oracle():
             # dropping a well-conditioned spike fails
             if h[j] > 0:
                 assert not match_to_horizon(steps[j][1:], steps[j], h[j])
+
+
+def test_pack_bits_layout():
+    """Bit k%32 of word k/32 of row m is A[m, k]; the words are int32."""
+    A = (np.random.default_rng(2).random((7, 100)) < 0.4)
+    b = W.pack_bits(A)
+    assert b.dtype == np.int32 and b.shape == (7, 4)
+    u = b.view(np.uint32)
+    for m in range(7):
+        for k in range(100):
+            assert ((int(u[m, k // 32]) >> (k % 32)) & 1) == int(A[m, k])
+    # bits past K are zero
+    assert (int(u[0, 3]) >> 4) == 0
