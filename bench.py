@@ -567,7 +567,10 @@ def counters_run():
     M.step_n(st, 32, 0, noise=(5.0, 3.0, seed), spikes=spikes)
     _sync()
     print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
-                      "k_step_alg_bytes": n * (2 * M.n_state * 4 + 40 * 4) + 32 * M.words * 4,
+                      # state rows read and written once; the coefficients a launch reads:
+                      # (A, B, K) of each of the 10 rates plus the bell rate's c = 31 per
+                      # neuron; one spike word per 32 neurons and step
+                      "k_step_alg_bytes": n * (2 * M.n_state * 4 + 31 * 4) + 32 * M.words * 4,
                       "src_hash": _src_hash(STEP_KERNEL_SOURCES)}))
 
 

@@ -189,12 +189,23 @@ int32_t hh_syn_propagate(hh_model* m, const uint32_t* spike_bits, float* state,
  * Outputs: dI [T][n] = dL/dI_t (written), dCm [N] = dL/dC_m summed over the
  * batch (written; nullable), dx0 [n_state][n] (written; nullable).
  * workspace: device scratch of hh_backward_workspace() bytes.
- * Errors: HH_E_UNSUPPORTED for models with synapses; HH_E_SHAPE for T < 1,
- * ckpt_every not a multiple of the register segment (10) nor 1..10. */
+ * Errors: HH_E_UNSUPPORTED for models with synapses or exponential Euler in
+ * V; HH_E_SHAPE for T < 1 or ckpt_every < 1 or a short workspace. */
 int32_t hh_backward(hh_model* m, const float* ckpt, int32_t ckpt_every, const hh_input* in,
                     int32_t T, const float* dL_dlevel, const float* dL_dV, float beta,
                     float* dI, float* dCm, float* dx0, void* workspace, size_t workspace_bytes,
                     void* stream);
+/* The same adjoint over steps [t_lo, t_hi) only, so that work on the
+ * gradients of later steps (dI rows t >= t_hi) can overlap the rest: calls
+ * go from the end backwards over adjacent ranges (t_hi = T first, t_lo = 0
+ * last), on one stream and one workspace, which carries the adjoint and the
+ * dC_m partial sums between them.  t_lo and t_hi are multiples of ckpt_every
+ * (t_hi may be T).  dI rows [t_lo, t_hi) are written; dCm and dx0 only by
+ * the call with t_lo = 0.  hh_backward is the call with (0, T). */
+int32_t hh_backward_part(hh_model* m, const float* ckpt, int32_t ckpt_every, const hh_input* in,
+                         int32_t T, int32_t t_lo, int32_t t_hi, const float* dL_dlevel,
+                         const float* dL_dV, float beta, float* dI, float* dCm, float* dx0,
+                         void* workspace, size_t workspace_bytes, void* stream);
 size_t hh_backward_workspace(const hh_model* m, int32_t ckpt_every);
 
 /* Synchronize `stream` and report the first neuron whose state is not finite
@@ -215,30 +226,33 @@ int32_t hh_proj_forward(const uint16_t* A, const uint16_t* Wt, float* out, int32
  * ignored.  A costs 1/16 of the bf16 input's memory traffic. */
 int32_t hh_proj_forward_bits(const uint32_t* A_bits, int32_t words_per_row, const uint16_t* Wt,
                              float* out, int32_t M, int32_t N, int32_t K, void* stream);
-/* Weight gradient dWt[N][K] (float, written) = dOut^T A, A [M][K] bf16,
- * dOut [M][N] float (split into bf16 high and low parts inside the kernel,
- * so the product keeps ~16 bits of dOut).  The reduction over M is split
- * into partial sums that are added in a fixed order (bit-reproducible);
- * workspace: device scratch of hh_proj_wgrad_workspace(M, N, K) bytes
- * (none for M == 0, where dWt is zeroed). */
-int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t M, int32_t N,
-                      int32_t K, void* workspace, size_t workspace_bytes, void* stream);
+/* Weight gradient dWt[N][K] = dOut^T A (float; written, or added to dWt's
+ * contents when accumulate != 0, so a product over M can be split into
+ * calls over row ranges), A [M][K] bf16, dOut [M][N] float (split into bf16
+ * high and low parts inside the kernel, so the product keeps ~16 bits of
+ * dOut).  The reduction over M is split into partial sums that are added in
+ * a fixed order (bit-reproducible); workspace: device scratch of
+ * hh_proj_wgrad_workspace(M, N, K) bytes (none for M == 0). */
+int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t accumulate,
+                      int32_t M, int32_t N, int32_t K, void* workspace, size_t workspace_bytes,
+                      void* stream);
 size_t hh_proj_wgrad_workspace(int32_t M, int32_t N, int32_t K);
 /* The same weight gradient for a binary A given transposed as bits:
  * At_bits [K][words_per_col] uint32 (device), bit m%32 of word m/32 of row k
  * is A[m][k] in {0, 1}; words_per_col >= ceil(M/32).  Same workspace. */
 int32_t hh_proj_wgrad_bits(const uint32_t* At_bits, int32_t words_per_col, const float* dOut,
-                           float* dWt, int32_t M, int32_t N, int32_t K, void* workspace,
-                           size_t workspace_bytes, void* stream);
+                           float* dWt, int32_t accumulate, int32_t M, int32_t N, int32_t K,
+                           void* workspace, size_t workspace_bytes, void* stream);
 
 /* Linear readout of the mean spike level and cross-entropy loss, forward and
  * backward (the readout layer of the differentiable network, Methods
  * "Training and preprocessing").  r = level / T with level [B][H] the
  * per-neuron count of steps with V >= v_th; logits = r W + bias, W [H][C],
  * bias [C]; loss = mean over b of -log softmax(logits_b)[labels[b]].
- * Writes loss [1], dlevel [B][H] = dL/dlevel, dW [H][C], db [C] and, when
- * non-NULL, logits [B][C].  C <= 32 (else HH_E_UNSUPPORTED).  workspace:
- * hh_readout_ce_workspace(B, C) bytes. */
+ * Writes loss [1], dlevel [B][H] = dL/dr (the gradient with respect to the
+ * rate r, which is what hh_backward's dL_dlevel takes), dW [H][C], db [C]
+ * and, when non-NULL, logits [B][C].  C <= 32 (else HH_E_UNSUPPORTED).
+ * workspace: hh_readout_ce_workspace(B, C) bytes. */
 int32_t hh_readout_ce(const float* level, int32_t T, const float* W, const float* bias,
                       const int32_t* labels, int32_t B, int32_t H, int32_t C, float* loss,
                       float* dlevel, float* dW, float* db, float* logits, void* workspace,

@@ -37,6 +37,10 @@ struct BwdArgs {
   float* dC_part;     // [n]
   float* dx0;         // [ns][n]
   float* sub;         // [ceil(S/R)][ns][n]
+  float* lam;         // [1 + NG][n]: the adjoint carried between partial calls
+  int32_t j_lo, j_hi; // checkpoint segments [j_lo, j_hi) of this call, in reverse
+  int32_t first;      // no later segment: lambda and dC start at zero
+  int32_t last;       // segment 0 included: write dx0
   int64_t n, N;
   const float* cm;
   const float* coef;
@@ -135,15 +139,22 @@ __global__ __launch_bounds__(256) void k_bptt(KModel M, BwdArgs A) {
   const float C = A.cm ? A.cm[pidx] : M.C;
   const float dtC = M.dt / C;
 
+  // adjoint at the end of this call's range: zero at T, else left by the
+  // call for the later segments
   float lamV = 0.0f, lamP[ng1<NG>];
 #pragma unroll
   for (int g = 0; g < NG; ++g) lamP[g] = 0.0f;
   float dc = 0.0f;
-  const int nseg = (A.T + A.S - 1) / A.S;
+  if (!A.first) {
+    lamV = A.lam[i];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) lamP[g] = A.lam[(int64_t)(1 + g) * n + i];
+    dc = A.dC_part[i];
+  }
   // the loss term on the level, per step: dL/dlevel / T
   const float dlv = A.dlevel ? A.dlevel[i] * A.inv_T : 0.0f;
 
-  for (int j = nseg - 1; j >= 0; --j) {
+  for (int j = A.j_hi - 1; j >= A.j_lo; --j) {
     const int ta = j * A.S, tb = min(ta + A.S, A.T);
     const float* ck = A.ckpt + (int64_t)j * ns * n;
     const int nwin = (tb - ta + kWin - 1) / kWin;
@@ -214,6 +225,12 @@ __global__ __launch_bounds__(256) void k_bptt(KModel M, BwdArgs A) {
     }
   }
   A.dC_part[i] = dc;
+  if (!A.last) {
+    A.lam[i] = lamV;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) A.lam[(int64_t)(1 + g) * n + i] = lamP[g];
+    return;
+  }
   if (A.dx0) {
     A.dx0[i] = lamV;
 #pragma unroll
@@ -267,16 +284,21 @@ extern "C" {
 size_t hh_backward_workspace(const hh_model* m, int32_t ckpt_every) {
   if (!m || ckpt_every < 1) return 0;
   const size_t part = (((size_t)m->n * sizeof(float)) + 255) & ~(size_t)255;
-  return part + sub_bytes(m, ckpt_every);
+  const size_t lam = ((((size_t)(1 + m->km.n_gates) * m->n * sizeof(float)) + 255) & ~(size_t)255);
+  return part + lam + sub_bytes(m, ckpt_every);
 }
 
-int32_t hh_backward(hh_model* m, const float* ckpt, int32_t ckpt_every, const hh_input* in,
-                    int32_t T, const float* dL_dlevel, const float* dL_dV, float beta, float* dI,
-                    float* dCm, float* dx0, void* workspace, size_t workspace_bytes, void* stream) {
+int32_t hh_backward_part(hh_model* m, const float* ckpt, int32_t ckpt_every, const hh_input* in,
+                         int32_t T, int32_t t_lo, int32_t t_hi, const float* dL_dlevel,
+                         const float* dL_dV, float beta, float* dI, float* dCm, float* dx0,
+                         void* workspace, size_t workspace_bytes, void* stream) {
   if (!m || !ckpt || !in || !dI) return HH_E_INVALID;
   if (m->km.has_syn || m->km.v_method != HH_V_FE) return HH_E_UNSUPPORTED;
   if (in->mode != HH_IN_DENSE || !in->i_dense) return HH_E_INVALID;
   if (T < 1 || ckpt_every < 1) return HH_E_SHAPE;
+  if (t_lo < 0 || t_hi > T || t_lo >= t_hi || t_lo % ckpt_every != 0 ||
+      (t_hi != T && t_hi % ckpt_every != 0))
+    return HH_E_SHAPE;
   if (!(beta > 0.0f)) return HH_E_INVALID;
   const size_t need = hh_backward_workspace(m, ckpt_every);
   if (!workspace || workspace_bytes < need) return HH_E_SHAPE;
@@ -291,9 +313,16 @@ int32_t hh_backward(hh_model* m, const float* ckpt, int32_t ckpt_every, const hh
   a.beta = beta;
   a.inv_T = 1.0f / (float)T;
   a.dI = dI;
+  const size_t part = (((size_t)m->n * sizeof(float)) + 255) & ~(size_t)255;
+  const size_t lam = ((((size_t)(1 + m->km.n_gates) * m->n * sizeof(float)) + 255) & ~(size_t)255);
   a.dC_part = (float*)workspace;
+  a.lam = (float*)((char*)workspace + part);
+  a.sub = (float*)((char*)workspace + part + lam);
   a.dx0 = dx0;
-  a.sub = (float*)((char*)workspace + ((((size_t)m->n * sizeof(float)) + 255) & ~(size_t)255));
+  a.j_lo = t_lo / ckpt_every;
+  a.j_hi = (t_hi + ckpt_every - 1) / ckpt_every;
+  a.first = t_hi == T;
+  a.last = t_lo == 0;
   a.n = m->n;
   a.N = m->N;
   a.cm = m->cm;
@@ -317,12 +346,20 @@ int32_t hh_backward(hh_model* m, const float* ckpt, int32_t ckpt_every, const hh
     }
   }
   if (e != hipSuccess) return HH_E_HIP;
-  if (dCm) {
+  if (dCm && a.last) {
     hipLaunchKernelGGL(k_sum_batch, dim3((unsigned)((m->N + SBH - 1) / SBH)), dim3(SBH * SBG), 0,
                        s, a.dC_part, dCm, m->N, m->B);
     if (hipGetLastError() != hipSuccess) return HH_E_HIP;
   }
   return HH_OK;
+}
+
+int32_t hh_backward(hh_model* m, const float* ckpt, int32_t ckpt_every, const hh_input* in,
+                    int32_t T, const float* dL_dlevel, const float* dL_dV, float beta, float* dI,
+                    float* dCm, float* dx0, void* workspace, size_t workspace_bytes, void* stream) {
+  if (T < 1) return HH_E_SHAPE;
+  return hh_backward_part(m, ckpt, ckpt_every, in, T, 0, T, dL_dlevel, dL_dV, beta, dI, dCm, dx0,
+                          workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

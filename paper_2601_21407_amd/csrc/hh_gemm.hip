@@ -297,7 +297,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_wgrad(const uint16_t* __restric
                                                        const uint32_t* __restrict__ Atb, int wpc,
                                                        const float* __restrict__ D,
                                                        float* __restrict__ part, int M, int N,
-                                                       int K, int rows_per_split) {
+                                                       int K, int rows_per_split, int vec4) {
   __shared__ __attribute__((aligned(16))) uint16_t Dh[2][GBN * LDK];  // [n][m]
   __shared__ __attribute__((aligned(16))) uint16_t Dl[2][GBN * LDK];  // [n][m]
   __shared__ __attribute__((aligned(16))) uint16_t At[2][GBK * LDK];  // [k][m]
@@ -310,8 +310,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_wgrad(const uint16_t* __restric
   const int wn = wave >> 1, wk = wave & 1;
   // gather assignment: column c = tid % 128, rows g*16 .. g*16+15 of the slab
   const int c = tid & 127, g = tid >> 7;
-  const bool dv = n0 + c < N, av = k0 + c < K;
-  const float* dcol = D + min(n0 + c, N - 1);
+  const bool av = k0 + c < K;
   const uint16_t* acol = BITS ? nullptr : A + min(k0 + c, K - 1);
 
   f32x16 acc[2][2];
@@ -322,19 +321,36 @@ __global__ __launch_bounds__(256, 2) void k_proj_wgrad(const uint16_t* __restric
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  float dreg[16];
+  // dOut: lane -> columns 4 n4 .. +3 and rows 4 mq .. +3 of the slab (16-byte
+  // loads of one row); A: lane -> column c, rows 16 g .. +15
+  const int n4 = tid & 31, mq = tid >> 5;
+  const int dn0 = n0 + 4 * n4;
+  const bool dfull = vec4 != 0 && dn0 + 3 < N;
+  float dq[4][4];
   uint16_t areg[16];
   uint32_t abits = 0u;
   const uint32_t* bcol = BITS ? Atb + (int64_t)min(k0 + c, K - 1) * wpc : nullptr;
   auto gather = [&](int ms) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int m = ms + g * 16 + e;
+    for (int r = 0; r < 4; ++r) {
+      const int m = ms + 4 * mq + r;
       const bool ok = m < mend;
-      dreg[e] = (ok && dv) ? dcol[(int64_t)m * N] : 0.0f;
-      if (!BITS) areg[e] = (ok && av) ? acol[(int64_t)m * K] : (uint16_t)0;
+      const float* src = D + (int64_t)min(m, M - 1) * N;
+      if (ok && dfull) {
+        const float4 v = *reinterpret_cast<const float4*>(src + dn0);
+        dq[r][0] = v.x; dq[r][1] = v.y; dq[r][2] = v.z; dq[r][3] = v.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dq[r][j] = (ok && dn0 + j < N) ? src[dn0 + j] : 0.0f;
+      }
     }
-    if (BITS) {
+    if (!BITS) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int m = ms + g * 16 + e;
+        areg[e] = (m < mend && av) ? acol[(int64_t)m * K] : (uint16_t)0;
+      }
+    } else {
       // rows ms + 16 g .. + 15: half (g) of word ms / 32 (ms is a multiple
       // of 32); rows at or past mend belong to the next split
       const int m = ms + g * 16;
@@ -345,25 +361,30 @@ __global__ __launch_bounds__(256, 2) void k_proj_wgrad(const uint16_t* __restric
     }
   };
   auto stash = [&](int buf) {
-    uint32_t h[8], l[8], a[8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t h[2], l[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const float x0 = dq[2 * q][j], x1 = dq[2 * q + 1][j];
+        const uint16_t h0 = f2bf(x0), h1 = f2bf(x1);
+        const uint16_t l0 = f2bf(x0 - bf2f(h0)), l1 = f2bf(x1 - bf2f(h1));
+        h[q] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+        l[q] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+      }
+      const int off = (4 * n4 + j) * LDK + 4 * mq;
+      *reinterpret_cast<uint2*>(&Dh[buf][off]) = make_uint2(h[0], h[1]);
+      *reinterpret_cast<uint2*>(&Dl[buf][off]) = make_uint2(l[0], l[1]);
+    }
+    uint32_t a[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const uint16_t h0 = f2bf(dreg[2 * e]), h1 = f2bf(dreg[2 * e + 1]);
-      const uint16_t l0 = f2bf(dreg[2 * e] - bf2f(h0)), l1 = f2bf(dreg[2 * e + 1] - bf2f(h1));
-      h[e] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-      l[e] = (uint32_t)l0 | ((uint32_t)l1 << 16);
       if (BITS)
         a[e] = ((abits >> (2 * e)) & 1u) * 0x3F80u + ((abits >> (2 * e + 1)) & 1u) * 0x3F800000u;
       else
         a[e] = (uint32_t)areg[2 * e] | ((uint32_t)areg[2 * e + 1] << 16);
     }
-    uint4* ph = reinterpret_cast<uint4*>(&Dh[buf][c * LDK + g * 16]);
-    uint4* pl = reinterpret_cast<uint4*>(&Dl[buf][c * LDK + g * 16]);
     uint4* pa = reinterpret_cast<uint4*>(&At[buf][c * LDK + g * 16]);
-    ph[0] = make_uint4(h[0], h[1], h[2], h[3]);
-    ph[1] = make_uint4(h[4], h[5], h[6], h[7]);
-    pl[0] = make_uint4(l[0], l[1], l[2], l[3]);
-    pl[1] = make_uint4(l[4], l[5], l[6], l[7]);
     pa[0] = make_uint4(a[0], a[1], a[2], a[3]);
     pa[1] = make_uint4(a[4], a[5], a[6], a[7]);
   };
@@ -422,15 +443,16 @@ hipError_t fill_zero(float* p, int64_t count, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Sum of the split partials in a fixed order (deterministic).
+// Sum of the split partials in a fixed order (deterministic); with
+// `accumulate` the sum is added to what out holds.
 __global__ __launch_bounds__(256) void k_sum_splits(const float* __restrict__ part,
                                                     float* __restrict__ out, int64_t count,
-                                                    int splits) {
+                                                    int splits, int accumulate) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= count) return;
   float s = 0.0f;
   for (int q = 0; q < splits; ++q) s += part[(int64_t)q * count + i];
-  out[i] = s;
+  out[i] = accumulate ? out[i] + s : s;
 }
 
 int wgrad_splits(int M) {
@@ -479,13 +501,17 @@ size_t hh_proj_wgrad_workspace(int32_t M, int32_t N, int32_t K) {
   return (size_t)wgrad_splits(M) * (size_t)K * (size_t)N * sizeof(float);
 }
 
-int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t M, int32_t N,
-                      int32_t K, void* workspace, size_t workspace_bytes, void* stream) {
+int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t accumulate,
+                      int32_t M, int32_t N, int32_t K, void* workspace, size_t workspace_bytes,
+                      void* stream) {
   if (M < 0 || N < 0 || K < 0) return HH_E_SHAPE;
   if (N == 0 || K == 0) return HH_OK;
   if (!dWt || (M > 0 && (!A || !dOut))) return HH_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
-  if (M == 0) return fill_zero(dWt, (int64_t)N * K, s) == hipSuccess ? HH_OK : HH_E_HIP;
+  if (M == 0) {
+    if (accumulate) return HH_OK;
+    return fill_zero(dWt, (int64_t)N * K, s) == hipSuccess ? HH_OK : HH_E_HIP;
+  }
   const size_t need = hh_proj_wgrad_workspace(M, N, K);
   if (!workspace || workspace_bytes < need) return HH_E_SHAPE;
   const int splits = wgrad_splits(M);
@@ -493,23 +519,27 @@ int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t 
   rows = (rows + SK - 1) / SK * SK;
   const int tiles = ((K + GBK - 1) / GBK) * ((N + GBN - 1) / GBN);
   float* part = (float*)workspace;
+  const int vec4 = (N % 4 == 0) && ((uintptr_t)dOut % 16 == 0);
   hipLaunchKernelGGL(k_proj_wgrad<false>, dim3(tiles, splits), dim3(256), 0, s, A, nullptr, 0, dOut,
-                     part, M, N, K, rows);
+                     part, M, N, K, rows, vec4);
   const int64_t count = (int64_t)K * N;
   hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, part,
-                     dWt, count, splits);
+                     dWt, count, splits, accumulate ? 1 : 0);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 
 int32_t hh_proj_wgrad_bits(const uint32_t* At_bits, int32_t words_per_col, const float* dOut,
-                           float* dWt, int32_t M, int32_t N, int32_t K, void* workspace,
-                           size_t workspace_bytes, void* stream) {
+                           float* dWt, int32_t accumulate, int32_t M, int32_t N, int32_t K,
+                           void* workspace, size_t workspace_bytes, void* stream) {
   if (M < 0 || N < 0 || K < 0) return HH_E_SHAPE;
   if (N == 0 || K == 0) return HH_OK;
   if (!dWt || (M > 0 && (!At_bits || !dOut))) return HH_E_INVALID;
   if (words_per_col < (M + 31) / 32) return HH_E_SHAPE;
   hipStream_t s = (hipStream_t)stream;
-  if (M == 0) return fill_zero(dWt, (int64_t)N * K, s) == hipSuccess ? HH_OK : HH_E_HIP;
+  if (M == 0) {
+    if (accumulate) return HH_OK;
+    return fill_zero(dWt, (int64_t)N * K, s) == hipSuccess ? HH_OK : HH_E_HIP;
+  }
   const size_t need = hh_proj_wgrad_workspace(M, N, K);
   if (!workspace || workspace_bytes < need) return HH_E_SHAPE;
   const int splits = wgrad_splits(M);
@@ -517,11 +547,12 @@ int32_t hh_proj_wgrad_bits(const uint32_t* At_bits, int32_t words_per_col, const
   rows = (rows + SK - 1) / SK * SK;
   const int tiles = ((K + GBK - 1) / GBK) * ((N + GBN - 1) / GBN);
   float* part = (float*)workspace;
+  const int vec4 = (N % 4 == 0) && ((uintptr_t)dOut % 16 == 0);
   hipLaunchKernelGGL(k_proj_wgrad<true>, dim3(tiles, splits), dim3(256), 0, s, nullptr, At_bits,
-                     words_per_col, dOut, part, M, N, K, rows);
+                     words_per_col, dOut, part, M, N, K, rows, vec4);
   const int64_t count = (int64_t)K * N;
   hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, part,
-                     dWt, count, splits);
+                     dWt, count, splits, accumulate ? 1 : 0);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 

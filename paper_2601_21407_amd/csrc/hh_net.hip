@@ -136,7 +136,7 @@ __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
                                              const int64_t* s_r0, const int* s_pre, int cnt,
                                              int total, unsigned long long* acc_e,
                                              unsigned long long* acc_i) {
-  constexpr int U = 8;
+  constexpr int U = 16;
   const int B = blockDim.x;
   for (int x0 = threadIdx.x; x0 < total; x0 += U * B) {
     int32_t tg[U];
@@ -168,6 +168,67 @@ __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
       }
     }
   }
+}
+
+// One step of neuron_step's arithmetic, reordered so that the previous
+// step's synaptic arrivals (read-and-clear atomics issued by the caller) are
+// needed only after the gates: the gate update, which reads V and the old
+// gates only, hides the atomics' latency.  Same operations as neuron_step,
+// so the same results.
+template <class S>
+__device__ __forceinline__ void net_update(const KModel& M, const LaneRates<S::kNG>& L, float dtC,
+                                           float& vh, float& vl, float (&p)[ng1<S::kNG>],
+                                           float I, float& ge, float& gi,
+                                           unsigned long long ae, unsigned long long ai) {
+  constexpr int NG = S::kNG;
+  const float V = vh;
+  float po[ng1<NG>];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) po[g] = p[g];
+  // gates by exponential Euler at V_t
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const float r0 = rate_eval<false>(S::form(M, g, 0), L.r[g][0], V, nullptr);
+    const float r1 = rate_eval<false>(S::form(M, g, 1), L.r[g][1], V, nullptr);
+    float pinf, e;
+    if (S::kind(M, g) == KIND_AB) {
+      const float sr = r0 + r1;
+      pinf = r0 * rcp(sr);
+      e = ex2(sr * M.kdt);
+    } else {
+      pinf = r0;
+      e = ex2(r1 * M.kdt);
+    }
+    p[g] = fmaf(p[g] - pinf, e, pinf);
+  }
+  // arrivals of the previous step's spikes
+  ge += (float)ae * kUnfix;
+  gi += (float)ai * kUnfix;
+  // channel terms at the start-of-step gates
+  float gsum = ge + gi;
+  float esum = fmaf(ge, M.E_e, gi * M.E_i);
+#pragma unroll
+  for (int c = 0; c < kMaxCh; ++c) {
+    if (c >= S::nch(M)) break;
+    float eta = M.gbar[c];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int e = S::cexp(M, c, g);
+      if (e) eta *= ipow(po[g], e);
+    }
+    gsum += eta;
+    esum = fmaf(eta, M.E[c], esum);
+  }
+  // membrane
+  float dv;
+  if (M.v_method == VFE) {
+    const float iion = fmaf(gsum, vl, fmaf(gsum, V, -esum));
+    dv = dtC * (I - iion);
+  } else {
+    const float vinf = (I + esum) * rcp(gsum);
+    dv = ((V - vinf) + vl) * expm1_neg(gsum * dtC);
+  }
+  add_to_v(vh, vl, dv);
 }
 
 template <class S>
@@ -202,11 +263,19 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   // block's scatter without another dependent load
   const int64_t my_r0 = A.row_ptr[ii];
   const int my_len = (int)(A.row_ptr[ii + 1] - my_r0);
+  int done = 0;  // steps whose barrier completed
 
   for (int k = 0; k < A.nsteps; ++k) {
     const int64_t t = A.t0 + k;
     const float V = vh;
-    neuron_step<S>(M, L, dtC, vh, vl, p, I, ge, gi);
+    // arrivals scattered during the previous step of this launch
+    unsigned long long ae = 0ull, ai = 0ull;
+    if (k > 0 && act) {
+      unsigned long long* pe = A.acc + (int64_t)((k - 1) & 1) * 2 * n;
+      ae = atomicExch(&pe[i], 0ull);
+      ai = atomicExch(&pe[n + i], 0ull);
+    }
+    net_update<S>(M, L, dtC, vh, vl, p, I, ge, gi, ae, ai);
     const bool spk = act && (V < M.v_th) && (vh >= M.v_th);
     ge *= M.decay_e;
     gi *= M.decay_i;
@@ -244,13 +313,13 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
     }
 
     if (!grid_barrier(A.bar, gridDim.x, gen, A.spin_limit, A.flags, &s_ok)) break;
-
-    if (act) {
-      const unsigned long long ae = atomicExch(&acc_e[i], 0ull);
-      const unsigned long long ai = atomicExch(&acc_i[i], 0ull);
-      ge += (float)ae * kUnfix;
-      gi += (float)ai * kUnfix;
-    }
+    done = k + 1;
+  }
+  // the last step's arrivals
+  if (done > 0 && act) {
+    unsigned long long* pe = A.acc + (int64_t)((done - 1) & 1) * 2 * n;
+    ge += (float)atomicExch(&pe[i], 0ull) * kUnfix;
+    gi += (float)atomicExch(&pe[n + i], 0ull) * kUnfix;
   }
 
   if (!act) return;

@@ -14,7 +14,7 @@ namespace {
 constexpr int kMaxC = 32;
 
 // One block per batch row: logits, softmax, per-row loss, dz = (p - y) / B
-// and dL/dlevel for the row.
+// and dL/dr for the row (r = level / T, the rate hh_backward differentiates).
 __global__ __launch_bounds__(256) void k_readout_row(const float* __restrict__ level, float invT,
                                                      const float* __restrict__ W,
                                                      const float* __restrict__ bias,
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_readout_row(const float* __restrict__ l
   for (int h = tid; h < H; h += blockDim.x) {
     float s = 0.0f;
     for (int c = 0; c < C; ++c) s = fmaf(s_dz[c], W[(int64_t)h * C + c], s);
-    dlevel[(int64_t)b * H + h] = s * invT;
+    dlevel[(int64_t)b * H + h] = s;  // dL/dr, r = level / T
   }
 }
 

@@ -83,13 +83,15 @@ def _load():
         "hh_set_external": ([vp, vp, u32, f32, u64], i32),
         "hh_syn_propagate": ([vp, vp, vp, vp, vp], i32),
         "hh_backward": ([vp, vp, i32, P(Input), i32, vp, vp, f32, vp, vp, vp, vp, sz, vp], i32),
+        "hh_backward_part": ([vp, vp, i32, P(Input), i32, i32, i32, vp, vp, f32, vp, vp, vp, vp, sz,
+                              vp], i32),
         "hh_backward_workspace": ([vp, i32], sz),
         "hh_check": ([vp, P(i64), vp], i32),
         "hh_proj_forward": ([vp, vp, vp, i32, i32, i32, vp], i32),
         "hh_proj_forward_bits": ([vp, i32, vp, vp, i32, i32, i32, vp], i32),
-        "hh_proj_wgrad": ([vp, vp, vp, i32, i32, i32, vp, sz, vp], i32),
+        "hh_proj_wgrad": ([vp, vp, vp, i32, i32, i32, i32, vp, sz, vp], i32),
         "hh_proj_wgrad_workspace": ([i32, i32, i32], sz),
-        "hh_proj_wgrad_bits": ([vp, i32, vp, vp, i32, i32, i32, vp, sz, vp], i32),
+        "hh_proj_wgrad_bits": ([vp, i32, vp, vp, i32, i32, i32, i32, vp, sz, vp], i32),
         "hh_readout_ce": ([vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "hh_readout_ce_workspace": ([i32, i32], sz),
         "hh_adam_step": ([vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp], i32),
@@ -120,7 +122,8 @@ def exported_symbols():
     return [n for n in ("hh_init", "hh_destroy", "hh_status_string", "hh_n_state", "hh_set_fusion",
                         "hh_set_specialize",
                         "hh_init_state", "hh_step_n", "hh_attach_csr", "hh_set_external",
-                        "hh_syn_propagate", "hh_backward", "hh_backward_workspace", "hh_check",
+                        "hh_syn_propagate", "hh_backward", "hh_backward_part",
+                        "hh_backward_workspace", "hh_check",
                         "hh_proj_forward", "hh_proj_forward_bits", "hh_proj_wgrad",
                         "hh_proj_wgrad_workspace", "hh_proj_wgrad_bits",
                         "hh_readout_ce", "hh_readout_ce_workspace", "hh_adam_step",
@@ -255,6 +258,20 @@ class Model:
                             _ptr(dL_dlevel), _ptr(dL_dV), float(beta), _ptr(dI), _ptr(dCm),
                             _ptr(dx0), _ptr(workspace), ws_bytes, _stream()), "hh_backward")
 
+    def backward_part(self, ckpt, ckpt_every: int, i_dense, T: int, t_lo: int, t_hi: int, dI, *,
+                      workspace, dL_dlevel=None, dL_dV=None, beta: float = 0.2, dCm=None,
+                      dx0=None):
+        """The adjoint over steps [t_lo, t_hi) (see hh_backward_part); calls go
+        backwards over adjacent ranges and share `workspace`."""
+        inp = Input()
+        inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
+        ws_bytes = self.backward_workspace(ckpt_every)
+        assert workspace.numel() * workspace.element_size() >= ws_bytes
+        _ok(lib.hh_backward_part(self.h, _ptr(ckpt), int(ckpt_every), ctypes.byref(inp), int(T),
+                                 int(t_lo), int(t_hi), _ptr(dL_dlevel), _ptr(dL_dV), float(beta),
+                                 _ptr(dI), _ptr(dCm), _ptr(dx0), _ptr(workspace), ws_bytes,
+                                 _stream()), "hh_backward_part")
+
     def check(self):
         """Synchronizes; returns (status, first_bad_index)."""
         fb = ctypes.c_int64(-1)
@@ -309,8 +326,8 @@ def proj_forward_bits(A_bits, K: int, Wt_bf16, out):
     return out
 
 
-def proj_wgrad(A_bf16, dOut, dWt, workspace=None):
-    """dWt [N][K] = dOut [M][N]^T . A [M][K]."""
+def proj_wgrad(A_bf16, dOut, dWt, workspace=None, accumulate=False):
+    """dWt [N][K] = dOut [M][N]^T . A [M][K] (added to dWt with accumulate)."""
     M, K = A_bf16.shape
     N = dOut.shape[1]
     assert A_bf16.dtype == torch.bfloat16 and dOut.dtype == torch.float32
@@ -319,25 +336,31 @@ def proj_wgrad(A_bf16, dOut, dWt, workspace=None):
     need = int(lib.hh_proj_wgrad_workspace(M, N, K))
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dWt.device)
-    _ok(lib.hh_proj_wgrad(_ptr(A_bf16), _ptr(dOut), _ptr(dWt), M, N, K, _ptr(workspace),
+    _ok(lib.hh_proj_wgrad(_ptr(A_bf16), _ptr(dOut), _ptr(dWt), 1 if accumulate else 0, M, N, K,
+                          _ptr(workspace),
                           workspace.numel() * workspace.element_size(), _stream()), "hh_proj_wgrad")
     return dWt
 
 
-def proj_wgrad_bits(At_bits, M: int, dOut, dWt, workspace=None):
+def proj_wgrad_bits(At_bits, M: int, dOut, dWt, workspace=None, accumulate=False, m0: int = 0):
     """dWt [N][K] = dOut [M][N]^T . A for a binary A given transposed as
-    bits: At_bits int32 [K][words], bit m%32 of word m/32 = A[m][k]."""
+    bits: At_bits int32 [K][words], bit m%32 of word m/32 = A[m][k].  With
+    m0 (a multiple of 32) the product covers rows m0 .. m0 + M - 1 of A, and
+    dOut holds just those rows; accumulate adds to dWt."""
     K, wpc = At_bits.shape
     N = dOut.shape[1]
     assert At_bits.dtype == torch.int32 and dOut.dtype == torch.float32
     assert tuple(dWt.shape) == (N, K) and dWt.dtype == torch.float32 and dOut.shape[0] == M
     assert At_bits.is_contiguous() and dOut.is_contiguous() and dWt.is_contiguous()
+    assert m0 % 32 == 0 and (m0 + M + 31) // 32 <= wpc
     need = int(lib.hh_proj_wgrad_workspace(M, N, K))
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dWt.device)
-    _ok(lib.hh_proj_wgrad_bits(_ptr(At_bits), int(wpc), _ptr(dOut), _ptr(dWt), int(M), N, K,
-                               _ptr(workspace), workspace.numel() * workspace.element_size(),
-                               _stream()), "hh_proj_wgrad_bits")
+    base = ctypes.c_void_p(At_bits.data_ptr() + (m0 // 32) * 4) if At_bits.numel() else None
+    _ok(lib.hh_proj_wgrad_bits(base, int(wpc), _ptr(dOut), _ptr(dWt), 1 if accumulate else 0,
+                               int(M), N, K, _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), _stream()),
+        "hh_proj_wgrad_bits")
     return dWt
 
 

@@ -277,7 +277,8 @@ def test_readout_ce_against_oracle():
     L, dr, gW, gb, z = O.readout_ce(level.astype(np.float64) / T, Wo, b, lab)
     assert abs(loss.item() - L) <= 1e-5 * abs(L)
     assert np.allclose(logits.cpu().numpy(), z, rtol=1e-5, atol=1e-6)
-    assert np.allclose(dl.cpu().numpy(), dr / T, rtol=1e-4, atol=1e-9)
+    # dL/dr, the rate gradient the adjoint takes
+    assert np.allclose(dl.cpu().numpy(), dr, rtol=1e-4, atol=1e-9)
     assert np.allclose(dW.cpu().numpy(), gW, rtol=1e-4, atol=1e-8)
     assert np.allclose(db.cpu().numpy(), gb, rtol=1e-4, atol=1e-8)
 
