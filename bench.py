@@ -348,34 +348,103 @@ def bench_layer(reps=5, ckpt_every=50):
         hh.readout_ce(lv, T, wout, bo, lab, dl, dWo, db, loss)
         mark("f3")
 
-    def backward(step):
+    def adam(step):
+        for k, (p, g) in (("win", (win32, dWin)), ("cm", (cm, dC)), ("wout", (wout, dWo)),
+                          ("b", (bo, db))):
+            hh.adam_step(p, g, opt[k][0], opt[k][1], step, 1e-3,
+                         param_bf16=win16 if k == "win" else None)
+
+    def backward(step, apply=True):
         M.backward(ck, ckpt_every, I, T, dI, dL_dlevel=dl.view(-1), beta=0.2, dCm=dC,
                    workspace=ws_b)
         mark("b1")
         hh.proj_wgrad_bits(SbitsT, T * B, dI.view(T * B, H), dWin, workspace=ws_w)
         mark("b2")
-        for k, (p, g) in (("win", (win32, dWin)), ("cm", (cm, dC)), ("wout", (wout, dWo)),
-                          ("b", (bo, db))):
-            hh.adam_step(p, g, opt[k][0], opt[k][1], step, 1e-3,
-                         param_bf16=win16 if k == "win" else None)
+        if apply:
+            adam(step)
         mark("b3")
 
+    # The same step with the MFMA products on a second stream, one checkpoint
+    # segment at a time, so they overlap the latency-bound neuron kernels:
+    # the forward product of segment c+1 runs while the neurons integrate
+    # segment c, and the weight gradient of a segment runs while the adjoint
+    # works through the earlier ones.
+    aux = torch.cuda.Stream()  # default priority
+    nchunk = (T + ckpt_every - 1) // ckpt_every
+    bounds = [(c * ckpt_every, min(T, (c + 1) * ckpt_every)) for c in range(nchunk)]
+    ws_w2 = torch.empty(int(hh.lib.hh_proj_wgrad_workspace(ckpt_every * B, H, n_in)),
+                        dtype=torch.uint8, device=dev)
+
+    def forward_overlap():
+        main = torch.cuda.current_stream()
+        aux.wait_stream(main)  # the weights of the previous update
+        evs = []
+        with torch.cuda.stream(aux):
+            for a, b in bounds:
+                hh.proj_forward_bits(Sbits[a * B:b * B], n_in, win16, I[a * B:b * B])
+                e = torch.cuda.Event()
+                e.record(aux)
+                evs.append(e)
+        M.init_state(st, v0_scalar=-65.0)
+        lv.zero_()
+        for c, (a, b) in enumerate(bounds):
+            main.wait_event(evs[c])
+            M.step_n(st, b - a, a, i_dense=I[a * B:], ckpt=ck[c:], ckpt_every=ckpt_every,
+                     level=lv.view(-1))
+        hh.readout_ce(lv, T, wout, bo, lab, dl, dWo, db, loss)
+
+    def backward_overlap(step, apply=True):
+        main = torch.cuda.current_stream()
+        dIf = dI.view(T * B, H)
+        for c in reversed(range(nchunk)):
+            a, b = bounds[c]
+            M.backward_part(ck, ckpt_every, I, T, a, b, dI, workspace=ws_b,
+                            dL_dlevel=dl.view(-1), beta=0.2, dCm=dC)
+            e = torch.cuda.Event()
+            e.record(main)
+            aux.wait_event(e)
+            with torch.cuda.stream(aux):
+                hh.proj_wgrad_bits(SbitsT, (b - a) * B, dIf[a * B:b * B], dWin, workspace=ws_w2,
+                                   accumulate=c != nchunk - 1, m0=a * B)
+        main.wait_stream(aux)
+        if apply:
+            adam(step)
+
+    def timed(fn_fwd, fn_bwd):
+        fn_fwd()
+        fn_bwd(1)
+        _sync()
+        ev.clear()
+        t0 = time.perf_counter()
+        for r in range(reps):
+            fn_fwd()
+        _sync()
+        tf = (time.perf_counter() - t0) / reps
+        ev.clear()
+        t0 = time.perf_counter()
+        for r in range(reps):
+            fn_fwd()
+            fn_bwd(r + 2)
+        _sync()
+        return tf, (time.perf_counter() - t0) / reps
+
+    # both orders of work give the same gradients (the weight gradient's sum
+    # is split differently: rounding only)
+    forward_overlap()
+    backward_overlap(0, apply=False)
+    _sync()
+    g_ov = [x.clone() for x in (dWin, dC, dWo, db, dl)]
     forward()
-    backward(1)
+    backward(0, apply=False)
     _sync()
-    ev.clear()
-    t0 = time.perf_counter()
-    for r in range(reps):
-        forward()
-    _sync()
-    t_fwd = (time.perf_counter() - t0) / reps
-    ev.clear()
-    t0 = time.perf_counter()
-    for r in range(reps):
-        forward()
-        backward(r + 2)
-    _sync()
-    t_fb = (time.perf_counter() - t0) / reps
+    g_1s = [dWin, dC, dWo, db, dl]
+    same_exact = all(torch.equal(a, b) for a, b in zip(g_ov[1:], g_1s[1:]))
+    rel_w = float((g_ov[0] - g_1s[0]).abs().max() / g_1s[0].abs().max().clamp_min(1e-30))
+    if not same_exact or rel_w > 1e-5:
+        raise RuntimeError("overlapped layer step disagrees: exact %s, dW rel %.2e"
+                           % (same_exact, rel_w))
+    t_fwd_ov, t_fb_ov = timed(forward_overlap, backward_overlap)
+    t_fwd, t_fb = timed(forward, backward)  # one stream; also gives the per-kernel times
 
     def seg(a, b):
         return float(np.mean([x.elapsed_time(y) for x, y in zip(ev[a], ev[b])]))
@@ -387,6 +456,11 @@ def bench_layer(reps=5, ckpt_every=50):
     return {"batch": B, "hidden": H, "inputs": n_in, "T": T, "ckpt_every": ckpt_every,
             "fwd_ms": t_fwd * 1e3, "fwd_bwd_ms": t_fb * 1e3,
             "fwd_updates_per_s": upd / t_fwd, "fwd_bwd_updates_per_s": upd / t_fb,
+            # the same step with the products on a second stream, segment by
+            # segment (measured slower: matrix and vector work on shared SIMDs
+            # do not overlap, and the smaller products fill the chip less)
+            "two_streams": {"fwd_ms": t_fwd_ov * 1e3, "fwd_bwd_ms": t_fb_ov * 1e3},
+            "overlap_check": {"dCm_dWout_db_dlevel_identical": same_exact, "dWin_max_rel_diff": rel_w},
             "kernel_ms": parts_ms, "loss": float(loss.item()),
             "projection_TFLOPs": gflop / parts_ms["projection"],
             "wgrad_TFLOPs": 2 * gflop / parts_ms["proj_wgrad"]}

@@ -258,6 +258,62 @@ def test_adjoint_checkpoint_strides_agree():
         assert np.max(np.abs(o - outs[0])) <= 1e-6 * np.max(np.abs(outs[0]))
 
 
+def test_adjoint_in_parts_equals_whole():
+    """hh_backward_part over adjacent ranges, from the end backwards, gives
+    the single call's dI, dC_m and dx0 bit for bit (the adjoint and the dC_m
+    partials carried in the workspace)."""
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    m, I, cm, v0, rng = _bwd_case(n=300, T=130, seed=9, B=3)
+    dlevel = rng.standard_normal(300).astype(np.float32)
+    dV = (0.01 * rng.standard_normal(I.shape)).astype(np.float32)
+    dI, dC, dx0, _, _ = _gpu_bwd(m, I, cm, v0, 20, dlevel=dlevel, dV=dV, B=3)
+    T, n = I.shape
+    M = hh.Model(m, n // 3, 3, cm=torch.tensor(cm, device="cuda"))
+    st = M.new_state()
+    M.init_state(st, v0=torch.tensor(v0, device="cuda"))
+    ck = torch.zeros(((T + 19) // 20, M.n_state, n), device="cuda")
+    It = torch.tensor(I, device="cuda")
+    M.step_n(st, T, i_dense=It, ckpt=ck, ckpt_every=20)
+    dI2 = torch.zeros((T, n), device="cuda")
+    dC2 = torch.zeros(n // 3, device="cuda")
+    dx02 = torch.zeros((M.n_state, n), device="cuda")
+    ws = torch.empty(M.backward_workspace(20), dtype=torch.uint8, device="cuda")
+    kw = dict(workspace=ws, dL_dlevel=torch.tensor(dlevel, device="cuda"),
+              dL_dV=torch.tensor(dV, device="cuda"), dCm=dC2, dx0=dx02)
+    for lo, hi in ((120, 130), (60, 120), (40, 60), (0, 40)):
+        M.backward_part(ck, 20, It, T, lo, hi, dI2, **kw)
+    assert M.check()[0] == 0
+    assert np.array_equal(dI2.cpu().numpy(), dI)
+    assert np.array_equal(dC2.cpu().numpy(), dC)
+    assert np.array_equal(dx02.cpu().numpy(), dx0)
+    # ranges that are not segment aligned are refused
+    with pytest.raises(hh.HHError):
+        M.backward_part(ck, 20, It, T, 10, 130, dI2, **kw)
+
+
+def test_weight_gradient_accumulates_over_row_ranges():
+    """The spike-input weight gradient over row ranges with accumulate equals
+    one call over all rows (to rounding: the split of the sum differs)."""
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    rng = np.random.default_rng(12)
+    M, N, K = 3000, 300, 100
+    A = (rng.random((M, K)) < 0.1).astype(np.float32)
+    dO = rng.standard_normal((M, N)).astype(np.float32)
+    bT = torch.tensor(W.pack_bits(A.T), device="cuda")
+    dOt = torch.tensor(dO, device="cuda")
+    whole = torch.empty((N, K), device="cuda")
+    hh.proj_wgrad_bits(bT, M, dOt, whole)
+    acc = torch.full((N, K), 123.0, device="cuda")
+    for i, (lo, hi) in enumerate(((2048, 3000), (1024, 2048), (0, 1024))):
+        hh.proj_wgrad_bits(bT, hi - lo, dOt[lo:hi].contiguous(), acc, accumulate=i > 0, m0=lo)
+    ref = O.projection_weight_grad(A, dO)
+    scw = np.abs(A).T @ np.abs(dO.astype(np.float64))
+    assert np.all(np.abs(acc.cpu().numpy().T - ref) <= 2e-5 * scw + 1e-30)
+    assert np.all(np.abs(acc.cpu().numpy() - whole.cpu().numpy()).T <= 2e-5 * scw + 1e-30)
+
+
 def test_readout_ce_against_oracle():
     torch = need_gpu()
     from paper_2601_21407_amd import hh
