@@ -23,9 +23,9 @@ __global__ __launch_bounds__(256) void k_readout_row(const float* __restrict__ l
                                                      float* __restrict__ row_loss,
                                                      float* __restrict__ dlevel,
                                                      float* __restrict__ logits_out) {
-  __shared__ float red[256][kMaxC + 1];
+  __shared__ float red[4][kMaxC];
   __shared__ float s_dz[kMaxC];
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   float acc[kMaxC];
 #pragma unroll
   for (int c = 0; c < kMaxC; ++c) acc[c] = 0.0f;
@@ -35,18 +35,22 @@ __global__ __launch_bounds__(256) void k_readout_row(const float* __restrict__ l
     for (int c = 0; c < kMaxC; ++c)
       if (c < C) acc[c] = fmaf(r, W[(int64_t)h * C + c], acc[c]);
   }
+  // butterfly sum over the 64 lanes of each wavefront, then the four
+  // wavefront sums in order (a fixed order: deterministic)
 #pragma unroll
-  for (int c = 0; c < kMaxC; ++c) red[tid][c] = acc[c];
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off)
-      for (int c = 0; c < C; ++c) red[tid][c] += red[tid + off][c];
-    __syncthreads();
+  for (int c = 0; c < kMaxC; ++c) {
+    if (c < C) {
+      float v = acc[c];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) red[wv][c] = v;
+    }
   }
+  __syncthreads();
   if (tid == 0) {
     float z[kMaxC], zmax = -INFINITY;
     for (int c = 0; c < C; ++c) {
-      z[c] = red[0][c] + bias[c];
+      z[c] = ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) + bias[c];
       zmax = fmaxf(zmax, z[c]);
     }
     float se = 0.0f;
@@ -70,58 +74,47 @@ __global__ __launch_bounds__(256) void k_readout_row(const float* __restrict__ l
 }
 
 // dW[h][c] = sum_b r[b][h] dz[b][c]; db[c] = sum_b dz[b][c]; loss = mean.
-// A block owns 32 readout rows h; the batch goes through LDS in chunks of
-// 256 rows of dz, whose eight 32-row parts are summed by the block's eight
-// lane groups; the group partials are added in group order.  Block 0 also
-// forms db and the loss.
-constexpr int RW_H = 32, RW_G = 8, RW_CH = 256;
+// Block (x, c) owns readout rows h = 32 x .. 32 x + 31 of class c; its 8
+// lane groups each sum every 8th batch row, and the eight partial sums are
+// added in group order.  Blocks (0, c) also form db[c]; block (0, 0) the
+// loss.
+constexpr int RW_H = 32, RW_G = 8;
 
 __global__ __launch_bounds__(RW_H * RW_G) void k_readout_wgrad(
     const float* __restrict__ level, float invT, const float* __restrict__ dz,
     const float* __restrict__ row_loss, int B, int H, int C, float* __restrict__ dW,
     float* __restrict__ db, float* __restrict__ loss) {
-  __shared__ float s_dz[RW_CH][kMaxC + 1];
-  __shared__ float part[RW_G][RW_H][kMaxC + 1];
+  __shared__ float part[RW_G][RW_H + 1];
+  __shared__ float pdb[RW_H * RW_G];
   const int tid = threadIdx.x, hx = tid % RW_H, g = tid / RW_H;
+  const int c = blockIdx.y;
   const int h = blockIdx.x * RW_H + hx;
-  float acc[kMaxC];
-#pragma unroll
-  for (int c = 0; c < kMaxC; ++c) acc[c] = 0.0f;
-  for (int c0 = 0; c0 < B; c0 += RW_CH) {
-    const int nb = min(RW_CH, B - c0);
-    __syncthreads();  // previous chunk consumed
-    for (int e = tid; e < nb * C; e += blockDim.x) s_dz[e / C][e % C] = dz[(int64_t)c0 * C + e];
-    __syncthreads();
-    const int per = RW_CH / RW_G;
-    const int b0 = g * per, b1 = min(nb, b0 + per);
-    if (h < H) {
-      for (int b = b0; b < b1; ++b) {
-        const float r = level[(int64_t)(c0 + b) * H + h] * invT;
-#pragma unroll
-        for (int c = 0; c < kMaxC; ++c)
-          if (c < C) acc[c] = fmaf(r, s_dz[b][c], acc[c]);
-      }
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < kMaxC; ++c) part[g][hx][c] = acc[c];
+  float acc = 0.0f;
+  if (h < H)
+    for (int b = g; b < B; b += RW_G)
+      acc = fmaf(level[(int64_t)b * H + h] * invT, dz[(int64_t)b * C + c], acc);
+  part[g][hx] = acc;
   __syncthreads();
-  for (int e = tid; e < RW_H * C; e += blockDim.x) {
-    const int hh = e / C, c = e % C;
+  if (g == 0 && h < H) {
     float s = 0.0f;
-    for (int q = 0; q < RW_G; ++q) s += part[q][hh][c];
-    const int hg = blockIdx.x * RW_H + hh;
-    if (hg < H) dW[(int64_t)hg * C + c] = s;
+    for (int q = 0; q < RW_G; ++q) s += part[q][hx];
+    dW[(int64_t)h * C + c] = s;
   }
   if (blockIdx.x == 0) {
-    if (tid < C) {
-      float s = 0.0f;
-      for (int b = 0; b < B; ++b) s += dz[(int64_t)b * C + tid];
-      db[tid] = s;
-    } else if (tid == C) {
-      float s = 0.0f;
-      for (int b = 0; b < B; ++b) s += row_loss[b];
-      *loss = s / (float)B;
+    // db[c]: 256 lanes each sum every 256th row, then lane 0 adds them in order
+    float s = 0.0f;
+    for (int b = tid; b < B; b += RW_H * RW_G) s += dz[(int64_t)b * C + c];
+    pdb[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+      float t = 0.0f;
+      for (int q = 0; q < RW_H * RW_G; ++q) t += pdb[q];
+      db[c] = t;
+      if (c == 0) {
+        float l = 0.0f;
+        for (int b = 0; b < B; ++b) l += row_loss[b];
+        *loss = l / (float)B;
+      }
     }
   }
 }
@@ -170,8 +163,8 @@ int32_t hh_readout_ce(const float* level, int32_t T, const float* W, const float
   const float invT = 1.0f / (float)T;
   hipLaunchKernelGGL(k_readout_row, dim3(B), dim3(256), 0, s, level, invT, W, bias, labels, B, H, C,
                      dz, row_loss, dlevel, logits);
-  hipLaunchKernelGGL(k_readout_wgrad, dim3((unsigned)((H + RW_H - 1) / RW_H)), dim3(RW_H * RW_G), 0,
-                     s, level, invT, dz, row_loss, B, H, C, dW, db, loss);
+  hipLaunchKernelGGL(k_readout_wgrad, dim3((unsigned)((H + RW_H - 1) / RW_H), (unsigned)C),
+                     dim3(RW_H * RW_G), 0, s, level, invT, dz, row_loss, B, H, C, dW, db, loss);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 
