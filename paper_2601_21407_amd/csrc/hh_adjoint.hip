@@ -114,7 +114,7 @@ __device__ __forceinline__ void step_with_jacobian(const KModel& M, const LaneRa
     }
     J.e[g] = e;
     J.dpv[g] = fmaf(dpinf, 1.0f - e, (p[g] - pinf) * de);
-    p[g] = fmaf(p[g] - pinf, e, pinf);
+    p[g] = gate_update(p[g], pinf, e);
   }
   // membrane (explicit Euler)
   const float iion = fmaf(gsum, vl, fmaf(gsum, V, -esum));

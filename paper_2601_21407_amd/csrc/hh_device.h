@@ -238,6 +238,14 @@ __device__ __forceinline__ void add_to_v(float& vh, float& vl, float dv) {
   vh = t;
 }
 
+// Exponential-Euler gate step p' = p_inf + (p - p_inf) e (Methods, "Simplified
+// discretization"), written as p + (p_inf - p)(1 - e): the fused multiply-add then
+// accumulates into p itself, so the loop-carried register needs no copy.  The
+// absolute error of e enters both forms the same way, times |p_inf - p|.
+__device__ __forceinline__ float gate_update(float p, float pinf, float e) {
+  return fmaf(pinf - p, 1.0f - e, p);
+}
+
 // e^{-z} - 1 for z >= 0 without cancellation at small z (series below 0.1,
 // truncation < 2e-9 relative).
 __device__ __forceinline__ float expm1_neg(float z) {
@@ -249,7 +257,9 @@ __device__ __forceinline__ float expm1_neg(float z) {
 // Advance the gates and V by one step (Jacobi: all right-hand sides at the
 // start-of-step state).  p is updated in place; (vh, vl) likewise.
 // I: external current; ge, gi: synaptic conductances held over the step.
-template <class S>
+// SYN = false: the caller knows the population has no synapses (ge = gi = 0);
+// the synaptic terms are left out, which gives bit-identical results.
+template <class S, bool SYN = true>
 __device__ __forceinline__ void neuron_step(const KModel& M, const LaneRates<S::kNG>& L, float dtC,
                                             float& vh, float& vl, float (&p)[ng1<S::kNG>], float I,
                                             float ge, float gi) {
@@ -257,8 +267,11 @@ __device__ __forceinline__ void neuron_step(const KModel& M, const LaneRates<S::
   const float V = vh;
   // channel terms at the start-of-step gates: total conductance gsum and
   // sum of g_X E_X, so that I_ion + I_syn = gsum V - esum
-  float gsum = ge + gi;
-  float esum = fmaf(ge, M.E_e, gi * M.E_i);
+  float gsum = 0.0f, esum = 0.0f;
+  if constexpr (SYN) {
+    gsum = ge + gi;
+    esum = fmaf(ge, M.E_e, gi * M.E_i);
+  }
 #pragma unroll
   for (int c = 0; c < kMaxCh; ++c) {
     if (c >= S::nch(M)) break;
@@ -285,7 +298,7 @@ __device__ __forceinline__ void neuron_step(const KModel& M, const LaneRates<S::
       pinf = r0;
       e = ex2(r1 * M.kdt);
     }
-    p[g] = fmaf(p[g] - pinf, e, pinf);
+    p[g] = gate_update(p[g], pinf, e);
   }
   // membrane
   float dv;

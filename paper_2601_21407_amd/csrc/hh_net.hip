@@ -199,7 +199,7 @@ __device__ __forceinline__ void net_update(const KModel& M, const LaneRates<S::k
       pinf = r0;
       e = ex2(r1 * M.kdt);
     }
-    p[g] = fmaf(p[g] - pinf, e, pinf);
+    p[g] = gate_update(p[g], pinf, e);
   }
   // arrivals of the previous step's spikes
   ge += (float)ae * kUnfix;

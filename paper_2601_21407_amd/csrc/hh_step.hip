@@ -34,12 +34,20 @@ __global__ __launch_bounds__(256) void k_init_state(KModel M, float* __restrict_
   state[(int64_t)(1 + NG + 2 * M.has_syn) * n + i] = 0.0f;  // low part of V
 }
 
-// PF: dense input whose rows are prefetched four steps ahead (the time loop
-// is unrolled by four so the prefetched values stay in registers); used for
-// the built-in channel sets, where a step is short enough that the load
-// latency would otherwise show.
-template <class S, bool JIT, bool PF>
+// Time-loop variants.  LOOP_GEN: one step per iteration, any input mode.
+// LOOP_DENSE: dense input whose rows are prefetched four steps ahead (the
+// loop is unrolled by four so the prefetched values stay in registers).
+// LOOP_NOISE: noise input; the four normals of one Philox block feed four
+// unrolled steps, so nothing is shuffled between registers from step to step.
+// The last two serve the built-in channel sets, where a step is short enough
+// that load latency and register copies would otherwise show.
+// SYN = false: the population is known to have no synapses, and the synaptic
+// terms drop out of the step (bit-identical results).
+enum { LOOP_GEN = 0, LOOP_DENSE = 1, LOOP_NOISE = 2 };
+
+template <class S, bool JIT, int LOOP, bool SYN>
 __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
+  constexpr bool PF = LOOP == LOOP_DENSE;
   constexpr int NG = S::kNG;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const bool act = i < A.n;
@@ -57,7 +65,7 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
 #pragma unroll
   for (int g = 0; g < NG; ++g) p[g] = A.state[(int64_t)(1 + g) * n + ii];
   float ge = 0.0f, gi = 0.0f;
-  if (M.has_syn) {
+  if (SYN && M.has_syn) {
     ge = A.state[(int64_t)(1 + NG) * n + ii];
     gi = A.state[(int64_t)(2 + NG) * n + ii];
   }
@@ -110,7 +118,7 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
         }
         if (to_ck > 0) --to_ck;
         const float V = vh;
-        neuron_step<S>(M, L, dtC, vh, vl, p, Icur[j], ge, gi);
+        neuron_step<S, SYN>(M, L, dtC, vh, vl, p, Icur[j], ge, gi);
         const float Vn = vh;
         const bool spk = act && (V < M.v_th) && (Vn >= M.v_th);
         if (A.spikes) {
@@ -123,11 +131,67 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
         }
         if (A.v_rec && act) A.v_rec[(int64_t)k * n + i] = Vn;
         lvl += (Vn >= M.v_th);
-        ge *= M.decay_e;
-        gi *= M.decay_i;
+        if (SYN) {
+          ge *= M.decay_e;
+          gi *= M.decay_i;
+        }
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) Icur[j] = Inext[j];
+    }
+  } else if constexpr (LOOP == LOOP_NOISE) {
+    // steps until the next checkpoint (a counter, not a division per step)
+    int to_ck = A.ckpt ? (A.ckpt_every - A.k_base % A.ckpt_every) % A.ckpt_every : -1;
+    auto one_step = [&](int k, float I) {
+      if (to_ck == 0) {
+        to_ck = A.ckpt_every;
+        if (act) {
+          float* c = A.ckpt + (int64_t)((A.k_base + k) / A.ckpt_every) * (2 + NG + 2 * M.has_syn) * n;
+          c[i] = vh;
+          c[row_lo + i] = vl;
+#pragma unroll
+          for (int g = 0; g < NG; ++g) c[(int64_t)(1 + g) * n + i] = p[g];
+          if (M.has_syn) {
+            c[(int64_t)(1 + NG) * n + i] = ge;
+            c[(int64_t)(2 + NG) * n + i] = gi;
+          }
+        }
+      }
+      if (to_ck > 0) --to_ck;
+      const float V = vh;
+      neuron_step<S, SYN>(M, L, dtC, vh, vl, p, I, ge, gi);
+      const float Vn = vh;
+      const bool spk = act && (V < M.v_th) && (Vn >= M.v_th);
+      if (A.spikes) {
+        const uint64_t b = __ballot(spk);
+        if (lane == 0 && w0 < A.words) {
+          uint32_t* row = A.spikes + (int64_t)k * A.words;
+          row[w0] = (uint32_t)b;
+          if (w0 + 1 < A.words) row[w0 + 1] = (uint32_t)(b >> 32);
+        }
+      }
+      if (A.v_rec && act) A.v_rec[(int64_t)k * n + i] = Vn;
+      lvl += (Vn >= M.v_th);
+      if (SYN) {
+        ge *= M.decay_e;
+        gi *= M.decay_i;
+      }
+    };
+    // finish the Philox block that an earlier launch began (z was filled and
+    // advanced above), then whole blocks of four steps
+    const int head = min(A.nsteps, (int)((4 - (A.t0 & 3)) & 3));
+    int k = 0;
+    for (; k < head; ++k) {
+      one_step(k, fmaf(A.sigma, z[0], A.mu));
+      z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
+    }
+    for (; k < A.nsteps; k += 4) {
+      normals4(A.seed, nid, (uint64_t)(A.t0 + k) >> 2, z);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (k + j >= A.nsteps) break;
+        one_step(k + j, fmaf(A.sigma, z[j], A.mu));
+      }
     }
   } else {
     for (int k = 0; k < A.nsteps; ++k) {
@@ -205,21 +269,28 @@ static hipError_t step_spec(const hh_model* m, const StepArgs& a, hipStream_t s)
   // Small populations use 64-lane blocks so their few wavefronts spread over
   // as many compute units as possible (the step is latency bound there).
   const int bs = (a.n < 65536) ? 64 : 256;
-  const int64_t nb = (a.n + bs - 1) / bs;
-  bool pf = false;
-  if constexpr (S::kFixed) pf = a.in_mode == IN_DENSE;
-  if (pf) {
-    if constexpr (S::kFixed) {
-      if (a.coef)
-        hipLaunchKernelGGL((k_step<S, true, true>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
-      else
-        hipLaunchKernelGGL((k_step<S, false, true>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
+  const dim3 grid((unsigned)((a.n + bs - 1) / bs)), block(bs);
+  const bool jit = a.coef != nullptr;
+  if constexpr (S::kFixed) {
+    const bool syn = m->km.has_syn != 0;
+    if (a.in_mode == IN_DENSE || a.in_mode == IN_NOISE) {
+#define HH_LAUNCH(LOOP)                                                                        \
+  do {                                                                                         \
+    if (jit && syn) hipLaunchKernelGGL((k_step<S, true, LOOP, true>), grid, block, 0, s, m->km, a);   \
+    else if (jit) hipLaunchKernelGGL((k_step<S, true, LOOP, false>), grid, block, 0, s, m->km, a);    \
+    else if (syn) hipLaunchKernelGGL((k_step<S, false, LOOP, true>), grid, block, 0, s, m->km, a);    \
+    else hipLaunchKernelGGL((k_step<S, false, LOOP, false>), grid, block, 0, s, m->km, a);            \
+  } while (0)
+      if (a.in_mode == IN_DENSE) HH_LAUNCH(LOOP_DENSE);
+      else HH_LAUNCH(LOOP_NOISE);
+#undef HH_LAUNCH
+      return hipGetLastError();
     }
-  } else if (a.coef) {
-    hipLaunchKernelGGL((k_step<S, true, false>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
-  } else {
-    hipLaunchKernelGGL((k_step<S, false, false>), dim3((unsigned)nb), dim3(bs), 0, s, m->km, a);
   }
+  if (jit)
+    hipLaunchKernelGGL((k_step<S, true, LOOP_GEN, true>), grid, block, 0, s, m->km, a);
+  else
+    hipLaunchKernelGGL((k_step<S, false, LOOP_GEN, true>), grid, block, 0, s, m->km, a);
   return hipGetLastError();
 }
 
