@@ -303,7 +303,7 @@ def bench_layer(reps=5, ckpt_every=50):
     S = torch.tensor(S8.reshape(T * B, n_in), device=dev).to(torch.bfloat16)
     # the same spikes bit-packed for the forward product (1/16 of the bytes)
     Sbits = torch.tensor(W.pack_bits(S8.reshape(T * B, n_in)), device=dev)
-    SbitsT = torch.tensor(W.pack_bits(S8.reshape(T * B, n_in).T), device=dev)  # for dW
+    SbitsT = torch.tensor(W.pack_bits_cols(S8.reshape(T * B, n_in)), device=dev)  # for dW
     # the projection keeps the weights transposed: [H][n_in], K contiguous
     win32 = torch.tensor(np.ascontiguousarray(Win.T), device=dev)
     win16 = win32.to(torch.bfloat16)

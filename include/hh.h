@@ -237,12 +237,14 @@ int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t 
                       int32_t M, int32_t N, int32_t K, void* workspace, size_t workspace_bytes,
                       void* stream);
 size_t hh_proj_wgrad_workspace(int32_t M, int32_t N, int32_t K);
-/* The same weight gradient for a binary A given transposed as bits:
- * At_bits [K][words_per_col] uint32 (device), bit m%32 of word m/32 of row k
- * is A[m][k] in {0, 1}; words_per_col >= ceil(M/32).  Same workspace. */
-int32_t hh_proj_wgrad_bits(const uint32_t* At_bits, int32_t words_per_col, const float* dOut,
-                           float* dWt, int32_t accumulate, int32_t M, int32_t N, int32_t K,
-                           void* workspace, size_t workspace_bytes, void* stream);
+/* The same weight gradient for a binary A given as bits in groups of 32
+ * rows: A_bits [ceil(M/32)][ld] uint32 (device), ld >= K; bit b of word
+ * (w, k) is A[32 w + b][k] in {0, 1} (bits of rows >= M are ignored).  The
+ * words of consecutive columns k are adjacent, which makes the kernel's reads
+ * of the spike operand whole cache lines.  Same workspace. */
+int32_t hh_proj_wgrad_bits(const uint32_t* A_bits, int32_t ld, const float* dOut, float* dWt,
+                           int32_t accumulate, int32_t M, int32_t N, int32_t K, void* workspace,
+                           size_t workspace_bytes, void* stream);
 
 /* Linear readout of the mean spike level and cross-entropy loss, forward and
  * backward (the readout layer of the differentiable network, Methods

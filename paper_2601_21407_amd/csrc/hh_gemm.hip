@@ -21,10 +21,11 @@
 // 16-byte fragment reads of eight consecutive rows hit all banks once.
 //
 // Weight gradient: the reduction runs over M, the slow dimension of both
-// A and dOut, so each lane gathers 16 consecutive rows of one column
-// (coalesced across lanes) and writes them as M-contiguous LDS rows; the
-// reduction over M is split across blocks and the partials are added in a
-// fixed order.
+// A and dOut.  A block spans all of K (up to 768 columns) for 64 columns of
+// dOut, so the large fp32 operand is read once; each lane gathers eight
+// consecutive rows of one dOut column (coalesced across lanes) and writes
+// them as an M-contiguous LDS row.  The reduction over M is split across
+// blocks and the partials are added in a fixed order.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -282,155 +283,215 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
     }
 }
 
-// Weight gradient, one split of the reduction over M per blockIdx.y.
-// Output tile: 128 (n) x 128 (k) of dWt; four wavefronts of 64 x 64.  Per
-// slab 32 rows of M are staged as dOut^T [n][m] (bf16 hi and lo parts) and
-// A^T [k][m]: lane t gathers rows m..m+15 of column t % 128 (each load
-// instruction reads consecutive columns of one row) and writes them as two
-// 16-byte LDS stores.
-constexpr int GBN = 128, GBK = 128;
+// Weight gradient dWt[N][K] = dOut^T A, one split of the reduction over M per
+// blockIdx.y.  A block covers 64 output rows n and up to WKB output columns
+// k (all of them when K <= WKB), so dOut -- the large fp32 operand -- is read
+// exactly once.  The block has eight wavefronts, two per SIMD; wavefront w
+// owns the k tiles w, w + 8, w + 16 (WKT of them) for both 32-row halves of
+// the n tile: 2 WKT MFMA accumulators of 32 x 32, in the accumulation
+// registers.  Slabs of 64 rows of M: each lane loads two 16-byte pieces of
+// dOut (4 columns x 2 rows), splits the values into bf16 hi and lo parts and
+// stores them as M-contiguous LDS rows [n][m] (double-buffered; the next slab's
+// loads are in flight while the current one is multiplied, one barrier per
+// slab).  The A operand of a lane -- eight consecutive m of one column k --
+// is for spike bits one byte of the column's 32-bit word, expanded through a
+// 256-entry LDS table (the bits come in 32-row groups, [M/32][ld], so the
+// words of 32 consecutive columns are one 128-byte line); for bf16 A it is
+// read from global memory.
+// Loads go to clamped in-range addresses and keep the raw values; invalid
+// ones are zeroed where they are consumed (zeroing at the load would make
+// the load wait at once).
+constexpr int WN = 64, WW = 8, WKT = 3, WKB = WW * WKT * 32, WSK = 64, WLD = WSK + 8;
 
-// BITS: A given transposed as bits, At_bits [K][wpc] (bit m%32 of word m/32
-// of row k = A[m][k]); a lane's 16 rows of one column are then one word.
-template <bool BITS>
-__global__ __launch_bounds__(256, 2) void k_proj_wgrad(const uint16_t* __restrict__ A,
-                                                       const uint32_t* __restrict__ Atb, int wpc,
+// BITS: A given as bits in 32-row groups, Ab [ceil(M/32)][ldb] (bit m%32 of
+// word (m/32, k) = A[m][k]).  VEC: dOut rows are 16-byte aligned (N % 4 == 0
+// and an aligned base), so its columns are read as 16-byte pieces.
+template <bool BITS, bool VEC>
+__global__ __launch_bounds__(64 * WW, 1) void k_proj_wgrad(const uint16_t* __restrict__ A,
+                                                       const uint32_t* __restrict__ Ab, int ldb,
                                                        const float* __restrict__ D,
                                                        float* __restrict__ part, int M, int N,
-                                                       int K, int rows_per_split, int vec4) {
-  __shared__ __attribute__((aligned(16))) uint16_t Dh[2][GBN * LDK];  // [n][m]
-  __shared__ __attribute__((aligned(16))) uint16_t Dl[2][GBN * LDK];  // [n][m]
-  __shared__ __attribute__((aligned(16))) uint16_t At[2][GBK * LDK];  // [k][m]
-  const int tiles_n = (N + GBN - 1) / GBN;
-  const int tn = blockIdx.x % tiles_n, tk = blockIdx.x / tiles_n;
-  const int n0 = tn * GBN, k0 = tk * GBK;
+                                                       int K, int rows_per_split, int tiles_n) {
+  __shared__ __attribute__((aligned(16))) uint16_t Dh[2][WN * WLD];  // [n][m]
+  __shared__ __attribute__((aligned(16))) uint16_t Dl[2][WN * WLD];  // [n][m]
+  __shared__ uint4 lut[256];
+  const int tn = blockIdx.x % tiles_n, kb = blockIdx.x / tiles_n;
+  const int n0 = tn * WN, kbase = kb * WKB;
   const int mbeg = blockIdx.y * rows_per_split;
   const int mend = min(M, mbeg + rows_per_split);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wn = wave >> 1, wk = wave & 1;
-  // gather assignment: column c = tid % 128, rows g*16 .. g*16+15 of the slab
-  const int c = tid & 127, g = tid >> 7;
-  const bool av = k0 + c < K;
-  const uint16_t* acol = BITS ? nullptr : A + min(k0 + c, K - 1);
+  const int tid = threadIdx.x, lane = tid & 63, kl = lane & 31;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (BITS && tid < 256) {
+    // entry b: eight bf16, element e = 1.0 where bit e of b is set
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      w[j] = ((tid >> (2 * j)) & 1) * 0x3F80u + ((tid >> (2 * j + 1)) & 1) * 0x3F800000u;
+    lut[tid] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
 
-  f32x16 acc[2][2];
+  f32x16 acc[WKT][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < WKT; ++j)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+      for (int r = 0; r < 16; ++r) acc[j][h][r] = 0.0f;
 
-  // dOut: lane -> columns 4 n4 .. +3 and rows 4 mq .. +3 of the slab (16-byte
-  // loads of one row); A: lane -> column c, rows 16 g .. +15
-  const int n4 = tid & 31, mq = tid >> 5;
-  const int dn0 = n0 + 4 * n4;
-  const bool dfull = vec4 != 0 && dn0 + 3 < N;
-  float dq[4][4];
-  uint16_t areg[16];
-  uint32_t abits = 0u;
-  const uint32_t* bcol = BITS ? Atb + (int64_t)min(k0 + c, K - 1) * wpc : nullptr;
+  // dOut: lane -> columns n0 + 4 (tid & 15) .. +3, rows 2 (tid >> 4) and +1
+  const int dn = n0 + 4 * (tid & 15), dm = 2 * (tid >> 4);
+  // with VEC a lane past N reads the last column group instead and is zeroed
+  // at the stash
+  const int dnl = VEC ? min(dn, N - 4) : 0;
+  float4 dq[2];
   auto gather = [&](int ms) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = ms + 4 * mq + r;
-      const bool ok = m < mend;
-      const float* src = D + (int64_t)min(m, M - 1) * N;
-      if (ok && dfull) {
-        const float4 v = *reinterpret_cast<const float4*>(src + dn0);
-        dq[r][0] = v.x; dq[r][1] = v.y; dq[r][2] = v.z; dq[r][3] = v.w;
+    for (int r = 0; r < 2; ++r) {
+      const float* row = D + (int64_t)min(ms + dm + r, M - 1) * N;
+      if (VEC) {
+        dq[r] = *reinterpret_cast<const float4*>(row + dnl);
       } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) dq[r][j] = (ok && dn0 + j < N) ? src[dn0 + j] : 0.0f;
+        dq[r].x = row[min(dn, N - 1)];
+        dq[r].y = row[min(dn + 1, N - 1)];
+        dq[r].z = row[min(dn + 2, N - 1)];
+        dq[r].w = row[min(dn + 3, N - 1)];
       }
-    }
-    if (!BITS) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int m = ms + g * 16 + e;
-        areg[e] = (m < mend && av) ? acol[(int64_t)m * K] : (uint16_t)0;
-      }
-    } else {
-      // rows ms + 16 g .. + 15: half (g) of word ms / 32 (ms is a multiple
-      // of 32); rows at or past mend belong to the next split
-      const int m = ms + g * 16;
-      const int valid = mend - m;
-      uint32_t w = (av && valid > 0) ? (bcol[m >> 5] >> (16 * g)) & 0xFFFFu : 0u;
-      if (valid < 16) w &= valid > 0 ? (1u << valid) - 1u : 0u;
-      abits = w;
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](int buf, int ms) {
+    const float v[2][4] = {{dq[0].x, dq[0].y, dq[0].z, dq[0].w},
+                           {dq[1].x, dq[1].y, dq[1].z, dq[1].w}};
+    const bool r0 = ms + dm < mend, r1 = ms + dm + 1 < mend;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      uint32_t h[2], l[2];
+    for (int c = 0; c < 4; ++c) {
+      const bool ok = dn + c < N;
+      const float x0 = (ok && r0) ? v[0][c] : 0.0f, x1 = (ok && r1) ? v[1][c] : 0.0f;
+      const uint16_t h0 = f2bf(x0), h1 = f2bf(x1);
+      const uint16_t l0 = f2bf(x0 - bf2f(h0)), l1 = f2bf(x1 - bf2f(h1));
+      const int off = (4 * (tid & 15) + c) * WLD + dm;
+      *reinterpret_cast<uint32_t*>(&Dh[buf][off]) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      *reinterpret_cast<uint32_t*>(&Dl[buf][off]) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    }
+  };
+  // spike bits of the slab: two words (rows ms .. ms + 31, ms + 32 .. +63)
+  // per owned k tile
+  uint32_t wcur[WKT][2], wnxt[WKT][2];
+  auto bits_load = [&](int ms, uint32_t (&w)[WKT][2]) {
+    if (!BITS) return;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const float x0 = dq[2 * q][j], x1 = dq[2 * q + 1][j];
-        const uint16_t h0 = f2bf(x0), h1 = f2bf(x1);
-        const uint16_t l0 = f2bf(x0 - bf2f(h0)), l1 = f2bf(x1 - bf2f(h1));
-        h[q] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-        l[q] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    for (int j = 0; j < WKT; ++j) {
+      const int kc = min(kbase + (wave + WW * j) * 32 + kl, K - 1);
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        w[j][q] = Ab[(int64_t)min((ms >> 5) + q, (M - 1) >> 5) * ldb + kc];
+    }
+  };
+  auto b_operand = [&](int j, int ms, int ks, int ml) -> bf16x8 {
+    const int kc = kbase + (wave + WW * j) * 32 + kl;
+    if (BITS) {
+      const uint32_t w = (kc < K && ms + 32 * (ks >> 1) < mend) ? wcur[j][ks >> 1] : 0u;
+      return *reinterpret_cast<const bf16x8*>(&lut[(w >> (ml & 31)) & 0xFFu]);
+    } else {
+      uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int m = ms + ml + e;
+        const uint32_t v = A[(int64_t)min(m, M - 1) * K + min(kc, K - 1)];
+        w[e >> 1] |= ((kc < K && m < mend) ? v : 0u) << (16 * (e & 1));
       }
-      const int off = (4 * n4 + j) * LDK + 4 * mq;
-      *reinterpret_cast<uint2*>(&Dh[buf][off]) = make_uint2(h[0], h[1]);
-      *reinterpret_cast<uint2*>(&Dl[buf][off]) = make_uint2(l[0], l[1]);
+      const uint4 u = make_uint4(w[0], w[1], w[2], w[3]);
+      return *reinterpret_cast<const bf16x8*>(&u);
     }
-    uint32_t a[8];
+  };
+  // Tiles past K (a wavefront with fewer than WKT) multiply zeros: the slab
+  // barrier would make that wavefront wait anyway.
+  auto compute = [&](int buf, int ms) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      if (BITS)
-        a[e] = ((abits >> (2 * e)) & 1u) * 0x3F80u + ((abits >> (2 * e + 1)) & 1u) * 0x3F800000u;
-      else
-        a[e] = (uint32_t)areg[2 * e] | ((uint32_t)areg[2 * e + 1] << 16);
+    for (int ks = 0; ks < WSK / 16; ++ks) {
+      const int ml = 16 * ks + 8 * (lane >> 5);
+      bf16x8 ah[2], al[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        ah[h] = lds8(&Dh[buf][(h * 32 + kl) * WLD + ml]);
+        al[h] = lds8(&Dl[buf][(h * 32 + kl) * WLD + ml]);
+      }
+      if constexpr (BITS) {
+        // the operands of the k step first, then every hi product before the
+        // lo ones: the two products into one accumulator are six apart
+        bf16x8 b[WKT];
+#pragma unroll
+        for (int j = 0; j < WKT; ++j) b[j] = b_operand(j, ms, ks, ml);
+#pragma unroll
+        for (int j = 0; j < WKT; ++j)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[j][h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[h], b[j], acc[j][h], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < WKT; ++j)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[j][h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[h], b[j], acc[j][h], 0, 0, 0);
+      } else {
+        // bf16 A: each operand is gathered from global memory just before use
+#pragma unroll
+        for (int j = 0; j < WKT; ++j) {
+          const bf16x8 b = b_operand(j, ms, ks, ml);
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[j][h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[h], b, acc[j][h], 0, 0, 0);
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[j][h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[h], b, acc[j][h], 0, 0, 0);
+        }
+      }
     }
-    uint4* pa = reinterpret_cast<uint4*>(&At[buf][c * LDK + g * 16]);
-    pa[0] = make_uint4(a[0], a[1], a[2], a[3]);
-    pa[1] = make_uint4(a[4], a[5], a[6], a[7]);
   };
 
+  // (the first slab's words go through wnxt as well, so the loop is entered
+  // the same way from here as from its own end: no load is then still
+  // pending at the loop head)
   gather(mbeg);
-  stash(0);
-  __syncthreads();
-  const int ns = (mend - mbeg + SK - 1) / SK;
+  bits_load(mbeg, wnxt);
+#pragma unroll
+  for (int j = 0; j < WKT; ++j) {
+    wcur[j][0] = wnxt[j][0];
+    wcur[j][1] = wnxt[j][1];
+  }
+  stash(0, mbeg);
+  __syncthreads();  // also publishes the table
+  const int ns = (mend - mbeg + WSK - 1) / WSK;
   for (int s = 0; s < ns; ++s) {
     const int buf = s & 1;
+    const int ms = mbeg + s * WSK;
     const bool more = s + 1 < ns;
-    if (more) gather(mbeg + (s + 1) * SK);
-#pragma unroll
-    for (int kk = 0; kk < SK; kk += 16) {
-      const int ml = kk + 8 * (lane >> 5);
-      bf16x8 ah[2], al[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ah[i] = lds8(&Dh[buf][(wn * 64 + i * 32 + (lane & 31)) * LDK + ml]);
-        al[i] = lds8(&Dl[buf][(wn * 64 + i * 32 + (lane & 31)) * LDK + ml]);
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = lds8(&At[buf][(wk * 64 + j * 32 + (lane & 31)) * LDK + ml]);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], b[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], b[j], acc[i][j], 0, 0, 0);
-        }
+    if (more) {
+      gather(ms + WSK);
+      bits_load(ms + WSK, wnxt);
     }
-    if (more) stash(buf ^ 1);
+    compute(buf, ms);
+    if (more) {
+      // buffer buf ^ 1 was last read in slab s - 1, before the previous barrier
+      stash(buf ^ 1, ms + WSK);
+#pragma unroll
+      for (int j = 0; j < WKT; ++j) {
+        wcur[j][0] = wnxt[j][0];
+        wcur[j][1] = wnxt[j][1];
+      }
+    }
     __syncthreads();
   }
   float* P = part + (int64_t)blockIdx.y * N * K;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < WKT; ++j) {
+    const int col = kbase + (wave + WW * j) * 32 + kl;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = k0 + wk * 64 + j * 32 + (lane & 31);
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = n0 + wn * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (row < N && col < K) P[(int64_t)row * K + col] = acc[i][j][r];
+        const int row = n0 + h * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row < N && col < K) P[(int64_t)row * K + col] = acc[j][h][r];
       }
-    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, int64_t count) {
@@ -517,24 +578,28 @@ int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t 
   const int splits = wgrad_splits(M);
   int rows = (M + splits - 1) / splits;
   rows = (rows + SK - 1) / SK * SK;
-  const int tiles = ((K + GBK - 1) / GBK) * ((N + GBN - 1) / GBN);
+  const int tiles_n = (N + WN - 1) / WN;
+  const int blocks = tiles_n * ((K + WKB - 1) / WKB);
   float* part = (float*)workspace;
-  const int vec4 = (N % 4 == 0) && ((uintptr_t)dOut % 16 == 0);
-  hipLaunchKernelGGL(k_proj_wgrad<false>, dim3(tiles, splits), dim3(256), 0, s, A, nullptr, 0, dOut,
-                     part, M, N, K, rows, vec4);
+  if ((N & 3) == 0 && ((uintptr_t)dOut & 15) == 0)
+    hipLaunchKernelGGL((k_proj_wgrad<false, true>), dim3(blocks, splits), dim3(64 * WW), 0, s, A,
+                       nullptr, 0, dOut, part, M, N, K, rows, tiles_n);
+  else
+    hipLaunchKernelGGL((k_proj_wgrad<false, false>), dim3(blocks, splits), dim3(64 * WW), 0, s, A,
+                       nullptr, 0, dOut, part, M, N, K, rows, tiles_n);
   const int64_t count = (int64_t)K * N;
   hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, part,
                      dWt, count, splits, accumulate ? 1 : 0);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 
-int32_t hh_proj_wgrad_bits(const uint32_t* At_bits, int32_t words_per_col, const float* dOut,
-                           float* dWt, int32_t accumulate, int32_t M, int32_t N, int32_t K,
-                           void* workspace, size_t workspace_bytes, void* stream) {
+int32_t hh_proj_wgrad_bits(const uint32_t* A_bits, int32_t ld, const float* dOut, float* dWt,
+                           int32_t accumulate, int32_t M, int32_t N, int32_t K, void* workspace,
+                           size_t workspace_bytes, void* stream) {
   if (M < 0 || N < 0 || K < 0) return HH_E_SHAPE;
   if (N == 0 || K == 0) return HH_OK;
-  if (!dWt || (M > 0 && (!At_bits || !dOut))) return HH_E_INVALID;
-  if (words_per_col < (M + 31) / 32) return HH_E_SHAPE;
+  if (!dWt || (M > 0 && (!A_bits || !dOut))) return HH_E_INVALID;
+  if (ld < K) return HH_E_SHAPE;
   hipStream_t s = (hipStream_t)stream;
   if (M == 0) {
     if (accumulate) return HH_OK;
@@ -545,11 +610,15 @@ int32_t hh_proj_wgrad_bits(const uint32_t* At_bits, int32_t words_per_col, const
   const int splits = wgrad_splits(M);
   int rows = (M + splits - 1) / splits;
   rows = (rows + SK - 1) / SK * SK;
-  const int tiles = ((K + GBK - 1) / GBK) * ((N + GBN - 1) / GBN);
+  const int tiles_n = (N + WN - 1) / WN;
+  const int blocks = tiles_n * ((K + WKB - 1) / WKB);
   float* part = (float*)workspace;
-  const int vec4 = (N % 4 == 0) && ((uintptr_t)dOut % 16 == 0);
-  hipLaunchKernelGGL(k_proj_wgrad<true>, dim3(tiles, splits), dim3(256), 0, s, nullptr, At_bits,
-                     words_per_col, dOut, part, M, N, K, rows, vec4);
+  if ((N & 3) == 0 && ((uintptr_t)dOut & 15) == 0)
+    hipLaunchKernelGGL((k_proj_wgrad<true, true>), dim3(blocks, splits), dim3(64 * WW), 0, s, nullptr,
+                       A_bits, ld, dOut, part, M, N, K, rows, tiles_n);
+  else
+    hipLaunchKernelGGL((k_proj_wgrad<true, false>), dim3(blocks, splits), dim3(64 * WW), 0, s,
+                       nullptr, A_bits, ld, dOut, part, M, N, K, rows, tiles_n);
   const int64_t count = (int64_t)K * N;
   hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, part,
                      dWt, count, splits, accumulate ? 1 : 0);

@@ -342,22 +342,23 @@ def proj_wgrad(A_bf16, dOut, dWt, workspace=None, accumulate=False):
     return dWt
 
 
-def proj_wgrad_bits(At_bits, M: int, dOut, dWt, workspace=None, accumulate=False, m0: int = 0):
-    """dWt [N][K] = dOut [M][N]^T . A for a binary A given transposed as
-    bits: At_bits int32 [K][words], bit m%32 of word m/32 = A[m][k].  With
-    m0 (a multiple of 32) the product covers rows m0 .. m0 + M - 1 of A, and
-    dOut holds just those rows; accumulate adds to dWt."""
-    K, wpc = At_bits.shape
+def proj_wgrad_bits(A_bits, M: int, dOut, dWt, workspace=None, accumulate=False, m0: int = 0):
+    """dWt [N][K] = dOut [M][N]^T . A for a binary A given as bits in 32-row
+    groups: A_bits int32 [ceil(rows/32)][K], bit b of word (w, k) = A[32 w + b][k]
+    (see workloads.pack_bits_cols).  With m0 (a multiple of 32) the product
+    covers rows m0 .. m0 + M - 1 of A, and dOut holds just those rows;
+    accumulate adds to dWt."""
+    W_, K = A_bits.shape
     N = dOut.shape[1]
-    assert At_bits.dtype == torch.int32 and dOut.dtype == torch.float32
+    assert A_bits.dtype == torch.int32 and dOut.dtype == torch.float32
     assert tuple(dWt.shape) == (N, K) and dWt.dtype == torch.float32 and dOut.shape[0] == M
-    assert At_bits.is_contiguous() and dOut.is_contiguous() and dWt.is_contiguous()
-    assert m0 % 32 == 0 and (m0 + M + 31) // 32 <= wpc
+    assert A_bits.is_contiguous() and dOut.is_contiguous() and dWt.is_contiguous()
+    assert m0 % 32 == 0 and (m0 + M + 31) // 32 <= W_
     need = int(lib.hh_proj_wgrad_workspace(M, N, K))
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dWt.device)
-    base = ctypes.c_void_p(At_bits.data_ptr() + (m0 // 32) * 4) if At_bits.numel() else None
-    _ok(lib.hh_proj_wgrad_bits(base, int(wpc), _ptr(dOut), _ptr(dWt), 1 if accumulate else 0,
+    base = ctypes.c_void_p(A_bits.data_ptr() + (m0 // 32) * K * 4) if A_bits.numel() else None
+    _ok(lib.hh_proj_wgrad_bits(base, int(K), _ptr(dOut), _ptr(dWt), 1 if accumulate else 0,
                                int(M), N, K, _ptr(workspace),
                                workspace.numel() * workspace.element_size(), _stream()),
         "hh_proj_wgrad_bits")

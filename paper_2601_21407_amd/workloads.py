@@ -217,6 +217,15 @@ def pack_bits(A) -> np.ndarray:
     return np.ascontiguousarray(by).view(np.uint32).view(np.int32).reshape(M, wpr)
 
 
+def pack_bits_cols(A) -> np.ndarray:
+    """Binary matrix [M, K] to int32 words [ceil(M/32), K] packed along M:
+    bit m%32 of word (m/32, k) is A[m, k] (the weight gradient's layout)."""
+    A = np.asarray(A)
+    if A.shape[0] == 0:
+        return np.zeros((0, A.shape[1]), np.int32)
+    return np.ascontiguousarray(pack_bits(A.T).T)
+
+
 def layer_params(n_in: int = 700, H: int = 1024, n_cls: int = 20, seed: int = 4,
                  w_mean: float = 0.5, w_std: float = 0.8):
     """Initial parameters of the differentiable layer: W_in [n_in, H] (to be

@@ -80,14 +80,12 @@ def test_projection_forward_bits(M, N, K):
         hh.proj_forward(_bf16_tensor(A), Wt, out2)
         # same products, same tile order: identical
         assert torch.equal(out, out2)
-    # weight gradient from the transposed bits (junk past M ignored)
+    # weight gradient from bits packed along M (junk past M ignored)
     dO = rng.standard_normal((M, N)).astype(np.float32)
-    bT = W.pack_bits(A.T) if K > 0 else np.zeros((0, 1), np.int32)
-    if bT.shape[1] == 0:
-        bT = np.zeros((K, 1), np.int32)
+    bT = W.pack_bits_cols(A) if M > 0 else np.zeros((1, K), np.int32)
     if M % 32:
         bT = bT.copy()
-        bT[:, -1] |= np.int32(-1 << (M % 32))
+        bT[-1, :] |= np.int32(-1 << (M % 32))
     dWt = torch.empty((N, K), device="cuda")
     hh.proj_wgrad_bits(torch.tensor(bT, device="cuda"), M, torch.tensor(dO, device="cuda"), dWt)
     refw = O.projection_weight_grad(A, dO)
@@ -301,7 +299,7 @@ def test_weight_gradient_accumulates_over_row_ranges():
     M, N, K = 3000, 300, 100
     A = (rng.random((M, K)) < 0.1).astype(np.float32)
     dO = rng.standard_normal((M, N)).astype(np.float32)
-    bT = torch.tensor(W.pack_bits(A.T), device="cuda")
+    bT = torch.tensor(W.pack_bits_cols(A), device="cuda")
     dOt = torch.tensor(dO, device="cuda")
     whole = torch.empty((N, K), device="cuda")
     hh.proj_wgrad_bits(bT, M, dOt, whole)

@@ -108,3 +108,16 @@ def test_pack_bits_layout():
             assert ((int(u[m, k // 32]) >> (k % 32)) & 1) == int(A[m, k])
     # bits past K are zero
     assert (int(u[0, 3]) >> 4) == 0
+
+
+def test_pack_bits_cols_layout():
+    """Packed along M: bit m%32 of word (m/32, k) is A[m, k]."""
+    A = (np.random.default_rng(3).random((70, 9)) < 0.4)
+    b = W.pack_bits_cols(A)
+    assert b.dtype == np.int32 and b.shape == (3, 9) and b.flags["C_CONTIGUOUS"]
+    u = b.view(np.uint32)
+    for m in range(70):
+        for k in range(9):
+            assert ((int(u[m // 32, k]) >> (m % 32)) & 1) == int(A[m, k])
+    assert (int(u[2, 0]) >> 6) == 0
+    assert W.pack_bits_cols(np.zeros((0, 5))).shape == (0, 5)
