@@ -45,6 +45,12 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// two floats to a bf16 pair (round to nearest even; one conversion instruction)
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  const bf2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
 
 __device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
   return *reinterpret_cast<const bf16x8*>(p);
@@ -366,11 +372,12 @@ __global__ __launch_bounds__(64 * WW, 1) void k_proj_wgrad(const uint16_t* __res
     for (int c = 0; c < 4; ++c) {
       const bool ok = dn + c < N;
       const float x0 = (ok && r0) ? v[0][c] : 0.0f, x1 = (ok && r1) ? v[1][c] : 0.0f;
-      const uint16_t h0 = f2bf(x0), h1 = f2bf(x1);
-      const uint16_t l0 = f2bf(x0 - bf2f(h0)), l1 = f2bf(x1 - bf2f(h1));
+      // hi = x rounded to bf16 (nearest even), lo = the remainder rounded
+      const uint32_t hp = pack_bf16(x0, x1);
+      const uint32_t lp = pack_bf16(x0 - __uint_as_float(hp << 16), x1 - __uint_as_float(hp & 0xFFFF0000u));
       const int off = (4 * (tid & 15) + c) * WLD + dm;
-      *reinterpret_cast<uint32_t*>(&Dh[buf][off]) = (uint32_t)h0 | ((uint32_t)h1 << 16);
-      *reinterpret_cast<uint32_t*>(&Dl[buf][off]) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+      *reinterpret_cast<uint32_t*>(&Dh[buf][off]) = hp;
+      *reinterpret_cast<uint32_t*>(&Dl[buf][off]) = lp;
     }
   };
   // spike bits of the slab: two words (rows ms .. ms + 31, ms + 32 .. +63)
@@ -517,8 +524,9 @@ __global__ __launch_bounds__(256) void k_sum_splits(const float* __restrict__ pa
 }
 
 int wgrad_splits(int M) {
-  // enough blocks to fill the chip; each split reduces at least 2048 rows
-  int s = (M + 2047) / 2048;
+  // each split reduces at least 4096 rows: with 16 or more column tiles that
+  // fills the chip in one round, and keeps the partial sums small
+  int s = (M + 4095) / 4096;
   if (s > 64) s = 64;
   return s < 1 ? 1 : s;
 }
