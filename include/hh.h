@@ -250,7 +250,9 @@ int32_t hh_proj_wgrad_bits(const uint32_t* A_bits, int32_t ld, const float* dOut
  * backward (the readout layer of the differentiable network, Methods
  * "Training and preprocessing").  r = level / T with level [B][H] the
  * per-neuron count of steps with V >= v_th; logits = r W + bias, W [H][C],
- * bias [C]; loss = mean over b of -log softmax(logits_b)[labels[b]].
+ * bias [C]; loss = mean over b of -log softmax(logits_b)[labels[b]], with
+ * every labels[b] in [0, C) (device data, not checked: an out-of-range label
+ * leaves that row's loss term undefined).
  * Writes loss [1], dlevel [B][H] = dL/dr (the gradient with respect to the
  * rate r, which is what hh_backward's dL_dlevel takes), dW [H][C], db [C]
  * and, when non-NULL, logits [B][C].  C <= 32 (else HH_E_UNSUPPORTED).

@@ -189,10 +189,13 @@ __device__ __forceinline__ uint4 bits_to_bf16x8(uint32_t b8) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// AL: weight rows are 8-byte aligned with K >= 8 (K % 4 == 0 and an aligned
+// base), so every weight load is one 16-byte piece; else guarded scalar loads.
+template <bool AL>
 __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __restrict__ Ab, int wpr,
                                                           const uint16_t* __restrict__ Wt,
                                                           float* __restrict__ C, int M, int N,
-                                                          int K, int al) {
+                                                          int K) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2][FBM * LDK];  // [m][k]
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][FBN * LDK];  // [n][k]
   const int tiles_m = (M + FBM - 1) / FBM, tiles_n = (N + FBN - 1) / FBN;
@@ -201,7 +204,6 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
   const int m0 = tm * FBM, n0 = tn * FBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const bool aligned = al != 0;
   // A: thread expands 16 bits (half h of the slab word) of row ar;
   // Wt: chunk tid (row br, k = 8 (tid % 4))
   const int ar = tid >> 1, ah = tid & 1;
@@ -212,19 +214,36 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
   const uint16_t* brow = Wt + (int64_t)min(n0 + br, N - 1) * K;
   const int ns = (K + SK - 1) / SK;
 
-  auto a_bits = [&](int s) -> uint32_t {
-    if (!av || s >= ns) return 0u;
-    uint32_t w = arow[s];
-    const int valid = K - s * SK;  // bits past K are ignored
-    if (valid < 32) w &= (1u << valid) - 1u;
-    return (w >> (16 * ah)) & 0xFFFFu;
-  };
+  // Loads go to clamped in-range addresses and keep the raw words; rows past
+  // M or N, slabs past K and bits past K are zeroed at the stash (a load
+  // whose value is selected on would be turned into a branch around it, and
+  // then waited for at once).  With AL the eight weights at k are read from
+  // kl = min(k, K - 8) and moved into place at the stash: the tail of the
+  // last slab shifts by 4 or is all past K.
+  auto a_bits = [&](int s) -> uint32_t { return arow[min(s, ns - 1)]; };
   auto b_load = [&](int s) -> uint4 {
-    const uint4 zero = {0u, 0u, 0u, 0u};
-    if (!bv || s >= ns) return zero;
-    return load8(brow, s * SK + bkc, K, aligned);
+    const int k = min(s, ns - 1) * SK + bkc;
+    if (AL) {
+      const int kl = min(k, K - 8);
+      const uint2 x = *reinterpret_cast<const uint2*>(brow + kl);
+      const uint2 y = *reinterpret_cast<const uint2*>(brow + kl + 4);
+      return make_uint4(x.x, x.y, y.x, y.y);
+    }
+    return load8(brow, k, K, false);
   };
-  auto stash = [&](int buf, uint32_t a16, uint4 b) {
+  auto stash = [&](int buf, int s, uint32_t w, uint4 b) {
+    uint32_t a16 = 0u;
+    if (av && s < ns) {
+      const int valid = K - s * SK;  // bits past K are ignored
+      if (valid < 32) w &= (1u << valid) - 1u;
+      a16 = (w >> (16 * ah)) & 0xFFFFu;
+    }
+    if (AL) {
+      const int shift = s * SK + bkc - min(s * SK + bkc, K - 8);  // 0, 4, or >= 8
+      if (shift >= 8) b = make_uint4(0u, 0u, 0u, 0u);
+      else if (shift == 4) b = make_uint4(b.z, b.w, 0u, 0u);
+    }
+    if (!bv || s >= ns) b = make_uint4(0u, 0u, 0u, 0u);
     uint4* pa = reinterpret_cast<uint4*>(&As[buf][ar * LDK + 16 * ah]);
     pa[0] = bits_to_bf16x8(a16 & 0xFFu);
     pa[1] = bits_to_bf16x8(a16 >> 8);
@@ -258,23 +277,31 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
     }
   };
 
-  // slab s sits in LDS buffer s % 2; the weight slabs s+1 and s+2 are in
-  // registers (rb1, rb2) while slab s is multiplied
-  stash(0, a_bits(0), b_load(0));
-  uint4 rb1 = b_load(1), rb2 = b_load(2);
-  uint32_t ra1 = a_bits(1), ra2 = a_bits(2);
+  // Slab s sits in LDS buffer s % 2.  The raw loads of slab t live in
+  // register set t % 2: issued at the top of step t - 2 (when that set's
+  // previous slab had gone to LDS), stashed at the end of step t - 1, so a
+  // load has two slabs of products to arrive.  The loop is unrolled by two
+  // so that the sets are fixed registers (no copies, which would wait).
+  uint32_t ra[2];
+  uint4 rb[2];
+  ra[0] = a_bits(0);
+  rb[0] = b_load(0);
+  ra[1] = a_bits(1);
+  rb[1] = b_load(1);
+  stash(0, 0, ra[0], rb[0]);
   __syncthreads();
-  for (int s = 0; s < ns; ++s) {
-    compute(s & 1);
-    if (s + 1 < ns) {
+  for (int s0 = 0; s0 < ns; s0 += 2) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int s = s0 + u;
+      if (s >= ns) break;  // uniform
+      ra[u] = a_bits(s + 2);
+      rb[u] = b_load(s + 2);
+      compute(u);
       // buffer (s+1)%2 was last read in slab s-1, before the previous barrier
-      stash((s + 1) & 1, ra1, rb1);
-      rb1 = rb2;
-      ra1 = ra2;
-      rb2 = b_load(s + 3);
-      ra2 = a_bits(s + 3);
+      if (s + 1 < ns) stash(u ^ 1, s + 1, ra[u ^ 1], rb[u ^ 1]);
+      __syncthreads();
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -559,9 +586,12 @@ int32_t hh_proj_forward_bits(const uint32_t* A_bits, int32_t words_per_row, cons
   if (K == 0) return fill_zero(out, (int64_t)M * N, s) == hipSuccess ? HH_OK : HH_E_HIP;
   const int tiles = ((M + FBM - 1) / FBM) * ((N + FBN - 1) / FBN);
   const int blocks = (tiles + 7) / 8 * 8;
-  const int al = (K % 4 == 0) && ((uintptr_t)Wt % 8 == 0);
-  hipLaunchKernelGGL(k_proj_fwd_bits, dim3(blocks), dim3(512), 0, s, A_bits, words_per_row, Wt, out,
-                     M, N, K, al);
+  if (K % 4 == 0 && K >= 8 && (uintptr_t)Wt % 8 == 0)
+    hipLaunchKernelGGL(k_proj_fwd_bits<true>, dim3(blocks), dim3(512), 0, s, A_bits, words_per_row,
+                       Wt, out, M, N, K);
+  else
+    hipLaunchKernelGGL(k_proj_fwd_bits<false>, dim3(blocks), dim3(512), 0, s, A_bits, words_per_row,
+                       Wt, out, M, N, K);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 

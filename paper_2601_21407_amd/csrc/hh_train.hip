@@ -13,8 +13,23 @@ namespace {
 
 constexpr int kMaxC = 32;
 
+// Butterfly sum / max over the 64 lanes of a wavefront.  Each step adds a
+// lane's value and its partner's, which is the same sum in either order, so
+// every lane ends with the identical, order-fixed result (deterministic).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+
 // One block per batch row: logits, softmax, per-row loss, dz = (p - y) / B
 // and dL/dr for the row (r = level / T, the rate hh_backward differentiates).
+// The softmax runs on the first wavefront, one class per lane.
 __global__ __launch_bounds__(256) void k_readout_row(const float* __restrict__ level, float invT,
                                                      const float* __restrict__ W,
                                                      const float* __restrict__ bias,
@@ -35,34 +50,29 @@ __global__ __launch_bounds__(256) void k_readout_row(const float* __restrict__ l
     for (int c = 0; c < kMaxC; ++c)
       if (c < C) acc[c] = fmaf(r, W[(int64_t)h * C + c], acc[c]);
   }
-  // butterfly sum over the 64 lanes of each wavefront, then the four
-  // wavefront sums in order (a fixed order: deterministic)
+  // each wavefront's sums, then the four in order
 #pragma unroll
   for (int c = 0; c < kMaxC; ++c) {
     if (c < C) {
-      float v = acc[c];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      const float v = wave_sum(acc[c]);
       if (lane == 0) red[wv][c] = v;
     }
   }
   __syncthreads();
-  if (tid == 0) {
-    float z[kMaxC], zmax = -INFINITY;
-    for (int c = 0; c < C; ++c) {
-      z[c] = ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) + bias[c];
-      zmax = fmaxf(zmax, z[c]);
-    }
-    float se = 0.0f;
-    for (int c = 0; c < C; ++c) se += expf(z[c] - zmax);
+  if (wv == 0) {
+    const bool ok = lane < C;
+    const int c = ok ? lane : 0;
+    const float z = ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) + bias[c];
+    const float zmax = wave_max(ok ? z : -INFINITY);
+    const float ez = ok ? expf(z - zmax) : 0.0f;
+    const float se = wave_sum(ez);
     const int y = labels[b];
-    row_loss[b] = -(z[y] - zmax - logf(se));
-    for (int c = 0; c < C; ++c) {
-      const float pc = expf(z[c] - zmax) / se;
-      const float d = (pc - (c == y ? 1.0f : 0.0f)) / (float)B;
-      s_dz[c] = d;
-      dz[(int64_t)b * C + c] = d;
-      if (logits_out) logits_out[(int64_t)b * C + c] = z[c];
+    if (ok) {
+      const float d = (ez / se - (lane == y ? 1.0f : 0.0f)) / (float)B;
+      s_dz[lane] = d;
+      dz[(int64_t)b * C + lane] = d;
+      if (logits_out) logits_out[(int64_t)b * C + lane] = z;
+      if (lane == y) row_loss[b] = -(z - zmax - logf(se));
     }
   }
   __syncthreads();
@@ -76,8 +86,9 @@ __global__ __launch_bounds__(256) void k_readout_row(const float* __restrict__ l
 // dW[h][c] = sum_b r[b][h] dz[b][c]; db[c] = sum_b dz[b][c]; loss = mean.
 // Block (x, c) owns readout rows h = 32 x .. 32 x + 31 of class c; its 8
 // lane groups each sum every 8th batch row, and the eight partial sums are
-// added in group order.  Blocks (0, c) also form db[c]; block (0, 0) the
-// loss.
+// added in group order.  Blocks (0, c) also form db[c], block (0, 0) the
+// loss: each lane sums every 256th row, then wavefront butterflies and the
+// four wavefront sums in order (all fixed orders: deterministic).
 constexpr int RW_H = 32, RW_G = 8;
 
 __global__ __launch_bounds__(RW_H * RW_G) void k_readout_wgrad(
@@ -85,37 +96,39 @@ __global__ __launch_bounds__(RW_H * RW_G) void k_readout_wgrad(
     const float* __restrict__ row_loss, int B, int H, int C, float* __restrict__ dW,
     float* __restrict__ db, float* __restrict__ loss) {
   __shared__ float part[RW_G][RW_H + 1];
-  __shared__ float pdb[RW_H * RW_G];
+  __shared__ float wsum[2][4];
   const int tid = threadIdx.x, hx = tid % RW_H, g = tid / RW_H;
   const int c = blockIdx.y;
   const int h = blockIdx.x * RW_H + hx;
   float acc = 0.0f;
-  if (h < H)
+  if (h < H) {
+#pragma unroll 8
     for (int b = g; b < B; b += RW_G)
       acc = fmaf(level[(int64_t)b * H + h] * invT, dz[(int64_t)b * C + c], acc);
+  }
   part[g][hx] = acc;
+  if (blockIdx.x == 0) {
+    float sd = 0.0f, sl = 0.0f;
+    for (int b = tid; b < B; b += RW_H * RW_G) {
+      sd += dz[(int64_t)b * C + c];
+      if (c == 0) sl += row_loss[b];
+    }
+    sd = wave_sum(sd);
+    sl = wave_sum(sl);
+    if ((tid & 63) == 0) {
+      wsum[0][tid >> 6] = sd;
+      wsum[1][tid >> 6] = sl;
+    }
+  }
   __syncthreads();
   if (g == 0 && h < H) {
     float s = 0.0f;
     for (int q = 0; q < RW_G; ++q) s += part[q][hx];
     dW[(int64_t)h * C + c] = s;
   }
-  if (blockIdx.x == 0) {
-    // db[c]: 256 lanes each sum every 256th row, then lane 0 adds them in order
-    float s = 0.0f;
-    for (int b = tid; b < B; b += RW_H * RW_G) s += dz[(int64_t)b * C + c];
-    pdb[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-      float t = 0.0f;
-      for (int q = 0; q < RW_H * RW_G; ++q) t += pdb[q];
-      db[c] = t;
-      if (c == 0) {
-        float l = 0.0f;
-        for (int b = 0; b < B; ++b) l += row_loss[b];
-        *loss = l / (float)B;
-      }
-    }
+  if (blockIdx.x == 0 && tid == 0) {
+    db[c] = (wsum[0][0] + wsum[0][1]) + (wsum[0][2] + wsum[0][3]);
+    if (c == 0) *loss = ((wsum[1][0] + wsum[1][1]) + (wsum[1][2] + wsum[1][3])) / (float)B;
   }
 }
 
