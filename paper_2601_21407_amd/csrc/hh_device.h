@@ -178,6 +178,16 @@ __device__ __forceinline__ KRate derive_rate(int form, float A, float B, float K
   return k;
 }
 
+// A copy of x in a vector register that the compiler cannot re-derive from a
+// scalar original: it then keeps the register for the whole loop instead of
+// copying the scalar into a vector register at every use (a vector
+// instruction reads at most one scalar operand).
+__device__ __forceinline__ float pin_vgpr(float x) {
+  float y;
+  asm("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+  return y;
+}
+
 // Integer power with a wave-uniform exponent.
 __device__ __forceinline__ float ipow(float p, int e) {
   switch (e) {

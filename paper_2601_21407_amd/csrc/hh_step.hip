@@ -57,6 +57,14 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
 
   LaneRates<NG> L;
   load_rates<S>(M, JIT ? A.coef : nullptr, pidx, A.N, L);
+  if constexpr (!JIT && LOOP != LOOP_GEN) {
+    // uniform rate offsets pinned in vector registers for the launch, so
+    // that x = V s + o reads one scalar operand (s) and needs no copy
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int r = 0; r < 2; ++r) L.r[g][r].o = pin_vgpr(L.r[g][r].o);
+  }
   const float dtC = A.cm ? M.dt / A.cm[pidx] : M.dt / M.C;
 
   const int64_t row_lo = (int64_t)(1 + NG + 2 * M.has_syn) * n;  // low part of V
@@ -88,6 +96,7 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
     const float* drow = A.i_dense + ii;
     // steps until the next checkpoint (a counter, not a division per step)
     int to_ck = A.ckpt ? (A.ckpt_every - A.k_base % A.ckpt_every) % A.ckpt_every : -1;
+    to_ck = __builtin_amdgcn_readfirstlane(to_ck);  // uniform: a scalar register
     float Icur[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -102,6 +111,7 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
         const int k = k0 + j;
         if (k >= A.nsteps) break;
         const int kk = A.k_base + k;
+        to_ck = __builtin_amdgcn_readfirstlane(to_ck);
         if (to_ck == 0) {
           to_ck = A.ckpt_every;
           if (act) {
@@ -142,7 +152,9 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
   } else if constexpr (LOOP == LOOP_NOISE) {
     // steps until the next checkpoint (a counter, not a division per step)
     int to_ck = A.ckpt ? (A.ckpt_every - A.k_base % A.ckpt_every) % A.ckpt_every : -1;
+    to_ck = __builtin_amdgcn_readfirstlane(to_ck);  // uniform: a scalar register
     auto one_step = [&](int k, float I) {
+      to_ck = __builtin_amdgcn_readfirstlane(to_ck);
       if (to_ck == 0) {
         to_ck = A.ckpt_every;
         if (act) {
