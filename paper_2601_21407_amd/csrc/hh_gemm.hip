@@ -322,9 +322,9 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
 // exactly once.  The block has eight wavefronts, two per SIMD; wavefront w
 // owns the k tiles w, w + 8, w + 16 (WKT of them) for both 32-row halves of
 // the n tile: 2 WKT MFMA accumulators of 32 x 32, in the accumulation
-// registers.  Slabs of 64 rows of M: each lane loads two 16-byte pieces of
-// dOut (4 columns x 2 rows), splits the values into bf16 hi and lo parts and
-// stores them as M-contiguous LDS rows [n][m] (double-buffered; the next slab's
+// registers.  Slabs of 64 rows of M: each lane loads 4 columns x 2 rows of
+// dOut, splits the values into bf16 hi and lo parts and stores them as
+// M-contiguous LDS rows [n][m] (double-buffered; the next slab's
 // loads are in flight while the current one is multiplied, one barrier per
 // slab).  The A operand of a lane -- eight consecutive m of one column k --
 // is for spike bits one byte of the column's 32-bit word, expanded through a
@@ -337,9 +337,8 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
 constexpr int WN = 64, WW = 8, WKT = 3, WKB = WW * WKT * 32, WSK = 64, WLD = WSK + 8;
 
 // BITS: A given as bits in 32-row groups, Ab [ceil(M/32)][ldb] (bit m%32 of
-// word (m/32, k) = A[m][k]).  VEC: dOut rows are 16-byte aligned (N % 4 == 0
-// and an aligned base), so its columns are read as 16-byte pieces.
-template <bool BITS, bool VEC>
+// word (m/32, k) = A[m][k]).
+template <bool BITS>
 __global__ __launch_bounds__(64 * WW, 1) void k_proj_wgrad(const uint16_t* __restrict__ A,
                                                        const uint32_t* __restrict__ Ab, int ldb,
                                                        const float* __restrict__ D,
@@ -371,38 +370,31 @@ __global__ __launch_bounds__(64 * WW, 1) void k_proj_wgrad(const uint16_t* __res
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[j][h][r] = 0.0f;
 
-  // dOut: lane -> columns n0 + 4 (tid & 15) .. +3, rows 2 (tid >> 4) and +1
-  const int dn = n0 + 4 * (tid & 15), dm = 2 * (tid >> 4);
-  // with VEC a lane past N reads the last column group instead and is zeroed
-  // at the stash
-  const int dnl = VEC ? min(dn, N - 4) : 0;
-  float4 dq[2];
+  // dOut: lane l of wavefront w takes columns n0 + (l & 15) + 16 a (a = 0..3)
+  // at rows 2 mp, 2 mp + 1 of the slab, mp = (l >> 4) + 4 w: a wavefront's
+  // 4-byte LDS stores then cover 16 consecutive columns x 4 row pairs, which
+  // with the 144-byte row pitch are 64 distinct banks (no conflicts).  Each
+  // load instruction reads four 64-byte row pieces.
+  const int dnl = n0 + (tid & 15), dmp = ((tid & 63) >> 4) + 4 * wave;
+  float dq[4][2];
   auto gather = [&](int ms) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      const float* row = D + (int64_t)min(ms + dm + r, M - 1) * N;
-      if (VEC) {
-        dq[r] = *reinterpret_cast<const float4*>(row + dnl);
-      } else {
-        dq[r].x = row[min(dn, N - 1)];
-        dq[r].y = row[min(dn + 1, N - 1)];
-        dq[r].z = row[min(dn + 2, N - 1)];
-        dq[r].w = row[min(dn + 3, N - 1)];
-      }
+      const float* row = D + (int64_t)min(ms + 2 * dmp + r, M - 1) * N;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) dq[a][r] = row[min(dnl + 16 * a, N - 1)];
     }
   };
   auto stash = [&](int buf, int ms) {
-    const float v[2][4] = {{dq[0].x, dq[0].y, dq[0].z, dq[0].w},
-                           {dq[1].x, dq[1].y, dq[1].z, dq[1].w}};
-    const bool r0 = ms + dm < mend, r1 = ms + dm + 1 < mend;
+    const bool r0 = ms + 2 * dmp < mend, r1 = ms + 2 * dmp + 1 < mend;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const bool ok = dn + c < N;
-      const float x0 = (ok && r0) ? v[0][c] : 0.0f, x1 = (ok && r1) ? v[1][c] : 0.0f;
+    for (int a = 0; a < 4; ++a) {
+      const bool ok = dnl + 16 * a < N;
+      const float x0 = (ok && r0) ? dq[a][0] : 0.0f, x1 = (ok && r1) ? dq[a][1] : 0.0f;
       // hi = x rounded to bf16 (nearest even), lo = the remainder rounded
       const uint32_t hp = pack_bf16(x0, x1);
       const uint32_t lp = pack_bf16(x0 - __uint_as_float(hp << 16), x1 - __uint_as_float(hp & 0xFFFF0000u));
-      const int off = (4 * (tid & 15) + c) * WLD + dm;
+      const int off = ((tid & 15) + 16 * a) * WLD + 2 * dmp;
       *reinterpret_cast<uint32_t*>(&Dh[buf][off]) = hp;
       *reinterpret_cast<uint32_t*>(&Dl[buf][off]) = lp;
     }
@@ -619,12 +611,8 @@ int32_t hh_proj_wgrad(const uint16_t* A, const float* dOut, float* dWt, int32_t 
   const int tiles_n = (N + WN - 1) / WN;
   const int blocks = tiles_n * ((K + WKB - 1) / WKB);
   float* part = (float*)workspace;
-  if ((N & 3) == 0 && ((uintptr_t)dOut & 15) == 0)
-    hipLaunchKernelGGL((k_proj_wgrad<false, true>), dim3(blocks, splits), dim3(64 * WW), 0, s, A,
-                       nullptr, 0, dOut, part, M, N, K, rows, tiles_n);
-  else
-    hipLaunchKernelGGL((k_proj_wgrad<false, false>), dim3(blocks, splits), dim3(64 * WW), 0, s, A,
-                       nullptr, 0, dOut, part, M, N, K, rows, tiles_n);
+  hipLaunchKernelGGL(k_proj_wgrad<false>, dim3(blocks, splits), dim3(64 * WW), 0, s, A, nullptr, 0,
+                     dOut, part, M, N, K, rows, tiles_n);
   const int64_t count = (int64_t)K * N;
   hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, part,
                      dWt, count, splits, accumulate ? 1 : 0);
@@ -651,12 +639,8 @@ int32_t hh_proj_wgrad_bits(const uint32_t* A_bits, int32_t ld, const float* dOut
   const int tiles_n = (N + WN - 1) / WN;
   const int blocks = tiles_n * ((K + WKB - 1) / WKB);
   float* part = (float*)workspace;
-  if ((N & 3) == 0 && ((uintptr_t)dOut & 15) == 0)
-    hipLaunchKernelGGL((k_proj_wgrad<true, true>), dim3(blocks, splits), dim3(64 * WW), 0, s, nullptr,
-                       A_bits, ld, dOut, part, M, N, K, rows, tiles_n);
-  else
-    hipLaunchKernelGGL((k_proj_wgrad<true, false>), dim3(blocks, splits), dim3(64 * WW), 0, s,
-                       nullptr, A_bits, ld, dOut, part, M, N, K, rows, tiles_n);
+  hipLaunchKernelGGL(k_proj_wgrad<true>, dim3(blocks, splits), dim3(64 * WW), 0, s, nullptr, A_bits,
+                     ld, dOut, part, M, N, K, rows, tiles_n);
   const int64_t count = (int64_t)K * N;
   hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, part,
                      dWt, count, splits, accumulate ? 1 : 0);

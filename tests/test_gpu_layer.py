@@ -97,6 +97,28 @@ def test_projection_forward_bits(M, N, K):
         assert torch.equal(dWt, dWt2)
 
 
+@pytest.mark.parametrize("M,N,K", [(700, 130, 1000), (2100, 64, 1601)])
+def test_weight_gradient_wide_K(M, N, K):
+    """K wider than one block's column span (768): the column blocks of the
+    weight gradient, for spike bits and bf16 input, match the oracle and each
+    other exactly."""
+    print_case("wgrad wide K M=%d N=%d K=%d" % (M, N, K))
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    rng = np.random.default_rng(M + K)
+    A = (rng.random((M, K)) < 0.05).astype(np.float32)
+    dO = rng.standard_normal((M, N)).astype(np.float32)
+    dWt = torch.empty((N, K), device="cuda")
+    hh.proj_wgrad_bits(torch.tensor(W.pack_bits_cols(A), device="cuda"), M,
+                       torch.tensor(dO, device="cuda"), dWt)
+    refw = O.projection_weight_grad(A, dO)
+    scw = np.abs(A.astype(np.float64)).T @ np.abs(dO.astype(np.float64))
+    assert np.all(np.abs(dWt.cpu().numpy().T - refw) <= 2e-5 * scw + 1e-30)
+    dWt2 = torch.empty((N, K), device="cuda")
+    hh.proj_wgrad(_bf16_tensor(A), torch.tensor(dO, device="cuda"), dWt2)
+    assert torch.equal(dWt, dWt2)
+
+
 def test_projection_full_size_sampled():
     """S [250*256 x 700] Bernoulli spikes x W_in [700 x 1024] bf16."""
     print_case("proj full 64000 x 1024 x 700")
