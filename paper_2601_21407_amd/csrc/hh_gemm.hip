@@ -15,9 +15,9 @@
 //
 // Forward: a 512-lane block computes a 256 x 128 output tile; its eight
 // wavefronts each own 64 x 64 = 2 x 2 MFMA tiles.  Slabs of 32 K values of
-// both operands are staged through two LDS buffers: the global loads of slab
-// s+1 are in flight (in registers) while slab s is multiplied, so one barrier
-// per slab suffices.  Rows are padded to 40 bf16 (80 bytes), which makes the
+// both operands are staged through two LDS buffers; the global loads of slab
+// s+2 are issued (into one of two register sets) while slab s is multiplied,
+// so one barrier per slab suffices.  Rows are padded to 40 bf16 (80 bytes), which makes the
 // 16-byte fragment reads of eight consecutive rows hit all banks once.
 //
 // Weight gradient: the reduction runs over M, the slow dimension of both
@@ -88,10 +88,38 @@ __device__ __forceinline__ uint4 load8(const uint16_t* row, int k, int K, bool a
   return v;
 }
 
+// Eight consecutive bf16 of a row from element k, raw: with AL (rows 8-byte
+// aligned, K % 4 == 0, K >= 8) read at kl = min(k, K - 8), to be moved into
+// place by fix8 where they are consumed; else guarded scalar reads.
+template <bool AL>
+__device__ __forceinline__ uint4 raw8(const uint16_t* row, int k, int K) {
+  if (AL) {
+    const int kl = min(k, K - 8);
+    const uint2 x = *reinterpret_cast<const uint2*>(row + kl);
+    const uint2 y = *reinterpret_cast<const uint2*>(row + kl + 4);
+    return make_uint4(x.x, x.y, y.x, y.y);
+  }
+  return load8(row, k, K, false);
+}
+// The eight values at k from what raw8 read (0 past K): the K tail shifts by
+// 4 or lies past K.
+template <bool AL>
+__device__ __forceinline__ uint4 fix8(uint4 v, int k, int K) {
+  if (AL) {
+    const int shift = k - min(k, K - 8);  // 0, 4, or >= 8
+    if (shift >= 8) return make_uint4(0u, 0u, 0u, 0u);
+    if (shift == 4) return make_uint4(v.z, v.w, 0u, 0u);
+  }
+  return v;
+}
+
+// AL: see raw8.  Loads go to clamped in-range rows and keep the raw values;
+// rows past M or N are zeroed at the stash (a loaded value that is selected
+// on would be turned into a branch around the load, and waited for at once).
+template <bool AL>
 __global__ __launch_bounds__(512, 4) void k_proj_fwd(const uint16_t* __restrict__ A,
                                                      const uint16_t* __restrict__ Wt,
-                                                     float* __restrict__ C, int M, int N, int K,
-                                                     int al) {
+                                                     float* __restrict__ C, int M, int N, int K) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2][FBM * LDK];  // [m][k]
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][FBN * LDK];  // [n][k]
   const int tiles_m = (M + FBM - 1) / FBM, tiles_n = (N + FBN - 1) / FBN;
@@ -100,7 +128,6 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd(const uint16_t* __restrict_
   const int m0 = tm * FBM, n0 = tn * FBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const bool aligned = al != 0;
   // load assignment: A chunks tid and tid + 512 (row = c / 4, k = 8 (c % 4)),
   // Wt chunk tid
   const int ar0 = tid >> 2, ar1 = (tid + 512) >> 2, akc = (tid & 3) * 8;
@@ -109,6 +136,22 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd(const uint16_t* __restrict_
   const uint16_t* arow1 = A + (int64_t)min(m0 + ar1, M - 1) * K;
   const uint16_t* brow = Wt + (int64_t)min(n0 + br, N - 1) * K;
   const bool av0 = m0 + ar0 < M, av1 = m0 + ar1 < M, bv = n0 + br < N;
+  const int ns = (K + SK - 1) / SK;
+  const uint4 zero = {0u, 0u, 0u, 0u};
+  struct Raw {
+    uint4 a0, a1, b;
+  };
+  auto load = [&](int s) -> Raw {
+    const int k = min(s, ns - 1) * SK + akc;
+    return Raw{raw8<AL>(arow0, k, K), raw8<AL>(arow1, k, K), raw8<AL>(brow, k, K)};
+  };
+  auto stash = [&](int buf, int s, const Raw& r) {
+    const int k = s * SK + akc;
+    const bool sv = s < ns;
+    *reinterpret_cast<uint4*>(&As[buf][ar0 * LDK + akc]) = (av0 && sv) ? fix8<AL>(r.a0, k, K) : zero;
+    *reinterpret_cast<uint4*>(&As[buf][ar1 * LDK + akc]) = (av1 && sv) ? fix8<AL>(r.a1, k, K) : zero;
+    *reinterpret_cast<uint4*>(&Bs[buf][br * LDK + akc]) = (bv && sv) ? fix8<AL>(r.b, k, K) : zero;
+  };
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -118,24 +161,7 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd(const uint16_t* __restrict_
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  const uint4 zero = {0u, 0u, 0u, 0u};
-  uint4 ra0 = av0 ? load8(arow0, akc, K, aligned) : zero;
-  uint4 ra1 = av1 ? load8(arow1, akc, K, aligned) : zero;
-  uint4 rb = bv ? load8(brow, akc, K, aligned) : zero;
-  *reinterpret_cast<uint4*>(&As[0][ar0 * LDK + akc]) = ra0;
-  *reinterpret_cast<uint4*>(&As[0][ar1 * LDK + akc]) = ra1;
-  *reinterpret_cast<uint4*>(&Bs[0][br * LDK + akc]) = rb;
-  __syncthreads();
-  const int ns = (K + SK - 1) / SK;
-  for (int s = 0; s < ns; ++s) {
-    const int buf = s & 1;
-    const bool more = s + 1 < ns;
-    if (more) {  // next slab's loads in flight during this slab's products
-      const int k1 = (s + 1) * SK + akc;
-      ra0 = av0 ? load8(arow0, k1, K, aligned) : zero;
-      ra1 = av1 ? load8(arow1, k1, K, aligned) : zero;
-      rb = bv ? load8(brow, k1, K, aligned) : zero;
-    }
+  auto compute = [&](int buf) {
     const uint16_t* as = As[buf];
     const uint16_t* bs = Bs[buf];
 #pragma unroll
@@ -152,13 +178,28 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd(const uint16_t* __restrict_
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (more) {
-      // the other buffer was last read in slab s-1, before the barrier below
-      *reinterpret_cast<uint4*>(&As[buf ^ 1][ar0 * LDK + akc]) = ra0;
-      *reinterpret_cast<uint4*>(&As[buf ^ 1][ar1 * LDK + akc]) = ra1;
-      *reinterpret_cast<uint4*>(&Bs[buf ^ 1][br * LDK + akc]) = rb;
+  };
+
+  // Slab s sits in LDS buffer s % 2; the raw loads of slab t live in register
+  // set t % 2 from the top of step t - 2 to the end of step t - 1 (two slabs of
+  // products to arrive; the loop is unrolled by two so the sets are fixed
+  // registers).
+  Raw rs[2];
+  rs[0] = load(0);
+  rs[1] = load(1);
+  stash(0, 0, rs[0]);
+  __syncthreads();
+  for (int s0 = 0; s0 < ns; s0 += 2) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int s = s0 + u;
+      if (s >= ns) break;  // uniform
+      rs[u] = load(s + 2);
+      compute(u);
+      // buffer (s+1)%2 was last read in slab s-1, before the previous barrier
+      if (s + 1 < ns) stash(u ^ 1, s + 1, rs[u ^ 1]);
+      __syncthreads();
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -189,8 +230,7 @@ __device__ __forceinline__ uint4 bits_to_bf16x8(uint32_t b8) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// AL: weight rows are 8-byte aligned with K >= 8 (K % 4 == 0 and an aligned
-// base), so every weight load is one 16-byte piece; else guarded scalar loads.
+// AL: as for raw8 (weight rows 8-byte aligned, K % 4 == 0, K >= 8).
 template <bool AL>
 __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __restrict__ Ab, int wpr,
                                                           const uint16_t* __restrict__ Wt,
@@ -217,20 +257,9 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
   // Loads go to clamped in-range addresses and keep the raw words; rows past
   // M or N, slabs past K and bits past K are zeroed at the stash (a load
   // whose value is selected on would be turned into a branch around it, and
-  // then waited for at once).  With AL the eight weights at k are read from
-  // kl = min(k, K - 8) and moved into place at the stash: the tail of the
-  // last slab shifts by 4 or is all past K.
+  // then waited for at once).  The weights go through raw8 / fix8.
   auto a_bits = [&](int s) -> uint32_t { return arow[min(s, ns - 1)]; };
-  auto b_load = [&](int s) -> uint4 {
-    const int k = min(s, ns - 1) * SK + bkc;
-    if (AL) {
-      const int kl = min(k, K - 8);
-      const uint2 x = *reinterpret_cast<const uint2*>(brow + kl);
-      const uint2 y = *reinterpret_cast<const uint2*>(brow + kl + 4);
-      return make_uint4(x.x, x.y, y.x, y.y);
-    }
-    return load8(brow, k, K, false);
-  };
+  auto b_load = [&](int s) -> uint4 { return raw8<AL>(brow, min(s, ns - 1) * SK + bkc, K); };
   auto stash = [&](int buf, int s, uint32_t w, uint4 b) {
     uint32_t a16 = 0u;
     if (av && s < ns) {
@@ -238,12 +267,7 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
       if (valid < 32) w &= (1u << valid) - 1u;
       a16 = (w >> (16 * ah)) & 0xFFFFu;
     }
-    if (AL) {
-      const int shift = s * SK + bkc - min(s * SK + bkc, K - 8);  // 0, 4, or >= 8
-      if (shift >= 8) b = make_uint4(0u, 0u, 0u, 0u);
-      else if (shift == 4) b = make_uint4(b.z, b.w, 0u, 0u);
-    }
-    if (!bv || s >= ns) b = make_uint4(0u, 0u, 0u, 0u);
+    b = (bv && s < ns) ? fix8<AL>(b, s * SK + bkc, K) : make_uint4(0u, 0u, 0u, 0u);
     uint4* pa = reinterpret_cast<uint4*>(&As[buf][ar * LDK + 16 * ah]);
     pa[0] = bits_to_bf16x8(a16 & 0xFFu);
     pa[1] = bits_to_bf16x8(a16 >> 8);
@@ -563,8 +587,10 @@ int32_t hh_proj_forward(const uint16_t* A, const uint16_t* Wt, float* out, int32
   if (K == 0) return fill_zero(out, (int64_t)M * N, s) == hipSuccess ? HH_OK : HH_E_HIP;
   const int tiles = ((M + FBM - 1) / FBM) * ((N + FBN - 1) / FBN);
   const int blocks = (tiles + 7) / 8 * 8;
-  const int al = (K % 4 == 0) && ((uintptr_t)A % 8 == 0) && ((uintptr_t)Wt % 8 == 0);
-  hipLaunchKernelGGL(k_proj_fwd, dim3(blocks), dim3(512), 0, s, A, Wt, out, M, N, K, al);
+  if (K % 4 == 0 && K >= 8 && (uintptr_t)A % 8 == 0 && (uintptr_t)Wt % 8 == 0)
+    hipLaunchKernelGGL(k_proj_fwd<true>, dim3(blocks), dim3(512), 0, s, A, Wt, out, M, N, K);
+  else
+    hipLaunchKernelGGL(k_proj_fwd<false>, dim3(blocks), dim3(512), 0, s, A, Wt, out, M, N, K);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 
