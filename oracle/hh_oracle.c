@@ -169,6 +169,39 @@ double ora_gate_inf(const ora_model* m, const double* coef, int64_t n, int64_t i
   return pinf;
 }
 
+/* Exact exponential-Euler terms of gate g at V: P = p_inf, Q = 1 - e. */
+static void exact_pq(const ora_model* m, const double* coef, int64_t n, int64_t i, int32_t g,
+                     double V, double* P, double* Q) {
+  double pinf, e, dp, de;
+  gate_terms(m, coef, n, i, g, V, &pinf, &e, &dp, &de);
+  *P = pinf;
+  *Q = 1.0 - e;
+}
+
+/* Tabulated kinetics: the exact P and Q at the nodes v_k = tab_vlo + k tab_h,
+ * joined by straight lines.  u = (V - tab_vlo) / tab_h locates V; it is
+ * clamped to [0, tab_n - 1], so V beyond either end takes the end node's
+ * values; the segment is k = floor(u) (the last segment at the top node) and
+ * t = u - k the position inside it. */
+void ora_gate_pq(const ora_model* m, const double* coef, int64_t n, int64_t i, int32_t g,
+                 double V, double* P, double* Q) {
+  if (m->tab_n < 2) {
+    exact_pq(m, coef, n, i, g, V, P, Q);
+    return;
+  }
+  double u = (V - m->tab_vlo) / m->tab_h;
+  if (u < 0.0) u = 0.0;
+  if (u > (double)(m->tab_n - 1)) u = (double)(m->tab_n - 1);
+  int64_t k = (int64_t)floor(u);
+  if (k > m->tab_n - 2) k = m->tab_n - 2;
+  const double t = u - (double)k;
+  double Pa, Qa, Pb, Qb;
+  exact_pq(m, coef, n, i, g, m->tab_vlo + (double)k * m->tab_h, &Pa, &Qa);
+  exact_pq(m, coef, n, i, g, m->tab_vlo + (double)(k + 1) * m->tab_h, &Pb, &Qb);
+  *P = Pa + t * (Pb - Pa);
+  *Q = Qa + t * (Qb - Qa);
+}
+
 void ora_init_state(const ora_model* m, const double* coef, int64_t n, const double* v0,
                     double* state) {
   for (int64_t i = 0; i < n; ++i) {
@@ -190,6 +223,7 @@ static int model_ok(const ora_model* m) {
     for (int k = 0; k < m->ch_n[c]; ++k)
       if (m->ch_gate[c][k] < 0 || m->ch_gate[c][k] >= m->n_gates || m->ch_expo[c][k] < 0) return 0;
   }
+  if (m->tab_n < 0 || m->tab_n == 1 || (m->tab_n >= 2 && !(m->tab_h > 0.0))) return 0;
   return m->dt > 0.0;
 }
 
@@ -219,9 +253,15 @@ static void neuron_step(const ora_model* m, const double* coef, int64_t n, int64
                         double V, const double* p, double ge, double gi, double I, double* Vn,
                         double* pn) {
   for (int g = 0; g < m->n_gates; ++g) {
-    double pinf, e, dp, de;
-    gate_terms(m, coef, n, i, g, V, &pinf, &e, &dp, &de);
-    pn[g] = pinf + (p[g] - pinf) * e;
+    if (m->tab_n >= 2) {
+      double P, Q;
+      ora_gate_pq(m, coef, n, i, g, V, &P, &Q);
+      pn[g] = p[g] + (P - p[g]) * Q;
+    } else {
+      double pinf, e, dp, de;
+      gate_terms(m, coef, n, i, g, V, &pinf, &e, &dp, &de);
+      pn[g] = pinf + (p[g] - pinf) * e;
+    }
   }
   if (m->v_method == ORA_FE) {
     double i_ion = 0.0;
@@ -360,7 +400,7 @@ int32_t ora_bptt(const ora_model* m, int64_t n, const double* cm, const double* 
                  int32_t T, const double* I, const double* dL_dr, const double* dL_dV,
                  int32_t smooth, double beta, double* r_out, double* dI, double* dCm,
                  double* dx0) {
-  if (!model_ok(m) || m->has_syn || n < 0 || T <= 0) return -1;
+  if (!model_ok(m) || m->has_syn || m->tab_n != 0 || n < 0 || T <= 0) return -1;
   const int G = m->n_gates, NS = 1 + G;
   const double dt = m->dt, th = m->v_th;
   double* traj = (double*)malloc(sizeof(double) * (size_t)(T + 1) * NS);

@@ -47,6 +47,11 @@ typedef struct {
   double ch_gbar[ORA_MAX_CH], ch_E[ORA_MAX_CH];
   double C, dt, v_th;
   double tau_e, tau_i, E_e, E_i;
+  /* Tabulated gate kinetics (Methods, "Engineering optimization": cheaper
+   * approximations of the rate functions).  tab_n = 0: the rate functions
+   * themselves.  tab_n >= 2: nodes v_k = tab_vlo + k tab_h, k = 0..tab_n-1. */
+  int32_t tab_n;
+  double tab_vlo, tab_h;
 } ora_model;
 
 /* Per-neuron coefficient override: coef[(g*8 + r*4 + j) * n + i] replaces
@@ -65,6 +70,12 @@ double ora_rate(int32_t form, const double k[4], double V, double* dV);
 /* Steady state of gate g at V (p_inf). */
 double ora_gate_inf(const ora_model* m, const double* coef, int64_t n, int64_t i,
                     int32_t g, double V);
+/* The two terms of the exponential-Euler gate update p' = p + (P - p) Q:
+ * P = p_inf(V), Q = 1 - exp(-dt / tau(V)).  With tab_n >= 2 both are the
+ * straight-line interpolants between the two nodes around V (V clamped to
+ * the node range) of the same terms evaluated at the nodes. */
+void ora_gate_pq(const ora_model* m, const double* coef, int64_t n, int64_t i, int32_t g,
+                 double V, double* P, double* Q);
 /* state[0][i] = v0[i]; state[1+g][i] = p_inf(v0[i]); synaptic slots = 0. */
 void ora_init_state(const ora_model* m, const double* coef, int64_t n, const double* v0,
                     double* state);

@@ -66,6 +66,9 @@ class OraModel(ctypes.Structure):
         ("tau_i", ctypes.c_double),
         ("E_e", ctypes.c_double),
         ("E_i", ctypes.c_double),
+        ("tab_n", ctypes.c_int32),
+        ("tab_vlo", ctypes.c_double),
+        ("tab_h", ctypes.c_double),
     ]
 
 
@@ -75,7 +78,8 @@ def model_to_struct(model: dict) -> OraModel:
     model = {"gates": [{"kind": "ab"|"inftau", "rates": [(form, A, B, K, c), (form, A, B, K, c)]}],
              "channels": [{"gbar": g, "E": E, "gates": [(gate_index, exponent), ...]}],
              "C": C_m, "dt": dt, "v_th": theta, "v_method": "fe"|"ee",
-             "syn": None | {"tau_e", "tau_i", "E_e", "E_i"}}
+             "syn": None | {"tau_e", "tau_i", "E_e", "E_i"},
+             "table": absent | (v_lo, v_hi, n_nodes)}   # tabulated gate kinetics
     """
     s = OraModel()
     gates, chans = model["gates"], model["channels"]
@@ -100,6 +104,10 @@ def model_to_struct(model: dict) -> OraModel:
     if syn:
         s.tau_e, s.tau_i = float(syn["tau_e"]), float(syn["tau_i"])
         s.E_e, s.E_i = float(syn["E_e"]), float(syn["E_i"])
+    tab = model.get("table")
+    if tab is not None:
+        v_lo, v_hi, n_nodes = float(tab[0]), float(tab[1]), int(tab[2])
+        s.tab_n, s.tab_vlo, s.tab_h = n_nodes, v_lo, (v_hi - v_lo) / (n_nodes - 1)
     return s
 
 
@@ -124,6 +132,8 @@ def lib():
         L.ora_rate.restype = d
         L.ora_gate_inf.argtypes = [P(OraModel), vp, i64, i64, i32, d]
         L.ora_gate_inf.restype = d
+        L.ora_gate_pq.argtypes = [P(OraModel), vp, i64, i64, i32, d, P(d), P(d)]
+        L.ora_gate_pq.restype = None
         L.ora_init_state.argtypes = [P(OraModel), vp, i64, vp, vp]
         L.ora_init_state.restype = None
         L.ora_n_state.argtypes = [P(OraModel)]
@@ -178,6 +188,15 @@ def rate(form: str, coefs, V: float):
     dv = ctypes.c_double()
     r = lib().ora_rate(FORMS[form], k, float(V), ctypes.byref(dv))
     return float(r), float(dv.value)
+
+
+def gate_pq(model: dict, g: int, V: float):
+    """(P, Q) of gate g at V, the terms of the gate update p' = p + (P - p) Q:
+    exact, or interpolated when the model carries a "table"."""
+    s = model_to_struct(model)
+    P, Q = ctypes.c_double(), ctypes.c_double()
+    lib().ora_gate_pq(ctypes.byref(s), None, 1, 0, int(g), float(V), ctypes.byref(P), ctypes.byref(Q))
+    return P.value, Q.value
 
 
 def n_state(model: dict) -> int:

@@ -558,3 +558,118 @@ def test_cortical_steady_state_inftau_gate(ora):
     for V in (-80.0, -35.0, -10.0):
         st = ora.init_state(m, [V])
         assert st[4, 0] == pytest.approx(1 / (1 + np.exp(-(V + 35) / 10)), rel=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Tabulated gate kinetics: p_inf(V) and q(V) = 1 - exp(-dt/tau(V)) replaced by
+# their straight-line interpolants between equally spaced nodes.
+# ---------------------------------------------------------------------------
+_TAB = (-100.0, 60.0, 161)  # h = 1 mV
+
+
+def _with_table(model, tab):
+    return dict(model, table=tab)
+
+
+def _classic_pq(ora, V, dt):
+    """Exact (P, Q) of the three classic gates at V from the textbook rate pairs."""
+    pairs = [(("linoid", (0.1, -40, 10, 0)), ("exp", (4, -65, -18, 0))),
+             (("exp", (0.07, -65, -20, 0)), ("sigmoid", (1, -35, -10, 0))),
+             (("linoid", (0.01, -55, 10, 0)), ("exp", (0.125, -65, -80, 0)))]
+    out = []
+    for ra, rb in pairs:
+        a = ora.rate(ra[0], ra[1], V)[0]
+        b = ora.rate(rb[0], rb[1], V)[0]
+        out.append((a / (a + b), 1.0 - np.exp(-(a + b) * dt)))
+    return out
+
+
+@pytest.mark.parametrize("which", ["classic", "cortical"])
+def test_table_exact_at_nodes_and_clamped_outside(ora, which):
+    m = W.classic_hh(dt=0.025) if which == "classic" else W.custom_channels(dt=0.025)
+    mt = _with_table(m, _TAB)
+    v_lo, v_hi, nn = _TAB
+    h = (v_hi - v_lo) / (nn - 1)
+    for g in range(len(m["gates"])):
+        for k in (0, 1, 37, 80, 159, 160):
+            V = v_lo + k * h
+            P, Q = ora.gate_pq(m, g, V)
+            Pt, Qt = ora.gate_pq(mt, g, V)
+            assert abs(Pt - P) < 1e-14 and abs(Qt - Q) < 1e-14, (g, k)
+        for V, edge in ((-130.0, v_lo), (-100.5, v_lo), (60.25, v_hi), (95.0, v_hi)):
+            assert ora.gate_pq(mt, g, V) == pytest.approx(ora.gate_pq(m, g, edge), abs=1e-14)
+
+
+@pytest.mark.parametrize("V", [-50.0, -48.3, 12.7])
+def test_table_gate_closed_form_at_clamped_voltage(ora, V):
+    """With V held fixed the tabulated gate obeys p_{k+1} = p_k + (P - p_k) Q
+    with constant P, Q, so p_K = P + (p_0 - P)(1 - Q)^K; P and Q are the
+    straight-line interpolants of the textbook p_inf and q between the two
+    nodes around V (V = -50 sits on a node)."""
+    dt = 0.05
+    m = _with_table(W.classic_hh(dt=dt, C=1e300), _TAB)
+    st = ora.init_state(W.classic_hh(dt=dt), [-70.0])
+    p0 = st[1:, 0].copy()
+    st[0, 0] = V
+    K = 41
+    ora.run(m, st, K, record_spikes=False)
+    v_lo, v_hi, nn = _TAB
+    h = (v_hi - v_lo) / (nn - 1)
+    k = int(np.floor((V - v_lo) / h))
+    t = (V - v_lo) / h - k
+    a, b = _classic_pq(ora, v_lo + k * h, dt), _classic_pq(ora, v_lo + (k + 1) * h, dt)
+    for g in range(3):
+        P = (1 - t) * a[g][0] + t * b[g][0]
+        Q = (1 - t) * a[g][1] + t * b[g][1]
+        exact = P + (p0[g] - P) * (1 - Q) ** K
+        assert abs(st[1 + g, 0] - exact) < 1e-13, (g, st[1 + g, 0], exact)
+    assert st[0, 0] == V
+
+
+@pytest.mark.parametrize("which", ["classic", "cortical"])
+def test_table_interpolation_error_bound(ora, which):
+    """Linear interpolation error is at most h^2/8 max|f''| on each segment
+    (f'' bounded by second differences of the exact function on a grid of
+    h/16 inside the segment, with a 10% margin for that estimate)."""
+    m = W.classic_hh(dt=0.025) if which == "classic" else W.custom_channels(dt=0.025)
+    v_lo, v_hi, nn = -100.0, 60.0, 81  # h = 2 mV: the error is far above rounding
+    mt = _with_table(m, (v_lo, v_hi, nn))
+    h = (v_hi - v_lo) / (nn - 1)
+    s = h / 16
+    for g in range(len(m["gates"])):
+        for k in range(0, nn - 1, 3):
+            a = v_lo + k * h
+            xs = a + s * np.arange(-1, 18)
+            f = np.array([ora.gate_pq(m, g, x) for x in xs])  # [.., (P, Q)]
+            d2 = np.max(np.abs(f[2:] - 2 * f[1:-1] + f[:-2]), axis=0) / s ** 2
+            bound = 1.1 * h * h / 8 * d2 + 1e-15
+            for x in a + h * np.array([0.13, 0.5, 0.71, 0.94]):
+                err = np.abs(np.array(ora.gate_pq(mt, g, x)) - np.array(ora.gate_pq(m, g, x)))
+                assert np.all(err <= bound), (g, k, x, err, bound)
+
+
+@pytest.mark.parametrize("which", ["classic", "cortical"])
+def test_table_trajectories_converge_second_order(ora, which):
+    """Halving the node spacing divides the deviation of the tabulated
+    trajectories from the exact ones by about four (second-order
+    interpolation error; the V trace is a smooth function of it)."""
+    m = W.classic_hh(dt=0.025) if which == "classic" else W.custom_channels(dt=0.025)
+    n, T = 16, 2000
+    I = W.validation_currents(n, seed=5).astype(np.float64)
+    st0 = ora.init_state(m, np.full(n, -65.0))
+    ex = ora.run(m, st0.copy(), T, i_const=I, record_v=True)
+    assert ex["spikes"].sum() > 20
+    errs = []
+    for nn in (641, 1281, 2561):
+        tb = ora.run(_with_table(m, (-100.0, 60.0, nn)), st0.copy(), T, i_const=I, record_v=True)
+        errs.append(np.max(np.abs(tb["v"] - ex["v"])))
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(3.5 < r < 4.5 for r in ratios), (errs, ratios)
+    assert errs[-1] < 0.5
+
+
+def test_table_not_accepted_by_bptt(ora):
+    m = _with_table(W.classic_hh(dt=0.025), _TAB)
+    st0 = ora.init_state(W.classic_hh(dt=0.025), [-65.0])
+    with pytest.raises(ValueError):
+        ora.bptt(m, st0, np.zeros((4, 1)), dL_dr=np.ones(1))
