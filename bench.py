@@ -54,7 +54,7 @@ FORM_COST = {"exp": (3, 1), "sigmoid": (4, 2), "linoid": (5, 2), "bell": (5, 2)}
 POW_MULS = {0: 0, 1: 0, 2: 1, 3: 2, 4: 2}
 
 
-def alg_ops_per_update(model: dict, noise: bool, synapses: bool = False):
+def alg_ops_per_update(model: dict, noise: bool, synapses: bool = False, table: bool = False):
     """Algorithmic operation count of one neuron-update, from the oracle's
     formulas.  Returns (fp32 ops, transcendentals, integer ops, 64-bit
     multiplies).
@@ -68,9 +68,15 @@ def alg_ops_per_update(model: dict, noise: bool, synapses: bool = False):
     noise (per step): Box-Muller gives 2 normals from (log, sqrt, cos, sin)
         and 5 ops; Philox4x32-10 gives 4 words from 10 rounds of two
         32x32->64 multiplies, 4 xors and 2 key additions; I = mu + s z -> 1
+    tabulated gate kinetics (table=True) replace every gate's rate terms:
+        locate V once (u = (V - v_lo) / h, clamp, floor, t = u - k) -> 6;
+        per gate P and Q by one FMA each, p' = p + (P - p) Q -> 4, plus
+        one 16-byte table read (not counted in slots)
     """
     fl = tr = it = m64 = 0.0
-    for g in model["gates"]:
+    if table:
+        fl += 6 + 4 * len(model["gates"])
+    for g in ([] if table else model["gates"]):
         for r in g["rates"]:
             a, b = FORM_COST[r[0]]
             fl += a
@@ -96,8 +102,8 @@ def alg_ops_per_update(model: dict, noise: bool, synapses: bool = False):
     return fl, tr, it, m64
 
 
-def slots_per_update(model, noise, synapses=False):
-    fl, tr, it, m64 = alg_ops_per_update(model, noise, synapses)
+def slots_per_update(model, noise, synapses=False, table=False):
+    fl, tr, it, m64 = alg_ops_per_update(model, noise, synapses, table)
     return fl + it + W_TRANS * tr + W_MUL64 * m64
 
 
@@ -188,6 +194,63 @@ def bench_headline(steps, warmup, fusion=32):
                      "ops_per_update": dict(zip(("fp32", "transcendental", "int", "mul64"),
                                                 alg_ops_per_update(m, True)))},
     }
+
+
+# ---------------------------------------------------------------------------
+# tabulated gate kinetics against the plain kernel on the headline workload
+# ---------------------------------------------------------------------------
+def bench_table(n=1 << 20, T=4000, nodes=(161, 641), eval_neurons=65536, fusion=32):
+    """The nominal cortical set (uniform coefficients: tables need them) on
+    n neurons x T steps of noisy input 5 + 3z, plain rate functions against
+    tables of the given node counts over [-100, 60] mV.  Kernel time from
+    events around the step call; spike-time error of each table against the
+    plain run on the first eval_neurons neurons."""
+    import torch
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import surrogate as SG
+    from paper_2601_21407_amd import workloads as W
+    m = W.custom_channels(dt=0.025)
+    M = hh.Model(m, n)
+    M.set_fusion(fusion)
+    st = M.new_state()
+    launches = (T + fusion - 1) // fusion
+
+    def timed_run(reps=3):
+        bits = torch.zeros((T, M.words), dtype=torch.int32, device="cuda")
+        ms = []
+        for k in range(reps + 1):
+            M.init_state(st, v0_scalar=-65.0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            M.step_n(st, T, 0, noise=(5.0, 3.0, 2), spikes=bits)
+            e1.record()
+            _sync()
+            if k:
+                ms.append(e0.elapsed_time(e1))
+        code, bad = M.check()
+        if code != 0:
+            raise RuntimeError("non-finite state in the table benchmark (neuron %d)" % bad)
+        return float(np.mean(ms)), bits.cpu().numpy()
+
+    ms_ref, ref = timed_run()
+    slots_ref = slots_per_update(m, noise=True)
+    rows = [dict(method="rate functions", ms=ms_ref, speedup=1.0, updates_per_s=n * T / ms_ref * 1e3,
+                 slots_per_update=slots_ref, avg_launch_us=ms_ref * 1e3 / launches,
+                 alu_frac=slots_ref * n * T / (ms_ref / 1e3) / PEAK_LANE_OPS,
+                 mean_abs_ms=0.0, p95_abs_ms=0.0, unmatched_frac=0.0)]
+    slots_tab = slots_per_update(m, noise=True, table=True)
+    for nn in nodes:
+        M.set_rate_table(-100.0, 60.0, nn)
+        ms, bits = timed_run()
+        e = SG.spike_time_error(ref, bits, n, 0.025, 0.025, max_neurons=eval_neurons)
+        rows.append(dict(method="table, %d nodes (h = %.3g mV)" % (nn, 160.0 / (nn - 1)), ms=ms,
+                         speedup=ms_ref / ms, updates_per_s=n * T / ms * 1e3,
+                         slots_per_update=slots_tab, avg_launch_us=ms * 1e3 / launches,
+                         alu_frac=slots_tab * n * T / (ms / 1e3) / PEAK_LANE_OPS,
+                         table_bytes=5 * nn * 16, **e))
+        del bits
+    M.set_rate_table(0.0, 0.0, 0)
+    return {"n": n, "T": T, "fusion": fusion, "input": "noise 5 + 3z", "rows": rows}
 
 
 def cpu_baseline_headline(n_sample=8192):
@@ -532,6 +595,14 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
     ms_plain_noise, _ = kernel_time(lambda: SG.plain_run(n, T, noise=(5.0, 3.0, 2), spikes=False))
     rows.append(dict(method="plain dt=0.025 (reference)", ms=ms_ref, speedup=1.0,
                      mean_abs_ms=0.0, p95_abs_ms=0.0, unmatched_frac=0.0))
+    for nn in (161, 641):
+        mst, (_, _, bits_t) = kernel_time(lambda: SG.plain_run(n, T, i_dense=I,
+                                                               table=(-100.0, 60.0, nn)))
+        e = SG.spike_time_error(ref_np, bits_t.cpu().numpy(), n, 0.025, 0.025,
+                                max_neurons=eval_neurons)
+        rows.append(dict(method="plain dt=0.025 tabulated %d nodes" % nn, ms=mst,
+                         speedup=ms_ref / mst, **e))
+        del bits_t
     for dt, vm in ((0.05, "fe"), (0.1, "ee"), (0.25, "ee")):
         r = int(round(dt / 0.025))
         Ic = SG.coarse_input(I, r)
@@ -653,7 +724,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--parts", default="layer,net,surrogate,probe")
+    ap.add_argument("--parts", default="layer,net,surrogate,table,probe")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--counters", action="store_true",
                     help="run the copy + one headline launch for rocprofv3 counter passes")
@@ -686,6 +757,9 @@ def main():
     if "surrogate" in parts:
         extra["surrogate"] = bench_surrogate()
         print("[bench] surrogate done", file=sys.stderr, flush=True)
+    if "table" in parts:
+        extra["tabulated_kinetics"] = bench_table()
+        print("[bench] table done", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline_headline()
 
     line = {

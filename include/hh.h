@@ -144,6 +144,23 @@ int32_t hh_set_fusion(hh_model* m, int32_t k_steps);
  * (results are identical up to FP32 rounding order).  Default 1. */
 int32_t hh_set_specialize(hh_model* m, int32_t on);
 
+/* Tabulated gate kinetics, an approximation of the rate functions (Methods,
+ * "Engineering optimization": the rates' cost is cut by cheaper
+ * approximations).  The gate update p' = p + (p_inf - p) q, q = 1 - e
+ * (exponential Euler, "Simplified discretization") then takes p_inf(V) and
+ * q(V) by linear interpolation between n_nodes equally spaced voltages from
+ * v_lo to v_hi (mV), tabulated once from the model's rate functions on the
+ * device (q without cancellation); V outside [v_lo, v_hi] is clamped to the
+ * range.  The membrane update is unchanged.  The table (n_gates x n_nodes x
+ * 16 bytes) is owned by the model and used by every later hh_step_n;
+ * n_nodes = 0 removes it.  Errors: HH_E_SHAPE for n_nodes outside [2, 2^20];
+ * HH_E_INVALID for v_hi <= v_lo or non-finite bounds; HH_E_UNSUPPORTED unless
+ * the channel set is one of the compiled ones (hh_set_specialize on), the
+ * coefficients are uniform (no per-neuron table) and no network is attached.
+ * hh_backward, hh_surrogate_step_n and the network path return
+ * HH_E_UNSUPPORTED while a table is set (they evaluate the rate functions). */
+int32_t hh_set_rate_table(hh_model* m, float v_lo, float v_hi, int32_t n_nodes, void* stream);
+
 /* state <- (V0, p_inf(V0) for every gate, g_e = g_i = 0, V_lo = 0).  v0: nullable [n]
  * device array; when NULL every neuron starts at v0_scalar. */
 int32_t hh_init_state(hh_model* m, float* state, const float* v0, float v0_scalar, void* stream);

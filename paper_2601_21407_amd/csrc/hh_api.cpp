@@ -151,6 +151,7 @@ int32_t hh_init(hh_model** out, const hh_model_desc* desc, int64_t N, int32_t B,
 
 int32_t hh_destroy(hh_model* m) {
   if (!m) return HH_OK;
+  if (m->d_tab) (void)hipFree(m->d_tab);
   if (m->d_scratch) (void)hipFree(m->d_scratch);
   if (m->d_flags) (void)hipFree(m->d_flags);
   delete m;
@@ -175,6 +176,39 @@ int32_t hh_set_specialize(hh_model* m, int32_t on) {
   return HH_OK;
 }
 
+int32_t hh_set_rate_table(hh_model* m, float v_lo, float v_hi, int32_t n_nodes, void* stream) {
+  if (!m) return HH_E_INVALID;
+  if (n_nodes == 0) {
+    if (m->d_tab) {
+      HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+      HIP_OK(hipFree(m->d_tab));
+    }
+    m->d_tab = nullptr;
+    m->tab_n = 0;
+    return HH_OK;
+  }
+  if (n_nodes < 2 || n_nodes > (1 << 20)) return HH_E_SHAPE;
+  if (!(v_hi > v_lo) || !(fabsf(v_lo) < 1e30f) || !(fabsf(v_hi) < 1e30f)) return HH_E_INVALID;
+  // the tabulated step exists for the built-in channel sets with uniform
+  // coefficients, outside the network (the network, adjoint and surrogate
+  // kernels evaluate the rate functions)
+  if (m->coef || m->row_ptr || !m->use_fixed) return HH_E_UNSUPPORTED;
+  if (!(hhk::ClassicSpec::matches(m->km) || hhk::CorticalSpec::matches(m->km))) return HH_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = (size_t)m->km.n_gates * (size_t)n_nodes * sizeof(float4);
+  if (m->d_tab && m->tab_n != n_nodes) {
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipFree(m->d_tab));
+    m->d_tab = nullptr;
+  }
+  if (!m->d_tab && hipMalloc((void**)&m->d_tab, bytes) != hipSuccess) return HH_E_OOM;
+  m->tab_n = n_nodes;
+  m->tab_vlo = v_lo;
+  m->tab_h = (v_hi - v_lo) / (float)(n_nodes - 1);
+  HIP_OK(launch_build_table(m, s));
+  return HH_OK;
+}
+
 int32_t hh_init_state(hh_model* m, float* state, const float* v0, float v0s, void* stream) {
   if (!m || !state) return HH_E_INVALID;
   HIP_OK(launch_init_state(m, state, v0, v0s, (hipStream_t)stream));
@@ -193,6 +227,7 @@ int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const 
   if (in->mode == HH_IN_CONST && !in->i_const) return HH_E_INVALID;
   if (in->mode == HH_IN_DENSE && !in->i_dense) return HH_E_INVALID;
   if (out->ckpt && out->ckpt_every < 1) return HH_E_SHAPE;
+  if (m->d_tab && (m->row_ptr || !m->use_fixed)) return HH_E_UNSUPPORTED;
   if (m->row_ptr) return hh_net_step_n_internal(m, state, t0, n_steps, in, out, stream);
   if (n_steps == 0) return HH_OK;
   hipStream_t s = (hipStream_t)stream;
@@ -213,6 +248,12 @@ int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const 
   a.ckpt_every = out->ckpt ? out->ckpt_every : 1;
   a.level = out->level;
   a.bad = m->d_flags;
+  if (m->d_tab) {
+    a.tab = m->d_tab;
+    a.tab_n = m->tab_n;
+    a.tab_vlo = m->tab_vlo;
+    a.tab_inv_h = 1.0f / m->tab_h;
+  }
   for (int32_t kb = 0; kb < n_steps; kb += m->k_fuse) {
     const int32_t ns = (n_steps - kb < m->k_fuse) ? n_steps - kb : m->k_fuse;
     a.t0 = t0 + kb;

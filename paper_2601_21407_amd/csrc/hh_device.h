@@ -178,6 +178,27 @@ __device__ __forceinline__ KRate derive_rate(int form, float A, float B, float K
   return k;
 }
 
+// Tabulated gate kinetics (the rate-function approximation lever of the
+// method, Engineering: rates replaced by cheaper approximations).  For gate g
+// and voltage node i (V_i = v_lo + i h), tab[g n + i] holds
+//   { P(V_i), P(V_i+1) - P(V_i), Q(V_i), Q(V_i+1) - Q(V_i) }
+// with P = p_inf and Q = 1 - e, the fraction of the way to p_inf that one
+// exponential-Euler step covers.  Between nodes both are interpolated
+// linearly in V; V outside [v_lo, v_lo + (n-1) h] is clamped to the range.
+struct TabRates {
+  const float4* tab;
+  int n;
+  float v_lo, inv_h;
+};
+template <class LR>
+struct is_tab {
+  static constexpr bool value = false;
+};
+template <>
+struct is_tab<TabRates> {
+  static constexpr bool value = true;
+};
+
 // A copy of x in a vector register that the compiler cannot re-derive from a
 // scalar original: it then keeps the register for the whole loop instead of
 // copying the scalar into a vector register at every use (a vector
@@ -268,9 +289,10 @@ __device__ __forceinline__ float expm1_neg(float z) {
 // start-of-step state).  p is updated in place; (vh, vl) likewise.
 // I: external current; ge, gi: synaptic conductances held over the step.
 // SYN = false: the caller knows the population has no synapses (ge = gi = 0);
-// the synaptic terms are left out, which gives bit-identical results.
-template <class S, bool SYN = true>
-__device__ __forceinline__ void neuron_step(const KModel& M, const LaneRates<S::kNG>& L, float dtC,
+// the synaptic terms are left out, which gives bit-identical results.  LR:
+// LaneRates (rate functions) or TabRates (tabulated gate kinetics).
+template <class S, bool SYN = true, class LR = LaneRates<S::kNG>>
+__device__ __forceinline__ void neuron_step(const KModel& M, const LR& L, float dtC,
                                             float& vh, float& vl, float (&p)[ng1<S::kNG>], float I,
                                             float ge, float gi) {
   constexpr int NG = S::kNG;
@@ -295,20 +317,33 @@ __device__ __forceinline__ void neuron_step(const KModel& M, const LaneRates<S::
     esum = fmaf(eta, M.E[c], esum);
   }
   // gates by exponential Euler at V_t
+  if constexpr (is_tab<LR>::value) {
+    // one voltage index for all gates, then per gate one 16-byte table read
+    const float u = fminf(fmaxf((V - L.v_lo) * L.inv_h, 0.0f), (float)(L.n - 1));
+    const int ix = min((int)u, L.n - 2);
+    const float t = u - (float)ix;
 #pragma unroll
-  for (int g = 0; g < NG; ++g) {
-    const float r0 = rate_eval<false>(S::form(M, g, 0), L.r[g][0], V, nullptr);
-    const float r1 = rate_eval<false>(S::form(M, g, 1), L.r[g][1], V, nullptr);
-    float pinf, e;
-    if (S::kind(M, g) == KIND_AB) {
-      const float s = r0 + r1;
-      pinf = r0 * rcp(s);
-      e = ex2(s * M.kdt);
-    } else {
-      pinf = r0;
-      e = ex2(r1 * M.kdt);
+    for (int g = 0; g < NG; ++g) {
+      const float4 c = L.tab[g * L.n + ix];
+      const float P = fmaf(c.y, t, c.x), Q = fmaf(c.w, t, c.z);
+      p[g] = fmaf(P - p[g], Q, p[g]);
     }
-    p[g] = gate_update(p[g], pinf, e);
+  } else {
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const float r0 = rate_eval<false>(S::form(M, g, 0), L.r[g][0], V, nullptr);
+      const float r1 = rate_eval<false>(S::form(M, g, 1), L.r[g][1], V, nullptr);
+      float pinf, e;
+      if (S::kind(M, g) == KIND_AB) {
+        const float s = r0 + r1;
+        pinf = r0 * rcp(s);
+        e = ex2(s * M.kdt);
+      } else {
+        pinf = r0;
+        e = ex2(r1 * M.kdt);
+      }
+      p[g] = gate_update(p[g], pinf, e);
+    }
   }
   // membrane
   float dv;

@@ -24,6 +24,10 @@ struct StepArgs {
   int32_t ckpt_every;
   float* level;
   int32_t* bad;
+  // tabulated gate kinetics (null: the rate functions)
+  const float4* tab;
+  int32_t tab_n;
+  float tab_vlo, tab_inv_h;
 };
 
 struct hh_model {
@@ -52,11 +56,17 @@ struct hh_model {
   // counters and the grid barrier
   void* d_scratch;
   size_t scratch_bytes;
+  // tabulated gate kinetics, owned by the model (null: none)
+  float4* d_tab;
+  int32_t tab_n;
+  float tab_vlo, tab_h;
 };
 
 hipError_t launch_init_state(const hh_model* m, float* state, const float* v0, float v0s,
                              hipStream_t s);
 hipError_t launch_step(const hh_model* m, const StepArgs& a, hipStream_t s);
+// fills m->d_tab (m->tab_n nodes from m->tab_vlo, spacing m->tab_h)
+hipError_t launch_build_table(const hh_model* m, hipStream_t s);
 
 // recurrent network path of hh_step_n (hh_net.hip)
 int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_steps,

@@ -45,8 +45,19 @@ __global__ __launch_bounds__(256) void k_init_state(KModel M, float* __restrict_
 // terms drop out of the step (bit-identical results).
 enum { LOOP_GEN = 0, LOOP_DENSE = 1, LOOP_NOISE = 2 };
 
-template <class S, bool JIT, int LOOP, bool SYN>
+// TAB: tabulated gate kinetics (A.tab) in place of the rate functions; only
+// with uniform coefficients (JIT = false).  TAB_GLOBAL gathers the entries
+// from the device table (served by L1/L2); TAB_LDS first copies the table
+// into LDS (dynamic size n_gates x n_nodes x 16 bytes), whose bandwidth is
+// twice that of the L1 path.
+enum { TAB_NONE = 0, TAB_GLOBAL = 1, TAB_LDS = 2 };
+// Largest table staged in LDS: seven 256-lane blocks per compute unit (the
+// step's occupancy) then fit the 160 KiB of LDS.
+constexpr int kTabLdsMaxBytes = 20 * 1024;
+
+template <class S, bool JIT, int LOOP, bool SYN, int TAB = TAB_NONE>
 __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
+  static_assert(!(TAB != TAB_NONE && JIT), "tabulated kinetics need uniform coefficients");
   constexpr bool PF = LOOP == LOOP_DENSE;
   constexpr int NG = S::kNG;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -57,7 +68,22 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
 
   LaneRates<NG> L;
   load_rates<S>(M, JIT ? A.coef : nullptr, pidx, A.N, L);
-  if constexpr (!JIT && LOOP != LOOP_GEN) {
+  TabRates LT;
+  if constexpr (TAB != TAB_NONE) {
+    LT.tab = A.tab;
+    LT.n = A.tab_n;
+    LT.v_lo = A.tab_vlo;
+    LT.inv_h = A.tab_inv_h;
+  }
+  if constexpr (TAB == TAB_LDS) {
+    // every lane of the block reaches this point (no early exit above)
+    extern __shared__ float4 tab_lds[];
+    const int cnt = NG * A.tab_n;
+    for (int x = threadIdx.x; x < cnt; x += blockDim.x) tab_lds[x] = A.tab[x];
+    __syncthreads();
+    LT.tab = tab_lds;
+  }
+  if constexpr (!JIT && TAB == TAB_NONE && LOOP != LOOP_GEN) {
     // uniform rate offsets pinned in vector registers for the launch, so
     // that x = V s + o reads one scalar operand (s) and needs no copy
 #pragma unroll
@@ -128,7 +154,10 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
         }
         if (to_ck > 0) --to_ck;
         const float V = vh;
-        neuron_step<S, SYN>(M, L, dtC, vh, vl, p, Icur[j], ge, gi);
+        if constexpr (TAB != TAB_NONE)
+          neuron_step<S, SYN>(M, LT, dtC, vh, vl, p, Icur[j], ge, gi);
+        else
+          neuron_step<S, SYN>(M, L, dtC, vh, vl, p, Icur[j], ge, gi);
         const float Vn = vh;
         const bool spk = act && (V < M.v_th) && (Vn >= M.v_th);
         if (A.spikes) {
@@ -171,7 +200,10 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
       }
       if (to_ck > 0) --to_ck;
       const float V = vh;
-      neuron_step<S, SYN>(M, L, dtC, vh, vl, p, I, ge, gi);
+      if constexpr (TAB != TAB_NONE)
+        neuron_step<S, SYN>(M, LT, dtC, vh, vl, p, I, ge, gi);
+      else
+        neuron_step<S, SYN>(M, L, dtC, vh, vl, p, I, ge, gi);
       const float Vn = vh;
       const bool spk = act && (V < M.v_th) && (Vn >= M.v_th);
       if (A.spikes) {
@@ -231,7 +263,10 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
         I = A.i_dense[(int64_t)k * n + ii];
       }
       const float V = vh;
-      neuron_step<S>(M, L, dtC, vh, vl, p, I, ge, gi);
+      if constexpr (TAB != TAB_NONE)
+        neuron_step<S>(M, LT, dtC, vh, vl, p, I, ge, gi);
+      else
+        neuron_step<S>(M, L, dtC, vh, vl, p, I, ge, gi);
       const float Vn = vh;
       const bool spk = act && (V < M.v_th) && (Vn >= M.v_th);
       if (A.spikes) {
@@ -266,6 +301,37 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
   if (!__builtin_isfinite(chk)) atomicMin(A.bad, (int32_t)i);
 }
 
+// Table of the gate kinetics at nodes V_i = v_lo + i h (one lane per gate and
+// node), from the same rate functions as the step: P = p_inf and Q = 1 - e,
+// with 1 - e taken without cancellation (e is close to 1 for slow gates).
+template <class S>
+__global__ __launch_bounds__(256) void k_build_table(KModel M, float v_lo, float h, int n,
+                                                     float4* __restrict__ tab) {
+  constexpr int NG = S::kNG;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= NG * n) return;
+  const int g = x / n, i = x % n;
+  float P[2], Q[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float V = v_lo + (float)min(i + j, n - 1) * h;
+    const float r0 = rate_eval<false>(S::form(M, g, 0), M.rate[g][0], V, nullptr);
+    const float r1 = rate_eval<false>(S::form(M, g, 1), M.rate[g][1], V, nullptr);
+    const float s = S::kind(M, g) == KIND_AB ? r0 + r1 : r1;  // 1 / tau
+    P[j] = S::kind(M, g) == KIND_AB ? r0 / s : r0;
+    Q[j] = -expm1_neg(M.dt * s);
+  }
+  tab[x] = make_float4(P[0], P[1] - P[0], Q[0], Q[1] - Q[0]);
+}
+
+template <class S>
+static hipError_t table_spec(const hh_model* m, hipStream_t s) {
+  const int count = S::kNG * m->tab_n;
+  hipLaunchKernelGGL(k_build_table<S>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, m->km,
+                     m->tab_vlo, m->tab_h, m->tab_n, m->d_tab);
+  return hipGetLastError();
+}
+
 template <class S>
 static hipError_t init_spec(const hh_model* m, float* state, const float* v0, float v0s,
                             hipStream_t s) {
@@ -273,6 +339,22 @@ static hipError_t init_spec(const hh_model* m, float* state, const float* v0, fl
   const int64_t nb = (m->n + bs - 1) / bs;
   hipLaunchKernelGGL(k_init_state<S>, dim3((unsigned)nb), dim3(bs), 0, s, m->km, state, m->n,
                      m->N, m->coef, v0, v0s);
+  return hipGetLastError();
+}
+
+template <class S, int TAB>
+static hipError_t step_tab(const hh_model* m, const StepArgs& a, hipStream_t s, dim3 grid, dim3 block,
+                           size_t lds) {
+  const bool syn = m->km.has_syn != 0;
+  if (a.in_mode == IN_DENSE) {
+    if (syn) hipLaunchKernelGGL((k_step<S, false, LOOP_DENSE, true, TAB>), grid, block, lds, s, m->km, a);
+    else hipLaunchKernelGGL((k_step<S, false, LOOP_DENSE, false, TAB>), grid, block, lds, s, m->km, a);
+  } else if (a.in_mode == IN_NOISE) {
+    if (syn) hipLaunchKernelGGL((k_step<S, false, LOOP_NOISE, true, TAB>), grid, block, lds, s, m->km, a);
+    else hipLaunchKernelGGL((k_step<S, false, LOOP_NOISE, false, TAB>), grid, block, lds, s, m->km, a);
+  } else {
+    hipLaunchKernelGGL((k_step<S, false, LOOP_GEN, true, TAB>), grid, block, lds, s, m->km, a);
+  }
   return hipGetLastError();
 }
 
@@ -285,6 +367,11 @@ static hipError_t step_spec(const hh_model* m, const StepArgs& a, hipStream_t s)
   const bool jit = a.coef != nullptr;
   if constexpr (S::kFixed) {
     const bool syn = m->km.has_syn != 0;
+    if (a.tab) {  // validated when the table was set: uniform coefficients
+      const size_t bytes = (size_t)S::kNG * (size_t)a.tab_n * sizeof(float4);
+      if (bytes <= (size_t)kTabLdsMaxBytes) return step_tab<S, TAB_LDS>(m, a, s, grid, block, bytes);
+      return step_tab<S, TAB_GLOBAL>(m, a, s, grid, block, 0);
+    }
     if (a.in_mode == IN_DENSE || a.in_mode == IN_NOISE) {
 #define HH_LAUNCH(LOOP)                                                                        \
   do {                                                                                         \
@@ -332,6 +419,13 @@ struct InitF {
   }
 };
 template <class S>
+struct TableF {
+  static hipError_t run(const hh_model* m, hipStream_t s) {
+    if constexpr (S::kFixed) return table_spec<S>(m, s);
+    return hipErrorInvalidValue;  // tables are set only for the built-in sets
+  }
+};
+template <class S>
 struct StepF {
   static hipError_t run(const hh_model* m, const StepArgs& a, hipStream_t s) {
     return step_spec<S>(m, a, s);
@@ -346,4 +440,8 @@ hipError_t launch_init_state(const hh_model* m, float* state, const float* v0, f
 hipError_t launch_step(const hh_model* m, const StepArgs& a, hipStream_t s) {
   return dispatch_spec<StepF, const hh_model*, const StepArgs&, hipStream_t>(m->km, m->use_fixed, m,
                                                                                a, s);
+}
+
+hipError_t launch_build_table(const hh_model* m, hipStream_t s) {
+  return dispatch_spec<TableF, const hh_model*, hipStream_t>(m->km, true, m, s);
 }

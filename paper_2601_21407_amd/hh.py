@@ -77,6 +77,7 @@ def _load():
         "hh_n_state": ([vp], i32),
         "hh_set_fusion": ([vp, i32], i32),
         "hh_set_specialize": ([vp, i32], i32),
+        "hh_set_rate_table": ([vp, f32, f32, i32, vp], i32),
         "hh_init_state": ([vp, vp, vp, f32, vp], i32),
         "hh_step_n": ([vp, vp, i64, i32, P(Input), P(Outputs), vp], i32),
         "hh_attach_csr": ([vp, vp, vp, vp, i64, f32], i32),
@@ -120,7 +121,7 @@ lib = _load()
 def exported_symbols():
     """Names of the C-ABI entry points this binding uses."""
     return [n for n in ("hh_init", "hh_destroy", "hh_status_string", "hh_n_state", "hh_set_fusion",
-                        "hh_set_specialize",
+                        "hh_set_specialize", "hh_set_rate_table",
                         "hh_init_state", "hh_step_n", "hh_attach_csr", "hh_set_external",
                         "hh_syn_propagate", "hh_backward", "hh_backward_part",
                         "hh_backward_workspace", "hh_check",
@@ -204,6 +205,11 @@ class Model:
 
     def set_specialize(self, on: bool):
         _ok(lib.hh_set_specialize(self.h, 1 if on else 0), "hh_set_specialize")
+
+    def set_rate_table(self, v_lo: float, v_hi: float, n_nodes: int):
+        """Tabulated gate kinetics on [v_lo, v_hi] mV with n_nodes nodes; 0 removes it."""
+        _ok(lib.hh_set_rate_table(self.h, float(v_lo), float(v_hi), int(n_nodes), _stream()),
+            "hh_set_rate_table")
 
     def new_state(self, device="cuda"):
         return torch.empty((self.n_state, self.n), dtype=torch.float32, device=device)

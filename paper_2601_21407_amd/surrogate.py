@@ -186,9 +186,13 @@ def deploy(packed, n, T, *, i_dense=None, noise=None, spikes=True, check_every=C
 
 
 def plain_run(n, T, *, dt=0.025, v_method="fe", i_dense=None, noise=None, spikes=True,
-              dev="cuda"):
+              dev="cuda", table=None):
+    """The plain kernel on the same workload; table = (v_lo, v_hi, n_nodes)
+    switches to tabulated gate kinetics."""
     m = W.custom_channels(dt=dt, v_method=v_method)
     M = hh.Model(m, n)
+    if table is not None:
+        M.set_rate_table(*table)
     st = M.new_state()
     M.init_state(st, v0_scalar=-65.0)
     bits = torch.zeros((T, M.words), dtype=torch.int32, device=dev) if spikes else None

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _run_gpu(model, n, T, *, B=1, i_const=None, noise=None, i_dense=None, coef=None, cm=None,
-             v0=-65.0, record_v=False, fusion=32, t0=0, state=None, specialize=True):
+             v0=-65.0, record_v=False, fusion=32, t0=0, state=None, specialize=True, table=None):
     torch = need_gpu()
     from paper_2601_21407_amd import hh
     N = n // B
@@ -29,6 +29,8 @@ def _run_gpu(model, n, T, *, B=1, i_const=None, noise=None, i_dense=None, coef=N
     M = hh.Model(model, N, B, coef=coef_t, cm=cm_t)
     M.set_fusion(fusion)
     M.set_specialize(specialize)
+    if table is not None:
+        M.set_rate_table(*table)
     st = M.new_state() if state is None else state
     if state is None:
         if np.isscalar(v0):
