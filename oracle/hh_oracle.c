@@ -324,6 +324,89 @@ int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double*
   return 0;
 }
 
+/* Multi-compartment neurons (Methods, Eq. (1) with the spatial term
+ * (1/r_l) d2V/dx2; "Simplified discretization": a second-order explicit
+ * difference in space).  Compartment c of neuron j is element j*K + c.  The
+ * edge between c and parent[c] has conductance g_axial[c] per unit reference
+ * area; the current it carries into compartment x (one of its two ends) per
+ * unit of x's area is g_axial[c] / area[x] (V_other - V_x), so the charge
+ * sum_x area[x] C V_x is conserved by the coupling.  All potentials are
+ * those at the start of the step (explicit), and each compartment then takes
+ * the point-neuron step with I + I_axial as its input.  gbar [K][n_channels]
+ * (nullable) replaces the channel conductances per compartment; coef
+ * (nullable) holds per-element rate coefficients as in ora_run.  The steps
+ * run in time order, all compartments within each step. */
+int32_t ora_cable_run(const ora_model* m, int64_t n, int32_t K, const int32_t* parent,
+                      const double* g_axial, const double* area, const double* gbar,
+                      const double* coef, const double* cm, double* state, int64_t t0, int32_t T, int32_t in_mode,
+                      const double* i_const, double mu, double sigma, uint64_t seed,
+                      const double* i_dense, uint8_t* spk, double* vrec) {
+  if (!model_ok(m) || K < 1 || n < 0 || T < 0 || n % K != 0) return -1;
+  for (int32_t c = 0; c < K; ++c)
+    if (parent[c] < -1 || parent[c] >= c) return -1;
+  const int G = m->n_gates;
+  double* Vt = (double*)malloc(sizeof(double) * (size_t)(n ? n : 1));
+  double* iax = (double*)malloc(sizeof(double) * (size_t)(n ? n : 1));
+  ora_model* mc = (ora_model*)malloc(sizeof(ora_model) * (size_t)K);
+  if (!Vt || !iax || !mc) {
+    free(Vt);
+    free(iax);
+    free(mc);
+    return -2;
+  }
+  for (int32_t c = 0; c < K; ++c) {
+    mc[c] = *m;
+    if (gbar)
+      for (int x = 0; x < m->n_channels; ++x) mc[c].ch_gbar[x] = gbar[(int64_t)c * m->n_channels + x];
+  }
+  const double de = m->has_syn ? exp(-m->dt / m->tau_e) : 1.0;
+  const double di = m->has_syn ? exp(-m->dt / m->tau_i) : 1.0;
+  for (int32_t k = 0; k < T; ++k) {
+    const int64_t t = t0 + k;
+    for (int64_t i = 0; i < n; ++i) {
+      Vt[i] = state[i];
+      iax[i] = 0.0;
+    }
+    /* every edge adds to both of its ends */
+    for (int64_t j = 0; j < n / K; ++j)
+      for (int32_t c = 0; c < K; ++c) {
+        const int32_t p = parent[c];
+        if (p < 0) continue;
+        const int64_t ic = j * K + c, ip = j * K + p;
+        const double ac = area ? area[c] : 1.0, ap = area ? area[p] : 1.0;
+        iax[ic] += g_axial[c] / ac * (Vt[ip] - Vt[ic]);
+        iax[ip] += g_axial[c] / ap * (Vt[ic] - Vt[ip]);
+      }
+    for (int64_t i = 0; i < n; ++i) {
+      const ora_model* mi = &mc[i % K];
+      double V = state[i], p[ORA_MAX_GATES], pn[ORA_MAX_GATES], ge = 0.0, gi = 0.0;
+      for (int g = 0; g < G; ++g) p[g] = state[(int64_t)(1 + g) * n + i];
+      if (m->has_syn) {
+        ge = state[(int64_t)(1 + G) * n + i];
+        gi = state[(int64_t)(2 + G) * n + i];
+      }
+      double I = 0.0;
+      if (in_mode == ORA_IN_CONST) I = i_const[i];
+      else if (in_mode == ORA_IN_NOISE) I = mu + sigma * ora_noise(seed, (uint32_t)i, t);
+      else if (in_mode == ORA_IN_DENSE) I = i_dense[(int64_t)k * n + i];
+      double Vn;
+      neuron_step(mi, coef, n, i, cm ? cm[i] : m->C, V, p, ge, gi, I + iax[i], &Vn, pn);
+      if (spk) spk[(int64_t)k * n + i] = (uint8_t)(V < m->v_th && Vn >= m->v_th);
+      if (vrec) vrec[(int64_t)k * n + i] = Vn;
+      state[i] = Vn;
+      for (int g = 0; g < G; ++g) state[(int64_t)(1 + g) * n + i] = pn[g];
+      if (m->has_syn) {
+        state[(int64_t)(1 + G) * n + i] = ge * de;
+        state[(int64_t)(2 + G) * n + i] = gi * di;
+      }
+    }
+  }
+  free(Vt);
+  free(iax);
+  free(mc);
+  return 0;
+}
+
 void ora_syn_deliver(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* w,
                      double w_scale, const uint8_t* s, double* ge, double* gi) {
   for (int64_t j = 0; j < n; ++j) {

@@ -132,6 +132,9 @@ def lib():
         L.ora_rate.restype = d
         L.ora_gate_inf.argtypes = [P(OraModel), vp, i64, i64, i32, d]
         L.ora_gate_inf.restype = d
+        L.ora_cable_run.argtypes = [P(OraModel), i64, i32, vp, vp, vp, vp, vp, vp, vp, i64, i32,
+                                    i32, vp, d, d, u64, vp, vp, vp]
+        L.ora_cable_run.restype = i32
         L.ora_gate_pq.argtypes = [P(OraModel), vp, i64, i64, i32, d, P(d), P(d)]
         L.ora_gate_pq.restype = None
         L.ora_init_state.argtypes = [P(OraModel), vp, i64, vp, vp]
@@ -243,6 +246,42 @@ def run(model: dict, state: np.ndarray, T: int, t0: int = 0, *, i_const=None, no
     if rc != 0:
         raise ValueError("oracle rejected the model (rc=%d)" % rc)
     return {"spikes": spk, "v": vr, "level": lv}
+
+
+def cable_run(model: dict, state: np.ndarray, T: int, morph: dict, t0: int = 0, *, i_const=None,
+              noise_mu=None, noise_sigma=None, seed: int = 0, i_dense=None, coef=None, cm=None,
+              record_v: bool = False, record_spikes: bool = True):
+    """Advance multi-compartment neurons T steps in place (state [n_state][n],
+    n = N*K).  morph = {"K": K, "parent": [K], "g_axial": [K],
+    "area": [K] or None, "gbar": [K][n_channels] or None}.  Returns dict with
+    'spikes' [T][n] and 'v' [T][n] (optional), as run()."""
+    s = model_to_struct(model)
+    n = state.shape[1]
+    assert state.dtype == np.float64 and state.flags.c_contiguous
+    K = int(morph["K"])
+    parent = np.ascontiguousarray(morph["parent"], dtype=np.int32)
+    g_ax = _f64(np.zeros(K) if morph.get("g_axial") is None else morph["g_axial"])
+    area = _f64(morph.get("area"))
+    gbar = _f64(morph.get("gbar"))
+    if i_dense is not None:
+        mode, i_dense = IN_DENSE, _f64(i_dense)
+        assert i_dense.shape == (T, n)
+    elif noise_mu is not None:
+        mode = IN_NOISE
+    elif i_const is not None:
+        mode, i_const = IN_CONST, _f64(i_const)
+    else:
+        mode = IN_NONE
+    coef, cm = _f64(coef), _f64(cm)
+    spk = np.zeros((T, n), np.uint8) if record_spikes else None
+    vr = np.zeros((T, n), np.float64) if record_v else None
+    rc = lib().ora_cable_run(ctypes.byref(s), n, K, _p(parent), _p(g_ax), _p(area), _p(gbar),
+                             _p(coef), _p(cm), _p(state), int(t0), int(T), mode, _p(i_const),
+                             float(noise_mu or 0.0), float(noise_sigma or 0.0), int(seed),
+                             _p(i_dense), _p(spk), _p(vr))
+    if rc != 0:
+        raise ValueError("oracle rejected the model or morphology (rc=%d)" % rc)
+    return {"spikes": spk, "v": vr}
 
 
 def net_run(model: dict, state: np.ndarray, csr, w_scale: float, T: int, t0: int = 0, *,

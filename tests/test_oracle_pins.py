@@ -673,3 +673,156 @@ def test_table_not_accepted_by_bptt(ora):
     st0 = ora.init_state(W.classic_hh(dt=0.025), [-65.0])
     with pytest.raises(ValueError):
         ora.bptt(m, st0, np.zeros((4, 1)), dL_dr=np.ones(1))
+
+
+# ---------------------------------------------------------------------------
+# Multi-compartment neurons: the spatial term of Eq. (1) by the second-order
+# explicit difference, compartments coupled through their start-of-step
+# potentials.
+# ---------------------------------------------------------------------------
+def _passive(g_l=1.0, e_l=0.0, C=1.0, dt=0.01, v_method="fe"):
+    return {"gates": [], "channels": [{"gbar": g_l, "E": e_l, "gates": []}], "C": C, "dt": dt,
+            "v_th": 1e9, "v_method": v_method, "syn": None}
+
+
+def _soma_3_dendrites(n_dend=5):
+    parent = [-1]
+    for _ in range(3):
+        first = len(parent)
+        parent.append(0)
+        parent += list(range(first, first + n_dend - 1))
+    return parent
+
+
+def test_cable_single_compartment_is_the_point_neuron(ora):
+    m = W.classic_hh(dt=0.025)
+    n, T = 7, 600
+    st0 = ora.init_state(m, np.linspace(-70, -60, n))
+    a, b = st0.copy(), st0.copy()
+    ra = ora.run(m, a, T, noise_mu=6.0, noise_sigma=3.0, seed=3, record_v=True)
+    rb = ora.cable_run(m, b, T, {"K": 1, "parent": [-1]}, noise_mu=6.0, noise_sigma=3.0, seed=3,
+                       record_v=True)
+    assert np.array_equal(a, b) and np.array_equal(ra["v"], rb["v"])
+    assert np.array_equal(ra["spikes"], rb["spikes"]) and ra["spikes"].sum() > 0
+
+
+@pytest.mark.parametrize("v_method", ["fe", "ee"])
+def test_cable_passive_map_closed_form(ora, v_method):
+    """Leak-only compartments on a branched morphology with unequal areas:
+    one step is affine, V' = A V + b, so T steps give
+    V_T = V* + A^T (V_0 - V*) with V* = (1 - A)^-1 b (numpy matrix power and
+    solve), A built from the edge list: each edge moves charge between its
+    two ends in proportion to their potential difference."""
+    parent = [-1, 0, 1, 1, 0]
+    g_ax = [0.0, 0.5, 0.3, 0.7, 0.2]
+    area = [1.0, 0.5, 2.0, 1.0, 1.5]
+    K, N, T, dt, g_l, e_l, C = 5, 3, 300, 0.05, 0.3, -60.0, 1.3
+    m = _passive(g_l, e_l, C, dt, v_method)
+    rng = np.random.default_rng(4)
+    v0 = -70.0 + 20.0 * rng.random(N * K)
+    I = 2.0 * rng.random(N * K)
+    st = v0[None, :].copy()
+    ora.cable_run(m, st, T, {"K": K, "parent": parent, "g_axial": g_ax, "area": area},
+                  i_const=I, record_spikes=False)
+    Lax = np.zeros((K, K))  # axial current = Lax @ V per unit area
+    for c, p in enumerate(parent):
+        if p < 0:
+            continue
+        Lax[c, c] -= g_ax[c] / area[c]
+        Lax[c, p] += g_ax[c] / area[c]
+        Lax[p, p] -= g_ax[c] / area[p]
+        Lax[p, c] += g_ax[c] / area[p]
+    for j in range(N):
+        sl = slice(j * K, (j + 1) * K)
+        if v_method == "fe":
+            A = np.eye(K) + dt / C * (Lax - g_l * np.eye(K))
+            b = dt / C * (I[sl] + g_l * e_l)
+        else:
+            e = np.exp(-dt * g_l / C)
+            A = e * np.eye(K) + (1 - e) / g_l * Lax
+            b = (1 - e) / g_l * (I[sl] + g_l * e_l)
+        vs = np.linalg.solve(np.eye(K) - A, b)
+        want = vs + np.linalg.matrix_power(A, T) @ (v0[sl] - vs)
+        assert np.max(np.abs(st[0, sl] - want)) < 1e-10, (j, st[0, sl] - want)
+
+
+def test_cable_steady_state_second_order_in_space(ora):
+    """Uniform sealed-end cable of length L with leak g_l and input
+    A cos(pi x / L).  The discrete steady state is exactly
+    A cos(pi x_c / L) / (g_l + (2 - 2 cos(pi dx / L)) / (r_l dx^2)) at the
+    compartment centres (the cosine is an eigenvector of the chain with
+    reflecting ends), and it tends to the continuous solution
+    A cos(pi x / L) / (g_l + (pi / L)^2 / r_l) at second order in dx."""
+    Lc, r_l, g_l, Amp = 10.0, 1.0, 1.0, 3.0
+    errs = []
+    for K in (8, 16, 32):
+        dx = Lc / K
+        g = 1.0 / (r_l * dx * dx)
+        dt = 0.5 / (g_l + 4 * g)
+        m = _passive(g_l, 0.0, 1.0, dt)
+        x = (np.arange(K) + 0.5) * dx
+        I = Amp * np.cos(np.pi * x / Lc)
+        st = np.zeros((1, K))
+        T = int(40.0 / dt)
+        ora.cable_run(m, st, T, {"K": K, "parent": [-1] + list(range(K - 1)),
+                                 "g_axial": [0.0] + [g] * (K - 1)}, i_const=I, record_spikes=False)
+        disc = I / (g_l + (2 - 2 * np.cos(np.pi * dx / Lc)) / (r_l * dx * dx))
+        assert np.max(np.abs(st[0] - disc)) < 1e-9, K
+        cont = I / (g_l + (np.pi / Lc) ** 2 / r_l)
+        errs.append(np.max(np.abs(st[0] - cont)))
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(3.8 < r < 4.2 for r in ratios), (errs, ratios)
+
+
+def test_cable_coupling_conserves_charge(ora):
+    """Without membrane currents or input, the coupling only moves charge
+    between compartments: sum_c area_c C V_c stays fixed while the
+    potentials equalize."""
+    parent = _soma_3_dendrites(3)
+    K = len(parent)  # 10
+    rng = np.random.default_rng(8)
+    g_ax = [0.0] + list(0.2 + rng.random(K - 1))
+    area = list(0.5 + rng.random(K))
+    m = {"gates": [], "channels": [], "C": 1.0, "dt": 0.05, "v_th": 1e9, "v_method": "fe",
+         "syn": None}
+    st = (-80.0 + 40.0 * rng.random(2 * K))[None, :].copy()
+    q0 = [np.dot(area, st[0, j * K:(j + 1) * K]) for j in range(2)]
+    ora.cable_run(m, st, 4000, {"K": K, "parent": parent, "g_axial": g_ax, "area": area},
+                  record_spikes=False)
+    for j in range(2):
+        v = st[0, j * K:(j + 1) * K]
+        assert abs(np.dot(area, v) - q0[j]) < 1e-10 * abs(q0[j])
+        assert np.ptp(v) < 1e-6  # equalized
+        assert abs(v[0] - q0[j] / sum(area)) < 1e-6
+
+
+def test_cable_identical_dendrites_identical_traces(ora):
+    parent = _soma_3_dendrites(5)
+    K = len(parent)
+    m = W.classic_hh(dt=0.025)
+    rng = np.random.default_rng(2)
+    T = 2000
+    I = np.zeros((T, K))
+    I[:, 0] = 30.0 + 4.0 * rng.standard_normal(T)
+    st = ora.init_state(m, np.full(K, -65.0))
+    r = ora.cable_run(m, st, T, {"K": K, "parent": parent, "g_axial": [0.0] + [2.0] * (K - 1)},
+                      i_dense=I, record_v=True)
+    d = [r["v"][:, 1 + 5 * b: 6 + 5 * b] for b in range(3)]
+    assert np.array_equal(d[0], d[1]) and np.array_equal(d[0], d[2])
+    assert r["spikes"][:, 0].sum() > 0 and not np.array_equal(r["v"][:, 0], d[0][:, 0])
+
+
+def test_cable_spike_propagates_from_tip_to_soma(ora):
+    """An active unbranched dendrite stimulated at its tip: the spike
+    crosses threshold in every compartment, in order from the tip to the
+    soma."""
+    K = 8
+    m = W.classic_hh(dt=0.01)
+    st = ora.init_state(m, np.full(K, -65.0))
+    I = np.zeros(K)
+    I[K - 1] = 40.0
+    r = ora.cable_run(m, st, 600, {"K": K, "parent": [-1] + list(range(K - 1)),
+                                   "g_axial": [0.0] + [3.0] * (K - 1)}, i_const=I)
+    first = [int(np.argmax(r["spikes"][:, c])) if r["spikes"][:, c].any() else -1 for c in range(K)]
+    assert min(first) >= 0, first
+    assert all(first[c] > first[c + 1] for c in range(K - 1)), first
