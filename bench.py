@@ -253,6 +253,65 @@ def bench_table(n=1 << 20, T=4000, nodes=(161, 641), eval_neurons=65536, fusion=
     return {"n": n, "T": T, "fusion": fusion, "input": "noise 5 + 3z", "rows": rows}
 
 
+# ---------------------------------------------------------------------------
+# multi-compartment neurons
+# ---------------------------------------------------------------------------
+def bench_cable(N=65536, T=4000, fusion=32):
+    """N neurons of a soma with three dendrites of five compartments
+    (1,048,576 compartments), classic HH channels, dendrites at 30% channel
+    density, noisy input 2.5 + 3z in every compartment, T steps of 0.025
+    ms.  The same number of point neurons with the same input gives the cost
+    of the coupling.  Algorithmic work per compartment-update: the point
+    neuron's, plus two operations per edge end (a difference and a
+    multiply-add) and the addition to the input."""
+    import torch
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import workloads as W
+    m = W.classic_hh(dt=0.025)
+    mo = W.soma_dendrites(m, 3, 5)
+    K = mo["K"]
+    n = N * K
+    launches = (T + fusion - 1) // fusion
+
+    def timed(M, reps=3):
+        st = M.new_state()
+        bits = torch.zeros((T, M.words), dtype=torch.int32, device="cuda")
+        ms = []
+        for k in range(reps + 1):
+            M.init_state(st, v0_scalar=-65.0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            M.step_n(st, T, 0, noise=(2.5, 3.0, 9), spikes=bits)
+            e1.record()
+            _sync()
+            if k:
+                ms.append(e0.elapsed_time(e1))
+        code, bad = M.check()
+        if code != 0:
+            raise RuntimeError("non-finite state in the cable benchmark (element %d)" % bad)
+        return float(np.mean(ms))
+
+    Mc = hh.Model(m, n)
+    Mc.set_fusion(fusion)
+    Mc.set_morphology(K, mo["parent"], mo["g_axial"], mo["area"], mo["gbar"])
+    ms_cable = timed(Mc)
+    del Mc
+    Mp = hh.Model(m, n)
+    Mp.set_fusion(fusion)
+    ms_point = timed(Mp)
+    del Mp
+    edge_ends = 2.0 * (K - 1) / K
+    slots = slots_per_update(m, noise=True) + 2.0 * edge_ends + 1.0
+    achieved = slots * n * T / (ms_cable / 1e3) / 1e12
+    return {"neurons": N, "compartments": n, "K": K, "T": T, "fusion": fusion,
+            "ms": ms_cable, "compartment_updates_per_s": n * T / ms_cable * 1e3,
+            "avg_launch_us": ms_cable * 1e3 / launches,
+            "point_neuron_ms": ms_point, "coupling_overhead": ms_cable / ms_point - 1.0,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS / 1e12,
+                         "unit": "Tslot/s", "frac": achieved * 1e12 / PEAK_LANE_OPS,
+                         "slots_per_update": slots}}
+
+
 def cpu_baseline_headline(n_sample=8192):
     """The FP64 oracle, single-threaded, on the first n_sample neurons of the
     headline workload for all 4,000 steps."""
@@ -724,7 +783,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--parts", default="layer,net,surrogate,table,probe")
+    ap.add_argument("--parts", default="layer,net,surrogate,table,cable,probe")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--counters", action="store_true",
                     help="run the copy + one headline launch for rocprofv3 counter passes")
@@ -760,6 +819,9 @@ def main():
     if "table" in parts:
         extra["tabulated_kinetics"] = bench_table()
         print("[bench] table done", file=sys.stderr, flush=True)
+    if "cable" in parts:
+        extra["cable"] = bench_cable()
+        print("[bench] cable done", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline_headline()
 
     line = {

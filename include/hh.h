@@ -161,6 +161,39 @@ int32_t hh_set_specialize(hh_model* m, int32_t on);
  * HH_E_UNSUPPORTED while a table is set (they evaluate the rate functions). */
 int32_t hh_set_rate_table(hh_model* m, float v_lo, float v_hi, int32_t n_nodes, void* stream);
 
+/* Multi-compartment neurons (Methods, Eq. (1) with its spatial term
+ * (1/r_l) d2V/dx2; "Simplified discretization": the second-order explicit
+ * difference in space).  Every neuron of the population becomes K
+ * consecutive compartments: compartment c of neuron j is element j*K + c of
+ * the population (and of every state row, input and output), so n = N*B
+ * counts compartments and N must be a multiple of K.  All neurons share the
+ * morphology, given as host arrays of K entries:
+ *   parent[c]   the compartment c is attached to, in [0, c), or -1 for a
+ *               root (a neuron may have several unconnected roots)
+ *   g_axial[c]  the conductance of the edge c - parent[c] per unit of
+ *               reference membrane area, mS/cm^2 (ignored for roots);
+ *               nullable when K = 1
+ *   area[c]     membrane area relative to the reference (nullable: all 1)
+ *   gbar        nullable [K][n_channels]: the channel conductances of each
+ *               compartment, replacing the descriptor's (passive dendrites,
+ *               active soma, ...)
+ * Each step, compartment c receives the axial current
+ *     sum over its edges e of (g_e / area[c]) (V_other - V_c)
+ * from the start-of-step potentials, added to its input current; for a
+ * uniform unbranched cable with g = 1/(r_l dx^2) this is the central
+ * difference (1/r_l)(V_{c-1} - 2V_c + V_{c+1})/dx^2 with sealed ends.
+ * Explicit coupling is stable for dt * sum_e g_e / (C area) below about 1
+ * (forward Euler).  K = 0 removes the morphology.  The arrays are copied;
+ * the call returns when the copy is done.
+ * Errors: HH_E_SHAPE for K not a power of two in [1, 64] or N not a multiple
+ * of K; HH_E_INVALID for a parent outside [-1, c), a negative or non-finite
+ * conductance, a non-positive area, or a missing array; HH_E_UNSUPPORTED for
+ * more than 4 children on one compartment, or with a network or a rate table
+ * set.  With a morphology, hh_step_n refuses checkpoints, level counts and
+ * networks, and hh_backward and hh_surrogate_step_n return HH_E_UNSUPPORTED. */
+int32_t hh_set_morphology(hh_model* m, int32_t K, const int32_t* parent, const float* g_axial,
+                          const float* area, const float* gbar, void* stream);
+
 /* state <- (V0, p_inf(V0) for every gate, g_e = g_i = 0, V_lo = 0).  v0: nullable [n]
  * device array; when NULL every neuron starts at v0_scalar. */
 int32_t hh_init_state(hh_model* m, float* state, const float* v0, float v0_scalar, void* stream);

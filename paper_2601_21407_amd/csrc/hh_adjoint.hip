@@ -295,6 +295,7 @@ int32_t hh_backward_part(hh_model* m, const float* ckpt, int32_t ckpt_every, con
   if (!m || !ckpt || !in || !dI) return HH_E_INVALID;
   if (m->km.has_syn || m->km.v_method != HH_V_FE) return HH_E_UNSUPPORTED;
   if (m->d_tab) return HH_E_UNSUPPORTED;  // the adjoint differentiates the rate functions
+  if (m->d_cable) return HH_E_UNSUPPORTED;  // and has no axial coupling
   if (in->mode != HH_IN_DENSE || !in->i_dense) return HH_E_INVALID;
   if (T < 1 || ckpt_every < 1) return HH_E_SHAPE;
   if (t_lo < 0 || t_hi > T || t_lo >= t_hi || t_lo % ckpt_every != 0 ||

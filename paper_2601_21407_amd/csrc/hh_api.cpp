@@ -152,6 +152,7 @@ int32_t hh_init(hh_model** out, const hh_model_desc* desc, int64_t N, int32_t B,
 int32_t hh_destroy(hh_model* m) {
   if (!m) return HH_OK;
   if (m->d_tab) (void)hipFree(m->d_tab);
+  if (m->d_cable) (void)hipFree(m->d_cable);
   if (m->d_scratch) (void)hipFree(m->d_scratch);
   if (m->d_flags) (void)hipFree(m->d_flags);
   delete m;
@@ -176,6 +177,69 @@ int32_t hh_set_specialize(hh_model* m, int32_t on) {
   return HH_OK;
 }
 
+int32_t hh_set_morphology(hh_model* m, int32_t K, const int32_t* parent, const float* g_axial,
+                          const float* area, const float* gbar, void* stream) {
+  if (!m) return HH_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  if (K == 0) {
+    if (m->d_cable) {
+      HIP_OK(hipStreamSynchronize(s));
+      HIP_OK(hipFree(m->d_cable));
+    }
+    m->d_cable = nullptr;
+    m->cable_K = m->cable_D = m->cable_gbar = 0;
+    return HH_OK;
+  }
+  if (K < 1 || K > 64 || (K & (K - 1)) != 0 || m->N % K != 0) return HH_E_SHAPE;
+  if (!parent || (K > 1 && !g_axial)) return HH_E_INVALID;
+  if (m->row_ptr || m->d_tab) return HH_E_UNSUPPORTED;
+  const int nch = m->km.n_ch;
+  hhk::CableComp comp[64];
+  int nchild[64];
+  memset(comp, 0, sizeof(comp));
+  for (int c = 0; c < K; ++c) {
+    const int p = parent[c];
+    if (p < -1 || p >= c) return HH_E_INVALID;  // roots, or an earlier compartment
+    const float a = area ? area[c] : 1.0f;
+    if (!(a > 0.0f) || !(a < 1e30f)) return HH_E_INVALID;
+    if (p >= 0 && (!(g_axial[c] >= 0.0f) || !(g_axial[c] < 1e30f))) return HH_E_INVALID;
+    comp[c].par = c;
+    for (int d = 0; d < hhk::kMaxChildren; ++d) comp[c].ch[d] = c;
+    nchild[c] = 0;
+    for (int x = 0; x < hhk::kMaxCh; ++x) {
+      float g = x < nch ? m->km.gbar[x] : 0.0f;
+      if (gbar && x < nch) {
+        g = gbar[(int64_t)c * nch + x];
+        if (!(g >= 0.0f) || !(g < 1e30f)) return HH_E_INVALID;
+      }
+      comp[c].gbar[x] = g;
+    }
+  }
+  int D = 0;
+  for (int c = 0; c < K; ++c) {
+    const int p = parent[c];
+    if (p < 0) continue;
+    const float g = g_axial[c];
+    comp[c].par = p;
+    comp[c].gup = g / (area ? area[c] : 1.0f);
+    const int d = nchild[p]++;
+    if (d >= hhk::kMaxChildren) return HH_E_UNSUPPORTED;
+    comp[p].ch[d] = c;
+    comp[p].gdn[d] = g / (area ? area[p] : 1.0f);
+    if (d + 1 > D) D = d + 1;
+  }
+  if (!m->d_cable && hipMalloc((void**)&m->d_cable, sizeof(comp)) != hipSuccess) {
+    m->d_cable = nullptr;
+    return HH_E_OOM;
+  }
+  HIP_OK(hipMemcpyAsync(m->d_cable, comp, sizeof(comp), hipMemcpyHostToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));  // comp lives on this stack frame
+  m->cable_K = K;
+  m->cable_D = D;
+  m->cable_gbar = gbar ? 1 : 0;
+  return HH_OK;
+}
+
 int32_t hh_set_rate_table(hh_model* m, float v_lo, float v_hi, int32_t n_nodes, void* stream) {
   if (!m) return HH_E_INVALID;
   if (n_nodes == 0) {
@@ -192,7 +256,7 @@ int32_t hh_set_rate_table(hh_model* m, float v_lo, float v_hi, int32_t n_nodes, 
   // the tabulated step exists for the built-in channel sets with uniform
   // coefficients, outside the network (the network, adjoint and surrogate
   // kernels evaluate the rate functions)
-  if (m->coef || m->row_ptr || !m->use_fixed) return HH_E_UNSUPPORTED;
+  if (m->coef || m->row_ptr || m->d_cable || !m->use_fixed) return HH_E_UNSUPPORTED;
   if (!(hhk::ClassicSpec::matches(m->km) || hhk::CorticalSpec::matches(m->km))) return HH_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   const size_t bytes = (size_t)m->km.n_gates * (size_t)n_nodes * sizeof(float4);
@@ -228,6 +292,7 @@ int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const 
   if (in->mode == HH_IN_DENSE && !in->i_dense) return HH_E_INVALID;
   if (out->ckpt && out->ckpt_every < 1) return HH_E_SHAPE;
   if (m->d_tab && (m->row_ptr || !m->use_fixed)) return HH_E_UNSUPPORTED;
+  if (m->d_cable && (m->row_ptr || out->ckpt || out->level)) return HH_E_UNSUPPORTED;
   if (m->row_ptr) return hh_net_step_n_internal(m, state, t0, n_steps, in, out, stream);
   if (n_steps == 0) return HH_OK;
   hipStream_t s = (hipStream_t)stream;
@@ -262,7 +327,14 @@ int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const 
     a.i_dense = in->i_dense ? in->i_dense + (int64_t)kb * m->n : nullptr;
     a.spikes = out->spikes ? out->spikes + (int64_t)kb * a.words : nullptr;
     a.v_rec = out->v_rec ? out->v_rec + (int64_t)kb * m->n : nullptr;
-    HIP_OK(launch_step(m, a, s));
+    if (m->d_cable) {
+      a.cable = m->d_cable;
+      a.cable_K = m->cable_K;
+      a.cable_D = m->cable_D;
+      HIP_OK(launch_cable(m, a, s));
+    } else {
+      HIP_OK(launch_step(m, a, s));
+    }
   }
   return HH_OK;
 }

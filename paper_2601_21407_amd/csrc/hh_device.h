@@ -285,16 +285,42 @@ __device__ __forceinline__ float expm1_neg(float z) {
   return (z < 0.1f) ? s : ex2(-z * kLog2e) - 1.0f;
 }
 
+// Channel conductances g_X: the model's, the same for every neuron
+// (ModelGbar), or one set per lane (LaneGbar: the compartments of a
+// morphology, each with its own channel densities).
+struct ModelGbar {
+  __device__ __forceinline__ float operator()(const KModel& M, int c) const { return M.gbar[c]; }
+};
+struct LaneGbar {
+  float g[kMaxCh];
+  __device__ __forceinline__ float operator()(const KModel&, int c) const { return g[c]; }
+};
+
+// One compartment of a morphology, shared by every neuron of a population
+// (Methods, Eq. (1): the spatial term, discretized by the second-order
+// explicit difference).  par / ch: compartment indices (within the neuron)
+// of the parent and of up to kMaxChildren children, the compartment's own
+// index where there is none (the term then vanishes).  gup / gdn: the
+// coupling coefficients g_edge / area of this compartment towards each of
+// them (mS/cm^2).  gbar: the compartment's channel conductances.
+constexpr int kMaxChildren = 4;
+struct CableComp {
+  int32_t par, ch[kMaxChildren];
+  float gup, gdn[kMaxChildren];
+  float gbar[kMaxCh];
+};
+
 // Advance the gates and V by one step (Jacobi: all right-hand sides at the
 // start-of-step state).  p is updated in place; (vh, vl) likewise.
 // I: external current; ge, gi: synaptic conductances held over the step.
 // SYN = false: the caller knows the population has no synapses (ge = gi = 0);
 // the synaptic terms are left out, which gives bit-identical results.  LR:
-// LaneRates (rate functions) or TabRates (tabulated gate kinetics).
-template <class S, bool SYN = true, class LR = LaneRates<S::kNG>>
+// LaneRates (rate functions) or TabRates (tabulated gate kinetics).  GB:
+// where the channel conductances come from (ModelGbar or LaneGbar).
+template <class S, bool SYN = true, class LR = LaneRates<S::kNG>, class GB = ModelGbar>
 __device__ __forceinline__ void neuron_step(const KModel& M, const LR& L, float dtC,
                                             float& vh, float& vl, float (&p)[ng1<S::kNG>], float I,
-                                            float ge, float gi) {
+                                            float ge, float gi, const GB& G = GB()) {
   constexpr int NG = S::kNG;
   const float V = vh;
   // channel terms at the start-of-step gates: total conductance gsum and
@@ -307,7 +333,7 @@ __device__ __forceinline__ void neuron_step(const KModel& M, const LR& L, float 
 #pragma unroll
   for (int c = 0; c < kMaxCh; ++c) {
     if (c >= S::nch(M)) break;
-    float eta = M.gbar[c];
+    float eta = G(M, c);
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
       const int e = S::cexp(M, c, g);

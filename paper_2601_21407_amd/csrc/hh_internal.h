@@ -28,6 +28,10 @@ struct StepArgs {
   const float4* tab;
   int32_t tab_n;
   float tab_vlo, tab_inv_h;
+  // morphology: K compartments per neuron (a power of two up to 64), at
+  // most D children per compartment
+  const hhk::CableComp* cable;
+  int32_t cable_K, cable_D;
 };
 
 struct hh_model {
@@ -60,13 +64,39 @@ struct hh_model {
   float4* d_tab;
   int32_t tab_n;
   float tab_vlo, tab_h;
+  // morphology (multi-compartment neurons), owned by the model (null: none)
+  hhk::CableComp* d_cable;
+  int32_t cable_K, cable_D;
+  int32_t cable_gbar;  // per-compartment channel conductances given
 };
+
+// Dispatch on the channel-set structure: compiled specializations for the
+// built-in sets, the run-time interpreter for any other set.
+template <template <class> class F, class... Args>
+inline hipError_t dispatch_spec(const hhk::KModel& km, bool allow_fixed, Args... args) {
+  using namespace hhk;
+  if (allow_fixed && ClassicSpec::matches(km)) return F<ClassicSpec>::run(args...);
+  if (allow_fixed && CorticalSpec::matches(km)) return F<CorticalSpec>::run(args...);
+  switch (km.n_gates) {
+    case 0: return F<GenericSpec<0>>::run(args...);
+    case 1: return F<GenericSpec<1>>::run(args...);
+    case 2: return F<GenericSpec<2>>::run(args...);
+    case 3: return F<GenericSpec<3>>::run(args...);
+    case 4: return F<GenericSpec<4>>::run(args...);
+    case 5: return F<GenericSpec<5>>::run(args...);
+    case 6: return F<GenericSpec<6>>::run(args...);
+    case 7: return F<GenericSpec<7>>::run(args...);
+    default: return F<GenericSpec<8>>::run(args...);
+  }
+}
 
 hipError_t launch_init_state(const hh_model* m, float* state, const float* v0, float v0s,
                              hipStream_t s);
 hipError_t launch_step(const hh_model* m, const StepArgs& a, hipStream_t s);
 // fills m->d_tab (m->tab_n nodes from m->tab_vlo, spacing m->tab_h)
 hipError_t launch_build_table(const hh_model* m, hipStream_t s);
+// the step of multi-compartment neurons (hh_cable.hip): a.cable set
+hipError_t launch_cable(const hh_model* m, const StepArgs& a, hipStream_t s);
 
 // recurrent network path of hh_step_n (hh_net.hip)
 int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_steps,

@@ -796,7 +796,8 @@ extern "C" int32_t hh_surrogate_step_n(hh_model* m, const void* mlp_packed, floa
     return HH_E_SHAPE;
   if (in->mode == HH_IN_CONST) return HH_E_UNSUPPORTED;
   if (in->mode == HH_IN_DENSE && !in->i_dense) return HH_E_INVALID;
-  if (m->km.has_syn || m->coef || m->cm || m->B != 1 || m->d_tab) return HH_E_UNSUPPORTED;
+  if (m->km.has_syn || m->coef || m->cm || m->B != 1 || m->d_tab || m->d_cable)
+    return HH_E_UNSUPPORTED;
   if (!CorticalSpec::matches(m->km)) return HH_E_UNSUPPORTED;
   if (n_steps == 0) return HH_OK;
   SurArgs a;

@@ -393,25 +393,6 @@ static hipError_t step_spec(const hh_model* m, const StepArgs& a, hipStream_t s)
   return hipGetLastError();
 }
 
-// Dispatch on the channel-set structure: compiled specializations for the
-// built-in sets, the run-time interpreter for any other set.
-template <template <class> class F, class... Args>
-static hipError_t dispatch_spec(const KModel& km, bool allow_fixed, Args... args) {
-  if (allow_fixed && ClassicSpec::matches(km)) return F<ClassicSpec>::run(args...);
-  if (allow_fixed && CorticalSpec::matches(km)) return F<CorticalSpec>::run(args...);
-  switch (km.n_gates) {
-    case 0: return F<GenericSpec<0>>::run(args...);
-    case 1: return F<GenericSpec<1>>::run(args...);
-    case 2: return F<GenericSpec<2>>::run(args...);
-    case 3: return F<GenericSpec<3>>::run(args...);
-    case 4: return F<GenericSpec<4>>::run(args...);
-    case 5: return F<GenericSpec<5>>::run(args...);
-    case 6: return F<GenericSpec<6>>::run(args...);
-    case 7: return F<GenericSpec<7>>::run(args...);
-    default: return F<GenericSpec<8>>::run(args...);
-  }
-}
-
 template <class S>
 struct InitF {
   static hipError_t run(const hh_model* m, float* state, const float* v0, float v0s, hipStream_t s) {

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -78,6 +79,7 @@ def _load():
         "hh_set_fusion": ([vp, i32], i32),
         "hh_set_specialize": ([vp, i32], i32),
         "hh_set_rate_table": ([vp, f32, f32, i32, vp], i32),
+        "hh_set_morphology": ([vp, i32, vp, vp, vp, vp, vp], i32),
         "hh_init_state": ([vp, vp, vp, f32, vp], i32),
         "hh_step_n": ([vp, vp, i64, i32, P(Input), P(Outputs), vp], i32),
         "hh_attach_csr": ([vp, vp, vp, vp, i64, f32], i32),
@@ -121,7 +123,7 @@ lib = _load()
 def exported_symbols():
     """Names of the C-ABI entry points this binding uses."""
     return [n for n in ("hh_init", "hh_destroy", "hh_status_string", "hh_n_state", "hh_set_fusion",
-                        "hh_set_specialize", "hh_set_rate_table",
+                        "hh_set_specialize", "hh_set_rate_table", "hh_set_morphology",
                         "hh_init_state", "hh_step_n", "hh_attach_csr", "hh_set_external",
                         "hh_syn_propagate", "hh_backward", "hh_backward_part",
                         "hh_backward_workspace", "hh_check",
@@ -210,6 +212,16 @@ class Model:
         """Tabulated gate kinetics on [v_lo, v_hi] mV with n_nodes nodes; 0 removes it."""
         _ok(lib.hh_set_rate_table(self.h, float(v_lo), float(v_hi), int(n_nodes), _stream()),
             "hh_set_rate_table")
+
+    def set_morphology(self, K: int, parent=None, g_axial=None, area=None, gbar=None):
+        """K compartments per neuron (host arrays of K entries; gbar [K][n_channels]);
+        K = 0 removes the morphology."""
+        def host(a, dt):
+            return None if a is None else np.ascontiguousarray(a, dtype=dt)
+        par = host(parent, np.int32)
+        gax, ar, gb = host(g_axial, np.float32), host(area, np.float32), host(gbar, np.float32)
+        ptr = [None if a is None else a.ctypes.data_as(ctypes.c_void_p) for a in (par, gax, ar, gb)]
+        _ok(lib.hh_set_morphology(self.h, int(K), *ptr, _stream()), "hh_set_morphology")
 
     def new_state(self, device="cuda"):
         return torch.empty((self.n_state, self.n), dtype=torch.float32, device=device)

@@ -79,6 +79,28 @@ def custom_channels(dt: float = 0.025, v_method: str = "fe") -> dict:
     }
 
 
+def soma_dendrites(model: dict, n_dend: int = 3, per_dend: int = 5, g_axial: float = 1.5,
+                   soma_area: float = 3.0, density: float = 0.3) -> dict:
+    """Morphology description: a soma (compartment 0) with n_dend unbranched
+    dendrites of per_dend compartments each, as in the paper's soma + three
+    dendrites example (Results, sub-cellular scale).  Dendrites carry every
+    channel of `model` at `density` times the soma's conductance (so their
+    resting potential equals the soma's) and unit area; the soma has
+    soma_area.  Every edge has conductance g_axial (mS/cm^2 per unit area).
+    Returns {"K", "parent", "g_axial", "area", "gbar"} with K = 1 +
+    n_dend * per_dend."""
+    parent = [-1]
+    for _ in range(n_dend):
+        first = len(parent)
+        parent.append(0)
+        parent += list(range(first, first + per_dend - 1))
+    K = len(parent)
+    g0 = np.array([c["gbar"] for c in model["channels"]], dtype=np.float64)
+    gbar = np.vstack([g0] + [density * g0] * (K - 1))
+    return {"K": K, "parent": parent, "g_axial": [0.0] + [g_axial] * (K - 1),
+            "area": [soma_area] + [1.0] * (K - 1), "gbar": gbar}
+
+
 def with_synapses(model: dict, tau_e=5.0, tau_i=10.0, E_e=0.0, E_i=-80.0) -> dict:
     m = copy.deepcopy(model)
     m["syn"] = {"tau_e": tau_e, "tau_i": tau_i, "E_e": E_e, "E_i": E_i}

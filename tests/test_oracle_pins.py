@@ -686,12 +686,7 @@ def _passive(g_l=1.0, e_l=0.0, C=1.0, dt=0.01, v_method="fe"):
 
 
 def _soma_3_dendrites(n_dend=5):
-    parent = [-1]
-    for _ in range(3):
-        first = len(parent)
-        parent.append(0)
-        parent += list(range(first, first + n_dend - 1))
-    return parent
+    return W.soma_dendrites(W.classic_hh(), 3, n_dend)["parent"]
 
 
 def test_cable_single_compartment_is_the_point_neuron(ora):
