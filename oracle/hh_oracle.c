@@ -334,11 +334,12 @@ int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double*
  * those at the start of the step (explicit), and each compartment then takes
  * the point-neuron step with I + I_axial as its input.  gbar [K][n_channels]
  * (nullable) replaces the channel conductances per compartment; coef
- * (nullable) holds per-element rate coefficients as in ora_run.  The steps
+ * (nullable) holds per-element rate coefficients and ids (nullable) the
+ * noise generator's element ids, as in ora_run.  The steps
  * run in time order, all compartments within each step. */
 int32_t ora_cable_run(const ora_model* m, int64_t n, int32_t K, const int32_t* parent,
                       const double* g_axial, const double* area, const double* gbar,
-                      const double* coef, const double* cm, double* state, int64_t t0, int32_t T, int32_t in_mode,
+                      const double* coef, const double* cm, const uint32_t* ids, double* state, int64_t t0, int32_t T, int32_t in_mode,
                       const double* i_const, double mu, double sigma, uint64_t seed,
                       const double* i_dense, uint8_t* spk, double* vrec) {
   if (!model_ok(m) || K < 1 || n < 0 || T < 0 || n % K != 0) return -1;
@@ -387,7 +388,7 @@ int32_t ora_cable_run(const ora_model* m, int64_t n, int32_t K, const int32_t* p
       }
       double I = 0.0;
       if (in_mode == ORA_IN_CONST) I = i_const[i];
-      else if (in_mode == ORA_IN_NOISE) I = mu + sigma * ora_noise(seed, (uint32_t)i, t);
+      else if (in_mode == ORA_IN_NOISE) I = mu + sigma * ora_noise(seed, ids ? ids[i] : (uint32_t)i, t);
       else if (in_mode == ORA_IN_DENSE) I = i_dense[(int64_t)k * n + i];
       double Vn;
       neuron_step(mi, coef, n, i, cm ? cm[i] : m->C, V, p, ge, gi, I + iax[i], &Vn, pn);

@@ -94,12 +94,12 @@ int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double*
 /* Multi-compartment neurons: n = N*K compartments, compartment c of neuron j
  * at j*K + c; parent[c] in [-1, c); g_axial [K] edge conductances per unit
  * reference area; area [K] relative membrane areas (nullable: 1); gbar
- * [K][n_channels] per-compartment channel conductances (nullable); coef
- * and cm per element as in ora_run (nullable).  Inputs, state and outputs as ora_run (noise ids = element
+ * [K][n_channels] per-compartment channel conductances (nullable); coef,
+ * cm and ids per element as in ora_run (nullable).  Inputs, state and outputs as ora_run (noise ids = element
  * index).  Returns 0, or -1 on a malformed model or morphology. */
 int32_t ora_cable_run(const ora_model* m, int64_t n, int32_t K, const int32_t* parent,
                       const double* g_axial, const double* area, const double* gbar,
-                      const double* coef, const double* cm, double* state, int64_t t0, int32_t T, int32_t in_mode,
+                      const double* coef, const double* cm, const uint32_t* ids, double* state, int64_t t0, int32_t T, int32_t in_mode,
                       const double* i_const, double mu, double sigma, uint64_t seed,
                       const double* i_dense, uint8_t* spk, double* vrec);
 

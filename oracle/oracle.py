@@ -132,8 +132,8 @@ def lib():
         L.ora_rate.restype = d
         L.ora_gate_inf.argtypes = [P(OraModel), vp, i64, i64, i32, d]
         L.ora_gate_inf.restype = d
-        L.ora_cable_run.argtypes = [P(OraModel), i64, i32, vp, vp, vp, vp, vp, vp, vp, i64, i32,
-                                    i32, vp, d, d, u64, vp, vp, vp]
+        L.ora_cable_run.argtypes = [P(OraModel), i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, i64,
+                                    i32, i32, vp, d, d, u64, vp, vp, vp]
         L.ora_cable_run.restype = i32
         L.ora_gate_pq.argtypes = [P(OraModel), vp, i64, i64, i32, d, P(d), P(d)]
         L.ora_gate_pq.restype = None
@@ -250,7 +250,7 @@ def run(model: dict, state: np.ndarray, T: int, t0: int = 0, *, i_const=None, no
 
 def cable_run(model: dict, state: np.ndarray, T: int, morph: dict, t0: int = 0, *, i_const=None,
               noise_mu=None, noise_sigma=None, seed: int = 0, i_dense=None, coef=None, cm=None,
-              record_v: bool = False, record_spikes: bool = True):
+              ids=None, record_v: bool = False, record_spikes: bool = True):
     """Advance multi-compartment neurons T steps in place (state [n_state][n],
     n = N*K).  morph = {"K": K, "parent": [K], "g_axial": [K],
     "area": [K] or None, "gbar": [K][n_channels] or None}.  Returns dict with
@@ -273,10 +273,11 @@ def cable_run(model: dict, state: np.ndarray, T: int, morph: dict, t0: int = 0, 
     else:
         mode = IN_NONE
     coef, cm = _f64(coef), _f64(cm)
+    ids = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
     spk = np.zeros((T, n), np.uint8) if record_spikes else None
     vr = np.zeros((T, n), np.float64) if record_v else None
     rc = lib().ora_cable_run(ctypes.byref(s), n, K, _p(parent), _p(g_ax), _p(area), _p(gbar),
-                             _p(coef), _p(cm), _p(state), int(t0), int(T), mode, _p(i_const),
+                             _p(coef), _p(cm), _p(ids), _p(state), int(t0), int(T), mode, _p(i_const),
                              float(noise_mu or 0.0), float(noise_sigma or 0.0), int(seed),
                              _p(i_dense), _p(spk), _p(vr))
     if rc != 0:
