@@ -69,6 +69,50 @@ double ora_noise(uint64_t seed, uint32_t id, int64_t t) {
   return (comp & 1) ? rad * sin(two_pi * ub) : rad * cos(two_pi * ub);
 }
 
+/* Background input of the cortex model (Methods, cortical network): the
+ * summed drive of many background synapses over one step, drawn directly
+ * from its distribution instead of synapse by synapse.  Read as a compound
+ * Poisson sum: N ~ Poisson(lam) events in the step, each of independent
+ * Gaussian amplitude (mu, sigma), so the sum is N mu + sqrt(N) sigma z.
+ *
+ * The random words are block (t, stream 2) of Philox4x32-10 for the element.
+ * Word 0 gives u = (2 floor(w0 / 2^9) + 1) 2^-24, which binary32 holds
+ * exactly, and N is the smallest k with u <= F(k), by sequential search.
+ * N is an integer that floating point decides, so the search runs in
+ * binary32 like the device kernel: every product, quotient and sum is
+ * rounded to binary32 on its own, and p_0 = e^-lam is rounded once from
+ * binary64.  The search stops at k_max = floor(lam + 12 sqrt(lam)) + 12.
+ * Words 2 and 3 give z by Box-Muller (cosine branch). */
+int32_t ora_background_count(uint32_t w0, double lam) {
+  const float u = (float)(2u * (w0 >> 9) + 1u) * 0x1p-24f;
+  const float lf = (float)lam;
+  const float p0 = (float)exp(-lam);
+  const int32_t kmax = (int32_t)floor(lam + 12.0 * sqrt(lam)) + 12;
+  int32_t k = 0;
+  float p = p0, F = p0;
+  /* binary32 arithmetic; the oracle is built without contraction, so each
+   * operation is rounded on its own */
+  while (u > F && k < kmax) {
+    k += 1;
+    p = p * (lf / (float)k);
+    F = F + p;
+  }
+  return k;
+}
+
+double ora_background(uint64_t seed, uint32_t id, int64_t t, double lam, double mu, double sigma,
+                      int32_t* count) {
+  uint32_t ctr[4] = {(uint32_t)(uint64_t)t, (uint32_t)((uint64_t)t >> 32), id, 2u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  ora_philox4x32_10(ctr, key, w);
+  const int32_t N = ora_background_count(w[0], lam);
+  const double two_pi = 6.283185307179586476925286766559;
+  const double z = sqrt(-2.0 * log(unit_open(w[2]))) * cos(two_pi * unit_open(w[3]));
+  if (count) *count = N;
+  return (double)N * mu + sqrt((double)N) * sigma * z;
+}
+
 uint32_t ora_event_word(uint64_t seed, uint32_t id, int64_t t) {
   uint32_t ctr[4] = {(uint32_t)(uint64_t)t, (uint32_t)((uint64_t)t >> 32), id, 1u};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -283,7 +327,7 @@ static void neuron_step(const ora_model* m, const double* coef, int64_t n, int64
 
 int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double* cm,
                 const uint32_t* ids, double* state, int64_t t0, int32_t T, int32_t in_mode,
-                const double* i_const, double mu, double sigma, uint64_t seed,
+                const double* i_const, double mu, double sigma, uint64_t seed, double lam,
                 const double* i_dense, uint8_t* spk, double* vrec, double* level) {
   if (!model_ok(m) || n < 0 || T < 0) return -1;
   const int G = m->n_gates;
@@ -304,6 +348,7 @@ int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double*
       if (in_mode == ORA_IN_CONST) I = i_const[i];
       else if (in_mode == ORA_IN_NOISE) I = mu + sigma * ora_noise(seed, id, t);
       else if (in_mode == ORA_IN_DENSE) I = i_dense[(int64_t)k * n + i];
+      else if (in_mode == ORA_IN_BACKGROUND) I = ora_background(seed, id, t, lam, mu, sigma, NULL);
       double Vn;
       neuron_step(m, coef, n, i, C, V, p, ge, gi, I, &Vn, pn);
       if (spk) spk[(int64_t)k * n + i] = (uint8_t)(V < m->v_th && Vn >= m->v_th);
@@ -339,9 +384,10 @@ int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double*
  * run in time order, all compartments within each step. */
 int32_t ora_cable_run(const ora_model* m, int64_t n, int32_t K, const int32_t* parent,
                       const double* g_axial, const double* area, const double* gbar,
-                      const double* coef, const double* cm, const uint32_t* ids, double* state, int64_t t0, int32_t T, int32_t in_mode,
-                      const double* i_const, double mu, double sigma, uint64_t seed,
-                      const double* i_dense, uint8_t* spk, double* vrec) {
+                      const double* coef, const double* cm, const uint32_t* ids, double* state,
+                      int64_t t0, int32_t T, int32_t in_mode, const double* i_const, double mu,
+                      double sigma, uint64_t seed, double lam, const double* i_dense, uint8_t* spk,
+                      double* vrec) {
   if (!model_ok(m) || K < 1 || n < 0 || T < 0 || n % K != 0) return -1;
   for (int32_t c = 0; c < K; ++c)
     if (parent[c] < -1 || parent[c] >= c) return -1;
@@ -390,6 +436,8 @@ int32_t ora_cable_run(const ora_model* m, int64_t n, int32_t K, const int32_t* p
       if (in_mode == ORA_IN_CONST) I = i_const[i];
       else if (in_mode == ORA_IN_NOISE) I = mu + sigma * ora_noise(seed, ids ? ids[i] : (uint32_t)i, t);
       else if (in_mode == ORA_IN_DENSE) I = i_dense[(int64_t)k * n + i];
+      else if (in_mode == ORA_IN_BACKGROUND)
+        I = ora_background(seed, ids ? ids[i] : (uint32_t)i, t, lam, mu, sigma, NULL);
       double Vn;
       neuron_step(mi, coef, n, i, cm ? cm[i] : m->C, V, p, ge, gi, I + iax[i], &Vn, pn);
       if (spk) spk[(int64_t)k * n + i] = (uint8_t)(V < m->v_th && Vn >= m->v_th);

@@ -34,7 +34,7 @@ enum { ORA_AB = 0, ORA_INFTAU = 1 };
 /* Membrane update: explicit Euler of Eq. (2), or exponential Euler in V. */
 enum { ORA_FE = 0, ORA_EE = 1 };
 /* External current modes. */
-enum { ORA_IN_NONE = 0, ORA_IN_CONST = 1, ORA_IN_NOISE = 2, ORA_IN_DENSE = 3 };
+enum { ORA_IN_NONE = 0, ORA_IN_CONST = 1, ORA_IN_NOISE = 2, ORA_IN_DENSE = 3, ORA_IN_BACKGROUND = 4 };
 
 typedef struct {
   int32_t n_gates, n_channels, v_method, has_syn;
@@ -64,6 +64,13 @@ void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 double ora_noise(uint64_t seed, uint32_t id, int64_t t);
 /* Raw 32-bit event word for (seed, id, absolute step t), stream 1. */
 uint32_t ora_event_word(uint64_t seed, uint32_t id, int64_t t);
+/* Background input for (seed, id, absolute step t): N ~ Poisson(lam) events
+ * of Gaussian amplitude (mu, sigma), returned as N mu + sqrt(N) sigma z;
+ * count (nullable) receives N.  ora_background_count: N for Philox word w0
+ * (inverse transform in binary32). */
+int32_t ora_background_count(uint32_t w0, double lam);
+double ora_background(uint64_t seed, uint32_t id, int64_t t, double lam, double mu, double sigma,
+                      int32_t* count);
 
 /* One rate function and its V-derivative. */
 double ora_rate(int32_t form, const double k[4], double V, double* dV);
@@ -88,7 +95,7 @@ int32_t ora_n_state(const ora_model* m);
  * (nullable = 0..n-1).  Returns 0, or -1 on a malformed model. */
 int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double* cm,
                 const uint32_t* ids, double* state, int64_t t0, int32_t T, int32_t in_mode,
-                const double* i_const, double mu, double sigma, uint64_t seed,
+                const double* i_const, double mu, double sigma, uint64_t seed, double lam,
                 const double* i_dense, uint8_t* spk, double* vrec, double* level);
 
 /* Multi-compartment neurons: n = N*K compartments, compartment c of neuron j
@@ -99,9 +106,10 @@ int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double*
  * index).  Returns 0, or -1 on a malformed model or morphology. */
 int32_t ora_cable_run(const ora_model* m, int64_t n, int32_t K, const int32_t* parent,
                       const double* g_axial, const double* area, const double* gbar,
-                      const double* coef, const double* cm, const uint32_t* ids, double* state, int64_t t0, int32_t T, int32_t in_mode,
-                      const double* i_const, double mu, double sigma, uint64_t seed,
-                      const double* i_dense, uint8_t* spk, double* vrec);
+                      const double* coef, const double* cm, const uint32_t* ids, double* state,
+                      int64_t t0, int32_t T, int32_t in_mode, const double* i_const, double mu,
+                      double sigma, uint64_t seed, double lam, const double* i_dense, uint8_t* spk,
+                      double* vrec);
 
 /* Recurrent network with exponential-decay conductance synapses. */
 int32_t ora_net_run(const ora_model* m, int64_t n, double* state, const int64_t* row_ptr,

@@ -27,7 +27,7 @@ MAX_CH = 8
 FORMS = {"exp": 0, "sigmoid": 1, "linoid": 2, "bell": 3}
 KINDS = {"ab": 0, "inftau": 1}
 VMETH = {"fe": 0, "ee": 1}
-IN_NONE, IN_CONST, IN_NOISE, IN_DENSE = 0, 1, 2, 3
+IN_NONE, IN_CONST, IN_NOISE, IN_DENSE, IN_BACKGROUND = 0, 1, 2, 3, 4
 
 
 def build(force: bool = False) -> str:
@@ -133,7 +133,7 @@ def lib():
         L.ora_gate_inf.argtypes = [P(OraModel), vp, i64, i64, i32, d]
         L.ora_gate_inf.restype = d
         L.ora_cable_run.argtypes = [P(OraModel), i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, i64,
-                                    i32, i32, vp, d, d, u64, vp, vp, vp]
+                                    i32, i32, vp, d, d, u64, d, vp, vp, vp]
         L.ora_cable_run.restype = i32
         L.ora_gate_pq.argtypes = [P(OraModel), vp, i64, i64, i32, d, P(d), P(d)]
         L.ora_gate_pq.restype = None
@@ -141,8 +141,12 @@ def lib():
         L.ora_init_state.restype = None
         L.ora_n_state.argtypes = [P(OraModel)]
         L.ora_n_state.restype = i32
-        L.ora_run.argtypes = [P(OraModel), i64, vp, vp, vp, vp, i64, i32, i32, vp, d, d, u64,
+        L.ora_run.argtypes = [P(OraModel), i64, vp, vp, vp, vp, i64, i32, i32, vp, d, d, u64, d,
                               vp, vp, vp, vp]
+        L.ora_background_count.argtypes = [u32, d]
+        L.ora_background_count.restype = i32
+        L.ora_background.argtypes = [u64, u32, i64, d, d, d, P(i32)]
+        L.ora_background.restype = d
         L.ora_run.restype = i32
         L.ora_net_run.argtypes = [P(OraModel), i64, vp, vp, vp, vp, d, vp, u32, d, u64, vp,
                                   i64, i32, vp]
@@ -216,33 +220,55 @@ def init_state(model: dict, v0, coef=None) -> np.ndarray:
     return st
 
 
+def _input_mode(T, n, i_const, noise_mu, noise_sigma, i_dense, background):
+    """(mode, i_const, i_dense, mu, sigma, lam) of one of the input kinds;
+    background = (lam, mu, sigma)."""
+    if i_dense is not None:
+        i_dense = _f64(i_dense)
+        assert i_dense.shape == (T, n)
+        return IN_DENSE, None, i_dense, 0.0, 0.0, 0.0
+    if background is not None:
+        lam, mu, sigma = (float(x) for x in background)
+        return IN_BACKGROUND, None, None, mu, sigma, lam
+    if noise_mu is not None:
+        return IN_NOISE, None, None, float(noise_mu), float(noise_sigma or 0.0), 0.0
+    if i_const is not None:
+        return IN_CONST, _f64(i_const), None, 0.0, 0.0, 0.0
+    return IN_NONE, None, None, 0.0, 0.0, 0.0
+
+
+def background_count(w0: int, lam: float) -> int:
+    """N for Philox word w0 (inverse transform in binary32)."""
+    return int(lib().ora_background_count(int(w0), float(lam)))
+
+
+def background(seed: int, nid: int, t: int, lam: float, mu: float, sigma: float):
+    """(current, N) of the background input for (seed, element, step)."""
+    N = ctypes.c_int32()
+    I = lib().ora_background(int(seed), int(nid), int(t), float(lam), float(mu), float(sigma),
+                             ctypes.byref(N))
+    return I, N.value
+
+
 def run(model: dict, state: np.ndarray, T: int, t0: int = 0, *, i_const=None, noise_mu=None,
         noise_sigma=None, seed: int = 0, i_dense=None, coef=None, cm=None, ids=None,
-        record_v: bool = False, record_spikes: bool = True, level: bool = False):
+        record_v: bool = False, record_spikes: bool = True, level: bool = False, background=None):
     """Advance independent neurons T steps in place.  Returns dict with
     'spikes' [T][n] uint8 (upward crossings), 'v' [T][n] (optional) and
     'level' [n] (count of steps with V >= v_th, optional)."""
     s = model_to_struct(model)
     n = state.shape[1]
     assert state.dtype == np.float64 and state.flags.c_contiguous
-    if i_dense is not None:
-        mode, i_dense = IN_DENSE, _f64(i_dense)
-        assert i_dense.shape == (T, n)
-    elif noise_mu is not None:
-        mode = IN_NOISE
-    elif i_const is not None:
-        mode = IN_CONST
-        i_const = _f64(i_const)
-    else:
-        mode = IN_NONE
+    mode, i_const, i_dense, mu, sigma, lam = _input_mode(T, n, i_const, noise_mu, noise_sigma,
+                                                        i_dense, background)
     coef, cm = _f64(coef), _f64(cm)
     ids = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
     spk = np.zeros((T, n), np.uint8) if record_spikes else None
     vr = np.zeros((T, n), np.float64) if record_v else None
     lv = np.zeros(n, np.float64) if level else None
     rc = lib().ora_run(ctypes.byref(s), n, _p(coef), _p(cm), _p(ids), _p(state), int(t0), int(T),
-                       mode, _p(i_const), float(noise_mu or 0.0), float(noise_sigma or 0.0),
-                       int(seed), _p(i_dense), _p(spk), _p(vr), _p(lv))
+                       mode, _p(i_const), mu, sigma, int(seed), lam, _p(i_dense), _p(spk), _p(vr),
+                       _p(lv))
     if rc != 0:
         raise ValueError("oracle rejected the model (rc=%d)" % rc)
     return {"spikes": spk, "v": vr, "level": lv}
@@ -250,7 +276,7 @@ def run(model: dict, state: np.ndarray, T: int, t0: int = 0, *, i_const=None, no
 
 def cable_run(model: dict, state: np.ndarray, T: int, morph: dict, t0: int = 0, *, i_const=None,
               noise_mu=None, noise_sigma=None, seed: int = 0, i_dense=None, coef=None, cm=None,
-              ids=None, record_v: bool = False, record_spikes: bool = True):
+              ids=None, record_v: bool = False, record_spikes: bool = True, background=None):
     """Advance multi-compartment neurons T steps in place (state [n_state][n],
     n = N*K).  morph = {"K": K, "parent": [K], "g_axial": [K],
     "area": [K] or None, "gbar": [K][n_channels] or None}.  Returns dict with
@@ -263,23 +289,15 @@ def cable_run(model: dict, state: np.ndarray, T: int, morph: dict, t0: int = 0, 
     g_ax = _f64(np.zeros(K) if morph.get("g_axial") is None else morph["g_axial"])
     area = _f64(morph.get("area"))
     gbar = _f64(morph.get("gbar"))
-    if i_dense is not None:
-        mode, i_dense = IN_DENSE, _f64(i_dense)
-        assert i_dense.shape == (T, n)
-    elif noise_mu is not None:
-        mode = IN_NOISE
-    elif i_const is not None:
-        mode, i_const = IN_CONST, _f64(i_const)
-    else:
-        mode = IN_NONE
+    mode, i_const, i_dense, mu, sigma, lam = _input_mode(T, n, i_const, noise_mu, noise_sigma,
+                                                        i_dense, background)
     coef, cm = _f64(coef), _f64(cm)
     ids = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
     spk = np.zeros((T, n), np.uint8) if record_spikes else None
     vr = np.zeros((T, n), np.float64) if record_v else None
     rc = lib().ora_cable_run(ctypes.byref(s), n, K, _p(parent), _p(g_ax), _p(area), _p(gbar),
                              _p(coef), _p(cm), _p(ids), _p(state), int(t0), int(T), mode, _p(i_const),
-                             float(noise_mu or 0.0), float(noise_sigma or 0.0), int(seed),
-                             _p(i_dense), _p(spk), _p(vr))
+                             mu, sigma, int(seed), lam, _p(i_dense), _p(spk), _p(vr))
     if rc != 0:
         raise ValueError("oracle rejected the model or morphology (rc=%d)" % rc)
     return {"spikes": spk, "v": vr}

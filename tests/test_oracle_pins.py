@@ -821,3 +821,61 @@ def test_cable_spike_propagates_from_tip_to_soma(ora):
     first = [int(np.argmax(r["spikes"][:, c])) if r["spikes"][:, c].any() else -1 for c in range(K)]
     assert min(first) >= 0, first
     assert all(first[c] > first[c + 1] for c in range(K - 1)), first
+
+
+# ---------------------------------------------------------------------------
+# Background input of the cortex model: N ~ Poisson(lam) events per step of
+# Gaussian amplitude (mu, sigma), drawn directly as N mu + sqrt(N) sigma z.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [0.05, 1.6, 7.3, 40.0, 80.0])
+def test_background_count_is_the_poisson_inverse_cdf(ora, lam):
+    """N equals scipy's Poisson quantile of u (the exact inverse CDF in
+    binary64) except where u lies within binary32 rounding of a CDF value."""
+    from scipy.stats import poisson
+    rng = np.random.default_rng(int(lam * 100))
+    w = rng.integers(0, 2 ** 32, 20000, dtype=np.uint64)
+    u = (2.0 * (w >> 9) + 1.0) * 2.0 ** -24
+    got = np.array([ora.background_count(int(x), lam) for x in w])
+    want = poisson.ppf(u, lam).astype(np.int64)
+    diff = np.nonzero(got != want)[0]
+    assert len(diff) <= 2, (lam, len(diff))
+    for j in diff:
+        assert abs(got[j] - want[j]) == 1
+        assert abs(u[j] - poisson.cdf(min(got[j], want[j]), lam)) < 1e-5 * max(1.0, lam)
+
+
+@pytest.mark.parametrize("lam", [0.3, 1.6, 12.0])
+def test_background_counts_and_current_moments(ora, lam):
+    """Counts follow Poisson(lam) (chi-square over the bulk of the pmf); the
+    current has the compound-Poisson mean lam mu and variance
+    lam (mu^2 + sigma^2)."""
+    from scipy.stats import chisquare, poisson
+    mu, sigma = 0.7, 1.3
+    n = 40000
+    I = np.empty(n)
+    N = np.empty(n, np.int64)
+    for j in range(n):
+        I[j], N[j] = ora.background(11, j % 997, j // 997, lam, mu, sigma)
+    kmax = int(poisson.ppf(0.999, lam))
+    obs = np.array([(N == k).sum() for k in range(kmax)] + [(N >= kmax).sum()])
+    exp = n * np.append(poisson.pmf(np.arange(kmax), lam), poisson.sf(kmax - 1, lam))
+    assert chisquare(obs, exp).pvalue > 1e-3
+    se_m = np.sqrt(lam * (mu ** 2 + sigma ** 2) / n)
+    assert abs(I.mean() - lam * mu) < 5 * se_m
+    assert abs(I.var() / (lam * (mu ** 2 + sigma ** 2)) - 1) < 0.05
+
+
+def test_background_special_cases_and_one_step(ora):
+    for t in range(50):
+        assert ora.background(3, 7, t, 0.0, 1.0, 1.0) == (0.0, 0)
+        I, N = ora.background(3, 7, t, 2.5, 1.25, 0.0)
+        assert I == 1.25 * N
+    # a gate-free, conductance-free element started at V = 0 with dt = C = 1
+    # integrates exactly the drawn current in one step
+    m = {"gates": [], "channels": [], "C": 1.0, "dt": 1.0, "v_th": 1e9, "v_method": "fe",
+         "syn": None}
+    for t0 in (0, 5, 1001):
+        st = np.zeros((1, 40))
+        ora.run(m, st, 1, t0=t0, seed=99, background=(3.0, 0.5, 2.0), record_spikes=False)
+        want = [ora.background(99, i, t0, 3.0, 0.5, 2.0)[0] for i in range(40)]
+        assert np.array_equal(st[0], want)
