@@ -53,10 +53,35 @@ def _subset_kw(kw, idx, n):
     return out
 
 
+def nominal_coef(model, count):
+    """The model's rate coefficients as a per-element table [G*8][count]."""
+    G = len(model["gates"])
+    nom = np.zeros(G * 8)
+    for g, gate in enumerate(model["gates"]):
+        for r, rt in enumerate(gate["rates"]):
+            nom[g * 8 + r * 4: g * 8 + r * 4 + 4] = rt[1:5]
+    return np.repeat(nom[:, None], count, axis=1)
+
+
+def input_probes(kw, f):
+    """Copies of the oracle arguments with the input scaled by f: the
+    constant, noise-mean or dense input, or the background amplitudes."""
+    out = []
+    for key in ("i_const", "noise_mu", "i_dense"):
+        if kw.get(key) is not None:
+            out.append(dict(kw, **{key: kw[key] * f}))
+    if kw.get("background") is not None:
+        lam, mu, sigma = kw["background"]
+        out.append(dict(kw, background=(lam, mu * f, sigma * f)))
+    return out
+
+
 def ill_conditioned(O, model, st0, T, idx, base_kw, *, v_tol=1e-3):
     """Returns (spike_ill, trace_ill): boolean arrays over idx.  spike_ill: a
     probe moves the oracle's spike train by more than one dt (or changes its
-    count); trace_ill: a probe moves V by more than v_tol at some step."""
+    count); trace_ill: a probe moves V by more than v_tol at some step.  The
+    probes are those of spike_horizons (input, capacitance, one group of rate
+    coefficients) and the initial state."""
     idx = np.asarray(idx, dtype=np.int64)
     n = st0.shape[1]
     if len(idx) == 0:
@@ -66,15 +91,18 @@ def ill_conditioned(O, model, st0, T, idx, base_kw, *, v_tol=1e-3):
     if cm is None:
         cm = np.full(len(idx), float(model["C"]))
     ref = O.run(model, st0[:, idx].copy(), T, record_v=True, **dict(kw, cm=cm))
+    coef = kw.get("coef")
+    if coef is None and len(model["gates"]):
+        coef = nominal_coef(model, len(idx))
     probes = []
     for f in (1 + PROBE, 1 - PROBE):
-        if kw.get("i_const") is not None:
-            probes.append(dict(kw, cm=cm, i_const=kw["i_const"] * f))
-        if kw.get("noise_mu") is not None:
-            probes.append(dict(kw, cm=cm, noise_mu=kw["noise_mu"] * f))
-        if kw.get("i_dense") is not None:
-            probes.append(dict(kw, cm=cm, i_dense=kw["i_dense"] * f))
+        probes += [dict(p, cm=cm) for p in input_probes(kw, f)]
         probes.append(dict(kw, cm=cm * f))
+        if coef is not None:
+            for j in range(3):  # A, B, K rows of every rate
+                c2 = coef.copy()
+                c2[j::4] *= f
+                probes.append(dict(kw, cm=cm, coef=c2))
     s0 = st0[:, idx]
     starts = [s0] * len(probes)
     # initial-state probes: V0 and every gate scaled by (1 +- 1e-6)
@@ -140,12 +168,7 @@ def spike_horizons(O, model, st0, T, idx, base_kw, *, shift_tol=0.1):
         cm = np.full(len(idx), float(model["C"]))
     coef = kw.get("coef")
     if coef is None:
-        G = len(model["gates"])
-        nom = np.zeros(G * 8)
-        for g, gate in enumerate(model["gates"]):
-            for r, rt in enumerate(gate["rates"]):
-                nom[g * 8 + r * 4: g * 8 + r * 4 + 4] = rt[1:5]
-        coef = np.repeat(nom[:, None], len(idx), axis=1)
+        coef = nominal_coef(model, len(idx))
     kw = dict(kw, cm=cm, coef=coef)
     s0 = st0[:, idx]
     thr = float(model["v_th"])
@@ -154,9 +177,7 @@ def spike_horizons(O, model, st0, T, idx, base_kw, *, shift_tol=0.1):
     base_t = _interp_times(v0, thr)
     probes = []
     for f in (1 + PROBE, 1 - PROBE):
-        for key in ("i_const", "noise_mu", "i_dense"):
-            if kw.get(key) is not None:
-                probes.append(dict(kw, **{key: kw[key] * f}))
+        probes += input_probes(kw, f)
         probes.append(dict(kw, cm=cm * f))
         for j in range(3):  # A, B, K rows of every rate
             c2 = coef.copy()

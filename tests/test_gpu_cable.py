@@ -3,8 +3,8 @@ term; second-order explicit difference in space) against the oracle's
 cable run.  Criteria as for point neurons: compartments that never spike
 follow the oracle within 1e-3 mV at every step, spike trains agree in count
 and within one dt; a mismatch is excused only when 1e-6 relative probes of
-the input, C_m or V0 move the oracle's own result for that compartment by
-more than the tolerance, or storing the oracle's state in FP32 after every
+the input, C_m, V0 or one group (A, B or K) of rate coefficients move the
+oracle's own result for that compartment by more than the tolerance, or storing the oracle's state in FP32 after every
 step moves its trace by more than half of it (ill-conditioned), and such
 cases are counted."""
 import numpy as np
@@ -12,7 +12,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2601_21407_amd import workloads as W
-from tests.gpu_util import need_gpu, print_case, spike_mismatch
+from tests.gpu_util import input_probes, need_gpu, nominal_coef, print_case, spike_mismatch
 
 pytestmark = pytest.mark.gpu
 
@@ -102,15 +102,21 @@ def _ill(model, morph, st0, T, cand, kw, *, v_tol, quiet):
     base = _cols(kw, cols)
     if base.get("cm") is None:
         base["cm"] = np.full(len(cols), float(model["C"]))
-    if "noise_mu" in base and base.get("ids") is None:
+    if ("noise_mu" in base or "background" in base) and base.get("ids") is None:
         base["ids"] = cols.astype(np.uint32)
     ref = O.cable_run(model, st0[:, cols].copy(), T, morph, record_v=True, **base)
+    coef = base.get("coef")
+    if coef is None and len(model["gates"]):
+        coef = nominal_coef(model, len(cols))
     probes = []
     for f in (1 + PROBE, 1 - PROBE):
-        for key in ("i_const", "i_dense", "noise_mu"):
-            if base.get(key) is not None:
-                probes.append((dict(base, **{key: base[key] * f}), st0[:, cols]))
+        probes += [(p, st0[:, cols]) for p in input_probes(base, f)]
         probes.append((dict(base, cm=base["cm"] * f), st0[:, cols]))
+        if coef is not None:
+            for j in range(3):  # A, B, K rows of every rate
+                c2 = coef.copy()
+                c2[j::4] *= f
+                probes.append((dict(base, coef=c2), st0[:, cols]))
         s = st0[:, cols].copy()
         s[0] *= f
         probes.append((base, s))

@@ -92,7 +92,7 @@ def _judge(model, st0, T, g, ro, base_kw, *, max_ill_frac, v_tol=1e-3, label="")
            % (label, n, len(quiet), max(wc or [0.0]), len(spike_bad), beyond,
               int((tr_ill_q | sp_ill_q).sum()), len(fails)))
     print(rep, flush=True)
-    assert not fails, (rep, fails[:10])
+    assert not fails, (rep, [(i, float(dv[i])) for i in fails[:10]])
     assert n_ill <= max_ill_frac * n, rep
     return rep
 

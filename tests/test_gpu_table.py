@@ -72,7 +72,8 @@ def test_tabulated_input_modes(which, mode, syn, nodes):
         kw_g["i_dense"], kw_o["i_dense"] = I, I
     elif mode == "noise":
         kw_g["noise"] = (5.0, 3.0, 7)
-        kw_o.update(noise_mu=5.0, noise_sigma=3.0, seed=7)
+        # ids travel with neuron subsets when the judge re-runs a few neurons
+        kw_o.update(noise_mu=5.0, noise_sigma=3.0, seed=7, ids=np.arange(n, dtype=np.uint32))
     else:
         I = (12.0 * rng.random(n)).astype(np.float32).astype(np.float64)
         kw_g["i_const"], kw_o["i_const"] = I, I
