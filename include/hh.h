@@ -68,7 +68,7 @@ enum { HH_GATE_ALPHA_BETA = 0, HH_GATE_INF_TAU = 1 };
 /* Membrane update: explicit Euler (Eq. (2)) or exponential Euler in V. */
 enum { HH_V_FE = 0, HH_V_EE = 1 };
 /* External current. */
-enum { HH_IN_NONE = 0, HH_IN_CONST = 1, HH_IN_NOISE = 2, HH_IN_DENSE = 3 };
+enum { HH_IN_NONE = 0, HH_IN_CONST = 1, HH_IN_NOISE = 2, HH_IN_DENSE = 3, HH_IN_BACKGROUND = 4 };
 
 typedef struct {
   int32_t form;
@@ -108,7 +108,18 @@ typedef struct {
   float mu, sigma;       /* HH_IN_NOISE: I = mu + sigma z, z standard normal */
   uint64_t seed;         /* HH_IN_NOISE: Philox4x32-10 key */
   const float* i_dense;  /* HH_IN_DENSE: [n_steps][n], row t is step t0 + t */
+  float lam;             /* HH_IN_BACKGROUND: expected events per step, [0, 80] */
 } hh_input;
+/* HH_IN_BACKGROUND (Methods, cortical network: the background input drawn
+ * directly from its distribution): per element and step, N ~ Poisson(lam)
+ * background events of independent Gaussian amplitude (mu, sigma), so
+ * I = N mu + sqrt(N) sigma z.  The random words are Philox4x32-10 block
+ * (t, stream 2) of the element, keyed by seed: word 0 gives
+ * u = (2 floor(w0 / 2^9) + 1) 2^-24 and N is the smallest k with u <= F(k),
+ * F the Poisson CDF accumulated in binary32 from p_0 = e^-lam (rounded once
+ * from binary64) with each product, quotient and sum rounded on its own,
+ * up to floor(lam + 12 sqrt(lam)) + 12; words 2 and 3 give z by Box-Muller
+ * (cosine branch, u = (w + 1/2) 2^-32). */
 
 /* Optional outputs of hh_step_n (any pointer may be NULL). */
 typedef struct {

@@ -99,22 +99,24 @@ __device__ __forceinline__ void step_with_jacobian(const KModel& M, const LaneRa
     float d0, d1;
     const float r0 = rate_eval<true>(S::form(M, g, 0), L.r[g][0], V, &d0);
     const float r1 = rate_eval<true>(S::form(M, g, 1), L.r[g][1], V, &d1);
-    float pinf, dpinf, e, de;
+    float pinf, dpinf, e, q, de;  // q = 1 - e, formed as the forward step forms it
     if (S::kind(M, g) == KIND_AB) {
       const float sr = r0 + r1, is = rcp(sr);
       pinf = r0 * is;
       dpinf = (d0 * r1 - r0 * d1) * is * is;
       e = ex2(sr * M.kdt);
+      q = 1.0f - e;
       de = ndt * (d0 + d1) * e;
     } else {
       pinf = r0;
       dpinf = d0;
-      e = ex2(r1 * M.kdt);
+      q = one_minus_exp_neg(r1 * M.dt);
+      e = 1.0f - q;
       de = ndt * d1 * e;
     }
     J.e[g] = e;
-    J.dpv[g] = fmaf(dpinf, 1.0f - e, (p[g] - pinf) * de);
-    p[g] = gate_update(p[g], pinf, e);
+    J.dpv[g] = fmaf(dpinf, q, (p[g] - pinf) * de);
+    p[g] = fmaf(pinf - p[g], q, p[g]);
   }
   // membrane (explicit Euler)
   const float iion = fmaf(gsum, vl, fmaf(gsum, V, -esum));

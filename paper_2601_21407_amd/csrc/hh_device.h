@@ -20,7 +20,7 @@ constexpr float kLn2 = 0.6931471805599453f;
 enum { FORM_EXP = 0, FORM_SIGMOID = 1, FORM_LINOID = 2, FORM_BELL = 3 };
 enum { KIND_AB = 0, KIND_INFTAU = 1 };
 enum { VFE = 0, VEE = 1 };
-enum { IN_NONE = 0, IN_CONST = 1, IN_NOISE = 2, IN_DENSE = 3 };
+enum { IN_NONE = 0, IN_CONST = 1, IN_NOISE = 2, IN_DENSE = 3, IN_BACKGROUND = 4 };
 
 // One rate function in a form ready for the exp2 unit.  With x = V*s + o =
 // log2(e) (V - B) / K:
@@ -285,6 +285,21 @@ __device__ __forceinline__ float expm1_neg(float z) {
   return (z < 0.1f) ? s : ex2(-z * kLog2e) - 1.0f;
 }
 
+// 1 - e^{-z} for z >= 0 (the exponential-Euler gate increment q): the
+// series z - z^2/2 + z^3/6 below 0.011 (truncation < 6e-8 relative), where
+// 1 - e would cancel; beyond it 1 - e keeps its relative error below 1e-5.
+__device__ __forceinline__ float one_minus_exp_neg(float z) {
+  float q = z * fmaf(z, fmaf(z, 1.0f / 6.0f, -0.5f), 1.0f);
+  if (z >= 0.011f) {
+    // rare for slow gates: kept a branch (the empty asm stops the compiler
+    // from evaluating it for every lane and selecting), so that its value
+    // is never live beside the series
+    asm volatile("");
+    q = 1.0f - ex2(-z * kLog2e);
+  }
+  return q;
+}
+
 // Channel conductances g_X: the model's, the same for every neuron
 // (ModelGbar), or one set per lane (LaneGbar: the compartments of a
 // morphology, each with its own channel densities).
@@ -359,16 +374,15 @@ __device__ __forceinline__ void neuron_step(const KModel& M, const LR& L, float 
     for (int g = 0; g < NG; ++g) {
       const float r0 = rate_eval<false>(S::form(M, g, 0), L.r[g][0], V, nullptr);
       const float r1 = rate_eval<false>(S::form(M, g, 1), L.r[g][1], V, nullptr);
-      float pinf, e;
       if (S::kind(M, g) == KIND_AB) {
         const float s = r0 + r1;
-        pinf = r0 * rcp(s);
-        e = ex2(s * M.kdt);
+        p[g] = gate_update(p[g], r0 * rcp(s), ex2(s * M.kdt));
       } else {
-        pinf = r0;
-        e = ex2(r1 * M.kdt);
+        // (p_inf, 1/tau) gates carry the slow kinetics (tau up to seconds):
+        // there e^{-dt/tau} lies within a few ulps of 1, and 1 - e formed from
+        // it would lose most of its digits, so q = 1 - e comes from the series
+        p[g] = fmaf(r0 - p[g], one_minus_exp_neg(r1 * M.dt), p[g]);
       }
-      p[g] = gate_update(p[g], pinf, e);
     }
   }
   // membrane
@@ -425,6 +439,39 @@ __device__ __forceinline__ void normals4(uint64_t seed, uint32_t id, uint64_t bl
   z[1] = ra * __builtin_amdgcn_sinf(u1);
   z[2] = rb * __builtin_amdgcn_cosf(u3);
   z[3] = rb * __builtin_amdgcn_sinf(u3);
+}
+
+// Background input (Methods, cortical network), drawn directly: N ~
+// Poisson(lam) events of Gaussian amplitude (mu, sigma), N mu + sqrt(N) sigma
+// z.  N is an integer decided by floating point, so its inverse-transform
+// search uses only correctly rounded binary32 operations, each rounded on
+// its own (contraction off), from p0 = e^-lam rounded once on the host;
+// u = (2 floor(w0 / 2^9) + 1) 2^-24 is exact in binary32.
+__device__ __forceinline__ int background_count(uint32_t w0, float lam, float p0, int kmax) {
+#pragma clang fp contract(off)
+  const float u = (float)(2u * (w0 >> 9) + 1u) * 0x1p-24f;
+  int k = 0;
+  float p = p0, F = p0;
+  while (u > F && k < kmax) {
+    ++k;
+    p = p * (lam / (float)k);
+    F = F + p;
+  }
+  return k;
+}
+
+__device__ __forceinline__ float background_current(uint64_t seed, uint32_t id, uint64_t t,
+                                                    float lam, float p0, int kmax, float mu,
+                                                    float sigma) {
+  U4 c = {(uint32_t)t, (uint32_t)(t >> 32), id, 2u};
+  const U4 w = philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const float fk = (float)background_count(w.x, lam, p0, kmax);
+  const float s = 2.3283064365386963e-10f;  // 2^-32
+  const float h = 1.1641532182693481e-10f;  // 2^-33
+  const float ua = fmaf((float)w.z, s, h), ub = fmaf((float)w.w, s, h);
+  const float z = __builtin_amdgcn_sqrtf(-2.0f * kLn2 * __builtin_amdgcn_logf(ua)) *
+                  __builtin_amdgcn_cosf(ub);
+  return fmaf(fk, mu, __builtin_amdgcn_sqrtf(fk) * sigma * z);
 }
 
 __device__ __forceinline__ uint32_t event_word(uint64_t seed, uint32_t id, uint64_t t) {

@@ -16,6 +16,8 @@ struct StepArgs {
   const float* i_const;
   float mu, sigma;
   uint64_t seed;
+  float bg_lam, bg_p0;   // background input: events per step, e^-lam
+  int32_t bg_kmax;       // and the count's cap
   const float* i_dense;  // row 0 = step k_base of the call
   uint32_t* spikes;      // row 0 = step k_base of the call
   int64_t words;

@@ -190,16 +190,13 @@ __device__ __forceinline__ void net_update(const KModel& M, const LaneRates<S::k
   for (int g = 0; g < NG; ++g) {
     const float r0 = rate_eval<false>(S::form(M, g, 0), L.r[g][0], V, nullptr);
     const float r1 = rate_eval<false>(S::form(M, g, 1), L.r[g][1], V, nullptr);
-    float pinf, e;
     if (S::kind(M, g) == KIND_AB) {
       const float sr = r0 + r1;
-      pinf = r0 * rcp(sr);
-      e = ex2(sr * M.kdt);
+      p[g] = gate_update(p[g], r0 * rcp(sr), ex2(sr * M.kdt));
     } else {
-      pinf = r0;
-      e = ex2(r1 * M.kdt);
+      // slow (p_inf, 1/tau) gates: 1 - e from the series, as in neuron_step
+      p[g] = fmaf(r0 - p[g], one_minus_exp_neg(r1 * M.dt), p[g]);
     }
-    p[g] = gate_update(p[g], pinf, e);
   }
   // arrivals of the previous step's spikes
   ge += (float)ae * kUnfix;

@@ -261,6 +261,9 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
         z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
       } else if (A.in_mode == IN_DENSE) {
         I = A.i_dense[(int64_t)k * n + ii];
+      } else if (A.in_mode == IN_BACKGROUND) {
+        I = background_current(A.seed, nid, (uint64_t)t, A.bg_lam, A.bg_p0, A.bg_kmax, A.mu,
+                               A.sigma);
       }
       const float V = vh;
       if constexpr (TAB != TAB_NONE)
