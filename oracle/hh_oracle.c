@@ -469,26 +469,33 @@ void ora_syn_deliver(int64_t n, const int64_t* row_ptr, const int32_t* col, cons
 }
 
 /* Recurrent network.  Each step: every neuron advances with its conductances
- * held at time t; a neuron spikes on an upward crossing of v_th; then
- *   g_e(t+1) = g_e(t) e^{-dt/tau_e} + scale * sum of w>0 from sources that
- *              spiked at t+1 + w_ext * (external event at t+1),
+ * held at time t (input: none, constant, or the background input); a neuron
+ * spikes on an upward crossing of v_th; then
+ *   g_e(t+1) = g_e(t) e^{-dt/tau_e} + scale * sum of w>0 over the synapses
+ *              whose source spiked at t + 1 - d (d the synapse's delay in
+ *              steps, 1 without a delay table) + w_ext * (external event at t+1),
  *   g_i(t+1) likewise with |w| of w<0 and no external term.
- * External events: driven neurons (ext_mask) get a Bernoulli event when the
- * stream-1 Philox word for (id, t+1) is below ext_thresh. */
+ * Arrivals due after the last step are dropped.  External events: driven
+ * neurons (ext_mask) get a Bernoulli event when the stream-1 Philox word for
+ * (id, t+1) is below ext_thresh. */
 int32_t ora_net_run(const ora_model* m, int64_t n, double* state, const int64_t* row_ptr,
-                    const int32_t* col, const double* w, double w_scale,
-                    const uint8_t* ext_mask, uint32_t ext_thresh, double w_ext, uint64_t seed,
-                    const double* i_const, int64_t t0, int32_t T, uint8_t* spk) {
+                    const int32_t* col, const double* w, double w_scale, const uint8_t* delay,
+                    int32_t max_delay, const uint8_t* ext_mask, uint32_t ext_thresh, double w_ext,
+                    uint64_t seed, int32_t in_mode, const double* i_const, double mu, double sigma,
+                    uint64_t in_seed, double lam, int64_t t0, int32_t T, uint8_t* spk) {
   if (!model_ok(m) || !m->has_syn || n < 0 || T < 0) return -1;
+  if (!delay) max_delay = 1;
+  if (max_delay < 1) return -1;
   const int G = m->n_gates;
+  const int R = max_delay + 1; /* arrival slots: times t+1 .. t+max_delay, and t */
   double* V = state;
   double* ge = state + (int64_t)(1 + G) * n;
   double* gi = state + (int64_t)(2 + G) * n;
   uint8_t* s = (uint8_t*)calloc((size_t)n + 1, 1);
-  double* acc_e = (double*)calloc((size_t)n + 1, sizeof(double));
-  double* acc_i = (double*)calloc((size_t)n + 1, sizeof(double));
-  if (!s || !acc_e || !acc_i) {
-    free(s); free(acc_e); free(acc_i);
+  double* pend_e = (double*)calloc((size_t)R * (size_t)n + 1, sizeof(double));
+  double* pend_i = (double*)calloc((size_t)R * (size_t)n + 1, sizeof(double));
+  if (!s || !pend_e || !pend_i) {
+    free(s); free(pend_e); free(pend_i);
     return -2;
   }
   const double de = exp(-m->dt / m->tau_e), di = exp(-m->dt / m->tau_i);
@@ -497,25 +504,37 @@ int32_t ora_net_run(const ora_model* m, int64_t n, double* state, const int64_t*
     for (int64_t i = 0; i < n; ++i) {
       double p[ORA_MAX_GATES], pn[ORA_MAX_GATES], Vn;
       for (int g = 0; g < G; ++g) p[g] = state[(int64_t)(1 + g) * n + i];
-      double I = i_const ? i_const[i] : 0.0;
+      double I = 0.0;
+      if (in_mode == ORA_IN_CONST) I = i_const[i];
+      else if (in_mode == ORA_IN_BACKGROUND) I = ora_background(in_seed, (uint32_t)i, t, lam, mu, sigma, NULL);
       neuron_step(m, NULL, n, i, m->C, V[i], p, ge[i], gi[i], I, &Vn, pn);
       s[i] = (uint8_t)(V[i] < m->v_th && Vn >= m->v_th);
       V[i] = Vn;
       for (int g = 0; g < G; ++g) state[(int64_t)(1 + g) * n + i] = pn[g];
     }
-    memset(acc_e, 0, (size_t)n * sizeof(double));
-    memset(acc_i, 0, (size_t)n * sizeof(double));
-    ora_syn_deliver(n, row_ptr, col, w, w_scale, s, acc_e, acc_i);
+    /* a spike of step t through a synapse of delay d arrives at step t + d:
+     * sources in index order, each row in CSR order */
+    for (int64_t j = 0; j < n; ++j) {
+      if (!s[j]) continue;
+      for (int64_t e = row_ptr[j]; e < row_ptr[j + 1]; ++e) {
+        const int64_t slot = (t + (delay ? delay[e] : 1)) % R;
+        if (w[e] > 0.0) pend_e[slot * n + col[e]] += w_scale * w[e];
+        else if (w[e] < 0.0) pend_i[slot * n + col[e]] += w_scale * (-w[e]);
+      }
+    }
+    const int64_t a = (t + 1) % R;
     for (int64_t i = 0; i < n; ++i) {
       double ext = 0.0;
       if (ext_mask && ext_mask[i] && ora_event_word(seed, (uint32_t)i, t + 1) < ext_thresh)
         ext = w_ext;
-      ge[i] = ge[i] * de + acc_e[i] + ext;
-      gi[i] = gi[i] * di + acc_i[i];
+      ge[i] = ge[i] * de + pend_e[a * n + i] + ext;
+      gi[i] = gi[i] * di + pend_i[a * n + i];
+      pend_e[a * n + i] = 0.0;
+      pend_i[a * n + i] = 0.0;
       if (spk) spk[(int64_t)k * n + i] = s[i];
     }
   }
-  free(s); free(acc_e); free(acc_i);
+  free(s); free(pend_e); free(pend_i);
   return 0;
 }
 

@@ -111,11 +111,15 @@ int32_t ora_cable_run(const ora_model* m, int64_t n, int32_t K, const int32_t* p
                       double sigma, uint64_t seed, double lam, const double* i_dense, uint8_t* spk,
                       double* vrec);
 
-/* Recurrent network with exponential-decay conductance synapses. */
+/* Recurrent network with exponential-decay conductance synapses.  delay
+ * (nullable): per-synapse delays in steps, [nnz], each in [1, max_delay].
+ * in_mode: ORA_IN_NONE, ORA_IN_CONST (i_const [n]) or ORA_IN_BACKGROUND
+ * (lam, mu, sigma, in_seed). */
 int32_t ora_net_run(const ora_model* m, int64_t n, double* state, const int64_t* row_ptr,
-                    const int32_t* col, const double* w, double w_scale,
-                    const uint8_t* ext_mask, uint32_t ext_thresh, double w_ext, uint64_t seed,
-                    const double* i_const, int64_t t0, int32_t T, uint8_t* spk);
+                    const int32_t* col, const double* w, double w_scale, const uint8_t* delay,
+                    int32_t max_delay, const uint8_t* ext_mask, uint32_t ext_thresh, double w_ext,
+                    uint64_t seed, int32_t in_mode, const double* i_const, double mu, double sigma,
+                    uint64_t in_seed, double lam, int64_t t0, int32_t T, uint8_t* spk);
 
 /* One synaptic delivery: g_e[i] += scale*w for every synapse j->i with w > 0
  * and s_j = 1; g_i[i] += scale*|w| for w < 0.  In CSR order. */

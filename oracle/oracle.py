@@ -148,8 +148,8 @@ def lib():
         L.ora_background.argtypes = [u64, u32, i64, d, d, d, P(i32)]
         L.ora_background.restype = d
         L.ora_run.restype = i32
-        L.ora_net_run.argtypes = [P(OraModel), i64, vp, vp, vp, vp, d, vp, u32, d, u64, vp,
-                                  i64, i32, vp]
+        L.ora_net_run.argtypes = [P(OraModel), i64, vp, vp, vp, vp, d, vp, i32, vp, u32, d, u64,
+                                  i32, vp, d, d, u64, d, i64, i32, vp]
         L.ora_net_run.restype = i32
         L.ora_syn_deliver.argtypes = [i64, vp, vp, vp, d, vp, vp, vp]
         L.ora_syn_deliver.restype = None
@@ -304,19 +304,30 @@ def cable_run(model: dict, state: np.ndarray, T: int, morph: dict, t0: int = 0, 
 
 
 def net_run(model: dict, state: np.ndarray, csr, w_scale: float, T: int, t0: int = 0, *,
-            ext_mask=None, ext_thresh: int = 0, w_ext: float = 0.0, seed: int = 0, i_const=None):
-    """Recurrent network, T steps in place; returns spikes [T][n] uint8."""
+            ext_mask=None, ext_thresh: int = 0, w_ext: float = 0.0, seed: int = 0, i_const=None,
+            delay=None, max_delay: int = 1, background=None, in_seed: int = 0):
+    """Recurrent network, T steps in place; returns spikes [T][n] uint8.
+    delay: per-synapse delays in steps [nnz] (None: 1); background =
+    (lam, mu, sigma) drawn with in_seed."""
     s = model_to_struct(model)
     n = state.shape[1]
     row_ptr = np.ascontiguousarray(csr[0], dtype=np.int64)
     col = np.ascontiguousarray(csr[1], dtype=np.int32)
     w = _f64(csr[2])
+    dl = None if delay is None else np.ascontiguousarray(delay, dtype=np.uint8)
     em = None if ext_mask is None else np.ascontiguousarray(ext_mask, dtype=np.uint8)
     ic = _f64(i_const)
+    mode, mu, sigma, lam = IN_NONE, 0.0, 0.0, 0.0
+    if background is not None:
+        mode = IN_BACKGROUND
+        lam, mu, sigma = (float(x) for x in background)
+    elif ic is not None:
+        mode = IN_CONST
     spk = np.zeros((T, n), np.uint8)
     rc = lib().ora_net_run(ctypes.byref(s), n, _p(state), _p(row_ptr), _p(col), _p(w),
-                           float(w_scale), _p(em), int(ext_thresh), float(w_ext), int(seed),
-                           _p(ic), int(t0), int(T), _p(spk))
+                           float(w_scale), _p(dl), int(max_delay), _p(em), int(ext_thresh),
+                           float(w_ext), int(seed), mode, _p(ic), mu, sigma, int(in_seed), lam,
+                           int(t0), int(T), _p(spk))
     if rc != 0:
         raise ValueError("oracle rejected the network (rc=%d)" % rc)
     return spk

@@ -879,3 +879,91 @@ def test_background_special_cases_and_one_step(ora):
         ora.run(m, st, 1, t0=t0, seed=99, background=(3.0, 0.5, 2.0), record_spikes=False)
         want = [ora.background(99, i, t0, 3.0, 0.5, 2.0)[0] for i in range(40)]
         assert np.array_equal(st[0], want)
+
+
+# ---------------------------------------------------------------------------
+# Network synapses with delays of several steps, and background input in the
+# network.
+# ---------------------------------------------------------------------------
+def test_net_unit_delays_equal_no_delay_table(ora):
+    m = W.net_model()
+    n = 300
+    csr = W.net_csr(n=n, fan_out=30, seed=4, inh_scale=4.0)
+    mask, thr = W.net_external(n=n, frac=0.1, seed=4)
+    v0 = W.net_v0(n, 4).astype(np.float64)
+    kw = dict(ext_mask=mask, ext_thresh=thr, w_ext=0.5, seed=4)
+    a, b = ora.init_state(m, v0), ora.init_state(m, v0)
+    ra = ora.net_run(m, a, csr, 0.3, 800, **kw)
+    rb = ora.net_run(m, b, csr, 0.3, 800, delay=np.ones(len(csr[1]), np.uint8), max_delay=9, **kw)
+    assert ra.sum() > 0 and np.array_equal(ra, rb) and np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("d", [1, 2, 7, 31])
+def test_net_single_delayed_synapse_closed_form(ora, d):
+    """Neuron 0 spikes repeatedly under a constant current and projects to
+    neuron 1 with weight 0.7 and delay d.  After T steps neuron 1's g_e is
+    sum over the source spikes at s of 0.7 scale e^{-dt (T - s - d)/tau_e}
+    for s + d <= T: each arrival lands exactly d steps after its spike and
+    then decays; later ones are still in flight."""
+    m = W.with_synapses(W.classic_hh(dt=0.05, v_method="ee"))
+    csr = (np.array([0, 1, 1], np.int64), np.array([1], np.int32), np.array([0.7]))
+    for T in (395, 400, 1237):
+        st = ora.init_state(m, np.full(2, -65.0))
+        spk = ora.net_run(m, st, csr, 0.01, T, i_const=np.array([15.0, 0.0]),
+                          delay=np.array([d], np.uint8), max_delay=max(d, 3))
+        s = np.nonzero(spk[:, 0])[0] + 1  # a spike in step k is at time k + 1
+        assert len(s) >= 2
+        due = s[s + d - 1 <= T]
+        want = sum(0.007 * np.exp(-0.05 * (T - (t + d - 1)) / 5.0) for t in due)
+        assert abs(st[4, 1] - want) < 1e-14, (T, st[4, 1], want)
+
+
+def test_net_background_without_synapses_is_the_independent_run(ora):
+    m = W.net_model()
+    n = 50
+    empty = (np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    v0 = W.net_v0(n, 2).astype(np.float64)
+    a, b = ora.init_state(m, v0), ora.init_state(m, v0)
+    ra = ora.net_run(m, a, empty, 0.3, 700, background=(1.2, 6.0, 3.0), in_seed=17)
+    rb = ora.run(m, b, 700, seed=17, background=(1.2, 6.0, 3.0))
+    assert ra.sum() > 0 and np.array_equal(ra, rb["spikes"]) and np.array_equal(a, b)
+
+
+def test_net_mixed_delays_brute_force(ora):
+    """A 6-neuron network with delays 1 to 5, stepped one step at a time
+    through the oracle's own neuron update (a network with no synapses) while
+    the delayed deliveries are kept in Python: the same spikes and state."""
+    m = W.net_model()
+    n, T, scale = 6, 900, 0.3
+    rng = np.random.default_rng(6)
+    rows = [sorted(rng.choice([x for x in range(n) if x != j], 3, replace=False)) for j in range(n)]
+    row_ptr = np.array([0] + list(np.cumsum([len(r) for r in rows])), np.int64)
+    col = np.array([c for r in rows for c in r], np.int32)
+    w = np.where(rng.random(len(col)) < 0.7, 1.0, -2.0) * (0.5 + rng.random(len(col)))
+    dl = rng.integers(1, 6, len(col)).astype(np.uint8)
+    I = 4.0 + 8.0 * rng.random(n)
+    v0 = W.net_v0(n, 6).astype(np.float64)
+    st = ora.init_state(m, v0)
+    ref = ora.net_run(m, st, (row_ptr, col, w), scale, T, i_const=I, delay=dl, max_delay=5)
+    assert ref.sum() > 10
+    empty = (np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    bs = ora.init_state(m, v0)
+    import math
+    pend = {}
+    de, di = math.exp(-0.1 / 5.0), math.exp(-0.1 / 10.0)  # the C library's exp, as the oracle's
+    G = len(m["gates"])
+    spikes = np.zeros((T, n), np.uint8)
+    for k in range(T):
+        ge, gi = bs[1 + G].copy(), bs[2 + G].copy()
+        sp = ora.net_run(m, bs, empty, scale, 1, t0=k, i_const=I)[0]
+        spikes[k] = sp
+        # the step's conductances decay and take the arrivals due at k + 1
+        for j in np.nonzero(sp)[0]:
+            for e in range(row_ptr[j], row_ptr[j + 1]):
+                key = (k + int(dl[e]), 0 if w[e] > 0 else 1, int(col[e]))
+                pend[key] = pend.get(key, 0.0) + scale * abs(w[e])
+        for i in range(n):
+            bs[1 + G, i] = (ge[i] * de + pend.pop((k + 1, 0, i), 0.0))
+            bs[2 + G, i] = (gi[i] * di + pend.pop((k + 1, 1, i), 0.0))
+    assert np.array_equal(spikes, ref)
+    assert np.array_equal(bs, st)
