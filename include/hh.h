@@ -226,6 +226,19 @@ int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const 
  * owned by the caller.  Requires has_syn and B == 1. */
 int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, const float* w,
                       int64_t nnz, float w_scale);
+/* Synaptic delays of several steps (Methods, cortical network: per-pathway
+ * synaptic delays): delay [nnz] (device, caller-owned, CSR order) gives each
+ * synapse's delay in steps, in [1, max_delay] with max_delay <= 255; a spike
+ * at step t then reaches g_e / g_i of its target at step t + delay instead
+ * of t + 1.  A pathway delay is every synapse of the pathway carrying it.
+ * The model keeps the arrivals still in flight in a ring of
+ * (max_delay + 1) x 2 x n 64-bit accumulators: consecutive hh_step_n calls
+ * on the same model (t0 continuing) deliver them, and a call with t0 = 0
+ * starts with none in flight.  delay = NULL returns to one-step delays;
+ * hh_attach_csr drops the table.  Errors: HH_E_INVALID without a CSR or for
+ * a delay outside [1, max_delay] (the table is read back once to check);
+ * HH_E_SHAPE for max_delay outside [1, 255]; HH_E_OOM. */
+int32_t hh_set_delays(hh_model* m, const uint8_t* delay, int32_t max_delay);
 /* External Poisson drive: neurons with ext_mask[i] != 0 receive w_ext on g_e
  * at step t when the stream-1 Philox4x32-10 word of (seed, i, t) is below
  * thresh (event probability thresh / 2^32 per step).  ext_mask: device [n]. */

@@ -58,6 +58,11 @@ struct hh_model {
   uint32_t ext_thresh;
   float w_ext;
   uint64_t ext_seed;
+  // synaptic delays: per-synapse steps (caller-owned [nnz]) and the ring of
+  // arrivals in flight, [max_delay + 1][2][n] (owned; null: one-step delay)
+  const uint8_t* delay;
+  int32_t max_delay;
+  unsigned long long* d_ring;
   // scratch for synaptic delivery: int64 accumulators [2][2][n], spike list [n],
   // counters and the grid barrier
   void* d_scratch;

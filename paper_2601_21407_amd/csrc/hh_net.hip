@@ -14,10 +14,15 @@
 //   -- grid barrier --
 //   B  each lane takes (and clears) its own arrivals into g_e, g_i.
 // Two accumulator buffers alternate between steps, so one barrier per step
-// suffices.
+// suffices.  With per-synapse delays of up to D steps the accumulators form
+// a ring of D + 1 slots indexed by absolute time: a step reads and clears
+// the slot of its own time and scatters into the slots 1..D steps ahead, so
+// reads and writes of one step never meet; arrivals still in flight at the
+// end of a call stay in the ring for the next call.
 //
 // hh_syn_propagate runs the same delivery once, outside the time loop, as
 // three kernels: global compaction, one wavefront per spiking row, apply.
+#include <stdlib.h>
 #include <string.h>
 
 #include <cmath>
@@ -48,7 +53,14 @@ struct NetArgs {
   int32_t nsteps;
   uint32_t* spikes;
   int64_t words;
-  unsigned long long* acc;  // [2 buffers][2 (e, i)][n]
+  unsigned long long* acc;  // [2 buffers][2 (e, i)][n], or with delays [R slots][2][n]
+  const uint8_t* delay;     // per-synapse delays in steps (null: 1)
+  int32_t R;                // ring slots (max delay + 1) when delay is set
+  // background input (Methods, cortical network): drawn per step when bg != 0
+  int32_t bg;
+  float mu, sigma, bg_lam, bg_p0;
+  int32_t bg_kmax;
+  uint64_t seed;
   unsigned* bar;            // [0] arrivals (monotonic within a launch)
   int32_t* flags;           // [0] first non-finite neuron, [1] timeout
   uint32_t spin_limit;
@@ -131,21 +143,29 @@ __device__ void block_inclusive_scan(int* v, int cnt) {
 // Scatter of `total` synaptic events of the block's spiking rows: lane t
 // takes events t, t + B, t + 2B, ... (B = block size), issuing up to 8
 // independent (col, w) loads before its atomics so the loads overlap.
+// DELAY: the events go to the ring slot (now + d) of their synapse's delay
+// d (clamped to [1, R - 1], so the slot always lies in the ring); acc_e is
+// then the ring's base and `now` the current time's slot.
+template <bool DELAY = false>
 __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
                                              const float* __restrict__ w, float scale40,
                                              const int64_t* s_r0, const int* s_pre, int cnt,
                                              int total, unsigned long long* acc_e,
-                                             unsigned long long* acc_i) {
+                                             unsigned long long* acc_i,
+                                             const uint8_t* __restrict__ delay = nullptr,
+                                             int now = 0, int R = 2, int64_t n = 0) {
   constexpr int U = 16;
   const int B = blockDim.x;
   for (int x0 = threadIdx.x; x0 < total; x0 += U * B) {
     int32_t tg[U];
     float wv[U];
+    int sl[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int x = x0 + u * B;
       tg[u] = -1;
       wv[u] = 0.0f;
+      sl[u] = 0;
       if (x < total) {
         // row e: first e with s_pre[e] > x
         int lo = 0, hi = cnt - 1;
@@ -158,13 +178,22 @@ __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
         const int64_t q = s_r0[lo] + (x - before);
         tg[u] = col[q];
         wv[u] = w[q];
+        if constexpr (DELAY) {
+          const int d = min(max((int)delay[q], 1), R - 1);
+          sl[u] = now + d >= R ? now + d - R : now + d;
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (tg[u] >= 0) {
         const unsigned long long inc = (unsigned long long)__float2ull_rn(fabsf(wv[u]) * scale40);
-        atomicAdd(wv[u] > 0.0f ? &acc_e[tg[u]] : &acc_i[tg[u]], inc);
+        if constexpr (DELAY) {
+          unsigned long long* slot = acc_e + (int64_t)sl[u] * 2 * n;
+          atomicAdd(wv[u] > 0.0f ? &slot[tg[u]] : &slot[n + tg[u]], inc);
+        } else {
+          atomicAdd(wv[u] > 0.0f ? &acc_e[tg[u]] : &acc_i[tg[u]], inc);
+        }
       }
     }
   }
@@ -228,7 +257,7 @@ __device__ __forceinline__ void net_update(const KModel& M, const LaneRates<S::k
   add_to_v(vh, vl, dv);
 }
 
-template <class S>
+template <class S, bool DELAY>
 __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   constexpr int NG = S::kNG;
   __shared__ int s_pre[kNetBlock];
@@ -261,18 +290,26 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   const int64_t my_r0 = A.row_ptr[ii];
   const int my_len = (int)(A.row_ptr[ii + 1] - my_r0);
   int done = 0;  // steps whose barrier completed
+  // ring slot of the current time (DELAY), advanced once per step
+  int now = DELAY ? (int)(A.t0 % A.R) : 0;
 
   for (int k = 0; k < A.nsteps; ++k) {
     const int64_t t = A.t0 + k;
     const float V = vh;
-    // arrivals scattered during the previous step of this launch
+    // arrivals due at this step (those due at the first step of a launch
+    // were folded into the state at the end of the previous launch, or the
+    // ring was cleared for a run that starts at t0 = 0)
     unsigned long long ae = 0ull, ai = 0ull;
     if (k > 0 && act) {
-      unsigned long long* pe = A.acc + (int64_t)((k - 1) & 1) * 2 * n;
+      unsigned long long* pe = DELAY ? A.acc + (int64_t)now * 2 * n
+                                     : A.acc + (int64_t)((k - 1) & 1) * 2 * n;
       ae = atomicExch(&pe[i], 0ull);
       ai = atomicExch(&pe[n + i], 0ull);
     }
-    net_update<S>(M, L, dtC, vh, vl, p, I, ge, gi, ae, ai);
+    const float Ik = A.bg ? background_current(A.seed, (uint32_t)ii, (uint64_t)t, A.bg_lam, A.bg_p0,
+                                               A.bg_kmax, A.mu, A.sigma)
+                          : I;
+    net_update<S>(M, L, dtC, vh, vl, p, Ik, ge, gi, ae, ai);
     const bool spk = act && (V < M.v_th) && (vh >= M.v_th);
     ge *= M.decay_e;
     gi *= M.decay_i;
@@ -301,20 +338,26 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
     }
     __syncthreads();
     const int cnt = s_cnt;
-    unsigned long long* acc_e = A.acc + (int64_t)(k & 1) * 2 * n;
-    unsigned long long* acc_i = acc_e + n;
     if (cnt > 0) {
       block_inclusive_scan(s_pre, cnt);
       const int total = s_pre[cnt - 1];
-      scatter_flat(A.col, A.w, scale40, s_r0, s_pre, cnt, total, acc_e, acc_i);
+      if constexpr (DELAY) {
+        scatter_flat<true>(A.col, A.w, scale40, s_r0, s_pre, cnt, total, A.acc, nullptr, A.delay,
+                           now, A.R, n);
+      } else {
+        unsigned long long* acc_e = A.acc + (int64_t)(k & 1) * 2 * n;
+        scatter_flat(A.col, A.w, scale40, s_r0, s_pre, cnt, total, acc_e, acc_e + n);
+      }
     }
 
     if (!grid_barrier(A.bar, gridDim.x, gen, A.spin_limit, A.flags, &s_ok)) break;
     done = k + 1;
+    if constexpr (DELAY) now = now + 1 == A.R ? 0 : now + 1;
   }
-  // the last step's arrivals
+  // the arrivals due at the step after the last one
   if (done > 0 && act) {
-    unsigned long long* pe = A.acc + (int64_t)((done - 1) & 1) * 2 * n;
+    unsigned long long* pe = DELAY ? A.acc + (int64_t)now * 2 * n
+                                   : A.acc + (int64_t)((done - 1) & 1) * 2 * n;
     ge += (float)atomicExch(&pe[i], 0ull) * kUnfix;
     gi += (float)atomicExch(&pe[n + i], 0ull) * kUnfix;
   }
@@ -327,6 +370,13 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   A.state[row_ge + i] = ge;
   A.state[row_gi + i] = gi;
   if (!__builtin_isfinite(vh + vl + ge + gi)) atomicMin(&A.flags[0], (int32_t)i);
+}
+
+// zero fill of the delay ring (a fill kernel rather than a memset, so that
+// a captured stream replays it correctly)
+__global__ void k_zero64(unsigned long long* p, int64_t count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
 }
 
 __global__ void k_net_reset(unsigned* bar) {
@@ -414,14 +464,14 @@ size_t list_off(int64_t n) { return acc_bytes(n); }
 size_t ctr_off(int64_t n) { return list_off(n) + (((size_t)n * 4 + 255) & ~(size_t)255); }
 size_t scratch_size(int64_t n) { return ctr_off(n) + 256; }
 
-template <class S>
+template <class S, bool DELAY>
 hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_net<S>, kNetBlock, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_net<S, DELAY>, kNetBlock, 0);
   if (e != hipSuccess) return e;
   const int64_t nb = (a.n + kNetBlock - 1) / kNetBlock;
   if (nb > (int64_t)ncu * per_cu) return hipErrorCooperativeLaunchTooLarge;
@@ -429,15 +479,31 @@ hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* args[] = {(void*)&m->km, (void*)&a};
-  return hipLaunchCooperativeKernel((const void*)k_net<S>, dim3((unsigned)nb), dim3(kNetBlock),
-                                    args, 0, s);
+  return hipLaunchCooperativeKernel((const void*)k_net<S, DELAY>, dim3((unsigned)nb),
+                                    dim3(kNetBlock), args, 0, s);
 }
 
 }  // namespace
 
+template <bool DELAY>
+static hipError_t launch_net_spec(hh_model* m, NetArgs& a, hipStream_t s) {
+  if (m->use_fixed && ClassicSpec::matches(m->km)) return launch_net<ClassicSpec, DELAY>(m, a, s);
+  switch (m->km.n_gates) {
+    case 1: return launch_net<GenericSpec<1>, DELAY>(m, a, s);
+    case 2: return launch_net<GenericSpec<2>, DELAY>(m, a, s);
+    case 3: return launch_net<GenericSpec<3>, DELAY>(m, a, s);
+    case 4: return launch_net<GenericSpec<4>, DELAY>(m, a, s);
+    case 5: return launch_net<GenericSpec<5>, DELAY>(m, a, s);
+    case 6: return launch_net<GenericSpec<6>, DELAY>(m, a, s);
+    default: return hipErrorNotSupported;
+  }
+}
+
 int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_steps,
                                const hh_input* in, const hh_outputs* out, void* stream) {
-  if (in->mode != HH_IN_NONE && in->mode != HH_IN_CONST) return HH_E_UNSUPPORTED;
+  if (in->mode != HH_IN_NONE && in->mode != HH_IN_CONST && in->mode != HH_IN_BACKGROUND)
+    return HH_E_UNSUPPORTED;
+  if (m->km.n_gates < 1 || m->km.n_gates > 6) return HH_E_UNSUPPORTED;
   if (out->v_rec || out->ckpt || out->level) return HH_E_UNSUPPORTED;
   if (n_steps == 0) return HH_OK;
   NetArgs a;
@@ -453,6 +519,15 @@ int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_
   a.w_ext = m->w_ext;
   a.ext_seed = m->ext_seed;
   a.i_const = (in->mode == HH_IN_CONST) ? in->i_const : nullptr;
+  if (in->mode == HH_IN_BACKGROUND) {
+    a.bg = 1;
+    a.mu = in->mu;
+    a.sigma = in->sigma;
+    a.seed = in->seed;
+    a.bg_lam = in->lam;
+    a.bg_p0 = (float)exp(-(double)in->lam);
+    a.bg_kmax = (int32_t)floor((double)in->lam + 12.0 * sqrt((double)in->lam)) + 12;
+  }
   a.t0 = t0;
   a.nsteps = n_steps;
   a.spikes = out->spikes;
@@ -464,20 +539,21 @@ int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_
   a.spin_limit = 1u << 24;
   hipError_t e;
   hipStream_t s = (hipStream_t)stream;
-  if (m->use_fixed && ClassicSpec::matches(m->km)) {
-    e = launch_net<ClassicSpec>(m, a, s);
-  } else {
-    switch (m->km.n_gates) {
-      case 1: e = launch_net<GenericSpec<1>>(m, a, s); break;
-      case 2: e = launch_net<GenericSpec<2>>(m, a, s); break;
-      case 3: e = launch_net<GenericSpec<3>>(m, a, s); break;
-      case 4: e = launch_net<GenericSpec<4>>(m, a, s); break;
-      case 5: e = launch_net<GenericSpec<5>>(m, a, s); break;
-      case 6: e = launch_net<GenericSpec<6>>(m, a, s); break;
-      default: return HH_E_UNSUPPORTED;
+  if (m->delay) {
+    a.acc = m->d_ring;
+    a.delay = m->delay;
+    a.R = m->max_delay + 1;
+    if (t0 == 0) {  // a run from the start has nothing in flight
+      const int64_t count = (int64_t)a.R * 2 * m->n;
+      hipLaunchKernelGGL(k_zero64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                         m->d_ring, count);
+      if ((e = hipGetLastError()) != hipSuccess) return HH_E_HIP;
     }
+    e = launch_net_spec<true>(m, a, s);
+  } else {
+    e = launch_net_spec<false>(m, a, s);
   }
-  if (e == hipErrorCooperativeLaunchTooLarge) return HH_E_UNSUPPORTED;
+  if (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorNotSupported) return HH_E_UNSUPPORTED;
   return e == hipSuccess ? HH_OK : HH_E_HIP;
 }
 
@@ -532,6 +608,11 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
     if (hipMemset(m->d_scratch, 0, bytes) != hipSuccess) return HH_E_HIP;
     m->scratch_bytes = bytes;
   }
+  // a delay table belongs to the connectivity it was set for
+  if (m->d_ring) (void)hipFree(m->d_ring);
+  m->d_ring = nullptr;
+  m->delay = nullptr;
+  m->max_delay = 0;
   m->row_ptr = row_ptr;
   m->col = col;
   m->w = w;
@@ -547,6 +628,43 @@ int32_t hh_set_external(hh_model* m, const uint8_t* ext_mask, uint32_t thresh, f
   m->ext_thresh = thresh;
   m->w_ext = w_ext;
   m->ext_seed = seed;
+  return HH_OK;
+}
+
+int32_t hh_set_delays(hh_model* m, const uint8_t* delay, int32_t max_delay) {
+  if (!m) return HH_E_INVALID;
+  if (!delay) {
+    if (m->d_ring) (void)hipFree(m->d_ring);
+    m->d_ring = nullptr;
+    m->delay = nullptr;
+    m->max_delay = 0;
+    return HH_OK;
+  }
+  if (!m->row_ptr) return HH_E_INVALID;
+  if (max_delay < 1 || max_delay > 255) return HH_E_SHAPE;
+  // every delay in [1, max_delay]: checked once here (the kernel also clamps)
+  if (m->nnz > 0) {
+    uint8_t* h = (uint8_t*)malloc((size_t)m->nnz);
+    if (!h) return HH_E_OOM;
+    if (hipMemcpy(h, delay, (size_t)m->nnz, hipMemcpyDeviceToHost) != hipSuccess) {
+      free(h);
+      return HH_E_HIP;
+    }
+    int bad = 0;
+    for (int64_t q = 0; q < m->nnz; ++q) bad |= (h[q] < 1 || h[q] > max_delay);
+    free(h);
+    if (bad) return HH_E_INVALID;
+  }
+  const size_t bytes = (size_t)(max_delay + 1) * 2 * (size_t)m->n * sizeof(unsigned long long);
+  if (m->d_ring) (void)hipFree(m->d_ring);
+  m->d_ring = nullptr;
+  if (hipMalloc((void**)&m->d_ring, bytes) != hipSuccess) {
+    m->d_ring = nullptr;
+    return HH_E_OOM;
+  }
+  if (hipMemset(m->d_ring, 0, bytes) != hipSuccess) return HH_E_HIP;
+  m->delay = delay;
+  m->max_delay = max_delay;
   return HH_OK;
 }
 

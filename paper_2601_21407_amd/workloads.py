@@ -198,6 +198,20 @@ NET_INH_SCALE = 4.0
 NET_W_EXT = 0.5
 
 
+def pathway_delays(csr, n_pop: int = 8, max_delay: int = 15, seed: int = 21):
+    """Per-synapse delays (steps, uint8 [nnz]) from a pathway table: the n
+    neurons form n_pop equal contiguous populations, and every synapse from
+    population a to population b carries the delay D[a][b], drawn once from
+    U{1..max_delay}.  A synthetic stand-in for per-pathway delays (the
+    published cortical tables are not available).  Returns (delays, D, pop)."""
+    row_ptr, col = np.asarray(csr[0]), np.asarray(csr[1])
+    n = len(row_ptr) - 1
+    pop = (np.arange(n) * n_pop) // max(n, 1)
+    D = np.random.default_rng([seed, 5]).integers(1, max_delay + 1, (n_pop, n_pop))
+    src = np.repeat(np.arange(n), np.diff(row_ptr))
+    return D[pop[src], pop[col]].astype(np.uint8), D, pop
+
+
 def net_model() -> dict:
     return with_synapses(classic_hh(dt=0.1, v_method="ee"))
 

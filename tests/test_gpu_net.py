@@ -201,3 +201,149 @@ def test_full_network_statistics_and_determinism():
     print("rates GPU %s oracle %s perturbed-oracle %s tol %s" % (rg, rr, rq, tol), flush=True)
     assert np.all(rr > 1.0)
     assert np.all(np.abs(rg - rr) <= tol)
+
+
+# ---------------------------------------------------------------------------
+# synaptic delays of several steps (a ring of arrivals in flight) and the
+# background input in the network kernel
+# ---------------------------------------------------------------------------
+def _net_model_gpu(m, csr, scale, *, delay=None, max_delay=1, ext=None):
+    need_gpu()
+    from paper_2601_21407_amd import hh
+    n = len(csr[0]) - 1
+    M = hh.Model(m, n)
+    bufs = [_dev(csr[0]), _dev(csr[1]), _dev(csr[2].astype(np.float32))]
+    M.attach_csr(bufs[0], bufs[1], bufs[2], scale)
+    if delay is not None:
+        d = _dev(delay)
+        bufs.append(d)
+        M.set_delays(d, max_delay)
+    if ext is not None:
+        em = _dev(ext[0])
+        bufs.append(em)
+        M.set_external(em, ext[1], ext[2], ext[3])
+    return M, bufs
+
+
+def _run_on(M, v0, T, *, state=None, t0=0, background=None, i_const=None):
+    import torch
+    st = state
+    if st is None:
+        st = M.new_state()
+        M.init_state(st, v0=_dev(v0.astype(np.float32)))
+    spikes = torch.zeros((max(T, 1), M.words), dtype=torch.int32, device="cuda")
+    ic = None if i_const is None else _dev(np.asarray(i_const, np.float32))
+    M.step_n(st, T, t0, spikes=spikes, background=background, i_const=ic)
+    status, bad = M.check()
+    assert status == 0, (status, bad)
+    return O.unpack_bits(spikes[:T].cpu().numpy().view(np.uint32), M.n), st
+
+
+def _horizon_kw(m, csr, scale, v0, T, kw):
+    ref = O.net_run(m, O.init_state(m, v0), csr, scale, T, **kw)
+    h = T
+    ulp = np.spacing(np.abs(v0.astype(np.float32))).astype(np.float64)
+    for pv0, ps in [(v0 + ulp, scale), (v0 - ulp, scale), (v0, scale * (1 + 1e-6)),
+                    (v0, scale * (1 - 1e-6))]:
+        r = O.net_run(m, O.init_state(m, pv0), csr, ps, T, **kw)
+        d = np.nonzero((r != ref).any(axis=1))[0]
+        if len(d):
+            h = min(h, int(d[0]))
+    return h, ref
+
+
+@pytest.mark.parametrize("drive", ["external", "background"])
+def test_network_pathway_delays_spike_exact_to_horizon(drive):
+    """1,500 neurons in 8 populations, 150 targets per source, a delay of 1
+    to 15 steps per pathway; spike-exact against the oracle up to the
+    horizon, and bit-identical on a rerun."""
+    print_case("network delays drive=%s" % drive)
+    m = W.net_model()
+    n, fan, T = 1500, 150, 2000
+    csr = W.net_csr(n=n, fan_out=fan, seed=5, inh_scale=4.0)
+    dl, _, _ = W.pathway_delays(csr, 8, 15, 5)
+    v0 = W.net_v0(n, 5).astype(np.float64)
+    kw = {"delay": dl, "max_delay": 15}
+    if drive == "external":
+        mask, thr = W.net_external(n=n, frac=0.05, seed=5)
+        ext = (mask, thr, 0.5, 5)
+        kw.update(ext_mask=mask, ext_thresh=thr, w_ext=0.5, seed=5)
+        bg = None
+    else:
+        ext = None
+        bg = (0.5, 3.0, 2.0, 3)
+        kw.update(background=bg[:3], in_seed=bg[3])
+    # weight scale 0.15: the oracle's raster stays predictable over the whole
+    # run under both drives (at 0.3 the external drive's diverges early)
+    M, bufs = _net_model_gpu(m, csr, 0.15, delay=dl, max_delay=15, ext=ext)
+    g, st = _run_on(M, v0, T, background=bg)
+    h, ref = _horizon_kw(m, csr, 0.15, v0, T, kw)
+    assert ref.sum() > 5 * n * T * 1e-4
+    upto = max(h - 1, 0)
+    bad = spike_mismatch(g[:upto], ref[:upto])
+    print("horizon %d of %d steps, spikes %d, mismatched neurons before horizon %d"
+          % (h, T, int(ref.sum()), len(bad)), flush=True)
+    assert h > 200 and len(bad) == 0
+    g2, st2 = _run_on(M, v0, T, background=bg)  # t0 = 0 again: nothing left in flight
+    assert np.array_equal(g2, g) and np.array_equal(st2.cpu().numpy(), st.cpu().numpy())
+    del bufs
+
+
+def test_network_delays_resume_carries_arrivals_in_flight():
+    """Split runs on one model equal the unsplit run: arrivals still in
+    flight at the end of a call are delivered by the next."""
+    m = W.net_model()
+    n, fan = 700, 50
+    csr = W.net_csr(n=n, fan_out=fan, seed=8, inh_scale=4.0)
+    dl, _, _ = W.pathway_delays(csr, 8, 12, 8)
+    mask, thr = W.net_external(n=n, frac=0.05, seed=8)
+    ext = (mask, thr, 0.5, 8)
+    v0 = W.net_v0(n, 8).astype(np.float64)
+    M, bufs = _net_model_gpu(m, csr, 0.3, delay=dl, max_delay=12, ext=ext)
+    full, stf = _run_on(M, v0, 600)
+    a, st = _run_on(M, v0, 250)
+    b, st = _run_on(M, v0, 7, state=st, t0=250)
+    c, st = _run_on(M, v0, 343, state=st, t0=257)
+    assert full.sum() > 0
+    assert np.array_equal(np.concatenate([a, b, c]), full)
+    assert np.array_equal(st.cpu().numpy(), stf.cpu().numpy())
+    del bufs
+
+
+def test_network_unit_delays_equal_one_step_kernel():
+    m = W.net_model()
+    n, fan = 900, 60
+    csr = W.net_csr(n=n, fan_out=fan, seed=9, inh_scale=4.0)
+    mask, thr = W.net_external(n=n, frac=0.05, seed=9)
+    ext = (mask, thr, 0.5, 9)
+    v0 = W.net_v0(n, 9).astype(np.float64)
+    M0, b0 = _net_model_gpu(m, csr, 0.3, ext=ext)
+    M1, b1 = _net_model_gpu(m, csr, 0.3, delay=np.ones(len(csr[1]), np.uint8), max_delay=4,
+                            ext=ext)
+    r0, s0 = _run_on(M0, v0, 800)
+    r1, s1 = _run_on(M1, v0, 800)
+    assert r0.sum() > 0 and np.array_equal(r0, r1)
+    assert np.array_equal(s0.cpu().numpy(), s1.cpu().numpy())
+    del b0, b1
+
+
+def test_network_delay_errors():
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    m = W.net_model()
+    n = 200
+    M = hh.Model(m, n)
+    d = _dev(np.ones(10, np.uint8))
+    with pytest.raises(hh.HHError) as e:
+        M.set_delays(d, 4)  # no connectivity attached
+    assert e.value.status == -1
+    csr = W.net_csr(n=n, fan_out=10, seed=2, inh_scale=4.0)
+    M, bufs = _net_model_gpu(m, csr, 0.3)
+    nnz = len(csr[1])
+    for arr, mx, status in ((np.full(nnz, 5, np.uint8), 4, -1), (np.zeros(nnz, np.uint8), 4, -1),
+                            (np.ones(nnz, np.uint8), 0, -2), (np.ones(nnz, np.uint8), 256, -2)):
+        with pytest.raises(hh.HHError) as e:
+            M.set_delays(_dev(arr), mx)
+        assert e.value.status == status, (mx, status)
+    M.set_delays(None, 0)
+    del torch, bufs
