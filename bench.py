@@ -396,10 +396,37 @@ def bench_network(T=10000):
         floor[name] = a.elapsed_time(b) / T * 1e3
     kern_us = e0.elapsed_time(e1) / T * 1e3
     floor["step_over_floor"] = kern_us / floor["barrier_plus_acc_us"]
+    # the same network with per-pathway delays (8 populations, 1 to 15
+    # steps) and background input in every neuron instead of the external
+    # events: the ring of arrivals in flight and the per-step draw
+    dl, _, _ = W.pathway_delays(csr, 8, 15, 3)
+    Md = hh.Model(m, n)
+    Md.attach_csr(rp, col, w, W.NET_W_SCALE)
+    dl_t = torch.tensor(dl, device="cuda")
+    Md.set_delays(dl_t, 15)
+    bg = (0.5, 3.0, 2.0, 7)
+    std = Md.new_state()
+    Md.init_state(std, v0=v0)
+    Md.step_n(std, 200, 0, spikes=spikes, background=bg)  # warm-up
+    Md.init_state(std, v0=v0)
+    _sync()
+    a.record()
+    Md.step_n(std, T, 0, spikes=spikes, background=bg)
+    b.record()
+    _sync()
+    status, bad = Md.check()
+    if status != 0:
+        raise RuntimeError("delayed network run failed: status %d (neuron %d)" % (status, bad))
+    n_spk_d = int(np.unpackbits(spikes.cpu().numpy().view(np.uint8)).sum())
+    delayed = {"max_delay_steps": 15, "populations": 8, "background": bg[:3],
+               "kernel_us_per_step": a.elapsed_time(b) / T * 1e3,
+               "mean_rate_hz": n_spk_d / n / (T * 1e-4)}
+    del Md, dl_t
     return {
         "n": n, "synapses": nnz, "T": T, "dt_ms": 0.1, "wall_s": wall,
         "kernel_ms": e0.elapsed_time(e1), "us_per_step": wall / T * 1e6,
         "kernel_us_per_step": kern_us, "barrier_floor": floor,
+        "pathway_delays_background": delayed,
         "updates_per_s": n * T / wall, "mean_rate_hz": n_spk / n / (T * 1e-4),
         "synaptic_events": n_spk * 2630,
         "scatter_full": {"events": nnz, "ms": sc_ms, "events_per_s": nnz / (sc_ms / 1e3),
