@@ -113,6 +113,20 @@ double ora_background(uint64_t seed, uint32_t id, int64_t t, double lam, double 
   return (double)N * mu + sqrt((double)N) * sigma * z;
 }
 
+/* Sinusoidal input (Results, HH encryption).  The phase advances by R / 2^32
+ * revolutions per step with R the binary32 product f * K rounded to an
+ * integer, so that R t wraps exactly in 32-bit arithmetic. */
+uint32_t ora_sine_rate(double f, double dt) {
+  const float K = (float)(dt * 4294967296.0 / 1000.0);
+  const float x = (float)f * K;
+  return (uint32_t)lrintf(x);
+}
+
+double ora_sine(double amp, uint32_t R, int64_t t) {
+  const uint32_t ph = R * (uint32_t)(uint64_t)t; /* mod 2^32 */
+  return amp * sin(6.283185307179586476925286766559 * ((double)ph / 4294967296.0));
+}
+
 uint32_t ora_event_word(uint64_t seed, uint32_t id, int64_t t) {
   uint32_t ctr[4] = {(uint32_t)(uint64_t)t, (uint32_t)((uint64_t)t >> 32), id, 1u};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -325,10 +339,33 @@ static void neuron_step(const ora_model* m, const double* coef, int64_t n, int64
   }
 }
 
+static int32_t run_impl(const ora_model* m, int64_t n, const double* coef, const double* cm,
+                        const uint32_t* ids, double* state, int64_t t0, int32_t T,
+                        int32_t in_mode, const double* i_const, double mu, double sigma,
+                        uint64_t seed, double lam, const double* freq, const double* i_dense,
+                        uint8_t* spk, double* vrec, double* level);
+
 int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double* cm,
                 const uint32_t* ids, double* state, int64_t t0, int32_t T, int32_t in_mode,
                 const double* i_const, double mu, double sigma, uint64_t seed, double lam,
                 const double* i_dense, uint8_t* spk, double* vrec, double* level) {
+  if (in_mode == ORA_IN_SINE) return -1; /* needs the frequencies: ora_run_sine */
+  return run_impl(m, n, coef, cm, ids, state, t0, T, in_mode, i_const, mu, sigma, seed, lam, NULL,
+                  i_dense, spk, vrec, level);
+}
+
+int32_t ora_run_sine(const ora_model* m, int64_t n, const double* coef, const double* cm,
+                     double* state, int64_t t0, int32_t T, const double* amp, const double* freq,
+                     uint8_t* spk, double* vrec, double* level) {
+  return run_impl(m, n, coef, cm, NULL, state, t0, T, ORA_IN_SINE, amp, 0.0, 0.0, 0, 0.0, freq,
+                  NULL, spk, vrec, level);
+}
+
+static int32_t run_impl(const ora_model* m, int64_t n, const double* coef, const double* cm,
+                        const uint32_t* ids, double* state, int64_t t0, int32_t T,
+                        int32_t in_mode, const double* i_const, double mu, double sigma,
+                        uint64_t seed, double lam, const double* freq, const double* i_dense,
+                        uint8_t* spk, double* vrec, double* level) {
   if (!model_ok(m) || n < 0 || T < 0) return -1;
   const int G = m->n_gates;
   for (int64_t i = 0; i < n; ++i) {
@@ -349,6 +386,7 @@ int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double*
       else if (in_mode == ORA_IN_NOISE) I = mu + sigma * ora_noise(seed, id, t);
       else if (in_mode == ORA_IN_DENSE) I = i_dense[(int64_t)k * n + i];
       else if (in_mode == ORA_IN_BACKGROUND) I = ora_background(seed, id, t, lam, mu, sigma, NULL);
+      else if (in_mode == ORA_IN_SINE) I = ora_sine(i_const[i], ora_sine_rate(freq[i], m->dt), t);
       double Vn;
       neuron_step(m, coef, n, i, C, V, p, ge, gi, I, &Vn, pn);
       if (spk) spk[(int64_t)k * n + i] = (uint8_t)(V < m->v_th && Vn >= m->v_th);

@@ -34,7 +34,8 @@ enum { ORA_AB = 0, ORA_INFTAU = 1 };
 /* Membrane update: explicit Euler of Eq. (2), or exponential Euler in V. */
 enum { ORA_FE = 0, ORA_EE = 1 };
 /* External current modes. */
-enum { ORA_IN_NONE = 0, ORA_IN_CONST = 1, ORA_IN_NOISE = 2, ORA_IN_DENSE = 3, ORA_IN_BACKGROUND = 4 };
+enum { ORA_IN_NONE = 0, ORA_IN_CONST = 1, ORA_IN_NOISE = 2, ORA_IN_DENSE = 3, ORA_IN_BACKGROUND = 4,
+       ORA_IN_SINE = 5 };
 
 typedef struct {
   int32_t n_gates, n_channels, v_method, has_syn;
@@ -69,6 +70,13 @@ uint32_t ora_event_word(uint64_t seed, uint32_t id, int64_t t);
  * count (nullable) receives N.  ora_background_count: N for Philox word w0
  * (inverse transform in binary32). */
 int32_t ora_background_count(uint32_t w0, double lam);
+/* Sinusoidal input (Results, HH encryption: sine-driven HH neurons):
+ * amplitude amp (uA/cm^2), frequency f (Hz), step dt (ms).  The frequency
+ * is quantized to R = round(f * K) revolutions / 2^32 per step, the product
+ * f * K taken in binary32 with K = binary32(dt 2^32 / 1000); the phase of
+ * absolute step t is (R t mod 2^32) / 2^32 revolutions, exactly. */
+uint32_t ora_sine_rate(double f, double dt);
+double ora_sine(double amp, uint32_t R, int64_t t);
 double ora_background(uint64_t seed, uint32_t id, int64_t t, double lam, double mu, double sigma,
                       int32_t* count);
 
@@ -97,6 +105,11 @@ int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double*
                 const uint32_t* ids, double* state, int64_t t0, int32_t T, int32_t in_mode,
                 const double* i_const, double mu, double sigma, uint64_t seed, double lam,
                 const double* i_dense, uint8_t* spk, double* vrec, double* level);
+/* ORA_IN_SINE for ora_run: i_const holds the amplitudes [n] and freq the
+ * frequencies [n] (Hz); ora_run_sine is ora_run with that extra array. */
+int32_t ora_run_sine(const ora_model* m, int64_t n, const double* coef, const double* cm,
+                     double* state, int64_t t0, int32_t T, const double* amp, const double* freq,
+                     uint8_t* spk, double* vrec, double* level);
 
 /* Multi-compartment neurons: n = N*K compartments, compartment c of neuron j
  * at j*K + c; parent[c] in [-1, c); g_axial [K] edge conductances per unit

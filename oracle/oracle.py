@@ -143,6 +143,12 @@ def lib():
         L.ora_n_state.restype = i32
         L.ora_run.argtypes = [P(OraModel), i64, vp, vp, vp, vp, i64, i32, i32, vp, d, d, u64, d,
                               vp, vp, vp, vp]
+        L.ora_run_sine.argtypes = [P(OraModel), i64, vp, vp, vp, i64, i32, vp, vp, vp, vp, vp]
+        L.ora_run_sine.restype = i32
+        L.ora_sine_rate.argtypes = [d, d]
+        L.ora_sine_rate.restype = u32
+        L.ora_sine.argtypes = [d, u32, i64]
+        L.ora_sine.restype = d
         L.ora_background_count.argtypes = [u32, d]
         L.ora_background_count.restype = i32
         L.ora_background.argtypes = [u64, u32, i64, d, d, d, P(i32)]
@@ -250,22 +256,39 @@ def background(seed: int, nid: int, t: int, lam: float, mu: float, sigma: float)
     return I, N.value
 
 
+def sine_rate(f: float, dt: float) -> int:
+    """R: the frequency f (Hz) as revolutions / 2^32 per step of dt (ms)."""
+    return int(lib().ora_sine_rate(float(f), float(dt)))
+
+
+def sine(amp: float, R: int, t: int) -> float:
+    return float(lib().ora_sine(float(amp), int(R), int(t)))
+
+
 def run(model: dict, state: np.ndarray, T: int, t0: int = 0, *, i_const=None, noise_mu=None,
         noise_sigma=None, seed: int = 0, i_dense=None, coef=None, cm=None, ids=None,
-        record_v: bool = False, record_spikes: bool = True, level: bool = False, background=None):
+        record_v: bool = False, record_spikes: bool = True, level: bool = False, background=None,
+        sine=None):
     """Advance independent neurons T steps in place.  Returns dict with
     'spikes' [T][n] uint8 (upward crossings), 'v' [T][n] (optional) and
     'level' [n] (count of steps with V >= v_th, optional)."""
     s = model_to_struct(model)
     n = state.shape[1]
     assert state.dtype == np.float64 and state.flags.c_contiguous
-    mode, i_const, i_dense, mu, sigma, lam = _input_mode(T, n, i_const, noise_mu, noise_sigma,
-                                                        i_dense, background)
     coef, cm = _f64(coef), _f64(cm)
-    ids = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
     spk = np.zeros((T, n), np.uint8) if record_spikes else None
     vr = np.zeros((T, n), np.float64) if record_v else None
     lv = np.zeros(n, np.float64) if level else None
+    if sine is not None:  # sine = (amplitudes [n], frequencies [n] in Hz)
+        amp, freq = _f64(sine[0]), _f64(sine[1])
+        rc = lib().ora_run_sine(ctypes.byref(s), n, _p(coef), _p(cm), _p(state), int(t0), int(T),
+                                _p(amp), _p(freq), _p(spk), _p(vr), _p(lv))
+        if rc != 0:
+            raise ValueError("oracle rejected the model (rc=%d)" % rc)
+        return {"spikes": spk, "v": vr, "level": lv}
+    mode, i_const, i_dense, mu, sigma, lam = _input_mode(T, n, i_const, noise_mu, noise_sigma,
+                                                        i_dense, background)
+    ids = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
     rc = lib().ora_run(ctypes.byref(s), n, _p(coef), _p(cm), _p(ids), _p(state), int(t0), int(T),
                        mode, _p(i_const), mu, sigma, int(seed), lam, _p(i_dense), _p(spk), _p(vr),
                        _p(lv))

@@ -967,3 +967,42 @@ def test_net_mixed_delays_brute_force(ora):
             bs[2 + G, i] = (gi[i] * di + pend.pop((k + 1, 1, i), 0.0))
     assert np.array_equal(spikes, ref)
     assert np.array_equal(bs, st)
+
+
+# ---------------------------------------------------------------------------
+# Sinusoidal input (HH encryption's sine-driven neurons): phase quantized to
+# R / 2^32 revolutions per step.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("f,dt", [(40.0, 0.025), (137.3, 0.01), (3.3, 0.1), (999.0, 0.025)])
+def test_sine_input_within_quantization_of_the_sinusoid(ora, f, dt):
+    """A sin(2 pi f t dt) to within the phase error the quantized rate can
+    accumulate: t (f dt 2^-23 + 2^-32) revolutions at step t."""
+    A = 3.5
+    R = ora.sine_rate(f, dt)
+    for t in (0, 1, 17, 4000, 123457):
+        got = ora.sine(A, R, t)
+        ideal = A * np.sin(2 * np.pi * f * t * dt * 1e-3)
+        bound = A * 2 * np.pi * t * (f * dt * 1e-3 * 2.0 ** -23 + 2.0 ** -32) + 1e-12
+        assert abs(got - ideal) <= bound, (t, got, ideal, bound)
+
+
+def test_sine_input_exact_period_and_one_step(ora):
+    # 1/256 revolution per step (R = 2^24): the input repeats bit for bit
+    # every 256 steps and reaches A exactly at the quarter period
+    dt = 0.1
+    f = 1000.0 / dt / 256.0
+    R = ora.sine_rate(f, dt)
+    assert R == 1 << 24
+    for t in range(0, 600, 7):
+        assert ora.sine(2.0, R, t) == ora.sine(2.0, R, t + 256)
+    assert ora.sine(2.0, R, 64) == 2.0 and ora.sine(2.0, R, 0) == 0.0
+    # a bare element integrates exactly the input of the step
+    m = {"gates": [], "channels": [], "C": 1.0, "dt": 1.0, "v_th": 1e9, "v_method": "fe",
+         "syn": None}
+    amp = np.linspace(0.5, 4.0, 9)
+    freq = np.linspace(1.0, 300.0, 9)
+    for t0 in (0, 3, 1001):
+        st = np.zeros((1, 9))
+        ora.run(m, st, 1, t0=t0, sine=(amp, freq), record_spikes=False)
+        want = [ora.sine(a, ora.sine_rate(fq, 1.0), t0) for a, fq in zip(amp, freq)]
+        assert np.array_equal(st[0], want)
