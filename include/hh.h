@@ -68,7 +68,8 @@ enum { HH_GATE_ALPHA_BETA = 0, HH_GATE_INF_TAU = 1 };
 /* Membrane update: explicit Euler (Eq. (2)) or exponential Euler in V. */
 enum { HH_V_FE = 0, HH_V_EE = 1 };
 /* External current. */
-enum { HH_IN_NONE = 0, HH_IN_CONST = 1, HH_IN_NOISE = 2, HH_IN_DENSE = 3, HH_IN_BACKGROUND = 4 };
+enum { HH_IN_NONE = 0, HH_IN_CONST = 1, HH_IN_NOISE = 2, HH_IN_DENSE = 3, HH_IN_BACKGROUND = 4,
+       HH_IN_SINE = 5 };
 
 typedef struct {
   int32_t form;
@@ -109,7 +110,14 @@ typedef struct {
   uint64_t seed;         /* HH_IN_NOISE: Philox4x32-10 key */
   const float* i_dense;  /* HH_IN_DENSE: [n_steps][n], row t is step t0 + t */
   float lam;             /* HH_IN_BACKGROUND: expected events per step, [0, 80] */
+  const float* freq;     /* HH_IN_SINE: [n] frequencies in Hz, 0 <= f <= 1000 / dt;
+                            i_const then holds the [n] amplitudes */
 } hh_input;
+/* HH_IN_SINE (Results, HH encryption: sine-driven neurons): I = A sin(2 pi phi)
+ * with phi the phase in revolutions.  The frequency is quantized to
+ * R = round(f K) / 2^32 revolutions per step, f K taken in binary32 with
+ * K = binary32(dt 2^32 / 1000), and the phase at absolute step t is exactly
+ * (R t mod 2^32) / 2^32, so long runs accumulate no phase error. */
 /* HH_IN_BACKGROUND (Methods, cortical network: the background input drawn
  * directly from its distribution): per element and step, N ~ Poisson(lam)
  * background events of independent Gaussian amplitude (mu, sigma), so

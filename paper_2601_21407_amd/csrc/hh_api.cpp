@@ -284,11 +284,13 @@ int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const 
                   const hh_outputs* out, void* stream) {
   if (!m || !state) return HH_E_INVALID;
   if (n_steps < 0 || t0 < 0) return HH_E_SHAPE;
-  hh_input none = {HH_IN_NONE, nullptr, 0.f, 0.f, 0, nullptr, 0.f};
+  hh_input none = {HH_IN_NONE, nullptr, 0.f, 0.f, 0, nullptr, 0.f, nullptr};
   hh_outputs nout = {nullptr, nullptr, nullptr, 1, nullptr};
   if (!in) in = &none;
   if (!out) out = &nout;
-  if (in->mode < HH_IN_NONE || in->mode > HH_IN_BACKGROUND) return HH_E_INVALID;
+  if (in->mode < HH_IN_NONE || in->mode > HH_IN_SINE) return HH_E_INVALID;
+  if (in->mode == HH_IN_SINE && (!in->i_const || !in->freq)) return HH_E_INVALID;
+  if (in->mode == HH_IN_SINE && (m->row_ptr || m->d_cable)) return HH_E_UNSUPPORTED;
   if (in->mode == HH_IN_BACKGROUND && !(in->lam >= 0.0f && in->lam <= 80.0f)) return HH_E_INVALID;
   if (in->mode == HH_IN_CONST && !in->i_const) return HH_E_INVALID;
   if (in->mode == HH_IN_DENSE && !in->i_dense) return HH_E_INVALID;
@@ -314,6 +316,10 @@ int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const 
     a.bg_lam = in->lam;
     a.bg_p0 = (float)exp(-(double)in->lam);
     a.bg_kmax = (int32_t)floor((double)in->lam + 12.0 * sqrt((double)in->lam)) + 12;
+  }
+  if (in->mode == HH_IN_SINE) {
+    a.freq = in->freq;
+    a.sine_K = (float)((double)m->km.dt * 4294967296.0 / 1000.0);
   }
   a.words = (m->n + 31) / 32;
   a.ckpt = out->ckpt;

@@ -20,7 +20,7 @@ constexpr float kLn2 = 0.6931471805599453f;
 enum { FORM_EXP = 0, FORM_SIGMOID = 1, FORM_LINOID = 2, FORM_BELL = 3 };
 enum { KIND_AB = 0, KIND_INFTAU = 1 };
 enum { VFE = 0, VEE = 1 };
-enum { IN_NONE = 0, IN_CONST = 1, IN_NOISE = 2, IN_DENSE = 3, IN_BACKGROUND = 4 };
+enum { IN_NONE = 0, IN_CONST = 1, IN_NOISE = 2, IN_DENSE = 3, IN_BACKGROUND = 4, IN_SINE = 5 };
 
 // One rate function in a form ready for the exp2 unit.  With x = V*s + o =
 // log2(e) (V - B) / K:
@@ -472,6 +472,17 @@ __device__ __forceinline__ float background_current(uint64_t seed, uint32_t id, 
   const float z = __builtin_amdgcn_sqrtf(-2.0f * kLn2 * __builtin_amdgcn_logf(ua)) *
                   __builtin_amdgcn_cosf(ub);
   return fmaf(fk, mu, __builtin_amdgcn_sqrtf(fk) * sigma * z);
+}
+
+// Sinusoidal input (Results, HH encryption): R = round(f K) revolutions / 2^32
+// per step (f K in binary32; clamped below 2^32), the phase of step t the
+// wrapped product R t, exact; v_sin_f32 takes the phase in revolutions.
+__device__ __forceinline__ uint32_t sine_rate(float f, float K) {
+  return (uint32_t)rintf(fminf(fmaxf(f * K, 0.0f), 4294967040.0f));
+}
+__device__ __forceinline__ float sine_input(float amp, uint32_t R, uint64_t t) {
+  const uint32_t ph = R * (uint32_t)t;
+  return amp * __builtin_amdgcn_sinf((float)ph * 0x1p-32f);
 }
 
 __device__ __forceinline__ uint32_t event_word(uint64_t seed, uint32_t id, uint64_t t) {

@@ -18,6 +18,8 @@ struct StepArgs {
   uint64_t seed;
   float bg_lam, bg_p0;   // background input: events per step, e^-lam
   int32_t bg_kmax;       // and the count's cap
+  const float* freq;     // sinusoidal input: [n] Hz (amplitudes in i_const)
+  float sine_K;          // dt 2^32 / 1000 in binary32
   const float* i_dense;  // row 0 = step k_base of the call
   uint32_t* spikes;      // row 0 = step k_base of the call
   int64_t words;

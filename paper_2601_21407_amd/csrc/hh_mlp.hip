@@ -794,7 +794,8 @@ extern "C" int32_t hh_surrogate_step_n(hh_model* m, const void* mlp_packed, floa
   if (!m || !mlp_packed || !state || !flags || !in) return HH_E_INVALID;
   if (k < 1 || k > KMAX || n_steps < 0 || n_steps % k != 0 || t0 < 0 || check_every < 0)
     return HH_E_SHAPE;
-  if (in->mode == HH_IN_CONST || in->mode == HH_IN_BACKGROUND) return HH_E_UNSUPPORTED;
+  if (in->mode == HH_IN_CONST || in->mode == HH_IN_BACKGROUND || in->mode == HH_IN_SINE)
+    return HH_E_UNSUPPORTED;
   if (in->mode == HH_IN_DENSE && !in->i_dense) return HH_E_INVALID;
   if (m->km.has_syn || m->coef || m->cm || m->B != 1 || m->d_tab || m->d_cable)
     return HH_E_UNSUPPORTED;

@@ -238,6 +238,9 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
       }
     }
   } else {
+    // sinusoidal input: amplitude and quantized rate, once per launch
+    const float sine_amp = A.in_mode == IN_SINE ? A.i_const[ii] : 0.0f;
+    const uint32_t sine_R = A.in_mode == IN_SINE ? sine_rate(A.freq[ii], A.sine_K) : 0u;
     for (int k = 0; k < A.nsteps; ++k) {
       const int64_t t = A.t0 + k;
       const int kk = A.k_base + k;
@@ -264,6 +267,8 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
       } else if (A.in_mode == IN_BACKGROUND) {
         I = background_current(A.seed, nid, (uint64_t)t, A.bg_lam, A.bg_p0, A.bg_kmax, A.mu,
                                A.sigma);
+      } else if (A.in_mode == IN_SINE) {
+        I = sine_input(sine_amp, sine_R, (uint64_t)t);
       }
       const float V = vh;
       if constexpr (TAB != TAB_NONE)

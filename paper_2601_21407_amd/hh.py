@@ -20,7 +20,7 @@ MAX_GATES, MAX_CH, MAX_CH_GATES = 8, 8, 4
 FORMS = {"exp": 0, "sigmoid": 1, "linoid": 2, "bell": 3}
 KINDS = {"ab": 0, "inftau": 1}
 VMETH = {"fe": 0, "ee": 1}
-IN_NONE, IN_CONST, IN_NOISE, IN_DENSE, IN_BACKGROUND = 0, 1, 2, 3, 4
+IN_NONE, IN_CONST, IN_NOISE, IN_DENSE, IN_BACKGROUND, IN_SINE = 0, 1, 2, 3, 4, 5
 STATUS = {0: "HH_OK", -1: "HH_E_INVALID", -2: "HH_E_SHAPE", -3: "HH_E_HIP",
           -4: "HH_E_NONFINITE", -5: "HH_E_UNSUPPORTED", -6: "HH_E_OOM", -7: "HH_E_TIMEOUT"}
 
@@ -57,7 +57,7 @@ class ModelDesc(ctypes.Structure):
 class Input(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("i_const", ctypes.c_void_p), ("mu", ctypes.c_float),
                 ("sigma", ctypes.c_float), ("seed", ctypes.c_uint64), ("i_dense", ctypes.c_void_p),
-                ("lam", ctypes.c_float)]
+                ("lam", ctypes.c_float), ("freq", ctypes.c_void_p)]
 
 
 class Outputs(ctypes.Structure):
@@ -236,11 +236,14 @@ class Model:
 
     def step_n(self, state, n_steps: int, t0: int = 0, *, i_const=None, noise=None, i_dense=None,
                spikes=None, v_rec=None, ckpt=None, ckpt_every: int = 1, level=None,
-               background=None):
-        """noise = (mu, sigma, seed); background = (lam, mu, sigma, seed)."""
+               background=None, sine=None):
+        """noise = (mu, sigma, seed); background = (lam, mu, sigma, seed);
+        sine = (amplitudes [n], frequencies [n] in Hz), device tensors."""
         inp = Input()
         if i_dense is not None:
             inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
+        elif sine is not None:
+            inp.mode, inp.i_const, inp.freq = IN_SINE, _ptr(sine[0]), _ptr(sine[1])
         elif background is not None:
             inp.mode = IN_BACKGROUND
             inp.lam, inp.mu, inp.sigma = (float(x) for x in background[:3])

@@ -198,6 +198,26 @@ NET_INH_SCALE = 4.0
 NET_W_EXT = 0.5
 
 
+def timescale_coef(model: dict, taus) -> np.ndarray:
+    """Per-neuron rate coefficients [G*8][len(taus)] (the layout of
+    coef_table) for neurons whose gate kinetics run tau times slower (the
+    HH filter bank's time constant, Results, HH encryption): both rates of
+    an (alpha, beta) gate and the 1/tau rate of a (p_inf, 1/tau) gate are
+    divided by tau.  The amplitude is the coefficient A of the exp,
+    sigmoid and linoid forms and 1/A of the bell form.  float32 values, the
+    device's precision, handed to both sides."""
+    base = coef_table(model).astype(np.float64)
+    out = np.repeat(base[:, None], len(taus), axis=1)
+    for g, gate in enumerate(model["gates"]):
+        for r, rate in enumerate(gate["rates"]):
+            if gate["kind"] != "ab" and r == 0:
+                continue  # p_inf keeps its value
+            row = g * 8 + r * 4
+            for j, tau in enumerate(taus):
+                out[row, j] = base[row] * tau if rate[0] == "bell" else base[row] / tau
+    return out.astype(np.float32)
+
+
 def pathway_delays(csr, n_pop: int = 8, max_delay: int = 15, seed: int = 21):
     """Per-synapse delays (steps, uint8 [nnz]) from a pathway table: the n
     neurons form n_pop equal contiguous populations, and every synapse from

@@ -44,7 +44,9 @@ PROBE = 1e-6
 def _subset_kw(kw, idx, n):
     out = {}
     for k, v in kw.items():
-        if isinstance(v, np.ndarray) and v.ndim == 1 and v.shape[0] == n:
+        if k == "sine" and v is not None:  # (amplitudes [n], frequencies [n])
+            out[k] = (np.asarray(v[0])[idx], np.asarray(v[1])[idx])
+        elif isinstance(v, np.ndarray) and v.ndim == 1 and v.shape[0] == n:
             out[k] = v[idx]
         elif k in ("coef", "i_dense") and v is not None:
             out[k] = v[:, idx]
@@ -73,6 +75,9 @@ def input_probes(kw, f):
     if kw.get("background") is not None:
         lam, mu, sigma = kw["background"]
         out.append(dict(kw, background=(lam, mu * f, sigma * f)))
+    if kw.get("sine") is not None:
+        amp, freq = kw["sine"]
+        out.append(dict(kw, sine=(np.asarray(amp) * f, freq)))
     return out
 
 

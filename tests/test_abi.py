@@ -37,7 +37,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(hh.Rate) == 20
     assert ctypes.sizeof(hh.Gate) == 44
     assert ctypes.sizeof(hh.Channel) == 44
-    assert ctypes.sizeof(hh.Input) == 48
+    assert ctypes.sizeof(hh.Input) == 56
     assert ctypes.sizeof(hh.Outputs) == 40
 
 

@@ -121,3 +121,45 @@ def test_pack_bits_cols_layout():
             assert ((int(u[m // 32, k]) >> (m % 32)) & 1) == int(A[m, k])
     assert (int(u[2, 0]) >> 6) == 0
     assert W.pack_bits_cols(np.zeros((0, 5))).shape == (0, 5)
+
+
+def test_encryption_segments_and_cbc_round_trip():
+    from paper_2601_21407_amd import encryption as E
+    rng = np.random.default_rng(3)
+    data = rng.integers(0, 256, 777, dtype=np.uint8).tobytes()
+    for nb in (1, 2, 4, 8):
+        seg = E.to_segments(data, nb)
+        assert seg.max() < (1 << nb) and E.from_segments(seg, nb) == data
+        B = rng.permutation(1 << nb)
+        c = E.encrypt(data, B, nb, iv=1)
+        assert c.max() < (1 << nb) and len(c) == len(seg)
+        # decryption sees B[c_i]: the bank's code of the key pair c_i selects
+        assert E.decrypt_with_codes(c, B[c], nb, iv=1) == data
+        if nb > 1:
+            wrong = np.roll(B, 1)
+            assert E.decrypt_with_codes(c, wrong[c], nb, iv=1) != data
+    # chaining: equal plaintext segments give different ciphertext segments
+    c = E.encrypt(bytes(64), np.array([2, 0, 3, 1]), 2, iv=1)
+    assert len(set(c[:8].tolist())) > 1
+
+
+def test_timescale_coefficients():
+    from paper_2601_21407_amd import workloads as W
+    m = W.classic_hh()
+    base = W.coef_table(m)
+    c = W.timescale_coef(m, [1.0, 2.0, 0.5])
+    assert c.dtype == np.float32
+    assert np.array_equal(c[:, 0], base.astype(np.float32))
+    for row in range(0, len(base), 4):  # every A of the (alpha, beta) gates
+        assert c[row, 1] == np.float32(base[row] / 2.0) and c[row, 2] == np.float32(base[row] / 0.5)
+    for row in range(len(base)):
+        if row % 4:
+            assert c[row, 1] == np.float32(base[row])  # B, K, c unchanged
+    mc = W.custom_channels()
+    cc = W.timescale_coef(mc, [3.0])
+    kinds = [g["kind"] for g in mc["gates"]]
+    g = kinds.index("inftau")
+    assert cc[g * 8, 0] == np.float32(W.coef_table(mc)[g * 8])  # p_inf untouched
+    form = mc["gates"][g]["rates"][1][0]
+    want = W.coef_table(mc)[g * 8 + 4] * (3.0 if form == "bell" else 1 / 3.0)
+    assert cc[g * 8 + 4, 0] == np.float32(want)
