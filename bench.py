@@ -312,6 +312,38 @@ def bench_cable(N=65536, T=4000, fusion=32):
                          "slots_per_update": slots}}
 
 
+# ---------------------------------------------------------------------------
+# HH encryption: decryption of a 64 KB synthetic image by the filter bank
+# ---------------------------------------------------------------------------
+def bench_encryption(nbytes=65536, T=8000, window=4000):
+    """2-bit bank (tau 0.5 and 4) of classic HH neurons: the key is drawn on a
+    24 x 16 (f, A) grid, nbytes of synthetic data are encrypted on the host
+    (CBC over 2-bit segments), and decryption simulates the bank on every
+    segment's key pair: 4 nbytes segments x 2 neurons x T steps of 0.025 ms
+    with sinusoidal input.  Reported: the simulation's kernel time, bytes/s
+    and neuron-updates/s, and that the plaintext came back."""
+    from paper_2601_21407_amd import encryption as E
+    from paper_2601_21407_amd import workloads as W
+    m = W.classic_hh(dt=0.025)
+    taus = [0.5, 4.0]
+    rng = np.random.default_rng(7)
+    kf, kA, B = E.make_key(m, taus, np.geomspace(4.0, 400.0, 24), np.linspace(1.0, 16.0, 16), rng,
+                           T, window)
+    data = rng.integers(0, 256, nbytes, dtype=np.uint8).tobytes()
+    c = E.encrypt(data, B, 2, iv=1)
+    E.decrypt(c[:4096], kf, kA, m, taus, 2, 1, T, window)  # warm-up
+    tm = {}
+    out = E.decrypt(c, kf, kA, m, taus, 2, 1, T, window, timing=tm)
+    neurons = len(c) * len(taus)
+    ms = tm["ms"]
+    slots = slots_per_update(m, noise=False) + 5.0  # + sine: phase, scale, v_sin, amplitude
+    return {"bytes": nbytes, "segments": int(len(c)), "neurons": neurons, "T": T,
+            "kernel_ms": ms, "bytes_per_s": nbytes / (ms / 1e3),
+            "neuron_updates_per_s": neurons * T / (ms / 1e3),
+            "alu_frac": slots * neurons * T / (ms / 1e3) / PEAK_LANE_OPS,
+            "slots_per_update": slots, "round_trip_ok": out == data}
+
+
 def cpu_baseline_headline(n_sample=8192):
     """The FP64 oracle, single-threaded, on the first n_sample neurons of the
     headline workload for all 4,000 steps."""
@@ -810,7 +842,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--parts", default="layer,net,surrogate,table,cable,probe")
+    ap.add_argument("--parts", default="layer,net,surrogate,table,cable,encryption,probe")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--counters", action="store_true",
                     help="run the copy + one headline launch for rocprofv3 counter passes")
@@ -849,6 +881,9 @@ def main():
     if "cable" in parts:
         extra["cable"] = bench_cable()
         print("[bench] cable done", file=sys.stderr, flush=True)
+    if "encryption" in parts:
+        extra["encryption"] = bench_encryption()
+        print("[bench] encryption done", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline_headline()
 
     line = {

@@ -20,25 +20,34 @@ from . import hh
 from . import workloads as W
 
 
-def bank_levels(model: dict, taus, freqs, amps, T: int, window: int, dev: str = "cuda"):
+def bank_levels(model: dict, taus, freqs, amps, T: int, window: int, dev: str = "cuda",
+                timing: dict | None = None):
     """Steps at or above threshold within the last `window` of T steps, for
     every (input, bank neuron): [P][n_taus].  Neuron p * n_taus + k gets
-    input (freqs[p], amps[p]) and time constant taus[k]."""
+    input (freqs[p], amps[p]) and time constant taus[k]: the bank is the
+    model's per-neuron dimension (N = n_taus) and the inputs its batch
+    (B = P), so the time constants' coefficients are stored once.  timing:
+    filled with the simulation's kernel time in ms."""
     nb = len(taus)
     P = len(freqs)
-    coef = np.tile(W.timescale_coef(model, taus), (1, P))
-    M = hh.Model(model, P * nb, coef=torch.tensor(coef, device=dev))
+    coef = W.timescale_coef(model, taus)
+    M = hh.Model(model, nb, P, coef=torch.tensor(coef, device=dev))
     amp = torch.tensor(np.repeat(np.asarray(amps, np.float32), nb), device=dev)
     fr = torch.tensor(np.repeat(np.asarray(freqs, np.float32), nb), device=dev)
     st = M.new_state()
     M.init_state(st, v0_scalar=-65.0)
+    lvl = torch.zeros(P * nb, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     if T > window:
         M.step_n(st, T - window, 0, sine=(amp, fr))
-    lvl = torch.zeros(P * nb, device=dev)
     M.step_n(st, window, T - window, sine=(amp, fr), level=lvl)
+    e1.record()
     status, bad = M.check()
     if status != 0:
         raise RuntimeError("filter bank simulation failed (%d at %d)" % (status, bad))
+    if timing is not None:
+        timing["ms"] = e0.elapsed_time(e1)
     return lvl.cpu().numpy().reshape(P, nb)
 
 
@@ -87,7 +96,10 @@ def from_segments(seg: np.ndarray, nb: int) -> bytes:
 
 
 def encrypt(data: bytes, B, nb: int, iv: int) -> np.ndarray:
-    """CBC over n-bit segments with the table A = B^-1."""
+    """CBC over n-bit segments with the table A = B^-1; iv in [0, 2^n)."""
+    if not 0 <= int(iv) < (1 << nb) or len(B) != (1 << nb):
+        raise ValueError("iv and the table must be n-bit: iv in [0, %d), %d entries"
+                         % (1 << nb, 1 << nb))
     A = np.argsort(np.asarray(B))
     p = to_segments(data, nb)
     c = np.empty_like(p)
@@ -101,16 +113,18 @@ def encrypt(data: bytes, B, nb: int, iv: int) -> np.ndarray:
 def decrypt_with_codes(cipher, codes, nb: int, iv: int) -> bytes:
     """p_i = code_i xor c_{i-1}, where code_i is the bank's response to the
     key pair c_i selects."""
+    if not 0 <= int(iv) < (1 << nb):
+        raise ValueError("iv must be in [0, %d)" % (1 << nb))
     c = np.asarray(cipher, np.int64)
     prev = np.concatenate([[int(iv)], c[:-1]])
     return from_segments(np.asarray(codes, np.int64) ^ prev, nb)
 
 
 def decrypt(cipher, key_f, key_A, model: dict, taus, nb: int, iv: int, T: int, window: int,
-            dev: str = "cuda") -> bytes:
+            dev: str = "cuda", timing: dict | None = None) -> bytes:
     """Decryption by simulation: the filter bank runs on the key pair of
     every ciphertext segment (one population of len(cipher) x n neurons)."""
     c = np.asarray(cipher, np.int64)
     codes = codes_from_levels(bank_levels(model, taus, np.asarray(key_f)[c], np.asarray(key_A)[c],
-                                          T, window, dev))
+                                          T, window, dev, timing))
     return decrypt_with_codes(c, codes, nb, iv)

@@ -138,6 +138,10 @@ def test_encryption_segments_and_cbc_round_trip():
         if nb > 1:
             wrong = np.roll(B, 1)
             assert E.decrypt_with_codes(c, wrong[c], nb, iv=1) != data
+    with pytest.raises(ValueError):
+        E.encrypt(data, np.arange(4), 2, iv=4)  # the iv is one n-bit segment
+    with pytest.raises(ValueError):
+        E.encrypt(data, np.arange(8), 2, iv=0)  # the table has 2^n entries
     # chaining: equal plaintext segments give different ciphertext segments
     c = E.encrypt(bytes(64), np.array([2, 0, 3, 1]), 2, iv=1)
     assert len(set(c[:8].tolist())) > 1
