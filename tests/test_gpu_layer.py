@@ -376,3 +376,37 @@ def test_adam_against_oracle():
         pr, m, v = O.adam_step(pr, g.astype(np.float64), m, v, step, 1e-2)
     assert np.allclose(tp.cpu().numpy(), pr, rtol=1e-5, atol=1e-6)
     assert np.array_equal(p16.float().cpu().numpy(), W.bf16_round(tp.cpu().numpy()))
+
+
+def test_autograd_function_routes_the_adjoint():
+    """HHFunction: r from the level output, and torch autograd delivers the
+    adjoint's dI, dx0 and dC_m, equal to the oracle's BPTT."""
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd.autograd import HHFunction
+    print_case("autograd function 2 x 128 x 120 ckpt 40")
+    m, I, cm, v0, rng = _bwd_case(n=256, T=120, seed=9, B=2)
+    T, n = I.shape
+    cm_t = torch.tensor(cm, device="cuda", requires_grad=True)
+    M = hh.Model(m, n // 2, 2, cm=cm_t.detach())
+    x0 = M.new_state()
+    M.init_state(x0, v0=torch.tensor(v0, device="cuda"))
+    It = torch.tensor(I, device="cuda", requires_grad=True)
+    x0r = x0.clone().requires_grad_(True)
+    wvec = torch.tensor(rng.standard_normal(n).astype(np.float32), device="cuda")
+    r = HHFunction.apply(It, x0r, cm_t, M, 40, 0.2)
+    (r * wvec).sum().backward()
+    # the same calls made directly
+    dI, dC, dx0, lv, _ = _gpu_bwd(m, I, cm, v0, 40, dlevel=wvec.cpu().numpy(), B=2)
+    assert np.array_equal(r.detach().cpu().numpy(), (lv / T).astype(np.float32))
+    assert np.array_equal(It.grad.cpu().numpy(), dI)
+    assert np.array_equal(x0r.grad.cpu().numpy(), dx0)
+    assert np.array_equal(cm_t.grad.cpu().numpy(), dC)
+    # and against the oracle
+    st0 = O.init_state(m, v0.astype(np.float64))
+    ro, oI, oC, _ = O.bptt(m, st0, I.astype(np.float64), cm=np.tile(cm.astype(np.float64), 2),
+                           dL_dr=wvec.cpu().numpy().astype(np.float64), smooth=False)
+    same = np.abs(lv - ro * T) == 0  # neurons whose level counts agree
+    assert same.mean() > 0.97
+    rel = np.linalg.norm((dI - oI)[:, same]) / max(np.linalg.norm(oI[:, same]), 1e-12)
+    assert rel < 1e-3, rel
