@@ -480,8 +480,9 @@ __device__ __forceinline__ float background_current(uint64_t seed, uint32_t id, 
 __device__ __forceinline__ uint32_t sine_rate(float f, float K) {
   return (uint32_t)rintf(fminf(fmaxf(f * K, 0.0f), 4294967040.0f));
 }
-__device__ __forceinline__ float sine_input(float amp, uint32_t R, uint64_t t) {
-  const uint32_t ph = R * (uint32_t)t;
+// the input at phase ph (revolutions / 2^32): a caller that starts at
+// ph = R t0 and adds R per step (wrapping) has ph = R t mod 2^32 exactly
+__device__ __forceinline__ float sine_input(float amp, uint32_t ph) {
   return amp * __builtin_amdgcn_sinf((float)ph * 0x1p-32f);
 }
 

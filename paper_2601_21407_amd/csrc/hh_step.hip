@@ -241,6 +241,7 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
     // sinusoidal input: amplitude and quantized rate, once per launch
     const float sine_amp = A.in_mode == IN_SINE ? A.i_const[ii] : 0.0f;
     const uint32_t sine_R = A.in_mode == IN_SINE ? sine_rate(A.freq[ii], A.sine_K) : 0u;
+    uint32_t sine_ph = sine_R * (uint32_t)A.t0;  // R t mod 2^32, advanced by R per step
     for (int k = 0; k < A.nsteps; ++k) {
       const int64_t t = A.t0 + k;
       const int kk = A.k_base + k;
@@ -268,13 +269,14 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
         I = background_current(A.seed, nid, (uint64_t)t, A.bg_lam, A.bg_p0, A.bg_kmax, A.mu,
                                A.sigma);
       } else if (A.in_mode == IN_SINE) {
-        I = sine_input(sine_amp, sine_R, (uint64_t)t);
+        I = sine_input(sine_amp, sine_ph);
+        sine_ph += sine_R;
       }
       const float V = vh;
       if constexpr (TAB != TAB_NONE)
-        neuron_step<S>(M, LT, dtC, vh, vl, p, I, ge, gi);
+        neuron_step<S, SYN>(M, LT, dtC, vh, vl, p, I, ge, gi);
       else
-        neuron_step<S>(M, L, dtC, vh, vl, p, I, ge, gi);
+        neuron_step<S, SYN>(M, L, dtC, vh, vl, p, I, ge, gi);
       const float Vn = vh;
       const bool spk = act && (V < M.v_th) && (Vn >= M.v_th);
       if (A.spikes) {
@@ -287,8 +289,10 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
       }
       if (A.v_rec && act) A.v_rec[(int64_t)k * n + i] = Vn;
       lvl += (Vn >= M.v_th);
-      ge *= M.decay_e;
-      gi *= M.decay_i;
+      if constexpr (SYN) {
+        ge *= M.decay_e;
+        gi *= M.decay_i;
+      }
     }
   }
 
@@ -361,7 +365,8 @@ static hipError_t step_tab(const hh_model* m, const StepArgs& a, hipStream_t s, 
     if (syn) hipLaunchKernelGGL((k_step<S, false, LOOP_NOISE, true, TAB>), grid, block, lds, s, m->km, a);
     else hipLaunchKernelGGL((k_step<S, false, LOOP_NOISE, false, TAB>), grid, block, lds, s, m->km, a);
   } else {
-    hipLaunchKernelGGL((k_step<S, false, LOOP_GEN, true, TAB>), grid, block, lds, s, m->km, a);
+    if (syn) hipLaunchKernelGGL((k_step<S, false, LOOP_GEN, true, TAB>), grid, block, lds, s, m->km, a);
+    else hipLaunchKernelGGL((k_step<S, false, LOOP_GEN, false, TAB>), grid, block, lds, s, m->km, a);
   }
   return hipGetLastError();
 }
@@ -391,6 +396,16 @@ static hipError_t step_spec(const hh_model* m, const StepArgs& a, hipStream_t s)
       if (a.in_mode == IN_DENSE) HH_LAUNCH(LOOP_DENSE);
       else HH_LAUNCH(LOOP_NOISE);
 #undef HH_LAUNCH
+      return hipGetLastError();
+    }
+  }
+  // general loop: the synapse-free variant for the compiled channel sets
+  // without synapses (bit-identical, fewer operations), the synaptic one
+  // otherwise
+  if constexpr (S::kFixed) {
+    if (!m->km.has_syn) {
+      if (jit) hipLaunchKernelGGL((k_step<S, true, LOOP_GEN, false>), grid, block, 0, s, m->km, a);
+      else hipLaunchKernelGGL((k_step<S, false, LOOP_GEN, false>), grid, block, 0, s, m->km, a);
       return hipGetLastError();
     }
   }
