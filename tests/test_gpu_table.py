@@ -38,12 +38,13 @@ def test_tabulated_validation_workload():
 @pytest.mark.parametrize("which", ["classic", "cortical"])
 @pytest.mark.parametrize("mode", ["dense", "noise", "const"])
 @pytest.mark.parametrize("syn", [False, True])
-@pytest.mark.parametrize("nodes", [201, 641])
+@pytest.mark.parametrize("nodes", [201, 1601])
 def test_tabulated_input_modes(which, mode, syn, nodes):
     """Every launch variant of the tabulated step (dense, noise and
     constant input; with and without synaptic state; the table staged in
-    LDS (201 nodes, at most 16 KB) or read from device memory (641 nodes,
-    over 20 KB)) on a ragged population of 300 neurons."""
+    LDS (201 nodes, at most 16 KB) or read from device memory (1,601 nodes,
+    77 KB and 128 KB, over the 64 KB a block may stage)) on a ragged
+    population of 300 neurons."""
     print_case("tabulated %s mode=%s syn=%s nodes=%d n=300" % (which, mode, syn, nodes))
     torch = need_gpu()
     from paper_2601_21407_amd import hh
@@ -121,7 +122,7 @@ def test_tabulated_range_edges(table):
     _judge(mt, st0, T, g, ro, {"i_const": I}, max_ill_frac=0.05, label="tab-edges")
 
 
-@pytest.mark.parametrize("nodes", [161, 321])
+@pytest.mark.parametrize("nodes", [161, 1601])
 def test_tabulated_fusion_and_resume_bit_identical(nodes):
     torch = need_gpu()
     from paper_2601_21407_amd import hh
