@@ -346,4 +346,12 @@ def test_network_delay_errors():
             M.set_delays(_dev(arr), mx)
         assert e.value.status == status, (mx, status)
     M.set_delays(None, 0)
+    # attaching a connectivity drops a delay table set for the previous one
+    v0 = W.net_v0(n, 2).astype(np.float64)
+    ref, _ = _run_on(M, v0, 300, i_const=np.full(n, 9.0))
+    M.set_delays(_dev(np.full(nnz, 7, np.uint8)), 8)
+    delayed, _ = _run_on(M, v0, 300, i_const=np.full(n, 9.0))
+    M.attach_csr(bufs[0], bufs[1], bufs[2], 0.3)
+    again, _ = _run_on(M, v0, 300, i_const=np.full(n, 9.0))
+    assert ref.sum() > 0 and not np.array_equal(delayed, ref) and np.array_equal(again, ref)
     del torch, bufs
