@@ -43,7 +43,9 @@ __global__ __launch_bounds__(256) void k_init_state(KModel M, float* __restrict_
 // that load latency and register copies would otherwise show.
 // SYN = false: the population is known to have no synapses, and the synaptic
 // terms drop out of the step (bit-identical results).
-enum { LOOP_GEN = 0, LOOP_DENSE = 1, LOOP_NOISE = 2 };
+// LOOP_SINE: sinusoidal input, four steps per iteration like the noise
+// loop, the phase carried in a register.
+enum { LOOP_GEN = 0, LOOP_DENSE = 1, LOOP_NOISE = 2, LOOP_SINE = 3 };
 
 // TAB: tabulated gate kinetics (A.tab) in place of the rate functions; only
 // with uniform coefficients (JIT = false).  TAB_GLOBAL gathers the entries
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) Icur[j] = Inext[j];
     }
-  } else if constexpr (LOOP == LOOP_NOISE) {
+  } else if constexpr (LOOP == LOOP_NOISE || LOOP == LOOP_SINE) {
     // steps until the next checkpoint (a counter, not a division per step)
     int to_ck = A.ckpt ? (A.ckpt_every - A.k_base % A.ckpt_every) % A.ckpt_every : -1;
     to_ck = __builtin_amdgcn_readfirstlane(to_ck);  // uniform: a scalar register
@@ -223,20 +225,34 @@ __global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
         gi *= M.decay_i;
       }
     };
-    // finish the Philox block that an earlier launch began (z was filled and
-    // advanced above), then whole blocks of four steps
-    const int head = min(A.nsteps, (int)((4 - (A.t0 & 3)) & 3));
-    int k = 0;
-    for (; k < head; ++k) {
-      one_step(k, fmaf(A.sigma, z[0], A.mu));
-      z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
-    }
-    for (; k < A.nsteps; k += 4) {
-      normals4(A.seed, nid, (uint64_t)(A.t0 + k) >> 2, z);
+    if constexpr (LOOP == LOOP_SINE) {
+      const float amp = A.i_const[ii];
+      const uint32_t R = sine_rate(A.freq[ii], A.sine_K);
+      uint32_t ph = R * (uint32_t)A.t0;  // R t mod 2^32, advanced by R per step
+      for (int k = 0; k < A.nsteps; k += 4) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (k + j >= A.nsteps) break;
-        one_step(k + j, fmaf(A.sigma, z[j], A.mu));
+        for (int j = 0; j < 4; ++j) {
+          if (k + j >= A.nsteps) break;
+          one_step(k + j, sine_input(amp, ph));
+          ph += R;
+        }
+      }
+    } else {
+      // finish the Philox block that an earlier launch began (z was filled
+      // and advanced above), then whole blocks of four steps
+      const int head = min(A.nsteps, (int)((4 - (A.t0 & 3)) & 3));
+      int k = 0;
+      for (; k < head; ++k) {
+        one_step(k, fmaf(A.sigma, z[0], A.mu));
+        z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
+      }
+      for (; k < A.nsteps; k += 4) {
+        normals4(A.seed, nid, (uint64_t)(A.t0 + k) >> 2, z);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (k + j >= A.nsteps) break;
+          one_step(k + j, fmaf(A.sigma, z[j], A.mu));
+        }
       }
     }
   } else {
@@ -387,7 +403,7 @@ static hipError_t step_spec(const hh_model* m, const StepArgs& a, hipStream_t s)
       if (bytes <= (size_t)kTabLdsMaxBytes) return step_tab<S, TAB_LDS>(m, a, s, grid, block, bytes);
       return step_tab<S, TAB_GLOBAL>(m, a, s, grid, block, 0);
     }
-    if (a.in_mode == IN_DENSE || a.in_mode == IN_NOISE) {
+    if (a.in_mode == IN_DENSE || a.in_mode == IN_NOISE || a.in_mode == IN_SINE) {
 #define HH_LAUNCH(LOOP)                                                                        \
   do {                                                                                         \
     if (jit && syn) hipLaunchKernelGGL((k_step<S, true, LOOP, true>), grid, block, 0, s, m->km, a);   \
@@ -396,6 +412,7 @@ static hipError_t step_spec(const hh_model* m, const StepArgs& a, hipStream_t s)
     else hipLaunchKernelGGL((k_step<S, false, LOOP, false>), grid, block, 0, s, m->km, a);            \
   } while (0)
       if (a.in_mode == IN_DENSE) HH_LAUNCH(LOOP_DENSE);
+      else if (a.in_mode == IN_SINE) HH_LAUNCH(LOOP_SINE);
       else HH_LAUNCH(LOOP_NOISE);
 #undef HH_LAUNCH
       return hipGetLastError();
