@@ -176,6 +176,7 @@ int32_t hh_set_specialize(hh_model* m, int32_t on);
  * HH_E_INVALID for v_hi <= v_lo or non-finite bounds; HH_E_UNSUPPORTED unless
  * the channel set is one of the compiled ones (hh_set_specialize on), the
  * coefficients are uniform (no per-neuron table) and no network is attached.
+ * Multi-compartment neurons (hh_set_morphology) use the table too.
  * hh_backward, hh_surrogate_step_n and the network path return
  * HH_E_UNSUPPORTED while a table is set (they evaluate the rate functions). */
 int32_t hh_set_rate_table(hh_model* m, float v_lo, float v_hi, int32_t n_nodes, void* stream);
@@ -207,9 +208,10 @@ int32_t hh_set_rate_table(hh_model* m, float v_lo, float v_hi, int32_t n_nodes, 
  * Errors: HH_E_SHAPE for K not a power of two in [1, 64] or N not a multiple
  * of K; HH_E_INVALID for a parent outside [-1, c), a negative or non-finite
  * conductance, a non-positive area, or a missing array; HH_E_UNSUPPORTED for
- * more than 4 children on one compartment, or with a network or a rate table
- * set.  With a morphology, hh_step_n refuses checkpoints, level counts and
- * networks, and hh_backward and hh_surrogate_step_n return HH_E_UNSUPPORTED. */
+ * more than 4 children on one compartment, or with a network attached.  A
+ * rate table (hh_set_rate_table) applies to every compartment.  With a
+ * morphology, hh_step_n refuses checkpoints, level counts and networks, and
+ * hh_backward and hh_surrogate_step_n return HH_E_UNSUPPORTED. */
 int32_t hh_set_morphology(hh_model* m, int32_t K, const int32_t* parent, const float* g_axial,
                           const float* area, const float* gbar, void* stream);
 

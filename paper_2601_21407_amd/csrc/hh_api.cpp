@@ -193,7 +193,7 @@ int32_t hh_set_morphology(hh_model* m, int32_t K, const int32_t* parent, const f
   }
   if (K < 1 || K > 64 || (K & (K - 1)) != 0 || m->N % K != 0) return HH_E_SHAPE;
   if (!parent || (K > 1 && !g_axial)) return HH_E_INVALID;
-  if (m->row_ptr || m->d_tab) return HH_E_UNSUPPORTED;
+  if (m->row_ptr) return HH_E_UNSUPPORTED;
   const int nch = m->km.n_ch;
   hhk::CableComp comp[64];
   int nchild[64];
@@ -257,7 +257,7 @@ int32_t hh_set_rate_table(hh_model* m, float v_lo, float v_hi, int32_t n_nodes, 
   // the tabulated step exists for the built-in channel sets with uniform
   // coefficients, outside the network (the network, adjoint and surrogate
   // kernels evaluate the rate functions)
-  if (m->coef || m->row_ptr || m->d_cable || !m->use_fixed) return HH_E_UNSUPPORTED;
+  if (m->coef || m->row_ptr || !m->use_fixed) return HH_E_UNSUPPORTED;
   if (!(hhk::ClassicSpec::matches(m->km) || hhk::CorticalSpec::matches(m->km))) return HH_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   const size_t bytes = (size_t)m->km.n_gates * (size_t)n_nodes * sizeof(float4);

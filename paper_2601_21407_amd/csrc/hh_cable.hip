@@ -21,7 +21,9 @@ __device__ __forceinline__ float lane_v(int addr, float v) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
 }
 
-template <class S, bool SYN, bool GBAR>
+// TAB: 0 the rate functions, 1 tabulated kinetics read from device memory,
+// 2 the table staged in LDS (as in the point step).
+template <class S, bool SYN, bool GBAR, int TAB>
 __global__ __launch_bounds__(256) void k_cable(KModel M, StepArgs A) {
   constexpr int NG = S::kNG;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -55,6 +57,21 @@ __global__ __launch_bounds__(256) void k_cable(KModel M, StepArgs A) {
 
   LaneRates<NG> L;
   load_rates<S>(M, A.coef, pidx, A.N, L);
+  TabRates LT;
+  if constexpr (TAB != 0) {
+    LT.tab = A.tab;
+    LT.n = A.tab_n;
+    LT.v_lo = A.tab_vlo;
+    LT.inv_h = A.tab_inv_h;
+  }
+  if constexpr (TAB == 2) {
+    // every lane of the block reaches this point (no early exit above)
+    extern __shared__ float4 cable_tab[];
+    const int cnt = NG * A.tab_n;
+    for (int x = threadIdx.x; x < cnt; x += blockDim.x) cable_tab[x] = A.tab[x];
+    __syncthreads();
+    LT.tab = cable_tab;
+  }
   const float dtC = A.cm ? M.dt / A.cm[pidx] : M.dt / M.C;
 
   const int64_t row_lo = (int64_t)(1 + NG + 2 * M.has_syn) * n;  // low part of V
@@ -99,7 +116,11 @@ __global__ __launch_bounds__(256) void k_cable(KModel M, StepArgs A) {
 #pragma unroll
     for (int d = 0; d < kMaxChildren; ++d)
       if (d < D) iax = fmaf(gdn[d], lane_v(a_ch[d], V) - V, iax);
-    if constexpr (GBAR)
+    if constexpr (TAB != 0 && GBAR)
+      neuron_step<S, SYN>(M, LT, dtC, vh, vl, p, I + iax, ge, gi, G);
+    else if constexpr (TAB != 0)
+      neuron_step<S, SYN>(M, LT, dtC, vh, vl, p, I + iax, ge, gi);
+    else if constexpr (GBAR)
       neuron_step<S, SYN>(M, L, dtC, vh, vl, p, I + iax, ge, gi, G);
     else
       neuron_step<S, SYN>(M, L, dtC, vh, vl, p, I + iax, ge, gi);
@@ -136,21 +157,37 @@ __global__ __launch_bounds__(256) void k_cable(KModel M, StepArgs A) {
   if (!__builtin_isfinite(chk)) atomicMin(A.bad, (int32_t)i);
 }
 
+template <class S, int TAB>
+static hipError_t launch_cable_tab(const hh_model* m, const StepArgs& a, hipStream_t s, dim3 grid,
+                                   dim3 block, size_t lds) {
+  const bool syn = m->km.has_syn != 0;
+  if (m->cable_gbar) {
+    if (syn) hipLaunchKernelGGL((k_cable<S, true, true, TAB>), grid, block, lds, s, m->km, a);
+    else hipLaunchKernelGGL((k_cable<S, false, true, TAB>), grid, block, lds, s, m->km, a);
+  } else {
+    if (syn) hipLaunchKernelGGL((k_cable<S, true, false, TAB>), grid, block, lds, s, m->km, a);
+    else hipLaunchKernelGGL((k_cable<S, false, false, TAB>), grid, block, lds, s, m->km, a);
+  }
+  return hipGetLastError();
+}
+
+// Largest table staged in LDS: the 64 KiB a block may allocate.
+constexpr int kCableTabLdsMaxBytes = 64 * 1024;
+
 template <class S>
 struct CableF {
   static hipError_t run(const hh_model* m, const StepArgs& a, hipStream_t s) {
     // 64-lane blocks for small populations spread them over more compute units
     const int bs = (a.n < 65536) ? 64 : 256;
     const dim3 grid((unsigned)((a.n + bs - 1) / bs)), block(bs);
-    const bool syn = m->km.has_syn != 0;
-    if (m->cable_gbar) {
-      if (syn) hipLaunchKernelGGL((k_cable<S, true, true>), grid, block, 0, s, m->km, a);
-      else hipLaunchKernelGGL((k_cable<S, false, true>), grid, block, 0, s, m->km, a);
-    } else {
-      if (syn) hipLaunchKernelGGL((k_cable<S, true, false>), grid, block, 0, s, m->km, a);
-      else hipLaunchKernelGGL((k_cable<S, false, false>), grid, block, 0, s, m->km, a);
+    if constexpr (S::kFixed) {
+      if (a.tab) {  // tables exist for the compiled channel sets only
+        const size_t bytes = (size_t)S::kNG * (size_t)a.tab_n * sizeof(float4);
+        if (bytes <= (size_t)kCableTabLdsMaxBytes) return launch_cable_tab<S, 2>(m, a, s, grid, block, bytes);
+        return launch_cable_tab<S, 1>(m, a, s, grid, block, 0);
+      }
     }
-    return hipGetLastError();
+    return launch_cable_tab<S, 0>(m, a, s, grid, block, 0);
   }
 };
 

@@ -5,14 +5,17 @@ follow the oracle within 1e-3 mV at every step, spike trains agree in count
 and within one dt; a mismatch is excused only when 1e-6 relative probes of
 the input, C_m, V0 or one group (A, B or K) of rate coefficients move the
 oracle's own result for that compartment by more than the tolerance, or storing the oracle's state in FP32 after every
-step moves its trace by more than half of it (ill-conditioned), and such
-cases are counted."""
+step moves its trace by more than half of it (ill-conditioned); spike
+trains agree up to each compartment's predictability horizon (the first
+spike whose interpolated time moves by more than 0.1 dt under such a
+probe), as for point neurons.  Excused cases are counted."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2601_21407_amd import workloads as W
-from tests.gpu_util import input_probes, need_gpu, nominal_coef, print_case, spike_mismatch
+from tests.gpu_util import (_interp_times, input_probes, match_to_horizon, need_gpu, nominal_coef,
+                            print_case, spike_mismatch)
 
 pytestmark = pytest.mark.gpu
 
@@ -148,6 +151,51 @@ def _ill(model, morph, st0, T, cand, kw, *, v_tol, quiet):
     return np.array([moved[pos[c]] for c in cand], bool)
 
 
+def _horizons(model, morph, st0, T, cand, kw, *, shift_tol=0.1):
+    """Per candidate compartment: the number of leading oracle spikes whose
+    timing is well conditioned, as for point neurons: a spike, and every
+    later one, lies beyond the horizon when its interpolated time moves by
+    more than shift_tol steps (or the count changes) under a 1e-6 probe of
+    the input, C_m or one group of rate coefficients of its neuron."""
+    K = morph["K"]
+    neurons = np.unique(np.asarray(cand) // K)
+    cols = (neurons[:, None] * K + np.arange(K)[None, :]).ravel()
+    base = _cols(kw, cols)
+    if base.get("cm") is None:
+        base["cm"] = np.full(len(cols), float(model["C"]))
+    if ("noise_mu" in base or "background" in base) and base.get("ids") is None:
+        base["ids"] = cols.astype(np.uint32)
+    coef = base.get("coef")
+    if coef is None and len(model["gates"]):
+        coef = nominal_coef(model, len(cols))
+    s0 = st0[:, cols]
+    thr = float(model["v_th"])
+    ref = O.cable_run(model, s0.copy(), T, morph, record_v=True, **base)
+    base_t = _interp_times(np.vstack([s0[0:1], ref["v"]]), thr)
+    probes = []
+    for f in (1 + PROBE, 1 - PROBE):
+        probes += input_probes(base, f)
+        probes.append(dict(base, cm=base["cm"] * f))
+        if coef is not None:
+            for j in range(3):
+                c2 = coef.copy()
+                c2[j::4] *= f
+                probes.append(dict(base, coef=c2))
+    h = np.array([len(b) for b in base_t])
+    for pk in probes:
+        r = O.cable_run(model, s0.copy(), T, morph, record_v=True, **pk)
+        tt = _interp_times(np.vstack([s0[0:1], r["v"]]), thr)
+        for c, (a, b) in enumerate(zip(tt, base_t)):
+            m_ = min(len(a), len(b))
+            d = np.abs(a[:m_] - b[:m_]) > shift_tol
+            first = int(np.argmax(d)) if d.any() else m_
+            if len(a) != len(b):
+                first = min(first, m_)
+            h[c] = min(h[c], first)
+    pos = {c: j for j, c in enumerate(cols.tolist())}
+    return {c: (int(h[pos[c]]), np.nonzero(ref["spikes"][:, pos[c]])[0]) for c in cand}
+
+
 def _judge(model, morph, st0, T, g, ro, kw, *, v_tol=1e-3, max_ill_frac=0.05, label=""):
     n = st0.shape[1]
     quiet = ro["spikes"].sum(0) == 0
@@ -158,6 +206,14 @@ def _judge(model, morph, st0, T, g, ro, kw, *, v_tol=1e-3, max_ill_frac=0.05, la
     spike_bad = spike_mismatch(g["raster"], ro["spikes"])
     cand = np.union1d(trace_bad, spike_bad).astype(np.int64)
     ill = _ill(model, morph, st0, T, cand, kw, v_tol=v_tol, quiet=quiet)
+    # spiking compartments: the trains must agree up to the predictability
+    # horizon (as for point neurons); beyond it a mismatch is excused
+    spiking = [int(c) for c in cand[~ill] if not quiet[c]]
+    if spiking:
+        hz = _horizons(model, morph, st0, T, spiking, kw)
+        for j, c in enumerate(cand.tolist()):
+            if c in hz and match_to_horizon(np.nonzero(g["raster"][:, c])[0], hz[c][1], hz[c][0]):
+                ill[j] = True
     fails = cand[~ill].tolist()
     wc = dv[quiet & (dv <= v_tol)] if g.get("v") is not None else np.zeros(1)
     rep = ("%s n=%d quiet=%d max|dV| (quiet, within tol)=%.3g mV; spike mismatches=%d; trace "
@@ -308,6 +364,38 @@ def test_cable_full_size_sampled():
            label="cable-full-size")
 
 
+@pytest.mark.parametrize("nodes", [321, 1601])
+def test_cable_with_rate_table(nodes):
+    """Tabulated gate kinetics in every compartment of the soma + 3
+    dendrites morphology: the table staged in LDS (321 nodes, 15 KB) or
+    read from device memory (1,601 nodes, 77 KB), against the oracle's
+    cable run with the same table."""
+    print_case("cable soma3x5 with table nodes=%d" % nodes)
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    m = W.classic_hh(dt=0.025)
+    morph = _morph("soma3x5", m)
+    table = (-100.0, 60.0, nodes)
+    mt = dict(m, table=table)
+    N, T = 37, 2000
+    n = N * morph["K"]
+    kw_g, kw_o = _inputs("const", morph, N, T, seed=N)
+    M = hh.Model(m, n)
+    M.set_rate_table(*table)
+    M.set_morphology(morph["K"], morph["parent"], morph["g_axial"], morph["area"], morph["gbar"])
+    st = M.init_state(M.new_state(), v0_scalar=-65.0)
+    spikes = torch.zeros((T, M.words), dtype=torch.int32, device="cuda")
+    vrec = torch.zeros((T, n), dtype=torch.float32, device="cuda")
+    M.step_n(st, T, 0, i_const=torch.tensor(np.asarray(kw_g["i_const"], np.float32), device="cuda"),
+             spikes=spikes, v_rec=vrec)
+    assert M.check()[0] == 0
+    g = {"raster": O.unpack_bits(spikes.cpu().numpy().view(np.uint32), n), "v": vrec.cpu().numpy()}
+    st0 = O.init_state(m, np.full(n, -65.0))
+    ro = O.cable_run(mt, st0.copy(), T, morph, record_v=True, **kw_o)
+    assert ro["spikes"].sum() > 0
+    _judge(mt, morph, st0, T, g, ro, kw_o, label="cable-table-%d" % nodes)
+
+
 def test_cable_fusion_and_resume_bit_identical():
     torch = need_gpu()
     from paper_2601_21407_amd import hh
@@ -364,9 +452,6 @@ def test_cable_errors_and_removal():
         with pytest.raises(hh.HHError) as e:
             M.step_n(cab, 10, i_const=ic, **kw)
         assert e.value.status == -5
-    with pytest.raises(hh.HHError) as e:
-        M.set_rate_table(-100.0, 60.0, 161)
-    assert e.value.status == -5
     Id = torch.zeros((20, n), device="cuda")
     with pytest.raises(hh.HHError) as e:
         M.backward(torch.zeros((2, M.n_state, n), device="cuda"), 10, Id, 20, torch.zeros_like(Id))
@@ -376,8 +461,9 @@ def test_cable_errors_and_removal():
     again = M.init_state(M.new_state(), v0_scalar=-65.0)
     M.step_n(again, 300, i_const=ic)
     assert torch.equal(again, ref) and not torch.equal(cab, ref)
-    # a table set first refuses a morphology
+    # a table and a morphology combine, in either order
     M.set_rate_table(-100.0, 60.0, 161)
-    with pytest.raises(hh.HHError) as e:
-        M.set_morphology(4, [-1, 0, 0, 0], [0, 1, 1, 1])
-    assert e.value.status == -5
+    M.set_morphology(4, [-1, 0, 0, 0], [0, 1, 1, 1])
+    both = M.init_state(M.new_state(), v0_scalar=-65.0)
+    M.step_n(both, 300, i_const=ic)
+    assert not torch.equal(both, cab)
