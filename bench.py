@@ -263,7 +263,8 @@ def bench_cable(N=65536, T=4000, fusion=32):
     ms.  The same number of point neurons with the same input gives the cost
     of the coupling.  Algorithmic work per compartment-update: the point
     neuron's, plus two operations per edge end (a difference and a
-    multiply-add) and the addition to the input."""
+    multiply-add) and the addition to the input.  A third run takes the
+    gate kinetics from a 161-node rate table."""
     import torch
     from paper_2601_21407_amd import hh
     from paper_2601_21407_amd import workloads as W
@@ -296,17 +297,27 @@ def bench_cable(N=65536, T=4000, fusion=32):
     Mc.set_morphology(K, mo["parent"], mo["g_axial"], mo["area"], mo["gbar"])
     ms_cable = timed(Mc)
     del Mc
+    Mt = hh.Model(m, n)
+    Mt.set_fusion(fusion)
+    Mt.set_morphology(K, mo["parent"], mo["g_axial"], mo["area"], mo["gbar"])
+    Mt.set_rate_table(-100.0, 60.0, 161)
+    ms_table = timed(Mt)
+    del Mt
     Mp = hh.Model(m, n)
     Mp.set_fusion(fusion)
     ms_point = timed(Mp)
     del Mp
     edge_ends = 2.0 * (K - 1) / K
     slots = slots_per_update(m, noise=True) + 2.0 * edge_ends + 1.0
+    slots_t = slots_per_update(m, noise=True, table=True) + 2.0 * edge_ends + 1.0
     achieved = slots * n * T / (ms_cable / 1e3) / 1e12
     return {"neurons": N, "compartments": n, "K": K, "T": T, "fusion": fusion,
             "ms": ms_cable, "compartment_updates_per_s": n * T / ms_cable * 1e3,
             "avg_launch_us": ms_cable * 1e3 / launches,
             "point_neuron_ms": ms_point, "coupling_overhead": ms_cable / ms_point - 1.0,
+            "table_161": {"ms": ms_table, "avg_launch_us": ms_table * 1e3 / launches,
+                          "speedup": ms_cable / ms_table, "slots_per_update": slots_t,
+                          "frac": slots_t * n * T / (ms_table / 1e3) / PEAK_LANE_OPS},
             "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS / 1e12,
                          "unit": "Tslot/s", "frac": achieved * 1e12 / PEAK_LANE_OPS,
                          "slots_per_update": slots}}
