@@ -196,9 +196,11 @@ class Model:
         self.h = h
         self.n_state = lib.hh_n_state(self.h)
 
-    def __del__(self):
+    # the library is bound as a default argument: at interpreter exit the
+    # module's globals may already be cleared when the last models go
+    def __del__(self, _destroy=lib.hh_destroy):
         if getattr(self, "h", None):
-            lib.hh_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     @property
