@@ -46,7 +46,7 @@ def _morph(kind, model):
 
 
 def _run_gpu(model, morph, n, T, *, v0=-65.0, state=None, i_const=None, noise=None, i_dense=None,
-             record_v=True, fusion=32, specialize=True, cm=None):
+             record_v=True, fusion=32, specialize=True, cm=None, table=None):
     torch = need_gpu()
     from paper_2601_21407_amd import hh
     dev = "cuda"
@@ -54,6 +54,8 @@ def _run_gpu(model, morph, n, T, *, v0=-65.0, state=None, i_const=None, noise=No
     M = hh.Model(model, n, cm=cm_t)
     M.set_fusion(fusion)
     M.set_specialize(specialize)
+    if table is not None:
+        M.set_rate_table(*table)
     M.set_morphology(morph["K"], morph["parent"], morph.get("g_axial"), morph.get("area"),
                      morph.get("gbar"))
     if state is None:
@@ -364,36 +366,26 @@ def test_cable_full_size_sampled():
            label="cable-full-size")
 
 
-@pytest.mark.parametrize("nodes", [321, 1601])
-def test_cable_with_rate_table(nodes):
+@pytest.mark.parametrize("nodes,mode", [(321, "const"), (1601, "const"), (321, "noise"),
+                                        (1601, "dense")])
+def test_cable_with_rate_table(nodes, mode):
     """Tabulated gate kinetics in every compartment of the soma + 3
     dendrites morphology: the table staged in LDS (321 nodes, 15 KB) or
-    read from device memory (1,601 nodes, 77 KB), against the oracle's
-    cable run with the same table."""
-    print_case("cable soma3x5 with table nodes=%d" % nodes)
-    torch = need_gpu()
-    from paper_2601_21407_amd import hh
+    read from device memory (1,601 nodes, 77 KB), under constant, noisy
+    and dense input, against the oracle's cable run with the same table."""
+    print_case("cable soma3x5 with table nodes=%d input=%s" % (nodes, mode))
     m = W.classic_hh(dt=0.025)
     morph = _morph("soma3x5", m)
     table = (-100.0, 60.0, nodes)
     mt = dict(m, table=table)
     N, T = 37, 2000
     n = N * morph["K"]
-    kw_g, kw_o = _inputs("const", morph, N, T, seed=N)
-    M = hh.Model(m, n)
-    M.set_rate_table(*table)
-    M.set_morphology(morph["K"], morph["parent"], morph["g_axial"], morph["area"], morph["gbar"])
-    st = M.init_state(M.new_state(), v0_scalar=-65.0)
-    spikes = torch.zeros((T, M.words), dtype=torch.int32, device="cuda")
-    vrec = torch.zeros((T, n), dtype=torch.float32, device="cuda")
-    M.step_n(st, T, 0, i_const=torch.tensor(np.asarray(kw_g["i_const"], np.float32), device="cuda"),
-             spikes=spikes, v_rec=vrec)
-    assert M.check()[0] == 0
-    g = {"raster": O.unpack_bits(spikes.cpu().numpy().view(np.uint32), n), "v": vrec.cpu().numpy()}
+    kw_g, kw_o = _inputs(mode, morph, N, T, seed=N)
+    g = _run_gpu(m, morph, n, T, table=table, **kw_g)
     st0 = O.init_state(m, np.full(n, -65.0))
     ro = O.cable_run(mt, st0.copy(), T, morph, record_v=True, **kw_o)
     assert ro["spikes"].sum() > 0
-    _judge(mt, morph, st0, T, g, ro, kw_o, label="cable-table-%d" % nodes)
+    _judge(mt, morph, st0, T, g, ro, kw_o, label="cable-table-%d-%s" % (nodes, mode))
 
 
 def test_cable_fusion_and_resume_bit_identical():
