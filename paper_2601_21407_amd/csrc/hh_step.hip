@@ -53,14 +53,17 @@ enum { LOOP_GEN = 0, LOOP_DENSE = 1, LOOP_NOISE = 2, LOOP_SINE = 3 };
 // into LDS (dynamic size n_gates x n_nodes x 16 bytes), whose bandwidth is
 // twice that of the L1 path.
 enum { TAB_NONE = 0, TAB_GLOBAL = 1, TAB_LDS = 2 };
-// Largest table staged in LDS: the 64 KiB a block may allocate.  LDS pays
-// even where it limits residency: a 51 KB table (641 nodes of the cortical
-// set) leaves three blocks per compute unit and still runs faster than the
-// same reads from device memory (11.8 against 14.1 ms for 1M x 4,000).
+// Largest table staged in LDS: the 64 KiB a block may allocate.
 constexpr int kTabLdsMaxBytes = 64 * 1024;
+// Above this size fewer than six 256-lane blocks share the 160 KB of LDS of a
+// compute unit, so large populations take 512-lane blocks: each copy of the
+// table then serves eight wavefronts instead of four (a 51 KB table, 641
+// nodes of the cortical set: 10.7 against 13.5 ms for 1M x 4,000, the speed
+// of a 161-node table).
+constexpr int kTabLdsWideBytes = 24 * 1024;
 
 template <class S, bool JIT, int LOOP, bool SYN, int TAB = TAB_NONE>
-__global__ __launch_bounds__(256) void k_step(KModel M, StepArgs A) {
+__global__ __launch_bounds__(TAB == TAB_LDS ? 512 : 256) void k_step(KModel M, StepArgs A) {
   static_assert(!(TAB != TAB_NONE && JIT), "tabulated kinetics need uniform coefficients");
   constexpr bool PF = LOOP == LOOP_DENSE;
   constexpr int NG = S::kNG;
@@ -400,6 +403,10 @@ static hipError_t step_spec(const hh_model* m, const StepArgs& a, hipStream_t s)
     const bool syn = m->km.has_syn != 0;
     if (a.tab) {  // validated when the table was set: uniform coefficients
       const size_t bytes = (size_t)S::kNG * (size_t)a.tab_n * sizeof(float4);
+      if (bytes > (size_t)kTabLdsWideBytes && bytes <= (size_t)kTabLdsMaxBytes && a.n >= 65536) {
+        const dim3 wgrid((unsigned)((a.n + 511) / 512)), wblock(512);
+        return step_tab<S, TAB_LDS>(m, a, s, wgrid, wblock, bytes);
+      }
       if (bytes <= (size_t)kTabLdsMaxBytes) return step_tab<S, TAB_LDS>(m, a, s, grid, block, bytes);
       return step_tab<S, TAB_GLOBAL>(m, a, s, grid, block, 0);
     }

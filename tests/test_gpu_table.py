@@ -84,12 +84,15 @@ def test_tabulated_input_modes(which, mode, syn, nodes):
     _judge(mt, st0, T, g, ro, kw_o, max_ill_frac=0.05, label="tab-%s-%s" % (which, mode))
 
 
-def test_tabulated_full_size_sampled():
+@pytest.mark.parametrize("nodes", [161, 641])
+def test_tabulated_full_size_sampled(nodes):
     """The benchmark's configuration (1,048,576 cortical neurons, noisy
     input 5 + 3z, dt = 0.025 ms, 4,000 steps, 32 fused steps per launch)
-    with 161 nodes (h = 1 mV); 2,048 sampled neurons against the oracle."""
-    print_case("tabulated cortical 1048576 x 4000 nodes=161 (sampled 2048)")
-    table = (-100.0, 60.0, 161)
+    with 161 nodes (h = 1 mV, 256-lane blocks) and 641 nodes (h = 0.25 mV,
+    51 KB in LDS, 512-lane blocks); 2,048 sampled neurons against the
+    oracle."""
+    print_case("tabulated cortical 1048576 x 4000 nodes=%d (sampled 2048)" % nodes)
+    table = (-100.0, 60.0, nodes)
     m = W.custom_channels(dt=0.025)
     mt = _tab(m, table)
     n, T, seed = 1 << 20, 4000, 2
@@ -99,7 +102,7 @@ def test_tabulated_full_size_sampled():
     ids = np.unique(np.concatenate([[0, 1, 63, 64, n - 1], rng.choice(n, 2043, replace=False)]))
     st0 = O.init_state(m, np.full(len(ids), -65.0))
     kw = {"noise_mu": 5.0, "noise_sigma": 3.0, "seed": seed, "ids": ids}
-    ro = _cached("tab-full", lambda: O.run(mt, st0.copy(), T, **kw))
+    ro = _cached("tab-full-%d" % nodes, lambda: O.run(mt, st0.copy(), T, **kw))
     assert ro["spikes"].sum(0).mean() > 1.0
     gs = {"raster": _columns(g["bits"], ids), "v": None}
     _judge(mt, st0, T, gs, ro, kw, max_ill_frac=0.02, label="tab-full-size")
@@ -122,12 +125,12 @@ def test_tabulated_range_edges(table):
     _judge(mt, st0, T, g, ro, {"i_const": I}, max_ill_frac=0.05, label="tab-edges")
 
 
-@pytest.mark.parametrize("nodes", [161, 1601])
+@pytest.mark.parametrize("nodes", [161, 641, 1601])
 def test_tabulated_fusion_and_resume_bit_identical(nodes):
     torch = need_gpu()
     from paper_2601_21407_amd import hh
     m = W.custom_channels(dt=0.025)
-    n, T = 70000, 300  # 256-lane blocks
+    n, T = 70000, 300  # 256-lane blocks (512 with the 641-node table in LDS), ragged last block
     outs = []
     for fusion, splits in ((32, (300,)), (5, (120, 180)), (1, (299, 1))):
         M = hh.Model(m, n)
