@@ -24,7 +24,7 @@ __device__ __forceinline__ float lane_v(int addr, float v) {
 // TAB: 0 the rate functions, 1 tabulated kinetics read from device memory,
 // 2 the table staged in LDS (as in the point step).
 template <class S, bool SYN, bool GBAR, int TAB>
-__global__ __launch_bounds__(256) void k_cable(KModel M, StepArgs A) {
+__global__ __launch_bounds__(TAB == 2 ? 512 : 256) void k_cable(KModel M, StepArgs A) {
   constexpr int NG = S::kNG;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const bool act = i < A.n;
@@ -171,8 +171,11 @@ static hipError_t launch_cable_tab(const hh_model* m, const StepArgs& a, hipStre
   return hipGetLastError();
 }
 
-// Largest table staged in LDS: the 64 KiB a block may allocate.
+// Largest table staged in LDS: the 64 KiB a block may allocate.  Above 24 KiB
+// large populations take 512-lane blocks, so that each copy of the table
+// serves eight wavefronts (blocks of whole wavefronts never split a neuron).
 constexpr int kCableTabLdsMaxBytes = 64 * 1024;
+constexpr int kCableTabLdsWideBytes = 24 * 1024;
 
 template <class S>
 struct CableF {
@@ -183,6 +186,11 @@ struct CableF {
     if constexpr (S::kFixed) {
       if (a.tab) {  // tables exist for the compiled channel sets only
         const size_t bytes = (size_t)S::kNG * (size_t)a.tab_n * sizeof(float4);
+        if (bytes > (size_t)kCableTabLdsWideBytes && bytes <= (size_t)kCableTabLdsMaxBytes &&
+            a.n >= 65536) {
+          const dim3 wgrid((unsigned)((a.n + 511) / 512)), wblock(512);
+          return launch_cable_tab<S, 2>(m, a, s, wgrid, wblock, bytes);
+        }
         if (bytes <= (size_t)kCableTabLdsMaxBytes) return launch_cable_tab<S, 2>(m, a, s, grid, block, bytes);
         return launch_cable_tab<S, 1>(m, a, s, grid, block, 0);
       }

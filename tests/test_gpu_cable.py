@@ -388,6 +388,28 @@ def test_cable_with_rate_table(nodes, mode):
     _judge(mt, morph, st0, T, g, ro, kw_o, label="cable-table-%d-%s" % (nodes, mode))
 
 
+def test_cable_wide_blocks_bit_identical():
+    """A 641-node table (31 KB in LDS) on 72,000 compartments runs in
+    512-lane blocks with a ragged last block; its first 65,472 compartments
+    equal, bit for bit, a 65,472-compartment run in 64-lane blocks (the
+    arithmetic per compartment does not depend on the block size)."""
+    print_case("cable wide blocks 641-node table")
+    m = W.classic_hh(dt=0.025)
+    morph = _morph("soma3x5", m)
+    table = (-100.0, 60.0, 641)
+    T = 400
+    outs = []
+    for n in (72000, 65472):
+        g = _run_gpu(m, morph, n, T, noise=(2.5, 3.0, 17), table=table)
+        outs.append(g)
+    big, small = outs
+    n = 65472
+    assert np.array_equal(big["bits"][:, :n // 32], small["bits"])
+    assert np.array_equal(big["v"][:, :n], small["v"])
+    assert np.array_equal(big["state"][:, :n], small["state"])
+    assert small["raster"].sum() > 0
+
+
 def test_cable_fusion_and_resume_bit_identical():
     torch = need_gpu()
     from paper_2601_21407_amd import hh
