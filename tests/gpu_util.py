@@ -1,6 +1,28 @@
-"""Shared helpers of the GPU parity tests (comparison logic only)."""
+"""Shared helpers of the GPU parity tests (comparison logic only).
+
+The parity judge follows the stated tolerance: non-spiking traces within
+1e-3 mV of the FP64 oracle at every step, spike trains equal in count with
+every spike within one dt.  A neuron is excused (counted and reported, not
+failed) only where the oracle's own result is not determined to that
+tolerance by FP32-sized perturbations, established with two probes of the
+oracle:
+  - the input current scaled by (1 +- 1e-6) (for background input: its
+    amplitudes; for sine input: its amplitude), and
+  - the same FP64 steps with the state rounded to binary32 before every step
+    (what any FP32 integrator must at least incur).
+A quiet trace is excused when an input probe moves it by more than the
+tolerance, or the FP32-state run by more than half of it (or either makes it
+spike).  A spike train is compared up to its predictability horizon: the
+first spike that one of the probes moves by more than one step (or a change
+of count); before the horizon the GPU must match within one step and have no
+other spike.  Every excusal is recorded and the counts are printed in the
+pytest terminal summary.
+"""
 import numpy as np
 import pytest
+
+# (label, elements judged, excused, failures, horizon-excused spike trains)
+JUDGE_LOG = []
 
 
 def need_gpu():
@@ -31,28 +53,7 @@ def print_case(msg: str):
     print("[case] " + msg, flush=True)
 
 
-# 1e-6 relative probes of the oracle's own sensitivity: input current,
-# capacitance, initial V and initial gates, each scaled by (1 +- 1e-6).  The
-# GPU computes in FP32, which perturbs every quantity by ~6e-8 relative per
-# operation; a neuron whose FP64 trajectory moves by more than the tolerance
-# under one of these (16x larger) probes is ill-conditioned: reported, not
-# failed.  Typical cases are near-miss excursions that stop just below the
-# spike threshold, and spikes triggered close to rheobase.
 PROBE = 1e-6
-
-
-def _subset_kw(kw, idx, n):
-    out = {}
-    for k, v in kw.items():
-        if k == "sine" and v is not None:  # (amplitudes [n], frequencies [n])
-            out[k] = (np.asarray(v[0])[idx], np.asarray(v[1])[idx])
-        elif isinstance(v, np.ndarray) and v.ndim == 1 and v.shape[0] == n:
-            out[k] = v[idx]
-        elif k in ("coef", "i_dense") and v is not None:
-            out[k] = v[:, idx]
-        else:
-            out[k] = v
-    return out
 
 
 def nominal_coef(model, count):
@@ -67,7 +68,8 @@ def nominal_coef(model, count):
 
 def input_probes(kw, f):
     """Copies of the oracle arguments with the input scaled by f: the
-    constant, noise-mean or dense input, or the background amplitudes."""
+    constant, noise-mean or dense input, the background amplitudes or the
+    sine amplitudes."""
     out = []
     for key in ("i_const", "noise_mu", "i_dense"):
         if kw.get(key) is not None:
@@ -81,126 +83,129 @@ def input_probes(kw, f):
     return out
 
 
-def ill_conditioned(O, model, st0, T, idx, base_kw, *, v_tol=1e-3):
-    """Returns (spike_ill, trace_ill): boolean arrays over idx.  spike_ill: a
-    probe moves the oracle's spike train by more than one dt (or changes its
-    count); trace_ill: a probe moves V by more than v_tol at some step.  The
-    probes are those of spike_horizons (input, capacitance, one group of rate
-    coefficients) and the initial state."""
-    idx = np.asarray(idx, dtype=np.int64)
-    n = st0.shape[1]
-    if len(idx) == 0:
-        return np.zeros(0, bool), np.zeros(0, bool)
-    kw = _subset_kw(base_kw, idx, n)
-    cm = kw.get("cm")
-    if cm is None:
-        cm = np.full(len(idx), float(model["C"]))
-    ref = O.run(model, st0[:, idx].copy(), T, record_v=True, **dict(kw, cm=cm))
-    coef = kw.get("coef")
-    if coef is None and len(model["gates"]):
-        coef = nominal_coef(model, len(idx))
-    probes = []
-    for f in (1 + PROBE, 1 - PROBE):
-        probes += [dict(p, cm=cm) for p in input_probes(kw, f)]
-        probes.append(dict(kw, cm=cm * f))
-        if coef is not None:
-            for j in range(3):  # A, B, K rows of every rate
-                c2 = coef.copy()
-                c2[j::4] *= f
-                probes.append(dict(kw, cm=cm, coef=c2))
-    s0 = st0[:, idx]
-    starts = [s0] * len(probes)
-    # initial-state probes: V0 and every gate scaled by (1 +- 1e-6)
-    G = len(model["gates"])
-    for f in (1 + PROBE, 1 - PROBE):
-        for rows in ([0], list(range(1, 1 + G))):
-            s1 = s0.copy()
-            s1[rows] *= f
-            probes.append(dict(kw, cm=cm))
-            starts.append(s1)
-    sp = np.zeros(len(idx), bool)
-    tr = np.zeros(len(idx), bool)
-    for p, s_init in zip(probes, starts):
-        r = O.run(model, s_init.copy(), T, record_v=True, **p)
-        bad = spike_mismatch(r["spikes"], ref["spikes"])
-        sp[bad] = True
-        tr |= np.max(np.abs(r["v"] - ref["v"]), axis=0) > v_tol
-    # representation probe: the same FP64 steps with the state stored in
-    # FP32 after every step (what any FP32 integrator must at least incur);
-    # ill-conditioned when that alone uses half the trace tolerance
-    s = s0.copy()
-    vr = np.zeros((T, len(idx)))
-    spk = np.zeros((T, len(idx)), np.uint8)
-    kw1 = dict(kw, cm=cm)
-    dense = kw1.pop("i_dense", None)
-    t0 = int(kw1.pop("t0", 0))
-    for k in range(T):
-        extra = {} if dense is None else {"i_dense": dense[k:k + 1]}
-        r = O.run(model, s, 1, t0=t0 + k, record_v=True, **kw1, **extra)
-        s[:] = s.astype(np.float32).astype(np.float64)
-        vr[k] = r["v"][0]
-        spk[k] = r["spikes"][0]
-    sp[spike_mismatch(spk, ref["spikes"])] = True
-    tr |= np.max(np.abs(vr - ref["v"]), axis=0) > 0.5 * v_tol
-    return sp, tr
-
-
-def _interp_times(v, thr):
-    """Upward threshold crossings, interpolated within the step (in steps)."""
-    out = []
-    for j in range(v.shape[1]):
-        x = v[:, j]
-        ks = np.nonzero((x[:-1] < thr) & (x[1:] >= thr))[0] + 1
-        t = [k - 1 + (thr - x[k - 1]) / (x[k] - x[k - 1]) for k in ks]
-        if x[0] >= thr:  # crossing in the first step is not interpolable here
-            t = [0.0] + t
-        out.append(np.array(t))
+def _subset(kw, cols, n):
+    """The oracle arguments restricted to elements `cols` of n; element ids
+    travel with the subset, so random inputs stay those of the elements."""
+    out = {}
+    for k, v in kw.items():
+        if k == "sine" and v is not None:  # (amplitudes [n], frequencies [n])
+            out[k] = (np.asarray(v[0])[cols], np.asarray(v[1])[cols])
+        elif k in ("coef", "i_dense") and v is not None:
+            out[k] = np.ascontiguousarray(np.asarray(v)[:, cols])
+        elif isinstance(v, np.ndarray) and v.ndim == 1 and v.shape[0] == n:
+            out[k] = v[cols]
+        else:
+            out[k] = v
+    if out.get("ids") is None and ("noise_mu" in out or out.get("background") is not None):
+        out["ids"] = np.asarray(cols, dtype=np.uint32)
     return out
 
 
-def spike_horizons(O, model, st0, T, idx, base_kw, *, shift_tol=0.1):
-    """Per neuron in idx: the number of leading oracle spikes whose timing is
-    well conditioned.  A spike is ill-conditioned when its interpolated time
-    moves by more than shift_tol steps under a 1e-6 relative probe of the
-    input, the capacitance or one group (A, B or K) of rate coefficients;
-    that spike and all later ones lie beyond the neuron's predictability
+class _Oracle:
+    """Oracle runs over a subset of the judged elements: point neurons, or
+    whole multi-compartment neurons when a morphology is given (a
+    compartment is only re-run together with its neuron)."""
+
+    def __init__(self, O, model, st0, T, kw, morph=None):
+        self.O, self.model, self.st0, self.T, self.kw, self.morph = O, model, st0, T, kw, morph
+        self.n = st0.shape[1]
+
+    def columns(self, idx):
+        idx = np.asarray(idx, dtype=np.int64)
+        if self.morph is None:
+            return idx
+        K = int(self.morph["K"])
+        neurons = np.unique(idx // K)
+        return (neurons[:, None] * K + np.arange(K)[None, :]).ravel()
+
+    def run(self, s0, T, **kw):
+        if self.morph is None:
+            return self.O.run(self.model, s0, T, record_v=True, **kw)
+        return self.O.cable_run(self.model, s0, T, self.morph, record_v=True, **kw)
+
+    def reference_and_probes(self, cols):
+        """(reference, [probe results]) for elements cols: the input probes
+        and the FP32-state run."""
+        kw = _subset(self.kw, cols, self.n)
+        s0 = np.ascontiguousarray(self.st0[:, cols])
+        ref = self.run(s0.copy(), self.T, **kw)
+        outs = []
+        for f in (1 + PROBE, 1 - PROBE):
+            for p in input_probes(kw, f):
+                outs.append(self.run(s0.copy(), self.T, **p))
+        outs.append(self.fp32_state_run(s0, kw))
+        return ref, outs
+
+    def fp32_state_run(self, s0, kw):
+        s = s0.astype(np.float32).astype(np.float64)
+        T = self.T
+        vr = np.zeros((T, s.shape[1]))
+        spk = np.zeros((T, s.shape[1]), np.uint8)
+        kw1 = dict(kw)
+        dense = kw1.pop("i_dense", None)
+        t0 = int(kw1.pop("t0", 0))
+        for k in range(T):
+            extra = {} if dense is None else {"i_dense": dense[k:k + 1]}
+            r = self.run(s, 1, t0=t0 + k, **kw1, **extra)
+            s[:] = s.astype(np.float32).astype(np.float64)
+            vr[k] = r["v"][0]
+            spk[k] = r["spikes"][0]
+        return {"v": vr, "spikes": spk, "fp32": True}
+
+
+def _first_moved(a, b):
+    """Index of the first spike of reference train b that train a moves by
+    more than one step, counting from the start; len(b) if none (a count
+    change ends the comparison at the shorter train)."""
+    m_ = min(len(a), len(b))
+    d = np.abs(np.asarray(a[:m_], np.int64) - np.asarray(b[:m_], np.int64)) > 1
+    first = int(np.argmax(d)) if d.any() else m_
+    if len(a) != len(b):
+        first = min(first, m_)
+    return first
+
+
+def ill_conditioned(O, model, st0, T, idx, base_kw, *, v_tol=1e-3, morph=None):
+    """Returns (spike_ill, trace_ill): boolean arrays over idx.  spike_ill: a
+    probe moves the oracle's spike train by more than one step (or changes
+    its count); trace_ill: an input probe moves V by more than v_tol, or the
+    FP32-state run by more than v_tol / 2, at some step."""
+    idx = np.asarray(idx, dtype=np.int64)
+    if len(idx) == 0:
+        return np.zeros(0, bool), np.zeros(0, bool)
+    R = _Oracle(O, model, st0, T, base_kw, morph)
+    cols = R.columns(idx)
+    ref, outs = R.reference_and_probes(cols)
+    sp = np.zeros(len(cols), bool)
+    tr = np.zeros(len(cols), bool)
+    for r in outs:
+        sp[spike_mismatch(r["spikes"], ref["spikes"])] = True
+        tol = 0.5 * v_tol if r.get("fp32") else v_tol
+        tr |= np.max(np.abs(r["v"] - ref["v"]), axis=0) > tol
+    pos = {c: j for j, c in enumerate(cols.tolist())}
+    sel = np.array([pos[c] for c in idx.tolist()], dtype=np.int64)
+    return sp[sel], tr[sel]
+
+
+def spike_horizons(O, model, st0, T, idx, base_kw, *, morph=None):
+    """Per element in idx: the number of leading oracle spikes that no probe
+    (input (1 +- 1e-6), FP32-state run) moves by more than one step; that
+    spike and all later ones lie beyond the element's predictability
     horizon.  Returns (horizon counts, oracle spike-step lists)."""
     idx = np.asarray(idx, dtype=np.int64)
-    n = st0.shape[1]
-    kw = _subset_kw(base_kw, idx, n)
-    cm = kw.get("cm")
-    if cm is None:
-        cm = np.full(len(idx), float(model["C"]))
-    coef = kw.get("coef")
-    if coef is None:
-        coef = nominal_coef(model, len(idx))
-    kw = dict(kw, cm=cm, coef=coef)
-    s0 = st0[:, idx]
-    thr = float(model["v_th"])
-    ref = O.run(model, s0.copy(), T, record_v=True, **kw)
-    v0 = np.vstack([s0[0:1], ref["v"]])
-    base_t = _interp_times(v0, thr)
-    probes = []
-    for f in (1 + PROBE, 1 - PROBE):
-        probes += input_probes(kw, f)
-        probes.append(dict(kw, cm=cm * f))
-        for j in range(3):  # A, B, K rows of every rate
-            c2 = coef.copy()
-            c2[j::4] *= f
-            probes.append(dict(kw, coef=c2))
-    h = np.array([len(b) for b in base_t])
-    for p in probes:
-        r = O.run(model, s0.copy(), T, record_v=True, **p)
-        tt = _interp_times(np.vstack([s0[0:1], r["v"]]), thr)
-        for j, (a, b) in enumerate(zip(tt, base_t)):
-            m_ = min(len(a), len(b))
-            d = np.abs(a[:m_] - b[:m_]) > shift_tol
-            first = int(np.argmax(d)) if d.any() else m_
-            if len(a) != len(b):
-                first = min(first, m_)
-            h[j] = min(h[j], first)
-    steps = [np.nonzero(ref["spikes"][:, j])[0] for j in range(len(idx))]
-    return h, steps
+    if len(idx) == 0:
+        return np.zeros(0, np.int64), []
+    R = _Oracle(O, model, st0, T, base_kw, morph)
+    cols = R.columns(idx)
+    ref, outs = R.reference_and_probes(cols)
+    base = spike_trains(ref["spikes"])
+    h = np.array([len(b) for b in base])
+    for r in outs:
+        for j, (a, b) in enumerate(zip(spike_trains(r["spikes"]), base)):
+            h[j] = min(h[j], _first_moved(a, b))
+    pos = {c: j for j, c in enumerate(cols.tolist())}
+    sel = [pos[c] for c in idx.tolist()]
+    return h[sel], [base[j] for j in sel]
 
 
 def match_to_horizon(g_steps, o_steps, h, tol_steps=1):
@@ -214,3 +219,50 @@ def match_to_horizon(g_steps, o_steps, h, tol_steps=1):
     if len(g_before) != h:
         return False
     return h == 0 or np.max(np.abs(g_before - o_steps[:h])) <= tol_steps
+
+
+def record_judge(label, n, excused, failures, beyond=0, extra=""):
+    JUDGE_LOG.append((label, int(n), int(excused), int(failures), int(beyond), extra))
+
+
+def judge(O, model, st0, T, g, ro, kw, *, max_excused_frac, v_tol=1e-3, label="", morph=None):
+    """Parity criteria for a GPU run g (dict with 'raster' [T][n] and
+    optionally 'v' [T][n]) against the oracle run ro over the same n
+    elements.  Failures are asserted empty; excused elements are counted
+    against max_excused_frac * n; the counts go to the terminal summary."""
+    n = st0.shape[1]
+    quiet_mask = ro["spikes"].sum(0) == 0
+    quiet = np.nonzero(quiet_mask)[0]
+    dv = np.zeros(n)
+    if g.get("v") is not None and len(quiet):
+        dv[quiet] = np.max(np.abs(g["v"][:, quiet] - ro["v"][:, quiet]), axis=0)
+    trace_bad = quiet[dv[quiet] > v_tol]
+    spike_bad = spike_mismatch(g["raster"], ro["spikes"])
+    # quiet in the oracle: the trace rule (a GPU spike there counts as a trace miss)
+    q_cand = np.union1d(trace_bad, np.intersect1d(spike_bad, quiet)).astype(np.int64)
+    sp_q, tr_q = ill_conditioned(O, model, st0, T, q_cand, kw, v_tol=v_tol, morph=morph)
+    q_exc = q_cand[sp_q | tr_q]
+    q_fail = q_cand[~(sp_q | tr_q)]
+    # spiking in the oracle: agreement up to the predictability horizon
+    s_cand = np.setdiff1d(spike_bad, quiet).astype(np.int64)
+    h, steps = spike_horizons(O, model, st0, T, s_cand, kw, morph=morph)
+    s_exc, s_fail = [], []
+    for j, i in enumerate(s_cand.tolist()):
+        gs = np.nonzero(g["raster"][:, i])[0]
+        (s_exc if match_to_horizon(gs, steps[j], h[j]) else s_fail).append(i)
+    fails = sorted(set(q_fail.tolist()) | set(s_fail))
+    excused = len(q_exc) + len(s_exc)
+    ok_quiet = np.setdiff1d(quiet, trace_bad)
+    rep = ("%s n=%d quiet=%d max|dV| (quiet within tol)=%.3g mV; spike-train mismatches=%d "
+           "(%d excused beyond the predictability horizon); quiet traces off=%d (%d excused as "
+           "ill-conditioned); excused=%d (cap %d); failures=%d"
+           % (label, n, len(quiet), float(dv[ok_quiet].max()) if len(ok_quiet) else 0.0,
+              len(spike_bad), len(s_exc), len(q_cand), len(q_exc), excused,
+              int(max_excused_frac * n), len(fails)))
+    print(rep, flush=True)
+    record_judge(label, n, excused, len(fails), len(s_exc),
+                 "cap %d" % int(max_excused_frac * n))
+    detail = [(int(i), float(dv[i])) for i in fails[:10]]
+    assert not fails, (rep, detail)
+    assert excused <= max_excused_frac * n, rep
+    return rep

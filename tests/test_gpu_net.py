@@ -136,6 +136,9 @@ def test_network_spike_exact_to_horizon(n, fan, T):
     g = _net_gpu(m, csr, scale, v0, T, ext=ext)
     h, ref = _horizon(m, csr, scale, v0, T, ext)
     assert ref.sum() > 5 * n * T * 1e-4  # the network is active (> 5 Hz)
+    # the comparison must cover most of the run: on these networks the
+    # oracle's raster is unchanged by the probes for all T steps
+    assert h >= 0.9 * T, h
     upto = max(h - 1, 0)
     bad = spike_mismatch(g["raster"][:upto], ref[:upto])
     print("horizon %d of %d steps, spikes %d, mismatched neurons before horizon %d"

@@ -1006,3 +1006,162 @@ def test_sine_input_exact_period_and_one_step(ora):
         ora.run(m, st, 1, t0=t0, sine=(amp, freq), record_spikes=False)
         want = [ora.sine(a, ora.sine_rate(fq, 1.0), t0) for a, fq in zip(amp, freq)]
         assert np.array_equal(st[0], want)
+
+
+# --------------------------------------------------------------------------
+# per-element overrides: rate coefficients, capacitance, noise element ids
+# (Methods, Eq. (1) and "Flexibility and extensibility": every rate function
+# is a parameterized form whose coefficients may differ per neuron).  Each
+# override is pinned against the model-dictionary path it replaces, so a
+# layout slip in the [G*8][n] coefficient table (row g*8 + r*4 + j, stride
+# n), in the [n] capacitance array or in the noise keys would show here.
+# --------------------------------------------------------------------------
+def _override_models():
+    return [("classic", W.classic_hh(dt=0.02)), ("cortical", W.custom_channels(dt=0.025)),
+            ("cortical-ee", W.custom_channels(dt=0.05, v_method="ee"))]
+
+
+def _with_rates(model, vec):
+    """A copy of model whose rate coefficients are vec [G*8] (g*8 + r*4 + j)."""
+    import copy
+    m = copy.deepcopy(model)
+    for g, gate in enumerate(m["gates"]):
+        gate["rates"] = [tuple([rt[0]] + [float(vec[g * 8 + r * 4 + j]) for j in range(4)])
+                         for r, rt in enumerate(gate["rates"])]
+    return m
+
+
+@pytest.mark.parametrize("name", ["classic", "cortical", "cortical-ee"])
+def test_coef_table_of_nominal_values_is_the_model(ora, name):
+    m = dict(_override_models())[name]
+    n, T = 6, 1200
+    nom = W.coef_table(m)
+    tiled = np.repeat(nom[:, None], n, axis=1)
+    v0 = np.linspace(-72.0, -58.0, n)
+    a = ora.init_state(m, v0)
+    b = ora.init_state(m, v0, coef=tiled)
+    assert np.array_equal(a, b)
+    ra = ora.run(m, a, T, noise_mu=6.0, noise_sigma=3.0, seed=4, record_v=True)
+    rb = ora.run(m, b, T, noise_mu=6.0, noise_sigma=3.0, seed=4, coef=tiled, record_v=True)
+    assert np.array_equal(ra["v"], rb["v"]) and np.array_equal(a, b)
+    assert ra["spikes"].sum() > 0
+
+
+@pytest.mark.parametrize("name", ["classic", "cortical", "cortical-ee"])
+def test_jittered_coef_columns_equal_models_with_those_rates(ora, name):
+    """Every neuron of a jittered population runs exactly as a one-neuron
+    model whose rate functions carry that neuron's coefficients."""
+    m = dict(_override_models())[name]
+    n, T = 5, 1000
+    coef = W.jitter_coef(m, n, seed=13).astype(np.float64)
+    v0 = np.linspace(-70.0, -60.0, n)
+    st = ora.init_state(m, v0, coef=coef)
+    ids = np.array([3, 0, 9, 4, 1])
+    r = ora.run(m, st, T, noise_mu=5.5, noise_sigma=3.0, seed=8, coef=coef, ids=ids, record_v=True)
+    for i in range(n):
+        mi = _with_rates(m, coef[:, i])
+        si = ora.init_state(mi, v0[i:i + 1])
+        ri = ora.run(mi, si, T, noise_mu=5.5, noise_sigma=3.0, seed=8, ids=ids[i:i + 1],
+                     record_v=True)
+        assert np.array_equal(ri["v"][:, 0], r["v"][:, i]), i
+        assert np.array_equal(si[:, 0], st[:, i]), i
+
+
+def test_each_coef_row_is_the_coefficient_it_names(ora):
+    """Changing one entry (g, r, j) of one neuron's column changes that run
+    exactly as changing coefficient j of rate r of gate g in the model, and
+    leaves the other neurons bit-identical; entries a form does not read
+    (c of every form but the bell) change nothing."""
+    m = W.custom_channels(dt=0.025)
+    G = len(m["gates"])
+    n, T, i = 3, 600, 1
+    nom = W.coef_table(m)
+    v0 = np.array([-64.0, -61.0, -67.0])
+    base = ora.run(m, ora.init_state(m, v0), T, noise_mu=5.0, noise_sigma=3.0, seed=2,
+                   record_v=True)["v"]
+    for g in range(G):
+        for r in range(2):
+            form = m["gates"][g]["rates"][r][0]
+            for j in range(4):
+                row = g * 8 + r * 4 + j
+                coef = np.repeat(nom[:, None], n, axis=1)
+                coef[row, i] = nom[row] * 1.05 if nom[row] != 0 else 0.5
+                st = ora.init_state(m, v0, coef=coef)
+                got = ora.run(m, st, T, noise_mu=5.0, noise_sigma=3.0, seed=2, coef=coef,
+                              record_v=True)["v"]
+                vec = nom.copy()
+                vec[row] = coef[row, i]
+                mi = _with_rates(m, vec)
+                want = ora.run(mi, ora.init_state(mi, v0[i:i + 1]), T, noise_mu=5.0,
+                               noise_sigma=3.0, seed=2, ids=[i], record_v=True)["v"][:, 0]
+                assert np.array_equal(got[:, i], want), (g, r, j)
+                others = [k for k in range(n) if k != i]
+                assert np.array_equal(got[:, others], base[:, others]), (g, r, j)
+                if j == 3 and form != "bell":
+                    assert np.array_equal(got[:, i], base[:, i]), (g, r, j)
+                else:
+                    assert not np.array_equal(got[:, i], base[:, i]), (g, r, j)
+
+
+def test_cm_array_equals_models_with_that_capacitance(ora):
+    m = W.custom_channels(dt=0.025)
+    n, T = 4, 1500
+    v0 = np.full(n, -65.0)
+    I = np.array([4.0, 6.0, 8.0, 10.0])
+    a = ora.run(m, ora.init_state(m, v0), T, i_const=I, record_v=True)
+    b = ora.run(m, ora.init_state(m, v0), T, i_const=I, cm=np.full(n, m["C"]), record_v=True)
+    assert np.array_equal(a["v"], b["v"])
+    cm = np.array([0.7, 1.0, 1.3, 0.85])
+    c = ora.run(m, ora.init_state(m, v0), T, i_const=I, cm=cm, record_v=True)
+    for i in range(n):
+        mi = dict(m, C=float(cm[i]))
+        ri = ora.run(mi, ora.init_state(mi, v0[i:i + 1]), T, i_const=I[i:i + 1], record_v=True)
+        assert np.array_equal(ri["v"][:, 0], c["v"][:, i]), i
+    assert not np.array_equal(c["v"][:, 0], a["v"][:, 0])
+
+
+def test_noise_ids_select_each_elements_own_stream(ora):
+    """A subset or permutation of neurons run with their ids follows exactly
+    the columns of the full population; the drawn input of element id at
+    step t is noise(seed, id, t)."""
+    m = W.classic_hh(dt=0.02)
+    n, T = 12, 900
+    v0 = np.linspace(-70.0, -60.0, n)
+    full = ora.run(m, ora.init_state(m, v0), T, noise_mu=7.0, noise_sigma=4.0, seed=21,
+                   record_v=True)["v"]
+    for sel in ([7, 3, 11], [11, 10, 9, 8, 7, 6, 5, 4, 3, 2, 1, 0], [5]):
+        sel = np.array(sel)
+        sub = ora.run(m, ora.init_state(m, v0[sel]), T, noise_mu=7.0, noise_sigma=4.0, seed=21,
+                      ids=sel, record_v=True)["v"]
+        assert np.array_equal(sub, full[:, sel]), sel
+    # without ids, element i draws the stream of id i: a shifted subset differs
+    shifted = ora.run(m, ora.init_state(m, v0[[7]]), T, noise_mu=7.0, noise_sigma=4.0, seed=21,
+                      record_v=True)["v"]
+    assert not np.array_equal(shifted[:, 0], full[:, 7])
+    # one step of a bare element (no gates, C = dt = 1, V0 = 0) reports the input
+    bare = {"gates": [], "channels": [], "C": 1.0, "dt": 1.0, "v_th": 1e9, "v_method": "fe",
+            "syn": None}
+    ids = np.array([17, 2, 40000])
+    for t0 in (0, 5):
+        s = np.zeros((1, 3))
+        ora.run(bare, s, 1, t0=t0, noise_mu=0.0, noise_sigma=1.0, seed=9, ids=ids)
+        assert np.array_equal(s[0], [ora.noise(9, int(k), t0) for k in ids])
+
+
+def test_cable_ids_and_coef_select_each_elements_own_run(ora):
+    """The multi-compartment run takes the same element ids and coefficient
+    columns: a subset of neurons with their ids and coefficient columns
+    follows the full population."""
+    m = W.classic_hh(dt=0.02)
+    morph = W.soma_dendrites(m, n_dend=1, per_dend=3)
+    K = morph["K"]
+    N, T = 3, 700
+    n = N * K
+    coef = W.jitter_coef(m, n, seed=3).astype(np.float64)
+    v0 = np.full(n, -65.0)
+    full = ora.cable_run(m, ora.init_state(m, v0, coef=coef), T, morph, noise_mu=3.0,
+                         noise_sigma=3.0, seed=5, coef=coef, record_v=True)["v"]
+    sel = np.arange(K, 2 * K)  # the middle neuron
+    sub = ora.cable_run(m, ora.init_state(m, v0[sel], coef=coef[:, sel]), T, morph, noise_mu=3.0,
+                        noise_sigma=3.0, seed=5, coef=coef[:, sel], ids=sel, record_v=True)["v"]
+    assert np.array_equal(sub, full[:, sel])
