@@ -153,12 +153,15 @@ def bench_headline(steps, warmup, fusion=32):
     M.set_fusion(fusion)
     st = M.new_state()
     launches = (T + fusion - 1) // fusion
+    # the spike words of every step are part of the output (threshold
+    # detection, one 64-bit ballot word per wavefront and step)
+    bits = torch.zeros((T, M.words), dtype=torch.int32, device="cuda")
 
     def one_pass(ev=None):
         M.init_state(st, v0_scalar=-65.0)
         if ev:
             ev[0].record()
-        M.step_n(st, T, 0, noise=(5.0, 3.0, seed))
+        M.step_n(st, T, 0, noise=(5.0, 3.0, seed), spikes=bits)
         if ev:
             ev[1].record()
 
@@ -176,6 +179,7 @@ def bench_headline(steps, warmup, fusion=32):
     st_code, bad = M.check()
     if st_code != 0:
         raise RuntimeError("non-finite state in the benchmark (neuron %d)" % bad)
+    spikes_per_pass = int(np.bitwise_count(bits.cpu().numpy().view(np.uint32)).sum())
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     per_launch_s = kern_ms / 1e3 / launches
     slots = slots_per_update(m, noise=True)
@@ -183,6 +187,7 @@ def bench_headline(steps, warmup, fusion=32):
     peak = PEAK_LANE_OPS / 1e12
     return {
         "n": n, "T": T, "wall_s": wall, "ms_per_pass": wall / steps * 1e3,
+        "spikes_recorded_per_pass": spikes_per_pass,
         "updates_per_s": n * T * steps / wall,
         "kernel_ms_per_pass": kern_ms, "launches_per_pass": launches,
         "avg_launch_us": per_launch_s * 1e6,
@@ -426,14 +431,15 @@ def bench_network(T=10000):
     nnz = int(csr[1].shape[0])
     # barrier floor: the same grid (blocks of 512) running only the per-step
     # grid barrier, then barrier + accumulator reads
+    from paper_2601_21407_amd import probe as PR
     blocks = (n + 511) // 512
     floor = {}
     work = None
     for mode, name in ((0, "barrier_us"), (1, "barrier_plus_acc_us")):
-        work = hh.probe_barrier(100, blocks, mode, work)
+        work = PR.probe_barrier(100, blocks, mode, work)
         _sync()
         a.record()
-        work = hh.probe_barrier(T, blocks, mode, work)
+        work = PR.probe_barrier(T, blocks, mode, work)
         b.record()
         _sync()
         floor[name] = a.elapsed_time(b) / T * 1e3
@@ -779,7 +785,7 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
 # ---------------------------------------------------------------------------
 def probe_rates():
     import torch
-    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import probe as hh
     out = torch.empty(1 << 20, device="cuda")
     blocks, iters = 256 * 32, 2000
     res, ms_of = {}, {}
@@ -918,7 +924,14 @@ def main():
         "cpu_baseline": cpu,
         "parts": dict(headline_detail={k: v for k, v in head.items() if k != "roofline"}, **extra),
     }
-    print(json.dumps(line))
+    print(json.dumps(line), flush=True)
+    # free the library's models and synchronize while the HIP runtime (and a
+    # profiler attached to the process) are still up
+    import gc
+    from paper_2601_21407_amd import hh
+    gc.collect()
+    hh._destroy_live_models()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -139,7 +139,15 @@ typedef struct {
   float* level;       /* [n] += number of steps ending with V >= v_th */
 } hh_outputs;
 
-/* Create a model for n = N * B neurons from a host descriptor (copied).
+/* Create a model for n = N * B neurons from a host descriptor (copied)
+ * (Methods, "Membrane potential and ion-channel definitions", Eq. (1): the
+ * state is V and the gate variables p; the parameters are C_m and, per
+ * channel X, gbar_X, E_X and the gates whose powers form eta_X(p); each gate
+ * carries its alpha_p / beta_p rate functions.  "Flexibility and
+ * extensibility": a channel is user-defined as a conductance plus its
+ * activation and deactivation terms, here parameterized rate forms.  The B
+ * copies are the paper's parallel simulations on one device (Results,
+ * "Cortical scale: cortex simulation").)
  * coef: nullable [n_gates*8][N] per-neuron rate coefficients, row
  * g*8 + r*4 + j holding (A, B, K, c)[j] of rate r of gate g; replaces the
  * descriptor's values.  cm: nullable [N] per-neuron C_m.  Both stay owned by
@@ -221,6 +229,12 @@ int32_t hh_init_state(hh_model* m, float* state, const float* v0, float v0_scala
 
 /* Advance `state` by n_steps steps starting at absolute step t0 (the noise
  * generator is keyed by the absolute step, so runs can be split and resumed).
+ * One step is Eq. (1) discretized as in Methods, "Simplified discretization":
+ * every gate by exponential Euler, V by explicit Euler (Eq. (2), "Analysis of
+ * C_m") or by exponential Euler, all right-hand sides at the start-of-step
+ * state; a spike is the upward crossing of v_th within the step.  Many steps
+ * are fused into one launch with the state in registers (Methods,
+ * "Engineering optimization": operator fusion).
  * With a CSR attached (hh_attach_csr) the population is a recurrent network
  * and each step also delivers that step's spikes through the synapses.
  * Errors: HH_E_SHAPE for n_steps < 0 or ckpt_every < 1 with ckpt set;
@@ -255,9 +269,11 @@ int32_t hh_set_delays(hh_model* m, const uint8_t* delay, int32_t max_delay);
 int32_t hh_set_external(hh_model* m, const uint8_t* ext_mask, uint32_t thresh, float w_ext,
                         uint64_t seed);
 
-/* One synaptic delivery outside the time loop: compacts the spiking sources
- * of `spike_bits` ([ceil(n/32)] words) and adds their synaptic increments to
- * g_e/g_i of `state`.  n_spikes_out: nullable device int32, receives the
+/* One synaptic delivery outside the time loop (Results, "Practical deployment
+ * on neuromorphic devices" and Methods, "Cerebral cortex network": spikes
+ * delivered over sparse synapses by indirect addressing into conductance
+ * synapses): compacts the spiking sources of `spike_bits` ([ceil(n/32)]
+ * words) and adds their synaptic increments to g_e/g_i of `state`.  n_spikes_out: nullable device int32, receives the
  * number of spiking sources.  Accumulation is in 64-bit fixed point
  * (2^-40 mS/cm^2), so the result does not depend on the order of arrivals. */
 int32_t hh_syn_propagate(hh_model* m, const uint32_t* spike_bits, float* state,
@@ -296,6 +312,13 @@ size_t hh_backward_workspace(const hh_model* m, int32_t ckpt_every);
  * (HH_E_NONFINITE, *first_bad = its index) or a persistent-kernel timeout
  * (HH_E_TIMEOUT).  Clears the flags. */
 int32_t hh_check(hh_model* m, int64_t* first_bad, void* stream);
+
+/* The output of the differentiable HH layer (Methods, "Gradient learning
+ * support"; the rate that hh_backward differentiates): rate[i] = level[i] / T
+ * for i < n, level as accumulated by hh_step_n over T steps (level and rate
+ * may be the same array).  Errors: HH_E_INVALID for a NULL array,
+ * HH_E_SHAPE for n < 0 or T < 1. */
+int32_t hh_level_rate(const float* level, int64_t n, int32_t T, float* rate, void* stream);
 
 /* Dense input projection of the layer in front of the neurons (the Linear
  * of the Sequential(Linear, HHNode) composition, Fig. 1e), on MFMA:

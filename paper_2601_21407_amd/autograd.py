@@ -36,7 +36,7 @@ class HHFunction(torch.autograd.Function):
         model.step_n(st, T, 0, i_dense=Ic, ckpt=ck, ckpt_every=ckpt_every, level=lv)
         ctx.save_for_backward(ck, Ic)
         ctx.model, ctx.ckpt_every, ctx.beta, ctx.has_cm = model, ckpt_every, beta, cm is not None
-        return lv * (1.0 / T)
+        return hh.level_rate(lv, T, torch.empty_like(lv))
 
     @staticmethod
     def backward(ctx, dr):

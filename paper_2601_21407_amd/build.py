@@ -1,8 +1,11 @@
-"""Build step for libhh.so (HIP, gfx950) -- compiles every source in csrc/.
+"""Build step for libhh.so (HIP, gfx950) -- compiles every source in csrc/ --
+and for libhh_probe.so, the measurement utilities in csrc/probe/ (issue-rate
+and barrier-floor probes, kept out of the product library).
 
 Run as ``python -m paper_2601_21407_amd.build``.  Each translation unit is
-compiled to an object in parallel, then linked into ``libhh.so`` next to this
-file.  Packed-FP32 instruction selection is disabled for all device code.
+compiled to an object in parallel, then linked into the libraries next to
+this file.  Packed-FP32 instruction selection is disabled for all device
+code.
 """
 from __future__ import annotations
 
@@ -16,6 +19,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhh.so")
+PROBE_LIB = os.path.join(HERE, "libhh_probe.so")
 ARCH = "gfx950"
 
 
@@ -38,21 +42,28 @@ def _compile(src: str, obj: str) -> None:
         raise RuntimeError("compile failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
 
 
-def build(verbose: bool = False) -> str:
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
-    bdir = os.path.join(HERE, "_build")
-    os.makedirs(bdir, exist_ok=True)
-    objs = [os.path.join(bdir, os.path.basename(s) + ".o") for s in srcs]
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        list(ex.map(_compile, srcs, objs))
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _link(objs, lib):
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    psrcs = sorted(glob.glob(os.path.join(CSRC, "probe", "*.hip")))
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    objs = [os.path.join(bdir, os.path.basename(s) + ".o") for s in srcs]
+    pobjs = [os.path.join(bdir, "probe_" + os.path.basename(s) + ".o") for s in psrcs]
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs) + len(psrcs))) as ex:
+        list(ex.map(_compile, srcs + psrcs, objs + pobjs))
+    _link(objs, LIB)
+    _link(pobjs, PROBE_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", PROBE_LIB)
     return LIB
 
 

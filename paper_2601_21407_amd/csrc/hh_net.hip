@@ -27,6 +27,7 @@
 
 #include <cmath>
 
+#include "hh_barrier.h"
 #include "hh_internal.h"
 
 using namespace hhk;
@@ -65,47 +66,6 @@ struct NetArgs {
   int32_t* flags;           // [0] first non-finite neuron, [1] timeout
   uint32_t spin_limit;
 };
-
-// Grid barrier over co-resident blocks on a monotonic arrival counter: the
-// g-th barrier of a launch is passed once the counter reaches
-// (g + 1) * nblocks, so nobody has to reset it and a waiting block needs
-// only the arrivals, not a second store from the last arriver.  Data
-// shared across blocks (the arrival accumulators) is only touched by
-// device-scope atomics, so most lanes need ordering, not cache maintenance:
-// every wavefront waits for its own memory operations to complete, the
-// block synchronizes, and one lane publishes the block's writes device-wide
-// (release on its arrival), polls the counter with device-scope relaxed
-// loads -- no cache invalidation per poll -- and performs one acquire fence
-// when it is complete.  Every wait is bounded: after spin_limit polls the
-// block flags a timeout, and any block that sees the flag leaves the time
-// loop, so the grid always drains.
-__device__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen, uint32_t spin_limit,
-                             int32_t* flags, int* s_ok) {
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned target = (gen + 1) * nblocks;
-    int ok = 1;
-    unsigned seen =
-        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    uint32_t spins = 0;
-    while ((int)(seen - target) < 0) {
-      if (++spins > spin_limit) {
-        ok = 0;
-        __hip_atomic_fetch_or(&flags[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-      seen = __hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (__hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-    gen = gen + 1;
-    *s_ok = ok;
-  }
-  __syncthreads();
-  return *s_ok != 0;
-}
 
 __device__ __forceinline__ void deliver_row(const int64_t* __restrict__ row_ptr,
                                             const int32_t* __restrict__ col,
@@ -386,29 +346,6 @@ __global__ void k_net_reset(unsigned* bar) {
   }
 }
 
-// ---- barrier floor (measurement) -------------------------------------------
-// The per-step synchronization of k_net without the neuron work: each step
-// is one grid barrier, plus (mode 1) the two accumulator reads-and-clears
-// per lane that follow it in k_net.  Same block size and barrier code.
-__global__ __launch_bounds__(kNetBlock) void k_barrier_floor(unsigned* bar, int32_t* flags,
-                                                             unsigned long long* acc, int n,
-                                                             int steps, int mode,
-                                                             uint32_t spin_limit) {
-  __shared__ int s_ok;
-  unsigned gen = 0;
-  const int i = blockIdx.x * kNetBlock + threadIdx.x;
-  float sink = 0.0f;
-  for (int t = 0; t < steps; ++t) {
-    if (!grid_barrier(bar, gridDim.x, gen, spin_limit, flags, &s_ok)) break;
-    if (mode == 1 && i < n) {
-      const unsigned long long* b = acc + (size_t)(t & 1) * 2 * n;
-      sink += (float)atomicExch((unsigned long long*)&b[i], 0ull);
-      sink += (float)atomicExch((unsigned long long*)&b[n + i], 0ull);
-    }
-  }
-  if (sink != 0.0f) flags[2] = 1;  // keeps the reads; never true (accumulators are zero)
-}
-
 // ---- one-shot delivery -----------------------------------------------------
 __global__ void k_zero_u32(unsigned* p, int count) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -558,40 +495,6 @@ int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_
 }
 
 extern "C" {
-
-size_t hh_probe_barrier_bytes(int32_t blocks) {
-  if (blocks < 1) return 0;
-  return 256 + (size_t)4 * blocks * kNetBlock * sizeof(unsigned long long);
-}
-
-int32_t hh_probe_barrier(int32_t steps, int32_t blocks, int32_t mode, void* work,
-                         size_t work_bytes, void* stream) {
-  if (steps < 1 || blocks < 1 || (mode != 0 && mode != 1) || !work) return HH_E_INVALID;
-  if (work_bytes < hh_probe_barrier_bytes(blocks)) return HH_E_SHAPE;
-  int dev = 0, ncu = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_barrier_floor, kNetBlock, 0) !=
-          hipSuccess)
-    return HH_E_HIP;
-  if (blocks > ncu * per_cu) return HH_E_UNSUPPORTED;
-  hipStream_t s = (hipStream_t)stream;
-  unsigned* bar = (unsigned*)work;
-  int32_t* flags = (int32_t*)((char*)work + 64);
-  unsigned long long* acc = (unsigned long long*)((char*)work + 256);
-  const int n = blocks * kNetBlock;
-  const int words = (int)(hh_probe_barrier_bytes(blocks) / 4);
-  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s,
-                     (unsigned*)work, words);
-  uint32_t spin = 1u << 24;
-  void* args[] = {(void*)&bar, (void*)&flags, (void*)&acc, (void*)&n, (void*)&steps, (void*)&mode,
-                  (void*)&spin};
-  if (hipLaunchCooperativeKernel((const void*)k_barrier_floor, dim3((unsigned)blocks),
-                                 dim3(kNetBlock), args, 0, s) != hipSuccess)
-    return HH_E_HIP;
-  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
-}
-
 
 int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, const float* w,
                       int64_t nnz, float w_scale) {

@@ -153,9 +153,25 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
   }
 }
 
+__global__ __launch_bounds__(256) void k_level_rate(const float* __restrict__ level, int64_t n,
+                                                    float invT, float* __restrict__ rate) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) rate[i] = level[i] * invT;
+}
+
 }  // namespace
 
 extern "C" {
+
+int32_t hh_level_rate(const float* level, int64_t n, int32_t T, float* rate, void* stream) {
+  if (!level || !rate) return HH_E_INVALID;
+  if (n < 0 || T < 1) return HH_E_SHAPE;
+  if (n == 0) return HH_OK;
+  // the readout kernels scale the level by the same binary32 1/T
+  hipLaunchKernelGGL(k_level_rate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, level, n, 1.0f / (float)T, rate);
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
 
 size_t hh_readout_ce_workspace(int32_t B, int32_t C) {
   if (B < 1 || C < 1) return 0;

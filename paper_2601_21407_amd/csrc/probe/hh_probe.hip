@@ -8,7 +8,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/hh_probe.h"
+#include "../../../include/hh_probe.h"
 
 namespace {
 

@@ -7,8 +7,10 @@ raises -- there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -99,10 +101,8 @@ def _load():
         "hh_proj_wgrad_bits": ([vp, i32, vp, vp, i32, i32, i32, i32, vp, sz, vp], i32),
         "hh_readout_ce": ([vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "hh_readout_ce_workspace": ([i32, i32], sz),
+        "hh_level_rate": ([vp, i64, i32, vp, vp], i32),
         "hh_adam_step": ([vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp], i32),
-        "hh_probe_issue": ([i32, i32, i32, vp, i32, vp], i32),
-        "hh_probe_barrier_bytes": ([i32], sz),
-        "hh_probe_barrier": ([i32, i32, i32, vp, sz, vp], i32),
         "hh_mlp_grad": ([vp, vp, vp, i32, i32, vp, vp, vp, sz, vp], i32),
         "hh_mlp_grad_workspace": ([i32], sz),
         "hh_mlp_forward": ([vp, vp, i32, i32, vp, vp], i32),
@@ -133,6 +133,7 @@ def exported_symbols():
                         "hh_proj_forward", "hh_proj_forward_bits", "hh_proj_wgrad",
                         "hh_proj_wgrad_workspace", "hh_proj_wgrad_bits",
                         "hh_readout_ce", "hh_readout_ce_workspace", "hh_adam_step",
+                        "hh_level_rate",
                         "hh_mlp_grad", "hh_mlp_grad_workspace", "hh_mlp_forward", "hh_mlp_pack",
                         "hh_mlp_packed_bytes", "hh_mlp_infer", "hh_surrogate_step_n")]
 
@@ -182,6 +183,41 @@ def desc_from_model(model: dict) -> ModelDesc:
     return d
 
 
+def _need(t, what, dtype, min_numel, exact=False):
+    """A device tensor argument of the given dtype with at least (or, with
+    exact, exactly) min_numel elements: the library writes or reads that many
+    and cannot check the size behind a raw pointer itself."""
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError("%s: expected a device tensor" % what)
+    if t.dtype not in dtype:
+        raise ValueError("%s: expected dtype %s, got %s" % (what, dtype, t.dtype))
+    if (t.numel() != min_numel) if exact else (t.numel() < min_numel):
+        raise ValueError("%s: expected %s%d elements, got %d"
+                         % (what, "" if exact else "at least ", min_numel, t.numel()))
+
+
+_F32 = (torch.float32,)
+_I32 = (torch.int32,)
+
+# models still alive at interpreter exit are destroyed by an exit hook that
+# runs before torch's and the HIP runtime's own teardown (a profiler attached
+# to the process has finalized by the time late finalizers would run)
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _destroy_live_models():
+    try:
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for m in list(_LIVE):
+        m.close()
+
+
 class Model:
     """A population of n = N * B HH neurons on the current device."""
 
@@ -190,11 +226,21 @@ class Model:
         self.N, self.B, self.n = int(N), int(B), int(N) * int(B)
         self._keep = [coef, cm]  # the library reads these for the model's lifetime
         self.desc = desc if desc is not None else desc_from_model(model)
+        G = len(model["gates"]) if desc is None else int(self.desc.n_gates)
+        _need(coef, "coef", _F32, G * 8 * self.N, exact=True)
+        _need(cm, "cm", _F32, self.N, exact=True)
         h = ctypes.c_void_p()
         _ok(lib.hh_init(ctypes.byref(h), ctypes.byref(self.desc), self.N, self.B, _ptr(coef),
                         _ptr(cm)), "hh_init")
         self.h = h
         self.n_state = lib.hh_n_state(self.h)
+        _LIVE.add(self)
+
+    def close(self, _destroy=lib.hh_destroy):
+        """Free the library's model now (also done when the object goes)."""
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
 
     # the library is bound as a default argument: at interpreter exit the
     # module's globals may already be cleared when the last models go
@@ -241,6 +287,18 @@ class Model:
                background=None, sine=None):
         """noise = (mu, sigma, seed); background = (lam, mu, sigma, seed);
         sine = (amplitudes [n], frequencies [n] in Hz), device tensors."""
+        n, T = self.n, max(int(n_steps), 0)
+        _need(state, "state", _F32, self.n_state * n, exact=True)
+        _need(spikes, "spikes", _I32, T * self.words)
+        _need(v_rec, "v_rec", _F32, T * n)
+        _need(i_dense, "i_dense", _F32, T * n)
+        _need(i_const, "i_const", _F32, n)
+        _need(level, "level", _F32, n)
+        if ckpt is not None:
+            _need(ckpt, "ckpt", _F32, -(-T // max(int(ckpt_every), 1)) * self.n_state * n)
+        if sine is not None:
+            _need(sine[0], "sine amplitudes", _F32, n)
+            _need(sine[1], "sine frequencies", _F32, n)
         inp = Input()
         if i_dense is not None:
             inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
@@ -281,11 +339,22 @@ class Model:
         _ok(lib.hh_syn_propagate(self.h, _ptr(spike_bits), _ptr(state), _ptr(n_spikes), _stream()),
             "hh_syn_propagate")
 
+    def _check_backward(self, ckpt, ckpt_every, i_dense, T, dI, dL_dlevel, dL_dV, dCm, dx0):
+        n, T = self.n, max(int(T), 0)
+        _need(ckpt, "ckpt", _F32, -(-T // max(int(ckpt_every), 1)) * self.n_state * n)
+        _need(i_dense, "i_dense", _F32, T * n)
+        _need(dI, "dI", _F32, T * n)
+        _need(dL_dlevel, "dL_dlevel", _F32, n)
+        _need(dL_dV, "dL_dV", _F32, T * n)
+        _need(dCm, "dCm", _F32, self.N)
+        _need(dx0, "dx0", _F32, self.n_state * n)
+
     def backward_workspace(self, ckpt_every: int) -> int:
         return int(lib.hh_backward_workspace(self.h, int(ckpt_every)))
 
     def backward(self, ckpt, ckpt_every: int, i_dense, T: int, dI, *, dL_dlevel=None, dL_dV=None,
                  beta: float = 0.2, dCm=None, dx0=None, workspace=None):
+        self._check_backward(ckpt, ckpt_every, i_dense, T, dI, dL_dlevel, dL_dV, dCm, dx0)
         inp = Input()
         inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
         ws_bytes = self.backward_workspace(ckpt_every)
@@ -300,6 +369,7 @@ class Model:
                       dx0=None):
         """The adjoint over steps [t_lo, t_hi) (see hh_backward_part); calls go
         backwards over adjacent ranges and share `workspace`."""
+        self._check_backward(ckpt, ckpt_every, i_dense, T, dI, dL_dlevel, dL_dV, dCm, dx0)
         inp = Input()
         inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
         ws_bytes = self.backward_workspace(ckpt_every)
@@ -314,28 +384,6 @@ class Model:
         fb = ctypes.c_int64(-1)
         st = lib.hh_check(self.h, ctypes.byref(fb), _stream())
         return st, fb.value
-
-
-PROBE_OPS = {"fma": 0, "exp2": 1, "rcp": 2, "sqrt": 3, "sin": 4, "mul64": 5, "mix": 6,
-             "pkfma16": 7, "exp16": 8, "mfma16": 9, "mfma16_valu": 10}
-
-
-def probe_issue(op: str, iters: int, blocks: int, out):
-    """Launch the issue-rate probe (include/hh_probe.h); blocks * 256 * 8 *
-    iters operations of kind `op`."""
-    _ok(lib.hh_probe_issue(PROBE_OPS[op], int(iters), int(blocks), _ptr(out), int(out.numel()),
-                           _stream()), "hh_probe_issue")
-
-
-def probe_barrier(steps: int, blocks: int, mode: int, work=None):
-    """Launch the barrier-floor probe (include/hh_probe.h); returns the work
-    buffer for reuse."""
-    need = int(lib.hh_probe_barrier_bytes(int(blocks)))
-    if work is None or work.numel() < need:
-        work = torch.empty(need, dtype=torch.uint8, device="cuda")
-    _ok(lib.hh_probe_barrier(int(steps), int(blocks), int(mode), _ptr(work), work.numel(), _stream()),
-        "hh_probe_barrier")
-    return work
 
 
 def proj_forward(A_bf16, Wt_bf16, out):
@@ -413,6 +461,15 @@ def readout_ce(level, T: int, W, bias, labels, dlevel, dW, db, loss, logits=None
     _ok(lib.hh_readout_ce(_ptr(level), int(T), _ptr(W), _ptr(bias), _ptr(labels), B, H, C,
                           _ptr(loss), _ptr(dlevel), _ptr(dW), _ptr(db), _ptr(logits),
                           _ptr(workspace), workspace.numel(), _stream()), "hh_readout_ce")
+
+
+def level_rate(level, T: int, rate):
+    """rate = level / T (the differentiable layer's output)."""
+    _need(level, "level", _F32, rate.numel())
+    _need(rate, "rate", _F32, level.numel(), exact=True)
+    _ok(lib.hh_level_rate(_ptr(level), rate.numel(), int(T), _ptr(rate), _stream()),
+        "hh_level_rate")
+    return rate
 
 
 def adam_step(param, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,

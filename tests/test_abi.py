@@ -10,9 +10,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    import glob
-    txt = "".join(open(f).read() for f in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
+def _declared(header="hh.h"):
+    txt = open(os.path.join(ROOT, "include", header)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(hh_[a-z0-9_]+)\s*\(", txt)))
 
@@ -30,6 +29,19 @@ def test_library_exports_every_declared_symbol():
     for nm in names:
         assert hasattr(hh.lib, nm), nm
     assert set(hh.exported_symbols()) <= set(names)
+
+
+def test_probe_library_is_separate():
+    """The measurement probes (include/hh_probe.h) live in libhh_probe.so,
+    not in the product library."""
+    hh = _lib()
+    from paper_2601_21407_amd import probe
+    names = _declared("hh_probe.h")
+    assert names == ["hh_probe_barrier", "hh_probe_barrier_bytes", "hh_probe_issue"]
+    for nm in names:
+        assert hasattr(probe.lib, nm), nm
+        with pytest.raises(AttributeError):
+            getattr(hh.lib, nm)
 
 
 def test_struct_sizes_match_header_layout():
