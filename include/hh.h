@@ -176,9 +176,10 @@ int32_t hh_set_specialize(hh_model* m, int32_t on);
  * approximations).  The gate update p' = p + (p_inf - p) q, q = 1 - e
  * (exponential Euler, "Simplified discretization") then takes p_inf(V) and
  * q(V) by linear interpolation between n_nodes equally spaced voltages from
- * v_lo to v_hi (mV), tabulated once from the model's rate functions on the
- * device (q without cancellation); V outside [v_lo, v_hi] is clamped to the
- * range.  The membrane update is unchanged.  The table (n_gates x n_nodes x
+ * v_lo to v_hi (mV), tabulated once on the device from the model's rate
+ * functions in binary64 (q = -expm1(-dt (alpha + beta)), without
+ * cancellation) and rounded once per entry; V outside [v_lo, v_hi] is
+ * clamped to the range.  The membrane update is unchanged.  The table (n_gates x n_nodes x
  * 16 bytes) is owned by the model and used by every later hh_step_n;
  * n_nodes = 0 removes it.  Errors: HH_E_SHAPE for n_nodes outside [2, 2^20];
  * HH_E_INVALID for v_hi <= v_lo or non-finite bounds; HH_E_UNSUPPORTED unless

@@ -335,34 +335,48 @@ __global__ __launch_bounds__(TAB == TAB_LDS ? 512 : 256) void k_step(KModel M, S
 }
 
 // Table of the gate kinetics at nodes V_i = v_lo + i h (one lane per gate and
-// node), from the same rate functions as the step: P = p_inf and Q = 1 - e,
-// with 1 - e taken without cancellation (e is close to 1 for slow gates).
-template <class S>
-__global__ __launch_bounds__(256) void k_build_table(KModel M, float v_lo, float h, int n,
-                                                     float4* __restrict__ tab) {
-  constexpr int NG = S::kNG;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= NG * n) return;
-  const int g = x / n, i = x % n;
-  float P[2], Q[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const float V = v_lo + (float)min(i + j, n - 1) * h;
-    const float r0 = rate_eval<false>(S::form(M, g, 0), M.rate[g][0], V, nullptr);
-    const float r1 = rate_eval<false>(S::form(M, g, 1), M.rate[g][1], V, nullptr);
-    const float s = S::kind(M, g) == KIND_AB ? r0 + r1 : r1;  // 1 / tau
-    P[j] = S::kind(M, g) == KIND_AB ? r0 / s : r0;
-    Q[j] = -expm1_neg(M.dt * s);
+// node): P = p_inf and Q = 1 - e = -expm1(-dt (alpha + beta)) (or dt / tau),
+// evaluated in binary64 from the descriptor's coefficients and rounded once
+// per entry, so the nodes carry no error of the step's binary32 rate
+// arithmetic (node errors act coherently on every visit of the interval).
+struct TabDesc {
+  int32_t n_gates;
+  int32_t kind[kMaxGates];
+  int32_t form[kMaxGates][2];
+  double A[kMaxGates][2], B[kMaxGates][2], K[kMaxGates][2], c[kMaxGates][2];
+  double dt;
+};
+
+__device__ double rate64(int form, double A, double B, double K, double c, double V) {
+  const double u = (V - B) / K;
+  switch (form) {
+    case FORM_EXP: return A * exp(u);
+    case FORM_SIGMOID: return A / (1.0 + exp(u));
+    case FORM_LINOID: {
+      // A (V - B) / (1 - e^{-u}) = A K u / (-expm1(-u)); value A K at u = 0
+      const double g = fabs(u) < 1e-12 ? 1.0 + 0.5 * u : u / -expm1(-u);
+      return A * K * g;
+    }
+    default: return (c * exp(u) + exp(-u)) / A;  // FORM_BELL
   }
-  tab[x] = make_float4(P[0], P[1] - P[0], Q[0], Q[1] - Q[0]);
 }
 
-template <class S>
-static hipError_t table_spec(const hh_model* m, hipStream_t s) {
-  const int count = S::kNG * m->tab_n;
-  hipLaunchKernelGGL(k_build_table<S>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, m->km,
-                     m->tab_vlo, m->tab_h, m->tab_n, m->d_tab);
-  return hipGetLastError();
+__global__ __launch_bounds__(256) void k_build_table(TabDesc D, double v_lo, double h, int n,
+                                                     float4* __restrict__ tab) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= D.n_gates * n) return;
+  const int g = x / n, i = x % n;
+  double P[2], Q[2];
+  for (int j = 0; j < 2; ++j) {
+    const double V = v_lo + (double)min(i + j, n - 1) * h;
+    const double r0 = rate64(D.form[g][0], D.A[g][0], D.B[g][0], D.K[g][0], D.c[g][0], V);
+    const double r1 = rate64(D.form[g][1], D.A[g][1], D.B[g][1], D.K[g][1], D.c[g][1], V);
+    const bool ab = D.kind[g] == KIND_AB;
+    const double s = ab ? r0 + r1 : r1;  // alpha + beta, or 1 / tau
+    P[j] = ab ? r0 / s : r0;
+    Q[j] = -expm1(-D.dt * s);
+  }
+  tab[x] = make_float4((float)P[0], (float)(P[1] - P[0]), (float)Q[0], (float)(Q[1] - Q[0]));
 }
 
 template <class S>
@@ -449,13 +463,6 @@ struct InitF {
   }
 };
 template <class S>
-struct TableF {
-  static hipError_t run(const hh_model* m, hipStream_t s) {
-    if constexpr (S::kFixed) return table_spec<S>(m, s);
-    return hipErrorInvalidValue;  // tables are set only for the built-in sets
-  }
-};
-template <class S>
 struct StepF {
   static hipError_t run(const hh_model* m, const StepArgs& a, hipStream_t s) {
     return step_spec<S>(m, a, s);
@@ -473,5 +480,23 @@ hipError_t launch_step(const hh_model* m, const StepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_build_table(const hh_model* m, hipStream_t s) {
-  return dispatch_spec<TableF, const hh_model*, hipStream_t>(m->km, true, m, s);
+  TabDesc D = {};
+  const hh_model_desc& d = m->desc;
+  D.n_gates = d.n_gates;
+  for (int g = 0; g < d.n_gates; ++g) {
+    D.kind[g] = d.gates[g].kind;
+    for (int r = 0; r < 2; ++r) {
+      const hh_rate& q = d.gates[g].r[r];
+      D.form[g][r] = q.form;
+      D.A[g][r] = q.A;
+      D.B[g][r] = q.B;
+      D.K[g][r] = q.K;
+      D.c[g][r] = q.c;
+    }
+  }
+  D.dt = d.dt;
+  const int count = d.n_gates * m->tab_n;
+  hipLaunchKernelGGL(k_build_table, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, D,
+                     (double)m->tab_vlo, (double)m->tab_h, m->tab_n, m->d_tab);
+  return hipGetLastError();
 }

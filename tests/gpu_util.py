@@ -4,19 +4,26 @@ The parity judge follows the stated tolerance: non-spiking traces within
 1e-3 mV of the FP64 oracle at every step, spike trains equal in count with
 every spike within one dt.  A neuron is excused (counted and reported, not
 failed) only where the oracle's own result is not determined to that
-tolerance by FP32-sized perturbations, established with two probes of the
+tolerance by FP32-sized perturbations, established with probes of the
 oracle:
   - the input current scaled by (1 +- 1e-6) (for background input: its
     amplitudes; for sine input: its amplitude), and
-  - the same FP64 steps with the state rounded to binary32 before every step
-    (what any FP32 integrator must at least incur).
+  - the same FP64 steps with the state stored in binary32 after every step
+    (what any integrator with binary32 state incurs), in four realizations
+    of that rounding noise: round to nearest, and three seeded stochastic
+    roundings (the unbiased model of rounding noise).  The deviation such
+    storage causes is a random quantity whose spread over realizations is
+    large on near-threshold traces under random drive; one realization
+    alone understates it.
 A quiet trace is excused when an input probe moves it by more than the
-tolerance, or the FP32-state run by more than half of it (or either makes it
-spike).  A spike train is compared up to its predictability horizon: the
-first spike that one of the probes moves by more than one step (or a change
-of count); before the horizon the GPU must match within one step and have no
-other spike.  Every excusal is recorded and the counts are printed in the
-pytest terminal summary.
+tolerance, or a binary32-state run by more than half of it (stochastic
+roundings, whose per-step noise variance is twice that of rounding to
+nearest, by more than half of it over sqrt(2)), or any of them makes it
+spike.  A spike train is compared up to its predictability horizon: the
+first spike that one of the probes moves by more than one step (or a
+change of count); before the horizon the GPU must match within one step
+and have no other spike.  Every excusal is recorded and the counts are
+printed in the pytest terminal summary.
 """
 import numpy as np
 import pytest
@@ -54,6 +61,21 @@ def print_case(msg: str):
 
 
 PROBE = 1e-6
+SR_SEEDS = (101, 202, 303)
+
+
+def stochastic_round(x, rng):
+    """x (float64 array) rounded to one of its two neighbouring binary32
+    values, the upper one with probability proportional to the distance from
+    the lower one (unbiased); values that binary32 holds stay unchanged."""
+    x = np.asarray(x, np.float64)
+    r = x.astype(np.float32)
+    lo = np.where(r.astype(np.float64) > x, np.nextafter(r, np.float32(-np.inf)), r)
+    hi = np.nextafter(lo, np.float32(np.inf))
+    lo64, hi64 = lo.astype(np.float64), hi.astype(np.float64)
+    span = hi64 - lo64
+    p = np.divide(x - lo64, span, out=np.zeros_like(x), where=span > 0)
+    return np.where(rng.random(x.shape) < p, hi64, lo64)
 
 
 def nominal_coef(model, count):
@@ -125,7 +147,7 @@ class _Oracle:
 
     def reference_and_probes(self, cols):
         """(reference, [probe results]) for elements cols: the input probes
-        and the FP32-state run."""
+        and the binary32-state runs."""
         kw = _subset(self.kw, cols, self.n)
         s0 = np.ascontiguousarray(self.st0[:, cols])
         ref = self.run(s0.copy(), self.T, **kw)
@@ -134,9 +156,15 @@ class _Oracle:
             for p in input_probes(kw, f):
                 outs.append(self.run(s0.copy(), self.T, **p))
         outs.append(self.fp32_state_run(s0, kw))
+        for seed in SR_SEEDS:
+            outs.append(self.fp32_state_run(s0, kw, sr_seed=seed))
         return ref, outs
 
-    def fp32_state_run(self, s0, kw):
+    def fp32_state_run(self, s0, kw, sr_seed=None):
+        """The oracle's steps with the state stored in binary32 after each
+        step: rounded to nearest, or stochastically rounded with a seeded
+        generator when sr_seed is given."""
+        rng = None if sr_seed is None else np.random.default_rng(sr_seed)
         s = s0.astype(np.float32).astype(np.float64)
         T = self.T
         vr = np.zeros((T, s.shape[1]))
@@ -147,10 +175,10 @@ class _Oracle:
         for k in range(T):
             extra = {} if dense is None else {"i_dense": dense[k:k + 1]}
             r = self.run(s, 1, t0=t0 + k, **kw1, **extra)
-            s[:] = s.astype(np.float32).astype(np.float64)
+            s[:] = s.astype(np.float32).astype(np.float64) if rng is None else stochastic_round(s, rng)
             vr[k] = r["v"][0]
             spk[k] = r["spikes"][0]
-        return {"v": vr, "spikes": spk, "fp32": True}
+        return {"v": vr, "spikes": spk, "fp32": "rn" if rng is None else "sr"}
 
 
 def _first_moved(a, b):
@@ -180,7 +208,8 @@ def ill_conditioned(O, model, st0, T, idx, base_kw, *, v_tol=1e-3, morph=None):
     tr = np.zeros(len(cols), bool)
     for r in outs:
         sp[spike_mismatch(r["spikes"], ref["spikes"])] = True
-        tol = 0.5 * v_tol if r.get("fp32") else v_tol
+        kind = r.get("fp32")
+        tol = v_tol if not kind else (0.5 * v_tol if kind == "rn" else 0.5 * v_tol / np.sqrt(2.0))
         tr |= np.max(np.abs(r["v"] - ref["v"]), axis=0) > tol
     pos = {c: j for j, c in enumerate(cols.tolist())}
     sel = np.array([pos[c] for c in idx.tolist()], dtype=np.int64)
