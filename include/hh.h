@@ -370,6 +370,20 @@ int32_t hh_readout_ce(const float* level, int32_t T, const float* W, const float
                       float* dlevel, float* dW, float* db, float* logits, void* workspace,
                       size_t workspace_bytes, void* stream);
 size_t hh_readout_ce_workspace(int32_t B, int32_t C);
+/* hh_readout_ce for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the scratch (dz [B][C] and
+ * the row losses [B]) in a static device array of
+ * HH_READOUT_NOALLOC_MAX_FLOATS floats (1 MiB) that each GPU the library runs
+ * on holds until the process ends.  The call allocates nothing.  All calls on
+ * one GPU share that array, so calls that overlap on one GPU (several streams
+ * or threads) race; calls in stream order do not.  Errors as hh_readout_ce,
+ * and HH_E_SHAPE for B * (C + 1) > HH_READOUT_NOALLOC_MAX_FLOATS (nothing
+ * launched). */
+#define HH_READOUT_NOALLOC_MAX_FLOATS 262144
+int32_t hh_readout_ce_noalloc(const float* level, int32_t T, const float* W, const float* bias,
+                              const int32_t* labels, int32_t B, int32_t H, int32_t C, float* loss,
+                              float* dlevel, float* dW, float* db, float* logits, void* stream);
 
 /* One Adam update (Kingma & Ba, 2015), step counted from 1:
  *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,

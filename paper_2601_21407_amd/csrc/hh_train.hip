@@ -7,6 +7,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/hh.h"
 
 namespace {
@@ -178,16 +180,26 @@ size_t hh_readout_ce_workspace(int32_t B, int32_t C) {
   return (size_t)B * (C + 1) * sizeof(float);
 }
 
-int32_t hh_readout_ce(const float* level, int32_t T, const float* W, const float* bias,
-                      const int32_t* labels, int32_t B, int32_t H, int32_t C, float* loss,
-                      float* dlevel, float* dW, float* db, float* logits, void* workspace,
-                      size_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+// Argument checks shared by both readout entry points (scratch aside).
+static int32_t readout_args_ok(const float* level, int32_t T, const float* W, const float* bias,
+                               const int32_t* labels, int32_t B, int32_t H, int32_t C,
+                               const float* loss, const float* dlevel, const float* dW,
+                               const float* db) {
   if (!level || !W || !bias || !labels || !loss || !dlevel || !dW || !db) return HH_E_INVALID;
   if (T < 1 || B < 1 || H < 1 || C < 1) return HH_E_SHAPE;
   if (C > kMaxC) return HH_E_UNSUPPORTED;
-  if (!workspace || workspace_bytes < hh_readout_ce_workspace(B, C)) return HH_E_SHAPE;
-  hipStream_t s = (hipStream_t)stream;
-  float* dz = (float*)workspace;
+  return HH_OK;
+}
+
+// The two readout kernels; scratch holds dz [B][C] then the row losses [B]
+// (every element used is written before it is read, so nothing is cleared).
+static int32_t readout_launch(const float* level, int32_t T, const float* W, const float* bias,
+                              const int32_t* labels, int32_t B, int32_t H, int32_t C, float* loss,
+                              float* dlevel, float* dW, float* db, float* logits, float* scratch,
+                              hipStream_t s) {
+  float* dz = scratch;
   float* row_loss = dz + (size_t)B * C;
   const float invT = 1.0f / (float)T;
   hipLaunchKernelGGL(k_readout_row, dim3(B), dim3(256), 0, s, level, invT, W, bias, labels, B, H, C,
@@ -195,6 +207,59 @@ int32_t hh_readout_ce(const float* level, int32_t T, const float* W, const float
   hipLaunchKernelGGL(k_readout_wgrad, dim3((unsigned)((H + RW_H - 1) / RW_H), (unsigned)C),
                      dim3(RW_H * RW_G), 0, s, level, invT, dz, row_loss, B, H, C, dW, db, loss);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+// Scratch of hh_readout_ce_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, taken once per device on
+// the entry point's first call there, with that device current.
+static __device__ __align__(256) float scratch[HH_READOUT_NOALLOC_MAX_FLOATS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static int32_t scratch_of_current_device(float** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return HH_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return HH_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HH_E_HIP;
+    g_scratch_ptr[dev] = (float*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HH_OK;
+}
+
+extern "C" {
+
+int32_t hh_readout_ce(const float* level, int32_t T, const float* W, const float* bias,
+                      const int32_t* labels, int32_t B, int32_t H, int32_t C, float* loss,
+                      float* dlevel, float* dW, float* db, float* logits, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+  const int32_t st = readout_args_ok(level, T, W, bias, labels, B, H, C, loss, dlevel, dW, db);
+  if (st != HH_OK) return st;
+  if (!workspace || workspace_bytes < hh_readout_ce_workspace(B, C)) return HH_E_SHAPE;
+  return readout_launch(level, T, W, bias, labels, B, H, C, loss, dlevel, dW, db, logits,
+                        (float*)workspace, (hipStream_t)stream);
+}
+
+int32_t hh_readout_ce_noalloc(const float* level, int32_t T, const float* W, const float* bias,
+                              const int32_t* labels, int32_t B, int32_t H, int32_t C, float* loss,
+                              float* dlevel, float* dW, float* db, float* logits, void* stream) {
+  const int32_t st = readout_args_ok(level, T, W, bias, labels, B, H, C, loss, dlevel, dW, db);
+  if (st != HH_OK) return st;
+  if ((int64_t)B * (C + 1) > (int64_t)HH_READOUT_NOALLOC_MAX_FLOATS) return HH_E_SHAPE;
+  float* ws = nullptr;
+  const int32_t sp = scratch_of_current_device(&ws);
+  if (sp != HH_OK) return sp;
+  return readout_launch(level, T, W, bias, labels, B, H, C, loss, dlevel, dW, db, logits, ws,
+                        (hipStream_t)stream);
 }
 
 int32_t hh_adam_step(float* param, const float* grad, float* m, float* v, int64_t count, float lr,

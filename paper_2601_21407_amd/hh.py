@@ -101,6 +101,7 @@ def _load():
         "hh_proj_wgrad_bits": ([vp, i32, vp, vp, i32, i32, i32, i32, vp, sz, vp], i32),
         "hh_readout_ce": ([vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "hh_readout_ce_workspace": ([i32, i32], sz),
+        "hh_readout_ce_noalloc": ([vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp], i32),
         "hh_level_rate": ([vp, i64, i32, vp, vp], i32),
         "hh_adam_step": ([vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp], i32),
         "hh_mlp_grad": ([vp, vp, vp, i32, i32, vp, vp, vp, sz, vp], i32),
@@ -132,7 +133,8 @@ def exported_symbols():
                         "hh_backward_workspace", "hh_check",
                         "hh_proj_forward", "hh_proj_forward_bits", "hh_proj_wgrad",
                         "hh_proj_wgrad_workspace", "hh_proj_wgrad_bits",
-                        "hh_readout_ce", "hh_readout_ce_workspace", "hh_adam_step",
+                        "hh_readout_ce", "hh_readout_ce_workspace", "hh_readout_ce_noalloc",
+                        "hh_adam_step",
                         "hh_level_rate",
                         "hh_mlp_grad", "hh_mlp_grad_workspace", "hh_mlp_forward", "hh_mlp_pack",
                         "hh_mlp_packed_bytes", "hh_mlp_infer", "hh_surrogate_step_n")]
