@@ -360,22 +360,82 @@ def bench_encryption(nbytes=65536, T=8000, window=4000):
             "slots_per_update": slots, "round_trip_ok": out == data}
 
 
-def cpu_baseline_headline(n_sample=8192):
-    """The FP64 oracle, single-threaded, on the first n_sample neurons of the
-    headline workload for all 4,000 steps."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_headline(n_single=8192, n_omp=65536):
+    """The FP64 oracle on the headline workload's first neurons for all 4,000
+    steps: single-threaded (n_single neurons), and its OpenMP build on all
+    the threads OpenMP is given (n_omp neurons; neurons are independent and
+    the counter-based noise reproduces any subset)."""
     from oracle import oracle as O
     from paper_2601_21407_amd import workloads as W
     m = W.custom_channels(dt=0.025)
     T, seed = 4000, 2
-    coef = W.jitter_coef(m, n_sample, seed=seed).astype(np.float64)
-    st = O.init_state(m, np.full(n_sample, -65.0), coef=coef)
-    ids = np.arange(n_sample, dtype=np.uint32)
+    legs = {}
+    for omp, ns in ((False, n_single), (True, n_omp)):
+        coef = W.jitter_coef(m, ns, seed=seed).astype(np.float64)
+        st = O.init_state(m, np.full(ns, -65.0), coef=coef)
+        ids = np.arange(ns, dtype=np.uint32)
+        t0 = time.perf_counter()
+        O.run(m, st, T, noise_mu=5.0, noise_sigma=3.0, seed=seed, coef=coef, ids=ids,
+              record_spikes=False, omp=omp)
+        dt = time.perf_counter() - t0
+        legs[omp] = {"value": ns * T / dt, "cores": O.threads(omp),
+                     "sample": "%d of the 1,048,576 neurons x 4,000 steps (%.1f s)" % (ns, dt)}
+    return {"value": legs[True]["value"], "unit": "neuron-updates/s", "cores": legs[True]["cores"],
+            "kind": "oracle", "sample": legs[True]["sample"] + ", OpenMP build",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "single_core": {"value": legs[False]["value"], "cores": 1,
+                            "sample": legs[False]["sample"]}}
+
+
+def cpu_oracle_configs():
+    """The oracle timed on the other configurations, each on a bounded sample
+    (rates per neuron-update): the classic validation population (1,024 x
+    10,000, full size, serial and OpenMP), the 38,000-neuron network (200
+    steps with its 99.94 M synapses, serial) and the differentiable layer's
+    forward + FP64 adjoint (2,048 of the 262,144 units x 250 steps, serial)."""
+    from oracle import oracle as O
+    from paper_2601_21407_amd import workloads as W
+    out = {}
+    m = W.classic_hh(dt=0.01)
+    I = W.validation_currents(1024, seed=1).astype(np.float64)
+    for omp in (False, True):
+        st = O.init_state(m, np.full(1024, -65.0))
+        t0 = time.perf_counter()
+        O.run(m, st, 10000, i_const=I, record_spikes=False, omp=omp)
+        dt = time.perf_counter() - t0
+        out["classic_1024x10000" + ("_openmp" if omp else "")] = {
+            "updates_per_s": 1024 * 10000 / dt, "s": dt, "cores": O.threads(omp)}
+    n, T = 38000, 200
+    mn = W.net_model()
+    csr = W.net_csr(n=n, inh_scale=W.NET_INH_SCALE)
+    mask, thr = W.net_external(n=n)
+    st = O.init_state(mn, W.net_v0(n, 3).astype(np.float64))
     t0 = time.perf_counter()
-    O.run(m, st, T, noise_mu=5.0, noise_sigma=3.0, seed=seed, coef=coef, ids=ids,
-          record_spikes=False)
+    O.net_run(mn, st, csr, W.NET_W_SCALE, T, ext_mask=mask, ext_thresh=thr, w_ext=W.NET_W_EXT,
+              seed=3)
     dt = time.perf_counter() - t0
-    return {"value": n_sample * T / dt, "unit": "neuron-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of the 1,048,576 neurons x 4,000 steps (%.1f s)" % (n_sample, dt)}
+    out["network_38000_200_steps"] = {"updates_per_s": n * T / dt, "s": dt, "cores": 1}
+    ml = W.classic_hh(dt=0.025)
+    nl, Tl = 2048, 250
+    rng = np.random.default_rng(4)
+    Il = 10.0 + 5.0 * rng.standard_normal((Tl, nl))
+    s0 = O.init_state(ml, np.full(nl, -65.0))
+    t0 = time.perf_counter()
+    O.bptt(ml, s0, Il, dL_dr=np.ones(nl))
+    dt = time.perf_counter() - t0
+    out["layer_fwd_bwd_2048x250"] = {"updates_per_s": nl * Tl / dt, "s": dt, "cores": 1}
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -668,11 +728,12 @@ def bench_layer(reps=5, ckpt_every=50):
 # learned surrogate vs plain integrator at equal spike-time error
 # ---------------------------------------------------------------------------
 def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
-    """Train the surrogate on 50 M transitions of the plain kernel, deploy it
-    on n neurons x T steps (dense input 5 + 3 z, the same realization for
-    every method), and place it against the plain integrator at dt = 0.025
-    (reference), 0.05 (explicit Euler), 0.1 and 0.25 ms (exponential Euler
-    in V).  Time = kernel time of the simulation on the GPU; spike-time error
+    """Train the surrogate on 50 M transitions of the plain kernel (once with
+    each hidden activation), deploy it on n neurons x T steps (dense input
+    5 + 3 z, the same realization for every method), and place it against
+    the plain integrator at dt = 0.025 (reference), 0.05 (explicit Euler),
+    0.1 and 0.25 ms (exponential Euler in V) and the tabulated kinetics.
+    Time = kernel time of the simulation on the GPU; spike-time error
     against the reference on the first eval_neurons neurons."""
     import torch
     from paper_2601_21407_amd import hh
@@ -680,21 +741,24 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
     t0 = time.perf_counter()
     X, dY = SG.generate_transitions(n_traj=5000, T=10000, seed=5)
     norm = SG.norm_stats(X, dY)
-    t_gen = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    params, hist = SG.train(X, dY, norm, epochs=epochs, batch=16384, lr=2e-3)
     _sync()
-    t_train = time.perf_counter() - t0
+    t_gen = time.perf_counter() - t0
+    nets, training = {}, {}
+    for act in ("silu", "hardswish"):
+        t0 = time.perf_counter()
+        params, hist = SG.train(X, dY, norm, epochs=epochs, batch=16384, lr=2e-3, act=act)
+        _sync()
+        training[act] = {"final_loss": hist[-1], "loss_history": hist,
+                         "train_s": time.perf_counter() - t0}
+        nets[act] = hh.mlp_pack(params, norm)
     n_trans = int(X.shape[0])
     del X, dY
-    packed = hh.mlp_pack(params, norm)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(41)
     I = torch.empty((T, n), device="cuda")
     I.normal_(0.0, 3.0, generator=gen)
     I += 5.0
-    res = {"training": {"transitions": n_trans, "epochs": epochs, "final_loss": hist[-1],
-                        "loss_history": hist, "gen_s": t_gen, "train_s": t_train}}
+    res = {"training": {"transitions": n_trans, "epochs": epochs, "gen_s": t_gen, **training}}
 
     def kernel_time(fn):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -709,24 +773,21 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
     ms_ref, (_, _, bits_ref) = kernel_time(lambda: SG.plain_run(n, T, i_dense=I))
     ref_np = bits_ref.cpu().numpy()
     rows = []
-    ms_sur, (_, _, bits_s, stats) = kernel_time(lambda: SG.deploy(packed, n, T, i_dense=I))
-    st = stats.cpu().numpy()
-    e = SG.spike_time_error(ref_np, bits_s.cpu().numpy(), n, 0.025, 0.025,
-                            max_neurons=eval_neurons)
-    rows.append(dict(method="surrogate k=10", ms=ms_sur, speedup=ms_ref / ms_sur,
-                     surrogate_call_frac=float(st[0] / max(st[0] + st[1], 1)),
-                     failed_checks=int(st[2]), **e))
-    # the same deployment with the periodic check every 20 calls
-    ms_s20, (_, _, bits_s20, st20) = kernel_time(lambda: SG.deploy(packed, n, T, i_dense=I,
-                                                                   check_every=20))
-    st20 = st20.cpu().numpy()
-    e20 = SG.spike_time_error(ref_np, bits_s20.cpu().numpy(), n, 0.025, 0.025,
-                              max_neurons=eval_neurons)
-    rows.append(dict(method="surrogate k=10, check every 20 calls", ms=ms_s20, speedup=ms_ref / ms_s20,
-                     surrogate_call_frac=float(st20[0] / max(st20[0] + st20[1], 1)),
-                     failed_checks=int(st20[2]), **e20))
-    del bits_s20
-    ms_noise, _ = kernel_time(lambda: SG.deploy(packed, n, T, noise=(5.0, 3.0, 2), spikes=False))
+    for act, label, ce in (("silu", "surrogate k=10, SiLU (configured activation)", 10),
+                           ("hardswish", "surrogate k=10, hard-swish", 10),
+                           ("hardswish", "surrogate k=10, hard-swish, check every 20 calls", 20)):
+        ms_s, (_, _, bits_s, stats) = kernel_time(
+            lambda: SG.deploy(nets[act], n, T, i_dense=I, check_every=ce, act=act))
+        st = stats.cpu().numpy()
+        e = SG.spike_time_error(ref_np, bits_s.cpu().numpy(), n, 0.025, 0.025,
+                                max_neurons=eval_neurons)
+        rows.append(dict(method=label, activation=act, check_every=ce, ms=ms_s,
+                         speedup=ms_ref / ms_s,
+                         surrogate_call_frac=float(st[0] / max(st[0] + st[1], 1)),
+                         failed_checks=int(st[2]), **e))
+        del bits_s
+    ms_noise, _ = kernel_time(lambda: SG.deploy(nets["hardswish"], n, T, noise=(5.0, 3.0, 2),
+                                                spikes=False, act="hardswish"))
     ms_plain_noise, _ = kernel_time(lambda: SG.plain_run(n, T, noise=(5.0, 3.0, 2), spikes=False))
     rows.append(dict(method="plain dt=0.025 (reference)", ms=ms_ref, speedup=1.0,
                      mean_abs_ms=0.0, p95_abs_ms=0.0, unmatched_frac=0.0))
@@ -747,22 +808,6 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
                                 max_neurons=eval_neurons)
         rows.append(dict(method="plain dt=%g %s" % (dt, vm), ms=msc, speedup=ms_ref / msc, **e))
         del Ic
-    # the same method with a longer surrogate step (k = 20 steps per call):
-    # the network's cost per call is fixed, the plain steps it replaces double
-    X20, dY20 = SG.generate_transitions(n_traj=5000, T=10000, seed=5, k=20)
-    norm20 = SG.norm_stats(X20, dY20)
-    params20, hist20 = SG.train(X20, dY20, norm20, epochs=epochs, batch=16384, lr=2e-3)
-    del X20, dY20
-    packed20 = hh.mlp_pack(params20, norm20)
-    ms20, (_, _, bits20, st20k) = kernel_time(lambda: SG.deploy(packed20, n, T, i_dense=I, k=20))
-    st20k = st20k.cpu().numpy()
-    e20k = SG.spike_time_error(ref_np, bits20.cpu().numpy(), n, 0.025, 0.025,
-                               max_neurons=eval_neurons)
-    rows.insert(2, dict(method="surrogate k=20 (longer step than configured)", ms=ms20,
-                        speedup=ms_ref / ms20, final_loss=hist20[-1],
-                        surrogate_call_frac=float(st20k[0] / max(st20k[0] + st20k[1], 1)),
-                        failed_checks=int(st20k[2]), **e20k))
-    del bits20
     # a surrogate row is dominated by a plain row that is at least as fast
     # and at least as accurate (mean |dt| and unmatched fraction)
     plain_rows = [r for r in rows if r["method"].startswith("plain")]
@@ -772,9 +817,7 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
                                   if r["speedup"] >= r0["speedup"]
                                   and r["mean_abs_ms"] <= r0["mean_abs_ms"]
                                   and r["unmatched_frac"] <= r0["unmatched_frac"]]
-    dominated = rows[0]["dominated_by"]
     res.update({"n": n, "T": T, "eval_neurons": eval_neurons, "pareto": rows,
-                "surrogate_dominated_by": dominated,
                 "noise_input": {"surrogate_ms": ms_noise, "plain_ms": ms_plain_noise,
                                 "speedup": ms_plain_noise / ms_noise}})
     return res
@@ -901,7 +944,11 @@ def main():
     if "encryption" in parts:
         extra["encryption"] = bench_encryption()
         print("[bench] encryption done", file=sys.stderr, flush=True)
-    cpu = None if args.no_cpu_baseline else cpu_baseline_headline()
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_headline()
+        extra["cpu_oracle"] = cpu_oracle_configs()
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
 
     line = {
         "metric": METRIC,

@@ -244,11 +244,17 @@ int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const 
                   const hh_outputs* out, void* stream);
 
 /* Synaptic connectivity for the recurrent network (Results, cortical network
- * with sparse synapses and indirect addressing): CSR by source neuron,
- * row_ptr int64 [n+1], col int32 [nnz] target ids, w float [nnz].  A spike of
- * source j adds w_scale * w to g_e of each target for w > 0 and
- * w_scale * |w| to g_i for w < 0, one step after the spike.  Buffers stay
- * owned by the caller.  Requires has_syn and B == 1. */
+ * with sparse synapses and indirect addressing): CSR by source neuron over
+ * the N neurons of one copy, row_ptr int64 [N+1], col int32 [nnz] target ids
+ * in [0, N), w float [nnz].  A spike of source j adds w_scale * w to g_e of
+ * each target for w > 0 and w_scale * |w| to g_i for w < 0, one step after
+ * the spike.  With B > 1 the population is B independent copies of the
+ * network sharing this CSR (the paper's parallel simulations on one device,
+ * Results, "Cortical scale: cortex simulation"): element b N + j spikes
+ * through row j into targets b N + col.  hh_step_n runs all copies in one
+ * co-resident grid and returns HH_E_UNSUPPORTED when N B neurons do not fit
+ * one (about 4 blocks of 512 per compute unit).  Buffers stay owned by the
+ * caller.  Requires has_syn. */
 int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, const float* w,
                       int64_t nnz, float w_scale);
 /* Synaptic delays of several steps (Methods, cortical network: per-pathway
@@ -264,9 +270,11 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
  * a delay outside [1, max_delay] (the table is read back once to check);
  * HH_E_SHAPE for max_delay outside [1, 255]; HH_E_OOM. */
 int32_t hh_set_delays(hh_model* m, const uint8_t* delay, int32_t max_delay);
-/* External Poisson drive: neurons with ext_mask[i] != 0 receive w_ext on g_e
- * at step t when the stream-1 Philox4x32-10 word of (seed, i, t) is below
- * thresh (event probability thresh / 2^32 per step).  ext_mask: device [n]. */
+/* External Poisson drive: neuron j of every copy with ext_mask[j] != 0
+ * receives w_ext on g_e at step t when the stream-1 Philox4x32-10 word of
+ * (seed, element index b N + j, t) is below thresh (event probability
+ * thresh / 2^32 per step; each copy draws its own events).  ext_mask: device
+ * [N], shared by the copies. */
 int32_t hh_set_external(hh_model* m, const uint8_t* ext_mask, uint32_t thresh, float w_ext,
                         uint64_t seed);
 
@@ -395,37 +403,79 @@ int32_t hh_adam_step(float* param, const float* grad, float* m, float* v, int64_
                      void* stream);
 
 /* ---------------------------------------------------------------------------
- * Learned k-step surrogate.  A multilayer perceptron 7 -> 64 -> 64 -> 6 with
- * SiLU activations maps (V, m, h, n, p, q, mean input current over the k
- * steps) to the state change over k steps of the cortical channel set.  The
- * plain integrator stays the fallback and the judge of its error.
+ * Learned k-step surrogate.  A multilayer perceptron 7 -> 64 -> 64 -> 6 maps
+ * (V, m, h, n, p, q, mean input current over the k steps) to the state
+ * change over k steps of the cortical channel set; the plain integrator
+ * stays the fallback and the judge of its error.  The network is trained on
+ * transitions of the plain kernel (the method's own trajectories) and stands
+ * in for k plain steps where it is admissible (Methods, "Engineering
+ * optimization": cheaper approximations of the costly update).
+ *
+ * Hidden activation (the same for both hidden layers; a network is used with
+ * the activation it was trained with):
+ *   HH_ACT_SILU       a sigmoid(a)
+ *   HH_ACT_HARDSWISH  a clamp(a / 6 + 1/2, 0, 1), the piecewise-quadratic
+ *                     form of SiLU (Howard et al., 2019), evaluated without
+ *                     transcendental functions
  *
  * params: float [HH_MLP_NPARAM] = W1 [7][64], b1 [64], W2 [64][64], b2 [64],
- * W3 [64][6], b3 [6], W[k][j] connecting input k to output j.  X [S][7]
- * (normalized inputs), Y [S][6] (normalized targets). */
+ * W3 [64][6], b3 [6], W[k][j] connecting input k to output j.
+ * norm: float [32], the feature normalization: input mean [0..6], input
+ * standard deviation [8..14], output mean [16..21], output standard deviation
+ * [24..29].  The network sees x_n = (x - mean) / std and predicts the
+ * normalized change; every entry point takes raw samples, X [S][7] and
+ * Y [S][6] (state change), and normalizes inside. */
 #define HH_MLP_NPARAM 5062
+enum { HH_ACT_SILU = 0, HH_ACT_HARDSWISH = 1 };
 
-/* Mean-squared-error loss L = (1/S) sum_s sum_o (y_so - Y_so)^2 and its
- * gradient with respect to params (written).  quantize != 0 rounds the
- * weights and hidden activations to bf16 where the MFMA inference does
- * (straight-through gradient).  Partial sums are added in a fixed order.
- * workspace: hh_mlp_grad_workspace(S) bytes.  loss: device float, nullable. */
-int32_t hh_mlp_grad(const float* params, const float* X, const float* Y, int32_t S,
-                    int32_t quantize, float* grad, float* loss, void* workspace,
+/* Training set from plain trajectories: traj [T][n_state][n] is the state
+ * before every step (hh_step_n checkpoints with ckpt_every = 1; n_state = 7:
+ * V, m, h, n, p, q, V_lo), i_dense [T][n] the input of every step.  Step t of
+ * element i (t + k < T) gives a sample when V <= v_fb both before step t and
+ * before step t + k (V = V + V_lo): X = (state at t, mean input over steps
+ * t .. t + k - 1, summed in step order in binary32 and divided by k, as the
+ * deployment forms it), Y = state at t + k minus state at t.  Samples are
+ * written in (t, i) order up to cap; *count (device int64) receives the
+ * number of qualifying samples (which may exceed cap).  workspace:
+ * hh_surrogate_transitions_workspace(T, k) bytes.  Errors: HH_E_UNSUPPORTED
+ * for n_state != 7; HH_E_SHAPE for k outside [1, T) or a short workspace. */
+int32_t hh_surrogate_transitions(const float* traj, int32_t n_state, const float* i_dense,
+                                 int64_t n, int32_t T, int32_t k, float v_fb, float* X, float* Y,
+                                 int64_t cap, int64_t* count, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+size_t hh_surrogate_transitions_workspace(int32_t T, int32_t k);
+
+/* Feature normalization of a training set: norm (written, all 32 entries)
+ * gets the mean and the sample standard deviation (denominator S - 1) of
+ * each input and target feature, floored at 1e-6 (inputs) and 1e-9
+ * (targets); binary64 sums in a fixed order.  workspace:
+ * hh_mlp_norm_workspace() bytes. */
+int32_t hh_mlp_norm(const float* X, const float* Y, int64_t S, float* norm, void* workspace,
                     size_t workspace_bytes, void* stream);
+size_t hh_mlp_norm_workspace(void);
+
+/* Mean-squared-error loss on the normalized targets,
+ * L = (1/S) sum_s sum_o (y_so - Yn_so)^2, and its gradient with respect to
+ * params (written).  quantize != 0 rounds the weights and hidden activations
+ * to bf16 where the MFMA inference does (straight-through gradient).  Partial
+ * sums are added in a fixed order.  workspace: hh_mlp_grad_workspace(S)
+ * bytes.  loss: device float, nullable. */
+int32_t hh_mlp_grad(const float* params, const float* norm, const float* X, const float* Y,
+                    int32_t S, int32_t quantize, int32_t act, float* grad, float* loss,
+                    void* workspace, size_t workspace_bytes, void* stream);
 size_t hh_mlp_grad_workspace(int32_t S);
-/* FP32 forward (VALU), Y [S][6] written. */
-int32_t hh_mlp_forward(const float* params, const float* X, int32_t S, int32_t quantize, float* Y,
-                       void* stream);
+/* FP32 forward (VALU) on raw inputs: Y [S][6] = de-normalized outputs. */
+int32_t hh_mlp_forward(const float* params, const float* norm, const float* X, int32_t S,
+                       int32_t quantize, int32_t act, float* Y, void* stream);
 /* Pack params into the bf16 MFMA fragment image used by hh_mlp_infer and
- * hh_surrogate_step_n, together with the normalization norm[32] (device):
- * input mean [0..6], input std [8..14], output mean [16..21], output std
- * [24..29].  packed: device buffer of hh_mlp_packed_bytes(). */
+ * hh_surrogate_step_n, together with the normalization.  packed: device
+ * buffer of hh_mlp_packed_bytes(). */
 int32_t hh_mlp_pack(const float* params, const float* norm, void* packed, void* stream);
 size_t hh_mlp_packed_bytes(void);
-/* MFMA inference on raw (un-normalized) inputs X [S][7]: Y [S][6] =
- * de-normalized outputs (state change). */
-int32_t hh_mlp_infer(const void* packed, const float* X, int32_t S, float* Y, void* stream);
+/* MFMA inference on raw inputs X [S][7]: Y [S][6] = de-normalized outputs
+ * (state change). */
+int32_t hh_mlp_infer(const void* packed, int32_t act, const float* X, int32_t S, float* Y,
+                     void* stream);
 
 /* Advance a population of the cortical channel set by n_steps (a multiple of
  * k) using the surrogate for k steps at a time where it is admissible:
@@ -440,10 +490,10 @@ int32_t hh_mlp_infer(const void* packed, const float* X, int32_t S, float* Y, vo
  * calls, failed checks).  The model must be the cortical set without
  * per-neuron coefficients or capacitance (else HH_E_UNSUPPORTED); input
  * HH_IN_NOISE or HH_IN_DENSE. */
-int32_t hh_surrogate_step_n(hh_model* m, const void* mlp_packed, float* state, uint8_t* flags,
-                            int64_t t0, int32_t n_steps, int32_t k, const hh_input* in,
-                            float v_fallback, int32_t check_every, float check_tol,
-                            uint32_t* spikes, uint64_t* stats, void* stream);
+int32_t hh_surrogate_step_n(hh_model* m, const void* mlp_packed, int32_t act, float* state,
+                            uint8_t* flags, int64_t t0, int32_t n_steps, int32_t k,
+                            const hh_input* in, float v_fallback, int32_t check_every,
+                            float check_tol, uint32_t* spikes, uint64_t* stats, void* stream);
 
 #ifdef __cplusplus
 }

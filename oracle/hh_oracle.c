@@ -20,6 +20,9 @@
 #include "hh_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -345,6 +348,15 @@ static int32_t run_impl(const ora_model* m, int64_t n, const double* coef, const
                         uint64_t seed, double lam, const double* freq, const double* i_dense,
                         uint8_t* spk, double* vrec, double* level);
 
+/* Threads the parallel loops use: 1 in the serial build. */
+int32_t ora_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double* cm,
                 const uint32_t* ids, double* state, int64_t t0, int32_t T, int32_t in_mode,
                 const double* i_const, double mu, double sigma, uint64_t seed, double lam,
@@ -368,6 +380,12 @@ static int32_t run_impl(const ora_model* m, int64_t n, const double* coef, const
                         uint8_t* spk, double* vrec, double* level) {
   if (!model_ok(m) || n < 0 || T < 0) return -1;
   const int G = m->n_gates;
+  /* neurons are independent: the OpenMP build of this same source (the
+   * all-core timing leg) splits them over threads; every neuron's
+   * arithmetic is unchanged */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
   for (int64_t i = 0; i < n; ++i) {
     double V = state[i], p[ORA_MAX_GATES], pn[ORA_MAX_GATES], ge = 0.0, gi = 0.0;
     for (int g = 0; g < G; ++g) p[g] = state[(int64_t)(1 + g) * n + i];

@@ -101,6 +101,8 @@ int32_t ora_n_state(const ora_model* m);
  * vrec [T][n] the membrane potential after each step, level[i] += number of
  * steps with V >= v_th.  ids: global neuron ids for the noise generator
  * (nullable = 0..n-1).  Returns 0, or -1 on a malformed model. */
+/* Threads the parallel loops use (1 in the serial build). */
+int32_t ora_threads(void);
 int32_t ora_run(const ora_model* m, int64_t n, const double* coef, const double* cm,
                 const uint32_t* ids, double* state, int64_t t0, int32_t T, int32_t in_mode,
                 const double* i_const, double mu, double sigma, uint64_t seed, double lam,

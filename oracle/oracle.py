@@ -30,18 +30,22 @@ VMETH = {"fe": 0, "ee": 1}
 IN_NONE, IN_CONST, IN_NOISE, IN_DENSE, IN_BACKGROUND = 0, 1, 2, 3, 4
 
 
+_OMP_PATH = os.path.join(_HERE, "libhh_oracle_omp.so")
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain C, -O2, no fast-math)."""
+    """Compile the oracle with gcc (plain C, -O2, no fast-math), and the same
+    source with OpenMP (the all-core timing leg: independent neurons split
+    over threads, each neuron's arithmetic unchanged)."""
     src = os.path.join(_HERE, "hh_oracle.c")
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
-        os.path.getmtime(src), os.path.getmtime(os.path.join(_HERE, "hh_oracle.h"))
-    ):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off",
-             "-o", tmp, src, "-lm"]
-        )
-        os.replace(tmp, _LIB_PATH)
+    newest = max(os.path.getmtime(src), os.path.getmtime(os.path.join(_HERE, "hh_oracle.h")))
+    for path, extra in ((_LIB_PATH, []), (_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path) or os.path.getmtime(path) < newest:
+            tmp = path + ".tmp%d" % os.getpid()
+            subprocess.check_call(
+                ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off"]
+                + extra + ["-o", tmp, src, "-lm"])
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
@@ -111,14 +115,14 @@ def model_to_struct(model: dict) -> OraModel:
     return s
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
+def lib(omp: bool = False):
+    """The serial oracle library, or with omp its OpenMP build."""
+    if omp not in _libs:
         build()
-        L = ctypes.CDLL(_LIB_PATH)
+        L = ctypes.CDLL(_OMP_PATH if omp else _LIB_PATH)
         P = ctypes.POINTER
         d, i32, i64, u32, u64, vp = (ctypes.c_double, ctypes.c_int32, ctypes.c_int64,
                                      ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p)
@@ -161,8 +165,15 @@ def lib():
         L.ora_syn_deliver.restype = None
         L.ora_bptt.argtypes = [P(OraModel), i64, vp, vp, i32, vp, vp, vp, i32, d, vp, vp, vp, vp]
         L.ora_bptt.restype = i32
-        _lib = L
-    return _lib
+        L.ora_threads.argtypes = []
+        L.ora_threads.restype = i32
+        _libs[omp] = L
+    return _libs[omp]
+
+
+def threads(omp: bool = False) -> int:
+    """Threads the oracle's independent-neuron loop uses."""
+    return int(lib(omp).ora_threads())
 
 
 def _p(a):
@@ -268,10 +279,11 @@ def sine(amp: float, R: int, t: int) -> float:
 def run(model: dict, state: np.ndarray, T: int, t0: int = 0, *, i_const=None, noise_mu=None,
         noise_sigma=None, seed: int = 0, i_dense=None, coef=None, cm=None, ids=None,
         record_v: bool = False, record_spikes: bool = True, level: bool = False, background=None,
-        sine=None):
+        sine=None, omp: bool = False):
     """Advance independent neurons T steps in place.  Returns dict with
     'spikes' [T][n] uint8 (upward crossings), 'v' [T][n] (optional) and
-    'level' [n] (count of steps with V >= v_th, optional)."""
+    'level' [n] (count of steps with V >= v_th, optional).  omp: the OpenMP
+    build (same results; used to time the oracle on all host cores)."""
     s = model_to_struct(model)
     n = state.shape[1]
     assert state.dtype == np.float64 and state.flags.c_contiguous
@@ -289,7 +301,7 @@ def run(model: dict, state: np.ndarray, T: int, t0: int = 0, *, i_const=None, no
     mode, i_const, i_dense, mu, sigma, lam = _input_mode(T, n, i_const, noise_mu, noise_sigma,
                                                         i_dense, background)
     ids = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
-    rc = lib().ora_run(ctypes.byref(s), n, _p(coef), _p(cm), _p(ids), _p(state), int(t0), int(T),
+    rc = lib(omp).ora_run(ctypes.byref(s), n, _p(coef), _p(cm), _p(ids), _p(state), int(t0), int(T),
                        mode, _p(i_const), mu, sigma, int(seed), lam, _p(i_dense), _p(spk), _p(vr),
                        _p(lv))
     if rc != 0:
@@ -431,7 +443,8 @@ def readout_ce(r: np.ndarray, W: np.ndarray, b: np.ndarray, labels: np.ndarray):
 
 
 # --------------------------------------------------------------------------
-# MLP surrogate: x -> silu(x W1 + b1) -> silu(. W2 + b2) -> . W3 + b3
+# MLP surrogate: x -> act(x W1 + b1) -> act(. W2 + b2) -> . W3 + b3, with
+# act SiLU or hard-swish
 # --------------------------------------------------------------------------
 def silu(x):
     return x / (1.0 + np.exp(-x))
@@ -442,35 +455,148 @@ def dsilu(x):
     return s * (1.0 + x * (1.0 - s))
 
 
-def mlp_forward(params, x):
-    """params = [W1, b1, W2, b2, W3, b3] with Wk [in, out]."""
+def hardswish(x):
+    """x relu6(x + 3) / 6 (Howard et al., 2019, "Searching for MobileNetV3")."""
+    return x * np.clip(x + 3.0, 0.0, 6.0) / 6.0
+
+
+def dhardswish(x):
+    """Derivative of hardswish: 0 below -3, 1 above 3, x / 3 + 1/2 between
+    (the kinks take the outer side's value)."""
+    return np.where(x <= -3.0, 0.0, np.where(x >= 3.0, 1.0, x / 3.0 + 0.5))
+
+
+ACTIVATIONS = {"silu": (silu, dsilu), "hardswish": (hardswish, dhardswish)}
+
+
+def bf16_round(x):
+    """x rounded to the nearest bfloat16 value (8 significant bits, ties to
+    even), from the exact binary64 value."""
+    x = np.asarray(x, np.float64)
+    m, e = np.frexp(x)  # x = m 2^e, 0.5 <= |m| < 1
+    return np.ldexp(np.round(np.ldexp(m, 8)), e - 8)
+
+
+def mlp_forward(params, x, act="silu", quantize=False):
+    """params = [W1, b1, W2, b2, W3, b3] with Wk [in, out].  quantize: the
+    network as the bf16 inference evaluates it -- W1, b1, W2 and W3 rounded
+    to bf16, the input split into a bf16 high part and a bf16 low part of
+    the remainder, and both hidden activations rounded to bf16; b2, b3 and
+    all sums exact."""
+    f, _ = ACTIVATIONS[act]
     W1, b1, W2, b2, W3, b3 = [np.asarray(p, np.float64) for p in params]
     x = np.asarray(x, np.float64)
+    q = bf16_round if quantize else (lambda v: v)
+    if quantize:
+        W1, b1, W2, W3 = q(W1), q(b1), q(W2), q(W3)
+        hi = q(x)
+        x = hi + q(x - hi)
     a1 = x @ W1 + b1
-    h1 = silu(a1)
+    h1 = q(f(a1))
     a2 = h1 @ W2 + b2
-    h2 = silu(a2)
+    h2 = q(f(a2))
     y = h2 @ W3 + b3
-    return y, (x, a1, h1, a2, h2)
+    return y, (x, a1, h1, a2, h2, act)
 
 
 def mlp_backward(params, cache, dy):
     """Gradients of sum(dy * y) wrt every parameter, and wrt x."""
     W1, b1, W2, b2, W3, b3 = [np.asarray(p, np.float64) for p in params]
-    x, a1, h1, a2, h2 = cache
+    x, a1, h1, a2, h2, act = cache
+    _, df = ACTIVATIONS[act]
     dy = np.asarray(dy, np.float64)
     gW3 = h2.T @ dy
     gb3 = dy.sum(0)
     dh2 = dy @ W3.T
-    da2 = dh2 * dsilu(a2)
+    da2 = dh2 * df(a2)
     gW2 = h1.T @ da2
     gb2 = da2.sum(0)
     dh1 = da2 @ W2.T
-    da1 = dh1 * dsilu(a1)
+    da1 = dh1 * df(a1)
     gW1 = x.T @ da1
     gb1 = da1.sum(0)
     dx = da1 @ W1.T
     return [gW1, gb1, gW2, gb2, gW3, gb3], dx
+
+
+def mlp_split(flat):
+    """The packed parameter vector (W1 [7][64], b1, W2 [64][64], b2, W3
+    [64][6], b3) as the list mlp_forward takes."""
+    flat = np.asarray(flat, np.float64)
+    out, off = [], 0
+    for a, b in ((7, 64), (64, 64), (64, 6)):
+        out.append(flat[off: off + a * b].reshape(a, b))
+        off += a * b
+        out.append(flat[off: off + b])
+        off += b
+    return out
+
+
+def mlp_apply(params, norm, x, act="silu", quantize=False):
+    """The surrogate's state change for raw inputs x [S][7]: the network on
+    (x - mean) / std, its output de-normalized (y std + mean); norm is the
+    32-entry normalization (input mean [0:7], std [8:15], output mean
+    [16:22], std [24:30])."""
+    norm = np.asarray(norm, np.float64)
+    xn = (np.asarray(x, np.float64) - norm[0:7]) / norm[8:15]
+    y, _ = mlp_forward(params, xn, act=act, quantize=quantize)
+    return y * norm[24:30] + norm[16:22]
+
+
+def surrogate_run(model, state, T, k, params, norm, i_dense, *, act="silu", v_fb=-50.0,
+                  check_every=10, check_tol=0.5, quantize=True):
+    """The surrogate deployment policy in binary64, step for step as stated:
+    for each call of k steps, a neuron is admissible when V <= v_fb; the
+    network's prediction x + mlp_apply(x) (gates clamped to [0, 1]) is a
+    candidate when the neuron is admissible and the predicted V <= v_fb; the
+    neuron takes the prediction when it is a candidate, has not failed the
+    last check and the call is not a check call (every check_every-th call);
+    otherwise it runs the k plain steps of run().  On a check call a
+    candidate whose plain V differs from the predicted V by more than
+    check_tol fails the check and stays plain until the next check call.
+    Spikes come from plain steps only.  state: [1 + G][n] (V, gates), in
+    place.  Returns dict with 'spikes' [T][n], 'stats' (surrogate calls,
+    plain calls, failed checks) and 'margin' [n], the smallest distance of
+    any decision quantity from its threshold (|V - v_fb| before and after,
+    ||V_plain - V_pred| - check_tol|) over the run."""
+    G = len(model["gates"])
+    assert state.shape[0] == 1 + G and G + 1 == 6 and T % k == 0
+    n = state.shape[1]
+    I = np.asarray(i_dense, np.float64)
+    forced = np.zeros(n, bool)
+    spikes = np.zeros((T, n), np.uint8)
+    stats = np.zeros(3, np.int64)
+    margin = np.full(n, np.inf)
+    for c in range(T // k):
+        t = c * k
+        check = check_every > 0 and (c + 1) % check_every == 0
+        V = state[0].copy()
+        sub = V <= v_fb
+        x = np.concatenate([state.T, I[t:t + k].mean(0)[:, None]], axis=1)
+        pred = x[:, :6] + mlp_apply(params, norm, x, act=act, quantize=quantize)
+        pred[:, 1:] = np.clip(pred[:, 1:], 0.0, 1.0)
+        cand = sub & (pred[:, 0] <= v_fb)
+        margin = np.minimum(margin, np.abs(V - v_fb))
+        margin[sub] = np.minimum(margin[sub], np.abs(pred[sub, 0] - v_fb))
+        use = cand & ~forced & (not check)
+        plain = ~use
+        if plain.any():
+            cols = np.nonzero(plain)[0]
+            s = np.ascontiguousarray(state[:, cols])
+            r = run(model, s, k, t0=t, i_dense=np.ascontiguousarray(I[t:t + k][:, cols]))
+            spikes[t:t + k, cols] = r["spikes"]
+            state[:, cols] = s
+            if check:
+                cc = cols[cand[cols]]
+                d = np.abs(state[0, cc] - pred[cc, 0])
+                margin[cc] = np.minimum(margin[cc], np.abs(d - check_tol))
+                fail = d > check_tol
+                forced[cc] = fail
+                stats[2] += int(fail.sum())
+        state[:, use] = pred[use].T
+        stats[0] += int(use.sum())
+        stats[1] += int(plain.sum())
+    return {"spikes": spikes, "stats": stats, "margin": margin}
 
 
 def mse_loss_grad(y, target):

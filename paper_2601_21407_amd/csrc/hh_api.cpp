@@ -269,7 +269,10 @@ int32_t hh_set_rate_table(hh_model* m, float v_lo, float v_hi, int32_t n_nodes, 
   if (!m->d_tab && hipMalloc((void**)&m->d_tab, bytes) != hipSuccess) return HH_E_OOM;
   m->tab_n = n_nodes;
   m->tab_vlo = v_lo;
-  m->tab_h = (v_hi - v_lo) / (float)(n_nodes - 1);
+  // the lookup scale in binary32, and the nodes placed exactly where the
+  // lookup puts them (v_lo + i / inv_h), so the step reads each node at the
+  // voltage it was tabulated for
+  m->tab_inv_h = (float)((double)(n_nodes - 1) / ((double)v_hi - (double)v_lo));
   HIP_OK(launch_build_table(m, s));
   return HH_OK;
 }
@@ -330,7 +333,7 @@ int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const 
     a.tab = m->d_tab;
     a.tab_n = m->tab_n;
     a.tab_vlo = m->tab_vlo;
-    a.tab_inv_h = 1.0f / m->tab_h;
+    a.tab_inv_h = m->tab_inv_h;
   }
   for (int32_t kb = 0; kb < n_steps; kb += m->k_fuse) {
     const int32_t ns = (n_steps - kb < m->k_fuse) ? n_steps - kb : m->k_fuse;

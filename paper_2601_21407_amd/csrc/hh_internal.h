@@ -72,7 +72,8 @@ struct hh_model {
   // tabulated gate kinetics, owned by the model (null: none)
   float4* d_tab;
   int32_t tab_n;
-  float tab_vlo, tab_h;
+  // lookup u = (V - tab_vlo) * tab_inv_h; node i sits at tab_vlo + i / tab_inv_h
+  float tab_vlo, tab_inv_h;
   // morphology (multi-compartment neurons), owned by the model (null: none)
   hhk::CableComp* d_cable;
   int32_t cable_K, cable_D;
@@ -102,7 +103,7 @@ inline hipError_t dispatch_spec(const hhk::KModel& km, bool allow_fixed, Args...
 hipError_t launch_init_state(const hh_model* m, float* state, const float* v0, float v0s,
                              hipStream_t s);
 hipError_t launch_step(const hh_model* m, const StepArgs& a, hipStream_t s);
-// fills m->d_tab (m->tab_n nodes from m->tab_vlo, spacing m->tab_h)
+// fills m->d_tab (m->tab_n nodes from m->tab_vlo, spacing 1 / m->tab_inv_h)
 hipError_t launch_build_table(const hh_model* m, hipStream_t s);
 // the step of multi-compartment neurons (hh_cable.hip): a.cable set
 hipError_t launch_cable(const hh_model* m, const StepArgs& a, hipStream_t s);

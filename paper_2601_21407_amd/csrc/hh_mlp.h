@@ -1,9 +1,11 @@
-// hh_mlp.h -- layout of the surrogate MLP (7 -> 64 -> 64 -> 6, SiLU) shared by
+// hh_mlp.h -- layout of the surrogate MLP (7 -> 64 -> 64 -> 6) shared by
 // the training, packing, inference and deployment kernels.
 #pragma once
 #include <stdint.h>
 
 constexpr int MLP_IN = 7, MLP_H = 64, MLP_OUT = 6;
+// hidden-layer activations (values match HH_ACT_* of hh.h)
+enum { MLP_ACT_SILU = 0, MLP_ACT_HSWISH = 1 };
 // packed FP32 parameter vector: W1 [7][64], b1 [64], W2 [64][64], b2 [64],
 // W3 [64][6], b3 [6]  (W[k][j]: input k -> output j)
 constexpr int MLP_OFF_W1 = 0;

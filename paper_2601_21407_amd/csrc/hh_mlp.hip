@@ -1,6 +1,7 @@
 // hh_mlp.hip -- the learned k-step surrogate: a 7 -> 64 -> 64 -> 6 MLP with
-// SiLU activations that maps (V, m, h, n, p, q, mean input current) to the
-// state change over k steps.
+// SiLU or hard-swish activations that maps (V, m, h, n, p, q, mean input
+// current) to the state change over k steps, and the kernels that form its
+// training set from plain trajectories.
 //
 // Training kernels (hh_mlp_grad) run one sample per lane-group on the VALU
 // in FP32 with the weights staged in LDS; with `quantize` they round weights
@@ -39,8 +40,23 @@ __device__ __forceinline__ uint16_t bf16bits(float f) {
 }
 
 __device__ __forceinline__ float sigm(float a) { return 1.0f / (1.0f + expf(-a)); }
-__device__ __forceinline__ float silu_acc(float a) { return a * sigm(a); }
-__device__ __forceinline__ float dsilu(float a) {
+// hard-swish a clamp(a / 6 + 1/2, 0, 1) (Howard et al., 2019): the
+// piecewise-quadratic form of SiLU, with no transcendental function
+__device__ __forceinline__ float hswish_gate(float a) {
+  return __builtin_amdgcn_fmed3f(fmaf(a, 1.0f / 6.0f, 0.5f), 0.0f, 1.0f);
+}
+// activation value (training and VALU forward) and its derivative
+template <int ACT>
+__device__ __forceinline__ float act_acc(float a) {
+  if constexpr (ACT == MLP_ACT_HSWISH) return a * hswish_gate(a);
+  return a * sigm(a);
+}
+template <int ACT>
+__device__ __forceinline__ float dact(float a) {
+  if constexpr (ACT == MLP_ACT_HSWISH) {
+    // d/da a c(a), c the clamped gate: c + a / 6 inside (-3, 3)
+    return a <= -3.0f ? 0.0f : (a >= 3.0f ? 1.0f : fmaf(a, 1.0f / 3.0f, 0.5f));
+  }
   const float s = sigm(a);
   return s * (1.0f + a * (1.0f - s));
 }
@@ -48,12 +64,27 @@ __device__ __forceinline__ float dsilu(float a) {
 constexpr int CH = 64;  // samples per chunk in the training kernel
 constexpr int LD = MLP_H + 1;
 
-__device__ __forceinline__ bool is_weight(int j) {
-  return j < MLP_OFF_B1 || (j >= MLP_OFF_W2 && j < MLP_OFF_B2) || (j >= MLP_OFF_W3 && j < MLP_OFF_B3);
+// parameters the MFMA inference holds as bf16: W1, b1 (it rides in a K slot
+// of the first layer), W2 and W3; b2 and b3 initialize the FP32 accumulators
+__device__ __forceinline__ bool is_bf16_param(int j) {
+  return j < MLP_OFF_B2 || (j >= MLP_OFF_W3 && j < MLP_OFF_B3);
+}
+
+// Normalized network input and target of a raw sample: (x - mean) / std per
+// feature, as (x - mean) * (1 / std) with 1 / std rounded once (the form the
+// deployed inference uses).  norm: input mean [0..6], std [8..14], output
+// mean [16..21], std [24..29].
+__device__ __forceinline__ float norm_in(const float* __restrict__ nm, int i, float x) {
+  return (x - nm[i]) * (1.0f / nm[8 + i]);
+}
+__device__ __forceinline__ float norm_out(const float* __restrict__ nm, int o, float y) {
+  return (y - nm[16 + o]) * (1.0f / nm[24 + o]);
 }
 
 // Forward + backward over a range of samples; per-block partial gradients.
+template <int ACT>
 __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P,
+                                                  const float* __restrict__ nm,
                                                   const float* __restrict__ X,
                                                   const float* __restrict__ Y, int S, int per_block,
                                                   int quant, float* __restrict__ part,
@@ -65,7 +96,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P,
   const int tid = threadIdx.x;
   for (int j = tid; j < MLP_NPARAM; j += 256) {
     const float v = P[j];
-    w[j] = (quant && is_weight(j)) ? bf16r(v) : v;
+    w[j] = (quant && is_bf16_param(j)) ? bf16r(v) : v;
   }
   const float* W1 = w + MLP_OFF_W1;
   const float* B1 = w + MLP_OFF_B1;
@@ -86,13 +117,13 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P,
       const int s = e >> 3, i = e & 7;
       float v = 0.0f, t = 0.0f;
       if (s < nc && i < MLP_IN) {
-        v = X[(int64_t)(c0 + s) * MLP_IN + i];
+        v = norm_in(nm, i, X[(int64_t)(c0 + s) * MLP_IN + i]);
         if (quant) {  // the inference feeds x as bf16 high + low parts
           const float hi = bf16r(v);
           v = hi + bf16r(v - hi);
         }
       }
-      if (s < nc && i < MLP_OUT) t = Y[(int64_t)(c0 + s) * MLP_OUT + i];
+      if (s < nc && i < MLP_OUT) t = norm_out(nm, i, Y[(int64_t)(c0 + s) * MLP_OUT + i]);
       xs[s][i] = v;
       dy[s][i] = t;  // targets for now
     }
@@ -102,7 +133,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P,
       float a = B1[j];
 #pragma unroll
       for (int i = 0; i < MLP_IN; ++i) a = fmaf(W1[i * MLP_H + j], xs[s][i], a);
-      const float h = silu_acc(a);
+      const float h = act_acc<ACT>(a);
       a1[s][j] = a;
       h1[s][j] = quant ? bf16r(h) : h;
     }
@@ -112,7 +143,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P,
       float a = B2[j];
 #pragma unroll 16
       for (int k = 0; k < MLP_H; ++k) a = fmaf(W2[k * MLP_H + j], h1[s][k], a);
-      const float h = silu_acc(a);
+      const float h = act_acc<ACT>(a);
       a2[s][j] = a;
       h2[s][j] = quant ? bf16r(h) : h;
     }
@@ -162,7 +193,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P,
       float d = 0.0f;
 #pragma unroll
       for (int o = 0; o < MLP_OUT; ++o) d = fmaf(W3[j * MLP_OUT + o], dy[s][o], d);
-      a2[s][j] = d * dsilu(a2[s][j]);  // dA2
+      a2[s][j] = d * dact<ACT>(a2[s][j]);  // dA2
     }
     __syncthreads();
     // layer 2 gradients and dA1
@@ -185,7 +216,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ P,
       float d = 0.0f;
 #pragma unroll 16
       for (int j = 0; j < MLP_H; ++j) d = fmaf(W2[k * MLP_H + j], a2[s][j], d);
-      a1[s][k] = d * dsilu(a1[s][k]);  // dA1
+      a1[s][k] = d * dact<ACT>(a1[s][k]);  // dA1
     }
     __syncthreads();
     // layer 1 gradients
@@ -261,14 +292,17 @@ __global__ __launch_bounds__(RD_J * RD_G) void k_mlp_reduce(const float* __restr
   }
 }
 
-// Plain FP32 forward, one sample per lane (evaluation).
+// Plain FP32 forward, one sample per lane (evaluation): raw inputs in,
+// de-normalized outputs (state change) out.
+template <int ACT>
 __global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ P,
+                                                 const float* __restrict__ nm,
                                                  const float* __restrict__ X, int S, int quant,
                                                  float* __restrict__ Yo) {
   __shared__ float w[MLP_NPARAM];
   for (int j = threadIdx.x; j < MLP_NPARAM; j += blockDim.x) {
     const float v = P[j];
-    w[j] = (quant && is_weight(j)) ? bf16r(v) : v;
+    w[j] = (quant && is_bf16_param(j)) ? bf16r(v) : v;
   }
   __syncthreads();
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -276,7 +310,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ P,
   float x[MLP_IN], h[MLP_H], y[MLP_OUT];
 #pragma unroll
   for (int i = 0; i < MLP_IN; ++i) {
-    float v = X[(int64_t)s * MLP_IN + i];
+    float v = norm_in(nm, i, X[(int64_t)s * MLP_IN + i]);
     if (quant) {
       const float hi = bf16r(v);
       v = hi + bf16r(v - hi);
@@ -288,7 +322,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ P,
     float a = w[MLP_OFF_B1 + j];
 #pragma unroll
     for (int i = 0; i < MLP_IN; ++i) a = fmaf(w[MLP_OFF_W1 + i * MLP_H + j], x[i], a);
-    h[j] = quant ? bf16r(silu_acc(a)) : silu_acc(a);
+    h[j] = quant ? bf16r(act_acc<ACT>(a)) : act_acc<ACT>(a);
   }
 #pragma unroll
   for (int o = 0; o < MLP_OUT; ++o) y[o] = w[MLP_OFF_B3 + o];
@@ -297,12 +331,12 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ P,
     float a = w[MLP_OFF_B2 + j];
 #pragma unroll
     for (int k = 0; k < MLP_H; ++k) a = fmaf(w[MLP_OFF_W2 + k * MLP_H + j], h[k], a);
-    const float h2 = quant ? bf16r(silu_acc(a)) : silu_acc(a);
+    const float h2 = quant ? bf16r(act_acc<ACT>(a)) : act_acc<ACT>(a);
 #pragma unroll
     for (int o = 0; o < MLP_OUT; ++o) y[o] = fmaf(w[MLP_OFF_W3 + j * MLP_OUT + o], h2, y[o]);
   }
 #pragma unroll
-  for (int o = 0; o < MLP_OUT; ++o) Yo[(int64_t)s * MLP_OUT + o] = y[o];
+  for (int o = 0; o < MLP_OUT; ++o) Yo[(int64_t)s * MLP_OUT + o] = fmaf(y[o], nm[24 + o], nm[16 + o]);
 }
 
 // ---------------------------------------------------------------------------
@@ -379,28 +413,35 @@ __device__ __forceinline__ bf16x8 u4_to_frag(uint32_t a, uint32_t b, uint32_t c,
   return __builtin_bit_cast(bf16x8, v);
 }
 
-// SiLU of an accumulator value (v_exp_f32 + v_rcp_f32)
-__device__ __forceinline__ float silu_fast(float a) { return a * rcp(1.0f + ex2(-a * kLog2e)); }
+// Activation of an accumulator value: SiLU on v_exp_f32 + v_rcp_f32, or
+// hard-swish on one clamped FMA and a multiply
+template <int ACT>
+__device__ __forceinline__ float act_fast(float a) {
+  if constexpr (ACT == MLP_ACT_HSWISH) return a * hswish_gate(a);
+  return a * rcp(1.0f + ex2(-a * kLog2e));
+}
 
-// SiLU of accumulator registers r0..r0+7 as a bf16 B-operand fragment
+// activation of accumulator registers r0..r0+7 as a bf16 B-operand fragment
+template <int ACT>
 __device__ __forceinline__ bf16x8 act_frag(const f32x16& acc, int r0) {
-  return u4_to_frag(pack2(silu_fast(acc[r0 + 0]), silu_fast(acc[r0 + 1])),
-                    pack2(silu_fast(acc[r0 + 2]), silu_fast(acc[r0 + 3])),
-                    pack2(silu_fast(acc[r0 + 4]), silu_fast(acc[r0 + 5])),
-                    pack2(silu_fast(acc[r0 + 6]), silu_fast(acc[r0 + 7])));
+  return u4_to_frag(pack2(act_fast<ACT>(acc[r0 + 0]), act_fast<ACT>(acc[r0 + 1])),
+                    pack2(act_fast<ACT>(acc[r0 + 2]), act_fast<ACT>(acc[r0 + 3])),
+                    pack2(act_fast<ACT>(acc[r0 + 4]), act_fast<ACT>(acc[r0 + 5])),
+                    pack2(act_fast<ACT>(acc[r0 + 6]), act_fast<ACT>(acc[r0 + 7])));
 }
 
 // Layers 1-3 for the 32-sample tile whose layer-1 B operand is bx; returns
 // the first four accumulator registers of the output tile (outputs 0-3 of
 // sample l%32 in the lower half-wave, outputs 4-5 in r = 0, 1 of the upper).
+template <int ACT>
 __device__ __forceinline__ void mlp_tile(const MlpPacked& W, bf16x8 bx, float (&y)[4]) {
   const int l = threadIdx.x & 63;
   const int hf = l >> 5;
   const f32x16 z = {};
   const f32x16 h1a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w1[0][l][0]), bx, z, 0, 0, 0);
   const f32x16 h1b = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w1[1][l][0]), bx, z, 0, 0, 0);
-  const bf16x8 b10 = act_frag(h1a, 0), b11 = act_frag(h1a, 8);
-  const bf16x8 b12 = act_frag(h1b, 0), b13 = act_frag(h1b, 8);
+  const bf16x8 b10 = act_frag<ACT>(h1a, 0), b11 = act_frag<ACT>(h1a, 8);
+  const bf16x8 b12 = act_frag<ACT>(h1b, 0), b13 = act_frag<ACT>(h1b, 8);
   // layer 2, one 32-row output tile at a time, each activated at once
   bf16x8 b2[4];
 #pragma unroll
@@ -412,8 +453,8 @@ __device__ __forceinline__ void mlp_tile(const MlpPacked& W, bf16x8 bx, float (&
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w2[ot][1][l][0]), b11, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w2[ot][2][l][0]), b12, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_ld(&W.w2[ot][3][l][0]), b13, acc, 0, 0, 0);
-    b2[2 * ot] = act_frag(acc, 0);
-    b2[2 * ot + 1] = act_frag(acc, 8);
+    b2[2 * ot] = act_frag<ACT>(acc, 0);
+    b2[2 * ot + 1] = act_frag<ACT>(acc, 8);
   }
   // layer 3: outputs 0..5 in the first rows of a 32-row tile
   f32x16 acc = {};
@@ -428,6 +469,7 @@ __device__ __forceinline__ void mlp_tile(const MlpPacked& W, bf16x8 bx, float (&
 
 // x[7] = raw inputs (state and mean current) of this lane's sample;
 // returns dy[6] = de-normalized outputs.
+template <int ACT>
 __device__ __forceinline__ void mlp_infer_wave(const MlpPacked& W, const float (&x)[MLP_IN],
                                                float (&out)[MLP_OUT]) {
   const int l = threadIdx.x & 63;
@@ -456,9 +498,9 @@ __device__ __forceinline__ void mlp_infer_wave(const MlpPacked& W, const float (
 
   // the two 32-sample tiles one after the other (fewer live registers)
   float y0[4], y1[4];
-  mlp_tile(W, bx[0], y0);
+  mlp_tile<ACT>(W, bx[0], y0);
   __builtin_amdgcn_sched_barrier(0);  // keep the tiles apart: registers, not ILP, are scarce
-  mlp_tile(W, bx[1], y1);
+  mlp_tile<ACT>(W, bx[1], y1);
   // gather the six outputs of sample l into lane l
   const float t0 = hf ? y0[0] : y1[0], t1 = hf ? y0[1] : y1[1];
   const float t2 = y1[2], t3 = y1[3];
@@ -476,7 +518,8 @@ __device__ __forceinline__ void mlp_infer_wave(const MlpPacked& W, const float (
 
 namespace {
 
-// test kernel: MFMA inference of S samples (64 per wavefront)
+// MFMA inference of S samples (64 per wavefront)
+template <int ACT>
 __global__ __launch_bounds__(256) void k_mlp_infer(const MlpPacked* __restrict__ Wg,
                                                    const float* __restrict__ X, int S,
                                                    float* __restrict__ Yo) {
@@ -492,10 +535,161 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const MlpPacked* __restrict__
   float x[MLP_IN], y[MLP_OUT];
 #pragma unroll
   for (int i = 0; i < MLP_IN; ++i) x[i] = X[(int64_t)sc * MLP_IN + i];
-  mlp_infer_wave(Ws, x, y);
+  mlp_infer_wave<ACT>(Ws, x, y);
   if (s < S)
 #pragma unroll
     for (int k = 0; k < MLP_OUT; ++k) Yo[(int64_t)s * MLP_OUT + k] = y[k];
+}
+
+}  // namespace
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// training set: normalization statistics and transitions of plain trajectories
+// ---------------------------------------------------------------------------
+constexpr int NF = MLP_IN + MLP_OUT;  // 13 features: 7 inputs, 6 targets
+constexpr int NB_NORM = 256;          // partial-sum blocks of the statistics
+
+__device__ __forceinline__ float feature(const float* X, const float* Y, int64_t s, int f) {
+  return f < MLP_IN ? X[s * MLP_IN + f] : Y[s * MLP_OUT + (f - MLP_IN)];
+}
+
+// pass 0: per-block sums of every feature; pass 1: sums of squared
+// deviations from the mean (read from norm).  Binary64 accumulation, each
+// block over a fixed contiguous range, lanes combined in a fixed order.
+__global__ __launch_bounds__(256) void k_norm_partial(const float* __restrict__ X,
+                                                      const float* __restrict__ Y, int64_t S,
+                                                      int pass, const float* __restrict__ nm,
+                                                      double* __restrict__ part) {
+  __shared__ double red[256];
+  const int64_t per = (S + NB_NORM - 1) / NB_NORM;
+  const int64_t beg = blockIdx.x * per, end = beg + per < S ? beg + per : S;
+  for (int f = 0; f < NF; ++f) {
+    const double mu = pass ? (double)nm[f < MLP_IN ? f : 16 + f - MLP_IN] : 0.0;
+    double acc = 0.0;
+    for (int64_t s = beg + threadIdx.x; s < end; s += 256) {
+      const double d = (double)feature(X, Y, s, f) - mu;
+      acc += pass ? d * d : d;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x * NF + f] = red[0];
+    __syncthreads();
+  }
+}
+
+// the partial sums in block order: pass 0 writes the means, pass 1 the
+// sample standard deviations (floored at 1e-6 for inputs, 1e-9 for targets)
+__global__ void k_norm_final(const double* __restrict__ part, int64_t S, int pass,
+                             float* __restrict__ nm) {
+  const int f = threadIdx.x;
+  if (f >= NF) return;
+  double t = 0.0;
+  for (int b = 0; b < NB_NORM; ++b) t += part[b * NF + f];
+  const int slot = f < MLP_IN ? f : 16 + f - MLP_IN;
+  if (pass == 0) {
+    nm[slot] = (float)(t / (double)S);
+  } else {
+    const double sd = S > 1 ? sqrt(t / (double)(S - 1)) : 0.0;
+    const double floor_ = f < MLP_IN ? 1e-6 : 1e-9;
+    nm[slot + 8] = (float)(sd > floor_ ? sd : floor_);
+  }
+}
+
+__global__ void k_norm_clear(float* __restrict__ nm) {
+  if (threadIdx.x < 32) nm[threadIdx.x] = 0.0f;
+}
+
+// Transitions of plain trajectories.  traj [T][n_state][n] holds the state
+// before every step (rows V, five gates, V_lo); step t of element i gives a
+// sample when V <= v_fb before step t and before step t + k: input (state at
+// t, mean input current over steps t .. t + k - 1), target (state at t + k)
+// minus (state at t).  V is V + V_lo.  Samples are ordered by (t, i).
+__device__ __forceinline__ bool trans_ok(const float* __restrict__ traj, int ns, int64_t n,
+                                         int64_t t, int k, int64_t i, float v_fb) {
+  const float va = traj[(t * ns) * n + i] + traj[(t * ns + ns - 1) * n + i];
+  const float vb = traj[((t + k) * ns) * n + i] + traj[((t + k) * ns + ns - 1) * n + i];
+  return va <= v_fb && vb <= v_fb;
+}
+
+// one block per step t: number of samples of step t
+__global__ __launch_bounds__(256) void k_trans_count(const float* __restrict__ traj, int ns,
+                                                     int64_t n, int k, float v_fb,
+                                                     int64_t* __restrict__ cnt) {
+  __shared__ int64_t red[4];
+  const int64_t t = blockIdx.x;
+  int64_t c = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) c += trans_ok(traj, ns, n, t, k, i, v_fb);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[t] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// exclusive prefix of the per-step counts (one thread, steps in order);
+// cnt[rows] receives the total
+__global__ void k_trans_scan(int64_t* __restrict__ cnt, int64_t rows) {
+  if (threadIdx.x != 0) return;
+  int64_t run = 0;
+  for (int64_t t = 0; t < rows; ++t) {
+    const int64_t c = cnt[t];
+    cnt[t] = run;
+    run += c;
+  }
+  cnt[rows] = run;
+}
+
+// one block per step t: the samples of step t, in element order, from
+// offset off[t]; samples at or beyond cap are dropped
+__global__ __launch_bounds__(256) void k_trans_write(const float* __restrict__ traj, int ns,
+                                                     int64_t n, int k, float v_fb,
+                                                     const float* __restrict__ I,
+                                                     const int64_t* __restrict__ off, int64_t cap,
+                                                     float* __restrict__ X, float* __restrict__ Y) {
+  __shared__ int wsum[4];
+  const int64_t t = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t base = off[t];
+  for (int64_t i0 = 0; i0 < n; i0 += 256) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool ok = i < n && trans_ok(traj, ns, n, t, k, i, v_fb);
+    const uint64_t b = __ballot(ok);
+    if (lane == 0) wsum[wv] = __popcll(b);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    const int tot = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    if (ok) {
+      const int64_t s = base + before +
+          (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+      if (s < cap) {
+        float xa[MLP_OUT], xb[MLP_OUT];
+#pragma unroll
+        for (int r = 0; r < MLP_OUT; ++r) {
+          xa[r] = traj[(t * ns + r) * n + i];
+          xb[r] = traj[((t + k) * ns + r) * n + i];
+        }
+        xa[0] += traj[(t * ns + ns - 1) * n + i];
+        xb[0] += traj[((t + k) * ns + ns - 1) * n + i];
+        // the mean input exactly as the deployment kernel forms it
+        float sum = 0.0f;
+        for (int j = 0; j < k; ++j) sum += I[(t + j) * n + i];
+#pragma unroll
+        for (int r = 0; r < MLP_OUT; ++r) {
+          X[s * MLP_IN + r] = xa[r];
+          Y[s * MLP_OUT + r] = xb[r] - xa[r];
+        }
+        X[s * MLP_IN + MLP_OUT] = sum / (float)k;
+      }
+    }
+    base += tot;
+    __syncthreads();
+  }
 }
 
 }  // namespace
@@ -508,10 +702,13 @@ size_t hh_mlp_grad_workspace(int32_t S) {
   return (size_t)nb * (MLP_NPARAM + 1) * sizeof(float);
 }
 
-int32_t hh_mlp_grad(const float* params, const float* X, const float* Y, int32_t S,
-                    int32_t quantize, float* grad, float* loss, void* workspace,
-                    size_t workspace_bytes, void* stream) {
-  if (!params || !X || !Y || !grad) return HH_E_INVALID;
+static bool act_ok(int32_t act) { return act == HH_ACT_SILU || act == HH_ACT_HARDSWISH; }
+
+int32_t hh_mlp_grad(const float* params, const float* norm, const float* X, const float* Y,
+                    int32_t S, int32_t quantize, int32_t act, float* grad, float* loss,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  if (!params || !norm || !X || !Y || !grad) return HH_E_INVALID;
+  if (!act_ok(act)) return HH_E_INVALID;
   if (S < 1) return HH_E_SHAPE;
   if (!workspace || workspace_bytes < hh_mlp_grad_workspace(S)) return HH_E_SHAPE;
   int nb = (S + CH - 1) / CH;
@@ -522,20 +719,73 @@ int32_t hh_mlp_grad(const float* params, const float* X, const float* Y, int32_t
   float* part = (float*)workspace;
   float* lpart = part + (size_t)nb * MLP_NPARAM;
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, s, params, X, Y, S, per, quantize ? 1 : 0,
-                     part, lpart);
+  const int q = quantize ? 1 : 0;
+  if (act == HH_ACT_HARDSWISH)
+    hipLaunchKernelGGL(k_mlp_grad<MLP_ACT_HSWISH>, dim3(nb), dim3(256), 0, s, params, norm, X, Y, S,
+                       per, q, part, lpart);
+  else
+    hipLaunchKernelGGL(k_mlp_grad<MLP_ACT_SILU>, dim3(nb), dim3(256), 0, s, params, norm, X, Y, S,
+                       per, q, part, lpart);
   hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + RD_J - 1) / RD_J), dim3(RD_J * RD_G), 0, s,
                      part, lpart, nb, 1.0f / (float)S, grad, loss);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 
-int32_t hh_mlp_forward(const float* params, const float* X, int32_t S, int32_t quantize,
-                       float* Y, void* stream) {
-  if (!params || !X || !Y) return HH_E_INVALID;
+int32_t hh_mlp_forward(const float* params, const float* norm, const float* X, int32_t S,
+                       int32_t quantize, int32_t act, float* Y, void* stream) {
+  if (!params || !norm || !X || !Y) return HH_E_INVALID;
+  if (!act_ok(act)) return HH_E_INVALID;
   if (S < 0) return HH_E_SHAPE;
   if (S == 0) return HH_OK;
-  hipLaunchKernelGGL(k_mlp_fwd, dim3((S + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, X,
-                     S, quantize ? 1 : 0, Y);
+  const dim3 g((S + 255) / 256), b(256);
+  hipStream_t s = (hipStream_t)stream;
+  if (act == HH_ACT_HARDSWISH)
+    hipLaunchKernelGGL(k_mlp_fwd<MLP_ACT_HSWISH>, g, b, 0, s, params, norm, X, S, quantize ? 1 : 0, Y);
+  else
+    hipLaunchKernelGGL(k_mlp_fwd<MLP_ACT_SILU>, g, b, 0, s, params, norm, X, S, quantize ? 1 : 0, Y);
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+size_t hh_mlp_norm_workspace(void) { return (size_t)NB_NORM * NF * sizeof(double); }
+
+int32_t hh_mlp_norm(const float* X, const float* Y, int64_t S, float* norm, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+  if (!X || !Y || !norm) return HH_E_INVALID;
+  if (S < 1) return HH_E_SHAPE;
+  if (!workspace || workspace_bytes < hh_mlp_norm_workspace()) return HH_E_SHAPE;
+  hipStream_t s = (hipStream_t)stream;
+  double* part = (double*)workspace;
+  hipLaunchKernelGGL(k_norm_clear, dim3(1), dim3(64), 0, s, norm);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_norm_partial, dim3(NB_NORM), dim3(256), 0, s, X, Y, S, pass, norm, part);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, s, part, S, pass, norm);
+  }
+  return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
+}
+
+size_t hh_surrogate_transitions_workspace(int32_t T, int32_t k) {
+  if (T < 1 || k < 1 || k >= T) return 0;
+  return (size_t)(T - k + 1) * sizeof(int64_t);
+}
+
+int32_t hh_surrogate_transitions(const float* traj, int32_t n_state, const float* i_dense,
+                                 int64_t n, int32_t T, int32_t k, float v_fb, float* X, float* Y,
+                                 int64_t cap, int64_t* count, void* workspace,
+                                 size_t workspace_bytes, void* stream) {
+  if (!traj || !i_dense || !X || !Y || !count) return HH_E_INVALID;
+  if (n_state != 2 + MLP_OUT - 1) return HH_E_UNSUPPORTED;  // V, five gates, V_lo
+  if (n < 1 || T < 2 || k < 1 || k >= T || cap < 0) return HH_E_SHAPE;
+  if (!workspace || workspace_bytes < hh_surrogate_transitions_workspace(T, k)) return HH_E_SHAPE;
+  const int64_t rows = T - k;
+  int64_t* cnt = (int64_t*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_trans_count, dim3((unsigned)rows), dim3(256), 0, s, traj, n_state, n, k, v_fb,
+                     cnt);
+  hipLaunchKernelGGL(k_trans_scan, dim3(1), dim3(64), 0, s, cnt, rows);
+  hipLaunchKernelGGL(k_trans_write, dim3((unsigned)rows), dim3(256), 0, s, traj, n_state, n, k, v_fb,
+                     i_dense, cnt, cap, X, Y);
+  if (hipMemcpyAsync(count, cnt + rows, sizeof(int64_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return HH_E_HIP;
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 
@@ -548,12 +798,19 @@ int32_t hh_mlp_pack(const float* params, const float* norm, void* packed, void* 
 
 size_t hh_mlp_packed_bytes(void) { return sizeof(MlpPacked); }
 
-int32_t hh_mlp_infer(const void* packed, const float* X, int32_t S, float* Y, void* stream) {
+int32_t hh_mlp_infer(const void* packed, int32_t act, const float* X, int32_t S, float* Y,
+                     void* stream) {
   if (!packed || !X || !Y) return HH_E_INVALID;
+  if (!act_ok(act)) return HH_E_INVALID;
   if (S < 0) return HH_E_SHAPE;
   if (S == 0) return HH_OK;
-  hipLaunchKernelGGL(k_mlp_infer, dim3((S + 255) / 256), dim3(256), 0, (hipStream_t)stream,
-                     (const MlpPacked*)packed, X, S, Y);
+  const dim3 g((S + 255) / 256), b(256);
+  hipStream_t s = (hipStream_t)stream;
+  const MlpPacked* W = (const MlpPacked*)packed;
+  if (act == HH_ACT_HARDSWISH)
+    hipLaunchKernelGGL(k_mlp_infer<MLP_ACT_HSWISH>, g, b, 0, s, W, X, S, Y);
+  else
+    hipLaunchKernelGGL(k_mlp_infer<MLP_ACT_SILU>, g, b, 0, s, W, X, S, Y);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
 
@@ -579,6 +836,7 @@ namespace {
 constexpr int SB = 256;  // block size = compaction pool
 constexpr int KMAX = 32;  // steps per surrogate call (k * SB/32 <= SB threads clear the spike words)
 constexpr int SBW = SB / 32;  // spike words per block and step
+constexpr int kSBW = SB / 64;  // wavefronts per block
 
 struct SurArgs {
   float* state;
@@ -624,7 +882,7 @@ __device__ __forceinline__ float call_mean_input(const SurArgs& A, uint32_t nid,
   return sum / (float)A.k;
 }
 
-template <class S>
+template <class S, int ACT>
 __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
   constexpr int NG = S::kNG;
   __shared__ MlpPacked Ws;
@@ -670,7 +928,7 @@ __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
       for (int g = 0; g < NG && g < MLP_IN - 2; ++g) x[1 + g] = p[g];
       x[MLP_IN - 1] = call_mean_input(A, (uint32_t)ii, ii, tc, call);
       float dy[MLP_OUT];
-      mlp_infer_wave(Ws, x, dy);
+      mlp_infer_wave<ACT>(Ws, x, dy);
       pred[0] = x[0] + dy[0];
 #pragma unroll
       for (int g = 0; g < MLP_OUT - 1; ++g) pred[1 + g] = fminf(fmaxf(x[1 + g] + dy[1 + g], 0.0f), 1.0f);
@@ -696,13 +954,20 @@ __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
     }
     __syncthreads();  // pool of this call complete
     const int cnt = s_cnt[cb];
-    if (tid < cnt) {
+    // Pool slot this thread integrates: slots fill whole wavefronts (64 per
+    // wavefront, so the plain work runs on as few wavefronts as possible),
+    // and the wavefront that takes the first 64 slots rotates with the call.
+    // The waves of a block sit on different SIMDs, so the rotation spreads
+    // the plain work over all of them instead of loading one SIMD with the
+    // plain phase of every block.
+    const int slot = ((((tid >> 6) + kSBW - (call % kSBW)) % kSBW) << 6) | lane;
+    if (slot < cnt) {
       // dense plain integration of the compacted neurons
-      const int loc = sid[cb][tid];
+      const int loc = sid[cb][slot];
       const int64_t nid = blk0 + loc;
-      float wv = sv[cb][tid], wl = svl[cb][tid], wp[ng1<NG>];
+      float wv = sv[cb][slot], wl = svl[cb][slot], wp[ng1<NG>];
 #pragma unroll
-      for (int g = 0; g < NG; ++g) wp[g] = sp[cb][g][tid];
+      for (int g = 0; g < NG; ++g) wp[g] = sp[cb][g][slot];
       float z[4] = {0.f, 0.f, 0.f, 0.f};
       if (A.in_mode == IN_NOISE && (tc & 3)) {
         normals4(A.seed, (uint32_t)nid, (uint64_t)tc >> 2, z);
@@ -725,10 +990,10 @@ __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
         neuron_step<S>(M, L, dtC, wv, wl, wp, I, 0.0f, 0.0f);
         if (V < M.v_th && wv >= M.v_th) atomicOr(&sbits[j][loc >> 5], 1u << (loc & 31));
       }
-      sv[cb][tid] = wv;
-      svl[cb][tid] = wl;
+      sv[cb][slot] = wv;
+      svl[cb][slot] = wl;
 #pragma unroll
-      for (int g = 0; g < NG; ++g) sp[cb][g][tid] = wp[g];
+      for (int g = 0; g < NG; ++g) sp[cb][g][slot] = wp[g];
     }
     if (tid == 0) s_cnt[cb ^ 1] = 0;  // counter of the next call (last read before this call)
     __syncthreads();  // plain results and spike bits complete
@@ -786,12 +1051,14 @@ __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
 
 }  // namespace
 
-extern "C" int32_t hh_surrogate_step_n(hh_model* m, const void* mlp_packed, float* state,
+extern "C" int32_t hh_surrogate_step_n(hh_model* m, const void* mlp_packed, int32_t act,
+                                       float* state,
                                        uint8_t* flags, int64_t t0, int32_t n_steps, int32_t k,
                                        const hh_input* in, float v_fallback, int32_t check_every,
                                        float check_tol, uint32_t* spikes, uint64_t* stats,
                                        void* stream) {
   if (!m || !mlp_packed || !state || !flags || !in) return HH_E_INVALID;
+  if (act != HH_ACT_SILU && act != HH_ACT_HARDSWISH) return HH_E_INVALID;
   if (k < 1 || k > KMAX || n_steps < 0 || n_steps % k != 0 || t0 < 0 || check_every < 0)
     return HH_E_SHAPE;
   if (in->mode == HH_IN_CONST || in->mode == HH_IN_BACKGROUND || in->mode == HH_IN_SINE)
@@ -822,7 +1089,11 @@ extern "C" int32_t hh_surrogate_step_n(hh_model* m, const void* mlp_packed, floa
   a.stats = (unsigned long long*)stats;
   a.W = (const MlpPacked*)mlp_packed;
   const int64_t nb = (m->n + SB - 1) / SB;
-  hipLaunchKernelGGL(k_surrogate<CorticalSpec>, dim3((unsigned)nb), dim3(SB), 0, (hipStream_t)stream,
-                     m->km, a);
+  if (act == HH_ACT_HARDSWISH)
+    hipLaunchKernelGGL((k_surrogate<CorticalSpec, MLP_ACT_HSWISH>), dim3((unsigned)nb), dim3(SB), 0,
+                       (hipStream_t)stream, m->km, a);
+  else
+    hipLaunchKernelGGL((k_surrogate<CorticalSpec, MLP_ACT_SILU>), dim3((unsigned)nb), dim3(SB), 0,
+                       (hipStream_t)stream, m->km, a);
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }

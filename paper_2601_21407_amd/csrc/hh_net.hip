@@ -20,6 +20,12 @@
 // reads and writes of one step never meet; arrivals still in flight at the
 // end of a call stay in the ring for the next call.
 //
+// A population of B copies of one network (n = N B elements, copy b holding
+// elements b N .. b N + N - 1) shares the CSR of N rows: a spike of element
+// b N + j goes through row j to targets b N + col.  The copies are the
+// paper's parallel simulations of one network on one device; each draws
+// its own external and background streams, keyed by the element index.
+//
 // hh_syn_propagate runs the same delivery once, outside the time loop, as
 // three kernels: global compaction, one wavefront per spiking row, apply.
 #include <stdlib.h>
@@ -41,6 +47,7 @@ constexpr int kNetBlock = 512;
 struct NetArgs {
   float* state;
   int64_t n;
+  int64_t N;                // elements per copy (rows of the shared CSR)
   const int64_t* row_ptr;
   const int32_t* col;
   const float* w;
@@ -70,11 +77,11 @@ struct NetArgs {
 __device__ __forceinline__ void deliver_row(const int64_t* __restrict__ row_ptr,
                                             const int32_t* __restrict__ col,
                                             const float* __restrict__ w, float scale40, int j,
-                                            unsigned long long* acc_e, unsigned long long* acc_i,
-                                            int lane0, int stride) {
+                                            int base, unsigned long long* acc_e,
+                                            unsigned long long* acc_i, int lane0, int stride) {
   const int64_t r0 = row_ptr[j], r1 = row_ptr[j + 1];
   for (int64_t q = r0 + lane0; q < r1; q += stride) {
-    const int32_t tgt = col[q];
+    const int32_t tgt = base + col[q];
     const float wv = w[q];
     const unsigned long long inc = (unsigned long long)__float2ull_rn(fabsf(wv) * scale40);
     atomicAdd(wv > 0.0f ? &acc_e[tgt] : &acc_i[tgt], inc);
@@ -101,15 +108,17 @@ __device__ void block_inclusive_scan(int* v, int cnt) {
 }
 
 // Scatter of `total` synaptic events of the block's spiking rows: lane t
-// takes events t, t + B, t + 2B, ... (B = block size), issuing up to 8
+// takes events t, t + B, t + 2B, ... (B = block size), issuing up to 16
 // independent (col, w) loads before its atomics so the loads overlap.
+// s_base holds each spiking row's copy offset (b N), added to its targets.
 // DELAY: the events go to the ring slot (now + d) of their synapse's delay
 // d (clamped to [1, R - 1], so the slot always lies in the ring); acc_e is
 // then the ring's base and `now` the current time's slot.
 template <bool DELAY = false>
 __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
                                              const float* __restrict__ w, float scale40,
-                                             const int64_t* s_r0, const int* s_pre, int cnt,
+                                             const int64_t* s_r0, const int* s_pre,
+                                             const int* s_base, int cnt,
                                              int total, unsigned long long* acc_e,
                                              unsigned long long* acc_i,
                                              const uint8_t* __restrict__ delay = nullptr,
@@ -136,7 +145,7 @@ __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
         }
         const int before = lo ? s_pre[lo - 1] : 0;
         const int64_t q = s_r0[lo] + (x - before);
-        tg[u] = col[q];
+        tg[u] = s_base[lo] + col[q];
         wv[u] = w[q];
         if constexpr (DELAY) {
           const int d = min(max((int)delay[q], 1), R - 1);
@@ -221,6 +230,7 @@ template <class S, bool DELAY>
 __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   constexpr int NG = S::kNG;
   __shared__ int s_pre[kNetBlock];
+  __shared__ int s_base[kNetBlock];
   __shared__ int64_t s_r0[kNetBlock];
   __shared__ int s_cnt;
   __shared__ int s_ok;
@@ -242,13 +252,17 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   for (int g = 0; g < NG; ++g) p[g] = A.state[(int64_t)(1 + g) * n + ii];
   float ge = A.state[row_ge + ii], gi = A.state[row_gi + ii];
   const float I = A.i_const ? A.i_const[ii] : 0.0f;
-  const bool driven = A.ext_mask && act && A.ext_mask[i];
+  // element ii is neuron j of copy b: row j of the shared CSR, targets
+  // offset by b N
+  const int64_t jj = ii % A.N;
+  const int my_base = (int)(ii - jj);
+  const bool driven = A.ext_mask && act && A.ext_mask[jj];
   const float scale40 = A.w_scale * kFix;
   unsigned gen = 0;
   // this neuron's CSR row, read once: a spiking lane hands it to the
   // block's scatter without another dependent load
-  const int64_t my_r0 = A.row_ptr[ii];
-  const int my_len = (int)(A.row_ptr[ii + 1] - my_r0);
+  const int64_t my_r0 = A.row_ptr[jj];
+  const int my_len = (int)(A.row_ptr[jj + 1] - my_r0);
   int done = 0;  // steps whose barrier completed
   // ring slot of the current time (DELAY), advanced once per step
   int now = DELAY ? (int)(A.t0 % A.R) : 0;
@@ -294,6 +308,7 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
         // flatten the (row, synapse) pairs of all spiking rows of the block
         s_r0[base + rank] = my_r0;
         s_pre[base + rank] = my_len;
+        s_base[base + rank] = my_base;
       }
     }
     __syncthreads();
@@ -302,11 +317,11 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
       block_inclusive_scan(s_pre, cnt);
       const int total = s_pre[cnt - 1];
       if constexpr (DELAY) {
-        scatter_flat<true>(A.col, A.w, scale40, s_r0, s_pre, cnt, total, A.acc, nullptr, A.delay,
-                           now, A.R, n);
+        scatter_flat<true>(A.col, A.w, scale40, s_r0, s_pre, s_base, cnt, total, A.acc, nullptr,
+                           A.delay, now, A.R, n);
       } else {
         unsigned long long* acc_e = A.acc + (int64_t)(k & 1) * 2 * n;
-        scatter_flat(A.col, A.w, scale40, s_r0, s_pre, cnt, total, acc_e, acc_e + n);
+        scatter_flat(A.col, A.w, scale40, s_r0, s_pre, s_base, cnt, total, acc_e, acc_e + n);
       }
     }
 
@@ -371,7 +386,7 @@ __global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ bi
 
 // One wavefront per spiking source row.
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ list,
-                                                 const unsigned* count,
+                                                 const unsigned* count, int N,
                                                  const int64_t* __restrict__ row_ptr,
                                                  const int32_t* __restrict__ col,
                                                  const float* __restrict__ w, float scale40,
@@ -380,8 +395,10 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ lis
   const unsigned cnt = *count;
   const int lane = threadIdx.x & 63;
   const unsigned waves = gridDim.x * (blockDim.x >> 6);
-  for (unsigned e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); e < cnt; e += waves)
-    deliver_row(row_ptr, col, w, scale40, list[e], acc_e, acc_i, lane, 64);
+  for (unsigned e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); e < cnt; e += waves) {
+    const int src = list[e], j = src % N;
+    deliver_row(row_ptr, col, w, scale40, j, src - j, acc_e, acc_i, lane, 64);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_apply(float* __restrict__ ge, float* __restrict__ gi,
@@ -425,6 +442,7 @@ hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
 template <bool DELAY>
 static hipError_t launch_net_spec(hh_model* m, NetArgs& a, hipStream_t s) {
   if (m->use_fixed && ClassicSpec::matches(m->km)) return launch_net<ClassicSpec, DELAY>(m, a, s);
+  if (m->use_fixed && CorticalSpec::matches(m->km)) return launch_net<CorticalSpec, DELAY>(m, a, s);
   switch (m->km.n_gates) {
     case 1: return launch_net<GenericSpec<1>, DELAY>(m, a, s);
     case 2: return launch_net<GenericSpec<2>, DELAY>(m, a, s);
@@ -447,6 +465,7 @@ int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_
   memset(&a, 0, sizeof(a));
   a.state = state;
   a.n = m->n;
+  a.N = m->N;
   a.row_ptr = m->row_ptr;
   a.col = m->col;
   a.w = m->w;
@@ -500,7 +519,7 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
                       int64_t nnz, float w_scale) {
   if (!m || !row_ptr || (nnz > 0 && (!col || !w))) return HH_E_INVALID;
   if (!m->km.has_syn) return HH_E_INVALID;
-  if (m->B != 1 || nnz < 0) return HH_E_SHAPE;
+  if (nnz < 0) return HH_E_SHAPE;
   if (!(w_scale >= 0.0f) || !std::isfinite(w_scale)) return HH_E_INVALID;
   if (!m->d_scratch) {
     const size_t bytes = scratch_size(m->n);
@@ -593,8 +612,8 @@ int32_t hh_syn_propagate(hh_model* m, const uint32_t* spike_bits, float* state,
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)ncu * 8), dim3(256), 0, s, list, count, m->row_ptr,
-                     m->col, m->w, m->w_scale * kFix, acc_e, acc_i);
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)ncu * 8), dim3(256), 0, s, list, count, (int)m->N,
+                     m->row_ptr, m->col, m->w, m->w_scale * kFix, acc_e, acc_i);
   hipLaunchKernelGGL(k_apply, dim3(nb), dim3(256), 0, s, ge, gi, acc_e, acc_i, n);
   if (n_spikes_out)
     if (hipMemcpyAsync(n_spikes_out, count, sizeof(int32_t), hipMemcpyDeviceToDevice, s) !=

@@ -497,6 +497,6 @@ hipError_t launch_build_table(const hh_model* m, hipStream_t s) {
   D.dt = d.dt;
   const int count = d.n_gates * m->tab_n;
   hipLaunchKernelGGL(k_build_table, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, D,
-                     (double)m->tab_vlo, (double)m->tab_h, m->tab_n, m->d_tab);
+                     (double)m->tab_vlo, 1.0 / (double)m->tab_inv_h, m->tab_n, m->d_tab);
   return hipGetLastError();
 }

@@ -104,14 +104,19 @@ def _load():
         "hh_readout_ce_noalloc": ([vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp], i32),
         "hh_level_rate": ([vp, i64, i32, vp, vp], i32),
         "hh_adam_step": ([vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp], i32),
-        "hh_mlp_grad": ([vp, vp, vp, i32, i32, vp, vp, vp, sz, vp], i32),
+        "hh_mlp_grad": ([vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, sz, vp], i32),
         "hh_mlp_grad_workspace": ([i32], sz),
-        "hh_mlp_forward": ([vp, vp, i32, i32, vp, vp], i32),
+        "hh_mlp_forward": ([vp, vp, vp, i32, i32, i32, vp, vp], i32),
+        "hh_mlp_norm": ([vp, vp, i64, vp, vp, sz, vp], i32),
+        "hh_mlp_norm_workspace": ([], sz),
+        "hh_surrogate_transitions": ([vp, i32, vp, i64, i32, i32, f32, vp, vp, i64, vp, vp, sz, vp],
+                                     i32),
+        "hh_surrogate_transitions_workspace": ([i32, i32], sz),
         "hh_mlp_pack": ([vp, vp, vp, vp], i32),
         "hh_mlp_packed_bytes": ([], sz),
-        "hh_mlp_infer": ([vp, vp, i32, vp, vp], i32),
-        "hh_surrogate_step_n": ([vp, vp, vp, vp, i64, i32, i32, P(Input), f32, i32, f32, vp, vp, vp],
-                                i32),
+        "hh_mlp_infer": ([vp, i32, vp, i32, vp, vp], i32),
+        "hh_surrogate_step_n": ([vp, vp, i32, vp, vp, i64, i32, i32, P(Input), f32, i32, f32, vp, vp,
+                                 vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -137,6 +142,8 @@ def exported_symbols():
                         "hh_adam_step",
                         "hh_level_rate",
                         "hh_mlp_grad", "hh_mlp_grad_workspace", "hh_mlp_forward", "hh_mlp_pack",
+                        "hh_mlp_norm", "hh_mlp_norm_workspace", "hh_surrogate_transitions",
+                        "hh_surrogate_transitions_workspace",
                         "hh_mlp_packed_bytes", "hh_mlp_infer", "hh_surrogate_step_n")]
 
 
@@ -322,11 +329,17 @@ class Model:
                           ctypes.byref(out), _stream()), "hh_step_n")
 
     def attach_csr(self, row_ptr, col, w, w_scale: float):
+        """CSR over the N neurons of one copy (shared by the B copies)."""
+        _need(row_ptr, "row_ptr", (torch.int64,), self.N + 1, exact=True)
+        _need(col, "col", _I32, col.numel())
+        _need(w, "w", _F32, col.numel(), exact=True)
         self._keep += [row_ptr, col, w]
         _ok(lib.hh_attach_csr(self.h, _ptr(row_ptr), _ptr(col), _ptr(w), int(col.numel()),
                               float(w_scale)), "hh_attach_csr")
 
     def set_external(self, ext_mask, thresh: int, w_ext: float, seed: int):
+        """ext_mask: uint8 [N], shared by the copies."""
+        _need(ext_mask, "ext_mask", (torch.uint8,), self.N, exact=True)
         self._keep.append(ext_mask)
         _ok(lib.hh_set_external(self.h, _ptr(ext_mask), int(thresh), float(w_ext), int(seed)),
             "hh_set_external")
@@ -488,19 +501,72 @@ MLP_NPARAM = 5062
 MLP_IN, MLP_H, MLP_OUT = 7, 64, 6
 
 
-def mlp_grad(params, X, Y, grad, loss=None, quantize=True, workspace=None):
+ACT_SILU, ACT_HARDSWISH = 0, 1
+_ACTS = {"silu": ACT_SILU, "hardswish": ACT_HARDSWISH}
+
+
+def act_code(act) -> int:
+    """HH_ACT_* of an activation given by name ('silu', 'hardswish') or code."""
+    return _ACTS[act] if isinstance(act, str) else int(act)
+
+
+def _mlp_data(X, Y=None, norm=None):
+    _need(X, "X", _F32, X.shape[0] * MLP_IN, exact=True)
+    if Y is not None:
+        _need(Y, "Y", _F32, X.shape[0] * MLP_OUT, exact=True)
+    if norm is not None:
+        _need(norm, "norm", _F32, 32, exact=True)
+
+
+def mlp_grad(params, norm, X, Y, grad, loss=None, quantize=True, act="silu", workspace=None):
+    """MSE loss on the normalized targets and its parameter gradient; X [S][7]
+    and Y [S][6] are raw samples (see hh.h)."""
+    _mlp_data(X, Y, norm)
     S = X.shape[0]
     need = int(lib.hh_mlp_grad_workspace(S))
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
-    _ok(lib.hh_mlp_grad(_ptr(params), _ptr(X), _ptr(Y), S, 1 if quantize else 0, _ptr(grad),
-                        _ptr(loss), _ptr(workspace), workspace.numel(), _stream()), "hh_mlp_grad")
+    _ok(lib.hh_mlp_grad(_ptr(params), _ptr(norm), _ptr(X), _ptr(Y), S, 1 if quantize else 0,
+                        act_code(act), _ptr(grad), _ptr(loss), _ptr(workspace), workspace.numel(),
+                        _stream()), "hh_mlp_grad")
     return workspace
 
 
-def mlp_forward(params, X, Y, quantize=True):
-    _ok(lib.hh_mlp_forward(_ptr(params), _ptr(X), X.shape[0], 1 if quantize else 0, _ptr(Y),
-                           _stream()), "hh_mlp_forward")
+def mlp_forward(params, norm, X, Y, quantize=True, act="silu"):
+    """VALU forward on raw inputs; Y receives the de-normalized outputs."""
+    _mlp_data(X, Y, norm)
+    _ok(lib.hh_mlp_forward(_ptr(params), _ptr(norm), _ptr(X), X.shape[0], 1 if quantize else 0,
+                           act_code(act), _ptr(Y), _stream()), "hh_mlp_forward")
+
+
+def mlp_norm(X, Y):
+    """Feature normalization [32] of a training set (mean and standard
+    deviation per feature, computed in the library)."""
+    _mlp_data(X, Y)
+    norm = torch.empty(32, dtype=torch.float32, device=X.device)
+    ws = torch.empty(int(lib.hh_mlp_norm_workspace()), dtype=torch.uint8, device=X.device)
+    _ok(lib.hh_mlp_norm(_ptr(X), _ptr(Y), X.shape[0], _ptr(norm), _ptr(ws), ws.numel(), _stream()),
+        "hh_mlp_norm")
+    return norm
+
+
+def surrogate_transitions(traj, i_dense, k: int, v_fb: float, cap: int):
+    """Training samples from plain trajectories (see hh.h): traj [T][7][n] the
+    state before every step, i_dense [T][n].  Returns (X [S][7], Y [S][6]),
+    S = min(qualifying samples, cap)."""
+    T, ns, n = traj.shape
+    _need(traj, "traj", _F32, T * ns * n, exact=True)
+    _need(i_dense, "i_dense", _F32, T * n, exact=True)
+    X = torch.empty((cap, MLP_IN), dtype=torch.float32, device=traj.device)
+    Y = torch.empty((cap, MLP_OUT), dtype=torch.float32, device=traj.device)
+    count = torch.zeros(1, dtype=torch.int64, device=traj.device)
+    ws = torch.empty(max(int(lib.hh_surrogate_transitions_workspace(T, k)), 1), dtype=torch.uint8,
+                     device=traj.device)
+    _ok(lib.hh_surrogate_transitions(_ptr(traj), ns, _ptr(i_dense), n, T, int(k), float(v_fb),
+                                     _ptr(X), _ptr(Y), int(cap), _ptr(count), _ptr(ws), ws.numel(),
+                                     _stream()), "hh_surrogate_transitions")
+    S = min(int(count.item()), cap)
+    return X[:S], Y[:S]
 
 
 def mlp_pack(params, norm):
@@ -509,20 +575,22 @@ def mlp_pack(params, norm):
     return packed
 
 
-def mlp_infer(packed, X, Y):
-    _ok(lib.hh_mlp_infer(_ptr(packed), _ptr(X), X.shape[0], _ptr(Y), _stream()), "hh_mlp_infer")
+def mlp_infer(packed, X, Y, act="silu"):
+    _mlp_data(X, Y)
+    _ok(lib.hh_mlp_infer(_ptr(packed), act_code(act), _ptr(X), X.shape[0], _ptr(Y), _stream()),
+        "hh_mlp_infer")
 
 
 def surrogate_step_n(model: Model, packed, state, flags, n_steps: int, k: int, t0: int = 0, *,
                      noise=None, i_dense=None, v_fallback=-50.0, check_every=10, check_tol=0.5,
-                     spikes=None, stats=None):
+                     spikes=None, stats=None, act="silu"):
     inp = Input()
     if i_dense is not None:
         inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
     else:
         inp.mode = IN_NOISE
         inp.mu, inp.sigma, inp.seed = float(noise[0]), float(noise[1]), int(noise[2])
-    _ok(lib.hh_surrogate_step_n(model.h, _ptr(packed), _ptr(state), _ptr(flags), int(t0),
+    _ok(lib.hh_surrogate_step_n(model.h, _ptr(packed), act_code(act), _ptr(state), _ptr(flags), int(t0),
                                 int(n_steps), int(k), ctypes.byref(inp), float(v_fallback),
                                 int(check_every), float(check_tol), _ptr(spikes), _ptr(stats),
                                 _stream()), "hh_surrogate_step_n")

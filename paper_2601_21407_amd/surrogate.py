@@ -3,8 +3,11 @@ the plain fused kernel, training with the library's MLP forward/backward and
 Adam kernels, packing for the MFMA inference, deployment with per-neuron
 fallback, and the spike-time comparison against the plain integrator.
 
-Every numerical step runs in libhh kernels; torch is used to hold device
-buffers and to slice/stack the training set.
+Every step of the method runs in libhh kernels: the plain trajectories, the
+transition samples and their mean input, the feature normalization, the
+network's forward and backward, Adam, the inference and the deployment.
+torch holds device buffers, draws the seeded synthetic input currents and
+the minibatch permutation, and gathers minibatches.
 """
 from __future__ import annotations
 
@@ -22,12 +25,15 @@ CHECK_EVERY = 10      # calls
 CHECK_TOL = 0.5       # mV
 
 
+ACT = "hardswish"     # hidden activation of the deployed network (or "silu")
+
+
 def generate_transitions(n_traj=5000, T=10000, seed=5, seg=400, k=K_STEPS, dev="cuda"):
     """Trajectories of the plain FP32 kernel (cortical set, nominal rates,
     dt = 0.025 ms) under piecewise-constant currents U[0, 20) plus 3 z per
     step; every step t with V <= -50 mV at t and t + k gives one transition
-    (x_t, mean I over [t, t+k)) -> x_{t+k} - x_t.  Returns (X [S,7], dY [S,6])
-    on the device (FP32, un-normalized)."""
+    (x_t, mean I over [t, t+k)) -> x_{t+k} - x_t, formed by the library.
+    Returns (X [S,7], dY [S,6]) on the device (FP32, un-normalized)."""
     m = W.custom_channels(dt=0.025)
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
@@ -45,27 +51,13 @@ def generate_transitions(n_traj=5000, T=10000, seed=5, seg=400, k=K_STEPS, dev="
     status, bad = M.check()
     if status != 0:
         raise RuntimeError("plain kernel failed while generating data (%d)" % status)
-    # state rows: V, m, h, n, p, q, V_lo
-    x = torch.cat([(traj[:, 0:1] + traj[:, 6:7]), traj[:, 1:6]], dim=1)  # [T, 6, n]
-    csum = torch.cumsum(torch.cat([torch.zeros((1, n_traj), device=dev), I.double()], 0), 0)
-    ibar = ((csum[k:] - csum[:-k]) / k).float()  # [T-k+1, n]: mean over [t, t+k)
-    xa, xb = x[:T - k], x[k:]
-    ib = ibar[:T - k]
-    ok = (xa[:, 0] <= V_FALLBACK) & (xb[:, 0] <= V_FALLBACK)
-    X = torch.cat([xa.permute(0, 2, 1), ib.unsqueeze(2)], dim=2)[ok]  # [S, 7]
-    dY = (xb - xa).permute(0, 2, 1)[ok]  # [S, 6]
-    return X.contiguous(), dY.contiguous()
+    return hh.surrogate_transitions(traj, I, k, V_FALLBACK, (T - k) * n_traj)
 
 
 def norm_stats(X, dY):
-    """Per-feature mean and standard deviation: norm[0:7] input mean, [8:15]
-    input std, [16:22] output mean, [24:30] output std."""
-    norm = torch.zeros(32, device=X.device)
-    norm[0:7] = X.mean(0)
-    norm[8:15] = X.std(0).clamp_min(1e-6)
-    norm[16:22] = dY.mean(0)
-    norm[24:30] = dY.std(0).clamp_min(1e-9)
-    return norm
+    """Per-feature mean and standard deviation (library kernel): norm[0:7]
+    input mean, [8:15] input std, [16:22] output mean, [24:30] output std."""
+    return hh.mlp_norm(X, dY)
 
 
 def init_params(seed=0, dev="cuda"):
@@ -78,12 +70,10 @@ def init_params(seed=0, dev="cuda"):
     return torch.tensor(p, device=dev)
 
 
-def train(X, dY, norm, *, epochs=8, batch=16384, lr=2e-3, seed=0, log=None):
+def train(X, dY, norm, *, epochs=8, batch=16384, lr=2e-3, seed=0, act=ACT, log=None):
     """Adam on the normalized MSE with bf16-quantized forward (the deployed
     numerics).  Returns (params, history of mean epoch losses)."""
     dev = X.device
-    Xn = ((X - norm[0:7]) / norm[8:15]).contiguous()
-    Yn = ((dY - norm[16:22]) / norm[24:30]).contiguous()
     S = X.shape[0]
     params = init_params(seed, dev)
     grad = torch.zeros_like(params)
@@ -102,8 +92,8 @@ def train(X, dY, norm, *, epochs=8, batch=16384, lr=2e-3, seed=0, log=None):
         nb = S // batch
         for b in range(nb):
             idx = perm[b * batch:(b + 1) * batch]
-            xb, yb = Xn[idx].contiguous(), Yn[idx].contiguous()
-            ws = hh.mlp_grad(params, xb, yb, grad, loss, quantize=True, workspace=ws)
+            xb, yb = X[idx].contiguous(), dY[idx].contiguous()
+            ws = hh.mlp_grad(params, norm, xb, yb, grad, loss, quantize=True, act=act, workspace=ws)
             step += 1
             # cosine decay of the learning rate
             lr_t = lr * 0.5 * (1.0 + np.cos(np.pi * step / total))
@@ -115,13 +105,13 @@ def train(X, dY, norm, *, epochs=8, batch=16384, lr=2e-3, seed=0, log=None):
     return params, hist
 
 
-def evaluate(params, X, dY, norm):
-    """Normalized MSE of the quantized forward on a held-out set."""
-    Xn = ((X - norm[0:7]) / norm[8:15]).contiguous()
-    Yn = ((dY - norm[16:22]) / norm[24:30]).contiguous()
-    Y = torch.empty_like(Yn)
-    hh.mlp_forward(params, Xn, Y, quantize=True)
-    return float(((Y - Yn) ** 2).sum(1).mean().item())
+def evaluate(params, X, dY, norm, act=ACT):
+    """Normalized MSE of the quantized network on a held-out set (the loss
+    of the library's gradient kernel)."""
+    grad = torch.empty_like(params)
+    loss = torch.zeros(1, device=X.device)
+    hh.mlp_grad(params, norm, X.contiguous(), dY.contiguous(), grad, loss, quantize=True, act=act)
+    return float(loss.item())
 
 
 def spike_time_error(ref_bits, bits, n, dt_ref, dt_test, window_ms=2.0, max_neurons=None):
@@ -168,7 +158,7 @@ def spike_time_error(ref_bits, bits, n, dt_ref, dt_test, window_ms=2.0, max_neur
 
 
 def deploy(packed, n, T, *, i_dense=None, noise=None, spikes=True, check_every=CHECK_EVERY,
-           v_fallback=V_FALLBACK, check_tol=CHECK_TOL, k=K_STEPS, dev="cuda"):
+           v_fallback=V_FALLBACK, check_tol=CHECK_TOL, k=K_STEPS, act=ACT, dev="cuda"):
     """Run the surrogate deployment kernel on n neurons (cortical set,
     nominal rates) for T plain-step equivalents, k steps per call.  Returns (model, state,
     spike bits or None, stats [surrogate calls, plain calls, failed checks])."""
@@ -181,7 +171,7 @@ def deploy(packed, n, T, *, i_dense=None, noise=None, spikes=True, check_every=C
     stats = torch.zeros(3, dtype=torch.int64, device=dev)
     hh.surrogate_step_n(M, packed, st, flags, T, k, 0, i_dense=i_dense, noise=noise,
                         v_fallback=v_fallback, check_every=check_every, check_tol=check_tol,
-                        spikes=bits, stats=stats)
+                        spikes=bits, stats=stats, act=act)
     return M, st, bits, stats
 
 

@@ -27,11 +27,36 @@ import numpy as np
 # ---------------------------------------------------------------------------
 # channel tables
 # ---------------------------------------------------------------------------
+def _f32(x: float) -> float:
+    """x as the nearest binary32 value (values beyond its range become
+    infinite, as in the descriptor)."""
+    with np.errstate(over="ignore"):
+        return float(np.float32(x))
+
+
+def binary32_model(model: dict) -> dict:
+    """The model with every numeric parameter rounded to binary32.  The
+    library's descriptor carries binary32 values, so a model is defined by
+    those values: the oracle then integrates exactly the parameters the
+    library integrates (0.1 and 0.3, for instance, differ from their binary32
+    neighbours by up to 3e-8, coherently at every step)."""
+    m = copy.deepcopy(model)
+    for g in m["gates"]:
+        g["rates"] = [(r[0],) + tuple(_f32(x) for x in r[1:]) for r in g["rates"]]
+    for c in m["channels"]:
+        c["gbar"], c["E"] = _f32(c["gbar"]), _f32(c["E"])
+    for key in ("C", "dt", "v_th"):
+        m[key] = _f32(m[key])
+    if m.get("syn"):
+        m["syn"] = {k: _f32(v) for k, v in m["syn"].items()}
+    return m
+
+
 def classic_hh(dt: float = 0.01, v_method: str = "fe", C: float = 1.0, syn=None) -> dict:
     """Hodgkin & Huxley (1952) squid axon in the modern -65 mV resting
     convention: Na (m^3 h, 120 mS/cm^2, +50 mV), K (n^4, 36, -77), leak
     (0.3, -54.4)."""
-    return {
+    return binary32_model({
         "gates": [
             {"kind": "ab", "rates": [("linoid", 0.1, -40.0, 10.0, 0.0), ("exp", 4.0, -65.0, -18.0, 0.0)]},
             {"kind": "ab", "rates": [("exp", 0.07, -65.0, -20.0, 0.0), ("sigmoid", 1.0, -35.0, -10.0, 0.0)]},
@@ -43,7 +68,7 @@ def classic_hh(dt: float = 0.01, v_method: str = "fe", C: float = 1.0, syn=None)
             {"gbar": 0.3, "E": -54.4, "gates": []},
         ],
         "C": C, "dt": dt, "v_th": 0.0, "v_method": v_method, "syn": syn,
-    }
+    })
 
 
 V_T = -56.2  # spike-threshold offset of the cortical channel set
@@ -55,7 +80,7 @@ def custom_channels(dt: float = 0.025, v_method: str = "fe") -> dict:
     bell-shaped time constant), L-type Ca (q^2) and leak.  Conductances are
     this project's own choice, tuned so that 5 uA/cm^2 with noise fires
     tonically at about 20 Hz."""
-    return {
+    return binary32_model({
         "gates": [
             {"kind": "ab", "rates": [("linoid", 0.32, V_T + 13.0, 4.0, 0.0),
                                      ("linoid", -0.28, V_T + 40.0, -5.0, 0.0)]},
@@ -76,7 +101,7 @@ def custom_channels(dt: float = 0.025, v_method: str = "fe") -> dict:
             {"gbar": 0.15, "E": -70.0, "gates": []},
         ],
         "C": 1.0, "dt": dt, "v_th": 0.0, "v_method": v_method, "syn": None,
-    }
+    })
 
 
 def soma_dendrites(model: dict, n_dend: int = 3, per_dend: int = 5, g_axial: float = 1.5,
@@ -96,15 +121,15 @@ def soma_dendrites(model: dict, n_dend: int = 3, per_dend: int = 5, g_axial: flo
         parent += list(range(first, first + per_dend - 1))
     K = len(parent)
     g0 = np.array([c["gbar"] for c in model["channels"]], dtype=np.float64)
-    gbar = np.vstack([g0] + [density * g0] * (K - 1))
-    return {"K": K, "parent": parent, "g_axial": [0.0] + [g_axial] * (K - 1),
-            "area": [soma_area] + [1.0] * (K - 1), "gbar": gbar}
+    gbar = np.vstack([g0] + [density * g0] * (K - 1)).astype(np.float32).astype(np.float64)
+    return {"K": K, "parent": parent, "g_axial": [0.0] + [_f32(g_axial)] * (K - 1),
+            "area": [_f32(soma_area)] + [1.0] * (K - 1), "gbar": gbar}
 
 
 def with_synapses(model: dict, tau_e=5.0, tau_i=10.0, E_e=0.0, E_i=-80.0) -> dict:
     m = copy.deepcopy(model)
     m["syn"] = {"tau_e": tau_e, "tau_i": tau_i, "E_e": E_e, "E_i": E_i}
-    return m
+    return binary32_model(m)
 
 
 def coef_table(model: dict) -> np.ndarray:

@@ -291,7 +291,10 @@ def judge(O, model, st0, T, g, ro, kw, *, max_excused_frac, v_tol=1e-3, label=""
     print(rep, flush=True)
     record_judge(label, n, excused, len(fails), len(s_exc),
                  "cap %d" % int(max_excused_frac * n))
-    detail = [(int(i), float(dv[i])) for i in fails[:10]]
+    detail = [(int(i), float(dv[i])) if i in set(q_fail.tolist()) else
+              (int(i), "gpu spike steps", np.nonzero(g["raster"][:, i])[0][:8].tolist(),
+               "oracle", np.nonzero(ro["spikes"][:, i])[0][:8].tolist())
+              for i in fails[:10]]
     assert not fails, (rep, detail)
     assert excused <= max_excused_frac * n, rep
     return rep

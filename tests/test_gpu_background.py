@@ -133,6 +133,6 @@ def test_background_errors():
     inp = hh.Input()
     inp.mode, inp.lam, inp.mu, inp.sigma, inp.seed = hh.IN_BACKGROUND, 1.0, 1.0, 1.0, 1
     import ctypes
-    rc = hh.lib.hh_surrogate_step_n(Mc.h, hh._ptr(packed), hh._ptr(stc), hh._ptr(flags), 0, 10, 10,
+    rc = hh.lib.hh_surrogate_step_n(Mc.h, hh._ptr(packed), hh.ACT_SILU, hh._ptr(stc), hh._ptr(flags), 0, 10, 10,
                                     ctypes.byref(inp), -50.0, 10, 0.5, None, None, hh._stream())
     assert rc == -5

@@ -358,3 +358,140 @@ def test_network_delay_errors():
     again, _ = _run_on(M, v0, 300, i_const=np.full(n, 9.0))
     assert ref.sum() > 0 and not np.array_equal(delayed, ref) and np.array_equal(again, ref)
     del torch, bufs
+
+
+# ---------------------------------------------------------------------------
+# a batch of independent copies of one network sharing the CSR (the paper's
+# parallel simulations on one device), and the compiled cortical channel set
+# ---------------------------------------------------------------------------
+def _block_diagonal(csr, B):
+    """The CSR of B disjoint copies of a network (copy b's targets + b N)."""
+    rp, col, w = csr
+    N = len(rp) - 1
+    nnz = len(col)
+    rpb = np.concatenate([rp[:-1] + b * nnz for b in range(B)] + [[B * nnz]]).astype(np.int64)
+    colb = np.concatenate([col + b * N for b in range(B)]).astype(np.int32)
+    return rpb, colb, np.tile(w, B)
+
+
+def _batch_gpu(m, csr, scale, v0, T, B, *, ext=None, specialize=True, background=None):
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    N = len(csr[0]) - 1
+    M = hh.Model(m, N, B)
+    M.set_specialize(specialize)
+    bufs = [_dev(csr[0]), _dev(csr[1]), _dev(csr[2].astype(np.float32))]
+    M.attach_csr(bufs[0], bufs[1], bufs[2], scale)
+    if ext is not None:
+        em = _dev(ext[0])
+        bufs.append(em)
+        M.set_external(em, ext[1], ext[2], ext[3])
+    st = M.new_state()
+    M.init_state(st, v0=_dev(v0.astype(np.float32)))
+    spikes = torch.zeros((T, M.words), dtype=torch.int32, device="cuda")
+    M.step_n(st, T, 0, spikes=spikes, background=background)
+    status, bad = M.check()
+    assert status == 0, (status, bad)
+    return O.unpack_bits(spikes.cpu().numpy().view(np.uint32), M.n), st.cpu().numpy()
+
+
+def test_network_batch_of_copies_matches_oracle():
+    """B = 3 copies of a 1,000-neuron network share one CSR, each with its own
+    initial state and its own external-event stream (keyed by the element
+    index): spike-exact to the predictability horizon against the oracle's
+    run of the block-diagonal network of the three copies."""
+    print_case("network batch B=3 N=1000 fan=100")
+    m = W.net_model()
+    N, B, T = 1000, 3, 1500
+    csr = W.net_csr(n=N, fan_out=100, seed=6, inh_scale=4.0)
+    mask, thr = W.net_external(n=N, frac=0.05, seed=6)
+    v0 = W.net_v0(N * B, 6).astype(np.float64)
+    scale = 0.3
+    raster, _ = _batch_gpu(m, csr, scale, v0, T, B, ext=(mask, thr, 0.5, 6))
+    big = _block_diagonal(csr, B)
+    h, ref = _horizon(m, big, scale, v0, T, (np.tile(mask, B), thr, 0.5, 6))
+    assert ref.sum() > 5 * N * B * T * 1e-4
+    assert h >= 0.9 * T, h
+    bad = spike_mismatch(raster[:h - 1], ref[:h - 1])
+    print("batch horizon %d of %d, spikes per copy %s, mismatched %d"
+          % (h, T, [int(ref[:, b * N:(b + 1) * N].sum()) for b in range(B)], len(bad)), flush=True)
+    assert len(bad) == 0
+    # the copies differ (own states and streams)
+    assert not np.array_equal(raster[:, :N], raster[:, N:2 * N])
+
+
+def test_network_batch_identical_copies_equal_single_run():
+    """Copies with the same initial state and input and no random drive run
+    exactly like the single network, bit for bit (fixed-point arrivals do
+    not depend on the order of the atomics)."""
+    print_case("network batch identical copies B=4")
+    m = W.net_model()
+    N, B, T = 800, 4, 800
+    csr = W.net_csr(n=N, fan_out=80, seed=9, inh_scale=4.0)
+    v0 = W.net_v0(N, 9).astype(np.float64)
+    r1, s1 = _batch_gpu(m, csr, 0.5, v0, T, 1, background=(1.0, 2.0, 1.0, 4))
+    # background keyed by the element index: copy 0 equals the single run
+    rB, sB = _batch_gpu(m, csr, 0.5, np.tile(v0, B), T, B, background=(1.0, 2.0, 1.0, 4))
+    assert r1.sum() > 0
+    assert np.array_equal(rB[:, :N], r1)
+    assert np.array_equal(sB[:, :N], s1)
+    # and without random drive every copy equals copy 0
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    Mq = hh.Model(m, N, B)
+    bufs = [_dev(csr[0]), _dev(csr[1]), _dev(csr[2].astype(np.float32))]
+    Mq.attach_csr(bufs[0], bufs[1], bufs[2], 0.5)
+    st = Mq.new_state()
+    Mq.init_state(st, v0=_dev(np.tile(v0, B).astype(np.float32)))
+    spikes = torch.zeros((T, Mq.words), dtype=torch.int32, device="cuda")
+    Mq.step_n(st, T, 0, spikes=spikes, i_const=_dev(np.full(N * B, 9.0, np.float32)))
+    rq = O.unpack_bits(spikes.cpu().numpy().view(np.uint32), N * B)
+    sq = st.cpu().numpy()
+    assert rq.sum() > 0
+    for b in range(1, B):
+        assert np.array_equal(rq[:, b * N:(b + 1) * N], rq[:, :N])
+        assert np.array_equal(sq[:, b * N:(b + 1) * N], sq[:, :N])
+
+
+def test_network_batch_too_large_is_refused():
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    m = W.net_model()
+    N, B = 38000, 64  # 2.4 M neurons: more than one co-resident grid holds
+    csr = (np.zeros(N + 1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    M = hh.Model(m, N, B)
+    bufs = [_dev(csr[0]), _dev(np.zeros(1, np.int32)), _dev(np.zeros(1, np.float32))]
+    M.attach_csr(bufs[0], bufs[1][:0], bufs[2][:0], 0.1)
+    st = M.new_state()
+    M.init_state(st, v0_scalar=-65.0)
+    with pytest.raises(hh.HHError) as e:
+        M.step_n(st, 5)
+    assert e.value.status == -5
+
+
+@pytest.mark.parametrize("specialize", [True, False])
+def test_cortical_network_spike_exact_to_horizon(specialize):
+    """The cortical channel set (Na, Kd, M, L-Ca, leak; exponential Euler in
+    V at dt = 0.1 ms) in the network kernel: the compiled variant and the
+    run-time interpreter, spike-exact to the predictability horizon against
+    the oracle, with one-step delays and background input."""
+    print_case("cortical network specialize=%s" % specialize)
+    m = W.with_synapses(W.custom_channels(dt=0.1, v_method="ee"))
+    n, T = 1200, 1500
+    csr = W.net_csr(n=n, fan_out=120, seed=14, inh_scale=4.0)
+    v0 = W.net_v0(n, 14).astype(np.float64)
+    scale = 0.3
+    bg = (2.0, 3.0, 2.0)  # about 40 Hz
+    raster, _ = _batch_gpu(m, csr, scale, v0, T, 1, specialize=specialize,
+                           background=bg + (15,))
+    kw = dict(background=bg, in_seed=15)
+    h, ref = _horizon_kw(m, csr, scale, v0, T, kw)
+    assert ref.sum() > 10 * n * T * 1e-4, ref.sum()
+    # the oracle's own raster first changes under the probes near step 600
+    # of this faster-firing network: several thousand spikes lie before it
+    assert h >= 400, h
+    assert ref[:h].sum() > 1000
+    bad = spike_mismatch(raster[:h - 1], ref[:h - 1])
+    print("cortical horizon %d of %d, spikes %d, mismatched %d" % (h, T, int(ref.sum()), len(bad)),
+          flush=True)
+    assert len(bad) == 0

@@ -1,9 +1,10 @@
-"""GPU checks of the learned surrogate: the MLP training kernel's loss and
-gradient against the FP64 oracle (and against an FP64 emulation of the bf16
-rounding it applies), the MFMA inference against the VALU forward, the
-deployment kernel's plumbing against the plain integrator, and a short
-end-to-end training run whose deployment is judged by the plain integrator.
-"""
+"""GPU checks of the learned surrogate against the FP64 oracle: the MLP
+training kernel's loss and gradient (plain and with the bf16 roundings of
+the deployed network), the MFMA inference against the oracle's network on
+the same bf16 values, the training-set kernels (transitions, normalization),
+the deployment policy against the oracle's binary64 run of that policy, and
+a short end-to-end training run whose deployment the plain integrator
+judges.  Each network check runs for both hidden activations."""
 import numpy as np
 import pytest
 
@@ -13,11 +14,13 @@ from tests.gpu_util import need_gpu, print_case
 
 pytestmark = pytest.mark.gpu
 
+ACTS = ["silu", "hardswish"]
 
-def _rand_params(rng):
+
+def _rand_params(rng, scale=1.0):
     ps = []
     for a, b in ((7, 64), (64, 64), (64, 6)):
-        ps += [rng.standard_normal((a, b)) / np.sqrt(a), 0.1 * rng.standard_normal(b)]
+        ps += [scale * rng.standard_normal((a, b)) / np.sqrt(a), 0.1 * rng.standard_normal(b)]
     return ps
 
 
@@ -25,79 +28,93 @@ def _flat(ps):
     return np.concatenate([p.reshape(-1) for p in ps]).astype(np.float32)
 
 
-def _unflat(v):
-    out, off = [], 0
-    for a, b in ((7, 64), (64, 64), (64, 6)):
-        out.append(v[off: off + a * b].reshape(a, b))
-        off += a * b
-        out.append(v[off: off + b])
-        off += b
-    return out
+def _norm(rng):
+    """A plausible normalization of the cortical surrogate's features."""
+    norm = np.zeros(32, np.float32)
+    norm[0:7] = [-62, 0.05, 0.6, 0.3, 0.05, 0.01, 5]
+    norm[8:15] = [5, 0.02, 0.1, 0.1, 0.02, 0.005, 3]
+    norm[16:22] = 0.01 * rng.standard_normal(6)
+    norm[24:30] = 0.1 + rng.random(6)
+    return norm
 
 
-def _bf(x):
-    return W.bf16_round(np.asarray(x, np.float32)).astype(np.float64)
+def _raw_inputs(rng, norm, S):
+    return (norm[0:7] + norm[8:15] * rng.standard_normal((S, 7))).astype(np.float32)
 
 
+def _dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def _normalized(norm, X, Y):
+    """The normalization the kernels apply, in binary64 from the same FP32
+    statistics: (x - mean) / std."""
+    n64 = norm.astype(np.float64)
+    Xn = (X.astype(np.float64) - n64[0:7]) / n64[8:15]
+    Yn = (Y.astype(np.float64) - n64[16:22]) / n64[24:30]
+    return Xn, Yn
+
+
+@pytest.mark.parametrize("act", ACTS)
 @pytest.mark.parametrize("S", [1, 100, 1000, 70001])
-def test_mlp_grad_matches_oracle(S):
-    print_case("mlp grad S=%d" % S)
+def test_mlp_grad_matches_oracle(S, act):
+    print_case("mlp grad S=%d act=%s" % (S, act))
     torch = need_gpu()
     from paper_2601_21407_amd import hh
     rng = np.random.default_rng(S)
     flat = _flat(_rand_params(rng))
-    X = rng.standard_normal((S, 7)).astype(np.float32)
-    Y = rng.standard_normal((S, 6)).astype(np.float32)
-    dev = lambda a: torch.tensor(a, device="cuda")
+    norm = _norm(rng)
+    X = _raw_inputs(rng, norm, S)
+    Y = (norm[16:22] + norm[24:30] * rng.standard_normal((S, 6))).astype(np.float32)
     g = torch.zeros(hh.MLP_NPARAM, device="cuda")
     loss = torch.zeros(1, device="cuda")
-    hh.mlp_grad(dev(flat), dev(X), dev(Y), g, loss, quantize=False)
-    ps = _unflat(flat.astype(np.float64))
-    y, cache = O.mlp_forward(ps, X)
-    L, dy = O.mse_loss_grad(y, Y)
+    hh.mlp_grad(_dev(torch, flat), _dev(torch, norm), _dev(torch, X), _dev(torch, Y), g, loss,
+                quantize=False, act=act)
+    ps = O.mlp_split(flat)
+    Xn, Yn = _normalized(norm, X, Y)
+    y, cache = O.mlp_forward(ps, Xn, act=act)
+    L, dy = O.mse_loss_grad(y, Yn)
     grads, _ = O.mlp_backward(ps, cache, dy)
     ref = np.concatenate([q.reshape(-1) for q in grads])
     got = g.cpu().numpy()
     assert abs(loss.item() - L) <= 1e-5 * L
     assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
-    # the plain forward
+    # the plain VALU forward (de-normalized outputs)
     Yg = torch.empty((S, 6), device="cuda")
-    hh.mlp_forward(dev(flat), dev(X), Yg, quantize=False)
-    assert np.allclose(Yg.cpu().numpy(), y, rtol=1e-5, atol=1e-5)
+    hh.mlp_forward(_dev(torch, flat), _dev(torch, norm), _dev(torch, X), Yg, quantize=False,
+                   act=act)
+    ref_y = O.mlp_apply(ps, norm, X, act=act)
+    err = np.abs(Yg.cpu().numpy() - ref_y) / norm[24:30]
+    assert err.max() < 1e-5, err.max()
 
 
-def test_mlp_grad_quantized_matches_emulation():
+@pytest.mark.parametrize("act", ACTS)
+def test_mlp_grad_quantized_matches_oracle(act):
     """quantize=1: weights, hidden activations and the input split rounded to
-    bf16 exactly as the MFMA inference does; compared with an FP64 emulation
-    of those roundings (straight-through gradient)."""
+    bf16 as the MFMA inference does; against the oracle's network on the
+    same bf16 values (straight-through gradient)."""
     torch = need_gpu()
     from paper_2601_21407_amd import hh
     rng = np.random.default_rng(3)
     S = 3000
     flat = _flat(_rand_params(rng))
-    X = rng.standard_normal((S, 7)).astype(np.float32)
-    Y = rng.standard_normal((S, 6)).astype(np.float32)
-    dev = lambda a: torch.tensor(a, device="cuda")
+    norm = _norm(rng)
+    X = _raw_inputs(rng, norm, S)
+    Y = (norm[16:22] + norm[24:30] * rng.standard_normal((S, 6))).astype(np.float32)
     g = torch.zeros(hh.MLP_NPARAM, device="cuda")
     loss = torch.zeros(1, device="cuda")
-    hh.mlp_grad(dev(flat), dev(X), dev(Y), g, loss, quantize=True)
-    W1, b1, W2, b2, W3, b3 = _unflat(flat.astype(np.float64))
-    W1q, W2q, W3q = _bf(W1), _bf(W2), _bf(W3)
-    xh = _bf(X)
-    xq = xh + _bf(X - xh)
-    a1 = xq @ W1q + b1
-    h1 = _bf(O.silu(a1))
-    a2 = h1 @ W2q + b2
-    h2 = _bf(O.silu(a2))
-    y = h2 @ W3q + b3
-    L, dy = O.mse_loss_grad(y, Y)
-    gW3 = h2.T @ dy
-    dA2 = (dy @ W3q.T) * O.dsilu(a2)
-    gW2 = h1.T @ dA2
-    dA1 = (dA2 @ W2q.T) * O.dsilu(a1)
-    gW1 = xq.T @ dA1
-    ref = np.concatenate([gW1.reshape(-1), dA1.sum(0), gW2.reshape(-1), dA2.sum(0),
-                          gW3.reshape(-1), dy.sum(0)])
+    hh.mlp_grad(_dev(torch, flat), _dev(torch, norm), _dev(torch, X), _dev(torch, Y), g, loss,
+                quantize=True, act=act)
+    ps = O.mlp_split(flat)
+    Xn, Yn = _normalized(norm, X, Y)
+    y, cache = O.mlp_forward(ps, Xn, act=act, quantize=True)
+    L, dy = O.mse_loss_grad(y, Yn)
+    # straight-through: the gradient flows through the rounded weights as if
+    # the rounding were the identity
+    pq = [O.bf16_round(ps[0]), O.bf16_round(ps[1]), O.bf16_round(ps[2]), ps[3],
+          O.bf16_round(ps[4]), ps[5]]
+    grads, _ = O.mlp_backward(pq, cache, dy)
+    ref = np.concatenate([q.reshape(-1) for q in grads])
     got = g.cpu().numpy()
     assert abs(loss.item() - L) <= 1e-4 * L
     # bf16 roundings of activations can differ where FP32 and FP64 straddle a
@@ -105,83 +122,176 @@ def test_mlp_grad_quantized_matches_emulation():
     assert np.linalg.norm(got - ref) <= 2e-3 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("act", ACTS)
 @pytest.mark.parametrize("S", [64, 1000, 4097])
-def test_mfma_inference_matches_valu_forward(S):
-    """The register-resident MFMA inference (packed fragments, transposed
-    activations) equals the quantized VALU forward up to accumulation order."""
-    print_case("mfma infer S=%d" % S)
+def test_mfma_inference_matches_oracle(S, act):
+    """The register-resident MFMA inference (packed bf16 fragments,
+    transposed activations, FP32 accumulation) against the oracle's network
+    evaluated in binary64 on the same bf16-rounded weights, input split and
+    hidden activations."""
+    print_case("mfma infer S=%d act=%s" % (S, act))
     torch = need_gpu()
     from paper_2601_21407_amd import hh
     rng = np.random.default_rng(S + 1)
     flat = _flat(_rand_params(rng))
-    mu = np.array([-60, 0.05, 0.6, 0.3, 0.05, 0.01, 5], np.float32)
-    sd = np.array([5, 0.02, 0.1, 0.1, 0.02, 0.005, 3], np.float32)
-    Xraw = (mu + sd * rng.standard_normal((S, 7))).astype(np.float32)
-    norm = np.zeros(32, np.float32)
-    norm[0:7], norm[8:15] = mu, sd
-    norm[16:22] = 0.01 * rng.standard_normal(6)
-    norm[24:30] = 0.1 + rng.random(6)
-    dev = lambda a: torch.tensor(np.ascontiguousarray(a), device="cuda")
-    packed = hh.mlp_pack(dev(flat), dev(norm))
+    norm = _norm(rng)
+    X = _raw_inputs(rng, norm, S)
+    packed = hh.mlp_pack(_dev(torch, flat), _dev(torch, norm))
     Y = torch.empty((S, 6), device="cuda")
-    hh.mlp_infer(packed, dev(Xraw), Y)
-    Xn = ((Xraw - mu) / sd).astype(np.float32)
-    Yr = torch.empty((S, 6), device="cuda")
-    hh.mlp_forward(dev(flat), dev(Xn), Yr, quantize=True)
-    ref = Yr.cpu().numpy() * norm[24:30] + norm[16:22]
-    got = Y.cpu().numpy()
-    err = np.abs(got - ref) / (norm[24:30])
-    print("mfma vs valu: max normalized error %.2e" % err.max())
-    assert err.max() < 2e-2 and np.median(err) < 2e-3
+    hh.mlp_infer(packed, _dev(torch, X), Y, act=act)
+    ref = O.mlp_apply(O.mlp_split(flat), norm, X, act=act, quantize=True)
+    err = np.abs(Y.cpu().numpy() - ref) / norm[24:30]
+    print("mfma vs oracle (bf16 network): max %.2e median %.2e (normalized)"
+          % (err.max(), np.median(err)))
+    # FP32 accumulation against binary64 sums; a hidden activation whose FP32
+    # value straddles a bf16 rounding boundary differs by one bf16 step
+    assert np.median(err) < 1e-4 and err.max() < 2e-2
 
 
-def _packed_random(torch, hh, scale=1e-3):
-    rng = np.random.default_rng(11)
-    flat = _flat(_rand_params(rng))
+def test_transitions_kernel():
+    """hh_surrogate_transitions on a seeded synthetic trajectory buffer:
+    selection (V <= v_fb at t and t + k), (t, i) order, the binary32 mean
+    input in step order, the state differences, and the cap."""
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    rng = np.random.default_rng(8)
+    T, n, k, vfb = 60, 300, 10, -50.0
+    traj = np.zeros((T, 7, n), np.float32)
+    traj[:, 0] = -50.0 + 4.0 * rng.standard_normal((T, n))
+    traj[:, 1:6] = rng.random((T, 5, n))
+    traj[:, 6] = 1e-6 * rng.standard_normal((T, n))
+    I = (5.0 + 3.0 * rng.standard_normal((T, n))).astype(np.float32)
+    X, Y = hh.surrogate_transitions(_dev(torch, traj), _dev(torch, I), k, vfb, cap=10 ** 6)
+    V = traj[:, 0] + traj[:, 6]
+    xs, ys = [], []
+    for t in range(T - k):
+        for i in range(n):
+            if V[t, i] <= vfb and V[t + k, i] <= vfb:
+                a = np.concatenate([[V[t, i]], traj[t, 1:6, i]]).astype(np.float32)
+                b = np.concatenate([[V[t + k, i]], traj[t + k, 1:6, i]]).astype(np.float32)
+                s = np.float32(0.0)
+                for j in range(k):
+                    s = np.float32(s + I[t + j, i])
+                xs.append(np.concatenate([a, [s / np.float32(k)]]))
+                ys.append(b - a)
+    xs, ys = np.asarray(xs, np.float32), np.asarray(ys, np.float32)
+    assert X.shape[0] == len(xs) > 1000
+    assert np.array_equal(X.cpu().numpy(), xs) and np.array_equal(Y.cpu().numpy(), ys)
+    Xc, Yc = hh.surrogate_transitions(_dev(torch, traj), _dev(torch, I), k, vfb, cap=777)
+    assert Xc.shape[0] == 777 and np.array_equal(Xc.cpu().numpy(), xs[:777])
+
+
+def test_norm_kernel():
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    rng = np.random.default_rng(9)
+    S = 200003
+    X = (np.array([-60, 0.1, 0.5, 0.3, 0.05, 0.01, 5]) +
+         np.array([4, 0.05, 0.2, 0.1, 0.01, 0.004, 3]) * rng.standard_normal((S, 7))).astype(np.float32)
+    Y = (1e-3 * rng.standard_normal((S, 6))).astype(np.float32)
+    Y[:, 5] = 0.0  # a constant target takes the floor
+    norm = hh.mlp_norm(_dev(torch, X), _dev(torch, Y)).cpu().numpy()
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    assert np.allclose(norm[0:7], X64.mean(0), rtol=1e-6, atol=1e-9)
+    assert np.allclose(norm[8:15], X64.std(0, ddof=1), rtol=1e-6)
+    assert np.allclose(norm[16:22], Y64.mean(0), rtol=1e-6, atol=1e-12)
+    assert np.allclose(norm[24:29], Y64.std(0, ddof=1)[:5], rtol=1e-6)
+    assert norm[29] == np.float32(1e-9)
+    assert np.all(norm[[7, 15, 22, 23, 30, 31]] == 0)
+
+
+def _policy_case(torch, hh, act, n=384, T=400, check_every=10, check_tol=0.5, seed=12):
+    """A seeded network whose predicted changes are small (output std 0.05
+    of its normalized output), so neurons drift under the surrogate, cross
+    the fallback threshold through plain steps and sometimes fail checks."""
+    rng = np.random.default_rng(seed)
+    flat = _flat(_rand_params(rng, scale=0.5))
     norm = np.zeros(32, np.float32)
     norm[0:7] = [-62, 0.05, 0.6, 0.3, 0.05, 0.01, 5]
     norm[8:15] = [5, 0.02, 0.1, 0.1, 0.02, 0.005, 3]
-    norm[24:30] = scale
-    return hh.mlp_pack(torch.tensor(flat, device="cuda"), torch.tensor(norm, device="cuda"))
+    norm[16:22] = [0.3, 0.0, 0.0, 0.0, 0.0, 0.0]
+    norm[24:30] = [0.8, 0.005, 0.01, 0.005, 0.002, 0.001]
+    I = (5.0 + 3.0 * rng.standard_normal((T, n))).astype(np.float32)
+    return flat, norm, I
 
 
-@pytest.mark.parametrize("n", [1000, 70000])
-def test_deployment_all_plain_equals_plain_kernel(n):
-    """With the fallback threshold below every V the deployment kernel runs
-    only plain steps through its compaction pool: states and spikes equal the
-    plain fused kernel bit for bit."""
-    print_case("surrogate all-plain n=%d" % n)
+@pytest.mark.parametrize("act", ACTS)
+def test_deployment_policy_matches_oracle(act):
+    """hh_surrogate_step_n on 384 neurons x 40 calls against the oracle's
+    binary64 run of the same policy (the network as the bf16 inference
+    evaluates it, the plain steps of run()): spike trains within one step,
+    the final state, and the call counts, where no decision of the neuron
+    came within 0.05 mV of its threshold in the oracle's run."""
+    print_case("surrogate policy vs oracle act=%s" % act)
     torch = need_gpu()
     from paper_2601_21407_amd import hh
     from paper_2601_21407_amd import surrogate as SG
-    packed = _packed_random(torch, hh)
+    flat, norm, I = _policy_case(torch, hh, act)
+    n, T, k = I.shape[1], I.shape[0], 10
+    packed = hh.mlp_pack(_dev(torch, flat), _dev(torch, norm))
+    M, st, bits, stats = SG.deploy(packed, n, T, i_dense=_dev(torch, I), check_every=10, act=act)
+    m = W.custom_channels(dt=0.025)
+    s0 = O.init_state(m, np.full(n, -65.0))
+    ro = O.surrogate_run(m, s0, T, k, O.mlp_split(flat), norm, I.astype(np.float64), act=act,
+                         v_fb=-50.0, check_every=10, check_tol=0.5)
+    g = st.cpu().numpy()
+    gr = O.unpack_bits(bits.cpu().numpy().view(np.uint32), n)
+    clear = ro["margin"] > 0.01
+    print("oracle stats", ro["stats"], "gpu stats", stats.cpu().numpy(), "clear", clear.sum())
+    assert clear.sum() >= 0.4 * n
+    st_o = ro["stats"]
+    assert st_o[0] > 0.3 * st_o.sum() / 1 and st_o[1] > 0  # both paths taken
+    bad = []
+    for i in np.nonzero(clear)[0]:
+        a, b = np.nonzero(gr[:, i])[0], np.nonzero(ro["spikes"][:, i])[0]
+        same = len(a) == len(b) and (len(a) == 0 or np.abs(a - b).max() <= 1)
+        dv = abs(g[0, i] + g[6, i] - s0[0, i])
+        if not same or dv > 0.02:
+            bad.append((int(i), a.tolist(), b.tolist(), float(dv)))
+    assert not bad, bad[:5]
+    # call counts: equal up to the neurons whose decisions sat near a threshold
+    st_g = stats.cpu().numpy()
+    assert abs(int(st_g[0]) - int(st_o[0])) <= (T // k) * int((~clear).sum())
+
+
+def test_deployment_all_plain_equals_plain_kernel():
+    """With the fallback threshold below every V the deployment kernel runs
+    only plain steps through its compaction pool: states and spikes equal the
+    plain fused kernel bit for bit."""
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import surrogate as SG
+    rng = np.random.default_rng(11)
+    packed = hh.mlp_pack(_dev(torch, _flat(_rand_params(rng))), _dev(torch, _norm(rng)))
     T = 800
-    _, st_s, bits_s, stats = SG.deploy(packed, n, T, noise=(5.0, 3.0, 9), v_fallback=-1000.0,
-                                       check_every=0)
-    _, st_p, bits_p = SG.plain_run(n, T, noise=(5.0, 3.0, 9))
-    torch.cuda.synchronize()
-    assert torch.equal(st_s, st_p)
-    assert torch.equal(bits_s, bits_p)
-    assert stats[0].item() == 0 and stats[1].item() == n * T // 10
+    for n in (1000, 70000):
+        print_case("surrogate all-plain n=%d" % n)
+        _, st_s, bits_s, stats = SG.deploy(packed, n, T, noise=(5.0, 3.0, 9), v_fallback=-1000.0,
+                                           check_every=0)
+        _, st_p, bits_p = SG.plain_run(n, T, noise=(5.0, 3.0, 9))
+        torch.cuda.synchronize()
+        assert torch.equal(st_s, st_p)
+        assert torch.equal(bits_s, bits_p)
+        assert stats[0].item() == 0 and stats[1].item() == n * T // 10
 
 
-def test_deployment_surrogate_step_equals_inference():
+@pytest.mark.parametrize("act", ACTS)
+def test_deployment_surrogate_step_equals_inference(act):
     """One surrogate call with dense input: every neuron below the threshold
     takes exactly the MFMA inference result for (state, mean current)."""
     torch = need_gpu()
     from paper_2601_21407_amd import hh
     from paper_2601_21407_amd import surrogate as SG
-    packed = _packed_random(torch, hh, scale=1e-2)
-    n, k = 3000, 10
     rng = np.random.default_rng(4)
+    norm = _norm(rng)
+    norm[24:30] = 1e-2
+    packed = hh.mlp_pack(_dev(torch, _flat(_rand_params(rng))), _dev(torch, norm))
+    n, k = 3000, 10
     I = (5.0 + 3.0 * rng.standard_normal((k, n))).astype(np.float32)
-    It = torch.tensor(I, device="cuda")
-    M, st, bits, stats = SG.deploy(packed, n, k, i_dense=It, check_every=0, v_fallback=1e6)
+    M, st, bits, stats = SG.deploy(packed, n, k, i_dense=_dev(torch, I), check_every=0,
+                                   v_fallback=1e6, act=act)
     m = W.custom_channels(dt=0.025)
-    s0 = O.init_state(m, np.full(n, -65.0))
     X = np.zeros((n, 7), np.float32)
-    X[:, 0] = s0[0]
-    X[:, 1:6] = s0[1:6].T
     ib = np.zeros(n, np.float32)
     for j in range(k):
         ib = ib + I[j]
@@ -194,7 +304,7 @@ def test_deployment_surrogate_step_equals_inference():
     X[:, 0] = s2n[0] + s2n[6]
     X[:, 1:6] = s2n[1:6].T
     Y = torch.empty((n, 6), device="cuda")
-    hh.mlp_infer(packed, torch.tensor(X, device="cuda"), Y)
+    hh.mlp_infer(packed, _dev(torch, X), Y, act=act)
     Yn = Y.cpu().numpy()
     got = st.cpu().numpy()
     assert stats[0].item() == n
@@ -203,8 +313,9 @@ def test_deployment_surrogate_step_equals_inference():
 
 
 def test_train_and_deploy_small():
-    """A short training run on trajectories of the plain kernel reduces the
-    loss; deployment on 4,096 neurons stays close to the plain integrator."""
+    """A short training run (hard-swish network) on trajectories of the plain
+    kernel reduces the loss; deployment on 4,096 neurons x 2,000 steps stays
+    close to the plain integrator."""
     print_case("surrogate train small")
     torch = need_gpu()
     from paper_2601_21407_amd import surrogate as SG
@@ -212,7 +323,7 @@ def test_train_and_deploy_small():
     X, dY = SG.generate_transitions(n_traj=400, T=4000, seed=3)
     assert X.shape[0] > 500000
     norm = SG.norm_stats(X, dY)
-    params, hist = SG.train(X, dY, norm, epochs=3, batch=8192, lr=3e-3)
+    params, hist = SG.train(X, dY, norm, epochs=3, batch=8192, lr=3e-3, act="hardswish")
     print("loss history", hist)
     assert hist[-1] < 0.5 * hist[0]
     packed = hh.mlp_pack(params, norm)
@@ -221,10 +332,12 @@ def test_train_and_deploy_small():
     gen.manual_seed(21)
     I = (5.0 + 3.0 * torch.randn((T, n), generator=gen, device="cuda")).contiguous()
     _, _, bits_p = SG.plain_run(n, T, i_dense=I)
-    _, _, bits_s, stats = SG.deploy(packed, n, T, i_dense=I)
+    _, _, bits_s, stats = SG.deploy(packed, n, T, i_dense=I, act="hardswish")
     torch.cuda.synchronize()
     e = SG.spike_time_error(bits_p.cpu().numpy(), bits_s.cpu().numpy(), n, 0.025, 0.025)
     st = stats.cpu().numpy()
     print("spike-time error", e, "stats", st)
     assert st[0] > st[1]  # most calls use the surrogate
-    assert e["unmatched_frac"] < 0.5
+    # a short training run: the pipeline works end to end (the accuracy of
+    # the fully trained network is asserted by the benchmark-sized test)
+    assert e["unmatched_frac"] < 0.2 and e["mean_abs_ms"] < 1.0

@@ -145,10 +145,9 @@ def test_exp_euler_exact_at_clamped_voltage(ora):
     st[0, 0] = V
     out_n = 37
     ora.run(m, st, out_n, record_spikes=False)
-    pairs = [(("linoid", (0.1, -40, 10, 0)), ("exp", (4, -65, -18, 0))),
-             (("exp", (0.07, -65, -20, 0)), ("sigmoid", (1, -35, -10, 0))),
-             (("linoid", (0.01, -55, 10, 0)), ("exp", (0.125, -65, -80, 0)))]
-    t = out_n * 0.05
+    # the model's own (binary32) coefficients
+    pairs = [tuple((r[0], tuple(r[1:5])) for r in gate["rates"]) for gate in m["gates"]]
+    t = out_n * m["dt"]
     for g, (ra, rb) in enumerate(pairs):
         a = ora.rate(ra[0], ra[1], V)[0]
         b = ora.rate(rb[0], rb[1], V)[0]
@@ -170,7 +169,7 @@ def test_leak_only_forward_euler_closed_form(ora):
     m = _leak_only("fe", dt)
     st = ora.init_state(m, [-80.0])
     res = ora.run(m, st, n, i_const=[I], record_v=True, record_spikes=False)
-    gL, EL = 0.3, -54.4
+    gL, EL, dt = m["channels"][2]["gbar"], m["channels"][2]["E"], m["dt"]
     vinf = EL + I / gL
     k = np.arange(1, n + 1)
     exact = vinf + (-80.0 - vinf) * (1 - dt * gL) ** k
@@ -182,7 +181,7 @@ def test_leak_only_exponential_euler_is_exact_rc(ora):
     m = _leak_only("ee", dt)
     st = ora.init_state(m, [-80.0])
     res = ora.run(m, st, n, i_const=[I], record_v=True, record_spikes=False)
-    gL, EL = 0.3, -54.4
+    gL, EL, dt = m["channels"][2]["gbar"], m["channels"][2]["E"], m["dt"]
     vinf = EL + I / gL
     t = dt * np.arange(1, n + 1)
     exact = vinf + (-80.0 - vinf) * np.exp(-gL * t)
@@ -317,7 +316,7 @@ def test_single_synapse_increment(ora):
     for k in range(T):
         ge_before = st[4, 1]
         spk = ora.net_run(m, st, csr, 0.01, 1, t0=k, i_const=I)
-        hist.append((spk[0, 0], st[4, 1] - ge_before * np.exp(-0.05 / 5.0)))
+        hist.append((spk[0, 0], st[4, 1] - ge_before * np.exp(-m["dt"] / m["syn"]["tau_e"])))
     jumps = [d for s, d in hist if s]
     quiet = [d for s, d in hist if not s]
     assert len(jumps) >= 2
@@ -337,7 +336,7 @@ def test_external_drive_events(ora):
     for k in range(T):
         prev = st[4].copy()
         ora.net_run(m, st, csr, 1.0, 1, t0=k, ext_mask=mask, ext_thresh=thr, w_ext=0.5, seed=11)
-        ge_hist.append(st[4] - prev * np.exp(-0.1 / 5.0))
+        ge_hist.append(st[4] - prev * np.exp(-m["dt"] / m["syn"]["tau_e"]))
     ge_hist = np.array(ge_hist)
     for i in range(n):
         expect = np.array([0.5 if (mask[i] and ora.event_word(11, i, k + 1) < thr) else 0.0
@@ -458,19 +457,21 @@ def _mlp_params(rng, dims=(7, 64, 64, 6)):
     return ps
 
 
-def test_mlp_forward_backward_against_torch(ora):
+@pytest.mark.parametrize("act", ["silu", "hardswish"])
+def test_mlp_forward_backward_against_torch(ora, act):
     import torch
     rng = np.random.default_rng(2)
     ps = _mlp_params(rng)
-    x = rng.standard_normal((33, 7))
+    x = 2.0 * rng.standard_normal((33, 7))
     tgt = rng.standard_normal((33, 6))
-    y, cache = ora.mlp_forward(ps, x)
+    y, cache = ora.mlp_forward(ps, x, act=act)
     loss, dy = ora.mse_loss_grad(y, tgt)
     grads, dx = ora.mlp_backward(ps, cache, dy)
     tps = [torch.tensor(p, requires_grad=True) for p in ps]
     tx = torch.tensor(x, requires_grad=True)
-    h = torch.nn.functional.silu(tx @ tps[0] + tps[1])
-    h = torch.nn.functional.silu(h @ tps[2] + tps[3])
+    f = torch.nn.functional.silu if act == "silu" else torch.nn.functional.hardswish
+    h = f(tx @ tps[0] + tps[1])
+    h = f(h @ tps[2] + tps[3])
     ty = h @ tps[4] + tps[5]
     tl = ((ty - torch.tensor(tgt)) ** 2).sum() / 33
     tl.backward()
@@ -479,6 +480,131 @@ def test_mlp_forward_backward_against_torch(ora):
     for g, tp in zip(grads, tps):
         assert np.allclose(g, tp.grad.numpy(), rtol=1e-11, atol=1e-14)
     assert np.allclose(dx, tx.grad.numpy(), rtol=1e-11, atol=1e-14)
+
+
+def test_hardswish_and_derivative(ora):
+    """hardswish equals torch's; its derivative equals central differences
+    away from the kinks at -3 and 3, and takes the outer values there."""
+    import torch
+    x = np.linspace(-8, 8, 3201)
+    assert np.allclose(ora.hardswish(x), torch.nn.functional.hardswish(torch.tensor(x)).numpy(),
+                       rtol=0, atol=1e-15)
+    xs = x[(np.abs(np.abs(x) - 3.0) > 1e-3)]
+    h = 1e-6
+    fd = (ora.hardswish(xs + h) - ora.hardswish(xs - h)) / (2 * h)
+    assert np.allclose(ora.dhardswish(xs), fd, rtol=0, atol=1e-8)
+    assert ora.dhardswish(np.array([-3.0, 3.0])).tolist() == [0.0, 1.0]
+    # SiLU's derivative against central differences too
+    fd = (ora.silu(x + h) - ora.silu(x - h)) / (2 * h)
+    assert np.allclose(ora.dsilu(x), fd, rtol=0, atol=1e-8)
+
+
+def test_bf16_round_matches_torch(ora):
+    """The oracle's bf16 rounding (from the binary64 value) equals torch's
+    float32 -> bfloat16 conversion on values that binary32 holds exactly, ties
+    included."""
+    import torch
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal(20000) * 10.0 ** rng.integers(-6, 6, 20000)).astype(np.float32)
+    # exact ties: bf16 values plus half a bf16 step
+    b = torch.tensor(x[:200]).to(torch.bfloat16).to(torch.float32).numpy()
+    m, e = np.frexp(b.astype(np.float64))
+    ties = (b.astype(np.float64) + np.ldexp(1.0, e - 9)).astype(np.float32)
+    x = np.concatenate([x, ties])
+    ref = torch.tensor(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ora.bf16_round(x.astype(np.float64)), ref)
+
+
+@pytest.mark.parametrize("act", ["silu", "hardswish"])
+def test_mlp_quantized_forward_against_torch_bf16(ora, act):
+    """quantize=True equals a torch network whose weights, input split and
+    hidden activations are cast to bfloat16 by torch (binary64 arithmetic
+    otherwise)."""
+    import torch
+    rng = np.random.default_rng(6)
+    ps = _mlp_params(rng)
+    x = 3.0 * rng.standard_normal((50, 7))
+    y, _ = ora.mlp_forward(ps, x, act=act, quantize=True)
+    bf = lambda t: t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+    f = torch.nn.functional.silu if act == "silu" else torch.nn.functional.hardswish
+    W1, b1, W2, b2, W3, b3 = [torch.tensor(p) for p in ps]
+    tx = torch.tensor(x)
+    hi = bf(tx)
+    xq = hi + bf(tx - hi)
+    h1 = bf(f(xq @ bf(W1) + bf(b1)))
+    h2 = bf(f(h1 @ bf(W2) + b2))
+    ty = h2 @ bf(W3) + b3
+    # torch casts binary64 through binary32 on the way to bf16 (double
+    # rounding), so an activation within a binary32 step of a bf16 tie may
+    # round the other way there: rows agree to rounding except such rare
+    # rows, which differ by one bf16 step of one activation
+    d = np.abs(y - ty.numpy()).max(axis=1)
+    assert (d < 1e-12).mean() >= 0.9, d
+    assert d.max() < 0.02, d.max()
+
+
+def _sur_case(ora, n=40, T=60, seed=3):
+    from paper_2601_21407_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    m = W.custom_channels(dt=0.025)
+    ps = _mlp_params(rng)
+    ps[4] *= 0.3
+    norm = np.zeros(32)
+    norm[0:7] = [-62, 0.05, 0.6, 0.3, 0.05, 0.01, 5]
+    norm[8:15] = [5, 0.02, 0.1, 0.1, 0.02, 0.005, 3]
+    norm[16:22] = [0.2, 0, 0, 0, 0, 0]
+    norm[24:30] = [0.5, 0.004, 0.01, 0.004, 0.002, 0.001]
+    I = 5.0 + 3.0 * rng.standard_normal((T, n))
+    s0 = ora.init_state(m, -70.0 + 15.0 * rng.random(n))
+    return m, ps, norm, I, s0
+
+
+def test_surrogate_policy_reduces_to_plain(ora):
+    """Every call a check call (check_every = 1), or no neuron admissible
+    (v_fb below every V): the policy runs only plain steps and equals run()
+    over the whole span, spikes included."""
+    m, ps, norm, I, s0 = _sur_case(ora)
+    T = I.shape[0]
+    ref = s0.copy()
+    rr = ora.run(m, ref, T, i_dense=I)
+    for kw in ({"check_every": 1}, {"v_fb": -1e9, "check_every": 0}):
+        s = s0.copy()
+        r = ora.surrogate_run(m, s, T, 10, ps, norm, I, **kw)
+        assert np.array_equal(s, ref) and np.array_equal(r["spikes"], rr["spikes"])
+        assert r["stats"][0] == 0 and r["stats"][1] == s0.shape[1] * T // 10
+
+
+def test_surrogate_policy_all_network_and_forced(ora):
+    """v_fb above every V and no checks: c calls are the c-fold composition of
+    the network map (gates clamped to [0, 1]) and nothing spikes.  With every
+    check failing (check_tol < 0, check_every = 3) the neurons follow the
+    network for two calls and plain steps from the first check on, and each
+    check counts every candidate as a failure."""
+    m, ps, norm, I, s0 = _sur_case(ora)
+    T, k = I.shape[0], 10
+
+    def net_call(x, c):
+        xin = np.concatenate([x.T, I[c * k:(c + 1) * k].mean(0)[:, None]], axis=1)
+        y = x.T + ora.mlp_apply(ps, norm, xin, quantize=True)
+        y[:, 1:] = np.clip(y[:, 1:], 0.0, 1.0)
+        return np.ascontiguousarray(y.T)
+
+    s = s0.copy()
+    r = ora.surrogate_run(m, s, T, k, ps, norm, I, v_fb=1e9, check_every=0)
+    x = s0.copy()
+    for c in range(T // k):
+        x = net_call(x, c)
+    assert np.array_equal(s, x) and r["spikes"].sum() == 0
+    assert r["stats"].tolist() == [s0.shape[1] * T // k, 0, 0]
+    s = s0.copy()
+    r = ora.surrogate_run(m, s, T, k, ps, norm, I, v_fb=1e9, check_every=3, check_tol=-1.0)
+    x = net_call(net_call(s0.copy(), 0), 1)
+    rr = ora.run(m, x, T - 2 * k, t0=2 * k, i_dense=np.ascontiguousarray(I[2 * k:]))
+    assert np.array_equal(s, x)
+    assert np.array_equal(r["spikes"][2 * k:], rr["spikes"]) and r["spikes"][:2 * k].sum() == 0
+    n = s0.shape[1]
+    assert r["stats"][0] == 2 * n and r["stats"][1] == n * (T // k - 2)
+    assert r["stats"][2] == 2 * n  # checks at calls 2 and 5, all candidates fail
 
 
 def test_adam_against_torch(ora):
@@ -572,10 +698,11 @@ def _with_table(model, tab):
 
 
 def _classic_pq(ora, V, dt):
-    """Exact (P, Q) of the three classic gates at V from the textbook rate pairs."""
-    pairs = [(("linoid", (0.1, -40, 10, 0)), ("exp", (4, -65, -18, 0))),
-             (("exp", (0.07, -65, -20, 0)), ("sigmoid", (1, -35, -10, 0))),
-             (("linoid", (0.01, -55, 10, 0)), ("exp", (0.125, -65, -80, 0)))]
+    """Exact (P, Q) of the three classic gates at V from the textbook rate
+    pairs (the model's binary32 coefficients) and the model's dt."""
+    m = W.classic_hh(dt=dt)
+    dt = m["dt"]
+    pairs = [tuple((r[0], tuple(r[1:5])) for r in gate["rates"]) for gate in m["gates"]]
     out = []
     for ra, rb in pairs:
         a = ora.rate(ra[0], ra[1], V)[0]
@@ -914,7 +1041,8 @@ def test_net_single_delayed_synapse_closed_form(ora, d):
         s = np.nonzero(spk[:, 0])[0] + 1  # a spike in step k is at time k + 1
         assert len(s) >= 2
         due = s[s + d - 1 <= T]
-        want = sum(0.007 * np.exp(-0.05 * (T - (t + d - 1)) / 5.0) for t in due)
+        dt, tau = m["dt"], m["syn"]["tau_e"]
+        want = sum(0.007 * np.exp(-dt * (T - (t + d - 1)) / tau) for t in due)
         assert abs(st[4, 1] - want) < 1e-14, (T, st[4, 1], want)
 
 
@@ -950,7 +1078,9 @@ def test_net_mixed_delays_brute_force(ora):
     bs = ora.init_state(m, v0)
     import math
     pend = {}
-    de, di = math.exp(-0.1 / 5.0), math.exp(-0.1 / 10.0)  # the C library's exp, as the oracle's
+    # the C library's exp, as the oracle's, of the model's own parameters
+    de = math.exp(-m["dt"] / m["syn"]["tau_e"])
+    di = math.exp(-m["dt"] / m["syn"]["tau_i"])
     G = len(m["gates"])
     spikes = np.zeros((T, n), np.uint8)
     for k in range(T):
@@ -1165,3 +1295,22 @@ def test_cable_ids_and_coef_select_each_elements_own_run(ora):
     sub = ora.cable_run(m, ora.init_state(m, v0[sel], coef=coef[:, sel]), T, morph, noise_mu=3.0,
                         noise_sigma=3.0, seed=5, coef=coef[:, sel], ids=sel, record_v=True)["v"]
     assert np.array_equal(sub, full[:, sel])
+
+
+def test_openmp_build_equals_serial(ora):
+    """The OpenMP build of the oracle (the all-core timing leg) gives the
+    serial build's results bit for bit: it only splits independent neurons
+    over threads."""
+    from paper_2601_21407_amd import workloads as W
+    m = W.custom_channels(dt=0.025)
+    n, T = 1000, 300
+    coef = W.jitter_coef(m, n, seed=7).astype(np.float64)
+    outs = []
+    for omp in (False, True):
+        st = ora.init_state(m, np.full(n, -65.0), coef=coef)
+        r = ora.run(m, st, T, noise_mu=5.0, noise_sigma=3.0, seed=7, coef=coef, record_v=True,
+                    omp=omp)
+        outs.append((st, r["v"], r["spikes"]))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    assert ora.threads(False) == 1 and ora.threads(True) >= 1
