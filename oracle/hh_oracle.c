@@ -557,6 +557,11 @@ int32_t ora_net_run(const ora_model* m, int64_t n, double* state, const int64_t*
   const double de = exp(-m->dt / m->tau_e), di = exp(-m->dt / m->tau_i);
   for (int32_t k = 0; k < T; ++k) {
     const int64_t t = t0 + k;
+    /* the neuron updates of a step are independent (the OpenMP build splits
+     * them over threads; the synaptic sums below stay sequential) */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int64_t i = 0; i < n; ++i) {
       double p[ORA_MAX_GATES], pn[ORA_MAX_GATES], Vn;
       for (int g = 0; g < G; ++g) p[g] = state[(int64_t)(1 + g) * n + i];
@@ -579,6 +584,9 @@ int32_t ora_net_run(const ora_model* m, int64_t n, double* state, const int64_t*
       }
     }
     const int64_t a = (t + 1) % R;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int64_t i = 0; i < n; ++i) {
       double ext = 0.0;
       if (ext_mask && ext_mask[i] && ora_event_word(seed, (uint32_t)i, t + 1) < ext_thresh)

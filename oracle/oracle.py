@@ -340,10 +340,11 @@ def cable_run(model: dict, state: np.ndarray, T: int, morph: dict, t0: int = 0, 
 
 def net_run(model: dict, state: np.ndarray, csr, w_scale: float, T: int, t0: int = 0, *,
             ext_mask=None, ext_thresh: int = 0, w_ext: float = 0.0, seed: int = 0, i_const=None,
-            delay=None, max_delay: int = 1, background=None, in_seed: int = 0):
+            delay=None, max_delay: int = 1, background=None, in_seed: int = 0, omp: bool = False):
     """Recurrent network, T steps in place; returns spikes [T][n] uint8.
     delay: per-synapse delays in steps [nnz] (None: 1); background =
-    (lam, mu, sigma) drawn with in_seed."""
+    (lam, mu, sigma) drawn with in_seed.  omp: the OpenMP build (the neuron
+    updates of a step on several threads; same results)."""
     s = model_to_struct(model)
     n = state.shape[1]
     row_ptr = np.ascontiguousarray(csr[0], dtype=np.int64)
@@ -359,7 +360,7 @@ def net_run(model: dict, state: np.ndarray, csr, w_scale: float, T: int, t0: int
     elif ic is not None:
         mode = IN_CONST
     spk = np.zeros((T, n), np.uint8)
-    rc = lib().ora_net_run(ctypes.byref(s), n, _p(state), _p(row_ptr), _p(col), _p(w),
+    rc = lib(omp).ora_net_run(ctypes.byref(s), n, _p(state), _p(row_ptr), _p(col), _p(w),
                            float(w_scale), _p(dl), int(max_delay), _p(em), int(ext_thresh),
                            float(w_ext), int(seed), mode, _p(ic), mu, sigma, int(in_seed), lam,
                            int(t0), int(T), _p(spk))

@@ -837,6 +837,10 @@ constexpr int SB = 256;  // block size = compaction pool
 constexpr int KMAX = 32;  // steps per surrogate call (k * SB/32 <= SB threads clear the spike words)
 constexpr int SBW = SB / 32;  // spike words per block and step
 constexpr int kSBW = SB / 64;  // wavefronts per block
+// Dense input of the next call prefetched into registers for calls of up to
+// KPF steps (its mean is the next call's network input); longer calls load
+// it when they need it.
+constexpr int KPF = 16;
 
 struct SurArgs {
   float* state;
@@ -913,6 +917,15 @@ __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
   bool forced = A.flags[ii] != 0;
   uint32_t n_mlp = 0, n_plain = 0, n_fail = 0;
   const int64_t blk_w0 = blk0 >> 5;  // first spike word of the block
+  // this neuron's dense input of the coming call, loaded one call ahead so
+  // the loads are in flight during the current call's work
+  const bool pf = A.in_mode == IN_DENSE && A.k <= KPF;
+  float pre[KPF];
+  if (pf) {
+#pragma unroll
+    for (int j = 0; j < KPF; ++j)
+      pre[j] = j < A.k ? A.i_dense[(int64_t)j * n + ii] : 0.0f;
+  }
   __syncthreads();
 
   for (int call = 0; call < A.ncalls; ++call) {
@@ -926,13 +939,28 @@ __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
       float x[MLP_IN] = {vh + vl, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int g = 0; g < NG && g < MLP_IN - 2; ++g) x[1 + g] = p[g];
-      x[MLP_IN - 1] = call_mean_input(A, (uint32_t)ii, ii, tc, call);
+      if (pf) {
+        // the same sum in step order as call_mean_input
+        float sum = 0.0f;
+#pragma unroll
+        for (int j = 0; j < KPF; ++j)
+          if (j < A.k) sum += pre[j];
+        x[MLP_IN - 1] = sum / (float)A.k;
+      } else {
+        x[MLP_IN - 1] = call_mean_input(A, (uint32_t)ii, ii, tc, call);
+      }
       float dy[MLP_OUT];
       mlp_infer_wave<ACT>(Ws, x, dy);
       pred[0] = x[0] + dy[0];
 #pragma unroll
       for (int g = 0; g < MLP_OUT - 1; ++g) pred[1 + g] = fminf(fmaxf(x[1 + g] + dy[1 + g], 0.0f), 1.0f);
       cand = sub && pred[0] <= A.v_fb;  // ... and after it
+    }
+    if (pf && call + 1 < A.ncalls) {
+      const float* nsrc = A.i_dense + (int64_t)(call + 1) * A.k * n + ii;
+#pragma unroll
+      for (int j = 0; j < KPF; ++j)
+        if (j < A.k) pre[j] = nsrc[(int64_t)j * n];
     }
     const bool use_mlp = cand && !forced && !check;
     const bool plain = act && !use_mlp;
@@ -976,6 +1004,13 @@ __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
         }
       }
       const float* dsrc = A.i_dense ? A.i_dense + (int64_t)call * A.k * A.n + nid : nullptr;
+      // dense input two steps ahead (the rows were just read by the owning
+      // lanes for the network's mean, so they come from the caches)
+      float d0 = 0.0f, d1 = 0.0f;
+      if (A.in_mode == IN_DENSE) {
+        d0 = dsrc[0];
+        if (A.k > 1) d1 = dsrc[A.n];
+      }
       for (int j = 0; j < A.k; ++j) {
         float I = 0.0f;
         if (A.in_mode == IN_NOISE) {
@@ -984,7 +1019,9 @@ __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
           I = fmaf(A.sigma, z[0], A.mu);
           z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
         } else if (A.in_mode == IN_DENSE) {
-          I = dsrc[(int64_t)j * A.n];
+          I = d0;
+          d0 = d1;
+          if (j + 2 < A.k) d1 = dsrc[(int64_t)(j + 2) * A.n];
         }
         const float V = wv;
         neuron_step<S>(M, L, dtC, wv, wl, wp, I, 0.0f, 0.0f);

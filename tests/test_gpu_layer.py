@@ -268,6 +268,45 @@ def test_adjoint_against_oracle_batched_two_level():
     assert np.median(relc) < 1e-3
 
 
+def test_adjoint_full_size_sampled():
+    """The configured layer at full size: 256 x 1,024 HH units (262,144
+    neurons) x 250 steps, checkpoints every 50 steps, level-output surrogate
+    gradient, dense input of the layer's mean drive (10 + 6 z uA/cm^2).  The
+    oracle's BPTT runs on every batch copy of 8 hidden units (2,048 neurons):
+    their dL/dI sequences per neuron and the 8 units' dL/dC_m (summed over the
+    batch) are compared."""
+    print_case("adjoint full size 262144 x 250 ckpt 50, 2048 sampled")
+    need_gpu()
+    m = W.classic_hh(dt=0.025)
+    N, B, T = 1024, 256, 250
+    n = N * B
+    rng = np.random.default_rng(31)
+    I = (10.0 + 6.0 * rng.standard_normal((T, n))).astype(np.float32)
+    cm = (0.8 + 0.4 * rng.random(N)).astype(np.float32)
+    v0 = (-65.0 + 30.0 * rng.random(n)).astype(np.float32)
+    dlevel = rng.standard_normal(n)
+    dI, dC, dx0, lv, _ = _gpu_bwd(m, I, cm, v0, 50, dlevel=dlevel, B=B)
+    units = np.array([0, 1, 137, 400, 511, 512, 777, 1023])
+    cols = (np.arange(B)[:, None] * N + units[None, :]).ravel()
+    st0 = O.init_state(m, v0[cols].astype(np.float64))
+    r, oI, oC, _ = O.bptt(m, st0, np.ascontiguousarray(I[:, cols].astype(np.float64)),
+                          cm=cm[cols % N].astype(np.float64), dL_dr=dlevel[cols], smooth=False)
+    same = np.abs(lv[cols] - r * T) == 0
+    assert same.mean() > 0.97, same.mean()
+    g = dI[:, cols]
+    rel = np.linalg.norm(g - oI, axis=0) / np.maximum(np.linalg.norm(oI, axis=0), 1e-12)
+    good = same & (np.linalg.norm(oI, axis=0) > 1e-9)
+    print("full-size adjoint rel err median %.2e p99 %.2e over %d neurons"
+          % (np.median(rel[good]), np.percentile(rel[good], 99), good.sum()), flush=True)
+    assert good.sum() > 1500
+    assert np.percentile(rel[good], 99) < 1e-3 and np.median(rel[good]) < 1e-4
+    # dC_m of a unit sums its 256 batch copies (all of them sampled)
+    oCu = oC.reshape(B, len(units)).sum(0)
+    relc = np.abs(dC[units] - oCu) / np.maximum(np.abs(oCu), 1e-9)
+    print("dC_m rel err per unit", relc, flush=True)
+    assert np.median(relc) < 1e-3
+
+
 def test_adjoint_checkpoint_strides_agree():
     """The same gradient from checkpoint strides 1, 10 and 50 (the replay
     reproduces the forward trajectory)."""

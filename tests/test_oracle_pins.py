@@ -1314,3 +1314,23 @@ def test_openmp_build_equals_serial(ora):
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
     assert ora.threads(False) == 1 and ora.threads(True) >= 1
+
+
+def test_openmp_network_equals_serial(ora):
+    """The OpenMP build's network run (neuron updates of a step on several
+    threads, synaptic sums sequential) equals the serial build bit for bit,
+    with delays, background and external drive."""
+    m = W.net_model()
+    n, T = 600, 400
+    csr = W.net_csr(n=n, fan_out=60, seed=12, inh_scale=4.0)
+    mask, thr = W.net_external(n=n, frac=0.05, seed=12)
+    dl = W.pathway_delays(csr, max_delay=6, seed=3)[0]
+    v0 = W.net_v0(n, 12).astype(np.float64)
+    outs = []
+    for omp in (False, True):
+        st = ora.init_state(m, v0)
+        spk = ora.net_run(m, st, csr, 0.3, T, ext_mask=mask, ext_thresh=thr, w_ext=0.5, seed=12,
+                          delay=dl, max_delay=6, background=(0.5, 2.0, 1.0), in_seed=4, omp=omp)
+        outs.append((spk, st))
+    assert outs[0][0].sum() > 0
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
