@@ -809,7 +809,9 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
         rows.append(dict(method="plain dt=%g %s" % (dt, vm), ms=msc, speedup=ms_ref / msc, **e))
         del Ic
     # a surrogate row is dominated by a plain row that is at least as fast
-    # and at least as accurate (mean |dt| and unmatched fraction)
+    # and at least as accurate (mean |dt| and unmatched fraction); "beats
+    # the reference" = faster than plain dt = 0.025 within the stated error
+    # (mean |dt| <= 0.05 ms, unmatched <= 0.5 %)
     plain_rows = [r for r in rows if r["method"].startswith("plain")]
     for r0 in rows:
         if r0["method"].startswith("surrogate"):
@@ -817,6 +819,10 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
                                   if r["speedup"] >= r0["speedup"]
                                   and r["mean_abs_ms"] <= r0["mean_abs_ms"]
                                   and r["unmatched_frac"] <= r0["unmatched_frac"]]
+    for r0 in rows:
+        if r0["method"].startswith("surrogate"):
+            r0["beats_reference"] = bool(r0["speedup"] > 1.0 and r0["mean_abs_ms"] <= 0.05
+                                         and r0["unmatched_frac"] <= 0.005)
     res.update({"n": n, "T": T, "eval_neurons": eval_neurons, "pareto": rows,
                 "noise_input": {"surrogate_ms": ms_noise, "plain_ms": ms_plain_noise,
                                 "speedup": ms_plain_noise / ms_noise}})

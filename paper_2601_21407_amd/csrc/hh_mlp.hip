@@ -886,7 +886,7 @@ __device__ __forceinline__ float call_mean_input(const SurArgs& A, uint32_t nid,
   return sum / (float)A.k;
 }
 
-template <class S, int ACT>
+template <class S, int ACT, int IN>
 __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
   constexpr int NG = S::kNG;
   __shared__ MlpPacked Ws;
@@ -919,7 +919,7 @@ __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
   const int64_t blk_w0 = blk0 >> 5;  // first spike word of the block
   // this neuron's dense input of the coming call, loaded one call ahead so
   // the loads are in flight during the current call's work
-  const bool pf = A.in_mode == IN_DENSE && A.k <= KPF;
+  const bool pf = IN == IN_DENSE && A.k <= KPF;
   float pre[KPF];
   if (pf) {
 #pragma unroll
@@ -997,7 +997,7 @@ __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
 #pragma unroll
       for (int g = 0; g < NG; ++g) wp[g] = sp[cb][g][slot];
       float z[4] = {0.f, 0.f, 0.f, 0.f};
-      if (A.in_mode == IN_NOISE && (tc & 3)) {
+      if (IN == IN_NOISE && (tc & 3)) {
         normals4(A.seed, (uint32_t)nid, (uint64_t)tc >> 2, z);
         for (int s = 0; s < (int)(tc & 3); ++s) {
           z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
@@ -1007,18 +1007,18 @@ __global__ __launch_bounds__(SB, 4) void k_surrogate(KModel M, SurArgs A) {
       // dense input two steps ahead (the rows were just read by the owning
       // lanes for the network's mean, so they come from the caches)
       float d0 = 0.0f, d1 = 0.0f;
-      if (A.in_mode == IN_DENSE) {
+      if (IN == IN_DENSE) {
         d0 = dsrc[0];
         if (A.k > 1) d1 = dsrc[A.n];
       }
       for (int j = 0; j < A.k; ++j) {
         float I = 0.0f;
-        if (A.in_mode == IN_NOISE) {
+        if (IN == IN_NOISE) {
           const int64_t t = tc + j;
           if ((t & 3) == 0) normals4(A.seed, (uint32_t)nid, (uint64_t)t >> 2, z);
           I = fmaf(A.sigma, z[0], A.mu);
           z[0] = z[1]; z[1] = z[2]; z[2] = z[3];
-        } else if (A.in_mode == IN_DENSE) {
+        } else {
           I = d0;
           d0 = d1;
           if (j + 2 < A.k) d1 = dsrc[(int64_t)(j + 2) * A.n];
@@ -1126,11 +1126,15 @@ extern "C" int32_t hh_surrogate_step_n(hh_model* m, const void* mlp_packed, int3
   a.stats = (unsigned long long*)stats;
   a.W = (const MlpPacked*)mlp_packed;
   const int64_t nb = (m->n + SB - 1) / SB;
-  if (act == HH_ACT_HARDSWISH)
-    hipLaunchKernelGGL((k_surrogate<CorticalSpec, MLP_ACT_HSWISH>), dim3((unsigned)nb), dim3(SB), 0,
-                       (hipStream_t)stream, m->km, a);
-  else
-    hipLaunchKernelGGL((k_surrogate<CorticalSpec, MLP_ACT_SILU>), dim3((unsigned)nb), dim3(SB), 0,
-                       (hipStream_t)stream, m->km, a);
+  const dim3 g((unsigned)nb), b(SB);
+  hipStream_t s = (hipStream_t)stream;
+  const bool dense = in->mode == HH_IN_DENSE;
+  if (act == HH_ACT_HARDSWISH) {
+    if (dense) hipLaunchKernelGGL((k_surrogate<CorticalSpec, MLP_ACT_HSWISH, IN_DENSE>), g, b, 0, s, m->km, a);
+    else hipLaunchKernelGGL((k_surrogate<CorticalSpec, MLP_ACT_HSWISH, IN_NOISE>), g, b, 0, s, m->km, a);
+  } else {
+    if (dense) hipLaunchKernelGGL((k_surrogate<CorticalSpec, MLP_ACT_SILU, IN_DENSE>), g, b, 0, s, m->km, a);
+    else hipLaunchKernelGGL((k_surrogate<CorticalSpec, MLP_ACT_SILU, IN_NOISE>), g, b, 0, s, m->km, a);
+  }
   return hipGetLastError() == hipSuccess ? HH_OK : HH_E_HIP;
 }
