@@ -155,6 +155,7 @@ int32_t hh_destroy(hh_model* m) {
   if (m->d_cable) (void)hipFree(m->d_cable);
   if (m->d_ring) (void)hipFree(m->d_ring);
   if (m->d_scratch) (void)hipFree(m->d_scratch);
+  if (m->d_seg) (void)hipFree(m->d_seg);
   if (m->d_flags) (void)hipFree(m->d_flags);
   delete m;
   return HH_OK;

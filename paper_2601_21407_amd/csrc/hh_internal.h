@@ -51,6 +51,12 @@ struct hh_model {
   // device flags: [0] first non-finite neuron (INT32_MAX = none), [1] timeout
   int32_t* d_flags;
   // recurrent network
+  // binned one-shot delivery (rows sorted by target, one copy): for row j
+  // and target range r (kSegRange targets each), d_seg[j (R + 1) + r] is the
+  // offset within the row of its first target >= r kSegRange; null when the
+  // rows are not sorted or B > 1
+  int32_t* d_seg;
+  int32_t seg_R;
   const int64_t* row_ptr;
   const int32_t* col;
   const float* w;

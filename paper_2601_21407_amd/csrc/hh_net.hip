@@ -27,7 +27,8 @@
 // its own external and background streams, keyed by the element index.
 //
 // hh_syn_propagate runs the same delivery once, outside the time loop, as
-// three kernels: global compaction, one wavefront per spiking row, apply.
+// three kernels: global compaction, the scatter (binned by target range when
+// the rows are sorted, else one wavefront per spiking row), apply.
 #include <stdlib.h>
 #include <string.h>
 
@@ -114,7 +115,7 @@ __device__ void block_inclusive_scan(int* v, int cnt) {
 // DELAY: the events go to the ring slot (now + d) of their synapse's delay
 // d (clamped to [1, R - 1], so the slot always lies in the ring); acc_e is
 // then the ring's base and `now` the current time's slot.
-template <bool DELAY = false>
+template <bool DELAY = false, bool BATCH = false>
 __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
                                              const float* __restrict__ w, float scale40,
                                              const int64_t* s_r0, const int* s_pre,
@@ -145,7 +146,7 @@ __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
         }
         const int before = lo ? s_pre[lo - 1] : 0;
         const int64_t q = s_r0[lo] + (x - before);
-        tg[u] = s_base[lo] + col[q];
+        tg[u] = BATCH ? s_base[lo] + col[q] : col[q];
         wv[u] = w[q];
         if constexpr (DELAY) {
           const int d = min(max((int)delay[q], 1), R - 1);
@@ -226,7 +227,9 @@ __device__ __forceinline__ void net_update(const KModel& M, const LaneRates<S::k
   add_to_v(vh, vl, dv);
 }
 
-template <class S, bool DELAY>
+// BATCH: more than one copy of the network (B > 1); a single network skips
+// the copy offsets entirely.
+template <class S, bool DELAY, bool BATCH>
 __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   constexpr int NG = S::kNG;
   __shared__ int s_pre[kNetBlock];
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   const float I = A.i_const ? A.i_const[ii] : 0.0f;
   // element ii is neuron j of copy b: row j of the shared CSR, targets
   // offset by b N
-  const int64_t jj = ii % A.N;
+  const int64_t jj = BATCH ? ii % A.N : ii;
   const int my_base = (int)(ii - jj);
   const bool driven = A.ext_mask && act && A.ext_mask[jj];
   const float scale40 = A.w_scale * kFix;
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
         // flatten the (row, synapse) pairs of all spiking rows of the block
         s_r0[base + rank] = my_r0;
         s_pre[base + rank] = my_len;
-        s_base[base + rank] = my_base;
+        if constexpr (BATCH) s_base[base + rank] = my_base;
       }
     }
     __syncthreads();
@@ -317,11 +320,12 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
       block_inclusive_scan(s_pre, cnt);
       const int total = s_pre[cnt - 1];
       if constexpr (DELAY) {
-        scatter_flat<true>(A.col, A.w, scale40, s_r0, s_pre, s_base, cnt, total, A.acc, nullptr,
-                           A.delay, now, A.R, n);
+        scatter_flat<true, BATCH>(A.col, A.w, scale40, s_r0, s_pre, s_base, cnt, total, A.acc,
+                                  nullptr, A.delay, now, A.R, n);
       } else {
         unsigned long long* acc_e = A.acc + (int64_t)(k & 1) * 2 * n;
-        scatter_flat(A.col, A.w, scale40, s_r0, s_pre, s_base, cnt, total, acc_e, acc_e + n);
+        scatter_flat<false, BATCH>(A.col, A.w, scale40, s_r0, s_pre, s_base, cnt, total, acc_e,
+                                   acc_e + n);
       }
     }
 
@@ -401,6 +405,83 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ lis
   }
 }
 
+// ---- binned one-shot delivery ----------------------------------------------
+// With the rows sorted by target, the delivery is split by target range: a
+// block owns kSegRange targets and a chunk of the spiking rows, adds the
+// rows' events that fall in its range into LDS accumulators (one LDS atomic
+// per event), and then adds each touched accumulator to the global one with
+// a single device-scope atomic.  Every event is read once; the global atomics
+// fall from one per event (contention on a few thousand cache lines) to one
+// per target and chunk.  The sums are integers, so the result equals the
+// per-event delivery's bit for bit.
+constexpr int kSegRange = 1024;   // targets per range (2 x 8 KB of LDS)
+constexpr int kSegChunk = 2048;   // spiking rows per block
+
+// Per row: sortedness check and the offsets of the range boundaries.
+__global__ __launch_bounds__(256) void k_csr_segments(const int64_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ col, int64_t N,
+                                                      int R, int32_t* __restrict__ seg,
+                                                      int* __restrict__ unsorted) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int64_t r0 = row_ptr[j], r1 = row_ptr[j + 1];
+  int32_t* sj = seg + j * (int64_t)(R + 1);
+  int r = 0;
+  int32_t prev = -1;
+  bool bad = false;
+  for (int64_t q = r0; q < r1; ++q) {
+    const int32_t c = col[q];
+    bad |= c < prev || c < 0 || c >= N;
+    prev = c;
+    while (r <= R && (int64_t)r * kSegRange <= c) sj[r++] = (int32_t)(q - r0);
+  }
+  while (r <= R) sj[r++] = (int32_t)(r1 - r0);
+  if (bad) atomicOr(unsorted, 1);
+}
+
+__global__ __launch_bounds__(256) void k_scatter_binned(const int32_t* __restrict__ list,
+                                                        const unsigned* count,
+                                                        const int64_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const float* __restrict__ w,
+                                                        const int32_t* __restrict__ seg, int R,
+                                                        float scale40,
+                                                        unsigned long long* __restrict__ acc_e,
+                                                        unsigned long long* __restrict__ acc_i,
+                                                        int64_t n) {
+  __shared__ unsigned long long se[kSegRange], si[kSegRange];
+  const unsigned cnt = *count;
+  const int r = blockIdx.x;
+  const unsigned e0 = blockIdx.y * (unsigned)kSegChunk;
+  if (e0 >= cnt) return;  // uniform: the whole block leaves
+  for (int t = threadIdx.x; t < kSegRange; t += blockDim.x) se[t] = si[t] = 0ull;
+  __syncthreads();
+  const unsigned e1 = min(cnt, e0 + (unsigned)kSegChunk);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lo = r * kSegRange;
+  // one wavefront per row: the row's events with targets in [lo, lo + kSegRange)
+  for (unsigned e = e0 + wv; e < e1; e += nw) {
+    const int src = list[e];
+    const int32_t* sj = seg + (int64_t)src * (R + 1);
+    const int64_t base = row_ptr[src];
+    const int64_t a = base + sj[r], b = base + sj[r + 1];
+    for (int64_t q = a + lane; q < b; q += 64) {
+      const int t = col[q] - lo;
+      const float wv2 = w[q];
+      const unsigned long long inc = (unsigned long long)__float2ull_rn(fabsf(wv2) * scale40);
+      atomicAdd(wv2 > 0.0f ? &se[t] : &si[t], inc);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kSegRange; t += blockDim.x) {
+    const int64_t g = (int64_t)lo + t;
+    if (g < n) {
+      if (se[t]) atomicAdd(&acc_e[g], se[t]);
+      if (si[t]) atomicAdd(&acc_i[g], si[t]);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_apply(float* __restrict__ ge, float* __restrict__ gi,
                                                unsigned long long* __restrict__ acc_e,
                                                unsigned long long* __restrict__ acc_i, int64_t n) {
@@ -418,14 +499,14 @@ size_t list_off(int64_t n) { return acc_bytes(n); }
 size_t ctr_off(int64_t n) { return list_off(n) + (((size_t)n * 4 + 255) & ~(size_t)255); }
 size_t scratch_size(int64_t n) { return ctr_off(n) + 256; }
 
-template <class S, bool DELAY>
+template <class S, bool DELAY, bool BATCH>
 hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_net<S, DELAY>, kNetBlock, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_net<S, DELAY, BATCH>, kNetBlock, 0);
   if (e != hipSuccess) return e;
   const int64_t nb = (a.n + kNetBlock - 1) / kNetBlock;
   if (nb > (int64_t)ncu * per_cu) return hipErrorCooperativeLaunchTooLarge;
@@ -433,25 +514,32 @@ hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* args[] = {(void*)&m->km, (void*)&a};
-  return hipLaunchCooperativeKernel((const void*)k_net<S, DELAY>, dim3((unsigned)nb),
+  return hipLaunchCooperativeKernel((const void*)k_net<S, DELAY, BATCH>, dim3((unsigned)nb),
                                     dim3(kNetBlock), args, 0, s);
 }
 
 }  // namespace
 
-template <bool DELAY>
+template <bool DELAY, bool BATCH>
 static hipError_t launch_net_spec(hh_model* m, NetArgs& a, hipStream_t s) {
-  if (m->use_fixed && ClassicSpec::matches(m->km)) return launch_net<ClassicSpec, DELAY>(m, a, s);
-  if (m->use_fixed && CorticalSpec::matches(m->km)) return launch_net<CorticalSpec, DELAY>(m, a, s);
+  if (m->use_fixed && ClassicSpec::matches(m->km))
+    return launch_net<ClassicSpec, DELAY, BATCH>(m, a, s);
+  if (m->use_fixed && CorticalSpec::matches(m->km))
+    return launch_net<CorticalSpec, DELAY, BATCH>(m, a, s);
   switch (m->km.n_gates) {
-    case 1: return launch_net<GenericSpec<1>, DELAY>(m, a, s);
-    case 2: return launch_net<GenericSpec<2>, DELAY>(m, a, s);
-    case 3: return launch_net<GenericSpec<3>, DELAY>(m, a, s);
-    case 4: return launch_net<GenericSpec<4>, DELAY>(m, a, s);
-    case 5: return launch_net<GenericSpec<5>, DELAY>(m, a, s);
-    case 6: return launch_net<GenericSpec<6>, DELAY>(m, a, s);
+    case 1: return launch_net<GenericSpec<1>, DELAY, BATCH>(m, a, s);
+    case 2: return launch_net<GenericSpec<2>, DELAY, BATCH>(m, a, s);
+    case 3: return launch_net<GenericSpec<3>, DELAY, BATCH>(m, a, s);
+    case 4: return launch_net<GenericSpec<4>, DELAY, BATCH>(m, a, s);
+    case 5: return launch_net<GenericSpec<5>, DELAY, BATCH>(m, a, s);
+    case 6: return launch_net<GenericSpec<6>, DELAY, BATCH>(m, a, s);
     default: return hipErrorNotSupported;
   }
+}
+
+template <bool DELAY>
+static hipError_t launch_net_b(hh_model* m, NetArgs& a, hipStream_t s) {
+  return m->B > 1 ? launch_net_spec<DELAY, true>(m, a, s) : launch_net_spec<DELAY, false>(m, a, s);
 }
 
 int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_steps,
@@ -505,9 +593,9 @@ int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_
                          m->d_ring, count);
       if ((e = hipGetLastError()) != hipSuccess) return HH_E_HIP;
     }
-    e = launch_net_spec<true>(m, a, s);
+    e = launch_net_b<true>(m, a, s);
   } else {
-    e = launch_net_spec<false>(m, a, s);
+    e = launch_net_b<false>(m, a, s);
   }
   if (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorNotSupported) return HH_E_UNSUPPORTED;
   return e == hipSuccess ? HH_OK : HH_E_HIP;
@@ -540,6 +628,41 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
   m->w = w;
   m->nnz = nnz;
   m->w_scale = w_scale;
+  // segment table of the binned one-shot delivery (one copy, rows sorted by
+  // target; otherwise the per-event delivery serves)
+  if (m->d_seg) (void)hipFree(m->d_seg);
+  m->d_seg = nullptr;
+  m->seg_R = 0;
+  if (m->B == 1 && nnz > 0) {
+    const int64_t N = m->N;
+    const int R = (int)((N + kSegRange - 1) / kSegRange);
+    int32_t* seg = nullptr;
+    int* flag = nullptr;
+    if (hipMalloc((void**)&seg, (size_t)N * (R + 1) * sizeof(int32_t)) != hipSuccess) return HH_E_OOM;
+    if (hipMalloc((void**)&flag, sizeof(int)) != hipSuccess) {
+      (void)hipFree(seg);
+      return HH_E_OOM;
+    }
+    int unsorted = 1;
+    bool ok = hipMemset(flag, 0, sizeof(int)) == hipSuccess;
+    if (ok) {
+      hipLaunchKernelGGL(k_csr_segments, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, 0, row_ptr,
+                         col, N, R, seg, flag);
+      ok = hipGetLastError() == hipSuccess &&
+           hipMemcpy(&unsorted, flag, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess;
+    }
+    (void)hipFree(flag);
+    if (!ok) {
+      (void)hipFree(seg);
+      return HH_E_HIP;
+    }
+    if (unsorted) {
+      (void)hipFree(seg);
+    } else {
+      m->d_seg = seg;
+      m->seg_R = R;
+    }
+  }
   return HH_OK;
 }
 
@@ -612,8 +735,15 @@ int32_t hh_syn_propagate(hh_model* m, const uint32_t* spike_bits, float* state,
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)ncu * 8), dim3(256), 0, s, list, count, (int)m->N,
-                     m->row_ptr, m->col, m->w, m->w_scale * kFix, acc_e, acc_i);
+  if (m->d_seg) {
+    const unsigned chunks = (unsigned)((n + kSegChunk - 1) / kSegChunk);
+    hipLaunchKernelGGL(k_scatter_binned, dim3((unsigned)m->seg_R, chunks), dim3(256), 0, s, list,
+                       count, m->row_ptr, m->col, m->w, m->d_seg, m->seg_R, m->w_scale * kFix,
+                       acc_e, acc_i, n);
+  } else {
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)ncu * 8), dim3(256), 0, s, list, count, (int)m->N,
+                       m->row_ptr, m->col, m->w, m->w_scale * kFix, acc_e, acc_i);
+  }
   hipLaunchKernelGGL(k_apply, dim3(nb), dim3(256), 0, s, ge, gi, acc_e, acc_i, n);
   if (n_spikes_out)
     if (hipMemcpyAsync(n_spikes_out, count, sizeof(int32_t), hipMemcpyDeviceToDevice, s) !=

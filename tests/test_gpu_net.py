@@ -83,6 +83,59 @@ def test_syn_propagate_matches_oracle_and_is_deterministic():
     assert np.array_equal(outs[0][: 1 + G], st.cpu().numpy()[: 1 + G])
 
 
+def test_syn_propagate_binned_equals_per_event_delivery():
+    """The binned delivery (rows sorted by target) and the per-event delivery
+    (the same CSR with every row's synapses shuffled, which the library
+    detects) give identical conductances, bit for bit; so do the B = 2 copies
+    of a batch (per-event path) and the single network, copy by copy."""
+    print_case("syn_propagate binned vs per-event")
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    n = 3001
+    m = W.net_model()
+    rp, col, w = W.net_csr(n=n, fan_out=700, seed=13, inh_scale=4.0)
+    rng = np.random.default_rng(2)
+    col_s, w_s = col.copy(), w.copy()
+    for j in range(n):
+        a, b = rp[j], rp[j + 1]
+        p = rng.permutation(b - a)
+        col_s[a:b], w_s[a:b] = col[a:b][p], w[a:b][p]
+    s = (rng.random(n) < 0.6).astype(np.uint8)
+    bits = np.zeros(((n + 31) // 32) * 32, np.uint8)
+    bits[:n] = s
+    packed = np.packbits(bits.reshape(-1, 8), axis=1, bitorder="little").reshape(-1).view(np.uint32)
+    G = len(m["gates"])
+    outs = []
+    for c_, w_ in ((col, w), (col_s, w_s)):
+        M = hh.Model(m, n)
+        bufs = [_dev(rp), _dev(c_), _dev(w_)]
+        M.attach_csr(bufs[0], bufs[1], bufs[2], 0.05)
+        st = M.init_state(M.new_state(), v0_scalar=-65.0)
+        cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+        M.syn_propagate(_dev(packed), st, cnt)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == int(s.sum())
+        outs.append(st.cpu().numpy())
+    assert outs[0][1 + G].sum() > 0
+    assert np.array_equal(outs[0], outs[1])
+    # two copies: copy 0 spikes as above, copy 1 with the complementary bits
+    s2 = np.concatenate([s, 1 - s])
+    bits2 = np.zeros(((2 * n + 31) // 32) * 32, np.uint8)
+    bits2[:2 * n] = s2
+    packed2 = np.packbits(bits2.reshape(-1, 8), axis=1, bitorder="little").reshape(-1).view(np.uint32)
+    M2 = hh.Model(m, n, 2)
+    bufs = [_dev(rp), _dev(col), _dev(w)]
+    M2.attach_csr(bufs[0], bufs[1], bufs[2], 0.05)
+    st2 = M2.init_state(M2.new_state(), v0_scalar=-65.0)
+    M2.syn_propagate(_dev(packed2), st2)
+    g2 = st2.cpu().numpy()
+    assert np.array_equal(g2[:, :n], outs[0])
+    ge, gi = np.zeros(n), np.zeros(n)
+    O.syn_deliver((rp, col, w), 0.05, 1 - s, ge, gi)
+    assert np.allclose(g2[1 + G, n:], ge, rtol=3e-7, atol=1e-9)
+    assert np.allclose(g2[2 + G, n:], gi, rtol=3e-7, atol=1e-9)
+
+
 def test_syn_propagate_full_network_all_spiking():
     print_case("syn_propagate full 38000 x 2630 all spiking")
     torch = need_gpu()
