@@ -202,6 +202,41 @@ def bench_headline(steps, warmup, fusion=32):
 
 
 # ---------------------------------------------------------------------------
+# classic validation population: 1,024 neurons x 10,000 steps, dt 0.01 ms
+# ---------------------------------------------------------------------------
+def bench_classic(reps=5):
+    """1,024 neurons are 16 wavefronts: one per SIMD on 16 of the 1,024
+    SIMDs, so the run is bounded by one wavefront's serial issue, not by the
+    chip.  The serial bound: each SIMD issues 32 lane-slots per cycle, so 64
+    neurons take 2 x slots cycles per step."""
+    import torch
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import workloads as W
+    n, T = 1024, 10000
+    m = W.classic_hh(dt=0.01)
+    M = hh.Model(m, n)
+    I = torch.tensor(W.validation_currents(n, seed=1), device="cuda")
+    st = M.new_state()
+    bits = torch.zeros((T, M.words), dtype=torch.int32, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for k in range(reps + 1):
+        M.init_state(st, v0_scalar=-65.0)
+        a.record()
+        M.step_n(st, T, 0, i_const=I, spikes=bits)
+        b.record()
+        _sync()
+        if k:
+            times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    slots = slots_per_update(m, noise=False)
+    bound = (n // 64) * 32 * 2.4e9 / slots
+    return {"n": n, "T": T, "dt_ms": 0.01, "ms": ms, "updates_per_s": n * T / (ms / 1e3),
+            "slots_per_update": slots, "serial_bound_updates_per_s": bound,
+            "frac_of_serial_bound": n * T / (ms / 1e3) / bound}
+
+
+# ---------------------------------------------------------------------------
 # tabulated gate kinetics against the plain kernel on the headline workload
 # ---------------------------------------------------------------------------
 def bench_table(n=1 << 20, T=4000, nodes=(161, 641), eval_neurons=65536, fusion=32):
@@ -473,7 +508,62 @@ def bench_network(T=10000):
     status, bad = M.check()
     if status != 0:
         raise RuntimeError("network run failed: status %d (neuron %d)" % (status, bad))
-    n_spk = int(np.unpackbits(spikes.cpu().numpy().view(np.uint8)).sum())
+    spk_bits = np.unpackbits(spikes.cpu().numpy().view(np.uint8), bitorder="little")
+    spk_bits = spk_bits.reshape(T, -1)[:, :n]
+    n_spk = int(spk_bits.sum())
+    row_len = np.diff(csr[0])
+    n_events = int((spk_bits.sum(axis=0).astype(np.int64) * row_len).sum())
+    # the same neurons, drive and grid with empty rows: the step without any
+    # synaptic delivery (the neurons then spike only from the external drive)
+    Me = hh.Model(m, n)
+    rp0 = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    Me.attach_csr(rp0, torch.empty(0, dtype=torch.int32, device="cuda"),
+                  torch.empty(0, dtype=torch.float32, device="cuda"), W.NET_W_SCALE)
+    Me.set_external(torch.tensor(mask, device="cuda"), thr, W.NET_W_EXT, 3)
+    ste = Me.new_state()
+    Me.init_state(ste, v0=v0)
+    Me.step_n(ste, 200, 0, spikes=spikes)
+    Me.init_state(ste, v0=v0)
+    _sync()
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record()
+    Me.step_n(ste, T, 0, spikes=spikes)
+    a1.record()
+    _sync()
+    no_deliv_us = a0.elapsed_time(a1) / T * 1e3
+    del Me, ste
+    # a batch of copies of the network in one grid (the paper's parallel
+    # simulations): throughput as copies x speed
+    batch = {}
+    for B in (2, 3, 4, 6):
+        Mb = hh.Model(m, n, B)
+        Mb.attach_csr(rp, col, w, W.NET_W_SCALE)
+        Mb.set_external(torch.tensor(mask, device="cuda"), thr, W.NET_W_EXT, 3)
+        stb = Mb.new_state()
+        v0b = torch.tensor(np.concatenate([W.net_v0(n, 3 + b) for b in range(B)]), device="cuda")
+        Tb = 2000
+        Mb.init_state(stb, v0=v0b)
+        try:
+            Mb.step_n(stb, 200, 0)
+        except hh.HHError as err:
+            # more copies than one co-resident grid holds: refused on the host
+            batch["B%d" % B] = {"copies": B, "refused": str(err)}
+            del Mb, stb
+            break
+        Mb.init_state(stb, v0=v0b)
+        _sync()
+        a0.record()
+        Mb.step_n(stb, Tb, 0)
+        a1.record()
+        _sync()
+        status, bad = Mb.check()
+        if status != 0:
+            raise RuntimeError("network batch failed: status %d (neuron %d)" % (status, bad))
+        us = a0.elapsed_time(a1) / Tb * 1e3
+        batch["B%d" % B] = {"copies": B, "steps": Tb, "kernel_us_per_step": us,
+                            "updates_per_s": B * n / (us * 1e-6),
+                            "copies_x_speed": B * (0.1e-3 / (us * 1e-6))}
+        del Mb, stb
     # full-load scatter: every neuron spikes once (99.94 M synaptic events)
     allbits = torch.full((M.words,), -1, dtype=torch.int32, device="cuda")
     s2 = st.clone()
@@ -537,7 +627,10 @@ def bench_network(T=10000):
         "kernel_us_per_step": kern_us, "barrier_floor": floor,
         "pathway_delays_background": delayed,
         "updates_per_s": n * T / wall, "mean_rate_hz": n_spk / n / (T * 1e-4),
-        "synaptic_events": n_spk * 2630,
+        "synaptic_events": n_events,
+        "no_delivery_us_per_step": no_deliv_us,
+        "delivery_us_per_step": kern_us - no_deliv_us,
+        "batch": batch,
         "scatter_full": {"events": nnz, "ms": sc_ms, "events_per_s": nnz / (sc_ms / 1e3),
                          "alg_GBs": nnz * 8 / (sc_ms / 1e3) / 1e9,
                          "hbm_frac": nnz * 8 / (sc_ms / 1e3) / 1e9 / HBM_PEAK_GBS},
@@ -760,24 +853,30 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
     I += 5.0
     res = {"training": {"transitions": n_trans, "epochs": epochs, "gen_s": t_gen, **training}}
 
-    def kernel_time(fn):
+    def kernel_time(fn, reps=3):
+        """Median over reps runs after one warm-up; models and buffers are
+        allocated before, so only the simulation is timed."""
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        fn()  # warm-up
-        _sync()
-        e0.record()
-        out = fn()
-        e1.record()
-        _sync()
-        return e0.elapsed_time(e1), out
+        out = fn()  # warm-up
+        ms = []
+        for _ in range(reps):
+            _sync()
+            e0.record()
+            out = fn()
+            e1.record()
+            _sync()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms)), out
 
-    ms_ref, (_, _, bits_ref) = kernel_time(lambda: SG.plain_run(n, T, i_dense=I))
+    runs = {"plain": SG.PlainRun(n, T), "sur": SG.SurrogateRun(n, T)}
+    ms_ref, (_, _, bits_ref) = kernel_time(lambda: runs["plain"].run(i_dense=I))
     ref_np = bits_ref.cpu().numpy()
     rows = []
     for act, label, ce in (("silu", "surrogate k=10, SiLU (configured activation)", 10),
                            ("hardswish", "surrogate k=10, hard-swish", 10),
                            ("hardswish", "surrogate k=10, hard-swish, check every 20 calls", 20)):
         ms_s, (_, _, bits_s, stats) = kernel_time(
-            lambda: SG.deploy(nets[act], n, T, i_dense=I, check_every=ce, act=act))
+            lambda: runs["sur"].run(nets[act], i_dense=I, check_every=ce, act=act))
         st = stats.cpu().numpy()
         e = SG.spike_time_error(ref_np, bits_s.cpu().numpy(), n, 0.025, 0.025,
                                 max_neurons=eval_neurons)
@@ -785,29 +884,31 @@ def bench_surrogate(n=1 << 20, T=4000, eval_neurons=65536, epochs=8):
                          speedup=ms_ref / ms_s,
                          surrogate_call_frac=float(st[0] / max(st[0] + st[1], 1)),
                          failed_checks=int(st[2]), **e))
-        del bits_s
-    ms_noise, _ = kernel_time(lambda: SG.deploy(nets["hardswish"], n, T, noise=(5.0, 3.0, 2),
-                                                spikes=False, act="hardswish"))
-    ms_plain_noise, _ = kernel_time(lambda: SG.plain_run(n, T, noise=(5.0, 3.0, 2), spikes=False))
+    del runs
+    sur_nb, plain_nb = SG.SurrogateRun(n, T, spikes=False), SG.PlainRun(n, T, spikes=False)
+    ms_noise, _ = kernel_time(lambda: sur_nb.run(nets["hardswish"], noise=(5.0, 3.0, 2),
+                                                 act="hardswish"))
+    ms_plain_noise, _ = kernel_time(lambda: plain_nb.run(noise=(5.0, 3.0, 2)))
+    del sur_nb, plain_nb
     rows.append(dict(method="plain dt=0.025 (reference)", ms=ms_ref, speedup=1.0,
                      mean_abs_ms=0.0, p95_abs_ms=0.0, unmatched_frac=0.0))
     for nn in (161, 641):
-        mst, (_, _, bits_t) = kernel_time(lambda: SG.plain_run(n, T, i_dense=I,
-                                                               table=(-100.0, 60.0, nn)))
+        pr = SG.PlainRun(n, T, table=(-100.0, 60.0, nn))
+        mst, (_, _, bits_t) = kernel_time(lambda: pr.run(i_dense=I))
         e = SG.spike_time_error(ref_np, bits_t.cpu().numpy(), n, 0.025, 0.025,
                                 max_neurons=eval_neurons)
         rows.append(dict(method="plain dt=0.025 tabulated %d nodes" % nn, ms=mst,
                          speedup=ms_ref / mst, **e))
-        del bits_t
+        del pr, bits_t
     for dt, vm in ((0.05, "fe"), (0.1, "ee"), (0.25, "ee")):
         r = int(round(dt / 0.025))
         Ic = SG.coarse_input(I, r)
-        msc, (_, _, bits_c) = kernel_time(lambda: SG.plain_run(n, T // r, dt=dt, v_method=vm,
-                                                               i_dense=Ic))
+        pr = SG.PlainRun(n, T // r, dt=dt, v_method=vm)
+        msc, (_, _, bits_c) = kernel_time(lambda: pr.run(i_dense=Ic))
         e = SG.spike_time_error(ref_np, bits_c.cpu().numpy(), n, 0.025, dt,
                                 max_neurons=eval_neurons)
         rows.append(dict(method="plain dt=%g %s" % (dt, vm), ms=msc, speedup=ms_ref / msc, **e))
-        del Ic
+        del Ic, pr, bits_c
     # a surrogate row is dominated by a plain row that is at least as fast
     # and at least as accurate (mean |dt| and unmatched fraction); "beats
     # the reference" = faster than plain dt = 0.025 within the stated error
@@ -908,7 +1009,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--parts", default="layer,net,surrogate,table,cable,encryption,probe")
+    ap.add_argument("--parts", default="classic,layer,net,surrogate,table,cable,encryption,probe")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--counters", action="store_true",
                     help="run the copy + one headline launch for rocprofv3 counter passes")
@@ -932,6 +1033,9 @@ def main():
     extra = {}
     if "probe" in parts:
         extra["issue_rates_Tops"] = probe_rates()
+    if "classic" in parts:
+        extra["classic_1024"] = bench_classic()
+        print("[bench] classic done", file=sys.stderr, flush=True)
     if "layer" in parts:
         extra["layer"] = bench_layer()
         print("[bench] layer done", file=sys.stderr, flush=True)

@@ -416,6 +416,9 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ lis
 // per-event delivery's bit for bit.
 constexpr int kSegRange = 1024;   // targets per range (2 x 8 KB of LDS)
 constexpr int kSegChunk = 2048;   // spiking rows per block
+constexpr int kBinBlock = 512;    // threads per block: 32 groups of 16 lanes
+constexpr int kBinGroup = 16;     // lanes that share one row's segment
+constexpr int kBinUnroll = 8;     // loads in flight per lane (128 events per pass)
 
 // Per row: sortedness check and the offsets of the range boundaries.
 __global__ __launch_bounds__(256) void k_csr_segments(const int64_t* __restrict__ row_ptr,
@@ -439,41 +442,75 @@ __global__ __launch_bounds__(256) void k_csr_segments(const int64_t* __restrict_
   if (bad) atomicOr(unsorted, 1);
 }
 
-__global__ __launch_bounds__(256) void k_scatter_binned(const int32_t* __restrict__ list,
-                                                        const unsigned* count,
-                                                        const int64_t* __restrict__ row_ptr,
-                                                        const int32_t* __restrict__ col,
-                                                        const float* __restrict__ w,
-                                                        const int32_t* __restrict__ seg, int R,
-                                                        float scale40,
-                                                        unsigned long long* __restrict__ acc_e,
-                                                        unsigned long long* __restrict__ acc_i,
-                                                        int64_t n) {
+// Grid: R ranges x chunks blocks in one dimension.  Consecutive hardware
+// block ids go to the eight XCDs in turn; the remap gives each XCD a run of
+// consecutive logical blocks, i.e. neighbouring ranges of the same chunk, so
+// the cache lines two neighbouring segments share are fetched into one L2.
+__global__ __launch_bounds__(kBinBlock) void k_scatter_binned(
+    const int32_t* __restrict__ list, const unsigned* count, const int64_t* __restrict__ row_ptr,
+    const int32_t* __restrict__ col, const float* __restrict__ w, const int32_t* __restrict__ seg,
+    int R, float scale40, unsigned long long* __restrict__ acc_e,
+    unsigned long long* __restrict__ acc_i, int64_t n) {
   __shared__ unsigned long long se[kSegRange], si[kSegRange];
+  __shared__ int64_t m_a[kSegChunk];
+  __shared__ int32_t m_len[kSegChunk];
+  const unsigned nb = gridDim.x, bid = blockIdx.x;
+  const unsigned xcd = bid & 7u, idx = bid >> 3, per = nb >> 3, rem = nb & 7u;
+  const unsigned logical = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+  const int r = (int)(logical % (unsigned)R);
+  const unsigned e0 = (logical / (unsigned)R) * (unsigned)kSegChunk;
   const unsigned cnt = *count;
-  const int r = blockIdx.x;
-  const unsigned e0 = blockIdx.y * (unsigned)kSegChunk;
   if (e0 >= cnt) return;  // uniform: the whole block leaves
-  for (int t = threadIdx.x; t < kSegRange; t += blockDim.x) se[t] = si[t] = 0ull;
-  __syncthreads();
-  const unsigned e1 = min(cnt, e0 + (unsigned)kSegChunk);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int lo = r * kSegRange;
-  // one wavefront per row: the row's events with targets in [lo, lo + kSegRange)
-  for (unsigned e = e0 + wv; e < e1; e += nw) {
-    const int src = list[e];
-    const int32_t* sj = seg + (int64_t)src * (R + 1);
-    const int64_t base = row_ptr[src];
-    const int64_t a = base + sj[r], b = base + sj[r + 1];
-    for (int64_t q = a + lane; q < b; q += 64) {
-      const int t = col[q] - lo;
-      const float wv2 = w[q];
-      const unsigned long long inc = (unsigned long long)__float2ull_rn(fabsf(wv2) * scale40);
-      atomicAdd(wv2 > 0.0f ? &se[t] : &si[t], inc);
+  const int rows = (int)min(cnt - e0, (unsigned)kSegChunk);
+  const int tid = threadIdx.x;
+  for (int t = tid; t < kSegRange; t += kBinBlock) se[t] = si[t] = 0ull;
+  // the chunk's segments for this range, four rows per thread loaded together
+  {
+    int src[kSegChunk / kBinBlock];
+#pragma unroll
+    for (int u = 0; u < kSegChunk / kBinBlock; ++u) {
+      const int i = tid + u * kBinBlock;
+      src[u] = i < rows ? list[e0 + i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kSegChunk / kBinBlock; ++u) {
+      const int i = tid + u * kBinBlock;
+      if (i < rows) {
+        const int32_t* sj = seg + (int64_t)src[u] * (R + 1) + r;
+        const int32_t s0 = sj[0], s1 = sj[1];
+        m_a[i] = row_ptr[src[u]] + s0;
+        m_len[i] = s1 - s0;
+      }
     }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < kSegRange; t += blockDim.x) {
+  const int lo = r * kSegRange;
+  const int sub = tid & (kBinGroup - 1);
+  constexpr int kGroups = kBinBlock / kBinGroup;
+  for (int i = tid / kBinGroup; i < rows; i += kGroups) {
+    const int64_t a = m_a[i];
+    const int len = m_len[i];
+    for (int b0 = 0; b0 < len; b0 += kBinGroup * kBinUnroll) {
+      int32_t c[kBinUnroll];
+      float wv[kBinUnroll];
+#pragma unroll
+      for (int u = 0; u < kBinUnroll; ++u) {
+        const int k = b0 + u * kBinGroup + sub;
+        c[u] = k < len ? col[a + k] : -1;
+        wv[u] = k < len ? w[a + k] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kBinUnroll; ++u) {
+        if (c[u] >= 0) {
+          const unsigned long long inc =
+              (unsigned long long)__float2ull_rn(fabsf(wv[u]) * scale40);
+          atomicAdd(wv[u] > 0.0f ? &se[c[u] - lo] : &si[c[u] - lo], inc);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < kSegRange; t += kBinBlock) {
     const int64_t g = (int64_t)lo + t;
     if (g < n) {
       if (se[t]) atomicAdd(&acc_e[g], se[t]);
@@ -633,9 +670,12 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
   if (m->d_seg) (void)hipFree(m->d_seg);
   m->d_seg = nullptr;
   m->seg_R = 0;
-  if (m->B == 1 && nnz > 0) {
+  // The table holds N (R + 1) offsets; it is built only while that is no
+  // more than the column array (N^2 / 1024 grows past it for large N).
+  const int64_t R_tab = (m->N + kSegRange - 1) / kSegRange;
+  if (m->B == 1 && nnz > 0 && m->N * (R_tab + 1) <= nnz) {
     const int64_t N = m->N;
-    const int R = (int)((N + kSegRange - 1) / kSegRange);
+    const int R = (int)R_tab;
     int32_t* seg = nullptr;
     int* flag = nullptr;
     if (hipMalloc((void**)&seg, (size_t)N * (R + 1) * sizeof(int32_t)) != hipSuccess) return HH_E_OOM;
@@ -737,7 +777,7 @@ int32_t hh_syn_propagate(hh_model* m, const uint32_t* spike_bits, float* state,
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (m->d_seg) {
     const unsigned chunks = (unsigned)((n + kSegChunk - 1) / kSegChunk);
-    hipLaunchKernelGGL(k_scatter_binned, dim3((unsigned)m->seg_R, chunks), dim3(256), 0, s, list,
+    hipLaunchKernelGGL(k_scatter_binned, dim3((unsigned)m->seg_R * chunks), dim3(kBinBlock), 0, s, list,
                        count, m->row_ptr, m->col, m->w, m->d_seg, m->seg_R, m->w_scale * kFix,
                        acc_e, acc_i, n);
   } else {

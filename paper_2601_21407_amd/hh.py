@@ -287,6 +287,8 @@ class Model:
         return torch.empty((self.n_state, self.n), dtype=torch.float32, device=device)
 
     def init_state(self, state, v0=None, v0_scalar: float = -65.0):
+        _need(state, "state", _F32, self.n_state * self.n, exact=True)
+        _need(v0, "v0", _F32, self.n, exact=True)
         _ok(lib.hh_init_state(self.h, _ptr(state), _ptr(v0), float(v0_scalar), _stream()),
             "hh_init_state")
         return state

@@ -157,37 +157,64 @@ def spike_time_error(ref_bits, bits, n, dt_ref, dt_test, window_ms=2.0, max_neur
             "unmatched_frac": unmatched / max(n_ref + int(ts[nn]), 1)}
 
 
+class SurrogateRun:
+    """Model, state, fallback flags, spike words and call counts of a
+    deployment on n neurons (cortical set, nominal rates) for T plain-step
+    equivalents, allocated once; run() starts the simulation from rest, so
+    repeated runs time only the simulation."""
+
+    def __init__(self, n, T, *, spikes=True, dev="cuda"):
+        self.T = T
+        self.M = hh.Model(W.custom_channels(dt=0.025), n)
+        self.st = self.M.new_state()
+        self.flags = torch.zeros(n, dtype=torch.uint8, device=dev)
+        self.bits = torch.zeros((T, self.M.words), dtype=torch.int32, device=dev) if spikes else None
+        self.stats = torch.zeros(3, dtype=torch.int64, device=dev)
+
+    def run(self, packed, *, i_dense=None, noise=None, check_every=CHECK_EVERY,
+            v_fallback=V_FALLBACK, check_tol=CHECK_TOL, k=K_STEPS, act=ACT):
+        """Returns (model, state, spike bits or None, stats [surrogate calls,
+        plain calls, failed checks])."""
+        self.M.init_state(self.st, v0_scalar=-65.0)
+        self.flags.zero_()
+        self.stats.zero_()
+        hh.surrogate_step_n(self.M, packed, self.st, self.flags, self.T, k, 0, i_dense=i_dense,
+                            noise=noise, v_fallback=v_fallback, check_every=check_every,
+                            check_tol=check_tol, spikes=self.bits, stats=self.stats, act=act)
+        return self.M, self.st, self.bits, self.stats
+
+
+class PlainRun:
+    """The plain kernel on the same workload, allocated once; table =
+    (v_lo, v_hi, n_nodes) switches to tabulated gate kinetics."""
+
+    def __init__(self, n, T, *, dt=0.025, v_method="fe", spikes=True, table=None, dev="cuda"):
+        self.T = T
+        self.M = hh.Model(W.custom_channels(dt=dt, v_method=v_method), n)
+        if table is not None:
+            self.M.set_rate_table(*table)
+        self.st = self.M.new_state()
+        self.bits = torch.zeros((T, self.M.words), dtype=torch.int32, device=dev) if spikes else None
+
+    def run(self, *, i_dense=None, noise=None):
+        self.M.init_state(self.st, v0_scalar=-65.0)
+        self.M.step_n(self.st, self.T, 0, i_dense=i_dense, noise=noise, spikes=self.bits)
+        return self.M, self.st, self.bits
+
+
 def deploy(packed, n, T, *, i_dense=None, noise=None, spikes=True, check_every=CHECK_EVERY,
            v_fallback=V_FALLBACK, check_tol=CHECK_TOL, k=K_STEPS, act=ACT, dev="cuda"):
-    """Run the surrogate deployment kernel on n neurons (cortical set,
-    nominal rates) for T plain-step equivalents, k steps per call.  Returns (model, state,
-    spike bits or None, stats [surrogate calls, plain calls, failed checks])."""
-    m = W.custom_channels(dt=0.025)
-    M = hh.Model(m, n)
-    st = M.new_state()
-    M.init_state(st, v0_scalar=-65.0)
-    flags = torch.zeros(n, dtype=torch.uint8, device=dev)
-    bits = torch.zeros((T, M.words), dtype=torch.int32, device=dev) if spikes else None
-    stats = torch.zeros(3, dtype=torch.int64, device=dev)
-    hh.surrogate_step_n(M, packed, st, flags, T, k, 0, i_dense=i_dense, noise=noise,
-                        v_fallback=v_fallback, check_every=check_every, check_tol=check_tol,
-                        spikes=bits, stats=stats, act=act)
-    return M, st, bits, stats
+    """One deployment run (SurrogateRun allocated and run once)."""
+    return SurrogateRun(n, T, spikes=spikes, dev=dev).run(
+        packed, i_dense=i_dense, noise=noise, check_every=check_every, v_fallback=v_fallback,
+        check_tol=check_tol, k=k, act=act)
 
 
 def plain_run(n, T, *, dt=0.025, v_method="fe", i_dense=None, noise=None, spikes=True,
               dev="cuda", table=None):
-    """The plain kernel on the same workload; table = (v_lo, v_hi, n_nodes)
-    switches to tabulated gate kinetics."""
-    m = W.custom_channels(dt=dt, v_method=v_method)
-    M = hh.Model(m, n)
-    if table is not None:
-        M.set_rate_table(*table)
-    st = M.new_state()
-    M.init_state(st, v0_scalar=-65.0)
-    bits = torch.zeros((T, M.words), dtype=torch.int32, device=dev) if spikes else None
-    M.step_n(st, T, 0, i_dense=i_dense, noise=noise, spikes=bits)
-    return M, st, bits
+    """One plain run (PlainRun allocated and run once)."""
+    return PlainRun(n, T, dt=dt, v_method=v_method, spikes=spikes, table=table,
+                    dev=dev).run(i_dense=i_dense, noise=noise)
 
 
 def coarse_input(I, r):

@@ -83,24 +83,26 @@ def test_syn_propagate_matches_oracle_and_is_deterministic():
     assert np.array_equal(outs[0][: 1 + G], st.cpu().numpy()[: 1 + G])
 
 
-def test_syn_propagate_binned_equals_per_event_delivery():
+@pytest.mark.parametrize("n,fan_out,p_spike", [(3001, 700, 0.6), (9001, 300, 0.7)])
+def test_syn_propagate_binned_equals_per_event_delivery(n, fan_out, p_spike):
     """The binned delivery (rows sorted by target) and the per-event delivery
     (the same CSR with every row's synapses shuffled, which the library
     detects) give identical conductances, bit for bit; so do the B = 2 copies
-    of a batch (per-event path) and the single network, copy by copy."""
-    print_case("syn_propagate binned vs per-event")
+    of a batch (per-event path) and the single network, copy by copy.  The
+    first case has segments longer than one 128-event pass in one chunk of
+    rows; the second several chunks of rows and target ranges, both ragged."""
+    print_case("syn_propagate binned vs per-event n=%d fan_out=%d" % (n, fan_out))
     torch = need_gpu()
     from paper_2601_21407_amd import hh
-    n = 3001
     m = W.net_model()
-    rp, col, w = W.net_csr(n=n, fan_out=700, seed=13, inh_scale=4.0)
+    rp, col, w = W.net_csr(n=n, fan_out=fan_out, seed=13, inh_scale=4.0)
     rng = np.random.default_rng(2)
     col_s, w_s = col.copy(), w.copy()
     for j in range(n):
         a, b = rp[j], rp[j + 1]
         p = rng.permutation(b - a)
         col_s[a:b], w_s[a:b] = col[a:b][p], w[a:b][p]
-    s = (rng.random(n) < 0.6).astype(np.uint8)
+    s = (rng.random(n) < p_spike).astype(np.uint8)
     bits = np.zeros(((n + 31) // 32) * 32, np.uint8)
     bits[:n] = s
     packed = np.packbits(bits.reshape(-1, 8), axis=1, bitorder="little").reshape(-1).view(np.uint32)
