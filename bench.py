@@ -508,6 +508,20 @@ def bench_network(T=10000):
     status, bad = M.check()
     if status != 0:
         raise RuntimeError("network run failed: status %d (neuron %d)" % (status, bad))
+    # the same run with the push delivery (device atomics into arrival
+    # accumulators) for comparison; the results are identical
+    M.set_delivery("push")
+    M.init_state(st, v0=v0)
+    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    spikes_push = torch.zeros_like(spikes)
+    p0.record()
+    M.step_n(st, T, 0, spikes=spikes_push)
+    p1.record()
+    _sync()
+    push_us = p0.elapsed_time(p1) / T * 1e3
+    push_identical = bool(torch.equal(spikes_push, spikes))
+    del spikes_push
+    M.set_delivery("auto")
     spk_bits = np.unpackbits(spikes.cpu().numpy().view(np.uint8), bitorder="little")
     spk_bits = spk_bits.reshape(T, -1)[:, :n]
     n_spk = int(spk_bits.sum())
@@ -628,6 +642,8 @@ def bench_network(T=10000):
         "pathway_delays_background": delayed,
         "updates_per_s": n * T / wall, "mean_rate_hz": n_spk / n / (T * 1e-4),
         "synaptic_events": n_events,
+        "delivery": "pull (each block adds the previous step's events for its own targets)",
+        "push_delivery_us_per_step": push_us, "push_raster_identical": push_identical,
         "no_delivery_us_per_step": no_deliv_us,
         "delivery_us_per_step": kern_us - no_deliv_us,
         "batch": batch,

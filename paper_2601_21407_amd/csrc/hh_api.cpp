@@ -131,6 +131,7 @@ int32_t hh_init(hh_model** out, const hh_model_desc* desc, int64_t N, int32_t B,
   m->cm = cm;
   m->k_fuse = 32;
   m->use_fixed = 1;
+  m->net_pull = 1;
   if (hipGetDevice(&m->device) != hipSuccess) {
     delete m;
     return HH_E_HIP;

@@ -51,12 +51,16 @@ struct hh_model {
   // device flags: [0] first non-finite neuron (INT32_MAX = none), [1] timeout
   int32_t* d_flags;
   // recurrent network
-  // binned one-shot delivery (rows sorted by target, one copy): for row j
-  // and target range r (kSegRange targets each), d_seg[j (R + 1) + r] is the
-  // offset within the row of its first target >= r kSegRange; null when the
-  // rows are not sorted or B > 1
+  // deliveries by target range (rows sorted by target, one copy): for row j
+  // and target range r (512 targets each, a network block's neurons),
+  // d_seg[j (R + 1) + r] is the offset within the row of its first target
+  // >= 512 r; null when the rows are not sorted, B > 1 or the table would
+  // be larger than the column array
   int32_t* d_seg;
   int32_t seg_R;
+  // network time loop: deliver by pull when the segment table exists (1,
+  // the default) or always by push (0)
+  int32_t net_pull;
   const int64_t* row_ptr;
   const int32_t* col;
   const float* w;

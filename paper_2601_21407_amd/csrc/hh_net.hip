@@ -70,6 +70,13 @@ struct NetArgs {
   float mu, sigma, bg_lam, bg_p0;
   int32_t bg_kmax;
   uint64_t seed;
+  // pull delivery (one network, one-step delays, rows sorted by target):
+  // the spiking rows of step k in plist[k & 1][0 .. pcount[k % 3]), and the
+  // segment table of the rows by the blocks' target ranges
+  int32_t* plist;
+  unsigned* pcount;
+  const int32_t* seg;
+  int32_t seg_R;
   unsigned* bar;            // [0] arrivals (monotonic within a launch)
   int32_t* flags;           // [0] first non-finite neuron, [1] timeout
   uint32_t spin_limit;
@@ -169,6 +176,76 @@ __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
   }
 }
 
+// Pull delivery of one step's spikes into the block's own targets: the
+// block owning targets [lo, lo + kNetBlock) reads the step's list of spiking
+// rows, then each row's segment of targets in its range (the segment table
+// of the rows sorted by target), and adds the events into LDS accumulators,
+// one per target and sign.  No device atomics and no accumulator buffers;
+// the integer sums equal those of the push delivery bit for bit.  The list
+// and its count were written by other blocks before the last grid barrier:
+// they are read with device-scope loads.  s_a and s_len are staging arrays
+// of kNetBlock entries; the accumulators are complete when it returns.
+__device__ void pull_deliver(const int32_t* list, const unsigned* countp, int64_t n,
+                             const int32_t* __restrict__ seg, int R, int r,
+                             const int64_t* __restrict__ row_ptr,
+                             const int32_t* __restrict__ col, const float* __restrict__ w,
+                             float scale40, int64_t lo, unsigned long long* s_e,
+                             unsigned long long* s_i, int64_t* s_a, int* s_len) {
+  const int tid = threadIdx.x;
+  // the count and the first kNetBlock entries in one round trip
+  unsigned cnt = __hip_atomic_load(countp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int32_t spec = tid < n ? __hip_atomic_load(&list[tid], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)
+                               : 0;
+  // every lane reads the same final count (no block adds to it until the
+  // barrier after this one); thread 0's copy is still broadcast so that the
+  // loop below, which holds barriers, is uniform over the block by
+  // construction
+  __shared__ unsigned s_pc;
+  if (tid == 0) s_pc = (unsigned)min((int64_t)cnt, n);
+  __syncthreads();
+  cnt = s_pc;
+  constexpr int G = 16;  // lanes per row segment
+  for (unsigned c0 = 0; c0 < cnt; c0 += kNetBlock) {
+    const unsigned e = c0 + tid;
+    if (e < cnt) {
+      const int32_t src = c0 == 0 ? spec
+                                  : __hip_atomic_load(&list[e], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+      const int32_t* sj = seg + (int64_t)src * (R + 1) + r;
+      const int32_t s0 = sj[0], s1 = sj[1];
+      s_a[tid] = row_ptr[src] + s0;
+      s_len[tid] = s1 - s0;
+    }
+    __syncthreads();
+    const int rows = (int)min(cnt - c0, (unsigned)kNetBlock);
+    for (int x = tid / G; x < rows; x += kNetBlock / G) {
+      const int64_t a = s_a[x];
+      const int len = s_len[x];
+      for (int b0 = 0; b0 < len; b0 += 4 * G) {
+        int32_t c[4];
+        float wv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = b0 + u * G + (tid & (G - 1));
+          c[u] = q < len ? col[a + q] : -1;
+          wv[u] = q < len ? w[a + q] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (c[u] >= 0) {
+            const unsigned long long inc =
+                (unsigned long long)__float2ull_rn(fabsf(wv[u]) * scale40);
+            const int t = (int)(c[u] - lo);
+            atomicAdd(wv[u] > 0.0f ? &s_e[t] : &s_i[t], inc);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // One step of neuron_step's arithmetic, reordered so that the previous
 // step's synaptic arrivals (read-and-clear atomics issued by the caller) are
 // needed only after the gates: the gate update, which reads V and the old
@@ -228,14 +305,18 @@ __device__ __forceinline__ void net_update(const KModel& M, const LaneRates<S::k
 }
 
 // BATCH: more than one copy of the network (B > 1); a single network skips
-// the copy offsets entirely.
-template <class S, bool DELAY, bool BATCH>
+// the copy offsets entirely.  PULL: a single network with one-step delays
+// and a segment table delivers by pull_deliver instead of the scatter.
+template <class S, bool DELAY, bool BATCH, bool PULL = false>
 __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
+  static_assert(!(PULL && (DELAY || BATCH)), "pull delivery: one network, one-step delays");
   constexpr int NG = S::kNG;
   __shared__ int s_pre[kNetBlock];
   __shared__ int s_base[kNetBlock];
   __shared__ int64_t s_r0[kNetBlock];
+  __shared__ unsigned long long s_ae[PULL ? kNetBlock : 1], s_ai[PULL ? kNetBlock : 1];
   __shared__ int s_cnt;
+  __shared__ unsigned s_gbase;
   __shared__ int s_ok;
   const int64_t n = A.n;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -269,6 +350,11 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   int done = 0;  // steps whose barrier completed
   // ring slot of the current time (DELAY), advanced once per step
   int now = DELAY ? (int)(A.t0 % A.R) : 0;
+  const int64_t lo = (int64_t)blockIdx.x * kNetBlock;  // the block's targets (PULL)
+  if constexpr (PULL) {
+    s_ae[threadIdx.x] = 0ull;
+    s_ai[threadIdx.x] = 0ull;
+  }
 
   for (int k = 0; k < A.nsteps; ++k) {
     const int64_t t = A.t0 + k;
@@ -277,7 +363,17 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
     // were folded into the state at the end of the previous launch, or the
     // ring was cleared for a run that starts at t0 = 0)
     unsigned long long ae = 0ull, ai = 0ull;
-    if (k > 0 && act) {
+    if constexpr (PULL) {
+      if (k > 0) {
+        pull_deliver(A.plist + (int64_t)((k - 1) & 1) * n, A.pcount + (k - 1) % 3, n, A.seg,
+                     A.seg_R, (int)blockIdx.x, A.row_ptr, A.col, A.w, scale40, lo, s_ae, s_ai,
+                     s_r0, s_pre);
+        ae = s_ae[threadIdx.x];
+        ai = s_ai[threadIdx.x];
+        s_ae[threadIdx.x] = 0ull;
+        s_ai[threadIdx.x] = 0ull;
+      }
+    } else if (k > 0 && act) {
       unsigned long long* pe = DELAY ? A.acc + (int64_t)now * 2 * n
                                      : A.acc + (int64_t)((k - 1) & 1) * 2 * n;
       ae = atomicExch(&pe[i], 0ull);
@@ -301,22 +397,41 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
       row[w0] = (uint32_t)b;
       if (w0 + 1 < A.words) row[w0 + 1] = (uint32_t)(b >> 32);
     }
+    int myslot = -1;  // this lane's rank among the block's spiking neurons
     if (b) {
       int base = 0;
       if (lane == 0) base = atomicAdd(&s_cnt, __popcll(b));
       base = __shfl(base, 0);
       if (spk) {
-        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-        // flatten the (row, synapse) pairs of all spiking rows of the block
-        s_r0[base + rank] = my_r0;
-        s_pre[base + rank] = my_len;
-        if constexpr (BATCH) s_base[base + rank] = my_base;
+        myslot = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+        if constexpr (!PULL) {
+          // flatten the (row, synapse) pairs of all spiking rows of the block
+          s_r0[myslot] = my_r0;
+          s_pre[myslot] = my_len;
+          if constexpr (BATCH) s_base[myslot] = my_base;
+        }
+      }
+    }
+    if constexpr (PULL) {
+      // the count of step k - 2 has been read by every block (before the
+      // last barrier) and is next added to at step k + 1: clear it now
+      if (blockIdx.x == 0 && threadIdx.x == 0)
+        __hip_atomic_store(A.pcount + (k + 1) % 3, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      const int cnt = s_cnt;
+      if (cnt > 0) {
+        // the block's spiking rows go to the step's list at one offset
+        if (threadIdx.x == 0)
+          s_gbase = __hip_atomic_fetch_add(A.pcount + k % 3, (unsigned)cnt, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        if (myslot >= 0) A.plist[(int64_t)(k & 1) * n + s_gbase + myslot] = (int32_t)jj;
       }
     }
     __syncthreads();
     const int cnt = s_cnt;
-    if (cnt > 0) {
+    if (!PULL && cnt > 0) {
       block_inclusive_scan(s_pre, cnt);
       const int total = s_pre[cnt - 1];
       if constexpr (DELAY) {
@@ -334,7 +449,15 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
     if constexpr (DELAY) now = now + 1 == A.R ? 0 : now + 1;
   }
   // the arrivals due at the step after the last one
-  if (done > 0 && act) {
+  if constexpr (PULL) {
+    if (done > 0) {  // uniform over the grid: every block passed the same barriers
+      pull_deliver(A.plist + (int64_t)((done - 1) & 1) * n, A.pcount + (done - 1) % 3, n, A.seg,
+                   A.seg_R, (int)blockIdx.x, A.row_ptr, A.col, A.w, scale40, lo, s_ae, s_ai,
+                   s_r0, s_pre);
+      ge += (float)s_ae[threadIdx.x] * kUnfix;
+      gi += (float)s_ai[threadIdx.x] * kUnfix;
+    }
+  } else if (done > 0 && act) {
     unsigned long long* pe = DELAY ? A.acc + (int64_t)now * 2 * n
                                    : A.acc + (int64_t)((done - 1) & 1) * 2 * n;
     ge += (float)atomicExch(&pe[i], 0ull) * kUnfix;
@@ -358,10 +481,12 @@ __global__ void k_zero64(unsigned long long* p, int64_t count) {
   if (i < count) p[i] = 0ull;
 }
 
-__global__ void k_net_reset(unsigned* bar) {
+// barrier counter and the pull delivery's three list counts
+__global__ void k_net_reset(unsigned* bar, unsigned* pcount) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     bar[0] = 0u;
     bar[1] = 0u;
+    pcount[0] = pcount[1] = pcount[2] = 0u;
   }
 }
 
@@ -414,7 +539,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ lis
 // fall from one per event (contention on a few thousand cache lines) to one
 // per target and chunk.  The sums are integers, so the result equals the
 // per-event delivery's bit for bit.
-constexpr int kSegRange = 1024;   // targets per range (2 x 8 KB of LDS)
+constexpr int kSegRange = kNetBlock;  // targets per range: a network block's neurons
 constexpr int kSegChunk = 2048;   // spiking rows per block
 constexpr int kBinBlock = 512;    // threads per block: 32 groups of 16 lanes
 constexpr int kBinGroup = 16;     // lanes that share one row's segment
@@ -530,52 +655,61 @@ __global__ __launch_bounds__(256) void k_apply(float* __restrict__ ge, float* __
   acc_i[i] = 0ull;
 }
 
-// scratch layout
+// scratch layout: arrival accumulators [2][2][n] (u64), the one-shot
+// delivery's list [n], the pull delivery's lists [2][n] (i32), counters
+// (one-shot count at 0, barrier at 4, pull counts at 8..10)
 size_t acc_bytes(int64_t n) { return (size_t)4 * n * sizeof(unsigned long long); }
 size_t list_off(int64_t n) { return acc_bytes(n); }
-size_t ctr_off(int64_t n) { return list_off(n) + (((size_t)n * 4 + 255) & ~(size_t)255); }
+size_t plist_off(int64_t n) { return list_off(n) + (((size_t)n * 4 + 255) & ~(size_t)255); }
+size_t ctr_off(int64_t n) { return plist_off(n) + (((size_t)n * 8 + 255) & ~(size_t)255); }
 size_t scratch_size(int64_t n) { return ctr_off(n) + 256; }
 
-template <class S, bool DELAY, bool BATCH>
+template <class S, bool DELAY, bool BATCH, bool PULL>
 hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_net<S, DELAY, BATCH>, kNetBlock, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_net<S, DELAY, BATCH, PULL>,
+                                                   kNetBlock, 0);
   if (e != hipSuccess) return e;
   const int64_t nb = (a.n + kNetBlock - 1) / kNetBlock;
   if (nb > (int64_t)ncu * per_cu) return hipErrorCooperativeLaunchTooLarge;
-  hipLaunchKernelGGL(k_net_reset, dim3(1), dim3(64), 0, s, a.bar);
+  hipLaunchKernelGGL(k_net_reset, dim3(1), dim3(64), 0, s, a.bar, a.pcount);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* args[] = {(void*)&m->km, (void*)&a};
-  return hipLaunchCooperativeKernel((const void*)k_net<S, DELAY, BATCH>, dim3((unsigned)nb),
+  return hipLaunchCooperativeKernel((const void*)k_net<S, DELAY, BATCH, PULL>, dim3((unsigned)nb),
                                     dim3(kNetBlock), args, 0, s);
 }
 
 }  // namespace
 
-template <bool DELAY, bool BATCH>
+template <bool DELAY, bool BATCH, bool PULL = false>
 static hipError_t launch_net_spec(hh_model* m, NetArgs& a, hipStream_t s) {
   if (m->use_fixed && ClassicSpec::matches(m->km))
-    return launch_net<ClassicSpec, DELAY, BATCH>(m, a, s);
+    return launch_net<ClassicSpec, DELAY, BATCH, PULL>(m, a, s);
   if (m->use_fixed && CorticalSpec::matches(m->km))
-    return launch_net<CorticalSpec, DELAY, BATCH>(m, a, s);
+    return launch_net<CorticalSpec, DELAY, BATCH, PULL>(m, a, s);
   switch (m->km.n_gates) {
-    case 1: return launch_net<GenericSpec<1>, DELAY, BATCH>(m, a, s);
-    case 2: return launch_net<GenericSpec<2>, DELAY, BATCH>(m, a, s);
-    case 3: return launch_net<GenericSpec<3>, DELAY, BATCH>(m, a, s);
-    case 4: return launch_net<GenericSpec<4>, DELAY, BATCH>(m, a, s);
-    case 5: return launch_net<GenericSpec<5>, DELAY, BATCH>(m, a, s);
-    case 6: return launch_net<GenericSpec<6>, DELAY, BATCH>(m, a, s);
+    case 1: return launch_net<GenericSpec<1>, DELAY, BATCH, PULL>(m, a, s);
+    case 2: return launch_net<GenericSpec<2>, DELAY, BATCH, PULL>(m, a, s);
+    case 3: return launch_net<GenericSpec<3>, DELAY, BATCH, PULL>(m, a, s);
+    case 4: return launch_net<GenericSpec<4>, DELAY, BATCH, PULL>(m, a, s);
+    case 5: return launch_net<GenericSpec<5>, DELAY, BATCH, PULL>(m, a, s);
+    case 6: return launch_net<GenericSpec<6>, DELAY, BATCH, PULL>(m, a, s);
     default: return hipErrorNotSupported;
   }
 }
 
+// Delivery by pull for one network with one-step delays whose rows have a
+// segment table; by push (device atomics into the accumulators) otherwise.
 template <bool DELAY>
 static hipError_t launch_net_b(hh_model* m, NetArgs& a, hipStream_t s) {
+  if constexpr (!DELAY) {
+    if (m->B == 1 && m->d_seg && m->net_pull) return launch_net_spec<false, false, true>(m, a, s);
+  }
   return m->B > 1 ? launch_net_spec<DELAY, true>(m, a, s) : launch_net_spec<DELAY, false>(m, a, s);
 }
 
@@ -616,6 +750,10 @@ int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_
   char* sc = (char*)m->d_scratch;
   a.acc = (unsigned long long*)sc;
   a.bar = (unsigned*)(sc + ctr_off(m->n)) + 4;
+  a.plist = (int32_t*)(sc + plist_off(m->n));
+  a.pcount = (unsigned*)(sc + ctr_off(m->n)) + 8;
+  a.seg = m->d_seg;
+  a.seg_R = m->seg_R;
   a.flags = m->d_flags;
   a.spin_limit = 1u << 24;
   hipError_t e;
@@ -703,6 +841,12 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
       m->seg_R = R;
     }
   }
+  return HH_OK;
+}
+
+int32_t hh_set_delivery(hh_model* m, int32_t mode) {
+  if (!m || (mode != HH_DELIVERY_AUTO && mode != HH_DELIVERY_PUSH)) return HH_E_INVALID;
+  m->net_pull = mode == HH_DELIVERY_AUTO ? 1 : 0;
   return HH_OK;
 }
 

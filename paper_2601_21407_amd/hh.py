@@ -88,6 +88,7 @@ def _load():
         "hh_attach_csr": ([vp, vp, vp, vp, i64, f32], i32),
         "hh_set_external": ([vp, vp, u32, f32, u64], i32),
         "hh_set_delays": ([vp, vp, i32], i32),
+        "hh_set_delivery": ([vp, i32], i32),
         "hh_syn_propagate": ([vp, vp, vp, vp, vp], i32),
         "hh_backward": ([vp, vp, i32, P(Input), i32, vp, vp, f32, vp, vp, vp, vp, sz, vp], i32),
         "hh_backward_part": ([vp, vp, i32, P(Input), i32, i32, i32, vp, vp, f32, vp, vp, vp, vp, sz,
@@ -133,7 +134,7 @@ def exported_symbols():
     return [n for n in ("hh_init", "hh_destroy", "hh_status_string", "hh_n_state", "hh_set_fusion",
                         "hh_set_specialize", "hh_set_rate_table", "hh_set_morphology",
                         "hh_init_state", "hh_step_n", "hh_attach_csr", "hh_set_external",
-                        "hh_set_delays",
+                        "hh_set_delays", "hh_set_delivery",
                         "hh_syn_propagate", "hh_backward", "hh_backward_part",
                         "hh_backward_workspace", "hh_check",
                         "hh_proj_forward", "hh_proj_forward_bits", "hh_proj_wgrad",
@@ -351,6 +352,12 @@ class Model:
         if delay is not None:
             self._keep.append(delay)
         _ok(lib.hh_set_delays(self.h, _ptr(delay), int(max_delay)), "hh_set_delays")
+
+    def set_delivery(self, mode: str):
+        """Network time-loop delivery: "auto" (by target range where the
+        library can) or "push" (device atomics)."""
+        code = {"auto": 0, "push": 1}[mode]
+        _ok(lib.hh_set_delivery(self.h, code), "hh_set_delivery")
 
     def syn_propagate(self, spike_bits, state, n_spikes=None):
         _ok(lib.hh_syn_propagate(self.h, _ptr(spike_bits), _ptr(state), _ptr(n_spikes), _stream()),
