@@ -692,7 +692,7 @@ def bench_layer(reps=5, ckpt_every=50):
     dI = torch.empty((T, n), device=dev)
     dC = torch.empty(H, device=dev)
     dWin = torch.empty_like(win32)
-    ws_b = torch.empty(M.backward_workspace(ckpt_every), dtype=torch.uint8, device=dev)
+    ws_b = torch.empty(M.backward_workspace(ckpt_every, T), dtype=torch.uint8, device=dev)
     ws_w = torch.empty(int(hh.lib.hh_proj_wgrad_workspace(T * B, H, n_in)), dtype=torch.uint8,
                        device=dev)
     opt = {k: (torch.zeros_like(v), torch.zeros_like(v)) for k, v in

@@ -331,7 +331,14 @@ int32_t hh_backward_part(hh_model* m, const float* ckpt, int32_t ckpt_every, con
                          int32_t T, int32_t t_lo, int32_t t_hi, const float* dL_dlevel,
                          const float* dL_dV, float beta, float* dI, float* dCm, float* dx0,
                          void* workspace, size_t workspace_bytes, void* stream);
-size_t hh_backward_workspace(const hh_model* m, int32_t ckpt_every);
+/* Bytes of the workspace of hh_backward / hh_backward_part for T steps with
+ * checkpoints every ckpt_every steps: the adjoint carried between partial
+ * calls, the dC_m partial sums, and the state at every 5th step of every
+ * segment (recomputed from the segment's checkpoint by the call, for all of
+ * its segments at once, before the reverse sweep): ceil(T / ckpt_every) x
+ * ceil(ckpt_every / 5) x n_state x n floats when ckpt_every > 5.  0 for
+ * invalid arguments. */
+size_t hh_backward_workspace(const hh_model* m, int32_t ckpt_every, int32_t T);
 
 /* Synchronize `stream` and report the first neuron whose state is not finite
  * (HH_E_NONFINITE, *first_bad = its index) or a persistent-kernel timeout

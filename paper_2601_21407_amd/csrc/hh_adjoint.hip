@@ -5,7 +5,11 @@
 // One lane owns one neuron and walks its checkpoint segments in reverse.  A
 // segment of S steps is replayed from its checkpoint; when S exceeds the
 // register window R, a first replay stores the state at every R-th step in
-// a small workspace.  Each R-step window is then replayed once more, and
+// a workspace.  The first replays of all segments of a call are independent
+// of the adjoint and of each other, so they run first, as one kernel over
+// (segment, neuron) -- many more wavefronts than the neurons alone give,
+// which hides the latency of the step's dependent chain.  Each R-step
+// window is then replayed once more, and
 // that replay evaluates every step's transposed Jacobian from the same rate
 // evaluations that advance the state, keeping only the Jacobian entries in
 // registers.  The reverse sweep over the window then only carries the
@@ -36,7 +40,7 @@ struct BwdArgs {
   float* dI;          // [T][n]
   float* dC_part;     // [n]
   float* dx0;         // [ns][n]
-  float* sub;         // [ceil(S/R)][ns][n]
+  float* sub;         // [nseg][ceil(S/R)][ns][n]: window starts of every segment
   float* lam;         // [1 + NG][n]: the adjoint carried between partial calls
   int32_t j_lo, j_hi; // checkpoint segments [j_lo, j_hi) of this call, in reverse
   int32_t first;      // no later segment: lambda and dC start at zero
@@ -128,6 +132,45 @@ __device__ __forceinline__ void step_with_jacobian(const KModel& M, const LaneRa
   add_to_v(vh, vl, dv);
 }
 
+// First replay of segment j = j_lo + blockIdx.y: the state at the start of
+// each R-step window of the segment into the workspace (the last window's
+// steps are not needed).  The same arithmetic as the forward step.
+template <class S>
+__global__ __launch_bounds__(256) void k_replay(KModel M, BwdArgs A) {
+  constexpr int NG = S::kNG;
+  const int64_t n = A.n;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = A.j_lo + (int)blockIdx.y;
+  const int ta = j * A.S, tb = min(ta + A.S, A.T);
+  const int nwin = (tb - ta + kWin - 1) / kWin;
+  if (nwin <= 1) return;
+  const int64_t pidx = i % A.N;
+  const int ns = 2 + NG;
+  const int wmax = (A.S + kWin - 1) / kWin;
+  LaneRates<NG> L;
+  load_rates<S>(M, A.coef, pidx, A.N, L);
+  const float dtC = M.dt / (A.cm ? A.cm[pidx] : M.C);
+  const float* ck = A.ckpt + (int64_t)j * ns * n;
+  float vh = ck[i], vl = ck[(int64_t)(1 + NG) * n + i], p[ng1<NG>];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) p[g] = ck[(int64_t)(1 + g) * n + i];
+  for (int w = 0; w < nwin; ++w) {
+    float* ws = A.sub + ((int64_t)j * wmax + w) * ns * n;
+    ws[i] = vh;
+    ws[(int64_t)(1 + NG) * n + i] = vl;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) ws[(int64_t)(1 + g) * n + i] = p[g];
+    if (w + 1 == nwin) break;
+    const int ua = ta + w * kWin;  // a full window: only the last can be short
+    float Icur[kWin];
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) Icur[k] = A.I[(int64_t)(ua + k) * n + i];
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) neuron_step<S>(M, L, dtC, vh, vl, p, Icur[k], 0.0f, 0.0f);
+  }
+}
+
 template <class S>
 __global__ __launch_bounds__(256) void k_bptt(KModel M, BwdArgs A) {
   constexpr int NG = S::kNG;
@@ -160,32 +203,11 @@ __global__ __launch_bounds__(256) void k_bptt(KModel M, BwdArgs A) {
     const int ta = j * A.S, tb = min(ta + A.S, A.T);
     const float* ck = A.ckpt + (int64_t)j * ns * n;
     const int nwin = (tb - ta + kWin - 1) / kWin;
-    if (nwin > 1) {
-      // first replay: window start states into the workspace.  The inputs
-      // of a window are loaded together before its steps (one memory
-      // latency per window, not per step).
-      float vh = ck[i], vl = ck[(int64_t)(1 + NG) * n + i], p[ng1<NG>];
-#pragma unroll
-      for (int g = 0; g < NG; ++g) p[g] = ck[(int64_t)(1 + g) * n + i];
-      for (int w = 0; w < nwin; ++w) {
-        const int ua = ta + w * kWin;
-        float Icur[kWin];
-#pragma unroll
-        for (int k = 0; k < kWin; ++k)
-          Icur[k] = ua + k < tb ? A.I[(int64_t)(ua + k) * n + i] : 0.0f;
-        float* ws = A.sub + (int64_t)w * ns * n;
-        ws[i] = vh;
-        ws[(int64_t)(1 + NG) * n + i] = vl;
-#pragma unroll
-        for (int g = 0; g < NG; ++g) ws[(int64_t)(1 + g) * n + i] = p[g];
-#pragma unroll
-        for (int k = 0; k < kWin; ++k)
-          if (ua + k < tb) neuron_step<S>(M, L, dtC, vh, vl, p, Icur[k], 0.0f, 0.0f);
-      }
-    }
+    // window starts: from k_replay, or the checkpoint itself for one window
+    const float* sub_j = A.sub + (int64_t)j * ((A.S + kWin - 1) / kWin) * ns * n;
     for (int q = nwin - 1; q >= 0; --q) {
       const int ua = ta + q * kWin, ub = min(ua + kWin, tb);
-      const float* src = (nwin > 1) ? A.sub + (int64_t)q * ns * n : ck;
+      const float* src = (nwin > 1) ? sub_j + (int64_t)q * ns * n : ck;
       float vh = src[i], vl = src[(int64_t)(1 + NG) * n + i], p[ng1<NG>];
 #pragma unroll
       for (int g = 0; g < NG; ++g) p[g] = src[(int64_t)(1 + g) * n + i];
@@ -269,25 +291,33 @@ __global__ __launch_bounds__(SBH * SBG) void k_sum_batch(const float* __restrict
 template <class S>
 hipError_t launch_bptt(const hh_model* m, const BwdArgs& a, hipStream_t s) {
   const int64_t nb = (a.n + 255) / 256;
+  if ((a.S + kWin - 1) / kWin > 1) {
+    hipLaunchKernelGGL(k_replay<S>, dim3((unsigned)nb, (unsigned)(a.j_hi - a.j_lo)), dim3(256), 0,
+                       s, m->km, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_bptt<S>, dim3((unsigned)nb), dim3(256), 0, s, m->km, a);
   return hipGetLastError();
 }
 
-size_t sub_bytes(const hh_model* m, int32_t S) {
+// window starts of every segment: nseg x ceil(S / R) x (2 + NG) x n floats
+size_t sub_bytes(const hh_model* m, int32_t S, int32_t T) {
   const int nwin = (S + kWin - 1) / kWin;
   if (nwin <= 1) return 0;
-  return (size_t)nwin * (size_t)(2 + m->km.n_gates) * (size_t)m->n * sizeof(float);
+  const size_t nseg = (size_t)((T + S - 1) / S);
+  return nseg * (size_t)nwin * (size_t)(2 + m->km.n_gates) * (size_t)m->n * sizeof(float);
 }
 
 }  // namespace
 
 extern "C" {
 
-size_t hh_backward_workspace(const hh_model* m, int32_t ckpt_every) {
-  if (!m || ckpt_every < 1) return 0;
+size_t hh_backward_workspace(const hh_model* m, int32_t ckpt_every, int32_t T) {
+  if (!m || ckpt_every < 1 || T < 1) return 0;
   const size_t part = (((size_t)m->n * sizeof(float)) + 255) & ~(size_t)255;
   const size_t lam = ((((size_t)(1 + m->km.n_gates) * m->n * sizeof(float)) + 255) & ~(size_t)255);
-  return part + lam + sub_bytes(m, ckpt_every);
+  return part + lam + sub_bytes(m, ckpt_every, T);
 }
 
 int32_t hh_backward_part(hh_model* m, const float* ckpt, int32_t ckpt_every, const hh_input* in,
@@ -304,7 +334,7 @@ int32_t hh_backward_part(hh_model* m, const float* ckpt, int32_t ckpt_every, con
       (t_hi != T && t_hi % ckpt_every != 0))
     return HH_E_SHAPE;
   if (!(beta > 0.0f)) return HH_E_INVALID;
-  const size_t need = hh_backward_workspace(m, ckpt_every);
+  const size_t need = hh_backward_workspace(m, ckpt_every, T);
   if (!workspace || workspace_bytes < need) return HH_E_SHAPE;
   BwdArgs a;
   memset(&a, 0, sizeof(a));

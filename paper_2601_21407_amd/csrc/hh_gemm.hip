@@ -231,47 +231,55 @@ __device__ __forceinline__ uint4 bits_to_bf16x8(uint32_t b8) {
 }
 
 // AL: as for raw8 (weight rows 8-byte aligned, K % 4 == 0, K >= 8).
+// The spike operand stays packed in LDS, two 32-bit words per row and slab,
+// and each lane expands the eight bits of its MFMA operand in registers: A
+// costs 8 bytes of LDS per row and slab instead of 128, so the LDS traffic
+// is the weights' alone.  Slabs are 64 wide (16 products per wavefront
+// between barriers), so that the loads issued two slabs ahead have about
+// a thousand cycles of products to arrive from L2.
+constexpr int SKB = 64, LDKB = SKB + 8;
 template <bool AL>
 __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __restrict__ Ab, int wpr,
                                                           const uint16_t* __restrict__ Wt,
                                                           float* __restrict__ C, int M, int N,
                                                           int K) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][FBM * LDK];  // [m][k]
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][FBN * LDK];  // [n][k]
+  __shared__ uint32_t As[2][FBM][2];                                   // [m][word]: slab bits
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][FBN * LDKB];  // [n][k]
   const int tiles_m = (M + FBM - 1) / FBM, tiles_n = (N + FBN - 1) / FBN;
   int tm, tn;
   if (!tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn)) return;
   const int m0 = tm * FBM, n0 = tn * FBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // A: thread expands 16 bits (half h of the slab word) of row ar;
-  // Wt: chunk tid (row br, k = 8 (tid % 4))
+  // A: the thread pair of row ar loads the slab's words ah = 0, 1;
+  // Wt: row br, k = 8 (tid % 4) and 32 + 8 (tid % 4) of the slab
   const int ar = tid >> 1, ah = tid & 1;
   const bool av = m0 + ar < M;
   const uint32_t* arow = Ab + (int64_t)min(m0 + ar, M - 1) * wpr;
   const int br = tid >> 2, bkc = (tid & 3) * 8;
   const bool bv = n0 + br < N;
   const uint16_t* brow = Wt + (int64_t)min(n0 + br, N - 1) * K;
-  const int ns = (K + SK - 1) / SK;
+  const int ns = (K + SKB - 1) / SKB;
+  const int nw = (K + 31) / 32;  // words of a row that hold bits below K
 
   // Loads go to clamped in-range addresses and keep the raw words; rows past
-  // M or N, slabs past K and bits past K are zeroed at the stash (a load
+  // M or N, words past K and bits past K are zeroed at the stash (a load
   // whose value is selected on would be turned into a branch around it, and
   // then waited for at once).  The weights go through raw8 / fix8.
-  auto a_bits = [&](int s) -> uint32_t { return arow[min(s, ns - 1)]; };
-  auto b_load = [&](int s) -> uint4 { return raw8<AL>(brow, min(s, ns - 1) * SK + bkc, K); };
-  auto stash = [&](int buf, int s, uint32_t w, uint4 b) {
-    uint32_t a16 = 0u;
-    if (av && s < ns) {
-      const int valid = K - s * SK;  // bits past K are ignored
-      if (valid < 32) w &= (1u << valid) - 1u;
-      a16 = (w >> (16 * ah)) & 0xFFFFu;
-    }
-    b = (bv && s < ns) ? fix8<AL>(b, s * SK + bkc, K) : make_uint4(0u, 0u, 0u, 0u);
-    uint4* pa = reinterpret_cast<uint4*>(&As[buf][ar * LDK + 16 * ah]);
-    pa[0] = bits_to_bf16x8(a16 & 0xFFu);
-    pa[1] = bits_to_bf16x8(a16 >> 8);
-    *reinterpret_cast<uint4*>(&Bs[buf][br * LDK + bkc]) = b;
+  auto a_bits = [&](int s) -> uint32_t { return arow[min(2 * s + ah, nw - 1)]; };
+  auto b_load = [&](int s, int h) -> uint4 {
+    return raw8<AL>(brow, min(s, ns - 1) * SKB + 32 * h + bkc, K);
+  };
+  auto stash = [&](int buf, int s, uint32_t w, uint4 b0, uint4 b1) {
+    const int valid = K - 32 * (2 * s + ah);  // bits of this word below K
+    if (!av || s >= ns || valid <= 0) w = 0u;
+    else if (valid < 32) w &= (1u << valid) - 1u;
+    As[buf][ar][ah] = w;
+    const bool ok = bv && s < ns;
+    b0 = ok ? fix8<AL>(b0, s * SKB + bkc, K) : make_uint4(0u, 0u, 0u, 0u);
+    b1 = ok ? fix8<AL>(b1, s * SKB + 32 + bkc, K) : make_uint4(0u, 0u, 0u, 0u);
+    *reinterpret_cast<uint4*>(&Bs[buf][br * LDKB + bkc]) = b0;
+    *reinterpret_cast<uint4*>(&Bs[buf][br * LDKB + 32 + bkc]) = b1;
   };
 
   f32x16 acc[2][2];
@@ -283,16 +291,23 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
   auto compute = [&](int buf) {
-    const uint16_t* as = As[buf];
     const uint16_t* bs = Bs[buf];
+    uint32_t wa[2][2];
 #pragma unroll
-    for (int kk = 0; kk < SK; kk += 16) {
+    for (int i = 0; i < 2; ++i) {
+      const int row = wm * 64 + i * 32 + (lane & 31);
+      wa[i][0] = As[buf][row][0];
+      wa[i][1] = As[buf][row][1];
+    }
+#pragma unroll
+    for (int kk = 0; kk < SKB; kk += 16) {
       const int kl = kk + 8 * (lane >> 5);
       bf16x8 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = lds8(as + (wm * 64 + i * 32 + (lane & 31)) * LDK + kl);
+      for (int i = 0; i < 2; ++i)
+        a[i] = __builtin_bit_cast(bf16x8, bits_to_bf16x8((wa[i][kk >> 5] >> (kl & 31)) & 0xFFu));
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = lds8(bs + (wn * 64 + j * 32 + (lane & 31)) * LDK + kl);
+      for (int j = 0; j < 2; ++j) b[j] = lds8(bs + (wn * 64 + j * 32 + (lane & 31)) * LDKB + kl);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -307,12 +322,14 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
   // load has two slabs of products to arrive.  The loop is unrolled by two
   // so that the sets are fixed registers (no copies, which would wait).
   uint32_t ra[2];
-  uint4 rb[2];
+  uint4 rb[2][2];
   ra[0] = a_bits(0);
-  rb[0] = b_load(0);
+  rb[0][0] = b_load(0, 0);
+  rb[0][1] = b_load(0, 1);
   ra[1] = a_bits(1);
-  rb[1] = b_load(1);
-  stash(0, 0, ra[0], rb[0]);
+  rb[1][0] = b_load(1, 0);
+  rb[1][1] = b_load(1, 1);
+  stash(0, 0, ra[0], rb[0][0], rb[0][1]);
   __syncthreads();
   for (int s0 = 0; s0 < ns; s0 += 2) {
 #pragma unroll
@@ -320,10 +337,11 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
       const int s = s0 + u;
       if (s >= ns) break;  // uniform
       ra[u] = a_bits(s + 2);
-      rb[u] = b_load(s + 2);
+      rb[u][0] = b_load(s + 2, 0);
+      rb[u][1] = b_load(s + 2, 1);
       compute(u);
       // buffer (s+1)%2 was last read in slab s-1, before the previous barrier
-      if (s + 1 < ns) stash(u ^ 1, s + 1, ra[u ^ 1], rb[u ^ 1]);
+      if (s + 1 < ns) stash(u ^ 1, s + 1, ra[u ^ 1], rb[u ^ 1][0], rb[u ^ 1][1]);
       __syncthreads();
     }
   }

@@ -532,7 +532,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ lis
 
 // ---- binned one-shot delivery ----------------------------------------------
 // With the rows sorted by target, the delivery is split by target range: a
-// block owns kSegRange targets and a chunk of the spiking rows, adds the
+// block owns kBinSpan table ranges of targets and a chunk of the spiking rows, adds the
 // rows' events that fall in its range into LDS accumulators (one LDS atomic
 // per event), and then adds each touched accumulator to the global one with
 // a single device-scope atomic.  Every event is read once; the global atomics
@@ -540,6 +540,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ lis
 // per target and chunk.  The sums are integers, so the result equals the
 // per-event delivery's bit for bit.
 constexpr int kSegRange = kNetBlock;  // targets per range: a network block's neurons
+constexpr int kBinSpan = 2;       // table ranges per one-shot block (1,024 targets)
 constexpr int kSegChunk = 2048;   // spiking rows per block
 constexpr int kBinBlock = 512;    // threads per block: 32 groups of 16 lanes
 constexpr int kBinGroup = 16;     // lanes that share one row's segment
@@ -576,19 +577,22 @@ __global__ __launch_bounds__(kBinBlock) void k_scatter_binned(
     const int32_t* __restrict__ col, const float* __restrict__ w, const int32_t* __restrict__ seg,
     int R, float scale40, unsigned long long* __restrict__ acc_e,
     unsigned long long* __restrict__ acc_i, int64_t n) {
-  __shared__ unsigned long long se[kSegRange], si[kSegRange];
+  constexpr int kSpan = kBinSpan * kSegRange;  // targets per block
+  __shared__ unsigned long long se[kSpan], si[kSpan];
   __shared__ int64_t m_a[kSegChunk];
   __shared__ int32_t m_len[kSegChunk];
   const unsigned nb = gridDim.x, bid = blockIdx.x;
   const unsigned xcd = bid & 7u, idx = bid >> 3, per = nb >> 3, rem = nb & 7u;
   const unsigned logical = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-  const int r = (int)(logical % (unsigned)R);
-  const unsigned e0 = (logical / (unsigned)R) * (unsigned)kSegChunk;
+  const int spans = (R + kBinSpan - 1) / kBinSpan;
+  const int rs = (int)(logical % (unsigned)spans);
+  const int r = rs * kBinSpan, r_end = min(r + kBinSpan, R);  // table ranges [r, r_end)
+  const unsigned e0 = (logical / (unsigned)spans) * (unsigned)kSegChunk;
   const unsigned cnt = *count;
   if (e0 >= cnt) return;  // uniform: the whole block leaves
   const int rows = (int)min(cnt - e0, (unsigned)kSegChunk);
   const int tid = threadIdx.x;
-  for (int t = tid; t < kSegRange; t += kBinBlock) se[t] = si[t] = 0ull;
+  for (int t = tid; t < kSpan; t += kBinBlock) se[t] = si[t] = 0ull;
   // the chunk's segments for this range, four rows per thread loaded together
   {
     int src[kSegChunk / kBinBlock];
@@ -601,8 +605,8 @@ __global__ __launch_bounds__(kBinBlock) void k_scatter_binned(
     for (int u = 0; u < kSegChunk / kBinBlock; ++u) {
       const int i = tid + u * kBinBlock;
       if (i < rows) {
-        const int32_t* sj = seg + (int64_t)src[u] * (R + 1) + r;
-        const int32_t s0 = sj[0], s1 = sj[1];
+        const int32_t* sj = seg + (int64_t)src[u] * (R + 1);
+        const int32_t s0 = sj[r], s1 = sj[r_end];
         m_a[i] = row_ptr[src[u]] + s0;
         m_len[i] = s1 - s0;
       }
@@ -635,7 +639,7 @@ __global__ __launch_bounds__(kBinBlock) void k_scatter_binned(
     }
   }
   __syncthreads();
-  for (int t = tid; t < kSegRange; t += kBinBlock) {
+  for (int t = tid; t < kSpan; t += kBinBlock) {
     const int64_t g = (int64_t)lo + t;
     if (g < n) {
       if (se[t]) atomicAdd(&acc_e[g], se[t]);
@@ -921,7 +925,8 @@ int32_t hh_syn_propagate(hh_model* m, const uint32_t* spike_bits, float* state,
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (m->d_seg) {
     const unsigned chunks = (unsigned)((n + kSegChunk - 1) / kSegChunk);
-    hipLaunchKernelGGL(k_scatter_binned, dim3((unsigned)m->seg_R * chunks), dim3(kBinBlock), 0, s, list,
+    const unsigned spans = (unsigned)((m->seg_R + kBinSpan - 1) / kBinSpan);
+    hipLaunchKernelGGL(k_scatter_binned, dim3(spans * chunks), dim3(kBinBlock), 0, s, list,
                        count, m->row_ptr, m->col, m->w, m->d_seg, m->seg_R, m->w_scale * kFix,
                        acc_e, acc_i, n);
   } else {

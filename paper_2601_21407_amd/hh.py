@@ -93,7 +93,7 @@ def _load():
         "hh_backward": ([vp, vp, i32, P(Input), i32, vp, vp, f32, vp, vp, vp, vp, sz, vp], i32),
         "hh_backward_part": ([vp, vp, i32, P(Input), i32, i32, i32, vp, vp, f32, vp, vp, vp, vp, sz,
                               vp], i32),
-        "hh_backward_workspace": ([vp, i32], sz),
+        "hh_backward_workspace": ([vp, i32, i32], sz),
         "hh_check": ([vp, P(i64), vp], i32),
         "hh_proj_forward": ([vp, vp, vp, i32, i32, i32, vp], i32),
         "hh_proj_forward_bits": ([vp, i32, vp, vp, i32, i32, i32, vp], i32),
@@ -373,15 +373,15 @@ class Model:
         _need(dCm, "dCm", _F32, self.N)
         _need(dx0, "dx0", _F32, self.n_state * n)
 
-    def backward_workspace(self, ckpt_every: int) -> int:
-        return int(lib.hh_backward_workspace(self.h, int(ckpt_every)))
+    def backward_workspace(self, ckpt_every: int, T: int) -> int:
+        return int(lib.hh_backward_workspace(self.h, int(ckpt_every), int(T)))
 
     def backward(self, ckpt, ckpt_every: int, i_dense, T: int, dI, *, dL_dlevel=None, dL_dV=None,
                  beta: float = 0.2, dCm=None, dx0=None, workspace=None):
         self._check_backward(ckpt, ckpt_every, i_dense, T, dI, dL_dlevel, dL_dV, dCm, dx0)
         inp = Input()
         inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
-        ws_bytes = self.backward_workspace(ckpt_every)
+        ws_bytes = self.backward_workspace(ckpt_every, T)
         if workspace is None and ws_bytes:
             workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dI.device)
         _ok(lib.hh_backward(self.h, _ptr(ckpt), int(ckpt_every), ctypes.byref(inp), int(T),
@@ -396,7 +396,7 @@ class Model:
         self._check_backward(ckpt, ckpt_every, i_dense, T, dI, dL_dlevel, dL_dV, dCm, dx0)
         inp = Input()
         inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
-        ws_bytes = self.backward_workspace(ckpt_every)
+        ws_bytes = self.backward_workspace(ckpt_every, T)
         assert workspace.numel() * workspace.element_size() >= ws_bytes
         _ok(lib.hh_backward_part(self.h, _ptr(ckpt), int(ckpt_every), ctypes.byref(inp), int(T),
                                  int(t_lo), int(t_hi), _ptr(dL_dlevel), _ptr(dL_dV), float(beta),

@@ -337,7 +337,7 @@ def test_adjoint_in_parts_equals_whole():
     dI2 = torch.zeros((T, n), device="cuda")
     dC2 = torch.zeros(n // 3, device="cuda")
     dx02 = torch.zeros((M.n_state, n), device="cuda")
-    ws = torch.empty(M.backward_workspace(20), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(M.backward_workspace(20, T), dtype=torch.uint8, device="cuda")
     kw = dict(workspace=ws, dL_dlevel=torch.tensor(dlevel, device="cuda"),
               dL_dV=torch.tensor(dV, device="cuda"), dCm=dC2, dx0=dx02)
     for lo, hi in ((120, 130), (60, 120), (40, 60), (0, 40)):
