@@ -121,6 +121,7 @@ def _src_hash(files):
 
 
 STEP_KERNEL_SOURCES = ["paper_2601_21407_amd/csrc/hh_step.hip", "paper_2601_21407_amd/csrc/hh_device.h"]
+NET_KERNEL_SOURCES = ["paper_2601_21407_amd/csrc/hh_net.hip"]
 
 
 def _traffic(kernel_key, sources, launches_per_pass=1):
@@ -649,7 +650,9 @@ def bench_network(T=10000):
         "batch": batch,
         "scatter_full": {"events": nnz, "ms": sc_ms, "events_per_s": nnz / (sc_ms / 1e3),
                          "alg_GBs": nnz * 8 / (sc_ms / 1e3) / 1e9,
-                         "hbm_frac": nnz * 8 / (sc_ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+                         "hbm_frac": nnz * 8 / (sc_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                         "kernel": "k_scatter_binned",
+                         "traffic": _traffic("k_scatter_binned_38000_full", NET_KERNEL_SOURCES)},
     }
 
 
@@ -1012,12 +1015,29 @@ def counters_run():
     _sync()
     M.step_n(st, 32, 0, noise=(5.0, 3.0, seed), spikes=spikes)
     _sync()
+    M_n_state, words = M.n_state, M.words
+    del M, st, coef, spikes, a, b
+    # one full-load delivery on the 38,000-neuron network: every source
+    # spikes, 99.94 M synaptic events (col and w of every synapse read once)
+    nn = 38000
+    csr = W.net_csr(n=nn, inh_scale=W.NET_INH_SCALE)
+    Mn = hh.Model(W.net_model(), nn)
+    rp, col, w = (torch.tensor(x, device="cuda") for x in csr)
+    Mn.attach_csr(rp, col, w, W.NET_W_SCALE)
+    stn = Mn.new_state()
+    Mn.init_state(stn, v0_scalar=-65.0)
+    allbits = torch.full((Mn.words,), -1, dtype=torch.int32, device="cuda")
+    _sync()
+    Mn.syn_propagate(allbits, stn)
+    _sync()
     print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
                       # state rows read and written once; the coefficients a launch reads:
                       # (A, B, K) of each of the 10 rates plus the bell rate's c = 31 per
                       # neuron; one spike word per 32 neurons and step
-                      "k_step_alg_bytes": n * (2 * M.n_state * 4 + 31 * 4) + 32 * M.words * 4,
-                      "src_hash": _src_hash(STEP_KERNEL_SOURCES)}))
+                      "k_step_alg_bytes": n * (2 * M_n_state * 4 + 31 * 4) + 32 * words * 4,
+                      "scatter_alg_bytes": int(csr[1].shape[0]) * 8,
+                      "src_hash": _src_hash(STEP_KERNEL_SOURCES),
+                      "net_src_hash": _src_hash(NET_KERNEL_SOURCES)}))
 
 
 def main():
