@@ -254,8 +254,8 @@ int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const 
  * through row j into targets b N + col.  hh_step_n runs all copies in one
  * co-resident grid and returns HH_E_UNSUPPORTED when N B neurons do not fit
  * one (two blocks of 512 per compute unit: 262,144 neurons on 256 compute
- * units).  For one copy whose rows list their targets in ascending order,
- * the call also builds a table of each row's offsets at every 512th target
+ * units).  When the rows list their targets in ascending order, the call
+ * also builds a table of each row's offsets at every 512th target
  * (N (ceil(N / 512) + 1) int32, kept while it is no larger than the column
  * array), which the deliveries by target range use.  Buffers stay owned by
  * the caller.  Requires has_syn.  Errors: HH_E_INVALID, HH_E_SHAPE, HH_E_OOM,
@@ -264,10 +264,11 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
                       int64_t nnz, float w_scale);
 
 /* Delivery in the network time loop.  HH_DELIVERY_AUTO (the default): by
- * target range when the table of hh_attach_csr exists, the copies are one
- * and the delays one step -- after each step's grid barrier every block
- * reads the list of the previous step's spiking rows and adds their events
- * for its own 512 targets in on-chip memory; otherwise, and always with
+ * target range when the table of hh_attach_csr exists, the delays are one
+ * step and either B = 1 or N >= 512 -- after each step's grid barrier every
+ * block reads the lists of the previous step's spiking rows of the copies
+ * its 512 elements belong to and adds their events for those elements in
+ * on-chip memory; otherwise, and always with
  * HH_DELIVERY_PUSH, each spiking row is added into arrival accumulators by
  * device-scope atomics.  Both add the same 64-bit fixed-point increments,
  * so the results are identical.  Errors: HH_E_INVALID for another mode. */

@@ -49,6 +49,7 @@ struct NetArgs {
   float* state;
   int64_t n;
   int64_t N;                // elements per copy (rows of the shared CSR)
+  int32_t B;                // copies
   const int64_t* row_ptr;
   const int32_t* col;
   const float* w;
@@ -70,9 +71,9 @@ struct NetArgs {
   float mu, sigma, bg_lam, bg_p0;
   int32_t bg_kmax;
   uint64_t seed;
-  // pull delivery (one network, one-step delays, rows sorted by target):
-  // the spiking rows of step k in plist[k & 1][0 .. pcount[k % 3]), and the
-  // segment table of the rows by the blocks' target ranges
+  // pull delivery (one-step delays, rows sorted by target): the spiking rows
+  // of copy c at step k in plist[k & 1][c][0 .. pcount[k % 3][c]), and the
+  // segment table of the rows by 512-target ranges
   int32_t* plist;
   unsigned* pcount;
   const int32_t* seg;
@@ -176,25 +177,27 @@ __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
   }
 }
 
-// Pull delivery of one step's spikes into the block's own targets: the
-// block owning targets [lo, lo + kNetBlock) reads the step's list of spiking
-// rows, then each row's segment of targets in its range (the segment table
-// of the rows sorted by target), and adds the events into LDS accumulators,
-// one per target and sign.  No device atomics and no accumulator buffers;
-// the integer sums equal those of the push delivery bit for bit.  The list
-// and its count were written by other blocks before the last grid barrier:
-// they are read with device-scope loads.  s_a and s_len are staging arrays
-// of kNetBlock entries; the accumulators are complete when it returns.
-__device__ void pull_deliver(const int32_t* list, const unsigned* countp, int64_t n,
-                             const int32_t* __restrict__ seg, int R, int r,
-                             const int64_t* __restrict__ row_ptr,
+// Pull delivery of one step's spikes of one copy into the block's own
+// targets: the block owning elements [lo, lo + kNetBlock) reads the copy's
+// list of spiking rows, then each row's span of targets that covers the
+// block's window [x0, x1) of the copy (table ranges r0..r1 of the segment
+// table of the rows sorted by target), and adds the events inside the window
+// into LDS accumulators, one per element and sign (element = col + ldsoff).
+// No device atomics and no accumulator buffers; the integer sums equal those
+// of the push delivery bit for bit.  The list and its count were written by
+// other blocks before the last grid barrier: they are read with device-scope
+// loads.  s_a and s_len are staging arrays of kNetBlock entries; the
+// accumulators are complete when it returns.
+__device__ void pull_deliver(const int32_t* list, const unsigned* countp, int64_t N,
+                             const int32_t* __restrict__ seg, int R, int r0, int r1, int x0,
+                             int x1, int ldsoff, const int64_t* __restrict__ row_ptr,
                              const int32_t* __restrict__ col, const float* __restrict__ w,
-                             float scale40, int64_t lo, unsigned long long* s_e,
-                             unsigned long long* s_i, int64_t* s_a, int* s_len) {
+                             float scale40, unsigned long long* s_e, unsigned long long* s_i,
+                             int64_t* s_a, int* s_len) {
   const int tid = threadIdx.x;
   // the count and the first kNetBlock entries in one round trip
   unsigned cnt = __hip_atomic_load(countp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int32_t spec = tid < n ? __hip_atomic_load(&list[tid], __ATOMIC_RELAXED,
+  const int32_t spec = tid < N ? __hip_atomic_load(&list[tid], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT)
                                : 0;
   // every lane reads the same final count (no block adds to it until the
@@ -202,18 +205,18 @@ __device__ void pull_deliver(const int32_t* list, const unsigned* countp, int64_
   // loop below, which holds barriers, is uniform over the block by
   // construction
   __shared__ unsigned s_pc;
-  if (tid == 0) s_pc = (unsigned)min((int64_t)cnt, n);
+  if (tid == 0) s_pc = (unsigned)min((int64_t)cnt, N);
   __syncthreads();
   cnt = s_pc;
-  constexpr int G = 16;  // lanes per row segment
+  constexpr int G = 16;  // lanes per row span
   for (unsigned c0 = 0; c0 < cnt; c0 += kNetBlock) {
     const unsigned e = c0 + tid;
     if (e < cnt) {
       const int32_t src = c0 == 0 ? spec
                                   : __hip_atomic_load(&list[e], __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
-      const int32_t* sj = seg + (int64_t)src * (R + 1) + r;
-      const int32_t s0 = sj[0], s1 = sj[1];
+      const int32_t* sj = seg + (int64_t)src * (R + 1);
+      const int32_t s0 = sj[r0], s1 = sj[r1 + 1];
       s_a[tid] = row_ptr[src] + s0;
       s_len[tid] = s1 - s0;
     }
@@ -233,10 +236,10 @@ __device__ void pull_deliver(const int32_t* list, const unsigned* countp, int64_
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          if (c[u] >= 0) {
+          if (c[u] >= x0 && c[u] < x1) {
             const unsigned long long inc =
                 (unsigned long long)__float2ull_rn(fabsf(wv[u]) * scale40);
-            const int t = (int)(c[u] - lo);
+            const int t = c[u] + ldsoff;
             atomicAdd(wv[u] > 0.0f ? &s_e[t] : &s_i[t], inc);
           }
         }
@@ -244,6 +247,22 @@ __device__ void pull_deliver(const int32_t* list, const unsigned* countp, int64_
     }
     __syncthreads();
   }
+}
+
+// The block's targets in copy c: window [x0, x1) of the copy's N elements,
+// its table ranges r0..r1, and the offset from copy-local target to LDS slot.
+struct PullWin {
+  int x0, x1, r0, r1, ldsoff;
+};
+__device__ __forceinline__ PullWin pull_window(int64_t lo, int64_t hi, int64_t c, int64_t N) {
+  PullWin p;
+  const int64_t base = c * N;
+  p.x0 = (int)max(lo - base, (int64_t)0);
+  p.x1 = (int)min(hi - base, N);
+  p.r0 = p.x0 / kNetBlock;
+  p.r1 = (p.x1 - 1) / kNetBlock;
+  p.ldsoff = (int)(base - lo);
+  return p;
 }
 
 // One step of neuron_step's arithmetic, reordered so that the previous
@@ -305,18 +324,20 @@ __device__ __forceinline__ void net_update(const KModel& M, const LaneRates<S::k
 }
 
 // BATCH: more than one copy of the network (B > 1); a single network skips
-// the copy offsets entirely.  PULL: a single network with one-step delays
-// and a segment table delivers by pull_deliver instead of the scatter.
+// the copy offsets entirely.  PULL: one-step delays and a segment table:
+// delivery by pull_deliver instead of the scatter (with BATCH, N >= 512, so
+// that a block's elements span at most two copies).
 template <class S, bool DELAY, bool BATCH, bool PULL = false>
 __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
-  static_assert(!(PULL && (DELAY || BATCH)), "pull delivery: one network, one-step delays");
+  static_assert(!(PULL && DELAY), "pull delivery: one-step delays");
   constexpr int NG = S::kNG;
   __shared__ int s_pre[kNetBlock];
   __shared__ int s_base[kNetBlock];
   __shared__ int64_t s_r0[kNetBlock];
   __shared__ unsigned long long s_ae[PULL ? kNetBlock : 1], s_ai[PULL ? kNetBlock : 1];
   __shared__ int s_cnt;
-  __shared__ unsigned s_gbase;
+  __shared__ unsigned s_gbase[2];
+  __shared__ int s_ccnt[2];
   __shared__ int s_ok;
   const int64_t n = A.n;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -350,11 +371,23 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   int done = 0;  // steps whose barrier completed
   // ring slot of the current time (DELAY), advanced once per step
   int now = DELAY ? (int)(A.t0 % A.R) : 0;
-  const int64_t lo = (int64_t)blockIdx.x * kNetBlock;  // the block's targets (PULL)
+  // the block's elements [lo, hi) and the copies cf..cl they belong to (PULL)
+  const int64_t lo = (int64_t)blockIdx.x * kNetBlock, hi = min(lo + kNetBlock, n);
+  const int64_t cf = lo / A.N, cl = (hi - 1) / A.N;  // cl <= cf + 1 (N >= 512)
+  const int my_c = (int)(ii / A.N - cf);              // 0 or 1
   if constexpr (PULL) {
     s_ae[threadIdx.x] = 0ull;
     s_ai[threadIdx.x] = 0ull;
   }
+  auto pull_all = [&](int step) {
+    for (int64_t c = cf; c <= cl; ++c) {
+      const PullWin pw = pull_window(lo, hi, c, A.N);
+      pull_deliver(A.plist + ((int64_t)(step & 1) * n + c * A.N),
+                   A.pcount + (int64_t)(step % 3) * A.B + c, A.N, A.seg, A.seg_R, pw.r0, pw.r1,
+                   pw.x0, pw.x1, pw.ldsoff, A.row_ptr, A.col, A.w, scale40, s_ae, s_ai, s_r0,
+                   s_pre);
+    }
+  };
 
   for (int k = 0; k < A.nsteps; ++k) {
     const int64_t t = A.t0 + k;
@@ -365,9 +398,7 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
     unsigned long long ae = 0ull, ai = 0ull;
     if constexpr (PULL) {
       if (k > 0) {
-        pull_deliver(A.plist + (int64_t)((k - 1) & 1) * n, A.pcount + (k - 1) % 3, n, A.seg,
-                     A.seg_R, (int)blockIdx.x, A.row_ptr, A.col, A.w, scale40, lo, s_ae, s_ai,
-                     s_r0, s_pre);
+        pull_all(k - 1);
         ae = s_ae[threadIdx.x];
         ai = s_ai[threadIdx.x];
         s_ae[threadIdx.x] = 0ull;
@@ -397,37 +428,52 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
       row[w0] = (uint32_t)b;
       if (w0 + 1 < A.words) row[w0 + 1] = (uint32_t)(b >> 32);
     }
-    int myslot = -1;  // this lane's rank among the block's spiking neurons
-    if (b) {
-      int base = 0;
-      if (lane == 0) base = atomicAdd(&s_cnt, __popcll(b));
-      base = __shfl(base, 0);
-      if (spk) {
-        myslot = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-        if constexpr (!PULL) {
+    int myslot = -1;  // this lane's rank among the block's spiking neurons (of its copy)
+    if constexpr (!PULL) {
+      if (b) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_cnt, __popcll(b));
+        base = __shfl(base, 0);
+        if (spk) {
+          myslot = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
           // flatten the (row, synapse) pairs of all spiking rows of the block
           s_r0[myslot] = my_r0;
           s_pre[myslot] = my_len;
           if constexpr (BATCH) s_base[myslot] = my_base;
         }
       }
-    }
-    if constexpr (PULL) {
-      // the count of step k - 2 has been read by every block (before the
-      // last barrier) and is next added to at step k + 1: clear it now
-      if (blockIdx.x == 0 && threadIdx.x == 0)
-        __hip_atomic_store(A.pcount + (k + 1) % 3, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      // ranks per copy: the block's elements belong to copy cf + 0 or cf + 1
+      if (threadIdx.x < 2) s_ccnt[threadIdx.x] = 0;
+      // the counts of step k - 2 have been read by every block (before the
+      // last barrier) and are next added to at step k + 1: clear them now
+      if (blockIdx.x == 0)
+        for (int c = threadIdx.x; c < A.B; c += kNetBlock)
+          __hip_atomic_store(A.pcount + (int64_t)((k + 1) % 3) * A.B + c, 0u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
       __syncthreads();
-      const int cnt = s_cnt;
-      if (cnt > 0) {
-        // the block's spiking rows go to the step's list at one offset
-        if (threadIdx.x == 0)
-          s_gbase = __hip_atomic_fetch_add(A.pcount + k % 3, (unsigned)cnt, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        if (myslot >= 0) A.plist[(int64_t)(k & 1) * n + s_gbase + myslot] = (int32_t)jj;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint64_t bh = __ballot(spk && my_c == h);
+        if (bh) {
+          int base = 0;
+          if (lane == 0) base = atomicAdd(&s_ccnt[h], __popcll(bh));
+          base = __shfl(base, 0);
+          if (spk && my_c == h)
+            myslot = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bh >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bh, 0u));
+        }
       }
+      __syncthreads();
+      // each copy's spiking rows of the block go to its list at one offset
+      if (threadIdx.x < 2 && s_ccnt[threadIdx.x] > 0)
+        s_gbase[threadIdx.x] = __hip_atomic_fetch_add(
+            A.pcount + (int64_t)(k % 3) * A.B + cf + threadIdx.x, (unsigned)s_ccnt[threadIdx.x],
+            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      if (myslot >= 0)
+        A.plist[(int64_t)(k & 1) * n + (cf + my_c) * A.N + s_gbase[my_c] + myslot] = (int32_t)jj;
     }
     __syncthreads();
     const int cnt = s_cnt;
@@ -450,10 +496,8 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   }
   // the arrivals due at the step after the last one
   if constexpr (PULL) {
-    if (done > 0) {  // uniform over the grid: every block passed the same barriers
-      pull_deliver(A.plist + (int64_t)((done - 1) & 1) * n, A.pcount + (done - 1) % 3, n, A.seg,
-                   A.seg_R, (int)blockIdx.x, A.row_ptr, A.col, A.w, scale40, lo, s_ae, s_ai,
-                   s_r0, s_pre);
+    if (done > 0) {  // uniform over the block: its threads passed the same barriers
+      pull_all(done - 1);
       ge += (float)s_ae[threadIdx.x] * kUnfix;
       gi += (float)s_ai[threadIdx.x] * kUnfix;
     }
@@ -481,13 +525,14 @@ __global__ void k_zero64(unsigned long long* p, int64_t count) {
   if (i < count) p[i] = 0ull;
 }
 
-// barrier counter and the pull delivery's three list counts
-__global__ void k_net_reset(unsigned* bar, unsigned* pcount) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+// barrier counter and the pull delivery's list counts (3 steps x B copies)
+__global__ void k_net_reset(unsigned* bar, unsigned* pcount, int count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     bar[0] = 0u;
     bar[1] = 0u;
-    pcount[0] = pcount[1] = pcount[2] = 0u;
   }
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < count; c += gridDim.x * blockDim.x)
+    pcount[c] = 0u;
 }
 
 // ---- one-shot delivery -----------------------------------------------------
@@ -660,13 +705,15 @@ __global__ __launch_bounds__(256) void k_apply(float* __restrict__ ge, float* __
 }
 
 // scratch layout: arrival accumulators [2][2][n] (u64), the one-shot
-// delivery's list [n], the pull delivery's lists [2][n] (i32), counters
-// (one-shot count at 0, barrier at 4, pull counts at 8..10)
+// delivery's list [n], the pull delivery's lists [2][B][N] (i32) and counts
+// [3][B] (u32), counters (one-shot count at 0, barrier at 4)
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t acc_bytes(int64_t n) { return (size_t)4 * n * sizeof(unsigned long long); }
 size_t list_off(int64_t n) { return acc_bytes(n); }
-size_t plist_off(int64_t n) { return list_off(n) + (((size_t)n * 4 + 255) & ~(size_t)255); }
-size_t ctr_off(int64_t n) { return plist_off(n) + (((size_t)n * 8 + 255) & ~(size_t)255); }
-size_t scratch_size(int64_t n) { return ctr_off(n) + 256; }
+size_t plist_off(int64_t n) { return list_off(n) + al256((size_t)n * 4); }
+size_t pcount_off(int64_t n) { return plist_off(n) + al256((size_t)n * 8); }
+size_t ctr_off(int64_t n, int32_t B) { return pcount_off(n) + al256((size_t)3 * B * 4); }
+size_t scratch_size(int64_t n, int32_t B) { return ctr_off(n, B) + 256; }
 
 template <class S, bool DELAY, bool BATCH, bool PULL>
 hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
@@ -680,7 +727,7 @@ hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int64_t nb = (a.n + kNetBlock - 1) / kNetBlock;
   if (nb > (int64_t)ncu * per_cu) return hipErrorCooperativeLaunchTooLarge;
-  hipLaunchKernelGGL(k_net_reset, dim3(1), dim3(64), 0, s, a.bar, a.pcount);
+  hipLaunchKernelGGL(k_net_reset, dim3(1), dim3(256), 0, s, a.bar, a.pcount, 3 * a.B);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* args[] = {(void*)&m->km, (void*)&a};
@@ -707,12 +754,16 @@ static hipError_t launch_net_spec(hh_model* m, NetArgs& a, hipStream_t s) {
   }
 }
 
-// Delivery by pull for one network with one-step delays whose rows have a
-// segment table; by push (device atomics into the accumulators) otherwise.
+// Delivery by pull with one-step delays when the rows have a segment table
+// (and, for a batch, copies of at least one block's 512 elements); by push
+// (device atomics into the accumulators) otherwise.
 template <bool DELAY>
 static hipError_t launch_net_b(hh_model* m, NetArgs& a, hipStream_t s) {
   if constexpr (!DELAY) {
-    if (m->B == 1 && m->d_seg && m->net_pull) return launch_net_spec<false, false, true>(m, a, s);
+    if (m->d_seg && m->net_pull) {
+      if (m->B == 1) return launch_net_spec<false, false, true>(m, a, s);
+      if (m->N >= kNetBlock) return launch_net_spec<false, true, true>(m, a, s);
+    }
   }
   return m->B > 1 ? launch_net_spec<DELAY, true>(m, a, s) : launch_net_spec<DELAY, false>(m, a, s);
 }
@@ -753,9 +804,10 @@ int32_t hh_net_step_n_internal(hh_model* m, float* state, int64_t t0, int32_t n_
   a.words = (m->n + 31) / 32;
   char* sc = (char*)m->d_scratch;
   a.acc = (unsigned long long*)sc;
-  a.bar = (unsigned*)(sc + ctr_off(m->n)) + 4;
+  a.B = m->B;
+  a.bar = (unsigned*)(sc + ctr_off(m->n, m->B)) + 4;
   a.plist = (int32_t*)(sc + plist_off(m->n));
-  a.pcount = (unsigned*)(sc + ctr_off(m->n)) + 8;
+  a.pcount = (unsigned*)(sc + pcount_off(m->n));
   a.seg = m->d_seg;
   a.seg_R = m->seg_R;
   a.flags = m->d_flags;
@@ -789,7 +841,7 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
   if (nnz < 0) return HH_E_SHAPE;
   if (!(w_scale >= 0.0f) || !std::isfinite(w_scale)) return HH_E_INVALID;
   if (!m->d_scratch) {
-    const size_t bytes = scratch_size(m->n);
+    const size_t bytes = scratch_size(m->n, m->B);
     if (hipMalloc(&m->d_scratch, bytes) != hipSuccess) {
       m->d_scratch = nullptr;
       return HH_E_OOM;
@@ -807,15 +859,15 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
   m->w = w;
   m->nnz = nnz;
   m->w_scale = w_scale;
-  // segment table of the binned one-shot delivery (one copy, rows sorted by
-  // target; otherwise the per-event delivery serves)
+  // segment table of the deliveries by target range (rows sorted by target;
+  // otherwise the per-event deliveries serve)
   if (m->d_seg) (void)hipFree(m->d_seg);
   m->d_seg = nullptr;
   m->seg_R = 0;
   // The table holds N (R + 1) offsets; it is built only while that is no
   // more than the column array (N^2 / 1024 grows past it for large N).
   const int64_t R_tab = (m->N + kSegRange - 1) / kSegRange;
-  if (m->B == 1 && nnz > 0 && m->N * (R_tab + 1) <= nnz) {
+  if (nnz > 0 && m->N * (R_tab + 1) <= nnz) {
     const int64_t N = m->N;
     const int R = (int)R_tab;
     int32_t* seg = nullptr;
@@ -913,7 +965,7 @@ int32_t hh_syn_propagate(hh_model* m, const uint32_t* spike_bits, float* state,
   unsigned long long* acc_e = (unsigned long long*)sc + 2 * n;
   unsigned long long* acc_i = acc_e + n;
   int32_t* list = (int32_t*)(sc + list_off(n));
-  unsigned* count = (unsigned*)(sc + ctr_off(n));
+  unsigned* count = (unsigned*)(sc + ctr_off(n, m->B));
   const int G = m->km.n_gates;
   float* ge = state + (int64_t)(1 + G) * n;
   float* gi = state + (int64_t)(2 + G) * n;
@@ -923,7 +975,7 @@ int32_t hh_syn_propagate(hh_model* m, const uint32_t* spike_bits, float* state,
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (m->d_seg) {
+  if (m->d_seg && m->B == 1) {
     const unsigned chunks = (unsigned)((n + kSegChunk - 1) / kSegChunk);
     const unsigned spans = (unsigned)((m->seg_R + kBinSpan - 1) / kBinSpan);
     hipLaunchKernelGGL(k_scatter_binned, dim3(spans * chunks), dim3(kBinBlock), 0, s, list,

@@ -480,7 +480,8 @@ def _block_diagonal(csr, B):
     return rpb, colb, np.tile(w, B)
 
 
-def _batch_gpu(m, csr, scale, v0, T, B, *, ext=None, specialize=True, background=None):
+def _batch_gpu(m, csr, scale, v0, T, B, *, ext=None, specialize=True, background=None,
+               i_const=None, delivery="auto"):
     torch = need_gpu()
     from paper_2601_21407_amd import hh
     N = len(csr[0]) - 1
@@ -488,6 +489,7 @@ def _batch_gpu(m, csr, scale, v0, T, B, *, ext=None, specialize=True, background
     M.set_specialize(specialize)
     bufs = [_dev(csr[0]), _dev(csr[1]), _dev(csr[2].astype(np.float32))]
     M.attach_csr(bufs[0], bufs[1], bufs[2], scale)
+    M.set_delivery(delivery)
     if ext is not None:
         em = _dev(ext[0])
         bufs.append(em)
@@ -495,10 +497,37 @@ def _batch_gpu(m, csr, scale, v0, T, B, *, ext=None, specialize=True, background
     st = M.new_state()
     M.init_state(st, v0=_dev(v0.astype(np.float32)))
     spikes = torch.zeros((T, M.words), dtype=torch.int32, device="cuda")
-    M.step_n(st, T, 0, spikes=spikes, background=background)
+    ic = None if i_const is None else _dev(np.asarray(i_const, np.float32))
+    M.step_n(st, T, 0, spikes=spikes, background=background, i_const=ic)
     status, bad = M.check()
     assert status == 0, (status, bad)
     return O.unpack_bits(spikes.cpu().numpy().view(np.uint32), M.n), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("N,B,fan,T,burst", [(700, 3, 80, 600, False), (1000, 6, 100, 400, False),
+                                             (3001, 2, 300, 100, True), (600, 5, 60, 300, True)])
+def test_network_batch_pull_delivery_equals_push(N, B, fan, T, burst):
+    """Batches of copies (N >= 512) deliver by target range too: a block's
+    512 elements straddle two copies wherever N is not a multiple of 512, and
+    it pulls from both copies' lists the spans of rows that cover its window.
+    Bit-identical to the push delivery, with external events, and in a burst
+    (thousands of spikes in one step, lists longer than one block stages)."""
+    print_case("batch pull vs push N=%d B=%d burst=%s" % (N, B, burst))
+    m = W.net_model()
+    csr = W.net_csr(n=N, fan_out=fan, seed=31, inh_scale=4.0)
+    mask, thr = W.net_external(n=N, frac=0.05, seed=31)
+    v0 = W.net_v0(N * B, 31).astype(np.float64)
+    ic = np.full(N * B, 40.0) if burst else None
+    out = {}
+    for d in ("auto", "push"):
+        out[d] = _batch_gpu(m, csr, 0.3, v0, T, B, ext=(mask, thr, 0.5, 31), i_const=ic,
+                            delivery=d)
+    r_p, s_p = out["push"]
+    if burst:
+        assert r_p.sum(axis=1).max() > 2 * 512
+    assert r_p.sum() > 0
+    assert np.array_equal(out["auto"][0], r_p)
+    assert np.array_equal(out["auto"][1], s_p)
 
 
 def test_network_batch_of_copies_matches_oracle():
