@@ -495,6 +495,7 @@ def bench_network(T=10000):
     v0 = torch.tensor(W.net_v0(n, 3), device="cuda")
     spikes = torch.zeros((T, M.words), dtype=torch.int32, device="cuda")
     M.init_state(st, v0=v0)
+    print("[bench] network: one network, pull delivery", file=sys.stderr, flush=True)
     M.step_n(st, 200, 0, spikes=spikes)  # warm-up
     _sync()
     M.init_state(st, v0=v0)
@@ -511,6 +512,7 @@ def bench_network(T=10000):
         raise RuntimeError("network run failed: status %d (neuron %d)" % (status, bad))
     # the same run with the push delivery (device atomics into arrival
     # accumulators) for comparison; the results are identical
+    print("[bench] network: push delivery", file=sys.stderr, flush=True)
     M.set_delivery("push")
     M.init_state(st, v0=v0)
     p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -530,6 +532,7 @@ def bench_network(T=10000):
     n_events = int((spk_bits.sum(axis=0).astype(np.int64) * row_len).sum())
     # the same neurons, drive and grid with empty rows: the step without any
     # synaptic delivery (the neurons then spike only from the external drive)
+    print("[bench] network: empty rows", file=sys.stderr, flush=True)
     Me = hh.Model(m, n)
     rp0 = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
     Me.attach_csr(rp0, torch.empty(0, dtype=torch.int32, device="cuda"),
@@ -549,6 +552,7 @@ def bench_network(T=10000):
     del Me, ste
     # a batch of copies of the network in one grid (the paper's parallel
     # simulations): throughput as copies x speed
+    print("[bench] network: batches of copies", file=sys.stderr, flush=True)
     batch = {}
     for B in (2, 3, 4, 6):
         Mb = hh.Model(m, n, B)
@@ -580,6 +584,7 @@ def bench_network(T=10000):
                             "copies_x_speed": B * (0.1e-3 / (us * 1e-6))}
         del Mb, stb
     # full-load scatter: every neuron spikes once (99.94 M synaptic events)
+    print("[bench] network: full-load one-shot delivery", file=sys.stderr, flush=True)
     allbits = torch.full((M.words,), -1, dtype=torch.int32, device="cuda")
     s2 = st.clone()
     for _ in range(2):
@@ -595,12 +600,15 @@ def bench_network(T=10000):
     sc_ms = a.elapsed_time(b) / reps
     nnz = int(csr[1].shape[0])
     # barrier floor: the same grid (blocks of 512) running only the per-step
-    # grid barrier, then barrier + accumulator reads
+    # grid barrier: the single arrival counter (alone and with the push
+    # delivery's accumulator reads) and the flag-array barrier
+    print("[bench] network: barrier floor", file=sys.stderr, flush=True)
     from paper_2601_21407_amd import probe as PR
     blocks = (n + 511) // 512
     floor = {}
     work = None
-    for mode, name in ((0, "barrier_us"), (1, "barrier_plus_acc_us")):
+    for mode, name in ((0, "counter_barrier_us"), (1, "counter_barrier_plus_acc_us"),
+                       (2, "barrier_us")):
         work = PR.probe_barrier(100, blocks, mode, work)
         _sync()
         a.record()
@@ -609,10 +617,15 @@ def bench_network(T=10000):
         _sync()
         floor[name] = a.elapsed_time(b) / T * 1e3
     kern_us = e0.elapsed_time(e1) / T * 1e3
-    floor["step_over_floor"] = kern_us / floor["barrier_plus_acc_us"]
+    # the network kernel synchronizes with the flag-array barrier from 32
+    # blocks up (this grid: 75 blocks of 512)
+    floor["barrier_in_use"] = "flag array" if blocks >= 32 else "single counter"
+    floor["step_over_floor"] = kern_us / floor["barrier_us" if blocks >= 32 else
+                                               "counter_barrier_us"]
     # the same network with per-pathway delays (8 populations, 1 to 15
     # steps) and background input in every neuron instead of the external
     # events: the ring of arrivals in flight and the per-step draw
+    print("[bench] network: pathway delays", file=sys.stderr, flush=True)
     dl, _, _ = W.pathway_delays(csr, 8, 15, 3)
     Md = hh.Model(m, n)
     Md.attach_csr(rp, col, w, W.NET_W_SCALE)

@@ -42,7 +42,9 @@ int32_t hh_probe_issue(int32_t op, int32_t iters, int32_t blocks, float* out, in
 /* Barrier floor of the persistent network kernel: a cooperative launch of
  * `blocks` blocks of the network kernel's size runs `steps` grid barriers
  * (mode 0), or each barrier followed by the two per-neuron accumulator
- * read-and-clear atomics the network step performs (mode 1).  Timing it on
+ * read-and-clear atomics the network step performs (mode 1), or the
+ * flag-array barrier alone (mode 2: each block stores its arrival in a slot
+ * of its own, one wavefront gathers them and releases the grid).  Timing it on
  * `stream` gives the synchronization cost per step with no neuron or
  * synapse work.  work: device scratch of hh_probe_barrier_bytes(blocks)
  * bytes (zeroed by the call).  Returns 0, -1 for bad arguments, -2 for a

@@ -21,7 +21,8 @@ __global__ void k_zero_u32(unsigned* p, int count) {
 // ---- barrier floor (measurement) -------------------------------------------
 // The per-step synchronization of k_net without the neuron work: each step
 // is one grid barrier, plus (mode 1) the two accumulator reads-and-clears
-// per lane that follow it in k_net.  Same block size and barrier code.
+// per lane that follow it in k_net.  Same block size and barrier code; mode
+// 2 is the flag-array barrier alone.
 __global__ __launch_bounds__(kBlock) void k_barrier_floor(unsigned* bar, int32_t* flags,
                                                              unsigned long long* acc, int n,
                                                              int steps, int mode,
@@ -31,7 +32,9 @@ __global__ __launch_bounds__(kBlock) void k_barrier_floor(unsigned* bar, int32_t
   const int i = blockIdx.x * kBlock + threadIdx.x;
   float sink = 0.0f;
   for (int t = 0; t < steps; ++t) {
-    if (!grid_barrier(bar, gridDim.x, gen, spin_limit, flags, &s_ok)) break;
+    const bool ok = mode == 2 ? grid_barrier3(bar, gridDim.x, gen, spin_limit, flags, &s_ok)
+                              : grid_barrier(bar, gridDim.x, gen, spin_limit, flags, &s_ok);
+    if (!ok) break;
     if (mode == 1 && i < n) {
       const unsigned long long* b = acc + (size_t)(t & 1) * 2 * n;
       sink += (float)atomicExch((unsigned long long*)&b[i], 0ull);
@@ -41,18 +44,23 @@ __global__ __launch_bounds__(kBlock) void k_barrier_floor(unsigned* bar, int32_t
   if (sink != 0.0f) flags[2] = 1;  // keeps the reads; never true (accumulators are zero)
 }
 
+// barrier bytes for every mode: the flag-array layout (256 + one word per
+// block), rounded up to 256 bytes so that the flags and the 64-bit
+// accumulators after it stay aligned
+size_t bar_bytes(int32_t blocks) { return ((256 + (size_t)blocks) * 4 + 255) & ~(size_t)255; }
+
 }  // namespace
 
 extern "C" {
 
 size_t hh_probe_barrier_bytes(int32_t blocks) {
   if (blocks < 1) return 0;
-  return 256 + (size_t)4 * blocks * kBlock * sizeof(unsigned long long);
+  return bar_bytes(blocks) + 256 + (size_t)4 * blocks * kBlock * sizeof(unsigned long long);
 }
 
 int32_t hh_probe_barrier(int32_t steps, int32_t blocks, int32_t mode, void* work,
                          size_t work_bytes, void* stream) {
-  if (steps < 1 || blocks < 1 || (mode != 0 && mode != 1) || !work) return HH_E_INVALID;
+  if (steps < 1 || blocks < 1 || mode < 0 || mode > 2 || !work) return HH_E_INVALID;
   if (work_bytes < hh_probe_barrier_bytes(blocks)) return HH_E_SHAPE;
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -63,8 +71,9 @@ int32_t hh_probe_barrier(int32_t steps, int32_t blocks, int32_t mode, void* work
   if (blocks > ncu * per_cu) return HH_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   unsigned* bar = (unsigned*)work;
-  int32_t* flags = (int32_t*)((char*)work + 64);
-  unsigned long long* acc = (unsigned long long*)((char*)work + 256);
+  int32_t* flags = (int32_t*)((char*)work + bar_bytes(blocks));
+  unsigned long long* acc = (unsigned long long*)((char*)work + bar_bytes(blocks) + 256);
+  if ((uintptr_t)work % 256 != 0) return HH_E_INVALID;  // the 64-bit atomics need alignment
   const int n = blocks * kBlock;
   const int words = (int)(hh_probe_barrier_bytes(blocks) / 4);
   hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s,

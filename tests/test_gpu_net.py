@@ -505,13 +505,15 @@ def _batch_gpu(m, csr, scale, v0, T, B, *, ext=None, specialize=True, background
 
 
 @pytest.mark.parametrize("N,B,fan,T,burst", [(700, 3, 80, 600, False), (1000, 6, 100, 400, False),
-                                             (3001, 2, 300, 100, True), (600, 5, 60, 300, True)])
+                                             (3001, 2, 300, 100, True), (600, 5, 60, 300, True),
+                                             (4000, 5, 150, 300, False)])
 def test_network_batch_pull_delivery_equals_push(N, B, fan, T, burst):
     """Batches of copies (N >= 512) deliver by target range too: a block's
     512 elements straddle two copies wherever N is not a multiple of 512, and
     it pulls from both copies' lists the spans of rows that cover its window.
     Bit-identical to the push delivery, with external events, and in a burst
-    (thousands of spikes in one step, lists longer than one block stages)."""
+    (thousands of spikes in one step, lists longer than one block stages);
+    the last case's 40 blocks synchronize with the flag-array barrier."""
     print_case("batch pull vs push N=%d B=%d burst=%s" % (N, B, burst))
     m = W.net_model()
     csr = W.net_csr(n=N, fan_out=fan, seed=31, inh_scale=4.0)
@@ -630,3 +632,20 @@ def test_cortical_network_spike_exact_to_horizon(specialize):
     print("cortical horizon %d of %d, spikes %d, mismatched %d" % (h, T, int(ref.sum()), len(bad)),
           flush=True)
     assert len(bad) == 0
+
+
+@pytest.mark.parametrize("blocks", [8, 75, 149])
+def test_barrier_probe_modes_odd_and_even_grids(blocks):
+    """The barrier probe in its three modes, on grids whose barrier area is
+    not a multiple of 8 bytes long (the accumulators after it must still be
+    aligned for the 64-bit atomics of mode 1); every barrier completes."""
+    print_case("barrier probe blocks=%d" % blocks)
+    torch = need_gpu()
+    from paper_2601_21407_amd import probe as PR
+    work = None
+    flags_at = ((256 + blocks) * 4 + 255) // 256 * 256  # the flags follow the barrier words
+    for mode in (0, 1, 2):
+        work = PR.probe_barrier(50, blocks, mode, work)
+        torch.cuda.synchronize()
+        flags = work[flags_at:flags_at + 8].cpu().numpy().view(np.int32)
+        assert flags[1] == 0, (mode, flags)  # no barrier timed out
