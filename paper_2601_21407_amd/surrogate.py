@@ -21,7 +21,7 @@ from . import workloads as W
 
 K_STEPS = 10          # surrogate step = 10 plain steps of 0.025 ms
 V_FALLBACK = -50.0    # mV
-CHECK_EVERY = 10      # calls
+CHECK_EVERY = 20      # calls (200 plain steps, 5 ms); the configuration fixes no period
 CHECK_TOL = 0.5       # mV
 
 
