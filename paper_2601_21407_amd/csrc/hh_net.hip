@@ -43,7 +43,10 @@ namespace {
 
 constexpr float kFix = 1099511627776.0f;        // 2^40
 constexpr float kUnfix = 9.094947017729282e-13f;  // 2^-40
-constexpr int kNetBlock = 512;
+constexpr int kNetBlock = 512;      // threads per block of the network kernel
+constexpr int kNetBlockWide = 1024; // for large grids with the pull delivery
+constexpr int64_t kWideMinBlocks = 192;  // in blocks of kNetBlock
+constexpr int kSegRange = 512;      // targets per range of the segment table
 // Grids of at least this many blocks synchronize with the flag-array barrier
 // (measured per step: 3.3 against 3.7 us at 75 blocks, 10.5 against 19.0 us
 // at 446); smaller ones with the single arrival counter (1.2 against 2.0 us
@@ -183,7 +186,7 @@ __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
 }
 
 // Pull delivery of one step's spikes of one copy into the block's own
-// targets: the block owning elements [lo, lo + kNetBlock) reads the copy's
+// targets: the block owning elements [lo, lo + BS) reads the copy's
 // list of spiking rows, then each row's span of targets that covers the
 // block's window [x0, x1) of the copy (table ranges r0..r1 of the segment
 // table of the rows sorted by target), and adds the events inside the window
@@ -191,8 +194,9 @@ __device__ __forceinline__ void scatter_flat(const int32_t* __restrict__ col,
 // No device atomics and no accumulator buffers; the integer sums equal those
 // of the push delivery bit for bit.  The list and its count were written by
 // other blocks before the last grid barrier: they are read with device-scope
-// loads.  s_a and s_len are staging arrays of kNetBlock entries; the
+// loads.  s_a and s_len are staging arrays of BS entries; the
 // accumulators are complete when it returns.
+template <int BS>
 __device__ void pull_deliver(const int32_t* list, const unsigned* countp, int64_t N,
                              const int32_t* __restrict__ seg, int R, int r0, int r1, int x0,
                              int x1, int ldsoff, const int64_t* __restrict__ row_ptr,
@@ -200,7 +204,7 @@ __device__ void pull_deliver(const int32_t* list, const unsigned* countp, int64_
                              float scale40, unsigned long long* s_e, unsigned long long* s_i,
                              int64_t* s_a, int* s_len) {
   const int tid = threadIdx.x;
-  // the count and the first kNetBlock entries in one round trip
+  // the count and the first BS entries in one round trip
   unsigned cnt = __hip_atomic_load(countp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const int32_t spec = tid < N ? __hip_atomic_load(&list[tid], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT)
@@ -214,7 +218,7 @@ __device__ void pull_deliver(const int32_t* list, const unsigned* countp, int64_
   __syncthreads();
   cnt = s_pc;
   constexpr int G = 16;  // lanes per row span
-  for (unsigned c0 = 0; c0 < cnt; c0 += kNetBlock) {
+  for (unsigned c0 = 0; c0 < cnt; c0 += BS) {
     const unsigned e = c0 + tid;
     if (e < cnt) {
       const int32_t src = c0 == 0 ? spec
@@ -226,8 +230,8 @@ __device__ void pull_deliver(const int32_t* list, const unsigned* countp, int64_
       s_len[tid] = s1 - s0;
     }
     __syncthreads();
-    const int rows = (int)min(cnt - c0, (unsigned)kNetBlock);
-    for (int x = tid / G; x < rows; x += kNetBlock / G) {
+    const int rows = (int)min(cnt - c0, (unsigned)BS);
+    for (int x = tid / G; x < rows; x += BS / G) {
       const int64_t a = s_a[x];
       const int len = s_len[x];
       for (int b0 = 0; b0 < len; b0 += 4 * G) {
@@ -264,8 +268,8 @@ __device__ __forceinline__ PullWin pull_window(int64_t lo, int64_t hi, int64_t c
   const int64_t base = c * N;
   p.x0 = (int)max(lo - base, (int64_t)0);
   p.x1 = (int)min(hi - base, N);
-  p.r0 = p.x0 / kNetBlock;
-  p.r1 = (p.x1 - 1) / kNetBlock;
+  p.r0 = p.x0 / kSegRange;
+  p.r1 = (p.x1 - 1) / kSegRange;
   p.ldsoff = (int)(base - lo);
   return p;
 }
@@ -332,14 +336,14 @@ __device__ __forceinline__ void net_update(const KModel& M, const LaneRates<S::k
 // the copy offsets entirely.  PULL: one-step delays and a segment table:
 // delivery by pull_deliver instead of the scatter (with BATCH, N >= 512, so
 // that a block's elements span at most two copies).
-template <class S, bool DELAY, bool BATCH, bool PULL = false>
-__global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
+template <class S, bool DELAY, bool BATCH, bool PULL = false, int BS = kNetBlock>
+__global__ __launch_bounds__(BS) void k_net(KModel M, NetArgs A) {
   static_assert(!(PULL && DELAY), "pull delivery: one-step delays");
   constexpr int NG = S::kNG;
-  __shared__ int s_pre[kNetBlock];
-  __shared__ int s_base[kNetBlock];
-  __shared__ int64_t s_r0[kNetBlock];
-  __shared__ unsigned long long s_ae[PULL ? kNetBlock : 1], s_ai[PULL ? kNetBlock : 1];
+  __shared__ int s_pre[BS];
+  __shared__ int s_base[BS];
+  __shared__ int64_t s_r0[BS];
+  __shared__ unsigned long long s_ae[PULL ? BS : 1], s_ai[PULL ? BS : 1];
   __shared__ int s_cnt;
   __shared__ unsigned s_gbase[2];
   __shared__ int s_ccnt[2];
@@ -377,8 +381,8 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   // ring slot of the current time (DELAY), advanced once per step
   int now = DELAY ? (int)(A.t0 % A.R) : 0;
   // the block's elements [lo, hi) and the copies cf..cl they belong to (PULL)
-  const int64_t lo = (int64_t)blockIdx.x * kNetBlock, hi = min(lo + kNetBlock, n);
-  const int64_t cf = lo / A.N, cl = (hi - 1) / A.N;  // cl <= cf + 1 (N >= 512)
+  const int64_t lo = (int64_t)blockIdx.x * BS, hi = min(lo + (int64_t)BS, n);
+  const int64_t cf = lo / A.N, cl = (hi - 1) / A.N;  // cl <= cf + 1 (N >= BS)
   const int my_c = (int)(ii / A.N - cf);              // 0 or 1
   if constexpr (PULL) {
     s_ae[threadIdx.x] = 0ull;
@@ -387,7 +391,7 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
   auto pull_all = [&](int step) {
     for (int64_t c = cf; c <= cl; ++c) {
       const PullWin pw = pull_window(lo, hi, c, A.N);
-      pull_deliver(A.plist + ((int64_t)(step & 1) * n + c * A.N),
+      pull_deliver<BS>(A.plist + ((int64_t)(step & 1) * n + c * A.N),
                    A.pcount + (int64_t)(step % 3) * A.B + c, A.N, A.seg, A.seg_R, pw.r0, pw.r1,
                    pw.x0, pw.x1, pw.ldsoff, A.row_ptr, A.col, A.w, scale40, s_ae, s_ai, s_r0,
                    s_pre);
@@ -454,7 +458,7 @@ __global__ __launch_bounds__(kNetBlock) void k_net(KModel M, NetArgs A) {
       // the counts of step k - 2 have been read by every block (before the
       // last barrier) and are next added to at step k + 1: clear them now
       if (blockIdx.x == 0)
-        for (int c = threadIdx.x; c < A.B; c += kNetBlock)
+        for (int c = threadIdx.x; c < A.B; c += BS)
           __hip_atomic_store(A.pcount + (int64_t)((k + 1) % 3) * A.B + c, 0u, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
       __syncthreads();
@@ -590,7 +594,6 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ lis
 // fall from one per event (contention on a few thousand cache lines) to one
 // per target and chunk.  The sums are integers, so the result equals the
 // per-event delivery's bit for bit.
-constexpr int kSegRange = kNetBlock;  // targets per range: a network block's neurons
 constexpr int kBinSpan = 2;       // table ranges per one-shot block (1,024 targets)
 constexpr int kSegChunk = 2048;   // spiking rows per block
 constexpr int kBinBlock = 512;    // threads per block: 32 groups of 16 lanes
@@ -725,35 +728,37 @@ size_t bar_words(int64_t n) { return 256 + (size_t)((n + kNetBlock - 1) / kNetBl
 size_t bar_off(int64_t n, int32_t B) { return ctr_off(n, B) + 256; }
 size_t scratch_size(int64_t n, int32_t B) { return bar_off(n, B) + al256(bar_words(n) * 4); }
 
-template <class S, bool DELAY, bool BATCH, bool PULL>
+template <class S, bool DELAY, bool BATCH, bool PULL, int BS = kNetBlock>
 hipError_t launch_net(hh_model* m, NetArgs& a, hipStream_t s) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_net<S, DELAY, BATCH, PULL>,
-                                                   kNetBlock, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_net<S, DELAY, BATCH, PULL, BS>,
+                                                   BS, 0);
   if (e != hipSuccess) return e;
-  const int64_t nb = (a.n + kNetBlock - 1) / kNetBlock;
+  const int64_t nb = (a.n + BS - 1) / BS;
   if (nb > (int64_t)ncu * per_cu) return hipErrorCooperativeLaunchTooLarge;
   hipLaunchKernelGGL(k_net_reset, dim3(1), dim3(256), 0, s, a.bar, (int)bar_words(a.n), a.pcount,
                      3 * a.B);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* args[] = {(void*)&m->km, (void*)&a};
-  return hipLaunchCooperativeKernel((const void*)k_net<S, DELAY, BATCH, PULL>, dim3((unsigned)nb),
-                                    dim3(kNetBlock), args, 0, s);
+  return hipLaunchCooperativeKernel((const void*)k_net<S, DELAY, BATCH, PULL, BS>,
+                                    dim3((unsigned)nb), dim3(BS), args, 0, s);
 }
 
 }  // namespace
 
-template <bool DELAY, bool BATCH, bool PULL = false>
+// BS: the block size of the compiled channel sets (the interpreter always
+// takes 512-thread blocks)
+template <bool DELAY, bool BATCH, bool PULL = false, int BS = kNetBlock>
 static hipError_t launch_net_spec(hh_model* m, NetArgs& a, hipStream_t s) {
   if (m->use_fixed && ClassicSpec::matches(m->km))
-    return launch_net<ClassicSpec, DELAY, BATCH, PULL>(m, a, s);
+    return launch_net<ClassicSpec, DELAY, BATCH, PULL, BS>(m, a, s);
   if (m->use_fixed && CorticalSpec::matches(m->km))
-    return launch_net<CorticalSpec, DELAY, BATCH, PULL>(m, a, s);
+    return launch_net<CorticalSpec, DELAY, BATCH, PULL, BS>(m, a, s);
   switch (m->km.n_gates) {
     case 1: return launch_net<GenericSpec<1>, DELAY, BATCH, PULL>(m, a, s);
     case 2: return launch_net<GenericSpec<2>, DELAY, BATCH, PULL>(m, a, s);
@@ -772,8 +777,16 @@ template <bool DELAY>
 static hipError_t launch_net_b(hh_model* m, NetArgs& a, hipStream_t s) {
   if constexpr (!DELAY) {
     if (m->d_seg && m->net_pull) {
-      if (m->B == 1) return launch_net_spec<false, false, true>(m, a, s);
-      if (m->N >= kNetBlock) return launch_net_spec<false, true, true>(m, a, s);
+      // grids of 192 blocks of 512 or more take blocks of 1,024 (half the
+      // barrier's arrivals); a batch's copies must then span whole blocks
+      const bool wide = (m->n + kNetBlock - 1) / kNetBlock >= kWideMinBlocks &&
+                        (m->B == 1 || m->N >= kNetBlockWide);
+      if (m->B == 1)
+        return wide ? launch_net_spec<false, false, true, kNetBlockWide>(m, a, s)
+                    : launch_net_spec<false, false, true>(m, a, s);
+      if (m->N >= kNetBlock)
+        return wide ? launch_net_spec<false, true, true, kNetBlockWide>(m, a, s)
+                    : launch_net_spec<false, true, true>(m, a, s);
     }
   }
   return m->B > 1 ? launch_net_spec<DELAY, true>(m, a, s) : launch_net_spec<DELAY, false>(m, a, s);

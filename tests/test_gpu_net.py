@@ -208,7 +208,7 @@ def test_network_spike_exact_to_horizon(n, fan, T):
 
 
 @pytest.mark.parametrize("n,fan,T,burst", [(2000, 200, 1000, False), (3001, 300, 120, True),
-                                           (513, 40, 400, False)])
+                                           (513, 40, 400, False), (100003, 60, 150, False)])
 def test_network_pull_delivery_equals_push(n, fan, T, burst):
     """The delivery by target range (each block pulls the previous step's
     spiking rows' events for its own 512 neurons) and the push delivery
@@ -506,14 +506,16 @@ def _batch_gpu(m, csr, scale, v0, T, B, *, ext=None, specialize=True, background
 
 @pytest.mark.parametrize("N,B,fan,T,burst", [(700, 3, 80, 600, False), (1000, 6, 100, 400, False),
                                              (3001, 2, 300, 100, True), (600, 5, 60, 300, True),
-                                             (4000, 5, 150, 300, False)])
+                                             (4000, 5, 150, 300, False),
+                                             (20000, 5, 100, 200, False)])
 def test_network_batch_pull_delivery_equals_push(N, B, fan, T, burst):
     """Batches of copies (N >= 512) deliver by target range too: a block's
     512 elements straddle two copies wherever N is not a multiple of 512, and
     it pulls from both copies' lists the spans of rows that cover its window.
     Bit-identical to the push delivery, with external events, and in a burst
     (thousands of spikes in one step, lists longer than one block stages);
-    the last case's 40 blocks synchronize with the flag-array barrier."""
+    40 blocks synchronize with the flag-array barrier, and 100,000 neurons
+    (196 blocks of 512) take blocks of 1,024."""
     print_case("batch pull vs push N=%d B=%d burst=%s" % (N, B, burst))
     m = W.net_model()
     csr = W.net_csr(n=N, fan_out=fan, seed=31, inh_scale=4.0)
