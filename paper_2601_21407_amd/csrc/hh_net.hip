@@ -45,7 +45,7 @@ constexpr float kFix = 1099511627776.0f;        // 2^40
 constexpr float kUnfix = 9.094947017729282e-13f;  // 2^-40
 constexpr int kNetBlock = 512;      // threads per block of the network kernel
 constexpr int kNetBlockWide = 1024; // for large grids with the pull delivery
-constexpr int64_t kWideMinBlocks = 192;  // in blocks of kNetBlock
+constexpr int64_t kWideMinBlocks = 128;  // in blocks of kNetBlock
 constexpr int kSegRange = 512;      // targets per range of the segment table
 // Grids of at least this many blocks synchronize with the flag-array barrier
 // (measured per step: 3.3 against 3.7 us at 75 blocks, 10.5 against 19.0 us
@@ -777,7 +777,7 @@ template <bool DELAY>
 static hipError_t launch_net_b(hh_model* m, NetArgs& a, hipStream_t s) {
   if constexpr (!DELAY) {
     if (m->d_seg && m->net_pull) {
-      // grids of 192 blocks of 512 or more take blocks of 1,024 (half the
+      // grids of 128 blocks of 512 or more take blocks of 1,024 (half the
       // barrier's arrivals); a batch's copies must then span whole blocks
       const bool wide = (m->n + kNetBlock - 1) / kNetBlock >= kWideMinBlocks &&
                         (m->B == 1 || m->N >= kNetBlockWide);
