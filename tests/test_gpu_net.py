@@ -515,7 +515,7 @@ def test_network_batch_pull_delivery_equals_push(N, B, fan, T, burst):
     Bit-identical to the push delivery, with external events, and in a burst
     (thousands of spikes in one step, lists longer than one block stages);
     40 blocks synchronize with the flag-array barrier, and 100,000 neurons
-    (196 blocks of 512; 128 or more take blocks of 1,024) the wide blocks."""
+    (196 blocks of 512) run in blocks of 1,024, as grids of 128 or more do."""
     print_case("batch pull vs push N=%d B=%d burst=%s" % (N, B, burst))
     m = W.net_model()
     csr = W.net_csr(n=N, fan_out=fan, seed=31, inh_scale=4.0)
