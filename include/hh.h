@@ -257,9 +257,13 @@ int32_t hh_step_n(hh_model* m, float* state, int64_t t0, int32_t n_steps, const 
  * units).  When the rows list their targets in ascending order, the call
  * also builds a table of each row's offsets at every 512th target
  * (N (ceil(N / 512) + 1) int32, kept while it is no larger than the column
- * array), which the deliveries by target range use.  Buffers stay owned by
- * the caller.  Requires has_syn.  Errors: HH_E_INVALID, HH_E_SHAPE, HH_E_OOM,
- * HH_E_HIP. */
+ * array), which the deliveries by target range use.  The call synchronizes
+ * the device and reads the CSR once to check it.  Buffers stay owned by the
+ * caller.  Requires has_syn.  Errors: HH_E_INVALID for missing arrays, a
+ * negative or non-finite w_scale, or an invalid CSR (row_ptr not starting at
+ * 0, decreasing, or not ending at nnz; a column outside [0, N)), in which
+ * case the model keeps its previous connectivity; HH_E_SHAPE for nnz < 0;
+ * HH_E_OOM; HH_E_HIP. */
 int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, const float* w,
                       int64_t nnz, float w_scale);
 

@@ -600,26 +600,37 @@ constexpr int kBinBlock = 512;    // threads per block: 32 groups of 16 lanes
 constexpr int kBinGroup = 16;     // lanes that share one row's segment
 constexpr int kBinUnroll = 8;     // loads in flight per lane (128 events per pass)
 
-// Per row: sortedness check and the offsets of the range boundaries.
+// Per row: validity (row_ptr non-decreasing within [0, nnz], starting at 0
+// and ending at nnz; every column in [0, N)), sortedness, and -- when seg is
+// given -- the offsets of the range boundaries.  flags bit 0: some row is
+// not sorted; bit 1: the CSR is invalid (nothing past a bad row_ptr entry
+// is read).
 __global__ __launch_bounds__(256) void k_csr_segments(const int64_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ col, int64_t N,
-                                                      int R, int32_t* __restrict__ seg,
-                                                      int* __restrict__ unsorted) {
+                                                      int64_t nnz, int R, int32_t* __restrict__ seg,
+                                                      int* __restrict__ flags) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= N) return;
   const int64_t r0 = row_ptr[j], r1 = row_ptr[j + 1];
-  int32_t* sj = seg + j * (int64_t)(R + 1);
+  if (r0 < 0 || r1 < r0 || r1 > nnz || (j == 0 && r0 != 0) || (j == N - 1 && r1 != nnz)) {
+    atomicOr(flags, 2);
+    return;
+  }
+  int32_t* sj = seg ? seg + j * (int64_t)(R + 1) : nullptr;
   int r = 0;
   int32_t prev = -1;
-  bool bad = false;
+  bool unsorted = false, bad = false;
   for (int64_t q = r0; q < r1; ++q) {
     const int32_t c = col[q];
-    bad |= c < prev || c < 0 || c >= N;
+    unsorted |= c < prev;
+    bad |= c < 0 || c >= N;
     prev = c;
-    while (r <= R && (int64_t)r * kSegRange <= c) sj[r++] = (int32_t)(q - r0);
+    if (sj)
+      while (r <= R && (int64_t)r * kSegRange <= c) sj[r++] = (int32_t)(q - r0);
   }
-  while (r <= R) sj[r++] = (int32_t)(r1 - r0);
-  if (bad) atomicOr(unsorted, 1);
+  if (sj)
+    while (r <= R) sj[r++] = (int32_t)(r1 - r0);
+  if (unsorted || bad) atomicOr(flags, (unsorted ? 1 : 0) | (bad ? 2 : 0));
 }
 
 // Grid: R ranges x chunks blocks in one dimension.  Consecutive hardware
@@ -873,6 +884,42 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
     if (hipMemset(m->d_scratch, 0, bytes) != hipSuccess) return HH_E_HIP;
     m->scratch_bytes = bytes;
   }
+  // Every row is read once on the device: the CSR is checked (a bad column
+  // or row pointer would send the delivery's writes out of bounds) and, for
+  // rows sorted by target, the segment table of the deliveries by target
+  // range is built.  The table holds N (R + 1) offsets and is built only
+  // while that is no more than the column array (N^2 / 512 grows past it).
+  // The device is synchronized first, so the CSR is complete whichever
+  // stream wrote it.
+  if (hipDeviceSynchronize() != hipSuccess) return HH_E_HIP;
+  const int64_t N = m->N;
+  const int R = (int)((N + kSegRange - 1) / kSegRange);
+  int32_t* seg = nullptr;
+  int* flag = nullptr;
+  if (nnz > 0 && N * (int64_t)(R + 1) <= nnz &&
+      hipMalloc((void**)&seg, (size_t)N * (R + 1) * sizeof(int32_t)) != hipSuccess)
+    seg = nullptr;  // no table: the per-event deliveries serve
+  if (hipMalloc((void**)&flag, sizeof(int)) != hipSuccess) {
+    if (seg) (void)hipFree(seg);
+    return HH_E_OOM;
+  }
+  int flags = 2;
+  bool ok = hipMemset(flag, 0, sizeof(int)) == hipSuccess;
+  if (ok) {
+    hipLaunchKernelGGL(k_csr_segments, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, 0, row_ptr,
+                       col, N, nnz, R, seg, flag);
+    ok = hipGetLastError() == hipSuccess &&
+         hipMemcpy(&flags, flag, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess;
+  }
+  (void)hipFree(flag);
+  if (!ok || (flags & 2)) {
+    if (seg) (void)hipFree(seg);
+    return ok ? HH_E_INVALID : HH_E_HIP;
+  }
+  if (flags & 1) {  // unsorted rows: no table
+    if (seg) (void)hipFree(seg);
+    seg = nullptr;
+  }
   // a delay table belongs to the connectivity it was set for
   if (m->d_ring) (void)hipFree(m->d_ring);
   m->d_ring = nullptr;
@@ -883,44 +930,9 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
   m->w = w;
   m->nnz = nnz;
   m->w_scale = w_scale;
-  // segment table of the deliveries by target range (rows sorted by target;
-  // otherwise the per-event deliveries serve)
   if (m->d_seg) (void)hipFree(m->d_seg);
-  m->d_seg = nullptr;
-  m->seg_R = 0;
-  // The table holds N (R + 1) offsets; it is built only while that is no
-  // more than the column array (N^2 / 1024 grows past it for large N).
-  const int64_t R_tab = (m->N + kSegRange - 1) / kSegRange;
-  if (nnz > 0 && m->N * (R_tab + 1) <= nnz) {
-    const int64_t N = m->N;
-    const int R = (int)R_tab;
-    int32_t* seg = nullptr;
-    int* flag = nullptr;
-    if (hipMalloc((void**)&seg, (size_t)N * (R + 1) * sizeof(int32_t)) != hipSuccess) return HH_E_OOM;
-    if (hipMalloc((void**)&flag, sizeof(int)) != hipSuccess) {
-      (void)hipFree(seg);
-      return HH_E_OOM;
-    }
-    int unsorted = 1;
-    bool ok = hipMemset(flag, 0, sizeof(int)) == hipSuccess;
-    if (ok) {
-      hipLaunchKernelGGL(k_csr_segments, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, 0, row_ptr,
-                         col, N, R, seg, flag);
-      ok = hipGetLastError() == hipSuccess &&
-           hipMemcpy(&unsorted, flag, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess;
-    }
-    (void)hipFree(flag);
-    if (!ok) {
-      (void)hipFree(seg);
-      return HH_E_HIP;
-    }
-    if (unsorted) {
-      (void)hipFree(seg);
-    } else {
-      m->d_seg = seg;
-      m->seg_R = R;
-    }
-  }
+  m->d_seg = seg;
+  m->seg_R = seg ? R : 0;
   return HH_OK;
 }
 

@@ -237,6 +237,38 @@ def test_network_pull_delivery_equals_push(n, fan, T, burst):
     assert np.array_equal(b["state"], out["push"]["state"])
 
 
+def test_attach_refuses_invalid_csr_and_keeps_the_previous_one():
+    """hh_attach_csr checks the CSR on the device before any delivery can use
+    it (a bad column or row pointer would send the delivery's writes out of
+    bounds): each invalid CSR is refused with HH_E_INVALID, and the model
+    keeps running on the connectivity attached before, bit for bit."""
+    print_case("attach invalid CSR")
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    m = W.net_model()
+    n, fan = 600, 40
+    rp, col, w = W.net_csr(n=n, fan_out=fan, seed=17, inh_scale=4.0)
+    v0 = W.net_v0(n, 17).astype(np.float64)
+    ref = _net_gpu(m, (rp, col, w), 0.3, v0, 200, i_const=np.full(n, 8.0))
+    M = ref["M"]
+    bad = []
+    c1 = col.copy(); c1[5] = n; bad.append((rp, c1))            # column = N
+    c2 = col.copy(); c2[fan * 7 + 3] = -1; bad.append((rp, c2))  # negative column
+    r3 = rp.copy(); r3[10], r3[11] = r3[11], r3[10]; bad.append((r3, col))  # decreasing
+    r4 = rp.copy(); r4[-1] -= 3; bad.append((r4, col))           # does not end at nnz
+    r5 = rp.copy(); r5[0] = 1; bad.append((r5, col))             # does not start at 0
+    for r_, c_ in bad:
+        bufs = [_dev(r_), _dev(c_), _dev(w.astype(np.float32))]
+        with pytest.raises(hh.HHError) as e:
+            M.attach_csr(bufs[0], bufs[1], bufs[2], 0.3)
+        assert e.value.status == -1
+    st = M.init_state(M.new_state(), v0=_dev(v0.astype(np.float32)))
+    spikes = torch.zeros((200, M.words), dtype=torch.int32, device="cuda")
+    M.step_n(st, 200, 0, i_const=_dev(np.full(n, 8.0, np.float32)), spikes=spikes)
+    assert np.array_equal(O.unpack_bits(spikes.cpu().numpy().view(np.uint32), n), ref["raster"])
+    assert np.array_equal(st.cpu().numpy(), ref["state"])
+
+
 def test_network_resume_and_tiny_cases():
     print_case("network resume / n=1")
     m = W.net_model()
