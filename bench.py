@@ -836,6 +836,29 @@ def bench_layer(reps=5, ckpt_every=50):
                 "proj_wgrad": seg("b1", "b2"), "adam": seg("b2", "b3")}
     upd = n * T
     gflop = 2.0 * T * B * n_in * H / 1e9
+
+    # Context, not part of the step: the vendor library's bf16 GEMM (torch
+    # matmul) on the two product shapes, with the spikes expanded to bf16 --
+    # the forward shape with a bf16 result (half the stores of the FP32 one),
+    # the weight-gradient shape with one bf16 term of dI (the library step
+    # above uses two, hi + lo).
+    W16 = win16.t().contiguous()
+    St = S.t().contiguous()
+    dI16 = dI.view(T * B, H).to(torch.bfloat16)
+
+    def lib_ms(fn, k=10):
+        fn()
+        _sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        _sync()
+        return e0.elapsed_time(e1) / k
+    library = {"forward_shape_bf16_result_ms": lib_ms(lambda: torch.matmul(S, W16)),
+               "wgrad_shape_one_bf16_term_ms": lib_ms(lambda: torch.matmul(St, dI16))}
+    del W16, St, dI16
     return {"batch": B, "hidden": H, "inputs": n_in, "T": T, "ckpt_every": ckpt_every,
             "fwd_ms": t_fwd * 1e3, "fwd_bwd_ms": t_fb * 1e3,
             "fwd_updates_per_s": upd / t_fwd, "fwd_bwd_updates_per_s": upd / t_fb,
@@ -846,7 +869,8 @@ def bench_layer(reps=5, ckpt_every=50):
             "overlap_check": {"dCm_dWout_db_dlevel_identical": same_exact, "dWin_max_rel_diff": rel_w},
             "kernel_ms": parts_ms, "loss": float(loss.item()),
             "projection_TFLOPs": gflop / parts_ms["projection"],
-            "wgrad_TFLOPs": 2 * gflop / parts_ms["proj_wgrad"]}
+            "wgrad_TFLOPs": 2 * gflop / parts_ms["proj_wgrad"],
+            "library_gemm_context": library}
 
 
 # ---------------------------------------------------------------------------
