@@ -360,6 +360,12 @@ class Model:
         _ok(lib.hh_set_delivery(self.h, code), "hh_set_delivery")
 
     def syn_propagate(self, spike_bits, state, n_spikes=None):
+        """One delivery of the sources set in spike_bits (one bit per element,
+        int32 or uint32 words) into the conductances of state; n_spikes, if
+        given, receives the number of spiking sources."""
+        _need(spike_bits, "spike_bits", (torch.int32, torch.uint32), self.words)
+        _need(state, "state", _F32, self.n_state * self.n, exact=True)
+        _need(n_spikes, "n_spikes", _I32, 1)
         _ok(lib.hh_syn_propagate(self.h, _ptr(spike_bits), _ptr(state), _ptr(n_spikes), _stream()),
             "hh_syn_propagate")
 

@@ -85,6 +85,65 @@ def test_syn_propagate_matches_oracle_and_is_deterministic():
     assert np.array_equal(outs[0][: 1 + G], st.cpu().numpy()[: 1 + G])
 
 
+@pytest.mark.parametrize("sorted_rows", [True, False])
+def test_syn_propagate_no_spikes_and_empty_rows(sorted_rows):
+    """Degenerate one-shot deliveries: with no source spiking the count is 0
+    and the state is untouched, bit for bit; on a CSR whose rows are mostly
+    empty (only every third row has synapses) with every source spiking, the
+    empty rows deliver nothing and the conductances match the oracle.  Rows
+    sorted by target take the binned delivery, shuffled rows the per-event
+    one."""
+    print_case("syn_propagate degenerate sorted=%s" % sorted_rows)
+    torch = need_gpu()
+    from paper_2601_21407_amd import hh
+    n, fan = 2000, 150
+    rng = np.random.default_rng(21)
+    counts = np.where(np.arange(n) % 3 == 0, fan, 0)
+    row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    cols, ws = [], []
+    for j in range(n):
+        if counts[j] == 0:
+            continue
+        c = rng.choice(n, size=fan, replace=False).astype(np.int32)
+        c = np.sort(c) if sorted_rows else rng.permutation(c)
+        sign = 1.0 if j < int(0.8 * n) else -4.0
+        cols.append(c)
+        ws.append((sign * rng.lognormal(-1.0, 0.5, fan)).astype(np.float32))
+    csr = (row_ptr, np.concatenate(cols), np.concatenate(ws))
+    m = W.net_model()
+    G = len(m["gates"])
+    M = hh.Model(m, n)
+    M.attach_csr(_dev(csr[0]), _dev(csr[1]), _dev(csr[2]), 0.03)
+    st = M.new_state()
+    M.init_state(st, v0_scalar=-65.0)
+    ge0 = rng.random(n).astype(np.float32) * 0.1
+    gi0 = rng.random(n).astype(np.float32) * 0.1
+    st[1 + G] = _dev(ge0)
+    st[2 + G] = _dev(gi0)
+    words = (n + 31) // 32
+    # no spikes
+    s2 = st.clone()
+    cnt = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    M.syn_propagate(torch.zeros(words, dtype=torch.int32, device="cuda"), s2, cnt)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == 0
+    assert torch.equal(s2, st)
+    # every source spikes: the empty rows contribute nothing
+    s3 = st.clone()
+    allbits = np.zeros(words * 32, np.uint8)
+    allbits[:n] = 1
+    packed = np.packbits(allbits.reshape(-1, 8), axis=1, bitorder="little").reshape(-1).view(np.uint32)
+    M.syn_propagate(_dev(packed), s3, cnt)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == n
+    out = s3.cpu().numpy()
+    ge, gi = ge0.astype(np.float64), gi0.astype(np.float64)
+    O.syn_deliver(csr, 0.03, np.ones(n, np.uint8), ge, gi)
+    assert np.allclose(out[1 + G], ge, rtol=3e-7, atol=1e-9)
+    assert np.allclose(out[2 + G], gi, rtol=3e-7, atol=1e-9)
+    assert np.array_equal(out[: 1 + G], st.cpu().numpy()[: 1 + G])
+
+
 @pytest.mark.parametrize("n,fan_out,p_spike", [(3001, 700, 0.6), (9001, 300, 0.7)])
 def test_syn_propagate_binned_equals_per_event_delivery(n, fan_out, p_spike):
     """The binned delivery (rows sorted by target) and the per-event delivery
