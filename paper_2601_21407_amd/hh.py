@@ -208,6 +208,18 @@ def _need(t, what, dtype, min_numel, exact=False):
                          % (what, "" if exact else "at least ", min_numel, t.numel()))
 
 
+def _need_bytes(t, what, nbytes):
+    """A device tensor argument of at least nbytes bytes (the library reads it
+    as raw bytes, whatever its dtype)."""
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError("%s: expected a device tensor" % what)
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError("%s: expected at least %d bytes, got %d"
+                         % (what, nbytes, t.numel() * t.element_size()))
+
+
 _F32 = (torch.float32,)
 _I32 = (torch.int32,)
 
@@ -337,6 +349,7 @@ class Model:
         _need(col, "col", _I32, col.numel())
         _need(w, "w", _F32, col.numel(), exact=True)
         self._keep += [row_ptr, col, w]
+        self._nnz = col.numel()
         _ok(lib.hh_attach_csr(self.h, _ptr(row_ptr), _ptr(col), _ptr(w), int(col.numel()),
                               float(w_scale)), "hh_attach_csr")
 
@@ -349,6 +362,7 @@ class Model:
 
     def set_delays(self, delay, max_delay: int):
         """Per-synapse delays in steps (device uint8 [nnz]); None: one step."""
+        _need(delay, "delay", (torch.uint8,), getattr(self, "_nnz", 0))
         if delay is not None:
             self._keep.append(delay)
         _ok(lib.hh_set_delays(self.h, _ptr(delay), int(max_delay)), "hh_set_delays")
@@ -485,6 +499,14 @@ def readout_ce(level, T: int, W, bias, labels, dlevel, dW, db, loss, logits=None
     B, H = level.shape
     C = W.shape[1]
     assert labels.dtype == torch.int32 and labels.numel() == B
+    _need(level, "level", _F32, B * H, exact=True)
+    _need(W, "W", _F32, H * C, exact=True)
+    _need(bias, "bias", _F32, C, exact=True)
+    _need(dlevel, "dlevel", _F32, B * H, exact=True)
+    _need(dW, "dW", _F32, H * C, exact=True)
+    _need(db, "db", _F32, C, exact=True)
+    _need(loss, "loss", _F32, 1)
+    _need(logits, "logits", _F32, B * C, exact=True)
     need = int(lib.hh_readout_ce_workspace(B, C))
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=level.device)
@@ -504,6 +526,11 @@ def level_rate(level, T: int, rate):
 
 def adam_step(param, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
               param_bf16=None):
+    n = param.numel()
+    _need(param, "param", _F32, n)
+    for t, what in ((grad, "grad"), (m, "m"), (v, "v")):
+        _need(t, what, _F32, n, exact=True)
+    _need(param_bf16, "param_bf16", (torch.bfloat16,), n, exact=True)
     _ok(lib.hh_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), float(lr),
                          float(beta1), float(beta2), float(eps), int(step), _ptr(param_bf16),
                          _stream()), "hh_adam_step")
@@ -585,6 +612,8 @@ def surrogate_transitions(traj, i_dense, k: int, v_fb: float, cap: int):
 
 
 def mlp_pack(params, norm):
+    _need(params, "params", _F32, MLP_NPARAM, exact=True)
+    _need(norm, "norm", _F32, 32, exact=True)
     packed = torch.empty(int(lib.hh_mlp_packed_bytes()), dtype=torch.uint8, device=params.device)
     _ok(lib.hh_mlp_pack(_ptr(params), _ptr(norm), _ptr(packed), _stream()), "hh_mlp_pack")
     return packed
@@ -599,6 +628,13 @@ def mlp_infer(packed, X, Y, act="silu"):
 def surrogate_step_n(model: Model, packed, state, flags, n_steps: int, k: int, t0: int = 0, *,
                      noise=None, i_dense=None, v_fallback=-50.0, check_every=10, check_tol=0.5,
                      spikes=None, stats=None, act="silu"):
+    n, T = model.n, max(int(n_steps), 0)
+    _need_bytes(packed, "packed", int(lib.hh_mlp_packed_bytes()))
+    _need(state, "state", _F32, model.n_state * n, exact=True)
+    _need_bytes(flags, "flags", n)
+    _need(i_dense, "i_dense", _F32, T * n)
+    _need(spikes, "spikes", _I32, T * model.words)
+    _need(stats, "stats", (torch.int64,), 3)
     inp = Input()
     if i_dense is not None:
         inp.mode, inp.i_dense = IN_DENSE, _ptr(i_dense)
