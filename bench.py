@@ -1099,6 +1099,78 @@ def counters_run():
                       "net_src_hash": _src_hash(NET_KERNEL_SOURCES)}))
 
 
+def layer_counters_run():
+    """One step of the differentiable layer (forward product, neurons,
+    readout, adjoint, weight gradient) after a warm-up step, for rocprofv3
+    --pmc runs on the layer's kernels."""
+    import torch
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import workloads as W
+    S8, labels = W.layer_inputs()
+    T, B, n_in = S8.shape
+    H, ck_every = 1024, 50
+    n = B * H
+    Win, cm0, Wout, bout = W.layer_params()
+    dev = "cuda"
+    Sbits = torch.tensor(W.pack_bits(S8.reshape(T * B, n_in)), device=dev)
+    SbitsT = torch.tensor(W.pack_bits_cols(S8.reshape(T * B, n_in)), device=dev)
+    win16 = torch.tensor(np.ascontiguousarray(Win.T), device=dev).to(torch.bfloat16)
+    M = hh.Model(W.classic_hh(dt=0.025), H, B, cm=torch.tensor(cm0, device=dev))
+    M.set_fusion(T)
+    st = M.new_state()
+    I = torch.empty((T * B, H), device=dev)
+    ck = torch.empty(((T + ck_every - 1) // ck_every, M.n_state, n), device=dev)
+    lv = torch.empty((B, H), device=dev)
+    dl = torch.empty((B, H), device=dev)
+    wout, bo = torch.tensor(Wout, device=dev), torch.tensor(bout, device=dev)
+    lab = torch.tensor(labels.astype(np.int32), device=dev)
+    dWo, db, loss = torch.empty_like(wout), torch.empty_like(bo), torch.empty(1, device=dev)
+    dI = torch.empty((T, n), device=dev)
+    dC = torch.empty(H, device=dev)
+    dWin = torch.empty((H, n_in), device=dev)
+    ws_b = torch.empty(M.backward_workspace(ck_every, T), dtype=torch.uint8, device=dev)
+    ws_w = torch.empty(int(hh.lib.hh_proj_wgrad_workspace(T * B, H, n_in)), dtype=torch.uint8,
+                       device=dev)
+    for _ in range(2):
+        hh.proj_forward_bits(Sbits, n_in, win16, I)
+        M.init_state(st, v0_scalar=-65.0)
+        lv.zero_()
+        M.step_n(st, T, 0, i_dense=I, ckpt=ck, ckpt_every=ck_every, level=lv.view(-1))
+        hh.readout_ce(lv, T, wout, bo, lab, dl, dWo, db, loss)
+        M.backward(ck, ck_every, I, T, dI, dL_dlevel=dl.view(-1), beta=0.2, dCm=dC,
+                   workspace=ws_b)
+        hh.proj_wgrad_bits(SbitsT, T * B, dI.view(T * B, H), dWin, workspace=ws_w)
+        _sync()
+    del M
+    print(json.dumps({"layer_step": "done", "neurons": n, "T": T}))
+
+
+def surrogate_counters_run():
+    """The deployed surrogate (hard-swish network trained as the benchmark
+    trains it) on 1,048,576 neurons x 4,000 steps, once after a warm-up, for
+    rocprofv3 --pmc runs on the deployment kernel."""
+    import torch
+    from paper_2601_21407_amd import hh
+    from paper_2601_21407_amd import surrogate as SG
+    X, dY = SG.generate_transitions(n_traj=5000, T=10000, seed=5)
+    norm = SG.norm_stats(X, dY)
+    params, _ = SG.train(X, dY, norm, epochs=8, batch=16384, lr=2e-3, act="hardswish")
+    del X, dY
+    packed = hh.mlp_pack(params, norm)
+    n, T = 1 << 20, 4000
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(41)
+    I = torch.empty((T, n), device="cuda")
+    I.normal_(0.0, 3.0, generator=gen)
+    I += 5.0
+    sr = SG.SurrogateRun(n, T)
+    for _ in range(2):
+        sr.run(packed, i_dense=I, act="hardswish", check_every=SG.CHECK_EVERY)
+        _sync()
+    st = sr.stats.cpu().numpy()
+    print(json.dumps({"surrogate_calls": int(st[0]), "plain_calls": int(st[1])}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1106,6 +1178,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--parts", default="classic,layer,net,surrogate,table,cable,encryption,probe")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters-layer", action="store_true",
+                    help="run one differentiable-layer step for rocprofv3 counter passes")
+    ap.add_argument("--counters-surrogate", action="store_true",
+                    help="run one surrogate deployment for rocprofv3 counter passes")
     ap.add_argument("--counters", action="store_true",
                     help="run the copy + one headline launch for rocprofv3 counter passes")
     args = ap.parse_args()
@@ -1118,6 +1194,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.counters_layer:
+        layer_counters_run()
+        return
+    if args.counters_surrogate:
+        surrogate_counters_run()
+        return
     if args.counters:
         counters_run()
         return
