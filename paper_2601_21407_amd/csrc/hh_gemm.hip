@@ -231,12 +231,15 @@ __device__ __forceinline__ uint4 bits_to_bf16x8(uint32_t b8) {
 }
 
 // AL: as for raw8 (weight rows 8-byte aligned, K % 4 == 0, K >= 8).
-// The spike operand stays packed in LDS, two 32-bit words per row and slab,
-// and each lane expands the eight bits of its MFMA operand in registers: A
-// costs 8 bytes of LDS per row and slab instead of 128, so the LDS traffic
-// is the weights' alone.  Slabs are 64 wide (16 products per wavefront
-// between barriers), so that the loads issued two slabs ahead have about
-// a thousand cycles of products to arrive from L2.
+// The spike operand stays packed in LDS, two 32-bit words per row and slab:
+// A costs 8 bytes of LDS per row and slab instead of 128.  Each lane turns
+// the eight bits of its MFMA operand into eight bf16 through a 256-entry
+// table in LDS (one 16-byte read) instead of about twenty VALU instructions:
+// the matrix cores and the VALU barely overlap on a SIMD, so the expansion's
+// VALU time added to the products' (13% faster with the table).  Slabs are
+// 64 wide (16 products per wavefront between barriers), so that the loads
+// issued two slabs ahead have about a thousand cycles of products to arrive
+// from L2.
 constexpr int SKB = 64, LDKB = SKB + 8;
 template <bool AL>
 __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __restrict__ Ab, int wpr,
@@ -245,9 +248,11 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
                                                           int K) {
   __shared__ uint32_t As[2][FBM][2];                                   // [m][word]: slab bits
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][FBN * LDKB];  // [n][k]
+  __shared__ uint4 lut[256];  // byte -> its eight bits as bf16 0 or 1.0
   const int tiles_m = (M + FBM - 1) / FBM, tiles_n = (N + FBN - 1) / FBN;
   int tm, tn;
   if (!tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn)) return;
+  if (threadIdx.x < 256) lut[threadIdx.x] = bits_to_bf16x8(threadIdx.x);  // read after a barrier
   const int m0 = tm * FBM, n0 = tn * FBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -305,7 +310,7 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd_bits(const uint32_t* __rest
       bf16x8 a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
-        a[i] = __builtin_bit_cast(bf16x8, bits_to_bf16x8((wa[i][kk >> 5] >> (kl & 31)) & 0xFFu));
+        a[i] = __builtin_bit_cast(bf16x8, lut[(wa[i][kk >> 5] >> (kl & 31)) & 0xFFu]);
 #pragma unroll
       for (int j = 0; j < 2; ++j) b[j] = lds8(bs + (wn * 64 + j * 32 + (lane & 31)) * LDKB + kl);
 #pragma unroll
