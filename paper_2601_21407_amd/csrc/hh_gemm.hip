@@ -215,10 +215,9 @@ __global__ __launch_bounds__(512, 4) void k_proj_fwd(const uint16_t* __restrict_
 }
 
 // Forward with binary (spike) input: A given as bits, A_bits [M][wpr] uint32,
-// bit k%32 of word k/32 = A[m][k] in {0, 1}.  The A slab of each 32-wide K
-// step is one word per row; it is expanded to bf16 (0 or 1.0) while being
-// written to LDS, so A costs 1/16 of the bf16 path's traffic and only the
-// weight slab is staged from memory -- prefetched two slabs ahead.
+// bit k%32 of word k/32 = A[m][k] in {0, 1}: A costs 1/16 of the bf16 path's
+// traffic.  bits_to_bf16x8 forms the eight bf16 (0 or 1.0) of one byte of
+// bits; the kernels keep it as a 256-entry table in LDS.
 __device__ __forceinline__ uint4 bits_to_bf16x8(uint32_t b8) {
   // bit j -> bf16 1.0 (0x3F80) or 0 in element j
   uint32_t w[4];
