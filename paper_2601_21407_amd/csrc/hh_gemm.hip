@@ -583,8 +583,17 @@ __global__ __launch_bounds__(256) void k_sum_splits(const float* __restrict__ pa
                                                     int splits, int accumulate) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= count) return;
+  // eight loads in flight, added in split order (the same sum as one at a time)
   float s = 0.0f;
-  for (int q = 0; q < splits; ++q) s += part[(int64_t)q * count + i];
+  int q = 0;
+  for (; q + 8 <= splits; q += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(q + u) * count + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; q < splits; ++q) s += part[(int64_t)q * count + i];
   out[i] = accumulate ? out[i] + s : s;
 }
 
