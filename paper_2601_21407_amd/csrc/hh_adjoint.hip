@@ -277,8 +277,18 @@ __global__ __launch_bounds__(SBH * SBG) void k_sum_batch(const float* __restrict
   const int per = (B + SBG - 1) / SBG;
   const int b0 = g * per, b1 = min(B, b0 + per);
   float s = 0.0f;
-  if (h < N)
-    for (int b = b0; b < b1; ++b) s += part[(int64_t)b * N + h];
+  if (h < N) {
+    // eight loads in flight, added in batch order (the same sum as one at a time)
+    int b = b0;
+    for (; b + 8 <= b1; b += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u) * N + h];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; b < b1; ++b) s += part[(int64_t)b * N + h];
+  }
   red[g][hx] = s;
   __syncthreads();
   if (g == 0 && h < N) {
