@@ -881,7 +881,11 @@ int32_t hh_attach_csr(hh_model* m, const int64_t* row_ptr, const int32_t* col, c
       m->d_scratch = nullptr;
       return HH_E_OOM;
     }
-    if (hipMemset(m->d_scratch, 0, bytes) != hipSuccess) return HH_E_HIP;
+    if (hipMemset(m->d_scratch, 0, bytes) != hipSuccess) {
+      (void)hipFree(m->d_scratch);  // the next call allocates and clears it again
+      m->d_scratch = nullptr;
+      return HH_E_HIP;
+    }
     m->scratch_bytes = bytes;
   }
   // Every row is read once on the device: the CSR is checked (a bad column
